@@ -1,0 +1,534 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here compares the oracle with itself: every expected value comes from a
+closed form, a textbook identity, a value printed in the paper
+(tests/golden/paper_values.json) or an independent numerical route (finite
+differences of the inverse map, a brute-force neighbourhood filter).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle.oracle import (CART, CIRCLE, FLAG_DEACT, FLAG_EFFGHOST, FLAG_LIVE, LINEAR, NG, SPH, OracleWorld,
+                           lagrange, world_from_config)
+from paper_2002_00088_amd import workloads as W
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def cell_centers(p, with_ghosts=False):
+    g = NG if with_ghosts else 0
+    xs = []
+    for a in range(3):
+        dx = (p["hi"][a] - p["lo"][a]) / p["n"][a]
+        i = np.arange(-g, p["n"][a] + g)
+        xs.append(p["lo"][a] + (i + 0.5) * dx)
+    z, y, x = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    return x, y, z
+
+
+# --------------------------------------------------------------------------
+# Stencils: exactness on polynomials (textbook 4th-order weights)
+# --------------------------------------------------------------------------
+def test_stencils_exact_on_polynomials():
+    n = [10, 9, 8]
+    p = W.patch(n, [0.1, -0.3, 0.2], [1.1, 0.6, 1.0], is_global=1)
+    w = OracleWorld()
+    w.add_patch(p)
+    x, y, z = cell_centers(p, with_ghosts=True)
+    dx = [(p["hi"][a] - p["lo"][a]) / n[a] for a in range(3)]
+    X = [x, y, z]
+    i, j, k = 4, 4, 4
+    xc = [p["lo"][a] + (c + 0.5) * dx[a] for a, c in enumerate((i, j, k))]
+    for d in range(3):
+        for deg in range(0, 7):
+            full = np.zeros((5,) + x.shape)
+            full[0] = X[d] ** deg
+            w.set_full(0, 0, full)
+            d1 = w.stencil(0, 0, d, 0, i, j, k)
+            d2 = w.stencil(0, 1, d, 0, i, j, k)
+            d6 = w.stencil(0, 3, d, 0, i, j, k)
+            if deg <= 4:
+                assert d1 == pytest.approx(deg * xc[d] ** (deg - 1) if deg else 0.0, abs=1e-10)
+            if deg <= 5:
+                assert d2 == pytest.approx(deg * (deg - 1) * xc[d] ** (deg - 2) if deg > 1 else 0.0, abs=1e-9)
+                assert abs(d6) < 1e-9
+            if deg == 6:
+                assert d6 == pytest.approx(720.0 * dx[d] ** 6, rel=1e-7)
+    # mixed derivative = composition of first-derivative stencils: exact on x^a y^b, a,b <= 4
+    for a in range(5):
+        for b in range(5):
+            full = np.zeros((5,) + x.shape)
+            full[0] = x ** a * y ** b
+            w.set_full(0, 0, full)
+            got = w.stencil(0, 2, 0, 1, i, j, k)
+            exp = (a * xc[0] ** (a - 1) if a else 0.0) * (b * xc[1] ** (b - 1) if b else 0.0)
+            assert got == pytest.approx(exp, abs=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Full periodic step on one Fourier mode: closed-form discrete evolution.
+# The RK update is built here from the printed Butcher tableau (Table rk4).
+# --------------------------------------------------------------------------
+def mode_matrix(kvec, dx, v, eps):
+    th = np.array(kvec) * np.array(dx)
+    kap = (8 * np.sin(th) - np.sin(2 * th)) / (6 * np.array(dx))
+    mu = np.sum((30 - 32 * np.cos(th) + 2 * np.cos(2 * th)) / (12 * np.array(dx) ** 2))
+    sig = np.sum(eps / np.array(dx) * np.sin(th / 2) ** 6)
+    A = np.zeros((5, 5), dtype=complex)
+    A[0, 0], A[0, 1] = -sig, 1
+    A[1, 0], A[1, 1] = -v * v * mu, -sig
+    for d in range(3):
+        A[2 + d, 1] = 1j * kap[d]
+        A[2 + d, 2 + d] = -sig
+    return A
+
+
+def rk_tableau_step(M, dt, u):
+    tab = GOLD["rk4_tableau"]
+    a, b = np.array(tab["a"]), np.array(tab["b"])
+    ks = []
+    for l in range(4):
+        arg = u + dt * sum(a[l, m] * ks[m] for m in range(l))
+        ks.append(M @ arg)
+    return u + dt * sum(b[l] * ks[l] for l in range(4))
+
+
+@pytest.mark.parametrize("v,eps", [(1.0, 0.005), (0.5, 0.0), (1.0, 0.2)])
+def test_single_mode_closed_form(v, eps):
+    n = [12, 10, 8]
+    Lb = [1.0, 1.25, 0.8]
+    p = W.patch(n, [0, 0, 0], Lb, is_global=1, periodic=(1, 1, 1))
+    w = OracleWorld(wave_speed=(v,), ko_eps=eps)
+    w.add_patch(p)
+    dx = [Lb[a] / n[a] for a in range(3)]
+    kint = [2, 1, 3]
+    kvec = [2 * math.pi * kint[a] / Lb[a] for a in range(3)]
+    rng = np.random.default_rng(7)
+    uhat = rng.normal(size=5) + 1j * rng.normal(size=5)
+    x, y, z = cell_centers(p)
+    ph = np.exp(1j * (kvec[0] * x + kvec[1] * y + kvec[2] * z))
+    w.set_state(0, 0, np.real(uhat[:, None, None, None] * ph[None]))
+    dt = 0.02
+    M = mode_matrix(kvec, dx, v, eps)
+    u = uhat.copy()
+    for _ in range(3):
+        u = rk_tableau_step(M, dt, u)
+    w.step(dt, 3)
+    got = w.get_state(0)
+    exp = np.real(u[:, None, None, None] * ph[None])
+    assert np.max(np.abs(got - exp)) < 1e-12 * np.max(np.abs(exp))
+
+
+# --------------------------------------------------------------------------
+# Continuum convergence on a periodic plane wave: 4th order
+# --------------------------------------------------------------------------
+def test_plane_wave_convergence_order():
+    errs = []
+    for n in (8, 16, 32):
+        cfg = W.single_periodic(seed=11, n=n)
+        cfg["exact"][0]["kappa"] = [2 * math.pi, 2 * math.pi, 0.0]
+        w = world_from_config(cfg)
+        w.init_exact(0.0)
+        T = 0.25
+        steps = int(round(T / (0.25 / n)))
+        w.step(T / steps, steps)
+        errs.append(w.diag(0)["err_max"][0])
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert slopes[1] > 3.7 and slopes[1] < 4.4, (errs, slopes)
+
+
+# --------------------------------------------------------------------------
+# Lagrange interpolation (Eq. Pijk)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("P", [5, 6])
+def test_lagrange_exact_partition_nodes(P):
+    rng = np.random.default_rng(3)
+    for q in list(rng.uniform(-3, 40, 50)) + [7.0, 7.5, 12.25]:
+        s, wts = lagrange(P, q)
+        nodes = s + np.arange(P)
+        assert abs(wts.sum() - 1) < 1e-13
+        for deg in range(P):
+            assert np.dot(wts, nodes.astype(float) ** deg) == pytest.approx(q ** deg, rel=1e-11, abs=1e-11)
+        if P == GOLD["interpolation"]["points"]:
+            ic = math.floor(q)
+            assert s == ic + GOLD["interpolation"]["first_offset"]
+            assert s + P - 1 == ic + GOLD["interpolation"]["last_offset"]
+        else:
+            assert s + 2 == math.floor(q + 0.5)
+    s, wts = lagrange(P, 9.0)
+    assert np.allclose(wts, np.eye(P)[9 - s], atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Metric and C^lambda
+# --------------------------------------------------------------------------
+def _world_with(local, v=1.0):
+    w = OracleWorld(wave_speed=(v,))
+    w.add_patch(W.patch([8, 8, 8], [-8] * 3, [8] * 3, is_global=1))
+    w.add_patch(local)
+    return w
+
+
+def test_static_spherical_metric_closed_form():
+    v = 0.5
+    w = _world_with(W.patch([8, 8, 8], [0.5, 0.3, 0.0], [6, 2.8, 2 * math.pi], coord=SPH, periodic=(0, 0, 1)), v)
+    for r, th, ph in [(1.0, 0.7, 0.3), (2.5, 1.9, 4.0), (0.6, 2.5, 6.0)]:
+        g, C, sg = w.metric(1, 0, 0.3, [r, th, ph])
+        exp = np.diag([-1 / v ** 2, 1.0, 1 / r ** 2, 1 / (r * math.sin(th)) ** 2])
+        assert np.allclose(g, exp, atol=1e-13)
+        assert np.allclose(C, [0.0, -2 / r, -math.cos(th) / math.sin(th) / r ** 2, 0.0], atol=1e-12)
+        assert sg == pytest.approx(r * r * math.sin(th), rel=1e-13)
+
+
+def zyz(e):
+    a, b, c = e
+    Rz = lambda t: np.array([[math.cos(t), -math.sin(t), 0], [math.sin(t), math.cos(t), 0], [0, 0, 1]])
+    Ry = np.array([[math.cos(b), 0, math.sin(b)], [0, 1, 0], [-math.sin(b), 0, math.cos(b)]])
+    return Rz(a) @ Ry @ Rz(c)
+
+
+def test_circle_moving_cartesian_metric_closed_form():
+    v = 0.8
+    eu = [0.4, 1.1, 2.3]
+    rho, speed, psi = 2.0, 0.3, 0.7
+    w = _world_with(W.patch([8] * 3, [-2] * 3, [2] * 3, euler=eu, motion=CIRCLE, radius=rho, speed=speed, phase=psi), v)
+    R = zyz(eu)
+    assert np.allclose(w.rotation(1), R, atol=1e-15)
+    om = speed / rho
+    for t in (0.0, 1.3):
+        cd = rho * om * np.array([-math.sin(om * t + psi), math.cos(om * t + psi), 0])
+        cdd = -rho * om * om * np.array([math.cos(om * t + psi), math.sin(om * t + psi), 0])
+        b = R.T @ cd
+        g, C, sg = w.metric(1, 0, t, [0.3, -0.5, 1.2])
+        assert g[0, 0] == pytest.approx(-1 / v ** 2, rel=1e-14)
+        assert np.allclose(g[0, 1:], b / v ** 2, atol=1e-14)
+        assert np.allclose(g[1:, 1:], np.eye(3) - np.outer(b, b) / v ** 2, atol=1e-14)
+        assert np.allclose(C[1:], -(R.T @ cdd) / v ** 2, atol=1e-14)
+        assert abs(C[0]) < 1e-14 and sg == pytest.approx(1.0, rel=1e-14)
+
+
+def test_metric_matches_inverse_map_finite_differences():
+    """g^{mu nu} = Lam eta^{-1} Lam^T and C^l = -eta^{ab} d_a d_b x'^l, with
+    Lam = d x'/d(t,X) taken by finite differences of the inverse map."""
+    v = 0.7
+    w = _world_with(W.patch([8] * 3, [0.5, 0.5, 0.0], [5, 2.6, 2 * math.pi], coord=SPH, periodic=(0, 0, 1),
+                            euler=[0.3, 0.9, -0.4], motion=LINEAR, c0=(0.2, -0.1, 0.3), vel=(0.15, -0.1, 0.05)), v)
+    t0 = 0.8
+    xp0 = np.array([1.7, 1.2, 2.0])
+    X0 = w.map_fwd(1, t0, xp0)
+    assert np.allclose(w.map_inv(1, t0, X0), xp0, atol=1e-13)
+    h = 1e-3
+
+    def f(tX):
+        return w.map_inv(1, tX[0], tX[1:])
+
+    base = np.concatenate([[t0], X0])
+    Lam = np.zeros((4, 4))
+    d2 = np.zeros((4, 3))
+    for a in range(4):
+        e = np.zeros(4)
+        e[a] = h
+        fp1, fm1, fp2, fm2 = f(base + e), f(base - e), f(base + 2 * e), f(base - 2 * e)
+        Lam[1:, a] = (8 * (fp1 - fm1) - (fp2 - fm2)) / (12 * h)
+        d2[a] = (-fp2 + 16 * fp1 - 30 * f(base) + 16 * fm1 - fm2) / (12 * h * h)
+    Lam[0, 0] = 1.0
+    etainv = np.diag([-1 / v ** 2, 1, 1, 1])
+    g_fd = Lam @ etainv @ Lam.T
+    C_fd = -(etainv.diagonal()[:, None] * d2).sum(axis=0)
+    g, C, _ = w.metric(1, 0, t0, xp0)
+    assert np.allclose(g, g_fd, rtol=1e-7, atol=1e-8)
+    assert np.allclose(C[1:], C_fd, rtol=1e-6, atol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# Exact solutions
+# --------------------------------------------------------------------------
+def test_gaussian_pulse_solves_wave_equation():
+    v = 0.6
+    w = OracleWorld(wave_speed=(v,))
+    w.add_patch(W.patch([8] * 3, [-4] * 3, [4] * 3, is_global=1))
+    xc = np.array([0.3, -0.2, 0.5])
+    wd = 0.7
+    w.set_exact(0, dict(kind="gauss", amp=[1.3], centers=[list(xc)], widths=[wd]))
+    # initial data
+    for X in ([0.3, -0.2, 0.5], [1.0, 0.4, -0.3]):
+        e = w.exact_bg(0, 0.0, np.array(X))
+        r2 = np.sum((np.array(X) - xc) ** 2)
+        assert e[0] == pytest.approx(1.3 * math.exp(-r2 / wd ** 2), rel=1e-13)
+        assert abs(e[1]) < 1e-13
+        assert np.allclose(e[2:], -2 * (np.array(X) - xc) / wd ** 2 * e[0], atol=1e-13)
+    # wave equation and derivative consistency by finite differences (also across
+    # the series / closed-form switch near the pulse centre)
+    h = 1e-3
+    for X, t in (([1.0, 0.4, -0.3], 0.9), ([0.31, -0.2, 0.5], 0.5), ([0.3, -0.2, 0.5], 1.4)):
+        X = np.array(X)
+        phi = lambda tt, XX: w.exact_bg(0, tt, XX)[0]
+        f0 = phi(t, X)
+        ftt = (-phi(t + 2 * h, X) + 16 * phi(t + h, X) - 30 * f0 + 16 * phi(t - h, X) - phi(t - 2 * h, X)) / (12 * h * h)
+        lap = 0.0
+        grad = np.zeros(3)
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            fp, fm, fp2, fm2 = phi(t, X + e), phi(t, X - e), phi(t, X + 2 * e), phi(t, X - 2 * e)
+            lap += (-fp2 + 16 * fp - 30 * f0 + 16 * fm - fm2) / (12 * h * h)
+            grad[a] = (8 * (fp - fm) - (fp2 - fm2)) / (12 * h)
+        ex = w.exact_bg(0, t, X)
+        pt = (8 * (phi(t + h, X) - phi(t - h, X)) - (phi(t + 2 * h, X) - phi(t - 2 * h, X))) / (12 * h)
+        assert abs(ftt - v * v * lap) < 2e-6
+        assert ex[1] == pytest.approx(pt, abs=1e-8)
+        assert np.allclose(ex[2:], grad, atol=1e-8)
+    # continuity across the series switch at rho = 0.05 w
+    d = np.array([1.0, 2.0, -0.5]) / math.sqrt(5.25)
+    a = w.exact_bg(0, 0.8, xc + d * 0.05 * wd * (1 - 1e-13))
+    b = w.exact_bg(0, 0.8, xc + d * 0.05 * wd * (1 + 1e-13))
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-13)
+
+
+def test_plane_wave_matches_paper_form():
+    L = GOLD["plane_wave"]["L"]
+    w = OracleWorld()
+    w.add_patch(W.patch([8] * 3, [-20] * 3, [20] * 3, is_global=1))
+    w.set_exact(0, dict(kind="plane", A=1.0, B=GOLD["plane_wave"]["offset"], kappa=[2 * math.pi / L, 0, 0], psi=0.0))
+    for X, t in (([3.0, 1.0, -2.0], 0.0), ([-7.5, 0.0, 4.0], 13.0)):
+        e = w.exact_bg(0, t, np.array(X))
+        assert e[0] == pytest.approx(math.sin(2 * math.pi * (X[0] - t) / L) + 2, rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# One-form transform between frames
+# --------------------------------------------------------------------------
+def _three_patch_world():
+    w = OracleWorld(wave_speed=(0.9,))
+    w.add_patch(W.patch([8] * 3, [-8] * 3, [8] * 3, is_global=1))
+    w.add_patch(W.patch([8] * 3, [-2] * 3, [2] * 3, euler=[0.5, 1.2, 2.0], motion=CIRCLE, radius=2, speed=0.3,
+                        phase=0.2))
+    w.add_patch(W.patch([8] * 3, [0.5, 0.6, 0.0], [4, 2.5, 2 * math.pi], coord=SPH, periodic=(0, 0, 1),
+                        euler=[1.0, 0.4, -0.7], motion=LINEAR, c0=(1, -1, 0.5), vel=(0.1, 0.0, -0.12)))
+    w.set_exact(0, dict(kind="gauss", amp=[1.0, -0.5], centers=[[0.5, 0.2, -0.3], [1.5, -1.0, 0.8]], widths=[0.8, 0.6]))
+    return w
+
+
+def test_transform_round_trip_and_exact_gradient():
+    w = _three_patch_world()
+    rng = np.random.default_rng(5)
+    t = 0.7
+    X = np.array([1.1, -0.6, 0.9])
+    xs = [w.map_inv(p, t, X) for p in range(3)]
+    for d in range(3):
+        for r in range(3):
+            s = rng.normal(size=5)
+            there = w.transform(d, xs[d], r, xs[r], t, s)
+            back = w.transform(r, xs[r], d, xs[d], t, there)
+            assert np.allclose(back, s, atol=1e-13)
+            # the exact state of frame d carried to frame r is the exact state of frame r
+            ed = w.exact_patch(d, 0, t, xs[d])
+            er = w.exact_patch(r, 0, t, xs[r])
+            assert np.allclose(w.transform(d, xs[d], r, xs[r], t, ed), er, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Cover flags with the NG+1 buffer
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,ratio", [(20, 1), (20, 2), (17, 2)])
+def test_flags_aligned_cube_counts(m, ratio):
+    w = OracleWorld()
+    w.add_patch(W.patch([40] * 3, [0] * 3, [40] * 3, is_global=1))
+    w.add_patch(W.patch([m * ratio] * 3, [10.0] * 3, [10.0 + m] * 3))
+    w.prepare()
+    f, c = w.flags()
+    B, ng = GOLD["ghosts"]["buffer"], GOLD["ghosts"]["NG"]
+    core = m - 2 * B
+    assert int((c == 1).sum()) == m ** 3
+    assert int((f != FLAG_LIVE).sum()) == core ** 3
+    assert int((f == FLAG_EFFGHOST).sum()) == core ** 3 - max(core - 2 * ng, 0) ** 3
+    assert int((f == FLAG_DEACT).sum()) == max(core - 2 * ng, 0) ** 3
+
+
+def test_flags_match_brute_force_filter_on_rotated_patch():
+    from scipy import ndimage
+    w = OracleWorld()
+    w.add_patch(W.patch([48] * 3, [-8] * 3, [8] * 3, is_global=1))
+    w.add_patch(W.patch([66] * 3, [-5.5] * 3, [5.5] * 3, euler=[0.4, 1.1, 2.5], c0=(0.2, -0.3, 0.1)))
+    w.prepare()
+    f, c = w.flags()
+    unc = np.pad(c < 0, 4, constant_values=True)
+    live = ndimage.maximum_filter(unc, size=9, mode="constant", cval=True)[4:-4, 4:-4, 4:-4]
+    eff = ndimage.maximum_filter(live, size=7, mode="constant", cval=False) & ~live
+    exp = np.where(live, FLAG_LIVE, np.where(eff, FLAG_EFFGHOST, FLAG_DEACT))
+    assert (exp == f).all()
+    assert (f == FLAG_DEACT).sum() > 0 and (f == FLAG_EFFGHOST).sum() > 0
+
+
+# --------------------------------------------------------------------------
+# The buffer property: no interpolation reads interpolated (or poisoned) data
+# --------------------------------------------------------------------------
+def test_exchange_never_reads_non_live_data():
+    cfg = W.two_patch(seed=4, ng=40, nl=32, P=6)
+    w = world_from_config(cfg)
+    w.init_exact(0.0)
+    w.prepare()
+    f, c = w.flags()
+    g = w.get_full(0)
+    core = np.zeros(g.shape[1:], dtype=bool)
+    core[NG:-NG, NG:-NG, NG:-NG] = f != FLAG_LIVE
+    g[:, core] = np.nan
+    w.set_full(0, 0, g)
+    l = w.get_full(1)
+    l[:, :NG] = np.nan
+    l[:, -NG:] = np.nan
+    l[:, :, :NG] = np.nan
+    l[:, :, -NG:] = np.nan
+    l[:, :, :, :NG] = np.nan
+    l[:, :, :, -NG:] = np.nan
+    w.set_full(1, 0, l)
+    w.exchange_ghosts(0.0)
+    assert w.counters()["skip_local"] == 0 and w.counters()["skip_eff"] == 0
+    assert np.isfinite(w.get_full(1)).all()
+    g2 = w.get_full(0)[:, NG:-NG, NG:-NG, NG:-NG]
+    assert np.isfinite(g2[:, f != FLAG_DEACT]).all()
+    assert np.isnan(g2[:, f == FLAG_DEACT]).all()
+    w.step(cfg["dt"], 2)
+    f2, _ = w.flags()
+    assert np.isfinite(w.get_state(0)[:, f2 == FLAG_LIVE]).all()
+    assert np.isfinite(w.get_state(1)).all()
+
+
+def test_skipped_points_counted_and_fall_back():
+    """A local patch poking out of the global domain: its outer ghosts cannot be
+    interpolated; they keep the analytic boundary value (skip rule)."""
+    w = OracleWorld()
+    w.add_patch(W.patch([24] * 3, [-6] * 3, [6] * 3, is_global=1))
+    w.add_patch(W.patch([16] * 3, [-2] * 3, [2] * 3, c0=(4.5, 0, 0)))
+    w.set_exact(0, dict(kind="gauss", amp=[1.0], centers=[[0, 0, 0]], widths=[1.0]))
+    w.init_exact(0.0)
+    w.exchange_ghosts(0.0)
+    assert w.counters()["skip_local"] > 0
+    l = w.get_full(1)
+    # the ghost layer beyond x = 6 equals the exact solution
+    xp = np.array([2 + 0.5 * 0.25, 0.125, 0.125])
+    e = w.exact_patch(1, 0, 0.0, xp)
+    assert np.allclose(l[:, NG + 8, NG + 8, NG + 16], e, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Constraint and energy on periodic Cartesian patches
+# --------------------------------------------------------------------------
+def periodic_D1(u, dx, axis):
+    return (np.roll(u, 2, axis) - 8 * np.roll(u, 1, axis) + 8 * np.roll(u, -1, axis) - np.roll(u, -2, axis)) / (12 * dx)
+
+
+def periodic_D2(u, dx, axis):
+    return (-np.roll(u, 2, axis) + 16 * np.roll(u, 1, axis) - 30 * u + 16 * np.roll(u, -1, axis)
+            - np.roll(u, -2, axis)) / (12 * dx * dx)
+
+
+def smooth_random(n, seed, nmodes=6):
+    rng = np.random.default_rng(seed)
+    x = [np.arange(n[a]) / n[a] for a in range(3)]
+    z, y, xx = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    out = np.zeros((5,) + z.shape)
+    for f in range(5):
+        for _ in range(nmodes):
+            k = rng.integers(-3, 4, 3)
+            out[f] += rng.normal() * np.cos(2 * math.pi * (k[0] * xx + k[1] * y + k[2] * z) + rng.uniform(0, 6.28))
+    return out
+
+
+def test_psi_constraint_preserved():
+    n = [12, 10, 14]
+    p = W.patch(n, [0, 0, 0], [1, 1, 1], is_global=1, periodic=(1, 1, 1))
+    w = OracleWorld()
+    w.add_patch(p)
+    u = smooth_random(n, 3)
+    dx = [1.0 / n[a] for a in range(3)]
+    axes = {0: 2, 1: 1, 2: 0}  # numerical axis -> numpy axis of [k][j][i]
+    for d in range(3):
+        u[2 + d] = periodic_D1(u[0], dx[d], axes[d])
+    w.set_state(0, 0, u)
+    w.step(0.01, 5)
+    s = w.get_state(0)
+    for d in range(3):
+        c = s[2 + d] - periodic_D1(s[0], dx[d], axes[d])
+        assert np.max(np.abs(c)) < 1e-11 * np.max(np.abs(s[2 + d]))
+
+
+def energy(s, dx, v):
+    axes = {0: 2, 1: 1, 2: 0}
+    Lphi = sum(periodic_D2(s[0], dx[d], axes[d]) for d in range(3))
+    return 0.5 * np.prod(dx) * np.sum(s[1] ** 2 - v * v * s[0] * Lphi)
+
+
+def test_energy_single_mode_factor_and_dissipation():
+    n = [10, 12, 8]
+    Lb = [1.0, 1.0, 1.0]
+    dx = [1.0 / x for x in n]
+    v = 0.9
+    w = OracleWorld(wave_speed=(v,), ko_eps=0.0)
+    p = W.patch(n, [0, 0, 0], Lb, is_global=1, periodic=(1, 1, 1))
+    w.add_patch(p)
+    x, y, z = cell_centers(p)
+    kv = 2 * math.pi * np.array([2, 1, 1])
+    arg = kv[0] * x + kv[1] * y + kv[2] * z
+    s0 = np.zeros((5,) + x.shape)
+    s0[0] = np.cos(arg)
+    s0[1] = 0.3 * np.sin(arg)
+    w.set_state(0, 0, s0)
+    dt = 0.03
+    w.step(dt, 1)
+    th = kv * np.array(dx)
+    mu = np.sum((30 - 32 * np.cos(th) + 2 * np.cos(2 * th)) / (12 * np.array(dx) ** 2))
+    om = v * math.sqrt(mu) * dt
+    ratio = energy(w.get_state(0), dx, v) / energy(s0, dx, v)
+    assert ratio == pytest.approx(1 - om ** 6 / 72 + om ** 8 / 576, abs=1e-13)
+    # with dissipation the discrete energy never increases on a generic field
+    w2 = OracleWorld(wave_speed=(v,), ko_eps=0.005)
+    w2.add_patch(p)
+    w2.set_state(0, 0, smooth_random(n, 8))
+    e_prev = energy(w2.get_state(0), dx, v)
+    for _ in range(5):
+        w2.step(dt, 1)
+        e = energy(w2.get_state(0), dx, v)
+        assert e <= e_prev * (1 + 1e-13)
+        e_prev = e
+
+
+# --------------------------------------------------------------------------
+# Multipatch: exact-solution residual stays small and converges at 4th order
+# --------------------------------------------------------------------------
+def _two_patch_plane(ng, motion):
+    L = 16.0
+    dxg = 2 * L / ng
+    half = 5.0
+    nl = int(round(2 * half / (dxg / 2)))
+    g = W.patch([ng] * 3, [-L] * 3, [L] * 3, is_global=1)
+    if motion == "fixed":
+        loc = W.patch([nl] * 3, [-half] * 3, [half] * 3, euler=[0.3, 0.8, 1.9], c0=(-0.5, -0.5, -0.5))
+    else:
+        loc = W.patch([nl] * 3, [-half] * 3, [half] * 3, euler=[0.3, 0.8, 1.9], motion=LINEAR, c0=(-0.5, -0.5, 0.0),
+                      vel=(0.1, 0.1, 0.0))
+    ex = dict(kind="plane", A=1.0, B=2.0, kappa=[2 * math.pi / 16 * x for x in (1.0, 0.6, 0.3)], psi=0.4)
+    cfg = dict(wave_speed=[1.0], interp_points=[6], patches=[g, loc], exact=[ex], ko_eps=0.005, buffer=4)
+    return cfg, dxg / 2
+
+
+@pytest.mark.parametrize("motion", ["fixed", "translating"])
+def test_two_patch_convergence(motion):
+    errs = []
+    T = 2.0
+    for ng in (32, 64):
+        cfg, dxl = _two_patch_plane(ng, motion)
+        w = world_from_config(cfg)
+        w.init_exact(0.0)
+        steps = int(round(T / (0.5 * dxl)))
+        w.step(T / steps, steps)
+        c = w.counters()
+        assert c["skip_local"] == 0 and c["skip_eff"] == 0 and c["skip_uncover"] == 0
+        e = w.diag(0)["int_rel_err"] + w.diag(1)["int_rel_err"]
+        errs.append(e)
+    slope = math.log2(errs[0] / errs[1])
+    assert 3.5 < slope < 4.8, (errs, slope)
