@@ -1,0 +1,225 @@
+"""Throughput of the multipatch RK4 wave step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched] [--precision mixed]
+
+A step is one classic-RK4 step over every patch: four ghost fills (analytic and
+periodic ghosts, global->local and local->global Lagrange interpolation with the
+frame transform) and four fused RHS + stage-update launches, plus the end-of-step
+cover flags and uncover fill.  Inputs start resident in HBM (exact initial data
+computed on the device).  The timed region is exactly K steps between two
+synchronisations, timed with HIP events on the library's stream.
+
+Printed: one JSON line with the metric (live cell-updates per second), the
+roofline figure of the dominant kernel (algorithmic bytes per launch divided by
+its average duration, measured with HIP events in a separate eager pass), the
+batched-vs-per-patch-FP64 comparison with its accuracy, and the CPU oracle's
+rate on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per live cell per stage kernel launch (five fields):
+# stage 1 reads u, writes acc and v2; stages 2-3 read v_s, u, acc and write acc,
+# v_{s+1}; stage 4 reads v4, acc and writes u.  FP64 state/accumulator always,
+# stage buffers FP64 (fp64) or FP32 (mixed).
+STAGE_BYTES = {"fp64": [120, 200, 200, 120], "mixed": [100, 160, 160, 100]}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("pw_kernels.hip", "pw_internal.h", "pw_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2002_00088_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, precision, dominant):
+    """HBM traffic of the dominant kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, precision))
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("kernels", {}).get(dominant)
+
+
+def make_config(name):
+    from paper_2002_00088_amd import workloads as W
+    if name == "batched":
+        return W.batched(seed=4)
+    if name == "two_patch":
+        return W.two_patch(seed=2)
+    if name == "spherical":
+        return W.spherical(seed=3)
+    if name == "periodic":
+        return W.single_periodic(seed=1)
+    if name == "multimethod":
+        return W.multimethod(seed=5)
+    raise SystemExit("unknown workload " + name)
+
+
+def cpu_baseline(cfg, steps=1):
+    """The FP64 oracle as it stands, one RK4 step of the full workload on every
+    host core (OpenMP), as live cell-updates per second."""
+    from oracle.oracle import world_from_config
+    w = world_from_config(cfg)
+    w.init_exact(0.0)
+    w.prepare()
+    f, _ = w.flags()
+    live = int((f == 0).sum()) + sum(int(p["n"][0] * p["n"][1] * p["n"][2]) for p in cfg["patches"][1:])
+    t0 = time.perf_counter()
+    w.step(cfg["dt"], steps)
+    sec = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = min(cores, os.cpu_count() or cores)
+    w.close()
+    return dict(value=live * steps / sec, unit="cell-updates/s", cores=cores, kind="oracle",
+                sample="%d RK4 step(s) of the full %s workload (%d live cells), FP64, %.1f s" % (
+                    steps, cfg["name"], live, sec))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--schedule", default="batched", choices=["batched", "per_patch"])
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--timing-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2002_00088_amd import pw
+
+    torch.cuda.set_device(0)
+    cfg = make_config(args.workload)
+    print("bench: workload %s, %d patches, precision %s, schedule %s" % (cfg["name"], len(cfg["patches"]),
+                                                                         args.precision, args.schedule),
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    prec = pw.PW_MIXED if args.precision == "mixed" else pw.PW_FP64
+    sched = pw.PW_SCHED_BATCHED if args.schedule == "batched" else pw.PW_SCHED_PER_PATCH
+    ctx = pw.context_from_config(cfg, precision=prec, schedule=sched, use_graph=not args.no_graph,
+                                 stream=stream.cuda_stream)
+    ctx.init_exact(0.0)
+    dt = cfg["dt"]
+    ctx.rk4_step(dt, args.warmup)
+    stream.synchronize()
+    live0 = ctx.live_cells()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    ctx.rk4_step(dt, args.steps)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    live1 = ctx.live_cells()
+    live = 0.5 * (live0 + live1)
+    value = live * args.steps / (ms / 1e3)
+    print("bench: %.3f ms/step, %.3e cell-updates/s (wall %.3f s)" % (ms / args.steps, value, t_wall),
+          file=sys.stderr, flush=True)
+
+    # per-kernel-class durations (eager pass with HIP events on the same stream)
+    ctx.enable_timing(True)
+    ctx.rk4_step(dt, args.timing_steps)
+    kt = ctx.kernel_times()
+    ctx.enable_timing(False)
+    sb = STAGE_BYTES[args.precision]
+    stage_avg = {s: kt["stage_s%d" % (s + 1)][0] / max(1, kt["stage_s%d" % (s + 1)][1]) for s in range(4)}
+    dom = max(range(4), key=lambda s: stage_avg[s])
+    bytes_launch = live * sb[dom]
+    achieved = bytes_launch / (stage_avg[dom] * 1e-3) / 1e9
+    step_bytes = live * sum(sb)
+    kinds = {k: round(v[0] / max(1, v[1]), 5) for k, v in kt.items()}
+    dominant_name = "stage_s%d" % (dom + 1)
+    traffic = load_traffic(cfg["name"], args.precision, dominant_name)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dominant_name, "avg_ms": round(stage_avg[dom], 5),
+                "algorithmic_bytes_per_launch": int(bytes_launch),
+                "bytes_per_live_cell": sb[dom]}
+
+    out = {"metric": "cell-updates/s per RK4 step (incl. ghost interp); HBM GB/s vs peak",
+           "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
+           "config": {"workload": cfg["name"], "global_cells": cfg["patches"][0]["n"],
+                      "local_patches": len(cfg["patches"]) - 1, "live_cells": int(live),
+                      "precision": args.precision,
+                      "schedule": args.schedule + ("" if args.no_graph or args.schedule != "batched" else "+graph"),
+                      "dt": dt},
+           "roofline": roofline,
+           "step_algorithmic_GBps": round(step_bytes / (ms / args.steps * 1e-3) / 1e9, 1),
+           "kernel_avg_ms": kinds}
+
+    if not args.no_compare and args.precision == "mixed":
+        # plain per-patch FP64 on the same GPU, same steps, and the accuracy of the
+        # batched mixed run against it
+        ref = pw.context_from_config(cfg, precision=pw.PW_FP64, schedule=pw.PW_SCHED_PER_PATCH, use_graph=False,
+                                     stream=stream.cuda_stream)
+        ref.init_exact(0.0)
+        ref.rk4_step(dt, args.warmup)
+        stream.synchronize()
+        e0.record(stream)
+        ref.rk4_step(dt, args.steps)
+        e1.record(stream)
+        e1.synchronize()
+        ms_ref = e0.elapsed_time(e1)
+        value_ref = ref.live_cells() * args.steps / (ms_ref / 1e3)
+        # same number of steps on both: mixed has taken warmup + steps + timing_steps
+        ref.rk4_step(dt, args.timing_steps)
+        f, _ = ref.flags()
+        errs = np.zeros(5)
+        l2 = np.zeros(5)
+        nrm = np.zeros(5)
+        for pid in range(len(cfg["patches"])):
+            a, b = ctx.get_state(pid), ref.get_state(pid)
+            m = (f == 0) if pid == 0 else np.ones(a.shape[1:], dtype=bool)
+            for k in range(5):
+                d = a[k][m] - b[k][m]
+                errs[k] = max(errs[k], np.abs(d).max() / max(np.abs(b[k][m]).max(), 1e-300))
+                l2[k] += (d * d).sum()
+                nrm[k] += (b[k][m] ** 2).sum()
+        out["compare"] = {"per_patch_fp64": {"value": value_ref, "ms_per_step": ms_ref / args.steps},
+                          "speedup_batched_mixed": value / value_ref,
+                          "mixed_vs_fp64_max_rel_err": [float("%.3e" % x) for x in errs],
+                          "mixed_vs_fp64_l2_rel_err": [float("%.3e" % x) for x in np.sqrt(l2 / np.maximum(nrm, 1e-300))]}
+        ref.close()
+    c = ctx.counters()
+    out["counters"] = c
+    ctx.close()
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle on one step of the same workload", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,258 @@
+/*
+ * pw.h - C ABI of the MI355X multipatch scalar-wave library (libpw).
+ *
+ * The library advances the scalar wave system of "PatchworkWave" (Bowen et al.,
+ * arXiv 2002.00088) on one global patch (id 0) plus any number of moving local
+ * patches, one classic-RK4 step at a time, on one AMD Instinct MI355X (gfx950).
+ *
+ * State vector per patch (Sec. 2.2, Eqs. eom1-eom3): u = [phi, Pi_t, Pi_1, Pi_2, Pi_3],
+ * the one-form Pi_mu = d_mu phi in the patch's own numerical coordinates.
+ *
+ * Conventions common to every call
+ *   - Host arrays of patch data are interior-only, FP64, laid out [5][n2][n1][n0]
+ *     with n0 fastest (field-major).  They are copied in or out; the library never
+ *     keeps a caller pointer.
+ *   - Ownership: the library owns all device memory.  It allocates through the
+ *     caller's allocator callbacks when given (pw_config.dev_alloc/dev_free), else
+ *     with hipMalloc.  It runs every kernel on the caller's stream (pw_config.stream,
+ *     a hipStream_t; if NULL the library creates and owns a non-blocking stream).
+ *     The caller owns host arrays and its stream, and must keep the stream alive
+ *     until pw_destroy.
+ *   - Errors: every call returns a pw_status; < 0 is an error and pw_last_error()
+ *     returns a message.  No C++ exception crosses the ABI.  A context is not
+ *     thread-safe; calls on one context must not overlap.
+ *   - Synchronisation: calls that return data to the host (pw_get_state with a
+ *     host destination, pw_get_flags, pw_diagnostics, pw_counters) synchronise the
+ *     stream.  pw_rk4_step and pw_exchange_ghosts only enqueue work.
+ */
+#ifndef PW_H
+#define PW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pw_context pw_context; /* opaque, library-owned */
+typedef int32_t pw_status;
+
+enum {
+  PW_OK = 0,
+  PW_EINVAL = -1,   /* bad argument or configuration */
+  PW_ENOMEM = -2,   /* device or host allocation failed */
+  PW_EDEVICE = -3,  /* a HIP runtime call failed */
+  PW_ESTATE = -4,   /* call not valid in the current state (e.g. no global patch) */
+  PW_EOVERLAP = -5, /* a global cell is covered by two local patches (Sec. 2.4.2 assumes none) */
+  PW_EMOTION = -6   /* a patch moves one global cell or more within a step: the NG+1 buffer
+                       covers at most one cell of motion per step (Sec. 2.4.2) */
+};
+
+enum { PW_FP64 = 0, PW_MIXED = 1 };       /* precision */
+enum { PW_CART = 0, PW_SPH = 1 };         /* patch topology */
+enum { PW_STATIC = 0, PW_LINEAR = 1, PW_CIRCLE = 2 }; /* patch motion */
+enum { PW_FLAG_LIVE = 0, PW_FLAG_EFFGHOST = 1, PW_FLAG_DEACT = 2 }; /* cover flags */
+enum { PW_SCHED_BATCHED = 0, PW_SCHED_PER_PATCH = 1 };
+enum { PW_EXACT_NONE = 0, PW_EXACT_PLANE = 1, PW_EXACT_GAUSS = 2 };
+
+#define PW_MAX_SV 4
+#define PW_MAX_PULSES 32
+
+/*
+ * Library configuration.
+ *   precision        PW_FP64: every array and operation FP64.  PW_MIXED: FP64 state
+ *                    u_n, FP64 RK accumulator, FP64 donor location, Lagrange weights
+ *                    and frame Jacobians; FP32 stage inputs, FP32 stencil and
+ *                    interpolation sums.
+ *   n_state_vectors  1..4 independent state vectors sharing maps and cover flags
+ *                    (multiple state vectors, Sec. 1.1); each has its own wave speed
+ *                    (d'Alembertian Lap - v^-2 d_t^2) and interpolation order.
+ *   interp_points    points per axis of the tensor-product Lagrange stencil: 6 is the
+ *                    paper's stencil i_c-2..i_c+3 (Sec. 2.4, Eq. Pijk); 5 centres on the
+ *                    nearest node.
+ *   buffer_width     live buffer under each local patch edge, >= 4 (NG+1, Sec. 2.4.2).
+ *   ko_eps           Kreiss-Oliger strength (0.005 in the paper, Sec. 2.3).
+ *   schedule         PW_SCHED_BATCHED: each RK stage is one launch over all patches
+ *                    and the step is captured in a HIP graph when use_graph != 0.
+ *                    PW_SCHED_PER_PATCH: one stencil launch per patch per stage, no graph.
+ *   stream           hipStream_t of the caller (NULL: a stream owned by the library).
+ *   dev_alloc/free   optional device allocator; alloc_user is passed back unchanged.
+ */
+typedef struct {
+  int32_t precision;
+  int32_t n_state_vectors;
+  double wave_speed[PW_MAX_SV];
+  int32_t interp_points[PW_MAX_SV];
+  int32_t buffer_width;
+  double ko_eps;
+  int32_t schedule;
+  int32_t use_graph;
+  void *stream;
+  void *(*dev_alloc)(uint64_t bytes, void *user);
+  void (*dev_free)(void *ptr, void *user);
+  void *alloc_user;
+} pw_config;
+
+/*
+ * Patch description (Secs. 2.1 and 2.4.1): numerical box [lo,hi] of n cells per axis
+ * (cell-centred), topology map M (Cartesian identity, or spherical (r,theta,phi)),
+ * fixed ZYZ Euler rotation R and centre motion c(t), so that the background
+ * Cartesian coordinates are X_B = c(t) + R M(x').
+ *   motion PW_STATIC: c = c0; PW_LINEAR: c = c0 + vel t;
+ *          PW_CIRCLE: c = c0 + radius (cos(w t + phase), sin(w t + phase), 0), w = speed/radius.
+ *   periodic[a]: axis a wraps (the spherical phi axis; every axis of a periodic global box).
+ *   sv_mask: bit s set if the patch carries state vector s.
+ * The first patch created must be the global one (is_global = 1, Cartesian, static,
+ * unrotated); every later patch is a local patch.
+ */
+typedef struct {
+  int32_t coord;
+  int32_t is_global;
+  int32_t n[3];
+  double lo[3], hi[3];
+  int32_t periodic[3];
+  double euler_zyz[3];
+  int32_t motion;
+  double c0[3], vel[3];
+  double radius, speed, phase;
+  uint32_t sv_mask;
+} pw_patch_desc;
+
+/*
+ * Exact solution of one state vector in the background frame, used for initial
+ * data, the analytic outer boundary (Sec. 3: analytic BCs at the global edge) and
+ * error norms.
+ *   PW_EXACT_PLANE: phi = amp sin(kappa.X - v|kappa| t + phase) + offset  (Eq. wave_solution)
+ *   PW_EXACT_GAUSS: sum of spherical pulses with phi(0) = A exp(-|X-x_c|^2/w^2), d_t phi(0) = 0.
+ */
+typedef struct {
+  int32_t kind;
+  double amp, offset, kappa[3], phase;
+  int32_t n_pulses;
+  double pulse_amp[PW_MAX_PULSES];
+  double pulse_center[PW_MAX_PULSES][3];
+  double pulse_width[PW_MAX_PULSES];
+} pw_exact_desc;
+
+/*
+ * Diagnostics of one patch and state vector over its live cells (all interior cells
+ * of a local patch; cells flagged PW_FLAG_LIVE on the global patch).
+ *   max_abs/sum_sq:          per field
+ *   err_max/err_sum_sq:      per field, against the registered exact solution (0 if none)
+ *   int_rel_err:             sum over live cells of |phi - phi_e| / |phi_e| sqrt(gamma) d^3x'
+ *                            (Sec. 3.2, with sqrt(gamma) = |det dX/dx'| the volume element)
+ *   live_cells, volume:      live cell count and sum of sqrt(gamma) d^3x'
+ */
+typedef struct {
+  double max_abs[5];
+  double sum_sq[5];
+  double err_max[5];
+  double err_sum_sq[5];
+  double int_rel_err;
+  double live_cells;
+  double volume;
+} pw_diag;
+
+/*
+ * Skip and event counters since creation (Secs. 2.4.1-2.4.2: points that cannot be
+ * interpolated are skipped and keep their lower-priority value).
+ *   skip_local:   local ghost points whose global donor stencil was not all live
+ *   skip_eff:     global effective ghosts whose local donor stencil left the interior
+ *   skip_uncover: cells that became live at a step end and could not be interpolated
+ *   n_uncover:    cells that became live at a step end
+ *   steps:        RK4 steps taken
+ */
+typedef struct {
+  int64_t skip_local, skip_eff, skip_uncover, n_uncover, steps;
+} pw_counters_t;
+
+/* Create a context.  cfg is copied.  *out receives the context on success. */
+pw_status pw_create(const pw_config *cfg, pw_context **out);
+
+/* Add a patch; the first one is the global patch.  *id_out receives its id
+ * (0 for the global patch, 1.. for local patches).  Allocates its device buffers. */
+pw_status pw_create_patch(pw_context *ctx, const pw_patch_desc *desc, int32_t *id_out);
+
+/* Register the exact solution of state vector sv (copied). */
+pw_status pw_set_exact(pw_context *ctx, int32_t sv, const pw_exact_desc *ex);
+
+/* Set every patch's interior to its registered exact solution at time t0
+ * (in the patch's frame) and set the current time to t0. */
+pw_status pw_init_exact(pw_context *ctx, double t0);
+
+/* Copy n_elems = 5*n0*n1*n2 FP64 values of patch `patch`, state vector sv, into the
+ * library (src on the host, or on the device if src_is_device) and set the current
+ * time to t0.  Cover flags are recomputed before the next step. */
+pw_status pw_set_state(pw_context *ctx, int32_t patch, int32_t sv, const double *src, int64_t n_elems,
+                       int32_t src_is_device, double t0);
+
+/* Copy the interior of u (FP64) of patch/sv out, layout as pw_set_state. */
+pw_status pw_get_state(pw_context *ctx, int32_t patch, int32_t sv, double *dst, int64_t n_elems,
+                       int32_t dst_is_device);
+
+/* Copy u including ghost cells, [5][n2+6][n1+6][n0+6] FP64, to host memory. */
+pw_status pw_get_state_full(pw_context *ctx, int32_t patch, int32_t sv, double *dst, int64_t n_elems);
+
+/* Copy the cover flags (PW_FLAG_*, one byte per global interior cell, [n2][n1][n0])
+ * and, if cover != NULL, the id of the covering local patch or -1 (Sec. 2.4.2).
+ * Computes them first if the state changed since the last step. */
+pw_status pw_get_flags(pw_context *ctx, uint8_t *flags, int32_t *cover, int64_t n_cells);
+
+/* Fill the ghost cells of u at time t in the order boundary -> periodic ->
+ * interpatch (Sec. 2.4, Fig. BC_order): analytic outer ghosts (or nearest copy),
+ * periodic copies, then global->local and local->global interpolation with the
+ * frame transform through the background frame (Secs. 2.4.1-2.4.2). */
+pw_status pw_exchange_ghosts(pw_context *ctx, double t);
+
+/* Advance nsteps classic-RK4 steps of size dt (Sec. 2.3, Table rk4): per stage a
+ * ghost fill of the stage input at t_n + c_s dt, then the RHS of Eqs. eom1-eom3
+ * with Kreiss-Oliger dissipation and the stage update on every live cell.  Cover
+ * flags are computed at t_n and frozen for the step, maps follow the substep times,
+ * and cells that become live at the step end are interpolated from the covering
+ * local patch (Sec. 2.4.2).  Returns PW_EMOTION before launching if a patch
+ * would move a global cell or more in one step, PW_EOVERLAP if two local patches
+ * cover one global cell. */
+pw_status pw_rk4_step(pw_context *ctx, double dt, int32_t nsteps);
+
+/* Current coordinate time. */
+pw_status pw_get_time(const pw_context *ctx, double *t);
+
+/* Diagnostics of one patch / state vector (synchronous). */
+pw_status pw_diagnostics(pw_context *ctx, int32_t patch, int32_t sv, pw_diag *out);
+
+/* Counters (synchronous). */
+pw_status pw_counters(pw_context *ctx, pw_counters_t *out);
+
+/* Number of live cells evolved per step summed over patches and state vectors
+ * (synchronous; uses the current cover flags). */
+pw_status pw_live_cells(pw_context *ctx, int64_t *out);
+
+/* Kernel classes timed by pw_kernel_times. */
+enum {
+  PW_K_POSE = 0,
+  PW_K_GHOST_S1 = 1, /* ghost fill of stage s (s = 1..4): PW_K_GHOST_S1 + s - 1 */
+  PW_K_STAGE_S1 = 5, /* RHS + RK update of stage s: PW_K_STAGE_S1 + s - 1 */
+  PW_K_FLAGS = 9,    /* cover flags at t_{n+1} */
+  PW_K_FINALIZE = 10, /* uncover fill, poison, flag swap */
+  PW_K_NCLASS = 11
+};
+
+/* Enable (on != 0) or disable per-kernel-class timing.  While enabled, steps run
+ * without the graph and every kernel class is bracketed by hipEvents on the
+ * library's stream; totals accumulate until pw_kernel_times resets them. */
+pw_status pw_enable_timing(pw_context *ctx, int32_t on);
+
+/* Copy the accumulated time (ms) and launch-group count of every kernel class
+ * (arrays of PW_K_NCLASS entries), then reset them (synchronous). */
+pw_status pw_kernel_times(pw_context *ctx, double *total_ms, int64_t *count);
+
+/* Message of the last error on this context (never NULL). */
+const char *pw_last_error(const pw_context *ctx);
+
+/* Free all device memory and the context.  NULL is ignored. */
+void pw_destroy(pw_context *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PW_H */

@@ -1,0 +1,901 @@
+// Host orchestration and C ABI of libpw (see include/pw.h).
+//
+// Owns the patch registry, device buffers, ghost and tile lists, the cover-flag
+// arrays and the captured step graph; every step of the method runs in the HIP
+// kernels of pw_kernels.hip on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pw.h"
+#include "pw_internal.h"
+#include "pw_kernels.h"
+
+using namespace pw;
+
+struct pw_context {
+  pw_config cfg;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<pw_patch_desc> desc;
+  std::vector<PatchDev> hp;
+  std::vector<void *> allocs;
+  PatchDev *dP = nullptr;
+  PoseDev *dPose = nullptr;  // 4 slots x np
+  ExactDev hex[PW_MAXSV];
+  ExactDev *dEx = nullptr;
+  double *dVs = nullptr;
+  int *dPts = nullptr;
+  double *dT = nullptr;       // current time t_n
+  double *dTx = nullptr;      // explicit time for eager calls
+  unsigned long long *dCounters = nullptr;  // skip_local, skip_eff, skip_uncover, n_uncover, steps
+  int *dErr = nullptr;
+  // flags of the global patch
+  long long gcells = 0;
+  uint8_t *flag_cur = nullptr, *flag_new = nullptr, *t1 = nullptr, *t2 = nullptr, *live = nullptr;
+  int32_t *cover_cur = nullptr, *cover_new = nullptr;
+  // lists
+  GhostRec *dLower = nullptr, *dG2L = nullptr;
+  int nLower = 0, nG2L = 0;
+  TileRec *dTiles = nullptr;
+  int nTiles = 0;
+  std::vector<int> tileOff, tileCnt;
+  CoverJob *dJobs = nullptr;
+  int nJobs = 0, coverBlocks = 1;
+  double *dStage = nullptr;  // staging for host copies
+  long long stageCap = 0;
+  double *dPartial = nullptr;
+  bool layout_dirty = true, flags_valid = false;
+  double t_host = 0.0;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  double graph_dt = 0.0;
+  long long steps_done = 0;
+  // per-kernel-class timing (eager path only)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  struct Mark { int cls; hipEvent_t a, b; };
+  std::vector<Mark> marks;
+  double k_ms[PW_K_NCLASS] = {0};
+  long long k_cnt[PW_K_NCLASS] = {0};
+};
+
+namespace {
+
+pw_status fail(pw_context *c, pw_status code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, PW_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void *dalloc(pw_context *c, size_t bytes) {
+  void *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (c->cfg.dev_alloc) {
+    p = c->cfg.dev_alloc((uint64_t)bytes, c->cfg.alloc_user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) c->allocs.push_back(p);
+  return p;
+}
+
+void dfree(pw_context *c, void *p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  if (c->cfg.dev_free) c->cfg.dev_free(p, c->cfg.alloc_user);
+  else (void)hipFree(p);
+}
+
+void euler_zyz(const double e[3], double R[9]) {
+  double ca = cos(e[0]), sa = sin(e[0]), cb = cos(e[1]), sb = sin(e[1]), cc = cos(e[2]), sc = sin(e[2]);
+  // Rz(a) Ry(b) Rz(c)
+  double A[3][3] = {{ca, -sa, 0}, {sa, ca, 0}, {0, 0, 1}};
+  double B[3][3] = {{cb, 0, sb}, {0, 1, 0}, {-sb, 0, cb}};
+  double C[3][3] = {{cc, -sc, 0}, {sc, cc, 0}, {0, 0, 1}};
+  double T[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      T[i][j] = 0;
+      for (int k = 0; k < 3; k++) T[i][j] += B[i][k] * C[k][j];
+    }
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0;
+      for (int k = 0; k < 3; k++) s += A[i][k] * T[k][j];
+      R[3 * i + j] = s;
+    }
+}
+
+double bound_radius(const pw_patch_desc &d) {
+  if (d.coord == PW_SPH) return d.hi[0];
+  double m = 0;
+  for (int c = 0; c < 8; c++) {
+    double y0 = (c & 1) ? d.hi[0] : d.lo[0], y1 = (c & 2) ? d.hi[1] : d.lo[1], y2 = (c & 4) ? d.hi[2] : d.lo[2];
+    m = std::max(m, sqrt(y0 * y0 + y1 * y1 + y2 * y2));
+  }
+  return m;
+}
+
+uint32_t pack_ijk(int i, int j, int k) {
+  return (uint32_t)(i + PW_NG) | ((uint32_t)(j + PW_NG) << 10) | ((uint32_t)(k + PW_NG) << 20);
+}
+
+bool mixed(const pw_context *c) { return c->cfg.precision == PW_MIXED; }
+size_t stage_elem(const pw_context *c) { return mixed(c) ? sizeof(float) : sizeof(double); }
+bool has_locals(const pw_context *c) { return c->hp.size() > 1; }
+
+hipEvent_t take_event(pw_context *c) {
+  if (!c->ev_free.empty()) {
+    hipEvent_t e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Bracket the launches issued between begin/end with events when timing is on.
+struct Timed {
+  pw_context *c;
+  int cls;
+  hipEvent_t a = nullptr;
+  Timed(pw_context *c_, int cls_) : c(c_), cls(cls_) {
+    if (c->timing) {
+      a = take_event(c);
+      (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Timed() {
+    if (c->timing) {
+      hipEvent_t b = take_event(c);
+      (void)hipEventRecord(b, c->stream);
+      c->marks.push_back(pw_context::Mark{cls, a, b});
+    }
+  }
+};
+
+void harvest_marks(pw_context *c) {
+  for (auto &m : c->marks) {
+    float ms = 0;
+    (void)hipEventSynchronize(m.b);
+    (void)hipEventElapsedTime(&ms, m.a, m.b);
+    c->k_ms[m.cls] += ms;
+    c->k_cnt[m.cls] += 1;
+    c->ev_free.push_back(m.a);
+    c->ev_free.push_back(m.b);
+  }
+  c->marks.clear();
+}
+
+pw_status upload_layout(pw_context *c) {
+  if (!c->layout_dirty) return PW_OK;
+  if (c->hp.empty()) return fail(c, PW_ESTATE, "no global patch");
+  int np = (int)c->hp.size();
+  dfree(c, c->dP);
+  dfree(c, c->dPose);
+  c->dP = (PatchDev *)dalloc(c, sizeof(PatchDev) * np);
+  c->dPose = (PoseDev *)dalloc(c, sizeof(PoseDev) * 4 * np);
+  if (!c->dP || !c->dPose) return fail(c, PW_ENOMEM, "device allocation failed");
+  HIPCHK(c, hipMemcpyAsync(c->dP, c->hp.data(), sizeof(PatchDev) * np, hipMemcpyHostToDevice, c->stream));
+
+  // Ghost lists: lower-priority ghosts (periodic copies, global outer ghosts) and
+  // the interpatch targets of every local patch (non-periodic ghost cells).
+  std::vector<GhostRec> lower, g2l;
+  for (int pid = 0; pid < np; pid++) {
+    const PatchDev &p = c->hp[pid];
+    for (int k = -PW_NG; k < p.n[2] + PW_NG; k++)
+      for (int j = -PW_NG; j < p.n[1] + PW_NG; j++)
+        for (int i = -PW_NG; i < p.n[0] + PW_NG; i++) {
+          int cc[3] = {i, j, k};
+          bool inside = true, wrapped_inside = true;
+          for (int a = 0; a < 3; a++) {
+            inside = inside && cc[a] >= 0 && cc[a] < p.n[a];
+            int w = p.periodic[a] ? ((cc[a] % p.n[a]) + p.n[a]) % p.n[a] : cc[a];
+            wrapped_inside = wrapped_inside && w >= 0 && w < p.n[a];
+          }
+          if (inside) continue;
+          GhostRec g{pid, pack_ijk(i, j, k)};
+          if (wrapped_inside || p.is_global) lower.push_back(g);
+          else g2l.push_back(g);
+        }
+  }
+  dfree(c, c->dLower);
+  dfree(c, c->dG2L);
+  c->nLower = (int)lower.size();
+  c->nG2L = (int)g2l.size();
+  c->dLower = (GhostRec *)dalloc(c, sizeof(GhostRec) * std::max<size_t>(1, lower.size()));
+  c->dG2L = (GhostRec *)dalloc(c, sizeof(GhostRec) * std::max<size_t>(1, g2l.size()));
+  if (!c->dLower || !c->dG2L) return fail(c, PW_ENOMEM, "device allocation failed");
+  if (!lower.empty())
+    HIPCHK(c, hipMemcpy(c->dLower, lower.data(), sizeof(GhostRec) * lower.size(), hipMemcpyHostToDevice));
+  if (!g2l.empty()) HIPCHK(c, hipMemcpy(c->dG2L, g2l.data(), sizeof(GhostRec) * g2l.size(), hipMemcpyHostToDevice));
+
+  // Tiles of every patch, grouped by patch.
+  std::vector<TileRec> tiles;
+  c->tileOff.assign(np, 0);
+  c->tileCnt.assign(np, 0);
+  for (int pid = 0; pid < np; pid++) {
+    const PatchDev &p = c->hp[pid];
+    c->tileOff[pid] = (int)tiles.size();
+    for (int z = 0; z < p.n[2]; z += TILE_Z)
+      for (int y = 0; y < p.n[1]; y += TILE_Y)
+        for (int x = 0; x < p.n[0]; x += TILE_X) tiles.push_back(TileRec{pid, x, y, z});
+    c->tileCnt[pid] = (int)tiles.size() - c->tileOff[pid];
+  }
+  dfree(c, c->dTiles);
+  c->nTiles = (int)tiles.size();
+  c->dTiles = (TileRec *)dalloc(c, sizeof(TileRec) * tiles.size());
+  if (!c->dTiles) return fail(c, PW_ENOMEM, "device allocation failed");
+  HIPCHK(c, hipMemcpy(c->dTiles, tiles.data(), sizeof(TileRec) * tiles.size(), hipMemcpyHostToDevice));
+
+  // Cover scans of the local patches.
+  std::vector<CoverJob> jobs;
+  const PatchDev &g = c->hp[0];
+  long long maxcells = 0;
+  for (int pid = 1; pid < np; pid++) {
+    CoverJob J;
+    J.patch = pid;
+    J.radius = bound_radius(c->desc[pid]) * (1.0 + 1e-12) + 1e-12;
+    long long tot = 1;
+    for (int a = 0; a < 3; a++) {
+      J.ext[a] = (int)ceil(2.0 * J.radius * g.idx[a]) + 3;
+      tot *= J.ext[a];
+    }
+    maxcells = std::max(maxcells, tot);
+    jobs.push_back(J);
+  }
+  dfree(c, c->dJobs);
+  c->nJobs = (int)jobs.size();
+  c->coverBlocks = (int)std::min<long long>(std::max<long long>(1, (maxcells + 255) / 256), 2048);
+  c->dJobs = (CoverJob *)dalloc(c, sizeof(CoverJob) * std::max<size_t>(1, jobs.size()));
+  if (!c->dJobs) return fail(c, PW_ENOMEM, "device allocation failed");
+  if (!jobs.empty()) HIPCHK(c, hipMemcpy(c->dJobs, jobs.data(), sizeof(CoverJob) * jobs.size(), hipMemcpyHostToDevice));
+
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+  }
+  c->layout_dirty = false;
+  c->flags_valid = false;
+  return PW_OK;
+}
+
+pw_status set_time(pw_context *c, double *dptr, double t) {
+  HIPCHK(c, hipMemcpyAsync(dptr, &t, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PW_OK;
+}
+
+void enqueue_flags(pw_context *c, const PoseDev *pose_slot) {
+  FlagsArgs a;
+  a.P = c->dP;
+  a.pose = pose_slot;
+  a.jobs = c->dJobs;
+  a.njobs = c->nJobs;
+  a.cover_blocks = c->coverBlocks;
+  a.cover_new = c->cover_new;
+  a.t1 = c->t1;
+  a.t2 = c->t2;
+  a.live = c->live;
+  a.flag_new = c->flag_new;
+  for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
+  a.buffer = c->cfg.buffer_width;
+  a.err = c->dErr;
+  launch_flags(c->stream, a);
+}
+
+void enqueue_finalize(pw_context *c, const PoseDev *pose_slot, int mode) {
+  FinalizeArgs a;
+  a.P = c->dP;
+  a.pose = pose_slot;
+  a.flag_cur = c->flag_cur;
+  a.flag_new = c->flag_new;
+  a.cover_cur = c->cover_cur;
+  a.cover_new = c->cover_new;
+  a.nsv = c->cfg.n_state_vectors;
+  a.Pts = c->dPts;
+  a.ex = c->dEx;
+  a.vs = c->dVs;
+  a.tdev = c->dT;
+  a.mode = mode;
+  a.counters = c->dCounters;
+  for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
+  launch_finalize(c->stream, a);
+}
+
+// Ghost fill of the buffers of `stage` (0: u) at time tdev[0] + tmul*dt.
+void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const double *tdev, double tmul, double dt) {
+  for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
+    GhostArgs a;
+    a.P = c->dP;
+    a.pose = pose_slot;
+    a.lower = c->dLower;
+    a.n_lower = c->nLower;
+    a.g2l = c->dG2L;
+    a.n_g2l = c->nG2L;
+    a.gflag = has_locals(c) ? c->flag_cur : nullptr;
+    a.cover = c->cover_cur;
+    a.has_locals = has_locals(c);
+    for (int d = 0; d < 3; d++) a.gn[d] = c->hp[0].n[d];
+    a.sv = sv;
+    a.stage = stage;
+    a.stage_fp64 = (stage == 0) || !mixed(c);
+    a.mixed = mixed(c);
+    a.Pts = c->cfg.interp_points[sv];
+    a.ex = c->dEx;
+    a.v = c->cfg.wave_speed[sv];
+    a.tdev = tdev;
+    a.tmul = tmul;
+    a.dt = dt;
+    a.skips = c->dCounters;
+    launch_ghosts(c->stream, a);
+  }
+}
+
+void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt) {
+  for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
+    StageArgs a;
+    a.P = c->dP;
+    a.pose = pose_slot;
+    a.gflag = has_locals(c) ? c->flag_cur : nullptr;
+    a.sv = sv;
+    a.stage = stage;
+    a.mixed = mixed(c);
+    a.dt = dt;
+    a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
+    a.eps = c->cfg.ko_eps;
+    if (c->cfg.schedule == PW_SCHED_PER_PATCH) {
+      for (size_t pid = 0; pid < c->hp.size(); pid++) {
+        if (!(c->hp[pid].sv_mask & (1u << sv))) continue;
+        a.tiles = c->dTiles + c->tileOff[pid];
+        a.ntiles = c->tileCnt[pid];
+        launch_stage(c->stream, a);
+      }
+    } else {
+      // batched: all tiles of every patch carrying sv in one launch
+      a.tiles = c->dTiles;
+      a.ntiles = c->nTiles;
+      bool all = true;
+      for (auto &p : c->hp) all = all && (p.sv_mask & (1u << sv));
+      if (all) {
+        launch_stage(c->stream, a);
+      } else {
+        for (size_t pid = 0; pid < c->hp.size(); pid++) {
+          if (!(c->hp[pid].sv_mask & (1u << sv))) continue;
+          a.tiles = c->dTiles + c->tileOff[pid];
+          a.ntiles = c->tileCnt[pid];
+          launch_stage(c->stream, a);
+        }
+      }
+    }
+  }
+}
+
+void enqueue_step(pw_context *c, double dt) {
+  int np = (int)c->hp.size();
+  {
+    Timed tm(c, PW_K_POSE);
+    launch_pose(c->stream, c->dP, np, c->dT, dt, c->dPose);
+  }
+  static const int slot_of_stage[4] = {0, 1, 1, 2};
+  static const double tmul[4] = {0.0, 0.5, 0.5, 1.0};
+  for (int s = 0; s < 4; s++) {
+    const PoseDev *ps = c->dPose + slot_of_stage[s] * np;
+    {
+      Timed tm(c, PW_K_GHOST_S1 + s);
+      enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt);
+    }
+    {
+      Timed tm(c, PW_K_STAGE_S1 + s);
+      enqueue_stage(c, s, ps, dt);
+    }
+  }
+  launch_advance_time(c->stream, c->dT, dt, (long long *)c->dCounters);
+  if (has_locals(c)) {
+    {
+      Timed tm(c, PW_K_FLAGS);
+      enqueue_flags(c, c->dPose + 2 * np);
+    }
+    Timed tm(c, PW_K_FINALIZE);
+    enqueue_finalize(c, c->dPose + 2 * np, 1);
+  }
+}
+
+pw_status ensure_flags(pw_context *c) {
+  pw_status rc = upload_layout(c);
+  if (rc) return rc;
+  if (c->flags_valid) return PW_OK;
+  int np = (int)c->hp.size();
+  if (has_locals(c)) {
+    launch_pose(c->stream, c->dP, np, c->dT, 0.0, c->dPose);
+    enqueue_flags(c, c->dPose);
+    enqueue_finalize(c, c->dPose, 0);
+    int err = 0;
+    HIPCHK(c, hipMemcpyAsync(&err, c->dErr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (err) return fail(c, PW_EOVERLAP, "two local patches cover one global cell");
+  }
+  HIPCHK(c, hipGetLastError());
+  c->flags_valid = true;
+  return PW_OK;
+}
+
+pw_status check_error_flag(pw_context *c) {
+  int err = 0;
+  HIPCHK(c, hipMemcpyAsync(&err, c->dErr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (err) return fail(c, PW_EOVERLAP, "two local patches cover one global cell");
+  return PW_OK;
+}
+
+pw_status ensure_stage(pw_context *c, long long n) {
+  if (n <= c->stageCap) return PW_OK;
+  dfree(c, c->dStage);
+  c->dStage = (double *)dalloc(c, sizeof(double) * n);
+  if (!c->dStage) return fail(c, PW_ENOMEM, "device allocation failed");
+  c->stageCap = n;
+  return PW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pw_status pw_create(const pw_config *cfg, pw_context **out) {
+  if (!cfg || !out) return PW_EINVAL;
+  *out = nullptr;
+  if (cfg->n_state_vectors < 1 || cfg->n_state_vectors > PW_MAX_SV) return PW_EINVAL;
+  if (cfg->precision != PW_FP64 && cfg->precision != PW_MIXED) return PW_EINVAL;
+  if (cfg->buffer_width < 4) return PW_EINVAL;
+  for (int s = 0; s < cfg->n_state_vectors; s++) {
+    if (cfg->interp_points[s] != 5 && cfg->interp_points[s] != 6) return PW_EINVAL;
+    if (!(cfg->wave_speed[s] > 0)) return PW_EINVAL;
+  }
+  if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return PW_EINVAL;
+  pw_context *c = new (std::nothrow) pw_context();
+  if (!c) return PW_ENOMEM;
+  c->cfg = *cfg;
+  if (cfg->stream) {
+    c->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return PW_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  for (int s = 0; s < PW_MAXSV; s++) memset(&c->hex[s], 0, sizeof(ExactDev));
+  c->dEx = (ExactDev *)dalloc(c, sizeof(ExactDev) * PW_MAXSV);
+  c->dVs = (double *)dalloc(c, sizeof(double) * PW_MAXSV);
+  c->dPts = (int *)dalloc(c, sizeof(int) * PW_MAXSV);
+  c->dT = (double *)dalloc(c, sizeof(double));
+  c->dTx = (double *)dalloc(c, sizeof(double));
+  c->dCounters = (unsigned long long *)dalloc(c, sizeof(unsigned long long) * 8);
+  c->dErr = (int *)dalloc(c, sizeof(int));
+  c->dPartial = (double *)dalloc(c, sizeof(double) * 1024 * DIAG_N);
+  if (!c->dEx || !c->dVs || !c->dPts || !c->dT || !c->dTx || !c->dCounters || !c->dErr || !c->dPartial) {
+    pw_destroy(c);
+    return PW_ENOMEM;
+  }
+  double vs[PW_MAXSV] = {0, 0, 0, 0};
+  int pts[PW_MAXSV] = {6, 6, 6, 6};
+  for (int s = 0; s < cfg->n_state_vectors; s++) {
+    vs[s] = cfg->wave_speed[s];
+    pts[s] = cfg->interp_points[s];
+  }
+  unsigned long long zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int zero = 0;
+  double t0 = 0.0;
+  if (hipMemcpy(c->dEx, c->hex, sizeof(ExactDev) * PW_MAXSV, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dVs, vs, sizeof(vs), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dPts, pts, sizeof(pts), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dT, &t0, sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dCounters, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dErr, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    pw_destroy(c);
+    return PW_EDEVICE;
+  }
+  *out = c;
+  return PW_OK;
+}
+
+pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out) {
+  if (!c || !d) return PW_EINVAL;
+  bool first = c->hp.empty();
+  if ((d->is_global != 0) != first) return fail(c, PW_EINVAL, "the first patch, and only it, is the global patch");
+  for (int a = 0; a < 3; a++) {
+    if (d->n[a] < 1 || d->n[a] + 2 * PW_NG > 1023) return fail(c, PW_EINVAL, "cells per axis must be in [1, 1017]");
+    if (!(d->hi[a] > d->lo[a])) return fail(c, PW_EINVAL, "empty numerical box");
+    if (d->periodic[a] && d->n[a] < PW_NG) return fail(c, PW_EINVAL, "periodic axis needs at least 3 cells");
+  }
+  if (d->coord != PW_CART && d->coord != PW_SPH) return fail(c, PW_EINVAL, "unknown topology");
+  if (d->motion < PW_STATIC || d->motion > PW_CIRCLE) return fail(c, PW_EINVAL, "unknown motion");
+  if (d->motion == PW_CIRCLE && !(d->radius > 0)) return fail(c, PW_EINVAL, "circle motion needs radius > 0");
+  if (first) {
+    if (d->coord != PW_CART || d->motion != PW_STATIC || d->euler_zyz[0] != 0 || d->euler_zyz[1] != 0 ||
+        d->euler_zyz[2] != 0 || d->c0[0] != 0 || d->c0[1] != 0 || d->c0[2] != 0)
+      return fail(c, PW_EINVAL, "the global patch is Cartesian, static and unrotated");
+  } else {
+    if (d->periodic[0] || d->periodic[1] || (d->periodic[2] && d->coord != PW_SPH))
+      return fail(c, PW_EINVAL, "local patches are periodic only along the spherical phi axis");
+    if (d->coord == PW_SPH && !(d->lo[0] > 0)) return fail(c, PW_EINVAL, "spherical patch needs r_min > 0");
+  }
+  if (d->coord == PW_SPH) {
+    double th_lo = d->lo[1] - PW_NG * (d->hi[1] - d->lo[1]) / d->n[1];
+    double th_hi = d->hi[1] + PW_NG * (d->hi[1] - d->lo[1]) / d->n[1];
+    double r_lo = d->lo[0] - PW_NG * (d->hi[0] - d->lo[0]) / d->n[0];
+    if (!(th_lo > 0 && th_hi < M_PI && r_lo > 0)) return fail(c, PW_EINVAL, "spherical ghosts must avoid r=0 and the poles");
+    if (d->periodic[2] && fabs(d->hi[2] - d->lo[2] - 2 * M_PI) > 1e-12)
+      return fail(c, PW_EINVAL, "periodic phi axis must span 2 pi");
+  }
+  unsigned mask_all = (1u << c->cfg.n_state_vectors) - 1u;
+  if ((d->sv_mask & ~mask_all) || d->sv_mask == 0) return fail(c, PW_EINVAL, "bad state-vector mask");
+  if (!first && c->hp.size() >= 4096) return fail(c, PW_EINVAL, "too many patches");
+
+  PatchDev p;
+  memset(&p, 0, sizeof(p));
+  p.coord = d->coord;
+  p.is_global = d->is_global ? 1 : 0;
+  p.motion = d->motion;
+  for (int a = 0; a < 3; a++) {
+    p.n[a] = d->n[a];
+    p.periodic[a] = d->periodic[a] ? 1 : 0;
+    p.lo[a] = d->lo[a];
+    p.hi[a] = d->hi[a];
+    p.dx[a] = (d->hi[a] - d->lo[a]) / d->n[a];
+    p.idx[a] = 1.0 / p.dx[a];
+    p.c0[a] = d->c0[a];
+    p.vel[a] = d->vel[a];
+  }
+  p.radius = d->radius;
+  p.omega = d->motion == PW_CIRCLE ? d->speed / d->radius : 0.0;
+  p.phase = d->phase;
+  euler_zyz(d->euler_zyz, p.R);
+  p.sv_mask = d->sv_mask;
+  p.pitch = ((PW_OX + p.n[0] + PW_NG) + 7) / 8 * 8;
+  p.rows = p.n[1] + 2 * PW_NG;
+  p.slabs = p.n[2] + 2 * PW_NG;
+  p.slab = (long long)p.pitch * p.rows;
+  p.fstride = p.slab * p.slabs;
+  long long nel = 5 * p.fstride;
+  for (int s = 0; s < c->cfg.n_state_vectors; s++) {
+    if (!(d->sv_mask & (1u << s))) continue;
+    p.u[s] = (double *)dalloc(c, sizeof(double) * nel);
+    p.acc[s] = (double *)dalloc(c, sizeof(double) * nel);
+    p.va[s] = dalloc(c, stage_elem(c) * nel);
+    p.vb[s] = dalloc(c, stage_elem(c) * nel);
+    if (!p.u[s] || !p.acc[s] || !p.va[s] || !p.vb[s]) return fail(c, PW_ENOMEM, "device allocation failed");
+    launch_fill_f64(c->stream, p.u[s], nel, NAN);
+    launch_fill_f64(c->stream, p.acc[s], nel, NAN);
+    if (mixed(c)) {
+      launch_fill_f32(c->stream, (float *)p.va[s], nel, NAN);
+      launch_fill_f32(c->stream, (float *)p.vb[s], nel, NAN);
+    } else {
+      launch_fill_f64(c->stream, (double *)p.va[s], nel, NAN);
+      launch_fill_f64(c->stream, (double *)p.vb[s], nel, NAN);
+    }
+  }
+  if (first) {
+    c->gcells = (long long)p.n[0] * p.n[1] * p.n[2];
+    c->flag_cur = (uint8_t *)dalloc(c, c->gcells);
+    c->flag_new = (uint8_t *)dalloc(c, c->gcells);
+    c->t1 = (uint8_t *)dalloc(c, c->gcells);
+    c->t2 = (uint8_t *)dalloc(c, c->gcells);
+    c->live = (uint8_t *)dalloc(c, c->gcells);
+    c->cover_cur = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
+    c->cover_new = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
+    if (!c->flag_cur || !c->flag_new || !c->t1 || !c->t2 || !c->live || !c->cover_cur || !c->cover_new)
+      return fail(c, PW_ENOMEM, "device allocation failed");
+    launch_fill_u8(c->stream, c->flag_cur, c->gcells, LIVE);
+    launch_fill_u8(c->stream, c->flag_new, c->gcells, LIVE);
+    launch_fill_i32(c->stream, c->cover_cur, c->gcells, -1);
+    launch_fill_i32(c->stream, c->cover_new, c->gcells, -1);
+  }
+  HIPCHK(c, hipGetLastError());
+  c->hp.push_back(p);
+  c->desc.push_back(*d);
+  c->layout_dirty = true;
+  c->flags_valid = false;
+  if (id_out) *id_out = (int32_t)c->hp.size() - 1;
+  return PW_OK;
+}
+
+pw_status pw_set_exact(pw_context *c, int32_t sv, const pw_exact_desc *ex) {
+  if (!c || !ex || sv < 0 || sv >= c->cfg.n_state_vectors) return PW_EINVAL;
+  ExactDev e;
+  memset(&e, 0, sizeof(e));
+  e.kind = ex->kind;
+  if (ex->kind == PW_EXACT_PLANE) {
+    e.amp = ex->amp;
+    e.offset = ex->offset;
+    e.phase = ex->phase;
+    for (int a = 0; a < 3; a++) e.kappa[a] = ex->kappa[a];
+    e.knorm = sqrt(e.kappa[0] * e.kappa[0] + e.kappa[1] * e.kappa[1] + e.kappa[2] * e.kappa[2]);
+  } else if (ex->kind == PW_EXACT_GAUSS) {
+    if (ex->n_pulses < 0 || ex->n_pulses > PW_MAX_PULSES) return fail(c, PW_EINVAL, "too many pulses");
+    e.n = ex->n_pulses;
+    for (int g = 0; g < e.n; g++) {
+      if (!(ex->pulse_width[g] > 0)) return fail(c, PW_EINVAL, "pulse width must be > 0");
+      e.pa[g] = ex->pulse_amp[g];
+      e.pw[g] = ex->pulse_width[g];
+      for (int a = 0; a < 3; a++) e.px[g][a] = ex->pulse_center[g][a];
+    }
+  } else if (ex->kind != PW_EXACT_NONE) {
+    return fail(c, PW_EINVAL, "unknown exact-solution kind");
+  }
+  c->hex[sv] = e;
+  HIPCHK(c, hipMemcpyAsync(c->dEx + sv, &c->hex[sv], sizeof(ExactDev), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PW_OK;
+}
+
+pw_status pw_init_exact(pw_context *c, double t0) {
+  if (!c) return PW_EINVAL;
+  pw_status rc = upload_layout(c);
+  if (rc) return rc;
+  rc = set_time(c, c->dT, t0);
+  if (rc) return rc;
+  int np = (int)c->hp.size();
+  launch_pose_at(c->stream, c->dP, np, t0, c->dPose + 3 * np);
+  for (int pid = 0; pid < np; pid++)
+    for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
+      if (!(c->hp[pid].sv_mask & (1u << sv)) || c->hex[sv].kind == PW_EXACT_NONE) continue;
+      long long ncell = (long long)c->hp[pid].n[0] * c->hp[pid].n[1] * c->hp[pid].n[2];
+      launch_init_exact(c->stream, c->dP, c->dPose + 3 * np, pid, sv, c->dEx, c->cfg.wave_speed[sv], t0, ncell);
+    }
+  HIPCHK(c, hipGetLastError());
+  c->t_host = t0;
+  c->flags_valid = false;
+  return PW_OK;
+}
+
+pw_status pw_set_state(pw_context *c, int32_t pid, int32_t sv, const double *src, int64_t n, int32_t is_dev,
+                       double t0) {
+  if (!c || !src || pid < 0 || pid >= (int)c->hp.size() || sv < 0 || sv >= c->cfg.n_state_vectors) return PW_EINVAL;
+  const PatchDev &p = c->hp[pid];
+  if (!(p.sv_mask & (1u << sv))) return fail(c, PW_EINVAL, "patch does not carry this state vector");
+  long long need = 5LL * p.n[0] * p.n[1] * p.n[2];
+  if (n != need) return fail(c, PW_EINVAL, "element count does not match 5*n0*n1*n2");
+  pw_status rc = upload_layout(c);
+  if (rc) return rc;
+  const double *dsrc = src;
+  if (!is_dev) {
+    rc = ensure_stage(c, need);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->dStage, src, sizeof(double) * need, hipMemcpyHostToDevice, c->stream));
+    dsrc = c->dStage;
+  }
+  launch_unpack(c->stream, c->dP, pid, sv, dsrc, need);
+  HIPCHK(c, hipGetLastError());
+  rc = set_time(c, c->dT, t0);
+  if (rc) return rc;
+  c->t_host = t0;
+  c->flags_valid = false;
+  return PW_OK;
+}
+
+static pw_status get_common(pw_context *c, int32_t pid, int32_t sv, double *dst, int64_t n, int32_t is_dev, int full) {
+  if (!c || !dst || pid < 0 || pid >= (int)c->hp.size() || sv < 0 || sv >= c->cfg.n_state_vectors) return PW_EINVAL;
+  const PatchDev &p = c->hp[pid];
+  if (!(p.sv_mask & (1u << sv))) return fail(c, PW_EINVAL, "patch does not carry this state vector");
+  int g = full ? 2 * PW_NG : 0;
+  long long need = 5LL * (p.n[0] + g) * (p.n[1] + g) * (p.n[2] + g);
+  if (n != need) return fail(c, PW_EINVAL, "element count does not match");
+  pw_status rc = upload_layout(c);
+  if (rc) return rc;
+  double *ddst = dst;
+  if (!is_dev) {
+    rc = ensure_stage(c, need);
+    if (rc) return rc;
+    ddst = c->dStage;
+  }
+  launch_pack(c->stream, c->dP, pid, sv, ddst, need, full);
+  HIPCHK(c, hipGetLastError());
+  if (!is_dev) HIPCHK(c, hipMemcpyAsync(dst, ddst, sizeof(double) * need, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PW_OK;
+}
+
+pw_status pw_get_state(pw_context *c, int32_t pid, int32_t sv, double *dst, int64_t n, int32_t is_dev) {
+  return get_common(c, pid, sv, dst, n, is_dev, 0);
+}
+
+pw_status pw_get_state_full(pw_context *c, int32_t pid, int32_t sv, double *dst, int64_t n) {
+  return get_common(c, pid, sv, dst, n, 0, 1);
+}
+
+pw_status pw_get_flags(pw_context *c, uint8_t *flags, int32_t *cover, int64_t n) {
+  if (!c || !flags) return PW_EINVAL;
+  if (c->hp.empty()) return fail(c, PW_ESTATE, "no global patch");
+  if (n != c->gcells) return fail(c, PW_EINVAL, "cell count does not match the global patch");
+  pw_status rc = ensure_flags(c);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(flags, c->flag_cur, c->gcells, hipMemcpyDeviceToHost, c->stream));
+  if (cover)
+    HIPCHK(c, hipMemcpyAsync(cover, c->cover_cur, sizeof(int32_t) * c->gcells, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PW_OK;
+}
+
+pw_status pw_exchange_ghosts(pw_context *c, double t) {
+  if (!c) return PW_EINVAL;
+  pw_status rc = ensure_flags(c);
+  if (rc) return rc;
+  int np = (int)c->hp.size();
+  rc = set_time(c, c->dTx, t);
+  if (rc) return rc;
+  launch_pose_at(c->stream, c->dP, np, t, c->dPose + 3 * np);
+  enqueue_ghosts(c, 0, c->dPose + 3 * np, c->dTx, 0.0, 0.0);
+  HIPCHK(c, hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw_rk4_step(pw_context *c, double dt, int32_t nsteps) {
+  if (!c || !(dt > 0) || nsteps < 0) return PW_EINVAL;
+  if (c->hp.empty()) return fail(c, PW_ESTATE, "no global patch");
+  // The NG+1 buffer lets a patch cross at most one global cell per step.
+  const PatchDev &g = c->hp[0];
+  double hmin = std::min(g.dx[0], std::min(g.dx[1], g.dx[2]));
+  for (size_t pid = 1; pid < c->hp.size(); pid++) {
+    const pw_patch_desc &d = c->desc[pid];
+    double sp = 0;
+    if (d.motion == PW_LINEAR) sp = sqrt(d.vel[0] * d.vel[0] + d.vel[1] * d.vel[1] + d.vel[2] * d.vel[2]);
+    if (d.motion == PW_CIRCLE) sp = fabs(d.speed);
+    if (sp * dt >= hmin) return fail(c, PW_EMOTION, "a patch moves one global cell or more within a step");
+  }
+  pw_status rc = ensure_flags(c);
+  if (rc) return rc;
+  bool graph = c->cfg.use_graph && c->cfg.schedule == PW_SCHED_BATCHED && !c->timing;
+  if (graph && (c->gexec == nullptr || c->graph_dt != dt)) {
+    if (c->gexec) {
+      (void)hipGraphExecDestroy(c->gexec);
+      (void)hipGraphDestroy(c->graph);
+      c->gexec = nullptr;
+    }
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_step(c, dt);
+    HIPCHK(c, hipStreamEndCapture(c->stream, &c->graph));
+    HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    c->graph_dt = dt;
+  }
+  for (int n = 0; n < nsteps; n++) {
+    if (graph) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    else enqueue_step(c, dt);
+    c->t_host = c->t_host + dt;
+  }
+  HIPCHK(c, hipGetLastError());
+  c->steps_done += nsteps;
+  return PW_OK;
+}
+
+pw_status pw_get_time(const pw_context *c, double *t) {
+  if (!c || !t) return PW_EINVAL;
+  *t = c->t_host;
+  return PW_OK;
+}
+
+pw_status pw_diagnostics(pw_context *c, int32_t pid, int32_t sv, pw_diag *out) {
+  if (!c || !out || pid < 0 || pid >= (int)c->hp.size() || sv < 0 || sv >= c->cfg.n_state_vectors) return PW_EINVAL;
+  if (!(c->hp[pid].sv_mask & (1u << sv))) return fail(c, PW_EINVAL, "patch does not carry this state vector");
+  pw_status rc = ensure_flags(c);
+  if (rc) return rc;
+  rc = check_error_flag(c);
+  if (rc) return rc;
+  int np = (int)c->hp.size();
+  launch_pose_at(c->stream, c->dP, np, c->t_host, c->dPose + 3 * np);
+  const int nb = 1024;
+  launch_diag(c->stream, c->dP, c->dPose + 3 * np, pid, sv, has_locals(c) ? c->flag_cur : nullptr, c->dEx,
+              c->cfg.wave_speed[sv], c->t_host, c->dPartial, nb);
+  HIPCHK(c, hipGetLastError());
+  std::vector<double> h((size_t)nb * DIAG_N);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->dPartial, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double acc[DIAG_N];
+  for (int x = 0; x < DIAG_N; x++) acc[x] = 0;
+  for (int b = 0; b < nb; b++)
+    for (int x = 0; x < DIAG_N; x++) {
+      double v = h[(size_t)b * DIAG_N + x];
+      bool mx = (x < 5) || (x >= 10 && x < 15);
+      acc[x] = mx ? std::max(acc[x], v) : acc[x] + v;
+    }
+  for (int f = 0; f < 5; f++) {
+    out->max_abs[f] = acc[f];
+    out->sum_sq[f] = acc[5 + f];
+    out->err_max[f] = acc[10 + f];
+    out->err_sum_sq[f] = acc[15 + f];
+  }
+  out->int_rel_err = acc[20];
+  out->live_cells = acc[21];
+  out->volume = acc[22];
+  return PW_OK;
+}
+
+pw_status pw_counters(pw_context *c, pw_counters_t *out) {
+  if (!c || !out) return PW_EINVAL;
+  if (c->dCounters == nullptr) return fail(c, PW_ESTATE, "no counters");
+  unsigned long long h[8];
+  HIPCHK(c, hipMemcpyAsync(h, c->dCounters, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  out->skip_local = (int64_t)h[0];
+  out->skip_eff = (int64_t)h[1];
+  out->skip_uncover = (int64_t)h[2];
+  out->n_uncover = (int64_t)h[3];
+  out->steps = (int64_t)h[4];
+  return check_error_flag(c);
+}
+
+pw_status pw_live_cells(pw_context *c, int64_t *out) {
+  if (!c || !out) return PW_EINVAL;
+  if (c->hp.empty()) return fail(c, PW_ESTATE, "no global patch");
+  pw_status rc = ensure_flags(c);
+  if (rc) return rc;
+  std::vector<uint8_t> f(c->gcells);
+  HIPCHK(c, hipMemcpyAsync(f.data(), c->flag_cur, c->gcells, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  long long glive = 0;
+  for (long long x = 0; x < c->gcells; x++) glive += f[x] == LIVE;
+  long long tot = 0;
+  for (size_t pid = 0; pid < c->hp.size(); pid++) {
+    const PatchDev &p = c->hp[pid];
+    long long cells = pid == 0 ? glive : (long long)p.n[0] * p.n[1] * p.n[2];
+    tot += cells * __builtin_popcount(p.sv_mask);
+  }
+  *out = tot;
+  return PW_OK;
+}
+
+pw_status pw_enable_timing(pw_context *c, int32_t on) {
+  if (!c) return PW_EINVAL;
+  c->timing = on != 0;
+  return PW_OK;
+}
+
+pw_status pw_kernel_times(pw_context *c, double *total_ms, int64_t *count) {
+  if (!c || !total_ms || !count) return PW_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  harvest_marks(c);
+  for (int k = 0; k < PW_K_NCLASS; k++) {
+    total_ms[k] = c->k_ms[k];
+    count[k] = c->k_cnt[k];
+    c->k_ms[k] = 0;
+    c->k_cnt[k] = 0;
+  }
+  return PW_OK;
+}
+
+const char *pw_last_error(const pw_context *c) { return c ? c->err.c_str() : "null context"; }
+
+void pw_destroy(pw_context *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    (void)hipGraphDestroy(c->graph);
+  }
+  harvest_marks(c);
+  for (auto e : c->ev_free) (void)hipEventDestroy(e);
+  std::vector<void *> all = c->allocs;
+  for (void *p : all) dfree(c, p);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

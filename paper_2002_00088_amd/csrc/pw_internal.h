@@ -1,0 +1,263 @@
+// Internal device-side data structures and math of libpw (gfx950).
+//
+// Patch arrays are padded by NG = 3 ghost cells per side; each x-row is laid out
+// [5 alignment pad][3 ghosts][n0 interior][3 ghosts][pad to a multiple of 8], so
+// the first interior element of every row starts 64-byte aligned in FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PW_NG 3
+#define PW_OX 8          // row offset of interior cell i = 0
+#define PW_MAXSV 4
+#define PW_MAXPULSE 32
+
+namespace pw {
+
+enum { CART = 0, SPH = 1 };
+enum { STATIC = 0, LINEAR = 1, CIRCLE = 2 };
+enum { LIVE = 0, EFFGHOST = 1, DEACT = 2 };
+enum { EX_NONE = 0, EX_PLANE = 1, EX_GAUSS = 2 };
+
+struct PatchDev {
+  int coord, is_global, motion;
+  int n[3];
+  int periodic[3];
+  int pitch;            // elements per padded x-row
+  int rows;             // n1 + 6
+  int slabs;            // n2 + 6
+  long long slab;       // pitch * rows
+  long long fstride;    // elements per field (slab * slabs)
+  double lo[3], hi[3], dx[3], idx[3];
+  double R[9];          // row-major rotation, X = c + R y
+  double c0[3], vel[3], radius, omega, phase;
+  unsigned sv_mask;
+  double *u[PW_MAXSV];
+  double *acc[PW_MAXSV];
+  void *va[PW_MAXSV];
+  void *vb[PW_MAXSV];
+};
+
+// Pose of a patch at one stage time: centre, its first and second time
+// derivatives, and their components along the patch axes (b = R^T c', a = R^T c'').
+struct PoseDev {
+  double c[3], cd[3], cdd[3], b[3], a[3];
+};
+
+struct ExactDev {
+  int kind;
+  double amp, offset, kappa[3], phase, knorm;
+  int n;
+  double pa[PW_MAXPULSE], px[PW_MAXPULSE][3], pw[PW_MAXPULSE];
+};
+
+__host__ __device__ inline long long cell_index(const PatchDev &p, int i, int j, int k) {
+  return (long long)(k + PW_NG) * p.slab + (long long)(j + PW_NG) * p.pitch + (i + PW_OX);
+}
+
+// ---------------------------------------------------------------------------
+// Pose c(t) for the three motions (a patch map is X = c(t) + R M(x')).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline void pose_at(const PatchDev &p, double t, PoseDev &o) {
+  for (int a = 0; a < 3; a++) { o.c[a] = p.c0[a]; o.cd[a] = 0.0; o.cdd[a] = 0.0; }
+  if (p.motion == LINEAR) {
+    for (int a = 0; a < 3; a++) { o.c[a] = p.c0[a] + p.vel[a] * t; o.cd[a] = p.vel[a]; }
+  } else if (p.motion == CIRCLE) {
+    double arg = p.omega * t + p.phase;
+    double s = sin(arg), c = cos(arg);
+    o.c[0] += p.radius * c;
+    o.c[1] += p.radius * s;
+    o.cd[0] = -p.radius * p.omega * s;
+    o.cd[1] = p.radius * p.omega * c;
+    o.cdd[0] = -p.radius * p.omega * p.omega * c;
+    o.cdd[1] = -p.radius * p.omega * p.omega * s;
+  }
+  for (int i = 0; i < 3; i++) {
+    o.b[i] = p.R[0 + i] * o.cd[0] + p.R[3 + i] * o.cd[1] + p.R[6 + i] * o.cd[2];
+    o.a[i] = p.R[0 + i] * o.cdd[0] + p.R[3 + i] * o.cdd[1] + p.R[6 + i] * o.cdd[2];
+  }
+}
+
+__device__ inline double xnum(const PatchDev &p, int a, int i) { return p.lo[a] + (i + 0.5) * p.dx[a]; }
+
+// Orthonormal spherical basis at (theta, phi).
+struct SphBasis {
+  double st, ct, sp, cp;
+  double er[3], et[3], ep[3];
+};
+__device__ inline void sph_basis(double th, double ph, SphBasis &B) {
+  sincos(th, &B.st, &B.ct);
+  sincos(ph, &B.sp, &B.cp);
+  B.er[0] = B.st * B.cp; B.er[1] = B.st * B.sp; B.er[2] = B.ct;
+  B.et[0] = B.ct * B.cp; B.et[1] = B.ct * B.sp; B.et[2] = -B.st;
+  B.ep[0] = -B.sp; B.ep[1] = B.cp; B.ep[2] = 0.0;
+}
+
+// Forward map: numerical x' of patch p -> background X at pose ps.
+__device__ inline void fwd_map(const PatchDev &p, const PoseDev &ps, const double xp[3], double X[3]) {
+  double y[3];
+  if (p.coord == CART) {
+    y[0] = xp[0]; y[1] = xp[1]; y[2] = xp[2];
+  } else {
+    SphBasis B;
+    sph_basis(xp[1], xp[2], B);
+    for (int a = 0; a < 3; a++) y[a] = xp[0] * B.er[a];
+  }
+  for (int a = 0; a < 3; a++) X[a] = ps.c[a] + p.R[3 * a] * y[0] + p.R[3 * a + 1] * y[1] + p.R[3 * a + 2] * y[2];
+}
+
+// Inverse map: background X -> numerical x' of patch p at pose ps.
+__device__ inline void inv_map(const PatchDev &p, const PoseDev &ps, const double X[3], double xp[3]) {
+  double d[3] = {X[0] - ps.c[0], X[1] - ps.c[1], X[2] - ps.c[2]};
+  double y[3];
+  for (int b = 0; b < 3; b++) y[b] = p.R[b] * d[0] + p.R[3 + b] * d[1] + p.R[6 + b] * d[2];
+  if (p.coord == CART) {
+    xp[0] = y[0]; xp[1] = y[1]; xp[2] = y[2];
+  } else {
+    double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    xp[0] = r;
+    xp[1] = acos(y[2] / r);
+    xp[2] = atan2(y[1], y[0]);
+  }
+}
+
+// One-form from patch frame to background: given (Pi_t, Pi_i) in the numerical
+// frame of p at x', return Pi_t^B and the background gradient G = d phi/dX.
+// (Pi_mu transforms with dx'/dX; for the spherical map the spatial part is the
+// usual gradient in the orthonormal basis.)
+__device__ inline void patch_to_bg(const PatchDev &p, const PoseDev &ps, const double xp[3], const double in[4],
+                                   double &pit, double G[3]) {
+  double gy[3];
+  if (p.coord == CART) {
+    gy[0] = in[1]; gy[1] = in[2]; gy[2] = in[3];
+  } else {
+    SphBasis B;
+    sph_basis(xp[1], xp[2], B);
+    double fr = in[1], ft = in[2] / xp[0], fp = in[3] / (xp[0] * B.st);
+    for (int a = 0; a < 3; a++) gy[a] = fr * B.er[a] + ft * B.et[a] + fp * B.ep[a];
+  }
+  for (int a = 0; a < 3; a++) G[a] = p.R[3 * a] * gy[0] + p.R[3 * a + 1] * gy[1] + p.R[3 * a + 2] * gy[2];
+  pit = in[0] - (ps.cd[0] * G[0] + ps.cd[1] * G[1] + ps.cd[2] * G[2]);
+}
+
+// Background one-form (Pi_t^B, G) -> numerical frame of p at x'.
+__device__ inline void bg_to_patch(const PatchDev &p, const PoseDev &ps, const double xp[3], double pit,
+                                   const double G[3], double out[4]) {
+  double gy[3];
+  for (int b = 0; b < 3; b++) gy[b] = p.R[b] * G[0] + p.R[3 + b] * G[1] + p.R[6 + b] * G[2];
+  out[0] = pit + ps.cd[0] * G[0] + ps.cd[1] * G[1] + ps.cd[2] * G[2];
+  if (p.coord == CART) {
+    out[1] = gy[0]; out[2] = gy[1]; out[3] = gy[2];
+  } else {
+    SphBasis B;
+    sph_basis(xp[1], xp[2], B);
+    out[1] = B.er[0] * gy[0] + B.er[1] * gy[1] + B.er[2] * gy[2];
+    out[2] = xp[0] * (B.et[0] * gy[0] + B.et[1] * gy[1] + B.et[2] * gy[2]);
+    out[3] = xp[0] * B.st * (B.ep[0] * gy[0] + B.ep[1] * gy[1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact solutions in the background frame: phi, d_t phi, grad phi.
+// ---------------------------------------------------------------------------
+// n-th derivative of g(s) = s exp(-s^2/w^2), via Hermite polynomials H_{n+1}:
+// g^(n)(s) = (-1)^n / 2 * w^(1-n) * H_{n+1}(s/w) * exp(-(s/w)^2).
+__device__ inline double gpulse_der(int n, double s, double w) {
+  double u = s / w, hm = 1.0, h = 2.0 * u;
+  for (int k = 1; k <= n; k++) {
+    double hn = 2.0 * u * h - 2.0 * k * hm;
+    hm = h;
+    h = hn;
+  }
+  double wp = 1.0;
+  for (int k = 1; k < n; k++) wp *= w;  // w^(n-1)
+  double sg = (n & 1) ? -1.0 : 1.0;
+  return 0.5 * sg * h * exp(-u * u) * (n == 0 ? w : 1.0 / wp);
+}
+
+// rho*phi obeys the 1-D wave equation; with tau = v t the pulse that starts at
+// rest is phi = [g(tau + rho) - g(tau - rho)] / (2 rho), summed as its Taylor
+// series in rho near the centre to avoid cancellation.
+__device__ inline void pulse_eval(double A, const double xc[3], double w, double v, double t, const double X[3],
+                                  double out[5]) {
+  double d[3] = {X[0] - xc[0], X[1] - xc[1], X[2] - xc[2]};
+  double rho = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double tau = v * t, phi, pt, gf;
+  if (rho < 0.05 * w) {
+    double r2 = rho * rho, pw2 = 1.0, fact = 1.0;
+    phi = 0.0; pt = 0.0; gf = 0.0;
+    for (int k = 0; k <= 5; k++) {
+      if (k > 0) fact *= (2.0 * k) * (2.0 * k + 1.0);
+      double g1 = gpulse_der(2 * k + 1, tau, w);
+      phi += g1 * pw2 / fact;
+      pt += gpulse_der(2 * k + 2, tau, w) * pw2 / fact;
+      if (k + 1 <= 5) {
+        // gradient factor term k+1: 2(k+1) g^(2k+3) rho^(2k) / (2k+3)!
+        double f3 = fact * (2.0 * k + 2.0) * (2.0 * k + 3.0);
+        gf += gpulse_der(2 * k + 3, tau, w) * 2.0 * (k + 1) * pw2 / f3;
+      }
+      pw2 *= r2;
+    }
+    pt *= v;
+  } else {
+    double gp = gpulse_der(0, tau + rho, w), gm = gpulse_der(0, tau - rho, w);
+    double g1p = gpulse_der(1, tau + rho, w), g1m = gpulse_der(1, tau - rho, w);
+    phi = (gp - gm) / (2.0 * rho);
+    pt = v * (g1p - g1m) / (2.0 * rho);
+    gf = ((g1p + g1m) / (2.0 * rho) - phi / rho) / rho;
+  }
+  out[0] = A * phi;
+  out[1] = A * pt;
+  for (int a = 0; a < 3; a++) out[2 + a] = A * gf * d[a];
+}
+
+__device__ inline void exact_bg(const ExactDev &e, double v, double t, const double X[3], double out[5]) {
+  for (int f = 0; f < 5; f++) out[f] = 0.0;
+  if (e.kind == EX_PLANE) {
+    double arg = e.kappa[0] * X[0] + e.kappa[1] * X[1] + e.kappa[2] * X[2] - v * e.knorm * t + e.phase;
+    double s, c;
+    sincos(arg, &s, &c);
+    out[0] = e.amp * s + e.offset;
+    out[1] = -e.amp * v * e.knorm * c;
+    for (int a = 0; a < 3; a++) out[2 + a] = e.amp * e.kappa[a] * c;
+  } else if (e.kind == EX_GAUSS) {
+    for (int g = 0; g < e.n; g++) {
+      double o[5];
+      pulse_eval(e.pa[g], e.px[g], e.pw[g], v, t, X, o);
+      for (int f = 0; f < 5; f++) out[f] += o[f];
+    }
+  }
+}
+
+// Exact state in the numerical frame of patch p at x'.
+__device__ inline void exact_patch(const ExactDev &e, double v, const PatchDev &p, const PoseDev &ps, double t,
+                                   const double xp[3], double out[5]) {
+  double X[3], bg[5];
+  fwd_map(p, ps, xp, X);
+  exact_bg(e, v, t, X, bg);
+  double o4[4];
+  bg_to_patch(p, ps, xp, bg[1], bg + 2, o4);
+  out[0] = bg[0];
+  for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
+}
+
+// ---------------------------------------------------------------------------
+// Lagrange weights (Eq. Pijk): stencil start s = floor(q - (P-2)/2), q the
+// fractional cell index of the point.
+// ---------------------------------------------------------------------------
+__device__ inline int lagrange_w(int P, double q, double *w) {
+  int s = (int)floor(q - 0.5 * (P - 2));
+  double t = q - (double)s;  // position relative to the first node
+  for (int m = 0; m < P; m++) {
+    double num = 1.0, den = 1.0;
+    for (int l = 0; l < P; l++) {
+      if (l == m) continue;
+      num *= (t - (double)l);
+      den *= (double)(m - l);
+    }
+    w[m] = num / den;
+  }
+  return s;
+}
+
+}  // namespace pw

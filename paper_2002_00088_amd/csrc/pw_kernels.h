@@ -1,0 +1,108 @@
+// Launch interface between the host orchestration and the HIP kernels of libpw.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pw_internal.h"
+
+#define TILE_X 64
+#define TILE_Y 4
+#define TILE_Z 4
+#define DIAG_N 23
+
+namespace pw {
+
+struct TileRec {
+  int32_t patch, x0, y0, z0;
+};
+
+// A ghost cell: patch id and packed padded coordinates (i+3) | (j+3) << 10 | (k+3) << 20.
+struct GhostRec {
+  int32_t patch;
+  uint32_t cell;
+};
+
+// One local patch's cover scan: the axis-aligned box of `ext` global cells around
+// its bounding sphere of radius `radius`.
+struct CoverJob {
+  int32_t patch;
+  int32_t ext[3];
+  double radius;
+};
+
+struct FlagsArgs {
+  const PatchDev *P;
+  const PoseDev *pose;
+  const CoverJob *jobs;
+  int njobs, cover_blocks;
+  int32_t *cover_new;
+  uint8_t *t1, *t2, *live, *flag_new;
+  int n[3];
+  int buffer;
+  int *err;
+};
+
+struct FinalizeArgs {
+  const PatchDev *P;
+  const PoseDev *pose;
+  uint8_t *flag_cur;
+  const uint8_t *flag_new;
+  int32_t *cover_cur, *cover_new;
+  int nsv;
+  const int *Pts;
+  const ExactDev *ex;
+  const double *vs;
+  const double *tdev;
+  int mode;
+  unsigned long long *counters;
+  int n[3];
+};
+
+struct GhostArgs {
+  const PatchDev *P;
+  const PoseDev *pose;
+  const GhostRec *lower;
+  int n_lower;
+  const GhostRec *g2l;
+  int n_g2l;
+  const uint8_t *gflag;
+  const int32_t *cover;
+  int has_locals;
+  int gn[3];
+  int sv, stage, stage_fp64, mixed, Pts;
+  const ExactDev *ex;
+  double v;
+  const double *tdev;  // stage time = tdev[0] + tmul * dt
+  double tmul, dt;
+  unsigned long long *skips;
+};
+
+struct StageArgs {
+  const PatchDev *P;
+  const PoseDev *pose;
+  const TileRec *tiles;
+  int ntiles;
+  const uint8_t *gflag;
+  int sv, stage, mixed;
+  double dt, v2, eps;
+};
+
+void launch_pose(hipStream_t s, const PatchDev *P, int np, const double *tdev, double dt, PoseDev *poses);
+void launch_pose_at(hipStream_t s, const PatchDev *P, int np, double t, PoseDev *out);
+void launch_advance_time(hipStream_t s, double *tdev, double dt, long long *counters);
+void launch_flags(hipStream_t s, const FlagsArgs &a);
+void launch_finalize(hipStream_t s, const FinalizeArgs &a);
+void launch_ghosts(hipStream_t s, const GhostArgs &a);
+void launch_stage(hipStream_t s, const StageArgs &a);
+void launch_fill_f64(hipStream_t s, double *p, long long n, double v);
+void launch_fill_f32(hipStream_t s, float *p, long long n, float v);
+void launch_fill_i32(hipStream_t s, int32_t *p, long long n, int32_t v);
+void launch_fill_u8(hipStream_t s, uint8_t *p, long long n, uint8_t v);
+void launch_unpack(hipStream_t s, const PatchDev *P, int pid, int sv, const double *src, long long n);
+void launch_pack(hipStream_t s, const PatchDev *P, int pid, int sv, double *dst, long long n, int full);
+void launch_init_exact(hipStream_t s, const PatchDev *P, const PoseDev *pose, int pid, int sv, const ExactDev *ex,
+                       double v, double t, long long ncell);
+void launch_diag(hipStream_t s, const PatchDev *P, const PoseDev *pose, int pid, int sv, const uint8_t *gflag,
+                 const ExactDev *ex, double v, double t, double *partial, int nblocks);
+
+}  // namespace pw

@@ -1,0 +1,702 @@
+// HIP kernels of libpw for gfx950 (MI355X).
+//
+// One RK4 step of the multipatch scalar-wave system (arXiv 2002.00088):
+//   pose      patch centres and velocities at the substep times      (Sec. 2.4.2)
+//   flags     cover test, NG+1 live buffer, effective ghosts          (Sec. 2.4.2, Fig. cflag)
+//   ghosts    analytic/periodic ghosts, then global->local and
+//             local->global Lagrange interpolation with the frame
+//             transform through the background frame                 (Secs. 2.4-2.4.2, Eq. Pijk)
+//   stage     RHS of Eqs. eom1-eom3 + Kreiss-Oliger, RK4 stage update (Secs. 2.2-2.3, Table rk4)
+//   finalize  flags at t_{n+1}, uncover fill, poison deactivated cells
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pw_internal.h"
+#include "pw_kernels.h"
+
+namespace pw {
+
+// ---------------------------------------------------------------------------
+// Pose: slot 0 = t_n, slot 1 = t_n + dt/2, slot 2 = t_n + dt (classic RK4
+// abscissae c = 0, 1/2, 1/2, 1), slot 3 = an explicit time.
+// ---------------------------------------------------------------------------
+__global__ void k_pose(const PatchDev *P, int np, const double *tdev, double dt, PoseDev *poses) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  double tn = tdev[0];
+  pose_at(P[p], tn, poses[p]);
+  pose_at(P[p], tn + 0.5 * dt, poses[np + p]);
+  pose_at(P[p], tn + dt, poses[2 * np + p]);
+}
+
+__global__ void k_pose_at(const PatchDev *P, int np, double t, PoseDev *out) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  pose_at(P[p], t, out[p]);
+}
+
+__global__ void k_advance_time(double *tdev, double dt, long long *counters) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    tdev[0] = tdev[0] + dt;
+    counters[4] += 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cover flags
+// ---------------------------------------------------------------------------
+// cover[c] = id of the local patch whose closed numerical box contains the
+// centre of global cell c (Sec. 2.4.2: the covered test is done in the local
+// patch's numerical coordinates).  Each local patch scans the global cells of
+// the axis-aligned box around its bounding sphere.
+__global__ void k_cover(const PatchDev *P, const PoseDev *pose, const CoverJob *jobs, int njobs, int32_t *cover,
+                        int *err) {
+  const CoverJob J = jobs[blockIdx.y];
+  const PatchDev &g = P[0];
+  const PatchDev &p = P[J.patch];
+  const PoseDev &ps = pose[J.patch];
+  int lo[3], ext[3];
+  for (int a = 0; a < 3; a++) {
+    double c = (ps.c[a] - J.radius - g.lo[a]) * g.idx[a] - 0.5;
+    lo[a] = (int)floor(c);
+    ext[a] = J.ext[a];
+  }
+  long long total = (long long)ext[0] * ext[1] * ext[2];
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (long long)gridDim.x * blockDim.x) {
+    int i = lo[0] + (int)(q % ext[0]);
+    int j = lo[1] + (int)((q / ext[0]) % ext[1]);
+    int k = lo[2] + (int)(q / ((long long)ext[0] * ext[1]));
+    if (i < 0 || j < 0 || k < 0 || i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) continue;
+    double X[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)}, xp[3];
+    inv_map(p, ps, X, xp);
+    bool in = true;
+    for (int a = 0; a < 3; a++) {
+      if (p.periodic[a]) continue;
+      in = in && (xp[a] >= p.lo[a]) && (xp[a] <= p.hi[a]);
+    }
+    if (!in) continue;
+    long long c = ((long long)k * g.n[1] + j) * g.n[0] + i;
+    int old = atomicCAS(&cover[c], -1, J.patch);
+    if (old != -1 && old != J.patch) atomicExch(err, 1);
+  }
+}
+
+// Chebyshev dilation along one axis: out[c] = max_{|d|<=R} in[c + d e_axis],
+// cells outside the domain read as `oob`.  With SRC_COVER the input is
+// "uncovered" = (cover == -1).
+template <int AXIS, bool SRC_COVER>
+__global__ void k_dilate(const void *in_, uint8_t *out, int n0, int n1, int n2, int R, int oob) {
+  long long total = (long long)n0 * n1 * n2;
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= total) return;
+  int i = (int)(c % n0), j = (int)((c / n0) % n1), k = (int)(c / ((long long)n0 * n1));
+  int pos = AXIS == 0 ? i : (AXIS == 1 ? j : k);
+  int len = AXIS == 0 ? n0 : (AXIS == 1 ? n1 : n2);
+  long long stride = AXIS == 0 ? 1 : (AXIS == 1 ? (long long)n0 : (long long)n0 * n1);
+  int m = 0;
+  for (int d = -R; d <= R; d++) {
+    int q = pos + d;
+    int v;
+    if (q < 0 || q >= len) {
+      v = oob;
+    } else if (SRC_COVER) {
+      v = ((const int32_t *)in_)[c + d * stride] == -1;
+    } else {
+      v = ((const uint8_t *)in_)[c + d * stride];
+    }
+    m = v > m ? v : m;
+  }
+  out[c] = (uint8_t)m;
+}
+
+// flag = live ? LIVE : (near a live cell ? EFFGHOST : DEACT)
+__global__ void k_combine_flags(const uint8_t *live, const uint8_t *near, uint8_t *flag, long long total) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= total) return;
+  flag[c] = live[c] ? LIVE : (near[c] ? EFFGHOST : DEACT);
+}
+
+// Tensor-product Lagrange interpolation of the 5 fields of buffer T of donor
+// patch p at numerical point xd.  For a global donor every stencil cell must be
+// live (gflag); for a local donor the stencil must lie in the interior (wrapping
+// periodic axes).  Returns false if the point cannot be interpolated.
+template <typename TB, typename TC>
+__device__ inline bool interp5(const PatchDev &p, const TB *T, const uint8_t *gflag, int P, const double xd[3],
+                               TC out[5]) {
+  double wx[8], wy[8], wz[8];
+  int s[3];
+  double q[3];
+  for (int a = 0; a < 3; a++) {
+    q[a] = (xd[a] - p.lo[a]) * p.idx[a] - 0.5;
+    if (!(q[a] > -1.0e6 && q[a] < 1.0e6)) return false;
+  }
+  s[0] = lagrange_w(P, q[0], wx);
+  s[1] = lagrange_w(P, q[1], wy);
+  s[2] = lagrange_w(P, q[2], wz);
+  for (int a = 0; a < 3; a++)
+    if (!p.periodic[a] && (s[a] < 0 || s[a] + P - 1 > p.n[a] - 1)) return false;
+  if (p.is_global && gflag) {
+    for (int c = 0; c < P; c++)
+      for (int b = 0; b < P; b++)
+        for (int a = 0; a < P; a++) {
+          long long gi = ((long long)(s[2] + c) * p.n[1] + (s[1] + b)) * p.n[0] + (s[0] + a);
+          if (gflag[gi] != LIVE) return false;
+        }
+  }
+  for (int f = 0; f < 5; f++) out[f] = (TC)0;
+  for (int c = 0; c < P; c++) {
+    int kk = s[2] + c;
+    if (p.periodic[2]) kk = ((kk % p.n[2]) + p.n[2]) % p.n[2];
+    for (int b = 0; b < P; b++) {
+      int jj = s[1] + b;
+      if (p.periodic[1]) jj = ((jj % p.n[1]) + p.n[1]) % p.n[1];
+      TC wyz = (TC)(wy[b] * wz[c]);
+      TC part[5] = {0, 0, 0, 0, 0};
+      for (int a = 0; a < P; a++) {
+        int ii = s[0] + a;
+        if (p.periodic[0]) ii = ((ii % p.n[0]) + p.n[0]) % p.n[0];
+        long long x = cell_index(p, ii, jj, kk);
+        TC w = (TC)wx[a];
+        for (int f = 0; f < 5; f++) part[f] += w * (TC)T[f * p.fstride + x];
+      }
+      for (int f = 0; f < 5; f++) out[f] += wyz * part[f];
+    }
+  }
+  return true;
+}
+
+template <typename TB>
+__device__ inline TB *stage_buf(const PatchDev &p, int sv, int stage) {
+  if (stage == 0) return (TB *)p.u[sv];
+  return (TB *)((stage == 2) ? p.vb[sv] : p.va[sv]);
+}
+
+// Interpolate donor d at background X, carry the result to receiver r at x_r.
+template <typename TB, typename TC>
+__device__ inline bool interp_transform(const PatchDev &d, const PoseDev &psd, const TB *T, const uint8_t *gflag,
+                                        int P, const double X[3], const PatchDev &r, const PoseDev &psr,
+                                        const double xr[3], double out[5]) {
+  double xd[3];
+  inv_map(d, psd, X, xd);
+  TC v[5];
+  if (!interp5<TB, TC>(d, T, gflag, P, xd, v)) return false;
+  double in4[4] = {(double)v[1], (double)v[2], (double)v[3], (double)v[4]}, G[3], pit, o4[4];
+  patch_to_bg(d, psd, xd, in4, pit, G);
+  bg_to_patch(r, psr, xr, pit, G, o4);
+  out[0] = (double)v[0];
+  for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
+  return true;
+}
+
+__device__ inline void unpack_ijk(uint32_t c, int &i, int &j, int &k) {
+  i = (int)(c & 1023u) - PW_NG;
+  j = (int)((c >> 10) & 1023u) - PW_NG;
+  k = (int)((c >> 20) & 1023u) - PW_NG;
+}
+
+// Lower-priority ghost data: periodic copy if the wrapped index is interior,
+// else the exact solution (analytic outer boundary) or the nearest interior cell.
+template <typename TB>
+__global__ void k_fill_lower(const PatchDev *P, const PoseDev *pose, const GhostRec *list, int count, int sv, int stage,
+                             const ExactDev *ex, double v, const double *tdev, double tmul, double dt) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const double t = tdev[0] + tmul * dt;
+  GhostRec g = list[q];
+  const PatchDev &p = P[g.patch];
+  if (!(p.sv_mask & (1u << sv))) return;
+  TB *T = stage_buf<TB>(p, sv, stage);
+  int c[3];
+  unpack_ijk(g.cell, c[0], c[1], c[2]);
+  int w[3];
+  bool interior = true;
+  for (int a = 0; a < 3; a++) {
+    w[a] = c[a];
+    if (p.periodic[a]) w[a] = ((c[a] % p.n[a]) + p.n[a]) % p.n[a];
+    interior = interior && w[a] >= 0 && w[a] < p.n[a];
+  }
+  long long dst = cell_index(p, c[0], c[1], c[2]);
+  if (interior) {
+    long long src = cell_index(p, w[0], w[1], w[2]);
+    for (int f = 0; f < 5; f++) T[f * p.fstride + dst] = T[f * p.fstride + src];
+  } else if (ex[sv].kind != EX_NONE) {
+    double xp[3] = {xnum(p, 0, c[0]), xnum(p, 1, c[1]), xnum(p, 2, c[2])}, e[5];
+    exact_patch(ex[sv], v, p, pose[g.patch], t, xp, e);
+    for (int f = 0; f < 5; f++) T[f * p.fstride + dst] = (TB)e[f];
+  } else {
+    for (int a = 0; a < 3; a++) w[a] = w[a] < 0 ? 0 : (w[a] >= p.n[a] ? p.n[a] - 1 : w[a]);
+    long long src = cell_index(p, w[0], w[1], w[2]);
+    for (int f = 0; f < 5; f++) T[f * p.fstride + dst] = T[f * p.fstride + src];
+  }
+}
+
+// Global -> local (Sec. 2.4.1): every non-periodic ghost cell of every local
+// patch is located in the global patch, interpolated there and transformed;
+// points that cannot be interpolated keep the lower-priority value.
+template <typename TB, typename TC>
+__global__ void k_fill_g2l(const PatchDev *P, const PoseDev *pose, const GhostRec *list, int count, int sv, int stage,
+                           const uint8_t *gflag, int Pts, const ExactDev *ex, double v, const double *tdev,
+                           double tmul, double dt, unsigned long long *skips) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const double t = tdev[0] + tmul * dt;
+  GhostRec g = list[q];
+  const PatchDev &r = P[g.patch];
+  const PatchDev &G0 = P[0];
+  if (!(r.sv_mask & (1u << sv))) return;
+  TB *T = stage_buf<TB>(r, sv, stage);
+  int c[3];
+  unpack_ijk(g.cell, c[0], c[1], c[2]);
+  long long dst = cell_index(r, c[0], c[1], c[2]);
+  double xr[3] = {xnum(r, 0, c[0]), xnum(r, 1, c[1]), xnum(r, 2, c[2])}, X[3], out[5];
+  fwd_map(r, pose[g.patch], xr, X);
+  bool ok = (G0.sv_mask & (1u << sv)) &&
+            interp_transform<TB, TC>(G0, pose[0], stage_buf<TB>(G0, sv, stage), gflag, Pts, X, r, pose[g.patch], xr,
+                                     out);
+  if (!ok) {
+    atomicAdd(skips, 1ull);
+    if (ex[sv].kind != EX_NONE) {
+      exact_patch(ex[sv], v, r, pose[g.patch], t, xr, out);
+    } else {
+      int w[3];
+      for (int a = 0; a < 3; a++) {
+        w[a] = c[a];
+        if (r.periodic[a]) w[a] = ((c[a] % r.n[a]) + r.n[a]) % r.n[a];
+        w[a] = w[a] < 0 ? 0 : (w[a] >= r.n[a] ? r.n[a] - 1 : w[a]);
+      }
+      long long src = cell_index(r, w[0], w[1], w[2]);
+      for (int f = 0; f < 5; f++) out[f] = (double)T[f * r.fstride + src];
+    }
+  }
+  for (int f = 0; f < 5; f++) T[f * r.fstride + dst] = (TB)out[f];
+}
+
+// Local -> global (Sec. 2.4.2): effective ghost cells of the global patch are
+// interpolated from the covering local patch and transformed to the global frame.
+template <typename TB, typename TC>
+__global__ void k_fill_l2g(const PatchDev *P, const PoseDev *pose, const uint8_t *gflag, const int32_t *cover, int sv,
+                           int stage, int Pts, const ExactDev *ex, double v, const double *tdev, double tmul, double dt,
+                           unsigned long long *skips) {
+  const PatchDev &G0 = P[0];
+  const double t = tdev[0] + tmul * dt;
+  long long total = (long long)G0.n[0] * G0.n[1] * G0.n[2];
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= total || gflag[c] != EFFGHOST) return;
+  if (!(G0.sv_mask & (1u << sv))) return;
+  int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]), k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
+  int d = cover[c];
+  const PatchDev &D = P[d];
+  double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)}, out[5];
+  bool ok = (D.sv_mask & (1u << sv)) &&
+            interp_transform<TB, TC>(D, pose[d], stage_buf<TB>(D, sv, stage), nullptr, Pts, X, G0, pose[0], X, out);
+  if (!ok) {
+    atomicAdd(skips, 1ull);
+    if (ex[sv].kind != EX_NONE) {
+      exact_patch(ex[sv], v, G0, pose[0], t, X, out);
+    } else {
+      for (int f = 0; f < 5; f++) out[f] = NAN;
+    }
+  }
+  TB *T = stage_buf<TB>(G0, sv, stage);
+  long long dst = cell_index(G0, i, j, k);
+  for (int f = 0; f < 5; f++) T[f * G0.fstride + dst] = (TB)out[f];
+}
+
+// End of step: cells live now but not live during the step get u_{n+1}
+// interpolated from the covering local patch; deactivated cells are poisoned;
+// the new flags become current.  mode 0: first flags (no uncover fill).
+__global__ void k_finalize(const PatchDev *P, const PoseDev *pose, uint8_t *flag_cur, const uint8_t *flag_new,
+                           int32_t *cover_cur, int32_t *cover_new, int nsv, const int *Pts, const ExactDev *ex,
+                           const double *vs, const double *tdev, int mode, unsigned long long *counters) {
+  const PatchDev &G0 = P[0];
+  long long total = (long long)G0.n[0] * G0.n[1] * G0.n[2];
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= total) return;
+  uint8_t fo = flag_cur[c], fn = flag_new[c];
+  int32_t cn = cover_new[c], co = cover_cur[c];
+  int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]), k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
+  long long x = cell_index(G0, i, j, k);
+  if (mode == 1 && fo != LIVE && fn == LIVE) {
+    int d = cn >= 1 ? cn : co;
+    const PatchDev &D = P[d >= 1 ? d : 0];
+    double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
+    atomicAdd(&counters[3], 1ull);
+    for (int sv = 0; sv < nsv; sv++) {
+      if (!(G0.sv_mask & (1u << sv))) continue;
+      double out[5];
+      bool ok = d >= 1 && (D.sv_mask & (1u << sv)) &&
+                interp_transform<double, double>(D, pose[d], D.u[sv], nullptr, Pts[sv], X, G0, pose[0], X, out);
+      if (!ok) {
+        atomicAdd(&counters[2], 1ull);
+        if (ex[sv].kind != EX_NONE) exact_patch(ex[sv], vs[sv], G0, pose[0], tdev[0], X, out);
+        else for (int f = 0; f < 5; f++) out[f] = NAN;
+      }
+      for (int f = 0; f < 5; f++) G0.u[sv][f * G0.fstride + x] = out[f];
+    }
+  }
+  if (fn == DEACT) {
+    for (int sv = 0; sv < nsv; sv++) {
+      if (!(G0.sv_mask & (1u << sv))) continue;
+      for (int f = 0; f < 5; f++) G0.u[sv][f * G0.fstride + x] = NAN;
+    }
+  }
+  flag_cur[c] = fn;
+  cover_cur[c] = cn;
+  cover_new[c] = -1;
+}
+
+// ---------------------------------------------------------------------------
+// RHS of Eqs. eom1-eom3 (source S = 0) with Kreiss-Oliger dissipation on all
+// five fields, fused with the classic-RK4 stage update.
+//
+// Metric terms (flat background with wave speed v, patch map X = c(t) + R M(x')):
+//   b = R^T c', a = R^T c'' (patch axes), beta = K b with K = (dM/dx')^-1,
+//   dPi_t/dt = m.D phi + 2 beta.D Pi_t + sum_i (v^2 h_i - beta_i^2) D_ii phi
+//              - 2 sum_{i<j} beta_i beta_j D_ij phi
+// Cartesian: h = 1, m = a.  Spherical: h = (1, 1/r^2, 1/(r sin th)^2) and
+//   m = K a - Q(b) + v^2 (2/r, cot th / r^2, 0), Q the coordinate acceleration of
+//   straight-line motion in spherical coordinates.
+// ---------------------------------------------------------------------------
+template <typename TIN, typename TOUT, typename TC, int STAGE>
+__global__ __launch_bounds__(256) void k_stage(const PatchDev *P, const PoseDev *pose_slot, const TileRec *tiles,
+                                               const uint8_t *gflag, int sv, double dt, double v2, double eps) {
+  const TileRec tl = tiles[blockIdx.x];
+  const PatchDev &p = P[tl.patch];
+  const PoseDev &ps = pose_slot[tl.patch];
+  const int i = tl.x0 + threadIdx.x;
+  const int j = tl.y0 + threadIdx.y;
+  if (i >= p.n[0] || j >= p.n[1]) return;
+  const TIN *in = (const TIN *)(STAGE == 0 ? (const void *)p.u[sv] : (STAGE == 2 ? p.vb[sv] : p.va[sv]));
+  TOUT *vout = (TOUT *)(STAGE == 1 ? p.vb[sv] : p.va[sv]);
+  double *U = p.u[sv];
+  double *A = p.acc[sv];
+  const long long fs = p.fstride, sy = p.pitch, sz = p.slab;
+  const TC i12dx[3] = {(TC)(p.idx[0] / 12.0), (TC)(p.idx[1] / 12.0), (TC)(p.idx[2] / 12.0)};
+  const TC i12dx2[3] = {(TC)(p.idx[0] * p.idx[0] / 12.0), (TC)(p.idx[1] * p.idx[1] / 12.0),
+                        (TC)(p.idx[2] * p.idx[2] / 12.0)};
+  const TC ko[3] = {(TC)(eps / 64.0 * p.idx[0]), (TC)(eps / 64.0 * p.idx[1]), (TC)(eps / 64.0 * p.idx[2])};
+  const long long st[3] = {1, sy, sz};
+  const bool moving = (ps.b[0] != 0.0) || (ps.b[1] != 0.0) || (ps.b[2] != 0.0);
+  for (int kk = 0; kk < TILE_Z; kk++) {
+    const int k = tl.z0 + kk;
+    if (k >= p.n[2]) break;
+    if (p.is_global && gflag && gflag[((long long)k * p.n[1] + j) * p.n[0] + i] != LIVE) continue;
+    const long long x0 = cell_index(p, i, j, k);
+    auto L = [&](int f, long long off) -> TC { return (TC)in[f * fs + x0 + off]; };
+    // metric coefficients
+    double m[3], beta[3], h[3];
+    if (p.coord == CART) {
+      for (int a = 0; a < 3; a++) { m[a] = ps.a[a]; beta[a] = ps.b[a]; h[a] = 1.0; }
+    } else {
+      double r = p.lo[0] + (i + 0.5) * p.dx[0];
+      double th = p.lo[1] + (j + 0.5) * p.dx[1];
+      double ph = p.lo[2] + (k + 0.5) * p.dx[2];
+      SphBasis B;
+      sph_basis(th, ph, B);
+      double ir = 1.0 / r, irs = ir / B.st, cot = B.ct / B.st;
+      double br = B.er[0] * ps.b[0] + B.er[1] * ps.b[1] + B.er[2] * ps.b[2];
+      double bt = B.et[0] * ps.b[0] + B.et[1] * ps.b[1] + B.et[2] * ps.b[2];
+      double bp = B.ep[0] * ps.b[0] + B.ep[1] * ps.b[1];
+      double ar = B.er[0] * ps.a[0] + B.er[1] * ps.a[1] + B.er[2] * ps.a[2];
+      double at = B.et[0] * ps.a[0] + B.et[1] * ps.a[1] + B.et[2] * ps.a[2];
+      double ap = B.ep[0] * ps.a[0] + B.ep[1] * ps.a[1];
+      beta[0] = br; beta[1] = bt * ir; beta[2] = bp * irs;
+      double Q0 = (bt * bt + bp * bp) * ir;
+      double Q1 = (-2.0 * br * bt + bp * bp * cot) * ir * ir;
+      double Q2 = -2.0 * bp * (br + bt * cot) * ir * irs;
+      m[0] = ar - Q0 + v2 * 2.0 * ir;
+      m[1] = at * ir - Q1 + v2 * cot * ir * ir;
+      m[2] = ap * irs - Q2;
+      h[0] = 1.0; h[1] = ir * ir; h[2] = irs * irs;
+    }
+    TC dphi[3], dpi[3], d2phi[3], kof[5];
+    for (int f = 0; f < 5; f++) kof[f] = (TC)0;
+    for (int a = 0; a < 3; a++) {
+      const long long s1 = st[a];
+      TC pm2 = L(0, -2 * s1), pm1 = L(0, -s1), p0 = L(0, 0), pp1 = L(0, s1), pp2 = L(0, 2 * s1);
+      dphi[a] = ((pm2 - pp2) + (TC)8 * (pp1 - pm1)) * i12dx[a];
+      d2phi[a] = ((TC)16 * (pm1 + pp1) - (pm2 + pp2) - (TC)30 * p0) * i12dx2[a];
+      TC qm2 = L(1, -2 * s1), qm1 = L(1, -s1), qp1 = L(1, s1), qp2 = L(1, 2 * s1);
+      dpi[a] = ((qm2 - qp2) + (TC)8 * (qp1 - qm1)) * i12dx[a];
+      for (int f = 0; f < 5; f++) {
+        TC c0 = L(f, 0);
+        TC d6 = (L(f, -3 * s1) + L(f, 3 * s1)) - (TC)6 * (L(f, -2 * s1) + L(f, 2 * s1)) +
+                (TC)15 * (L(f, -s1) + L(f, s1)) - (TC)20 * c0;
+        kof[f] += d6 * ko[a];
+      }
+    }
+    TC rhs_pi = (TC)0;
+    for (int a = 0; a < 3; a++)
+      rhs_pi += (TC)m[a] * dphi[a] + (TC)(2.0 * beta[a]) * dpi[a] + (TC)(v2 * h[a] - beta[a] * beta[a]) * d2phi[a];
+    if (moving) {
+      // mixed derivatives D_i D_j phi, i < j, as products of first-derivative stencils
+      const TC w1[5] = {(TC)1, (TC)-8, (TC)0, (TC)8, (TC)-1};
+      for (int a = 0; a < 3; a++)
+        for (int b = a + 1; b < 3; b++) {
+          TC s = (TC)0;
+          for (int o1 = -2; o1 <= 2; o1++) {
+            if (o1 == 0) continue;
+            TC inner = (TC)0;
+            for (int o2 = -2; o2 <= 2; o2++) {
+              if (o2 == 0) continue;
+              inner += w1[o2 + 2] * L(0, o1 * st[a] + o2 * st[b]);
+            }
+            s += w1[o1 + 2] * inner;
+          }
+          TC dab = s * i12dx[a] * i12dx[b];
+          rhs_pi -= (TC)(2.0 * beta[a] * beta[b]) * dab;
+        }
+    }
+    TC K[5];
+    K[0] = L(1, 0) + kof[0];
+    K[1] = rhs_pi + kof[1];
+    for (int a = 0; a < 3; a++) K[2 + a] = dpi[a] + kof[2 + a];
+    // classic RK4 (Table rk4): acc holds u_n + dt sum_l b_l K_l, v_{s+1} = u_n + a dt K_s
+    for (int f = 0; f < 5; f++) {
+      const long long x = f * fs + x0;
+      const double kf = (double)K[f];
+      if (STAGE == 0) {
+        const double un = U[x];
+        A[x] = un + (dt / 6.0) * kf;
+        vout[x] = (TOUT)(un + (dt / 2.0) * kf);
+      } else if (STAGE == 1) {
+        A[x] = A[x] + (dt / 3.0) * kf;
+        vout[x] = (TOUT)(U[x] + (dt / 2.0) * kf);
+      } else if (STAGE == 2) {
+        A[x] = A[x] + (dt / 3.0) * kf;
+        vout[x] = (TOUT)(U[x] + dt * kf);
+      } else {
+        U[x] = A[x] + (dt / 6.0) * kf;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Utilities: fills, interior pack/unpack, exact initial data, diagnostics
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill_value(T *ptr, long long n, T val) {
+  long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; q < n; q += (long long)gridDim.x * blockDim.x) ptr[q] = val;
+}
+
+__global__ void k_unpack(const PatchDev *P, int pid, int sv, const double *src) {
+  const PatchDev &p = P[pid];
+  long long per = (long long)p.n[0] * p.n[1] * p.n[2];
+  long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 5 * per) return;
+  int f = (int)(q / per);
+  long long c = q % per;
+  int i = (int)(c % p.n[0]), j = (int)((c / p.n[0]) % p.n[1]), k = (int)(c / ((long long)p.n[0] * p.n[1]));
+  p.u[sv][f * p.fstride + cell_index(p, i, j, k)] = src[q];
+}
+
+__global__ void k_pack(const PatchDev *P, int pid, int sv, double *dst, int full) {
+  const PatchDev &p = P[pid];
+  int m0 = full ? p.n[0] + 2 * PW_NG : p.n[0], m1 = full ? p.n[1] + 2 * PW_NG : p.n[1],
+      m2 = full ? p.n[2] + 2 * PW_NG : p.n[2];
+  int off = full ? -PW_NG : 0;
+  long long per = (long long)m0 * m1 * m2;
+  long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 5 * per) return;
+  int f = (int)(q / per);
+  long long c = q % per;
+  int i = (int)(c % m0) + off, j = (int)((c / m0) % m1) + off, k = (int)(c / ((long long)m0 * m1)) + off;
+  dst[q] = p.u[sv][f * p.fstride + cell_index(p, i, j, k)];
+}
+
+__global__ void k_init_exact(const PatchDev *P, const PoseDev *pose, int pid, int sv, const ExactDev *ex, double v,
+                             double t) {
+  const PatchDev &p = P[pid];
+  long long per = (long long)p.n[0] * p.n[1] * p.n[2];
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= per) return;
+  int i = (int)(c % p.n[0]), j = (int)((c / p.n[0]) % p.n[1]), k = (int)(c / ((long long)p.n[0] * p.n[1]));
+  double xp[3] = {xnum(p, 0, i), xnum(p, 1, j), xnum(p, 2, k)}, e[5];
+  exact_patch(ex[sv], v, p, pose[pid], t, xp, e);
+  long long x = cell_index(p, i, j, k);
+  for (int f = 0; f < 5; f++) p.u[sv][f * p.fstride + x] = e[f];
+}
+
+// Per-block partial diagnostics: 23 doubles per block (see pw_diag).
+__global__ void k_diag(const PatchDev *P, const PoseDev *pose, int pid, int sv, const uint8_t *gflag,
+                       const ExactDev *ex, double v, double t, double *partial) {
+  const PatchDev &p = P[pid];
+  long long per = (long long)p.n[0] * p.n[1] * p.n[2];
+  __shared__ double red[256][DIAG_N];
+  double acc[DIAG_N];
+  for (int x = 0; x < DIAG_N; x++) acc[x] = 0.0;
+  const bool has = ex[sv].kind != EX_NONE;
+  const double cellvol = p.dx[0] * p.dx[1] * p.dx[2];
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < per; c += (long long)gridDim.x * blockDim.x) {
+    if (p.is_global && gflag && gflag[c] != LIVE) continue;
+    int i = (int)(c % p.n[0]), j = (int)((c / p.n[0]) % p.n[1]), k = (int)(c / ((long long)p.n[0] * p.n[1]));
+    double xp[3] = {xnum(p, 0, i), xnum(p, 1, j), xnum(p, 2, k)}, e[5] = {0, 0, 0, 0, 0};
+    if (has) exact_patch(ex[sv], v, p, pose[pid], t, xp, e);
+    long long x = cell_index(p, i, j, k);
+    double phi = 0;
+    for (int f = 0; f < 5; f++) {
+      double val = p.u[sv][f * p.fstride + x];
+      if (f == 0) phi = val;
+      acc[f] = fmax(acc[f], fabs(val));
+      acc[5 + f] += val * val;
+      if (has) {
+        double d = val - e[f];
+        acc[10 + f] = fmax(acc[10 + f], fabs(d));
+        acc[15 + f] += d * d;
+      }
+    }
+    double sg = p.coord == CART ? 1.0 : xp[0] * xp[0] * fabs(sin(xp[1]));
+    if (has) acc[20] += fabs(phi - e[0]) / fabs(e[0]) * sg * cellvol;
+    acc[21] += 1.0;
+    acc[22] += sg * cellvol;
+  }
+  for (int x = 0; x < DIAG_N; x++) red[threadIdx.x][x] = acc[x];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int x = 0; x < DIAG_N; x++) {
+        bool mx = (x < 5) || (x >= 10 && x < 15);
+        double o = red[threadIdx.x + s][x];
+        red[threadIdx.x][x] = mx ? fmax(red[threadIdx.x][x], o) : red[threadIdx.x][x] + o;
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int x = 0; x < DIAG_N; x++) partial[(long long)blockIdx.x * DIAG_N + x] = red[0][x];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_pose(hipStream_t s, const PatchDev *P, int np, const double *tdev, double dt, PoseDev *poses) {
+  hipLaunchKernelGGL(k_pose, dim3(nblk(np, 64)), dim3(64), 0, s, P, np, tdev, dt, poses);
+}
+void launch_pose_at(hipStream_t s, const PatchDev *P, int np, double t, PoseDev *out) {
+  hipLaunchKernelGGL(k_pose_at, dim3(nblk(np, 64)), dim3(64), 0, s, P, np, t, out);
+}
+void launch_advance_time(hipStream_t s, double *tdev, double dt, long long *counters) {
+  hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, s, tdev, dt, counters);
+}
+
+void launch_flags(hipStream_t s, const FlagsArgs &a) {
+  const int bs = 256;
+  if (a.njobs > 0)
+    hipLaunchKernelGGL(k_cover, dim3(a.cover_blocks, a.njobs), dim3(bs), 0, s, a.P, a.pose, a.jobs, a.njobs,
+                       a.cover_new, a.err);
+  long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
+  unsigned nb = nblk(tot, bs);
+  hipLaunchKernelGGL((k_dilate<0, true>), dim3(nb), dim3(bs), 0, s, (const void *)a.cover_new, a.t1, a.n[0], a.n[1],
+                     a.n[2], a.buffer, 1);
+  hipLaunchKernelGGL((k_dilate<1, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t1, a.t2, a.n[0], a.n[1], a.n[2],
+                     a.buffer, 1);
+  hipLaunchKernelGGL((k_dilate<2, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t2, a.live, a.n[0], a.n[1],
+                     a.n[2], a.buffer, 1);
+  hipLaunchKernelGGL((k_dilate<0, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.live, a.t1, a.n[0], a.n[1],
+                     a.n[2], PW_NG, 0);
+  hipLaunchKernelGGL((k_dilate<1, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t1, a.t2, a.n[0], a.n[1], a.n[2],
+                     PW_NG, 0);
+  hipLaunchKernelGGL((k_dilate<2, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t2, a.t1, a.n[0], a.n[1], a.n[2],
+                     PW_NG, 0);
+  hipLaunchKernelGGL(k_combine_flags, dim3(nb), dim3(bs), 0, s, (const uint8_t *)a.live, (const uint8_t *)a.t1,
+                     a.flag_new, tot);
+}
+
+void launch_finalize(hipStream_t s, const FinalizeArgs &a) {
+  long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
+  hipLaunchKernelGGL(k_finalize, dim3(nblk(tot, 256)), dim3(256), 0, s, a.P, a.pose, a.flag_cur, a.flag_new,
+                     a.cover_cur, a.cover_new, a.nsv, a.Pts, a.ex, a.vs, a.tdev, a.mode, a.counters);
+}
+
+void launch_ghosts(hipStream_t s, const GhostArgs &a) {
+  const int bs = 256;
+  long long gtot = (long long)a.gn[0] * a.gn[1] * a.gn[2];
+  if (a.stage_fp64) {
+    if (a.n_lower > 0)
+      hipLaunchKernelGGL(k_fill_lower<double>, dim3(nblk(a.n_lower, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower,
+                         a.n_lower, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
+    if (a.n_g2l > 0) {
+      if (a.mixed)
+        hipLaunchKernelGGL((k_fill_g2l<double, float>), dim3(nblk(a.n_g2l, bs)), dim3(bs), 0, s, a.P, a.pose, a.g2l,
+                           a.n_g2l, a.sv, a.stage, a.gflag, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips);
+      else
+        hipLaunchKernelGGL((k_fill_g2l<double, double>), dim3(nblk(a.n_g2l, bs)), dim3(bs), 0, s, a.P, a.pose, a.g2l,
+                           a.n_g2l, a.sv, a.stage, a.gflag, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips);
+    }
+    if (a.has_locals) {
+      if (a.mixed)
+        hipLaunchKernelGGL((k_fill_l2g<double, float>), dim3(nblk(gtot, bs)), dim3(bs), 0, s, a.P, a.pose, a.gflag,
+                           a.cover, a.sv, a.stage, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
+      else
+        hipLaunchKernelGGL((k_fill_l2g<double, double>), dim3(nblk(gtot, bs)), dim3(bs), 0, s, a.P, a.pose, a.gflag,
+                           a.cover, a.sv, a.stage, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
+    }
+  } else {
+    if (a.n_lower > 0)
+      hipLaunchKernelGGL(k_fill_lower<float>, dim3(nblk(a.n_lower, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower,
+                         a.n_lower, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
+    if (a.n_g2l > 0)
+      hipLaunchKernelGGL((k_fill_g2l<float, float>), dim3(nblk(a.n_g2l, bs)), dim3(bs), 0, s, a.P, a.pose, a.g2l,
+                         a.n_g2l, a.sv, a.stage, a.gflag, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips);
+    if (a.has_locals)
+      hipLaunchKernelGGL((k_fill_l2g<float, float>), dim3(nblk(gtot, bs)), dim3(bs), 0, s, a.P, a.pose, a.gflag,
+                         a.cover, a.sv, a.stage, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
+  }
+}
+
+void launch_stage(hipStream_t s, const StageArgs &a) {
+  dim3 bs(TILE_X, TILE_Y);
+  dim3 g(a.ntiles);
+  if (a.ntiles <= 0) return;
+#define PW_STAGE(TIN, TOUT, TC, ST) \
+  hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST>), g, bs, 0, s, a.P, a.pose, a.tiles, a.gflag, a.sv, a.dt, a.v2, a.eps)
+  if (!a.mixed) {
+    switch (a.stage) {
+      case 0: PW_STAGE(double, double, double, 0); break;
+      case 1: PW_STAGE(double, double, double, 1); break;
+      case 2: PW_STAGE(double, double, double, 2); break;
+      default: PW_STAGE(double, double, double, 3); break;
+    }
+  } else {
+    switch (a.stage) {
+      case 0: PW_STAGE(double, float, float, 0); break;
+      case 1: PW_STAGE(float, float, float, 1); break;
+      case 2: PW_STAGE(float, float, float, 2); break;
+      default: PW_STAGE(float, float, float, 3); break;
+    }
+  }
+#undef PW_STAGE
+}
+
+void launch_fill_f64(hipStream_t s, double *p, long long n, double v) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_value<double>, dim3(nblk(n, 256) < 4096 ? nblk(n, 256) : 4096), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_f32(hipStream_t s, float *p, long long n, float v) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_value<float>, dim3(nblk(n, 256) < 4096 ? nblk(n, 256) : 4096), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_i32(hipStream_t s, int32_t *p, long long n, int32_t v) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_value<int32_t>, dim3(nblk(n, 256) < 4096 ? nblk(n, 256) : 4096), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_u8(hipStream_t s, uint8_t *p, long long n, uint8_t v) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_value<uint8_t>, dim3(nblk(n, 256) < 4096 ? nblk(n, 256) : 4096), dim3(256), 0, s, p, n, v);
+}
+void launch_unpack(hipStream_t s, const PatchDev *P, int pid, int sv, const double *src, long long n) {
+  hipLaunchKernelGGL(k_unpack, dim3(nblk(n, 256)), dim3(256), 0, s, P, pid, sv, src);
+}
+void launch_pack(hipStream_t s, const PatchDev *P, int pid, int sv, double *dst, long long n, int full) {
+  hipLaunchKernelGGL(k_pack, dim3(nblk(n, 256)), dim3(256), 0, s, P, pid, sv, dst, full);
+}
+void launch_init_exact(hipStream_t s, const PatchDev *P, const PoseDev *pose, int pid, int sv, const ExactDev *ex,
+                       double v, double t, long long ncell) {
+  hipLaunchKernelGGL(k_init_exact, dim3(nblk(ncell, 256)), dim3(256), 0, s, P, pose, pid, sv, ex, v, t);
+}
+void launch_diag(hipStream_t s, const PatchDev *P, const PoseDev *pose, int pid, int sv, const uint8_t *gflag,
+                 const ExactDev *ex, double v, double t, double *partial, int nblocks) {
+  hipLaunchKernelGGL(k_diag, dim3(nblocks), dim3(256), 0, s, P, pose, pid, sv, gflag, ex, v, t, partial);
+}
+
+}  // namespace pw

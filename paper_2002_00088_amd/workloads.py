@@ -118,14 +118,6 @@ def spherical(seed=3, ng=256, nr=64, nth=64, nph=128, steps=500):
     return _finish(cfg)
 
 
-def _obb_corners(c, R, lo, hi):
-    pts = []
-    for m in range(8):
-        y = np.array([hi[0] if m & 1 else lo[0], hi[1] if m & 2 else lo[1], hi[2] if m & 4 else lo[2]])
-        pts.append(c + R @ y)
-    return np.array(pts)
-
-
 def _rot(eu):
     a, b, c = eu
     Z1 = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
@@ -134,31 +126,50 @@ def _rot(eu):
     return Z1 @ Y @ Z2
 
 
-def _separated(A, B):
-    """Separating-axis test between two convex bodies given as (corners, axes)."""
-    (pa, ax_a), (pb, ax_b) = A, B
-    axes = list(ax_a) + list(ax_b)
-    for u in ax_a:
-        for v in ax_b:
-            c = np.cross(u, v)
-            if np.linalg.norm(c) > 1e-9:
-                axes.append(c / np.linalg.norm(c))
+def _obb_overlap(c1, R1, h1, c2, R2, h2):
+    """Separating-axis test of two oriented boxes (centre, axes as columns, half sizes)."""
+    axes = [R1[:, i] for i in range(3)] + [R2[:, i] for i in range(3)]
+    for i in range(3):
+        for j in range(3):
+            v = np.cross(R1[:, i], R2[:, j])
+            nv = np.linalg.norm(v)
+            if nv > 1e-9:
+                axes.append(v / nv)
+    d = c2 - c1
     for ax in axes:
-        a = pa @ ax
-        b = pb @ ax
-        if a.max() < b.min() or b.max() < a.min():
-            return True
-    return False
+        r1 = np.sum(h1 * np.abs(R1.T @ ax))
+        r2 = np.sum(h2 * np.abs(R2.T @ ax))
+        if abs(d @ ax) > r1 + r2:
+            return False
+    return True
 
 
-def batched(seed=4, ng=256, nlocal=64, nmin=24, nmax=96, frac_cart=0.7, vmax=0.2, steps=23, margin=4,
-            max_tries=3000):
+def _sphere_obb_overlap(cs, r, c, R, h):
+    q = np.clip(R.T @ (cs - c), -h, h)
+    return np.linalg.norm(R @ q + c - cs) <= r
+
+
+def _overlap(a, b):
+    if a["kind"] == "sph" and b["kind"] == "sph":
+        return np.linalg.norm(a["c"] - b["c"]) <= a["r"] + b["r"]
+    if a["kind"] == "sph":
+        return _sphere_obb_overlap(a["c"], a["r"], b["c"], b["R"], b["h"])
+    if b["kind"] == "sph":
+        return _sphere_obb_overlap(b["c"], b["r"], a["c"], a["R"], a["h"])
+    return _obb_overlap(a["c"], a["R"], a["h"], b["c"], b["R"], b["h"])
+
+
+def batched(seed=4, ng=256, nlocal=64, nmin=24, nmax=96, frac_cart=0.7, vmax=0.2, steps=23, pad_cells=4,
+            edge_cells=8, tries=400):
     """Global Cartesian [-8,8]^3 plus `nlocal` moving local patches of uneven
     sizes: per-axis cells from [nmin,nmax], 70/30 Cartesian/spherical, random
-    orientation, linear velocity |v| <= vmax, resolution 1-4x the global one.
-    Placement: largest first, oriented-box separating-axis test with a margin of
-    `margin` global cells plus the motion sweep; on failure the refinement ratio
-    grows by 1.25 (cap 4), then the cell counts shrink by 0.8."""
+    orientation, linear velocity |v| <= vmax, resolution 1-4x the global one
+    (spherical patches 2-4x, radial spacing; r_in = n_r dr / 4, theta in
+    [pi/4, 3pi/4], phi periodic).  Placement: largest first; each patch is an
+    oriented box (a sphere for spherical patches) grown by `pad_cells` global cells
+    plus its motion over the run, kept `edge_cells` from the domain edge and
+    disjoint from every placed one.  When no spot is found in `tries` draws the
+    refinement ratio grows by 1.25 (cap 4), then the cell counts shrink by 0.8."""
     rng = np.random.default_rng(seed)
     L = 8.0
     dxg = 2 * L / ng
@@ -167,7 +178,7 @@ def batched(seed=4, ng=256, nlocal=64, nmin=24, nmax=96, frac_cart=0.7, vmax=0.2
     for _ in range(nlocal):
         n = rng.integers(nmin, nmax + 1, 3)
         coord = CART if rng.uniform() < frac_cart else SPH
-        ratio = rng.uniform(1.0, 4.0)
+        ratio = rng.uniform(1.0, 4.0) if coord == CART else rng.uniform(2.0, 4.0)
         eu = random_euler(rng)
         vdir = rng.normal(size=3)
         vdir /= np.linalg.norm(vdir)
@@ -178,52 +189,51 @@ def batched(seed=4, ng=256, nlocal=64, nmin=24, nmax=96, frac_cart=0.7, vmax=0.2
         dx = dxg / d["ratio"]
         n = d["n"]
         if d["coord"] == CART:
-            half = n * dx / 2.0
-            return dict(lo=-half, hi=half, dx=dx)
-        r_in = max(n[1] * dx / 2.0, 6 * dx)
-        return dict(lo=np.array([r_in, math.pi / 4, 0.0]), hi=np.array([r_in + n[0] * dx, 3 * math.pi / 4, 2 * math.pi]),
-                    dx=dx)
+            return dict(lo=-n * dx / 2.0, hi=n * dx / 2.0)
+        r_in = n[0] * dx / 4.0
+        return dict(lo=np.array([r_in, math.pi / 4, 0.0]), hi=np.array([r_in + n[0] * dx, 3 * math.pi / 4, 2 * math.pi]))
 
-    def extent(d):
+    def bound(d):
         gm = geometry(d)
-        if d["coord"] == CART:
-            return float(np.linalg.norm(gm["hi"]))
-        return float(gm["hi"][0])
+        return float(np.linalg.norm(gm["hi"])) if d["coord"] == CART else float(gm["hi"][0])
 
-    order = sorted(range(nlocal), key=lambda i: -extent(descs[i]))
-    t_end = (steps + 1) * 0.25 * dxg / 4.0 * 4  # generous motion sweep
+    order = sorted(range(nlocal), key=lambda i: -bound(descs[i]))
+    t_run = (steps + 1) * 0.25 * dxg  # generous bound on the simulated time of a run
     placed = []
     locs = []
     for i in order:
         d = descs[i]
-        ok = False
-        for attempt in range(200):
+        body = None
+        for attempt in range(40):
             gm = geometry(d)
-            R = _rot(d["euler"])
-            ext = extent(d)
-            pad = margin * dxg + np.linalg.norm(d["vel"]) * t_end
-            room = L - ext - pad - 6 * dxg
+            pad = pad_cells * dxg + np.linalg.norm(d["vel"]) * t_run
+            rb = bound(d) + pad
+            room = L - rb - edge_cells * dxg
             if room > 0:
-                for _ in range(max_tries // 20):
-                    c = rng.uniform(-room, room, 3)
+                cands = rng.uniform(-room, room, (tries, 3))
+                pc = np.array([b["c"] for b in placed]) if placed else np.zeros((0, 3))
+                pr = np.array([b["rb"] for b in placed]) if placed else np.zeros(0)
+                R = _rot(d["euler"])
+                for c in cands:
+                    near = np.nonzero(np.linalg.norm(pc - c, axis=1) <= pr + rb)[0] if len(pc) else []
                     if d["coord"] == CART:
-                        body = (_obb_corners(c, R, gm["lo"] - pad, gm["hi"] + pad), [R[:, 0], R[:, 1], R[:, 2]])
+                        cand = dict(kind="cart", c=c, R=R, h=gm["hi"] + pad, rb=rb)
                     else:
-                        r = gm["hi"][0] + pad
-                        body = (_obb_corners(c, np.eye(3), -np.full(3, r), np.full(3, r)), [np.eye(3)[k] for k in range(3)])
-                    if all(_separated(body, other) for other in placed):
-                        placed.append(body)
-                        ok = True
+                        cand = dict(kind="sph", c=c, r=rb, rb=rb)
+                    if all(not _overlap(cand, placed[k]) for k in near):
+                        body = cand
                         break
-            if ok:
+            if body is not None:
                 break
             if d["ratio"] < 4.0:
                 d["ratio"] = min(4.0, d["ratio"] * 1.25)
             else:
                 d["n"] = np.maximum(nmin, (0.8 * d["n"]).astype(int))
-        if not ok:
+        if body is None:
             continue
+        placed.append(body)
         gm = geometry(d)
+        c = body["c"]
         if d["coord"] == CART:
             locs.append(patch(d["n"], gm["lo"], gm["hi"], euler=d["euler"], motion=LINEAR, c0=c, vel=d["vel"]))
         else:

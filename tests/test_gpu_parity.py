@@ -1,0 +1,243 @@
+"""GPU parity: libpw (HIP, through the C ABI) against the FP64 CPU oracle.
+
+FP64 bar: per field, max |u_gpu - u_oracle| over live cells divided by
+max |u_oracle| over the same cells must be <= 1e-12; cover flags, cover ids and
+skip/uncover counts must match exactly.  The mixed path is compared to the
+oracle with a stated looser bound (FP32 stage inputs carry ~1e-7 relative
+rounding into every stage).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.oracle import world_from_config
+from paper_2002_00088_amd import pw
+from paper_2002_00088_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def live_mask(cfg, pid, flags):
+    n = cfg["patches"][pid]["n"]
+    if pid == 0 and len(cfg["patches"]) > 1:
+        return flags == 0
+    return np.ones((n[2], n[1], n[0]), dtype=bool)
+
+
+def rel_err(a, b, mask):
+    out = []
+    for f in range(5):
+        x = a[f][mask]
+        y = b[f][mask]
+        assert np.isfinite(x).all() and np.isfinite(y).all()
+        scale = np.max(np.abs(y)) if y.size else 0.0
+        d = np.max(np.abs(x - y)) if y.size else 0.0
+        out.append(d / scale if scale > 0 else d)
+    return np.array(out)
+
+
+def run_pair(cfg, steps, precision=pw.PW_FP64, schedule=pw.PW_SCHED_BATCHED, use_graph=True, init="exact",
+             seed=0):
+    o = world_from_config(cfg)
+    g = pw.context_from_config(cfg, precision=precision, schedule=schedule, use_graph=use_graph)
+    if init == "exact":
+        o.init_exact(0.0)
+        g.init_exact(0.0)
+    else:
+        for pid, p in enumerate(cfg["patches"]):
+            for sv in range(len(cfg["wave_speed"])):
+                if p["sv_mask"] & (1 << sv):
+                    n = p["n"]
+                    a = W.random_state((5, n[2], n[1], n[0]), seed + 31 * pid + sv)
+                    o.set_state(pid, sv, a, 0.0)
+                    g.set_state(pid, sv, a, 0.0)
+    o.step(cfg["dt"], steps)
+    g.rk4_step(cfg["dt"], steps)
+    return o, g
+
+
+def compare(cfg, o, g, tol, check_counts=True):
+    worst = 0.0
+    fo, co = o.flags() if len(cfg["patches"]) > 1 else (None, None)
+    if fo is not None:
+        fg, cg = g.flags()
+        assert (fo == fg).all(), "cover flags differ in %d cells" % int((fo != fg).sum())
+        assert (co == cg).all()
+    for pid, p in enumerate(cfg["patches"]):
+        for sv in range(len(cfg["wave_speed"])):
+            if not p["sv_mask"] & (1 << sv):
+                continue
+            m = live_mask(cfg, pid, fo)
+            e = rel_err(g.get_state(pid, sv), o.get_state(pid, sv), m)
+            worst = max(worst, e.max())
+            assert (e <= tol).all(), (pid, sv, e)
+    if check_counts:
+        co_ = o.counters()
+        cg_ = g.counters()
+        for k in ("skip_local", "skip_eff", "skip_uncover", "n_uncover"):
+            assert co_[k] == cg_[k], (k, co_, cg_)
+    return worst
+
+
+@pytest.mark.parametrize("n", [32, (70, 9, 6)])
+def test_periodic_single_patch(n):
+    cfg = W.single_periodic(seed=1, n=n if np.isscalar(n) else list(n), steps=20)
+    say("periodic", n)
+    steps = 20 if np.isscalar(n) else 5
+    o, g = run_pair(cfg, steps)
+    w = compare(cfg, o, g, TOL64)
+    say("  worst rel err", w)
+    assert abs(g.t - o.t) == 0.0
+
+
+@pytest.mark.parametrize("P", [5, 6])
+def test_two_patch_circle(P):
+    cfg = W.two_patch(seed=2, ng=48, nl=40, P=P)
+    say("two-patch circle P=%d" % P)
+    o, g = run_pair(cfg, 3)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def test_two_patch_random_data_linear_motion():
+    cfg = W.two_patch(seed=5, ng=44, nl=36, P=6, motion=W.LINEAR)
+    say("two-patch linear, random data")
+    o, g = run_pair(cfg, 2, init="random", seed=11)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def _fast_uncover_cfg():
+    cfg = W.two_patch(seed=7, ng=48, nl=40, P=6, motion=W.LINEAR)
+    cfg["patches"][1]["vel"] = [1.5, -0.4, 0.3]
+    return cfg
+
+
+def test_uncover_fill_matches():
+    cfg = _fast_uncover_cfg()
+    say("uncover")
+    o, g = run_pair(cfg, 6)
+    assert o.counters()["n_uncover"] > 0
+    say("  worst rel err", compare(cfg, o, g, TOL64), o.counters())
+
+
+def _sph_cfg(moving):
+    g0 = W.patch([48] * 3, [-8] * 3, [8] * 3, is_global=1)
+    if moving:
+        s = W.patch([20, 16, 32], [0.8, math.pi / 4, 0.0], [4.0, 3 * math.pi / 4, 2 * math.pi], coord=W.SPH,
+                    periodic=(0, 0, 1), euler=[0.4, 1.0, 2.2], motion=W.LINEAR, c0=(0.3, -0.2, 0.1),
+                    vel=(0.15, 0.1, -0.05))
+    else:
+        s = W.patch([20, 16, 32], [0.8, math.pi / 4, 0.0], [4.0, 3 * math.pi / 4, 2 * math.pi], coord=W.SPH,
+                    periodic=(0, 0, 1))
+    ex = dict(kind="gauss", amp=[1.0, -0.6], centers=[[0.5, 0.2, -0.3], [-1.5, 1.0, 0.8]], widths=[0.9, 0.7])
+    return W._finish(dict(wave_speed=[1.0], interp_points=[6], patches=[g0, s], exact=[ex]))
+
+
+@pytest.mark.parametrize("moving", [False, True])
+def test_spherical_local_patch(moving):
+    cfg = _sph_cfg(moving)
+    say("spherical moving=%s" % moving)
+    o, g = run_pair(cfg, 2)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def test_two_state_vectors_with_membership():
+    g0 = W.patch([40] * 3, [-8] * 3, [8] * 3, is_global=1, sv_mask=1)
+    l1 = W.patch([32] * 3, [-3.2] * 3, [3.2] * 3, euler=[0.2, 0.7, 1.1], motion=W.LINEAR, c0=(-3.5, 0, 0),
+                 vel=(0.1, 0.05, 0), sv_mask=3)
+    l2 = W.patch([24] * 3, [-2.4] * 3, [2.4] * 3, euler=[1.2, 0.3, 0.1], motion=W.LINEAR, c0=(3.8, 0.5, 0),
+                 vel=(-0.1, 0, 0.05), sv_mask=1)
+    rng = np.random.default_rng(5)
+    cfg = W._finish(dict(wave_speed=[1.0, 0.5], interp_points=[6, 6], patches=[g0, l1, l2],
+                         exact=[W.gauss_sum(rng, 4, 4.0), W.gauss_sum(rng, 4, 4.0)]))
+    say("two state vectors")
+    o, g = run_pair(cfg, 2)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def test_exchange_ghosts_including_ghost_cells():
+    cfg = W.two_patch(seed=3, ng=48, nl=40, P=6)
+    o = world_from_config(cfg)
+    g = pw.context_from_config(cfg)
+    o.init_exact(0.0)
+    g.init_exact(0.0)
+    o.exchange_ghosts(0.37)
+    g.exchange_ghosts(0.37)
+    fo, _ = o.flags()
+    a, b = g.get_state_full(1), o.get_full(1)
+    assert np.isfinite(a).all()
+    scale = np.abs(b).max(axis=(1, 2, 3))
+    assert (np.abs(a - b).max(axis=(1, 2, 3)) <= TOL64 * scale).all()
+    ga, gb = g.get_state_full(0), o.get_full(0)
+    core = np.zeros(ga.shape[1:], dtype=bool)
+    core[3:-3, 3:-3, 3:-3] = fo == 2
+    keep = ~core
+    for f in range(5):
+        assert np.abs(ga[f][keep] - gb[f][keep]).max() <= TOL64 * np.abs(gb[f][keep]).max()
+
+
+def test_schedules_and_graph_bitwise_identical():
+    cfg = W.two_patch(seed=4, ng=40, nl=32, P=6)
+    outs = []
+    for sched, graph in ((pw.PW_SCHED_BATCHED, True), (pw.PW_SCHED_BATCHED, False), (pw.PW_SCHED_PER_PATCH, False)):
+        g = pw.context_from_config(cfg, schedule=sched, use_graph=graph)
+        g.init_exact(0.0)
+        g.rk4_step(cfg["dt"], 3)
+        outs.append((g.get_state(0), g.get_state(1)))
+        g.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0], equal_nan=True)
+        assert np.array_equal(o[1], outs[0][1], equal_nan=True)
+
+
+def test_mixed_precision_close_to_oracle():
+    cfg = W.two_patch(seed=2, ng=48, nl=40, P=6)
+    say("mixed precision")
+    o, g = run_pair(cfg, 4, precision=pw.PW_MIXED)
+    fo, _ = o.flags()
+    worst = 0
+    for pid in range(2):
+        e = rel_err(g.get_state(pid), o.get_state(pid), live_mask(cfg, pid, fo))
+        say("  patch", pid, "rel err per field", e)
+        worst = max(worst, e.max())
+    assert worst < 2e-5
+
+
+def test_full_size_two_patch_one_step():
+    cfg = W.two_patch(seed=2)  # 128^3 global + 64^3 local, P = 5
+    say("full-size two-patch 1 step")
+    o, g = run_pair(cfg, 1)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def test_error_paths():
+    cfg = W.two_patch(seed=2, ng=32, nl=24, P=6, motion=W.LINEAR)
+    cfg["patches"][1]["vel"] = [40.0, 0, 0]
+    g = pw.context_from_config(cfg)
+    g.init_exact(0.0)
+    with pytest.raises(pw.PwError) as e:
+        g.rk4_step(cfg["dt"], 1)
+    assert e.value.code == -6
+    g.close()
+    cfg = W.two_patch(seed=2, ng=32, nl=24, P=6, motion=W.STATIC)
+    cfg["patches"].append(dict(cfg["patches"][1]))
+    g = pw.context_from_config(cfg)
+    g.init_exact(0.0)
+    with pytest.raises(pw.PwError) as e:
+        g.rk4_step(cfg["dt"], 1)
+    assert e.value.code == -5
+    g.close()
+    g = pw.Context()
+    with pytest.raises(pw.PwError):
+        g.create_patch(W.patch([8] * 3, [0] * 3, [1] * 3, is_global=0))
+    with pytest.raises(pw.PwError):
+        g.rk4_step(0.1, 1)
+    g.close()
