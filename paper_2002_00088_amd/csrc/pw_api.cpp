@@ -42,8 +42,13 @@ struct pw_context {
   uint8_t *flag_cur = nullptr, *flag_new = nullptr, *t1 = nullptr, *t2 = nullptr, *live = nullptr;
   int32_t *cover_cur = nullptr, *cover_new = nullptr;
   // lists
-  GhostRec *dLower = nullptr, *dG2L = nullptr;
-  int nLower = 0, nG2L = 0;
+  GhostRec *dLower = nullptr;
+  int nLower = 0;
+  GBrick *dBricks = nullptr;
+  int nBricks = 0;
+  int32_t *efflist = nullptr;
+  int *effcount = nullptr;
+  uint8_t *dvalid[2] = {nullptr, nullptr};  // donor-valid bytes for P = 5, 6
   TileRec *dTiles = nullptr;
   int nTiles = 0;
   std::vector<int> tileOff, tileCnt;
@@ -194,9 +199,12 @@ pw_status upload_layout(pw_context *c) {
   if (!c->dP || !c->dPose) return fail(c, PW_ENOMEM, "device allocation failed");
   HIPCHK(c, hipMemcpyAsync(c->dP, c->hp.data(), sizeof(PatchDev) * np, hipMemcpyHostToDevice, c->stream));
 
-  // Ghost lists: lower-priority ghosts (periodic copies, global outer ghosts) and
-  // the interpatch targets of every local patch (non-periodic ghost cells).
-  std::vector<GhostRec> lower, g2l;
+  // Lower-priority ghost cells (periodic copies, global outer ghosts) as a list;
+  // the interpatch targets of every local patch as bricks of at most 8x8x3 cells
+  // on its six faces (z faces span the full padded x-y range, y faces the full
+  // padded x range, x faces the interior y-z range, so the faces are disjoint).
+  std::vector<GhostRec> lower;
+  std::vector<GBrick> bricks;
   for (int pid = 0; pid < np; pid++) {
     const PatchDev &p = c->hp[pid];
     for (int k = -PW_NG; k < p.n[2] + PW_NG; k++)
@@ -210,21 +218,51 @@ pw_status upload_layout(pw_context *c) {
             wrapped_inside = wrapped_inside && w >= 0 && w < p.n[a];
           }
           if (inside) continue;
-          GhostRec g{pid, pack_ijk(i, j, k)};
-          if (wrapped_inside || p.is_global) lower.push_back(g);
-          else g2l.push_back(g);
+          if (wrapped_inside || p.is_global) lower.push_back(GhostRec{pid, pack_ijk(i, j, k)});
         }
+    if (p.is_global) continue;
+    auto target = [&](int i, int j, int k) {
+      int cc[3] = {i, j, k};
+      bool inside = true, wrapped_inside = true;
+      for (int a = 0; a < 3; a++) {
+        inside = inside && cc[a] >= 0 && cc[a] < p.n[a];
+        int w = p.periodic[a] ? ((cc[a] % p.n[a]) + p.n[a]) % p.n[a] : cc[a];
+        wrapped_inside = wrapped_inside && w >= 0 && w < p.n[a];
+      }
+      return !inside && !wrapped_inside;
+    };
+    auto add = [&](int i0, int i1, int j0, int j1, int k0, int k1, int bi, int bj, int bk) {
+      for (int k = k0; k < k1; k += bk)
+        for (int j = j0; j < j1; j += bj)
+          for (int i = i0; i < i1; i += bi) {
+            GBrick b{pid, i, j, k, std::min(bi, i1 - i), std::min(bj, j1 - j), std::min(bk, k1 - k), 0};
+            bool any = false;
+            for (int z = b.k0; z < b.k0 + b.dk && !any; z++)
+              for (int y = b.j0; y < b.j0 + b.dj && !any; y++)
+                for (int x = b.i0; x < b.i0 + b.di && !any; x++) any = target(x, y, z);
+            if (any) bricks.push_back(b);
+          }
+    };
+    const int g = PW_NG;
+    const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+    add(-g, n0 + g, -g, n1 + g, -g, 0, 8, 8, 3);        // z- face (with edges and corners)
+    add(-g, n0 + g, -g, n1 + g, n2, n2 + g, 8, 8, 3);   // z+ face
+    add(-g, n0 + g, -g, 0, 0, n2, 8, 3, 8);             // y- face
+    add(-g, n0 + g, n1, n1 + g, 0, n2, 8, 3, 8);        // y+ face
+    add(-g, 0, 0, n1, 0, n2, 3, 8, 8);                  // x- face
+    add(n0, n0 + g, 0, n1, 0, n2, 3, 8, 8);             // x+ face
   }
   dfree(c, c->dLower);
-  dfree(c, c->dG2L);
+  dfree(c, c->dBricks);
   c->nLower = (int)lower.size();
-  c->nG2L = (int)g2l.size();
+  c->nBricks = (int)bricks.size();
   c->dLower = (GhostRec *)dalloc(c, sizeof(GhostRec) * std::max<size_t>(1, lower.size()));
-  c->dG2L = (GhostRec *)dalloc(c, sizeof(GhostRec) * std::max<size_t>(1, g2l.size()));
-  if (!c->dLower || !c->dG2L) return fail(c, PW_ENOMEM, "device allocation failed");
+  c->dBricks = (GBrick *)dalloc(c, sizeof(GBrick) * std::max<size_t>(1, bricks.size()));
+  if (!c->dLower || !c->dBricks) return fail(c, PW_ENOMEM, "device allocation failed");
   if (!lower.empty())
     HIPCHK(c, hipMemcpy(c->dLower, lower.data(), sizeof(GhostRec) * lower.size(), hipMemcpyHostToDevice));
-  if (!g2l.empty()) HIPCHK(c, hipMemcpy(c->dG2L, g2l.data(), sizeof(GhostRec) * g2l.size(), hipMemcpyHostToDevice));
+  if (!bricks.empty())
+    HIPCHK(c, hipMemcpy(c->dBricks, bricks.data(), sizeof(GBrick) * bricks.size(), hipMemcpyHostToDevice));
 
   // Tiles of every patch, grouped by patch.
   std::vector<TileRec> tiles;
@@ -302,6 +340,21 @@ void enqueue_flags(pw_context *c, const PoseDev *pose_slot) {
   launch_flags(c->stream, a);
 }
 
+void enqueue_post_flags(pw_context *c) {
+  PostFlagsArgs a;
+  a.flag = c->flag_cur;
+  a.efflist = c->efflist;
+  a.effcount = c->effcount;
+  a.dvalid[0] = c->dvalid[0];
+  a.dvalid[1] = c->dvalid[1];
+  a.Pvals[0] = 5;
+  a.Pvals[1] = 6;
+  a.t1 = c->t1;
+  a.t2 = c->t2;
+  for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
+  launch_post_flags(c->stream, a);
+}
+
 void enqueue_finalize(pw_context *c, const PoseDev *pose_slot, int mode) {
   FinalizeArgs a;
   a.P = c->dP;
@@ -329,9 +382,11 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.pose = pose_slot;
     a.lower = c->dLower;
     a.n_lower = c->nLower;
-    a.g2l = c->dG2L;
-    a.n_g2l = c->nG2L;
-    a.gflag = has_locals(c) ? c->flag_cur : nullptr;
+    a.bricks = c->dBricks;
+    a.n_bricks = has_locals(c) ? c->nBricks : 0;
+    a.dvalid = c->dvalid[c->cfg.interp_points[sv] == 5 ? 0 : 1];
+    a.efflist = c->efflist;
+    a.effcount = c->effcount;
     a.cover = c->cover_cur;
     a.has_locals = has_locals(c);
     for (int d = 0; d < 3; d++) a.gn[d] = c->hp[0].n[d];
@@ -416,6 +471,7 @@ void enqueue_step(pw_context *c, double dt) {
     }
     Timed tm(c, PW_K_FINALIZE);
     enqueue_finalize(c, c->dPose + 2 * np, 1);
+    enqueue_post_flags(c);
   }
 }
 
@@ -428,6 +484,7 @@ pw_status ensure_flags(pw_context *c) {
     launch_pose(c->stream, c->dP, np, c->dT, 0.0, c->dPose);
     enqueue_flags(c, c->dPose);
     enqueue_finalize(c, c->dPose, 0);
+    enqueue_post_flags(c);
     int err = 0;
     HIPCHK(c, hipMemcpyAsync(&err, c->dErr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -537,6 +594,9 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     if (d->periodic[0] || d->periodic[1] || (d->periodic[2] && d->coord != PW_SPH))
       return fail(c, PW_EINVAL, "local patches are periodic only along the spherical phi axis");
     if (d->coord == PW_SPH && !(d->lo[0] > 0)) return fail(c, PW_EINVAL, "spherical patch needs r_min > 0");
+    const PatchDev &g = c->hp[0];
+    if (g.periodic[0] || g.periodic[1] || g.periodic[2])
+      return fail(c, PW_EINVAL, "local patches need a non-periodic global patch");
   }
   if (d->coord == PW_SPH) {
     double th_lo = d->lo[1] - PW_NG * (d->hi[1] - d->lo[1]) / d->n[1];
@@ -602,7 +662,16 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     c->live = (uint8_t *)dalloc(c, c->gcells);
     c->cover_cur = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
     c->cover_new = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
-    if (!c->flag_cur || !c->flag_new || !c->t1 || !c->t2 || !c->live || !c->cover_cur || !c->cover_new)
+    c->efflist = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
+    c->effcount = (int *)dalloc(c, sizeof(int));
+    for (int m = 0; m < 2; m++) {
+      bool used = false;
+      for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) used = used || c->cfg.interp_points[sv] == 5 + m;
+      c->dvalid[m] = used ? (uint8_t *)dalloc(c, c->gcells) : nullptr;
+      if (used && !c->dvalid[m]) return fail(c, PW_ENOMEM, "device allocation failed");
+    }
+    if (!c->flag_cur || !c->flag_new || !c->t1 || !c->t2 || !c->live || !c->cover_cur || !c->cover_new ||
+        !c->efflist || !c->effcount)
       return fail(c, PW_ENOMEM, "device allocation failed");
     launch_fill_u8(c->stream, c->flag_cur, c->gcells, LIVE);
     launch_fill_u8(c->stream, c->flag_new, c->gcells, LIVE);

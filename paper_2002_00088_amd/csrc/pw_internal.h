@@ -260,4 +260,44 @@ __device__ inline int lagrange_w(int P, double q, double *w) {
   return s;
 }
 
+// Compile-time-P Lagrange weights: the same nodes and start index as
+// lagrange_w, with the constant denominators prod_{l != m} (m - l) folded.
+template <int P>
+__device__ inline double lagrange_den(int m) {
+  double d = 1.0;
+  for (int l = 0; l < P; l++)
+    if (l != m) d *= (double)(m - l);
+  return d;
+}
+
+template <int P>
+__device__ inline int lagrange_wt(double q, double *w) {
+  const int s = (int)floor(q - 0.5 * (P - 2));
+  const double t = q - (double)s;
+  double pre[P], suf[P];
+  pre[0] = 1.0;
+#pragma unroll
+  for (int m = 1; m < P; m++) pre[m] = pre[m - 1] * (t - (double)(m - 1));
+  suf[P - 1] = 1.0;
+#pragma unroll
+  for (int m = P - 2; m >= 0; m--) suf[m] = suf[m + 1] * (t - (double)(m + 1));
+#pragma unroll
+  for (int m = 0; m < P; m++) w[m] = pre[m] * suf[m] / lagrange_den<P>(m);
+  return s;
+}
+
+// Weight of node m alone (used when a lane needs only a few of the weights).
+template <int P>
+__device__ inline double lagrange_one(double t, int m) {
+  double num = 1.0;
+#pragma unroll
+  for (int l = 0; l < P; l++)
+    if (l != m) num *= (t - (double)l);
+  double den = 1.0;
+#pragma unroll
+  for (int l = 0; l < P; l++)
+    if (l != m) den *= (double)(m - l);
+  return num / den;
+}
+
 }  // namespace pw

@@ -9,6 +9,9 @@
 #define TILE_Y 4
 #define TILE_Z 4
 #define DIAG_N 23
+#define BRICK_THREADS 192
+#define BRICK_LDS 6144
+#define L2G_BLOCKS 2048
 
 namespace pw {
 
@@ -28,6 +31,22 @@ struct CoverJob {
   int32_t patch;
   int32_t ext[3];
   double radius;
+};
+
+// A brick of ghost cells of one local patch: box [i0,i0+di) x [j0,j0+dj) x [k0,k0+dk)
+// in interior-relative cell indices, at most BRICK_THREADS cells.
+struct GBrick {
+  int32_t patch, i0, j0, k0, di, dj, dk, pad;
+};
+
+struct PostFlagsArgs {
+  const uint8_t *flag;
+  int32_t *efflist;
+  int *effcount;
+  uint8_t *dvalid[2];
+  int Pvals[2];
+  uint8_t *t1, *t2;
+  int n[3];
 };
 
 struct FlagsArgs {
@@ -63,9 +82,11 @@ struct GhostArgs {
   const PoseDev *pose;
   const GhostRec *lower;
   int n_lower;
-  const GhostRec *g2l;
-  int n_g2l;
-  const uint8_t *gflag;
+  const GBrick *bricks;
+  int n_bricks;
+  const uint8_t *dvalid;
+  const int32_t *efflist;
+  const int *effcount;
   const int32_t *cover;
   int has_locals;
   int gn[3];
@@ -93,6 +114,7 @@ void launch_advance_time(hipStream_t s, double *tdev, double dt, long long *coun
 void launch_flags(hipStream_t s, const FlagsArgs &a);
 void launch_finalize(hipStream_t s, const FinalizeArgs &a);
 void launch_ghosts(hipStream_t s, const GhostArgs &a);
+void launch_post_flags(hipStream_t s, const PostFlagsArgs &a);
 void launch_stage(hipStream_t s, const StageArgs &a);
 void launch_fill_f64(hipStream_t s, double *p, long long n, double v);
 void launch_fill_f32(hipStream_t s, float *p, long long n, float v);

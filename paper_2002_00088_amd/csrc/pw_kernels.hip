@@ -231,33 +231,185 @@ __global__ void k_fill_lower(const PatchDev *P, const PoseDev *pose, const Ghost
   }
 }
 
-// Global -> local (Sec. 2.4.1): every non-periodic ghost cell of every local
-// patch is located in the global patch, interpolated there and transformed;
-// points that cannot be interpolated keep the lower-priority value.
-template <typename TB, typename TC>
-__global__ void k_fill_g2l(const PatchDev *P, const PoseDev *pose, const GhostRec *list, int count, int sv, int stage,
-                           const uint8_t *gflag, int Pts, const ExactDev *ex, double v, const double *tdev,
-                           double tmul, double dt, unsigned long long *skips) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= count) return;
-  const double t = tdev[0] + tmul * dt;
-  GhostRec g = list[q];
-  const PatchDev &r = P[g.patch];
+// ---------------------------------------------------------------------------
+// Per-step helper arrays of the global patch
+// ---------------------------------------------------------------------------
+// Forward window minimum along one axis: out[c] = min_{0<=d<P} in[c + d e_axis],
+// cells beyond the domain read 0.  Applied along x (from the flags, LIVE -> 1),
+// y and z it gives dvalid[c] = 1 iff the P^3 donor box starting at c is all live.
+template <int AXIS>
+__global__ void k_window_min(const uint8_t *in, uint8_t *out, int n0, int n1, int n2, int P, int from_flags) {
+  long long total = (long long)n0 * n1 * n2;
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= total) return;
+  int i = (int)(c % n0), j = (int)((c / n0) % n1), k = (int)(c / ((long long)n0 * n1));
+  int pos = AXIS == 0 ? i : (AXIS == 1 ? j : k);
+  int len = AXIS == 0 ? n0 : (AXIS == 1 ? n1 : n2);
+  long long stride = AXIS == 0 ? 1 : (AXIS == 1 ? (long long)n0 : (long long)n0 * n1);
+  int m = 1;
+  for (int d = 0; d < P; d++) {
+    int v = 0;
+    if (pos + d < len) v = from_flags ? (in[c + d * stride] == LIVE) : in[c + d * stride];
+    m = v < m ? v : m;
+  }
+  out[c] = (uint8_t)m;
+}
+
+__global__ void k_set_int(int *p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+
+// Compacted list of the effective ghost cells (wave-aggregated append; the
+// order of the list does not affect any result).
+__global__ void k_efflist(const uint8_t *flag, long long total, int32_t *list, int *count) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool e = c < total && flag[c] == EFFGHOST;
+  unsigned long long mask = __ballot(e);
+  int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 0 && mask) base = atomicAdd(count, (int)__popcll(mask));
+  base = __shfl(base, 0);
+  if (e) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)c;
+}
+
+// ---------------------------------------------------------------------------
+// Global -> local (Sec. 2.4.1).  One workgroup per brick of up to 8x8x3 ghost
+// cells of one face of a local patch.  Each thread locates its point in the
+// global patch (FP64) and forms its Lagrange weights (FP64); the union of the
+// donor stencils is staged in LDS one field at a time (coalesced rows) and every
+// thread sums its P^3 taps from LDS.  Validity is one byte: every cell of the
+// donor stencil must be live.  Points that cannot be interpolated keep the
+// lower-priority value (analytic or nearest interior) and are counted.
+// ---------------------------------------------------------------------------
+template <typename TB, typename TC, int Pts>
+__global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *P, const PoseDev *pose,
+                                                             const GBrick *bricks, int sv, int stage,
+                                                             const uint8_t *dvalid, const ExactDev *ex,
+                                                             double v, const double *tdev, double tmul, double dt,
+                                                             unsigned long long *skips) {
+  __shared__ TC box[BRICK_LDS];
+  __shared__ int blo[3], bhi[3];
+  const GBrick B = bricks[blockIdx.x];
+  const PatchDev &r = P[B.patch];
   const PatchDev &G0 = P[0];
-  if (!(r.sv_mask & (1u << sv))) return;
-  TB *T = stage_buf<TB>(r, sv, stage);
-  int c[3];
-  unpack_ijk(g.cell, c[0], c[1], c[2]);
-  long long dst = cell_index(r, c[0], c[1], c[2]);
-  double xr[3] = {xnum(r, 0, c[0]), xnum(r, 1, c[1]), xnum(r, 2, c[2])}, X[3], out[5];
-  fwd_map(r, pose[g.patch], xr, X);
-  bool ok = (G0.sv_mask & (1u << sv)) &&
-            interp_transform<TB, TC>(G0, pose[0], stage_buf<TB>(G0, sv, stage), gflag, Pts, X, r, pose[g.patch], xr,
-                                     out);
-  if (!ok) {
-    atomicAdd(skips, 1ull);
+  const double t = tdev[0] + tmul * dt;
+  const int tid = threadIdx.x;
+  if (tid < 3) {
+    blo[tid] = 1 << 30;
+    bhi[tid] = -(1 << 30);
+  }
+  __syncthreads();
+  const int c[3] = {B.i0 + tid % B.di, B.j0 + (tid / B.di) % B.dj, B.k0 + tid / (B.di * B.dj)};
+  bool active = tid < B.di * B.dj * B.dk;
+  if (active) {
+    bool inside = true, winside = true;
+    for (int a = 0; a < 3; a++) {
+      inside = inside && c[a] >= 0 && c[a] < r.n[a];
+      int w = r.periodic[a] ? ((c[a] % r.n[a]) + r.n[a]) % r.n[a] : c[a];
+      winside = winside && w >= 0 && w < r.n[a];
+    }
+    active = (r.sv_mask & (1u << sv)) && !inside && !winside;
+  }
+  const bool has_donor = (G0.sv_mask & (1u << sv)) != 0;
+  bool valid = false;
+  int s[3] = {0, 0, 0};
+  double wx[Pts], wy[Pts], wz[Pts];
+  double xr[3] = {0, 0, 0}, xd[3] = {0, 0, 0};
+  if (active && has_donor) {
+    double X[3];
+    for (int a = 0; a < 3; a++) xr[a] = xnum(r, a, c[a]);
+    fwd_map(r, pose[B.patch], xr, X);
+    inv_map(G0, pose[0], X, xd);
+    double q[3];
+    bool fin = true;
+    for (int a = 0; a < 3; a++) {
+      q[a] = (xd[a] - G0.lo[a]) * G0.idx[a] - 0.5;
+      fin = fin && (q[a] > -1.0e6 && q[a] < 1.0e6);
+    }
+    if (fin) {
+      s[0] = lagrange_wt<Pts>(q[0], wx);
+      s[1] = lagrange_wt<Pts>(q[1], wy);
+      s[2] = lagrange_wt<Pts>(q[2], wz);
+      bool inr = true;
+      for (int a = 0; a < 3; a++) inr = inr && s[a] >= 0 && s[a] + Pts - 1 <= G0.n[a] - 1;
+      if (inr) valid = dvalid[((long long)s[2] * G0.n[1] + s[1]) * G0.n[0] + s[0]] != 0;
+    }
+    if (valid)
+      for (int a = 0; a < 3; a++) {
+        atomicMin(&blo[a], s[a]);
+        atomicMax(&bhi[a], s[a] + Pts - 1);
+      }
+  }
+  __syncthreads();
+  const int lo0 = blo[0], lo1 = blo[1], lo2 = blo[2];
+  const int e0 = bhi[0] - lo0 + 1, e1 = bhi[1] - lo1 + 1, e2 = bhi[2] - lo2 + 1;
+  const long long vol = (e0 > 0 && e1 > 0 && e2 > 0) ? (long long)e0 * e1 * e2 : 0;
+  const TB *T = stage_buf<TB>(G0, sv, stage);
+  TC acc[5] = {0, 0, 0, 0, 0};
+  TC wxc[Pts], wyzc[Pts][Pts];
+#pragma unroll
+  for (int a = 0; a < Pts; a++) wxc[a] = (TC)wx[a];
+#pragma unroll
+  for (int cc = 0; cc < Pts; cc++)
+#pragma unroll
+    for (int b = 0; b < Pts; b++) wyzc[cc][b] = (TC)(wy[b] * wz[cc]);
+  if (vol > 0 && vol <= BRICK_LDS) {
+    const int e01 = e0 * e1;
+    const int nrows = e1 * e2;
+    const int lane32 = tid & 31, row0 = tid >> 5;
+    for (int f = 0; f < 5; f++) {
+      const TB *Tf = T + f * G0.fstride;
+      // rows of the donor box, 32 threads per row
+      for (int row = row0; row < nrows; row += BRICK_THREADS / 32) {
+        const int b = row % e1, cc = row / e1;
+        const TB *src = Tf + cell_index(G0, lo0, lo1 + b, lo2 + cc);
+        TC *dst = box + cc * e01 + b * e0;
+        for (int x = lane32; x < e0; x += 32) dst[x] = (TC)src[x];
+      }
+      __syncthreads();
+      if (valid) {
+        TC sum = (TC)0;
+        const TC *base = box + (s[2] - lo2) * e01 + (s[1] - lo1) * e0 + (s[0] - lo0);
+#pragma unroll
+        for (int cc = 0; cc < Pts; cc++)
+#pragma unroll
+          for (int b = 0; b < Pts; b++) {
+            const TC *row = base + cc * e01 + b * e0;
+            TC part = (TC)0;
+#pragma unroll
+            for (int a = 0; a < Pts; a++) part += wxc[a] * row[a];
+            sum += wyzc[cc][b] * part;
+          }
+        acc[f] = sum;
+      }
+      __syncthreads();
+    }
+  } else if (valid) {
+    // donor box larger than the LDS tile: gather straight from global memory
+    for (int cc = 0; cc < Pts; cc++)
+      for (int b = 0; b < Pts; b++) {
+        TC part[5] = {0, 0, 0, 0, 0};
+        const long long x0 = cell_index(G0, s[0], s[1] + b, s[2] + cc);
+#pragma unroll
+        for (int a = 0; a < Pts; a++)
+#pragma unroll
+          for (int f = 0; f < 5; f++) part[f] += wxc[a] * (TC)T[f * G0.fstride + x0 + a];
+        for (int f = 0; f < 5; f++) acc[f] += wyzc[cc][b] * part[f];
+      }
+  }
+  if (!active) return;
+  double out[5];
+  if (valid) {
+    double in4[4] = {(double)acc[1], (double)acc[2], (double)acc[3], (double)acc[4]}, G[3], pit, o4[4];
+    patch_to_bg(G0, pose[0], xd, in4, pit, G);
+    bg_to_patch(r, pose[B.patch], xr, pit, G, o4);
+    out[0] = (double)acc[0];
+    for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
+  } else {
+    if (has_donor) atomicAdd(skips, 1ull);
+    for (int a = 0; a < 3; a++) xr[a] = xnum(r, a, c[a]);
     if (ex[sv].kind != EX_NONE) {
-      exact_patch(ex[sv], v, r, pose[g.patch], t, xr, out);
+      exact_patch(ex[sv], v, r, pose[B.patch], t, xr, out);
     } else {
       int w[3];
       for (int a = 0; a < 3; a++) {
@@ -265,42 +417,100 @@ __global__ void k_fill_g2l(const PatchDev *P, const PoseDev *pose, const GhostRe
         if (r.periodic[a]) w[a] = ((c[a] % r.n[a]) + r.n[a]) % r.n[a];
         w[a] = w[a] < 0 ? 0 : (w[a] >= r.n[a] ? r.n[a] - 1 : w[a]);
       }
+      const TB *TR = stage_buf<TB>(r, sv, stage);
       long long src = cell_index(r, w[0], w[1], w[2]);
-      for (int f = 0; f < 5; f++) out[f] = (double)T[f * r.fstride + src];
+      for (int f = 0; f < 5; f++) out[f] = (double)TR[f * r.fstride + src];
     }
   }
-  for (int f = 0; f < 5; f++) T[f * r.fstride + dst] = (TB)out[f];
+  TB *TR = stage_buf<TB>(r, sv, stage);
+  long long dst = cell_index(r, c[0], c[1], c[2]);
+  for (int f = 0; f < 5; f++) TR[f * r.fstride + dst] = (TB)out[f];
 }
 
-// Local -> global (Sec. 2.4.2): effective ghost cells of the global patch are
-// interpolated from the covering local patch and transformed to the global frame.
-template <typename TB, typename TC>
-__global__ void k_fill_l2g(const PatchDev *P, const PoseDev *pose, const uint8_t *gflag, const int32_t *cover, int sv,
-                           int stage, int Pts, const ExactDev *ex, double v, const double *tdev, double tmul, double dt,
-                           unsigned long long *skips) {
+// ---------------------------------------------------------------------------
+// Local -> global (Sec. 2.4.2).  One wavefront per effective ghost cell: every
+// lane forms the point's donor location and weights (FP64, identical in all
+// lanes), takes up to four of the P^3 taps, and the five partial sums are
+// reduced across the 64 lanes with shuffles.  Lane 0 transforms to the global
+// frame and writes.
+// ---------------------------------------------------------------------------
+template <typename TB, typename TC, int Pts>
+__global__ __launch_bounds__(256) void k_l2g_wave(const PatchDev *P, const PoseDev *pose, const int32_t *list,
+                                                  const int *count, const int32_t *cover, int sv, int stage,
+                                                  const ExactDev *ex, double v, const double *tdev, double tmul,
+                                                  double dt, unsigned long long *skips) {
   const PatchDev &G0 = P[0];
-  const double t = tdev[0] + tmul * dt;
-  long long total = (long long)G0.n[0] * G0.n[1] * G0.n[2];
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= total || gflag[c] != EFFGHOST) return;
   if (!(G0.sv_mask & (1u << sv))) return;
-  int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]), k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
-  int d = cover[c];
-  const PatchDev &D = P[d];
-  double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)}, out[5];
-  bool ok = (D.sv_mask & (1u << sv)) &&
-            interp_transform<TB, TC>(D, pose[d], stage_buf<TB>(D, sv, stage), nullptr, Pts, X, G0, pose[0], X, out);
-  if (!ok) {
-    atomicAdd(skips, 1ull);
-    if (ex[sv].kind != EX_NONE) {
-      exact_patch(ex[sv], v, G0, pose[0], t, X, out);
-    } else {
-      for (int f = 0; f < 5; f++) out[f] = NAN;
+  const int lane = threadIdx.x & 63;
+  const long long wid = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long long nw = ((long long)gridDim.x * blockDim.x) >> 6;
+  const int n = count[0];
+  const double t = tdev[0] + tmul * dt;
+  constexpr int P3 = Pts * Pts * Pts;
+  constexpr int NT = (P3 + 63) / 64;
+  TB *TG = stage_buf<TB>(G0, sv, stage);
+  for (long long qi = wid; qi < n; qi += nw) {
+    const long long c = list[qi];
+    const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]),
+              k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
+    const int d = cover[c];
+    const PatchDev &D = P[d >= 1 ? d : 0];
+    double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)}, xd[3] = {0, 0, 0};
+    bool valid = d >= 1 && (D.sv_mask & (1u << sv));
+    int s[3] = {0, 0, 0};
+    double tq[3] = {0, 0, 0};
+    if (valid) {
+      inv_map(D, pose[d], X, xd);
+      for (int a = 0; a < 3; a++) {
+        double q = (xd[a] - D.lo[a]) * D.idx[a] - 0.5;
+        valid = valid && (q > -1.0e6 && q < 1.0e6);
+        if (valid) {
+          s[a] = (int)floor(q - 0.5 * (Pts - 2));
+          tq[a] = q - (double)s[a];
+          if (!D.periodic[a] && (s[a] < 0 || s[a] + Pts - 1 > D.n[a] - 1)) valid = false;
+        }
+      }
+    }
+    TC part[5] = {0, 0, 0, 0, 0};
+    if (valid) {
+      const TB *T = stage_buf<TB>(D, sv, stage);
+#pragma unroll
+      for (int m = 0; m < NT; m++) {
+        const int tt = lane + 64 * m;
+        if (tt < P3) {
+          const int a = tt % Pts, b = (tt / Pts) % Pts, cc = tt / (Pts * Pts);
+          int ii = s[0] + a, jj = s[1] + b, kk = s[2] + cc;
+          if (D.periodic[0]) ii = ((ii % D.n[0]) + D.n[0]) % D.n[0];
+          if (D.periodic[1]) jj = ((jj % D.n[1]) + D.n[1]) % D.n[1];
+          if (D.periodic[2]) kk = ((kk % D.n[2]) + D.n[2]) % D.n[2];
+          const long long x = cell_index(D, ii, jj, kk);
+          const TC w = (TC)(lagrange_one<Pts>(tq[0], a) * lagrange_one<Pts>(tq[1], b) * lagrange_one<Pts>(tq[2], cc));
+#pragma unroll
+          for (int f = 0; f < 5; f++) part[f] += w * (TC)T[f * D.fstride + x];
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+      for (int f = 0; f < 5; f++) part[f] += __shfl_xor(part[f], off);
+    if (lane == 0) {
+      double out[5];
+      if (valid) {
+        double in4[4] = {(double)part[1], (double)part[2], (double)part[3], (double)part[4]}, G[3], pit, o4[4];
+        patch_to_bg(D, pose[d], xd, in4, pit, G);
+        bg_to_patch(G0, pose[0], X, pit, G, o4);
+        out[0] = (double)part[0];
+        for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
+      } else {
+        atomicAdd(skips, 1ull);
+        if (ex[sv].kind != EX_NONE) exact_patch(ex[sv], v, G0, pose[0], t, X, out);
+        else for (int f = 0; f < 5; f++) out[f] = NAN;
+      }
+      long long dst = cell_index(G0, i, j, k);
+      for (int f = 0; f < 5; f++) TG[f * G0.fstride + dst] = (TB)out[f];
     }
   }
-  TB *T = stage_buf<TB>(G0, sv, stage);
-  long long dst = cell_index(G0, i, j, k);
-  for (int f = 0; f < 5; f++) T[f * G0.fstride + dst] = (TB)out[f];
 }
 
 // End of step: cells live now but not live during the step get u_{n+1}
@@ -612,39 +822,53 @@ void launch_finalize(hipStream_t s, const FinalizeArgs &a) {
                      a.cover_cur, a.cover_new, a.nsv, a.Pts, a.ex, a.vs, a.tdev, a.mode, a.counters);
 }
 
-void launch_ghosts(hipStream_t s, const GhostArgs &a) {
+template <typename TB, typename TC>
+static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
   const int bs = 256;
-  long long gtot = (long long)a.gn[0] * a.gn[1] * a.gn[2];
+  if (a.n_lower > 0)
+    hipLaunchKernelGGL(k_fill_lower<TB>, dim3(nblk(a.n_lower, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower, a.n_lower,
+                       a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
+  if (a.n_bricks > 0) {
+    if (a.Pts == 5)
+      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 5>), dim3(a.n_bricks), dim3(BRICK_THREADS), 0, s, a.P, a.pose,
+                         a.bricks, a.sv, a.stage, a.dvalid, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips);
+    else
+      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 6>), dim3(a.n_bricks), dim3(BRICK_THREADS), 0, s, a.P, a.pose,
+                         a.bricks, a.sv, a.stage, a.dvalid, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips);
+  }
+  if (a.has_locals) {
+    if (a.Pts == 5)
+      hipLaunchKernelGGL((k_l2g_wave<TB, TC, 5>), dim3(L2G_BLOCKS), dim3(256), 0, s, a.P, a.pose, a.efflist,
+                         a.effcount, a.cover, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
+    else
+      hipLaunchKernelGGL((k_l2g_wave<TB, TC, 6>), dim3(L2G_BLOCKS), dim3(256), 0, s, a.P, a.pose, a.efflist,
+                         a.effcount, a.cover, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
+  }
+}
+
+void launch_ghosts(hipStream_t s, const GhostArgs &a) {
   if (a.stage_fp64) {
-    if (a.n_lower > 0)
-      hipLaunchKernelGGL(k_fill_lower<double>, dim3(nblk(a.n_lower, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower,
-                         a.n_lower, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
-    if (a.n_g2l > 0) {
-      if (a.mixed)
-        hipLaunchKernelGGL((k_fill_g2l<double, float>), dim3(nblk(a.n_g2l, bs)), dim3(bs), 0, s, a.P, a.pose, a.g2l,
-                           a.n_g2l, a.sv, a.stage, a.gflag, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips);
-      else
-        hipLaunchKernelGGL((k_fill_g2l<double, double>), dim3(nblk(a.n_g2l, bs)), dim3(bs), 0, s, a.P, a.pose, a.g2l,
-                           a.n_g2l, a.sv, a.stage, a.gflag, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips);
-    }
-    if (a.has_locals) {
-      if (a.mixed)
-        hipLaunchKernelGGL((k_fill_l2g<double, float>), dim3(nblk(gtot, bs)), dim3(bs), 0, s, a.P, a.pose, a.gflag,
-                           a.cover, a.sv, a.stage, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
-      else
-        hipLaunchKernelGGL((k_fill_l2g<double, double>), dim3(nblk(gtot, bs)), dim3(bs), 0, s, a.P, a.pose, a.gflag,
-                           a.cover, a.sv, a.stage, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
-    }
+    if (a.mixed) ghosts_typed<double, float>(s, a);
+    else ghosts_typed<double, double>(s, a);
   } else {
-    if (a.n_lower > 0)
-      hipLaunchKernelGGL(k_fill_lower<float>, dim3(nblk(a.n_lower, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower,
-                         a.n_lower, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
-    if (a.n_g2l > 0)
-      hipLaunchKernelGGL((k_fill_g2l<float, float>), dim3(nblk(a.n_g2l, bs)), dim3(bs), 0, s, a.P, a.pose, a.g2l,
-                         a.n_g2l, a.sv, a.stage, a.gflag, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips);
-    if (a.has_locals)
-      hipLaunchKernelGGL((k_fill_l2g<float, float>), dim3(nblk(gtot, bs)), dim3(bs), 0, s, a.P, a.pose, a.gflag,
-                         a.cover, a.sv, a.stage, a.Pts, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
+    ghosts_typed<float, float>(s, a);
+  }
+}
+
+void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
+  long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
+  unsigned nb = nblk(tot, 256);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.effcount, 0);
+  hipLaunchKernelGGL(k_efflist, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.flag, tot, a.efflist, a.effcount);
+  for (int m = 0; m < 2; m++) {
+    if (!a.dvalid[m]) continue;
+    int P = a.Pvals[m];
+    hipLaunchKernelGGL(k_window_min<0>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.flag, a.t1, a.n[0], a.n[1],
+                       a.n[2], P, 1);
+    hipLaunchKernelGGL(k_window_min<1>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.t1, a.t2, a.n[0], a.n[1],
+                       a.n[2], P, 0);
+    hipLaunchKernelGGL(k_window_min<2>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.t2, a.dvalid[m], a.n[0],
+                       a.n[1], a.n[2], P, 0);
   }
 }
 
