@@ -52,6 +52,7 @@ struct pw_context {
   TileRec *dTiles = nullptr;
   int nTiles = 0;
   std::vector<int> tileOff, tileCnt;
+  int nCartTiles = 0;
   CoverJob *dJobs = nullptr;
   int nJobs = 0, coverBlocks = 1;
   double *dStage = nullptr;  // staging for host copies
@@ -264,17 +265,24 @@ pw_status upload_layout(pw_context *c) {
   if (!bricks.empty())
     HIPCHK(c, hipMemcpy(c->dBricks, bricks.data(), sizeof(GBrick) * bricks.size(), hipMemcpyHostToDevice));
 
-  // Tiles of every patch, grouped by patch.
+  // Tiles of every patch, grouped by patch, Cartesian patches first.
   std::vector<TileRec> tiles;
   c->tileOff.assign(np, 0);
   c->tileCnt.assign(np, 0);
-  for (int pid = 0; pid < np; pid++) {
+  std::vector<int> order;
+  for (int pid = 0; pid < np; pid++)
+    if (c->hp[pid].coord == CART) order.push_back(pid);
+  for (int pid = 0; pid < np; pid++)
+    if (c->hp[pid].coord != CART) order.push_back(pid);
+  c->nCartTiles = 0;
+  for (int pid : order) {
     const PatchDev &p = c->hp[pid];
     c->tileOff[pid] = (int)tiles.size();
-    for (int z = 0; z < p.n[2]; z += TILE_Z)
-      for (int y = 0; y < p.n[1]; y += TILE_Y)
-        for (int x = 0; x < p.n[0]; x += TILE_X) tiles.push_back(TileRec{pid, x, y, z});
+    for (int z = 0; z < p.n[2]; z += ST_TZ)
+      for (int y = 0; y < p.n[1]; y += ST_TY)
+        for (int x = 0; x < p.n[0]; x += ST_TX) tiles.push_back(TileRec{pid, x, y, z});
     c->tileCnt[pid] = (int)tiles.size() - c->tileOff[pid];
+    if (p.coord == CART) c->nCartTiles = (int)tiles.size();
   }
   dfree(c, c->dTiles);
   c->nTiles = (int)tiles.size();
@@ -417,29 +425,27 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
     a.dt = dt;
     a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
     a.eps = c->cfg.ko_eps;
-    if (c->cfg.schedule == PW_SCHED_PER_PATCH) {
+    bool all = true;
+    for (auto &p : c->hp) all = all && (p.sv_mask & (1u << sv));
+    if (c->cfg.schedule == PW_SCHED_PER_PATCH || !all) {
       for (size_t pid = 0; pid < c->hp.size(); pid++) {
         if (!(c->hp[pid].sv_mask & (1u << sv))) continue;
         a.tiles = c->dTiles + c->tileOff[pid];
         a.ntiles = c->tileCnt[pid];
+        a.coord = c->hp[pid].coord;
         launch_stage(c->stream, a);
       }
     } else {
-      // batched: all tiles of every patch carrying sv in one launch
+      // batched: one launch over the tiles of all Cartesian patches, one over
+      // the tiles of all spherical patches
       a.tiles = c->dTiles;
-      a.ntiles = c->nTiles;
-      bool all = true;
-      for (auto &p : c->hp) all = all && (p.sv_mask & (1u << sv));
-      if (all) {
-        launch_stage(c->stream, a);
-      } else {
-        for (size_t pid = 0; pid < c->hp.size(); pid++) {
-          if (!(c->hp[pid].sv_mask & (1u << sv))) continue;
-          a.tiles = c->dTiles + c->tileOff[pid];
-          a.ntiles = c->tileCnt[pid];
-          launch_stage(c->stream, a);
-        }
-      }
+      a.ntiles = c->nCartTiles;
+      a.coord = CART;
+      launch_stage(c->stream, a);
+      a.tiles = c->dTiles + c->nCartTiles;
+      a.ntiles = c->nTiles - c->nCartTiles;
+      a.coord = SPH;
+      launch_stage(c->stream, a);
     }
   }
 }

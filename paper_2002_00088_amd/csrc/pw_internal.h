@@ -51,6 +51,18 @@ struct ExactDev {
   double pa[PW_MAXPULSE], px[PW_MAXPULSE][3], pw[PW_MAXPULSE];
 };
 
+// Loads and stores through the global address space (the pointers held in the
+// patch table are generic; these casts let the compiler emit global_load/store
+// with a scalar base and a 32-bit offset instead of flat instructions).
+template <typename T>
+__device__ __forceinline__ T gld(const T *base, uint32_t off) {
+  return ((const __attribute__((address_space(1))) T *)base)[off];
+}
+template <typename T>
+__device__ __forceinline__ void gst(T *base, uint32_t off, T v) {
+  ((__attribute__((address_space(1))) T *)base)[off] = v;
+}
+
 __host__ __device__ inline long long cell_index(const PatchDev &p, int i, int j, int k) {
   return (long long)(k + PW_NG) * p.slab + (long long)(j + PW_NG) * p.pitch + (i + PW_OX);
 }

@@ -5,9 +5,13 @@
 
 #include "pw_internal.h"
 
-#define TILE_X 64
-#define TILE_Y 4
-#define TILE_Z 4
+// stage-kernel tile: ST_TX x ST_TY columns, up to ST_TZ planes per workgroup
+#define ST_TX 32
+#define ST_TY 8
+#define ST_TZ 32
+#define ST_PX (ST_TX + 6)
+#define ST_PY (ST_TY + 6)
+#define ST_PW (ST_PX * ST_PY)
 #define DIAG_N 23
 #define BRICK_THREADS 192
 #define BRICK_LDS 6144
@@ -101,8 +105,9 @@ struct GhostArgs {
 struct StageArgs {
   const PatchDev *P;
   const PoseDev *pose;
-  const TileRec *tiles;
+  const TileRec *tiles;  // all of one topology (coord)
   int ntiles;
+  int coord;
   const uint8_t *gflag;
   int sv, stage, mixed;
   double dt, v2, eps;

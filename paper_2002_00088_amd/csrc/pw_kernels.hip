@@ -259,17 +259,39 @@ __global__ void k_set_int(int *p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
 }
 
-// Compacted list of the effective ghost cells (wave-aggregated append; the
-// order of the list does not affect any result).
-__global__ void k_efflist(const uint8_t *flag, long long total, int32_t *list, int *count) {
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  bool e = c < total && flag[c] == EFFGHOST;
-  unsigned long long mask = __ballot(e);
-  int lane = threadIdx.x & 63;
-  int base = 0;
-  if (lane == 0 && mask) base = atomicAdd(count, (int)__popcll(mask));
-  base = __shfl(base, 0);
-  if (e) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)c;
+// Compacted list of the effective ghost cells (one atomic per workgroup of
+// 256 x EFF_PER_THREAD cells; the order of the list does not affect any result).
+#define EFF_PER_THREAD 16
+__global__ __launch_bounds__(256) void k_efflist(const uint8_t *flag, long long total, int32_t *list, int *count) {
+  __shared__ int wsum[4], wbase[4], bbase;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long start = (long long)blockIdx.x * 256 * EFF_PER_THREAD;
+  unsigned long long masks[EFF_PER_THREAD];
+  int mine = 0;
+#pragma unroll
+  for (int r = 0; r < EFF_PER_THREAD; r++) {
+    const long long c = start + (long long)r * 256 + threadIdx.x;
+    const bool e = c < total && flag[c] == EFFGHOST;
+    masks[r] = __ballot(e);
+    mine += (int)__popcll(masks[r]);
+  }
+  if (lane == 0) wsum[w] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    bbase = tot ? atomicAdd(count, tot) : 0;
+    int acc = 0;
+    for (int q = 0; q < 4; q++) { wbase[q] = acc; acc += wsum[q]; }
+  }
+  __syncthreads();
+  int off = bbase + wbase[w];
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int r = 0; r < EFF_PER_THREAD; r++) {
+    const long long c = start + (long long)r * 256 + threadIdx.x;
+    if ((masks[r] >> lane) & 1ull) list[off + __popcll(masks[r] & below)] = (int32_t)c;
+    off += (int)__popcll(masks[r]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -428,14 +450,25 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *P, 
 }
 
 // ---------------------------------------------------------------------------
-// Local -> global (Sec. 2.4.2).  One wavefront per effective ghost cell: every
-// lane forms the point's donor location and weights (FP64, identical in all
-// lanes), takes up to four of the P^3 taps, and the five partial sums are
-// reduced across the 64 lanes with shuffles.  Lane 0 transforms to the global
-// frame and writes.
+// Local -> global (Sec. 2.4.2).  A wavefront takes 64 effective ghost cells of
+// the compacted list, one per lane: each lane locates its point in the covering
+// local patch and forms its Lagrange weights (FP64).  The P^3 taps are then
+// summed cooperatively, one point at a time: the point's stencil start and
+// weights are broadcast with readlane, lane (a, b) reads the x-row element a of
+// row b for every z-layer c, and the five partial sums are reduced across the
+// wavefront with xor shuffles.  Each lane finally transforms its own point to
+// the global frame and stores it.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int bcast_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ double bcast_d(double v, int lane) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <typename TB, typename TC, int Pts>
-__global__ __launch_bounds__(256) void k_l2g_wave(const PatchDev *P, const PoseDev *pose, const int32_t *list,
+__global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *P, const PoseDev *pose, const int32_t *list,
                                                   const int *count, const int32_t *cover, int sv, int stage,
                                                   const ExactDev *ex, double v, const double *tdev, double tmul,
                                                   double dt, unsigned long long *skips) {
@@ -446,68 +479,95 @@ __global__ __launch_bounds__(256) void k_l2g_wave(const PatchDev *P, const PoseD
   const long long nw = ((long long)gridDim.x * blockDim.x) >> 6;
   const int n = count[0];
   const double t = tdev[0] + tmul * dt;
-  constexpr int P3 = Pts * Pts * Pts;
-  constexpr int NT = (P3 + 63) / 64;
+  const int la = lane % Pts, lb = lane / Pts;
+  const bool tap_lane = lane < Pts * Pts;
   TB *TG = stage_buf<TB>(G0, sv, stage);
-  for (long long qi = wid; qi < n; qi += nw) {
-    const long long c = list[qi];
+  for (long long base = wid * 64; base < n; base += nw * 64) {
+    const long long qi = base + lane;
+    const bool have = qi < n;
+    const long long c = have ? list[qi] : 0;
     const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]),
               k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
-    const int d = cover[c];
-    const PatchDev &D = P[d >= 1 ? d : 0];
+    const int d = have ? cover[c] : 0;
     double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)}, xd[3] = {0, 0, 0};
-    bool valid = d >= 1 && (D.sv_mask & (1u << sv));
+    bool valid = have && d >= 1 && (P[d].sv_mask & (1u << sv));
     int s[3] = {0, 0, 0};
-    double tq[3] = {0, 0, 0};
+    double wx[Pts], wy[Pts], wz[Pts];
+#pragma unroll
+    for (int m = 0; m < Pts; m++) { wx[m] = 0.0; wy[m] = 0.0; wz[m] = 0.0; }
     if (valid) {
+      const PatchDev &D = P[d];
       inv_map(D, pose[d], X, xd);
+      double q[3];
       for (int a = 0; a < 3; a++) {
-        double q = (xd[a] - D.lo[a]) * D.idx[a] - 0.5;
-        valid = valid && (q > -1.0e6 && q < 1.0e6);
-        if (valid) {
-          s[a] = (int)floor(q - 0.5 * (Pts - 2));
-          tq[a] = q - (double)s[a];
+        q[a] = (xd[a] - D.lo[a]) * D.idx[a] - 0.5;
+        valid = valid && (q[a] > -1.0e6 && q[a] < 1.0e6);
+      }
+      if (valid) {
+        s[0] = lagrange_wt<Pts>(q[0], wx);
+        s[1] = lagrange_wt<Pts>(q[1], wy);
+        s[2] = lagrange_wt<Pts>(q[2], wz);
+        for (int a = 0; a < 3; a++)
           if (!D.periodic[a] && (s[a] < 0 || s[a] + Pts - 1 > D.n[a] - 1)) valid = false;
-        }
       }
     }
-    TC part[5] = {0, 0, 0, 0, 0};
-    if (valid) {
+    TC res[5] = {0, 0, 0, 0, 0};
+    const unsigned long long vmask = __ballot(valid);
+    for (int pnt = 0; pnt < 64; pnt++) {
+      if (!((vmask >> pnt) & 1ull)) continue;
+      const int dd = bcast_i(d, pnt);
+      const int s0 = bcast_i(s[0], pnt), s1 = bcast_i(s[1], pnt), s2 = bcast_i(s[2], pnt);
+      double wxa = 0.0, wyb = 0.0, wzc[Pts];
+#pragma unroll
+      for (int m = 0; m < Pts; m++) {
+        const double bx = bcast_d(wx[m], pnt), by = bcast_d(wy[m], pnt);
+        wxa = (m == la) ? bx : wxa;
+        wyb = (m == lb) ? by : wyb;
+        wzc[m] = bcast_d(wz[m], pnt);
+      }
+      const PatchDev &D = P[dd];
       const TB *T = stage_buf<TB>(D, sv, stage);
+      const uint32_t fs = (uint32_t)D.fstride;
+      TC acc[5] = {0, 0, 0, 0, 0};
+      if (tap_lane) {
+        const double wab = wxa * wyb;
+        int ii = s0 + la, jj = s1 + lb;
+        if (D.periodic[0]) ii = ((ii % D.n[0]) + D.n[0]) % D.n[0];
+        if (D.periodic[1]) jj = ((jj % D.n[1]) + D.n[1]) % D.n[1];
 #pragma unroll
-      for (int m = 0; m < NT; m++) {
-        const int tt = lane + 64 * m;
-        if (tt < P3) {
-          const int a = tt % Pts, b = (tt / Pts) % Pts, cc = tt / (Pts * Pts);
-          int ii = s[0] + a, jj = s[1] + b, kk = s[2] + cc;
-          if (D.periodic[0]) ii = ((ii % D.n[0]) + D.n[0]) % D.n[0];
-          if (D.periodic[1]) jj = ((jj % D.n[1]) + D.n[1]) % D.n[1];
+        for (int cc = 0; cc < Pts; cc++) {
+          int kk = s2 + cc;
           if (D.periodic[2]) kk = ((kk % D.n[2]) + D.n[2]) % D.n[2];
-          const long long x = cell_index(D, ii, jj, kk);
-          const TC w = (TC)(lagrange_one<Pts>(tq[0], a) * lagrange_one<Pts>(tq[1], b) * lagrange_one<Pts>(tq[2], cc));
+          const uint32_t x = (uint32_t)cell_index(D, ii, jj, kk);
+          const TC w = (TC)(wab * wzc[cc]);
 #pragma unroll
-          for (int f = 0; f < 5; f++) part[f] += w * (TC)T[f * D.fstride + x];
+          for (int f = 0; f < 5; f++) acc[f] += w * (TC)gld(T, f * fs + x);
         }
       }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int f = 0; f < 5; f++) acc[f] += __shfl_xor(acc[f], off);
+      if (lane == pnt) {
+#pragma unroll
+        for (int f = 0; f < 5; f++) res[f] = acc[f];
+      }
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-      for (int f = 0; f < 5; f++) part[f] += __shfl_xor(part[f], off);
-    if (lane == 0) {
+    if (have) {
       double out[5];
       if (valid) {
-        double in4[4] = {(double)part[1], (double)part[2], (double)part[3], (double)part[4]}, G[3], pit, o4[4];
+        const PatchDev &D = P[d];
+        double in4[4] = {(double)res[1], (double)res[2], (double)res[3], (double)res[4]}, G[3], pit, o4[4];
         patch_to_bg(D, pose[d], xd, in4, pit, G);
         bg_to_patch(G0, pose[0], X, pit, G, o4);
-        out[0] = (double)part[0];
+        out[0] = (double)res[0];
         for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
       } else {
         atomicAdd(skips, 1ull);
         if (ex[sv].kind != EX_NONE) exact_patch(ex[sv], v, G0, pose[0], t, X, out);
         else for (int f = 0; f < 5; f++) out[f] = NAN;
       }
-      long long dst = cell_index(G0, i, j, k);
+      const long long dst = cell_index(G0, i, j, k);
       for (int f = 0; f < 5; f++) TG[f * G0.fstride + dst] = (TB)out[f];
     }
   }
@@ -567,117 +627,273 @@ __global__ void k_finalize(const PatchDev *P, const PoseDev *pose, uint8_t *flag
 // Cartesian: h = 1, m = a.  Spherical: h = (1, 1/r^2, 1/(r sin th)^2) and
 //   m = K a - Q(b) + v^2 (2/r, cot th / r^2, 0), Q the coordinate acceleration of
 //   straight-line motion in spherical coordinates.
+//
+// Tiling (2.5-D): a workgroup owns a 32 x 8 column tile and marches up to 32
+// planes in z.  Each thread keeps its column's 7-plane window of the 5 fields in
+// registers (z stencils) and a 5-plane window of D_x phi, D_y phi (mixed x-z and
+// y-z derivatives as D_z of D_x phi, D_y phi).  The centre plane of the 5 fields
+// and the plane two above it of phi are staged in LDS with a 3-cell x-y halo
+// for the x-y stencils.
 // ---------------------------------------------------------------------------
-template <typename TIN, typename TOUT, typename TC, int STAGE>
+template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD>
 __global__ __launch_bounds__(256) void k_stage(const PatchDev *P, const PoseDev *pose_slot, const TileRec *tiles,
-                                               const uint8_t *gflag, int sv, double dt, double v2, double eps) {
-  const TileRec tl = tiles[blockIdx.x];
+                                               int ntiles, int chunk, const uint8_t *gflag, int sv, double dt,
+                                               double v2, double eps) {
+  __shared__ TC Bc[2][5][ST_PW];
+  __shared__ TC Ad[2][ST_PW];
+  const int bid = blockIdx.x;
+  const int tidx = (bid & 7) * chunk + (bid >> 3);  // contiguous tile runs per XCD
+  if (tidx >= ntiles) return;
+  const TileRec tl = tiles[tidx];
   const PatchDev &p = P[tl.patch];
   const PoseDev &ps = pose_slot[tl.patch];
-  const int i = tl.x0 + threadIdx.x;
-  const int j = tl.y0 + threadIdx.y;
-  if (i >= p.n[0] || j >= p.n[1]) return;
+  const int tid = threadIdx.x;
+  const int tx = tid % ST_TX, ty = tid / ST_TX;
+  const int i = tl.x0 + tx, j = tl.y0 + ty;
+  const bool inpad = (i < p.n[0] + PW_NG) && (j < p.n[1] + PW_NG);
+  const bool icol = (i < p.n[0]) && (j < p.n[1]);
+  const int z0 = tl.z0;
+  const int nz = min(ST_TZ, p.n[2] - z0);
   const TIN *in = (const TIN *)(STAGE == 0 ? (const void *)p.u[sv] : (STAGE == 2 ? p.vb[sv] : p.va[sv]));
   TOUT *vout = (TOUT *)(STAGE == 1 ? p.vb[sv] : p.va[sv]);
   double *U = p.u[sv];
-  double *A = p.acc[sv];
-  const long long fs = p.fstride, sy = p.pitch, sz = p.slab;
+  double *Acc = p.acc[sv];
+  // 32-bit element offsets (a field of one patch holds < 2^31 elements)
+  const uint32_t fs = (uint32_t)p.fstride, sz = (uint32_t)p.slab;
+  const uint32_t col = (uint32_t)cell_index(p, i, j, 0);
+  uint32_t hoff[3];
+  bool hval[3];
+  int hslot[3];
+#pragma unroll
+  for (int m = 0; m < 3; m++) {
+    const int e = tid + 256 * m;
+    hval[m] = false;
+    hoff[m] = 0;
+    hslot[m] = e < ST_PW ? e : 0;
+    if (e < ST_PW) {
+      const int hx = e % ST_PX, hy = e / ST_PX;
+      const bool own = hx >= 3 && hx < 3 + ST_TX && hy >= 3 && hy < 3 + ST_TY;
+      const int gi = tl.x0 - 3 + hx, gj = tl.y0 - 3 + hy;
+      if (!own && gi < p.n[0] + PW_NG && gj < p.n[1] + PW_NG) {
+        hval[m] = true;
+        hoff[m] = (uint32_t)cell_index(p, gi, gj, 0);
+      }
+    }
+  }
+  const int own = (ty + 3) * ST_PX + (tx + 3);
   const TC i12dx[3] = {(TC)(p.idx[0] / 12.0), (TC)(p.idx[1] / 12.0), (TC)(p.idx[2] / 12.0)};
   const TC i12dx2[3] = {(TC)(p.idx[0] * p.idx[0] / 12.0), (TC)(p.idx[1] * p.idx[1] / 12.0),
                         (TC)(p.idx[2] * p.idx[2] / 12.0)};
   const TC ko[3] = {(TC)(eps / 64.0 * p.idx[0]), (TC)(eps / 64.0 * p.idx[1]), (TC)(eps / 64.0 * p.idx[2])};
-  const long long st[3] = {1, sy, sz};
   const bool moving = (ps.b[0] != 0.0) || (ps.b[1] != 0.0) || (ps.b[2] != 0.0);
-  for (int kk = 0; kk < TILE_Z; kk++) {
-    const int k = tl.z0 + kk;
-    if (k >= p.n[2]) break;
-    if (p.is_global && gflag && gflag[((long long)k * p.n[1] + j) * p.n[0] + i] != LIVE) continue;
-    const long long x0 = cell_index(p, i, j, k);
-    auto L = [&](int f, long long off) -> TC { return (TC)in[f * fs + x0 + off]; };
-    // metric coefficients
-    double m[3], beta[3], h[3];
-    if (p.coord == CART) {
-      for (int a = 0; a < 3; a++) { m[a] = ps.a[a]; beta[a] = ps.b[a]; h[a] = 1.0; }
-    } else {
-      double r = p.lo[0] + (i + 0.5) * p.dx[0];
-      double th = p.lo[1] + (j + 0.5) * p.dx[1];
-      double ph = p.lo[2] + (k + 0.5) * p.dx[2];
-      SphBasis B;
-      sph_basis(th, ph, B);
-      double ir = 1.0 / r, irs = ir / B.st, cot = B.ct / B.st;
-      double br = B.er[0] * ps.b[0] + B.er[1] * ps.b[1] + B.er[2] * ps.b[2];
-      double bt = B.et[0] * ps.b[0] + B.et[1] * ps.b[1] + B.et[2] * ps.b[2];
-      double bp = B.ep[0] * ps.b[0] + B.ep[1] * ps.b[1];
-      double ar = B.er[0] * ps.a[0] + B.er[1] * ps.a[1] + B.er[2] * ps.a[2];
-      double at = B.et[0] * ps.a[0] + B.et[1] * ps.a[1] + B.et[2] * ps.a[2];
-      double ap = B.ep[0] * ps.a[0] + B.ep[1] * ps.a[1];
-      beta[0] = br; beta[1] = bt * ir; beta[2] = bp * irs;
-      double Q0 = (bt * bt + bp * bp) * ir;
-      double Q1 = (-2.0 * br * bt + bp * bp * cot) * ir * ir;
-      double Q2 = -2.0 * bp * (br + bt * cot) * ir * irs;
-      m[0] = ar - Q0 + v2 * 2.0 * ir;
-      m[1] = at * ir - Q1 + v2 * cot * ir * ir;
-      m[2] = ap * irs - Q2;
-      h[0] = 1.0; h[1] = ir * ir; h[2] = irs * irs;
+  const double bdt = STAGE == 0 ? dt / 6.0 : (STAGE == 3 ? dt / 6.0 : dt / 3.0);
+  const double adt = STAGE == 2 ? dt : dt / 2.0;
+  TC q[5][7];
+  TC dqx[5], dqy[5];
+#pragma unroll
+  for (int f = 0; f < 5; f++)
+#pragma unroll
+    for (int d = 0; d < 7; d++) q[f][d] = (TC)0;
+#pragma unroll
+  for (int d = 0; d < 5; d++) { dqx[d] = (TC)0; dqy[d] = (TC)0; }
+  const TC w1[5] = {(TC)1, (TC)-8, (TC)0, (TC)8, (TC)-1};
+
+  // software pipeline: the loads of iteration it+1 are in flight while
+  // iteration it computes
+  TC pown[5], phA[3], phB[3][5];
+  double pu[5], pa[5];
+  auto prefetch = [&](int itp) {
+    const int zn = z0 - 3 + itp;
+    const uint32_t zo = (uint32_t)(zn + PW_NG) * sz;  // cell_index already holds the +NG of z = 0
+#pragma unroll
+    for (int f = 0; f < 5; f++) pown[f] = inpad ? (TC)gld(in, f * fs + col + zo - PW_NG * sz) : (TC)0;
+    if (itp >= 2) {
+      const uint32_t za = zo - (PW_NG + 1) * sz;
+#pragma unroll
+      for (int m = 0; m < 3; m++) phA[m] = hval[m] ? (TC)gld(in, hoff[m] + za) : (TC)0;
     }
-    TC dphi[3], dpi[3], d2phi[3], kof[5];
-    for (int f = 0; f < 5; f++) kof[f] = (TC)0;
-    for (int a = 0; a < 3; a++) {
-      const long long s1 = st[a];
-      TC pm2 = L(0, -2 * s1), pm1 = L(0, -s1), p0 = L(0, 0), pp1 = L(0, s1), pp2 = L(0, 2 * s1);
-      dphi[a] = ((pm2 - pp2) + (TC)8 * (pp1 - pm1)) * i12dx[a];
-      d2phi[a] = ((TC)16 * (pm1 + pp1) - (pm2 + pp2) - (TC)30 * p0) * i12dx2[a];
-      TC qm2 = L(1, -2 * s1), qm1 = L(1, -s1), qp1 = L(1, s1), qp2 = L(1, 2 * s1);
-      dpi[a] = ((qm2 - qp2) + (TC)8 * (qp1 - qm1)) * i12dx[a];
-      for (int f = 0; f < 5; f++) {
-        TC c0 = L(f, 0);
-        TC d6 = (L(f, -3 * s1) + L(f, 3 * s1)) - (TC)6 * (L(f, -2 * s1) + L(f, 2 * s1)) +
-                (TC)15 * (L(f, -s1) + L(f, s1)) - (TC)20 * c0;
-        kof[f] += d6 * ko[a];
+    if (itp >= 6) {
+      const uint32_t zb = zo - (PW_NG + 3) * sz;
+#pragma unroll
+      for (int m = 0; m < 3; m++)
+#pragma unroll
+        for (int f = 0; f < 5; f++) phB[m][f] = hval[m] ? (TC)gld(in, f * fs + hoff[m] + zb) : (TC)0;
+      if (icol) {
+#pragma unroll
+        for (int f = 0; f < 5; f++) {
+          if (STAGE != 3) pu[f] = gld(U, f * fs + col + zb);
+          if (STAGE != 0) pa[f] = gld(Acc, f * fs + col + zb);
+        }
       }
     }
-    TC rhs_pi = (TC)0;
-    for (int a = 0; a < 3; a++)
-      rhs_pi += (TC)m[a] * dphi[a] + (TC)(2.0 * beta[a]) * dpi[a] + (TC)(v2 * h[a] - beta[a] * beta[a]) * d2phi[a];
-    if (moving) {
-      // mixed derivatives D_i D_j phi, i < j, as products of first-derivative stencils
-      const TC w1[5] = {(TC)1, (TC)-8, (TC)0, (TC)8, (TC)-1};
-      for (int a = 0; a < 3; a++)
-        for (int b = a + 1; b < 3; b++) {
-          TC s = (TC)0;
-          for (int o1 = -2; o1 <= 2; o1++) {
-            if (o1 == 0) continue;
-            TC inner = (TC)0;
-            for (int o2 = -2; o2 <= 2; o2++) {
-              if (o2 == 0) continue;
-              inner += w1[o2 + 2] * L(0, o1 * st[a] + o2 * st[b]);
-            }
-            s += w1[o1 + 2] * inner;
-          }
-          TC dab = s * i12dx[a] * i12dx[b];
-          rhs_pi -= (TC)(2.0 * beta[a] * beta[b]) * dab;
-        }
-    }
-    TC K[5];
-    K[0] = L(1, 0) + kof[0];
-    K[1] = rhs_pi + kof[1];
-    for (int a = 0; a < 3; a++) K[2 + a] = dpi[a] + kof[2 + a];
-    // classic RK4 (Table rk4): acc holds u_n + dt sum_l b_l K_l, v_{s+1} = u_n + a dt K_s
+  };
+  prefetch(0);
+  for (int it = 0; it < nz + 6; it++) {
+    const int zn = z0 - 3 + it;
+    const int buf = it & 1;
+#pragma unroll
     for (int f = 0; f < 5; f++) {
-      const long long x = f * fs + x0;
-      const double kf = (double)K[f];
-      if (STAGE == 0) {
-        const double un = U[x];
-        A[x] = un + (dt / 6.0) * kf;
-        vout[x] = (TOUT)(un + (dt / 2.0) * kf);
-      } else if (STAGE == 1) {
-        A[x] = A[x] + (dt / 3.0) * kf;
-        vout[x] = (TOUT)(U[x] + (dt / 2.0) * kf);
-      } else if (STAGE == 2) {
-        A[x] = A[x] + (dt / 3.0) * kf;
-        vout[x] = (TOUT)(U[x] + dt * kf);
-      } else {
-        U[x] = A[x] + (dt / 6.0) * kf;
+#pragma unroll
+      for (int d = 0; d < 6; d++) q[f][d] = q[f][d + 1];
+      q[f][6] = pown[f];
+    }
+    const bool do_d = it >= 2;  // phi plane zd = zn - 1 for D_x phi, D_y phi
+    const bool do_c = it >= 6;  // centre plane zc = zn - 3
+    TC *A_ = Ad[buf];
+    if (do_d) {
+      if (inpad) A_[own] = q[0][5];
+#pragma unroll
+      for (int m = 0; m < 3; m++)
+        if (hval[m]) A_[hslot[m]] = phA[m];
+    }
+    double cu[5], ca[5];
+    if (do_c) {
+      if (inpad) {
+#pragma unroll
+        for (int f = 0; f < 5; f++) Bc[buf][f][own] = q[f][3];
+      }
+#pragma unroll
+      for (int m = 0; m < 3; m++)
+        if (hval[m]) {
+#pragma unroll
+          for (int f = 0; f < 5; f++) Bc[buf][f][hslot[m]] = phB[m][f];
+        }
+#pragma unroll
+      for (int f = 0; f < 5; f++) { cu[f] = pu[f]; ca[f] = pa[f]; }
+    }
+    __syncthreads();
+    if (it + 1 < nz + 6) prefetch(it + 1);
+    if (do_d && icol) {
+#pragma unroll
+      for (int d = 0; d < 4; d++) { dqx[d] = dqx[d + 1]; dqy[d] = dqy[d + 1]; }
+      dqx[4] = ((A_[own - 2] - A_[own + 2]) + (TC)8 * (A_[own + 1] - A_[own - 1])) * i12dx[0];
+      dqy[4] = ((A_[own - 2 * ST_PX] - A_[own + 2 * ST_PX]) + (TC)8 * (A_[own + ST_PX] - A_[own - ST_PX])) * i12dx[1];
+    }
+    if (do_c && icol) {
+      const int k = zn - 3;
+      bool live = true;
+      if (p.is_global && gflag) live = gflag[((long long)k * p.n[1] + j) * p.n[0] + i] == LIVE;
+      if (live) {
+        TC m_[3], b2_[3], h_[3], bb_[3];
+        if (COORD == CART) {
+#pragma unroll
+          for (int a = 0; a < 3; a++) {
+            m_[a] = (TC)ps.a[a];
+            b2_[a] = (TC)(2.0 * ps.b[a]);
+            h_[a] = (TC)(v2 - ps.b[a] * ps.b[a]);
+          }
+          bb_[0] = (TC)(2.0 * ps.b[0] * ps.b[1]);
+          bb_[1] = (TC)(2.0 * ps.b[0] * ps.b[2]);
+          bb_[2] = (TC)(2.0 * ps.b[1] * ps.b[2]);
+        } else {
+          double r = p.lo[0] + (i + 0.5) * p.dx[0];
+          double th = p.lo[1] + (j + 0.5) * p.dx[1];
+          double ph = p.lo[2] + (k + 0.5) * p.dx[2];
+          SphBasis Bs;
+          sph_basis(th, ph, Bs);
+          double ir = 1.0 / r, irs = ir / Bs.st, cot = Bs.ct / Bs.st;
+          double br = Bs.er[0] * ps.b[0] + Bs.er[1] * ps.b[1] + Bs.er[2] * ps.b[2];
+          double bt = Bs.et[0] * ps.b[0] + Bs.et[1] * ps.b[1] + Bs.et[2] * ps.b[2];
+          double bp = Bs.ep[0] * ps.b[0] + Bs.ep[1] * ps.b[1];
+          double ar = Bs.er[0] * ps.a[0] + Bs.er[1] * ps.a[1] + Bs.er[2] * ps.a[2];
+          double at = Bs.et[0] * ps.a[0] + Bs.et[1] * ps.a[1] + Bs.et[2] * ps.a[2];
+          double ap = Bs.ep[0] * ps.a[0] + Bs.ep[1] * ps.a[1];
+          double beta[3] = {br, bt * ir, bp * irs};
+          double Q0 = (bt * bt + bp * bp) * ir;
+          double Q1 = (-2.0 * br * bt + bp * bp * cot) * ir * ir;
+          double Q2 = -2.0 * bp * (br + bt * cot) * ir * irs;
+          double mm[3] = {ar - Q0 + v2 * 2.0 * ir, at * ir - Q1 + v2 * cot * ir * ir, ap * irs - Q2};
+          double hh[3] = {1.0, ir * ir, irs * irs};
+#pragma unroll
+          for (int a = 0; a < 3; a++) {
+            m_[a] = (TC)mm[a];
+            b2_[a] = (TC)(2.0 * beta[a]);
+            h_[a] = (TC)(v2 * hh[a] - beta[a] * beta[a]);
+          }
+          bb_[0] = (TC)(2.0 * beta[0] * beta[1]);
+          bb_[1] = (TC)(2.0 * beta[0] * beta[2]);
+          bb_[2] = (TC)(2.0 * beta[1] * beta[2]);
+        }
+        const TC(*Bf)[ST_PW] = Bc[buf];
+        TC dphi[3], d2phi[3], dpi[3], kof[5];
+        {
+          const TC *F = Bf[0];
+          TC u0 = F[own];
+          TC xm1 = F[own - 1], xp1 = F[own + 1], xm2 = F[own - 2], xp2 = F[own + 2];
+          TC ym1 = F[own - ST_PX], yp1 = F[own + ST_PX], ym2 = F[own - 2 * ST_PX], yp2 = F[own + 2 * ST_PX];
+          TC zm1 = q[0][2], zp1 = q[0][4], zm2 = q[0][1], zp2 = q[0][5];
+          dphi[0] = ((xm2 - xp2) + (TC)8 * (xp1 - xm1)) * i12dx[0];
+          dphi[1] = ((ym2 - yp2) + (TC)8 * (yp1 - ym1)) * i12dx[1];
+          dphi[2] = ((zm2 - zp2) + (TC)8 * (zp1 - zm1)) * i12dx[2];
+          d2phi[0] = ((TC)16 * (xm1 + xp1) - (xm2 + xp2) - (TC)30 * u0) * i12dx2[0];
+          d2phi[1] = ((TC)16 * (ym1 + yp1) - (ym2 + yp2) - (TC)30 * u0) * i12dx2[1];
+          d2phi[2] = ((TC)16 * (zm1 + zp1) - (zm2 + zp2) - (TC)30 * u0) * i12dx2[2];
+        }
+        {
+          const TC *F = Bf[1];
+          dpi[0] = ((F[own - 2] - F[own + 2]) + (TC)8 * (F[own + 1] - F[own - 1])) * i12dx[0];
+          dpi[1] = ((F[own - 2 * ST_PX] - F[own + 2 * ST_PX]) + (TC)8 * (F[own + ST_PX] - F[own - ST_PX])) * i12dx[1];
+          dpi[2] = ((q[1][1] - q[1][5]) + (TC)8 * (q[1][4] - q[1][2])) * i12dx[2];
+        }
+#pragma unroll
+        for (int f = 0; f < 5; f++) {
+          const TC *F = Bf[f];
+          const TC u0 = q[f][3];
+          TC kx = (F[own - 3] + F[own + 3]) - (TC)6 * (F[own - 2] + F[own + 2]) + (TC)15 * (F[own - 1] + F[own + 1]) -
+                  (TC)20 * u0;
+          TC kyv = (F[own - 3 * ST_PX] + F[own + 3 * ST_PX]) - (TC)6 * (F[own - 2 * ST_PX] + F[own + 2 * ST_PX]) +
+                   (TC)15 * (F[own - ST_PX] + F[own + ST_PX]) - (TC)20 * u0;
+          TC kz = (q[f][0] + q[f][6]) - (TC)6 * (q[f][1] + q[f][5]) + (TC)15 * (q[f][2] + q[f][4]) - (TC)20 * u0;
+          kof[f] = kx * ko[0] + kyv * ko[1] + kz * ko[2];
+        }
+        TC rhs_pi = (TC)0;
+#pragma unroll
+        for (int a = 0; a < 3; a++) rhs_pi += m_[a] * dphi[a] + b2_[a] * dpi[a] + h_[a] * d2phi[a];
+        if (moving) {
+          const TC *F = Bf[0];
+          TC sxy = (TC)0;
+#pragma unroll
+          for (int o2 = 0; o2 < 5; o2++) {
+            if (o2 == 2) continue;
+            TC inner = (TC)0;
+#pragma unroll
+            for (int o1 = 0; o1 < 5; o1++) {
+              if (o1 == 2) continue;
+              inner += w1[o1] * F[own + (o1 - 2) + (o2 - 2) * ST_PX];
+            }
+            sxy += w1[o2] * inner;
+          }
+          TC dxy = sxy * i12dx[0] * i12dx[1];
+          TC sxz = (TC)0, syz = (TC)0;
+#pragma unroll
+          for (int o = 0; o < 5; o++) {
+            sxz += w1[o] * dqx[o];
+            syz += w1[o] * dqy[o];
+          }
+          TC dxz = sxz * i12dx[2], dyz = syz * i12dx[2];
+          rhs_pi -= bb_[0] * dxy + bb_[1] * dxz + bb_[2] * dyz;
+        }
+        TC K[5];
+        K[0] = q[1][3] + kof[0];
+        K[1] = rhs_pi + kof[1];
+#pragma unroll
+        for (int a = 0; a < 3; a++) K[2 + a] = dpi[a] + kof[2 + a];
+        const uint32_t x0 = col + (uint32_t)k * sz;
+        // classic RK4 (Table rk4): acc holds u_n + dt sum_l b_l K_l, v_{s+1} = u_n + a dt K_s
+#pragma unroll
+        for (int f = 0; f < 5; f++) {
+          const uint32_t x = f * fs + x0;
+          const double kf = (double)K[f];
+          if (STAGE == 0) {
+            gst(Acc, x, cu[f] + bdt * kf);
+            gst(vout, x, (TOUT)(cu[f] + adt * kf));
+          } else if (STAGE == 3) {
+            gst(U, x, ca[f] + bdt * kf);
+          } else {
+            gst(Acc, x, ca[f] + bdt * kf);
+            gst(vout, x, (TOUT)(cu[f] + adt * kf));
+          }
+        }
       }
     }
   }
@@ -838,10 +1054,10 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
   }
   if (a.has_locals) {
     if (a.Pts == 5)
-      hipLaunchKernelGGL((k_l2g_wave<TB, TC, 5>), dim3(L2G_BLOCKS), dim3(256), 0, s, a.P, a.pose, a.efflist,
+      hipLaunchKernelGGL((k_l2g_coop<TB, TC, 5>), dim3(L2G_BLOCKS), dim3(256), 0, s, a.P, a.pose, a.efflist,
                          a.effcount, a.cover, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
     else
-      hipLaunchKernelGGL((k_l2g_wave<TB, TC, 6>), dim3(L2G_BLOCKS), dim3(256), 0, s, a.P, a.pose, a.efflist,
+      hipLaunchKernelGGL((k_l2g_coop<TB, TC, 6>), dim3(L2G_BLOCKS), dim3(256), 0, s, a.P, a.pose, a.efflist,
                          a.effcount, a.cover, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
   }
 }
@@ -859,7 +1075,8 @@ void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
   long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
   unsigned nb = nblk(tot, 256);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.effcount, 0);
-  hipLaunchKernelGGL(k_efflist, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.flag, tot, a.efflist, a.effcount);
+  hipLaunchKernelGGL(k_efflist, dim3(nblk(tot, 256 * EFF_PER_THREAD)), dim3(256), 0, s, (const uint8_t *)a.flag, tot,
+                     a.efflist, a.effcount);
   for (int m = 0; m < 2; m++) {
     if (!a.dvalid[m]) continue;
     int P = a.Pvals[m];
@@ -873,11 +1090,19 @@ void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
 }
 
 void launch_stage(hipStream_t s, const StageArgs &a) {
-  dim3 bs(TILE_X, TILE_Y);
-  dim3 g(a.ntiles);
   if (a.ntiles <= 0) return;
-#define PW_STAGE(TIN, TOUT, TC, ST) \
-  hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST>), g, bs, 0, s, a.P, a.pose, a.tiles, a.gflag, a.sv, a.dt, a.v2, a.eps)
+  const int chunk = (a.ntiles + 7) / 8;
+  dim3 bs(256);
+  dim3 g(8 * chunk);
+#define PW_STAGE(TIN, TOUT, TC, ST)                                                                         \
+  do {                                                                                                       \
+    if (a.coord == CART)                                                                                     \
+      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART>), g, bs, 0, s, a.P, a.pose, a.tiles, a.ntiles, chunk, \
+                         a.gflag, a.sv, a.dt, a.v2, a.eps);                                                  \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH>), g, bs, 0, s, a.P, a.pose, a.tiles, a.ntiles, chunk,  \
+                         a.gflag, a.sv, a.dt, a.v2, a.eps);                                                  \
+  } while (0)
   if (!a.mixed) {
     switch (a.stage) {
       case 0: PW_STAGE(double, double, double, 0); break;
