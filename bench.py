@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=3)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one device copy of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
@@ -212,6 +214,14 @@ def main():
                           "mixed_vs_fp64_max_rel_err": [float("%.3e" % x) for x in errs],
                           "mixed_vs_fp64_l2_rel_err": [float("%.3e" % x) for x in np.sqrt(l2 / np.maximum(nrm, 1e-300))]}
         ref.close()
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            dst.copy_(src)
+        stream.synchronize()
+        out["copy_probe_bytes"] = int(src.numel() * 4)
+        del src, dst
     c = ctx.counters()
     out["counters"] = c
     ctx.close()

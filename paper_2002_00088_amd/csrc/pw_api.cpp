@@ -43,16 +43,22 @@ struct pw_context {
   int32_t *cover_cur = nullptr, *cover_new = nullptr;
   // lists
   GhostRec *dLower = nullptr;
-  int nLower = 0;
+  int nLower = 0, nLowerGlobal = 0;
+  hipStream_t stream2 = nullptr;  // second branch of the overlapped step
+  hipEvent_t evFork = nullptr, evG[4] = {nullptr, nullptr, nullptr, nullptr},
+             evL[4] = {nullptr, nullptr, nullptr, nullptr};
   GBrick *dBricks = nullptr;
   int nBricks = 0;
   int32_t *efflist = nullptr;
   int *effcount = nullptr;
+  FallbackRec *fbList[2] = {nullptr, nullptr};  // skipped points of the local / global part
+  int *fbCount[2] = {nullptr, nullptr};
+  long long fbCap = 0;
   uint8_t *dvalid[2] = {nullptr, nullptr};  // donor-valid bytes for P = 5, 6
   TileRec *dTiles = nullptr;
   int nTiles = 0;
   std::vector<int> tileOff, tileCnt;
-  int nCartTiles = 0;
+  int nCartTiles = 0, nGlobalTiles = 0;
   CoverJob *dJobs = nullptr;
   int nJobs = 0, coverBlocks = 1;
   double *dStage = nullptr;  // staging for host copies
@@ -221,7 +227,10 @@ pw_status upload_layout(pw_context *c) {
           if (inside) continue;
           if (wrapped_inside || p.is_global) lower.push_back(GhostRec{pid, pack_ijk(i, j, k)});
         }
-    if (p.is_global) continue;
+    if (p.is_global) {
+      c->nLowerGlobal = (int)lower.size();
+      continue;
+    }
     auto target = [&](int i, int j, int k) {
       int cc[3] = {i, j, k};
       bool inside = true, wrapped_inside = true;
@@ -264,6 +273,23 @@ pw_status upload_layout(pw_context *c) {
     HIPCHK(c, hipMemcpy(c->dLower, lower.data(), sizeof(GhostRec) * lower.size(), hipMemcpyHostToDevice));
   if (!bricks.empty())
     HIPCHK(c, hipMemcpy(c->dBricks, bricks.data(), sizeof(GBrick) * bricks.size(), hipMemcpyHostToDevice));
+  // fallback lists: every local ghost cell (local part) or every global cell (global part)
+  long long nloc = 0;
+  for (int pid = 1; pid < np; pid++) {
+    const PatchDev &p = c->hp[pid];
+    nloc += (long long)(p.n[0] + 2 * PW_NG) * (p.n[1] + 2 * PW_NG) * (p.n[2] + 2 * PW_NG);
+  }
+  long long cap = std::max(nloc, c->gcells);
+  if (cap > c->fbCap) {
+    for (int m = 0; m < 2; m++) {
+      dfree(c, c->fbList[m]);
+      dfree(c, c->fbCount[m]);
+      c->fbList[m] = (FallbackRec *)dalloc(c, sizeof(FallbackRec) * cap);
+      c->fbCount[m] = (int *)dalloc(c, sizeof(int));
+      if (!c->fbList[m] || !c->fbCount[m]) return fail(c, PW_ENOMEM, "device allocation failed");
+    }
+    c->fbCap = cap;
+  }
 
   // Tiles of every patch, grouped by patch, Cartesian patches first.
   std::vector<TileRec> tiles;
@@ -284,6 +310,7 @@ pw_status upload_layout(pw_context *c) {
     c->tileCnt[pid] = (int)tiles.size() - c->tileOff[pid];
     if (p.coord == CART) c->nCartTiles = (int)tiles.size();
   }
+  c->nGlobalTiles = c->tileCnt[0];  // the global patch is Cartesian and comes first
   dfree(c, c->dTiles);
   c->nTiles = (int)tiles.size();
   c->dTiles = (TileRec *)dalloc(c, sizeof(TileRec) * tiles.size());
@@ -383,13 +410,17 @@ void enqueue_finalize(pw_context *c, const PoseDev *pose_slot, int mode) {
 }
 
 // Ghost fill of the buffers of `stage` (0: u) at time tdev[0] + tmul*dt.
-void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const double *tdev, double tmul, double dt) {
+void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const double *tdev, double tmul, double dt,
+                    int parts = GH_GLOBAL | GH_LOCAL, hipStream_t st = nullptr) {
+  if (!st) st = c->stream;
   for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
     GhostArgs a;
     a.P = c->dP;
     a.pose = pose_slot;
+    a.parts = parts;
     a.lower = c->dLower;
     a.n_lower = c->nLower;
+    a.n_lower_global = c->nLowerGlobal;
     a.bricks = c->dBricks;
     a.n_bricks = has_locals(c) ? c->nBricks : 0;
     a.dvalid = c->dvalid[c->cfg.interp_points[sv] == 5 ? 0 : 1];
@@ -409,7 +440,10 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.tmul = tmul;
     a.dt = dt;
     a.skips = c->dCounters;
-    launch_ghosts(c->stream, a);
+    const int which = (parts & GH_LOCAL) ? 0 : 1;  // separate lists for concurrently running parts
+    a.fb = c->fbList[which];
+    a.fb_count = c->fbCount[which];
+    launch_ghosts(st, a);
   }
 }
 
@@ -450,8 +484,86 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
   }
 }
 
+// Stage kernels of the global patch (which = 1) or of the local patches (which = 2).
+void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, double dt, int which, hipStream_t st) {
+  for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
+    StageArgs a;
+    a.P = c->dP;
+    a.pose = pose_slot;
+    a.gflag = has_locals(c) ? c->flag_cur : nullptr;
+    a.sv = sv;
+    a.stage = stage;
+    a.mixed = mixed(c);
+    a.dt = dt;
+    a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
+    a.eps = c->cfg.ko_eps;
+    if (which == 1) {
+      if (!(c->hp[0].sv_mask & (1u << sv))) continue;
+      a.tiles = c->dTiles;
+      a.ntiles = c->nGlobalTiles;
+      a.coord = CART;
+      launch_stage(st, a);
+      continue;
+    }
+    bool all = true;
+    for (size_t pid = 1; pid < c->hp.size(); pid++) all = all && (c->hp[pid].sv_mask & (1u << sv));
+    if (all) {
+      a.tiles = c->dTiles + c->nGlobalTiles;
+      a.ntiles = c->nCartTiles - c->nGlobalTiles;
+      a.coord = CART;
+      launch_stage(st, a);
+      a.tiles = c->dTiles + c->nCartTiles;
+      a.ntiles = c->nTiles - c->nCartTiles;
+      a.coord = SPH;
+      launch_stage(st, a);
+    } else {
+      for (size_t pid = 1; pid < c->hp.size(); pid++) {
+        if (!(c->hp[pid].sv_mask & (1u << sv))) continue;
+        a.tiles = c->dTiles + c->tileOff[pid];
+        a.ntiles = c->tileCnt[pid];
+        a.coord = c->hp[pid].coord;
+        launch_stage(st, a);
+      }
+    }
+  }
+}
+
+// One step as two interleaved chains on two streams: the local chain
+// (global->local fill, local stage kernels) and the global chain (local->global
+// fill, outer ghosts, global stage kernel).  Stage s of one chain waits for
+// stage s-1 of the other, whose output it interpolates from.
+void enqueue_step_overlap(pw_context *c, double dt) {
+  int np = (int)c->hp.size();
+  hipStream_t X = c->stream, Y = c->stream2;
+  launch_pose(X, c->dP, np, c->dT, dt, c->dPose);
+  (void)hipEventRecord(c->evFork, X);
+  (void)hipStreamWaitEvent(Y, c->evFork, 0);
+  static const int slot_of_stage[4] = {0, 1, 1, 2};
+  static const double tmul[4] = {0.0, 0.5, 0.5, 1.0};
+  for (int s = 0; s < 4; s++) {
+    const PoseDev *ps = c->dPose + slot_of_stage[s] * np;
+    if (s > 0) (void)hipStreamWaitEvent(X, c->evG[s - 1], 0);
+    enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X);
+    enqueue_stage_part(c, s, ps, dt, 2, X);
+    (void)hipEventRecord(c->evL[s], X);
+    if (s > 0) (void)hipStreamWaitEvent(Y, c->evL[s - 1], 0);
+    enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, Y);
+    enqueue_stage_part(c, s, ps, dt, 1, Y);
+    (void)hipEventRecord(c->evG[s], Y);
+  }
+  (void)hipStreamWaitEvent(X, c->evG[3], 0);
+  launch_advance_time(X, c->dT, dt, (long long *)c->dCounters);
+  enqueue_flags(c, c->dPose + 2 * np);
+  enqueue_finalize(c, c->dPose + 2 * np, 1);
+  enqueue_post_flags(c);
+}
+
 void enqueue_step(pw_context *c, double dt) {
   int np = (int)c->hp.size();
+  if (has_locals(c) && c->cfg.schedule == PW_SCHED_BATCHED && !c->timing && c->stream2) {
+    enqueue_step_overlap(c, dt);
+    return;
+  }
   {
     Timed tm(c, PW_K_POSE);
     launch_pose(c->stream, c->dP, np, c->dT, dt, c->dPose);
@@ -545,6 +657,17 @@ pw_status pw_create(const pw_config *cfg, pw_context **out) {
     }
     c->own_stream = true;
   }
+  if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->evFork, hipEventDisableTiming) != hipSuccess) {
+    pw_destroy(c);
+    return PW_EDEVICE;
+  }
+  for (int s = 0; s < 4; s++)
+    if (hipEventCreateWithFlags(&c->evG[s], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evL[s], hipEventDisableTiming) != hipSuccess) {
+      pw_destroy(c);
+      return PW_EDEVICE;
+    }
   for (int s = 0; s < PW_MAXSV; s++) memset(&c->hex[s], 0, sizeof(ExactDev));
   c->dEx = (ExactDev *)dalloc(c, sizeof(ExactDev) * PW_MAXSV);
   c->dVs = (double *)dalloc(c, sizeof(double) * PW_MAXSV);
@@ -969,6 +1092,15 @@ void pw_destroy(pw_context *c) {
   for (auto e : c->ev_free) (void)hipEventDestroy(e);
   std::vector<void *> all = c->allocs;
   for (void *p : all) dfree(c, p);
+  if (c->stream2) {
+    (void)hipStreamSynchronize(c->stream2);
+    (void)hipStreamDestroy(c->stream2);
+  }
+  if (c->evFork) (void)hipEventDestroy(c->evFork);
+  for (int s = 0; s < 4; s++) {
+    if (c->evG[s]) (void)hipEventDestroy(c->evG[s]);
+    if (c->evL[s]) (void)hipEventDestroy(c->evL[s]);
+  }
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

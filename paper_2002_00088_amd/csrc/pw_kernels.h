@@ -8,7 +8,8 @@
 // stage-kernel tile: ST_TX x ST_TY columns, up to ST_TZ planes per workgroup
 #define ST_TX 32
 #define ST_TY 8
-#define ST_TZ 32
+#define ST_TZ 64
+#define ST_MINB 1
 #define ST_PX (ST_TX + 6)
 #define ST_PY (ST_TY + 6)
 #define ST_PW (ST_PX * ST_PY)
@@ -41,6 +42,13 @@ struct CoverJob {
 // in interior-relative cell indices, at most BRICK_THREADS cells.
 struct GBrick {
   int32_t patch, i0, j0, k0, di, dj, dk, pad;
+};
+
+// A ghost point that could not be interpolated: kind 0 = local ghost cell
+// (packed padded coordinates), kind 1 = global effective ghost (linear index).
+struct FallbackRec {
+  int32_t patch, kind;
+  uint32_t cell;
 };
 
 struct PostFlagsArgs {
@@ -81,11 +89,16 @@ struct FinalizeArgs {
   int n[3];
 };
 
+// Parts of a ghost fill: the global patch's (outer ghosts, effective ghosts)
+// and the local patches' (periodic copies, interpatch bricks).
+enum { GH_GLOBAL = 1, GH_LOCAL = 2 };
+
 struct GhostArgs {
   const PatchDev *P;
   const PoseDev *pose;
-  const GhostRec *lower;
-  int n_lower;
+  int parts;
+  const GhostRec *lower;  // global-patch entries first, then local-patch entries
+  int n_lower, n_lower_global;
   const GBrick *bricks;
   int n_bricks;
   const uint8_t *dvalid;
@@ -100,6 +113,8 @@ struct GhostArgs {
   const double *tdev;  // stage time = tdev[0] + tmul * dt
   double tmul, dt;
   unsigned long long *skips;
+  FallbackRec *fb;  // capacity: every interpatch target of this part
+  int *fb_count;
 };
 
 struct StageArgs {

@@ -259,19 +259,39 @@ __global__ void k_set_int(int *p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
 }
 
-// Compacted list of the effective ghost cells (one atomic per workgroup of
-// 256 x EFF_PER_THREAD cells; the order of the list does not affect any result).
+// Compacted list of the effective ghost cells.  Cells are visited in 4x4x4
+// brick order, so consecutive list entries are 3-D neighbours whose donor
+// stencils overlap (cache reuse in the local->global gather).  One atomic per
+// workgroup of 256 x EFF_PER_THREAD cells; the order of the list does not affect
+// any result.
 #define EFF_PER_THREAD 16
-__global__ __launch_bounds__(256) void k_efflist(const uint8_t *flag, long long total, int32_t *list, int *count) {
+__global__ __launch_bounds__(256) void k_efflist(const uint8_t *flag, int n0, int n1, int n2, int32_t *list,
+                                                 int *count) {
   __shared__ int wsum[4], wbase[4], bbase;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nbx = (n0 + 3) >> 2, nby = (n1 + 3) >> 2, nbz = (n2 + 3) >> 2;
+  const long long total = (long long)nbx * nby * nbz * 64;
   const long long start = (long long)blockIdx.x * 256 * EFF_PER_THREAD;
   unsigned long long masks[EFF_PER_THREAD];
+  int32_t cells[EFF_PER_THREAD];
   int mine = 0;
 #pragma unroll
   for (int r = 0; r < EFF_PER_THREAD; r++) {
-    const long long c = start + (long long)r * 256 + threadIdx.x;
-    const bool e = c < total && flag[c] == EFFGHOST;
+    const long long L = start + (long long)r * 256 + threadIdx.x;
+    bool e = false;
+    int32_t c = 0;
+    if (L < total) {
+      const long long b = L >> 6;
+      const int q = (int)(L & 63);
+      const int i = (int)(b % nbx) * 4 + (q & 3);
+      const int j = (int)((b / nbx) % nby) * 4 + ((q >> 2) & 3);
+      const int k = (int)(b / ((long long)nbx * nby)) * 4 + (q >> 4);
+      if (i < n0 && j < n1 && k < n2) {
+        c = (int32_t)(((long long)k * n1 + j) * n0 + i);
+        e = flag[c] == EFFGHOST;
+      }
+    }
+    cells[r] = c;
     masks[r] = __ballot(e);
     mine += (int)__popcll(masks[r]);
   }
@@ -288,8 +308,7 @@ __global__ __launch_bounds__(256) void k_efflist(const uint8_t *flag, long long 
   const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
   for (int r = 0; r < EFF_PER_THREAD; r++) {
-    const long long c = start + (long long)r * 256 + threadIdx.x;
-    if ((masks[r] >> lane) & 1ull) list[off + __popcll(masks[r] & below)] = (int32_t)c;
+    if ((masks[r] >> lane) & 1ull) list[off + __popcll(masks[r] & below)] = cells[r];
     off += (int)__popcll(masks[r]);
   }
 }
@@ -306,15 +325,13 @@ __global__ __launch_bounds__(256) void k_efflist(const uint8_t *flag, long long 
 template <typename TB, typename TC, int Pts>
 __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *P, const PoseDev *pose,
                                                              const GBrick *bricks, int sv, int stage,
-                                                             const uint8_t *dvalid, const ExactDev *ex,
-                                                             double v, const double *tdev, double tmul, double dt,
-                                                             unsigned long long *skips) {
+                                                             const uint8_t *dvalid, unsigned long long *skips,
+                                                             FallbackRec *fb, int *fb_count) {
   __shared__ TC box[BRICK_LDS];
   __shared__ int blo[3], bhi[3];
   const GBrick B = bricks[blockIdx.x];
   const PatchDev &r = P[B.patch];
   const PatchDev &G0 = P[0];
-  const double t = tdev[0] + tmul * dt;
   const int tid = threadIdx.x;
   if (tid < 3) {
     blo[tid] = 1 << 30;
@@ -420,29 +437,20 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *P, 
       }
   }
   if (!active) return;
+  if (!valid) {
+    // rare: handled by k_fallback (lower-priority value, counted if a donor exists)
+    if (has_donor) atomicAdd(skips, 1ull);
+    const int slot = atomicAdd(fb_count, 1);
+    fb[slot] = FallbackRec{B.patch, 0, (uint32_t)((c[0] + PW_NG) | ((c[1] + PW_NG) << 10) | ((c[2] + PW_NG) << 20))};
+    return;
+  }
   double out[5];
-  if (valid) {
+  {
     double in4[4] = {(double)acc[1], (double)acc[2], (double)acc[3], (double)acc[4]}, G[3], pit, o4[4];
     patch_to_bg(G0, pose[0], xd, in4, pit, G);
     bg_to_patch(r, pose[B.patch], xr, pit, G, o4);
     out[0] = (double)acc[0];
     for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
-  } else {
-    if (has_donor) atomicAdd(skips, 1ull);
-    for (int a = 0; a < 3; a++) xr[a] = xnum(r, a, c[a]);
-    if (ex[sv].kind != EX_NONE) {
-      exact_patch(ex[sv], v, r, pose[B.patch], t, xr, out);
-    } else {
-      int w[3];
-      for (int a = 0; a < 3; a++) {
-        w[a] = c[a];
-        if (r.periodic[a]) w[a] = ((c[a] % r.n[a]) + r.n[a]) % r.n[a];
-        w[a] = w[a] < 0 ? 0 : (w[a] >= r.n[a] ? r.n[a] - 1 : w[a]);
-      }
-      const TB *TR = stage_buf<TB>(r, sv, stage);
-      long long src = cell_index(r, w[0], w[1], w[2]);
-      for (int f = 0; f < 5; f++) out[f] = (double)TR[f * r.fstride + src];
-    }
   }
   TB *TR = stage_buf<TB>(r, sv, stage);
   long long dst = cell_index(r, c[0], c[1], c[2]);
@@ -470,15 +478,13 @@ __device__ __forceinline__ double bcast_d(double v, int lane) {
 template <typename TB, typename TC, int Pts>
 __global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *P, const PoseDev *pose, const int32_t *list,
                                                   const int *count, const int32_t *cover, int sv, int stage,
-                                                  const ExactDev *ex, double v, const double *tdev, double tmul,
-                                                  double dt, unsigned long long *skips) {
+                                                  unsigned long long *skips, FallbackRec *fb, int *fb_count) {
   const PatchDev &G0 = P[0];
   if (!(G0.sv_mask & (1u << sv))) return;
   const int lane = threadIdx.x & 63;
   const long long wid = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const long long nw = ((long long)gridDim.x * blockDim.x) >> 6;
   const int n = count[0];
-  const double t = tdev[0] + tmul * dt;
   const int la = lane % Pts, lb = lane / Pts;
   const bool tap_lane = lane < Pts * Pts;
   TB *TG = stage_buf<TB>(G0, sv, stage);
@@ -513,8 +519,8 @@ __global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *P, const PoseD
     }
     TC res[5] = {0, 0, 0, 0, 0};
     const unsigned long long vmask = __ballot(valid);
-    for (int pnt = 0; pnt < 64; pnt++) {
-      if (!((vmask >> pnt) & 1ull)) continue;
+    // taps of one point by the whole wavefront; two points in flight per pass
+    auto taps = [&](int pnt, TC acc[5]) {
       const int dd = bcast_i(d, pnt);
       const int s0 = bcast_i(s[0], pnt), s1 = bcast_i(s[1], pnt), s2 = bcast_i(s[2], pnt);
       double wxa = 0.0, wyb = 0.0, wzc[Pts];
@@ -528,7 +534,8 @@ __global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *P, const PoseD
       const PatchDev &D = P[dd];
       const TB *T = stage_buf<TB>(D, sv, stage);
       const uint32_t fs = (uint32_t)D.fstride;
-      TC acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+      for (int f = 0; f < 5; f++) acc[f] = (TC)0;
       if (tap_lane) {
         const double wab = wxa * wyb;
         int ii = s0 + la, jj = s1 + lb;
@@ -544,32 +551,97 @@ __global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *P, const PoseD
           for (int f = 0; f < 5; f++) acc[f] += w * (TC)gld(T, f * fs + x);
         }
       }
+    };
+    unsigned long long todo = vmask;
+    while (todo) {
+      const int p0 = __ffsll((long long)todo) - 1;
+      todo &= todo - 1ull;
+      int p1 = -1;
+      if (todo) {
+        p1 = __ffsll((long long)todo) - 1;
+        todo &= todo - 1ull;
+      }
+      TC a0[5], a1[5];
+      taps(p0, a0);
+      if (p1 >= 0) taps(p1, a1);
+      else {
+#pragma unroll
+        for (int f = 0; f < 5; f++) a1[f] = (TC)0;
+      }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1)
 #pragma unroll
-        for (int f = 0; f < 5; f++) acc[f] += __shfl_xor(acc[f], off);
-      if (lane == pnt) {
+        for (int f = 0; f < 5; f++) {
+          a0[f] += __shfl_xor(a0[f], off);
+          a1[f] += __shfl_xor(a1[f], off);
+        }
+      if (lane == p0) {
 #pragma unroll
-        for (int f = 0; f < 5; f++) res[f] = acc[f];
+        for (int f = 0; f < 5; f++) res[f] = a0[f];
+      }
+      if (lane == p1) {
+#pragma unroll
+        for (int f = 0; f < 5; f++) res[f] = a1[f];
       }
     }
     if (have) {
-      double out[5];
       if (valid) {
         const PatchDev &D = P[d];
-        double in4[4] = {(double)res[1], (double)res[2], (double)res[3], (double)res[4]}, G[3], pit, o4[4];
+        double in4[4] = {(double)res[1], (double)res[2], (double)res[3], (double)res[4]}, G[3], pit, o4[4], out[5];
         patch_to_bg(D, pose[d], xd, in4, pit, G);
         bg_to_patch(G0, pose[0], X, pit, G, o4);
         out[0] = (double)res[0];
         for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
+        const long long dst = cell_index(G0, i, j, k);
+        for (int f = 0; f < 5; f++) TG[f * G0.fstride + dst] = (TB)out[f];
       } else {
         atomicAdd(skips, 1ull);
-        if (ex[sv].kind != EX_NONE) exact_patch(ex[sv], v, G0, pose[0], t, X, out);
-        else for (int f = 0; f < 5; f++) out[f] = NAN;
+        const int slot = atomicAdd(fb_count, 1);
+        fb[slot] = FallbackRec{0, 1, (uint32_t)c};
       }
-      const long long dst = cell_index(G0, i, j, k);
-      for (int f = 0; f < 5; f++) TG[f * G0.fstride + dst] = (TB)out[f];
     }
+  }
+}
+
+// Points that could not be interpolated keep their lower-priority value: a
+// local ghost gets the exact solution (if registered) or a copy of the nearest
+// interior cell; a global effective ghost gets the exact solution or NaN.
+template <typename TB>
+__global__ void k_fallback(const PatchDev *P, const PoseDev *pose, const FallbackRec *fb, const int *fb_count, int sv,
+                           int stage, const ExactDev *ex, double v, const double *tdev, double tmul, double dt) {
+  const int n = fb_count[0];
+  const double t = tdev[0] + tmul * dt;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const FallbackRec F = fb[q];
+    const PatchDev &r = P[F.patch];
+    int c[3];
+    if (F.kind == 0) {
+      c[0] = (int)(F.cell & 1023u) - PW_NG;
+      c[1] = (int)((F.cell >> 10) & 1023u) - PW_NG;
+      c[2] = (int)((F.cell >> 20) & 1023u) - PW_NG;
+    } else {
+      c[0] = (int)(F.cell % r.n[0]);
+      c[1] = (int)((F.cell / r.n[0]) % r.n[1]);
+      c[2] = (int)(F.cell / ((unsigned)r.n[0] * r.n[1]));
+    }
+    double xr[3] = {xnum(r, 0, c[0]), xnum(r, 1, c[1]), xnum(r, 2, c[2])}, out[5];
+    TB *TR = stage_buf<TB>(r, sv, stage);
+    if (ex[sv].kind != EX_NONE) {
+      exact_patch(ex[sv], v, r, pose[F.patch], t, xr, out);
+    } else if (F.kind == 0) {
+      int w[3];
+      for (int a = 0; a < 3; a++) {
+        w[a] = c[a];
+        if (r.periodic[a]) w[a] = ((c[a] % r.n[a]) + r.n[a]) % r.n[a];
+        w[a] = w[a] < 0 ? 0 : (w[a] >= r.n[a] ? r.n[a] - 1 : w[a]);
+      }
+      const long long src = cell_index(r, w[0], w[1], w[2]);
+      for (int f = 0; f < 5; f++) out[f] = (double)TR[f * r.fstride + src];
+    } else {
+      for (int f = 0; f < 5; f++) out[f] = NAN;
+    }
+    const long long dst = cell_index(r, c[0], c[1], c[2]);
+    for (int f = 0; f < 5; f++) TR[f * r.fstride + dst] = (TB)out[f];
   }
 }
 
@@ -636,7 +708,7 @@ __global__ void k_finalize(const PatchDev *P, const PoseDev *pose, uint8_t *flag
 // for the x-y stencils.
 // ---------------------------------------------------------------------------
 template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD>
-__global__ __launch_bounds__(256) void k_stage(const PatchDev *P, const PoseDev *pose_slot, const TileRec *tiles,
+__global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *P, const PoseDev *pose_slot, const TileRec *tiles,
                                                int ntiles, int chunk, const uint8_t *gflag, int sv, double dt,
                                                double v2, double eps) {
   __shared__ TC Bc[2][5][ST_PW];
@@ -661,20 +733,36 @@ __global__ __launch_bounds__(256) void k_stage(const PatchDev *P, const PoseDev 
   // 32-bit element offsets (a field of one patch holds < 2^31 elements)
   const uint32_t fs = (uint32_t)p.fstride, sz = (uint32_t)p.slab;
   const uint32_t col = (uint32_t)cell_index(p, i, j, 0);
-  uint32_t hoff[3];
-  bool hval[3];
-  int hslot[3];
+  // halo cells of the LDS planes: the ring of ST_PW - 256 cells around the
+  // tile, enumerated row by row; thread t takes ring cells t and t + 256
+  constexpr int NHALO = ST_PW - ST_TX * ST_TY;
+  uint32_t hoff[2];
+  bool hval[2];
+  int hslot[2];
 #pragma unroll
-  for (int m = 0; m < 3; m++) {
-    const int e = tid + 256 * m;
+  for (int m = 0; m < 2; m++) {
+    const int h = tid + 256 * m;
     hval[m] = false;
     hoff[m] = 0;
-    hslot[m] = e < ST_PW ? e : 0;
-    if (e < ST_PW) {
-      const int hx = e % ST_PX, hy = e / ST_PX;
-      const bool own = hx >= 3 && hx < 3 + ST_TX && hy >= 3 && hy < 3 + ST_TY;
+    hslot[m] = 0;
+    if (h < NHALO) {
+      int hx, hy;
+      if (h < 3 * ST_PX) {  // three rows below the tile
+        hx = h % ST_PX;
+        hy = h / ST_PX;
+      } else if (h < 3 * ST_PX + 6 * ST_TY) {  // 3 + 3 side cells of the tile rows
+        const int r = h - 3 * ST_PX;
+        hy = 3 + r / 6;
+        const int sx = r % 6;
+        hx = sx < 3 ? sx : ST_TX + sx;
+      } else {  // three rows above the tile
+        const int r = h - 3 * ST_PX - 6 * ST_TY;
+        hx = r % ST_PX;
+        hy = 3 + ST_TY + r / ST_PX;
+      }
+      hslot[m] = hy * ST_PX + hx;
       const int gi = tl.x0 - 3 + hx, gj = tl.y0 - 3 + hy;
-      if (!own && gi < p.n[0] + PW_NG && gj < p.n[1] + PW_NG) {
+      if (gi < p.n[0] + PW_NG && gj < p.n[1] + PW_NG) {
         hval[m] = true;
         hoff[m] = (uint32_t)cell_index(p, gi, gj, 0);
       }
@@ -700,8 +788,7 @@ __global__ __launch_bounds__(256) void k_stage(const PatchDev *P, const PoseDev 
 
   // software pipeline: the loads of iteration it+1 are in flight while
   // iteration it computes
-  TC pown[5], phA[3], phB[3][5];
-  double pu[5], pa[5];
+  TC pown[5], phA[2], phB[2][5];
   auto prefetch = [&](int itp) {
     const int zn = z0 - 3 + itp;
     const uint32_t zo = (uint32_t)(zn + PW_NG) * sz;  // cell_index already holds the +NG of z = 0
@@ -710,21 +797,14 @@ __global__ __launch_bounds__(256) void k_stage(const PatchDev *P, const PoseDev 
     if (itp >= 2) {
       const uint32_t za = zo - (PW_NG + 1) * sz;
 #pragma unroll
-      for (int m = 0; m < 3; m++) phA[m] = hval[m] ? (TC)gld(in, hoff[m] + za) : (TC)0;
+      for (int m = 0; m < 2; m++) phA[m] = hval[m] ? (TC)gld(in, hoff[m] + za) : (TC)0;
     }
     if (itp >= 6) {
       const uint32_t zb = zo - (PW_NG + 3) * sz;
 #pragma unroll
-      for (int m = 0; m < 3; m++)
+      for (int m = 0; m < 2; m++)
 #pragma unroll
         for (int f = 0; f < 5; f++) phB[m][f] = hval[m] ? (TC)gld(in, f * fs + hoff[m] + zb) : (TC)0;
-      if (icol) {
-#pragma unroll
-        for (int f = 0; f < 5; f++) {
-          if (STAGE != 3) pu[f] = gld(U, f * fs + col + zb);
-          if (STAGE != 0) pa[f] = gld(Acc, f * fs + col + zb);
-        }
-      }
     }
   };
   prefetch(0);
@@ -743,23 +823,30 @@ __global__ __launch_bounds__(256) void k_stage(const PatchDev *P, const PoseDev 
     if (do_d) {
       if (inpad) A_[own] = q[0][5];
 #pragma unroll
-      for (int m = 0; m < 3; m++)
+      for (int m = 0; m < 2; m++)
         if (hval[m]) A_[hslot[m]] = phA[m];
     }
+    // FP64 state of the centre cell for the RK update, issued before the barrier
     double cu[5], ca[5];
+    if (do_c && icol) {
+      const uint32_t xc = col + (uint32_t)(zn - 3) * sz;
+#pragma unroll
+      for (int f = 0; f < 5; f++) {
+        cu[f] = STAGE != 3 ? gld(U, f * fs + xc) : 0.0;
+        ca[f] = STAGE != 0 ? gld(Acc, f * fs + xc) : 0.0;
+      }
+    }
     if (do_c) {
       if (inpad) {
 #pragma unroll
         for (int f = 0; f < 5; f++) Bc[buf][f][own] = q[f][3];
       }
 #pragma unroll
-      for (int m = 0; m < 3; m++)
+      for (int m = 0; m < 2; m++)
         if (hval[m]) {
 #pragma unroll
           for (int f = 0; f < 5; f++) Bc[buf][f][hslot[m]] = phB[m][f];
         }
-#pragma unroll
-      for (int f = 0; f < 5; f++) { cu[f] = pu[f]; ca[f] = pa[f]; }
     }
     __syncthreads();
     if (it + 1 < nz + 6) prefetch(it + 1);
@@ -1041,25 +1128,33 @@ void launch_finalize(hipStream_t s, const FinalizeArgs &a) {
 template <typename TB, typename TC>
 static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
   const int bs = 256;
-  if (a.n_lower > 0)
-    hipLaunchKernelGGL(k_fill_lower<TB>, dim3(nblk(a.n_lower, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower, a.n_lower,
+  const int l0 = (a.parts & GH_GLOBAL) ? 0 : a.n_lower_global;
+  const int l1 = (a.parts & GH_LOCAL) ? a.n_lower : a.n_lower_global;
+  const bool g2l = a.n_bricks > 0 && (a.parts & GH_LOCAL);
+  const bool l2g = a.has_locals && (a.parts & GH_GLOBAL);
+  if (l1 > l0)
+    hipLaunchKernelGGL(k_fill_lower<TB>, dim3(nblk(l1 - l0, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower + l0, l1 - l0,
                        a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
-  if (a.n_bricks > 0) {
+  if (!g2l && !l2g) return;
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
+  if (g2l) {
     if (a.Pts == 5)
       hipLaunchKernelGGL((k_g2l_brick<TB, TC, 5>), dim3(a.n_bricks), dim3(BRICK_THREADS), 0, s, a.P, a.pose,
-                         a.bricks, a.sv, a.stage, a.dvalid, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips);
+                         a.bricks, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
     else
       hipLaunchKernelGGL((k_g2l_brick<TB, TC, 6>), dim3(a.n_bricks), dim3(BRICK_THREADS), 0, s, a.P, a.pose,
-                         a.bricks, a.sv, a.stage, a.dvalid, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips);
+                         a.bricks, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
   }
-  if (a.has_locals) {
+  if (l2g) {
     if (a.Pts == 5)
       hipLaunchKernelGGL((k_l2g_coop<TB, TC, 5>), dim3(L2G_BLOCKS), dim3(256), 0, s, a.P, a.pose, a.efflist,
-                         a.effcount, a.cover, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
+                         a.effcount, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count);
     else
       hipLaunchKernelGGL((k_l2g_coop<TB, TC, 6>), dim3(L2G_BLOCKS), dim3(256), 0, s, a.P, a.pose, a.efflist,
-                         a.effcount, a.cover, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt, a.skips + 1);
+                         a.effcount, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count);
   }
+  hipLaunchKernelGGL(k_fallback<TB>, dim3(64), dim3(256), 0, s, a.P, a.pose, a.fb, a.fb_count, a.sv, a.stage, a.ex,
+                     a.v, a.tdev, a.tmul, a.dt);
 }
 
 void launch_ghosts(hipStream_t s, const GhostArgs &a) {
@@ -1075,8 +1170,9 @@ void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
   long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
   unsigned nb = nblk(tot, 256);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.effcount, 0);
-  hipLaunchKernelGGL(k_efflist, dim3(nblk(tot, 256 * EFF_PER_THREAD)), dim3(256), 0, s, (const uint8_t *)a.flag, tot,
-                     a.efflist, a.effcount);
+  const long long tot_bricks = (long long)((a.n[0] + 3) / 4) * ((a.n[1] + 3) / 4) * ((a.n[2] + 3) / 4) * 64;
+  hipLaunchKernelGGL(k_efflist, dim3(nblk(tot_bricks, 256 * EFF_PER_THREAD)), dim3(256), 0, s,
+                     (const uint8_t *)a.flag, a.n[0], a.n[1], a.n[2], a.efflist, a.effcount);
   for (int m = 0; m < 2; m++) {
     if (!a.dvalid[m]) continue;
     int P = a.Pvals[m];
