@@ -49,8 +49,10 @@ struct pw_context {
              evL[4] = {nullptr, nullptr, nullptr, nullptr};
   GBrick *dBricks = nullptr;
   int nBricks = 0;
-  int32_t *efflist = nullptr;
+  int32_t *efflist = nullptr, *effsorted = nullptr;
   int *effcount = nullptr;
+  int nBuckets = 0;
+  int *bkCnt = nullptr, *bkOff = nullptr, *eBkt = nullptr, *eRank = nullptr;
   FallbackRec *fbList[2] = {nullptr, nullptr};  // skipped points of the local / global part
   int *fbCount[2] = {nullptr, nullptr};
   long long fbCap = 0;
@@ -273,6 +275,11 @@ pw_status upload_layout(pw_context *c) {
     HIPCHK(c, hipMemcpy(c->dLower, lower.data(), sizeof(GhostRec) * lower.size(), hipMemcpyHostToDevice));
   if (!bricks.empty())
     HIPCHK(c, hipMemcpy(c->dBricks, bricks.data(), sizeof(GBrick) * bricks.size(), hipMemcpyHostToDevice));
+  dfree(c, c->bkCnt);
+  dfree(c, c->bkOff);
+  c->bkCnt = (int *)dalloc(c, sizeof(int) * std::max(1, c->nBuckets));
+  c->bkOff = (int *)dalloc(c, sizeof(int) * std::max(1, c->nBuckets));
+  if (!c->bkCnt || !c->bkOff) return fail(c, PW_ENOMEM, "device allocation failed");
   // fallback lists: every local ghost cell (local part) or every global cell (global part)
   long long nloc = 0;
   for (int pid = 1; pid < np; pid++) {
@@ -375,7 +382,7 @@ void enqueue_flags(pw_context *c, const PoseDev *pose_slot) {
   launch_flags(c->stream, a);
 }
 
-void enqueue_post_flags(pw_context *c) {
+void enqueue_post_flags(pw_context *c, const PoseDev *pose_slot) {
   PostFlagsArgs a;
   a.flag = c->flag_cur;
   a.efflist = c->efflist;
@@ -388,6 +395,19 @@ void enqueue_post_flags(pw_context *c) {
   a.t2 = c->t2;
   for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
   launch_post_flags(c->stream, a);
+  L2GOrderArgs o;
+  o.P = c->dP;
+  o.pose = pose_slot;
+  o.list = c->efflist;
+  o.count = c->effcount;
+  o.cover = c->cover_cur;
+  o.nbuckets = c->nBuckets;
+  o.cnt = c->bkCnt;
+  o.off = c->bkOff;
+  o.ebkt = c->eBkt;
+  o.erank = c->eRank;
+  o.sorted = c->effsorted;
+  launch_l2g_order(c->stream, o);
 }
 
 void enqueue_finalize(pw_context *c, const PoseDev *pose_slot, int mode) {
@@ -424,7 +444,7 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.bricks = c->dBricks;
     a.n_bricks = has_locals(c) ? c->nBricks : 0;
     a.dvalid = c->dvalid[c->cfg.interp_points[sv] == 5 ? 0 : 1];
-    a.efflist = c->efflist;
+    a.efflist = c->effsorted;
     a.effcount = c->effcount;
     a.cover = c->cover_cur;
     a.has_locals = has_locals(c);
@@ -555,7 +575,7 @@ void enqueue_step_overlap(pw_context *c, double dt) {
   launch_advance_time(X, c->dT, dt, (long long *)c->dCounters);
   enqueue_flags(c, c->dPose + 2 * np);
   enqueue_finalize(c, c->dPose + 2 * np, 1);
-  enqueue_post_flags(c);
+  enqueue_post_flags(c, c->dPose + 2 * np);
 }
 
 void enqueue_step(pw_context *c, double dt) {
@@ -589,7 +609,7 @@ void enqueue_step(pw_context *c, double dt) {
     }
     Timed tm(c, PW_K_FINALIZE);
     enqueue_finalize(c, c->dPose + 2 * np, 1);
-    enqueue_post_flags(c);
+    enqueue_post_flags(c, c->dPose + 2 * np);
   }
 }
 
@@ -602,7 +622,7 @@ pw_status ensure_flags(pw_context *c) {
     launch_pose(c->stream, c->dP, np, c->dT, 0.0, c->dPose);
     enqueue_flags(c, c->dPose);
     enqueue_finalize(c, c->dPose, 0);
-    enqueue_post_flags(c);
+    enqueue_post_flags(c, c->dPose);
     int err = 0;
     HIPCHK(c, hipMemcpyAsync(&err, c->dErr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -759,6 +779,12 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
   p.phase = d->phase;
   euler_zyz(d->euler_zyz, p.R);
   p.sv_mask = d->sv_mask;
+  p.bkt_base = 0;
+  for (int a = 0; a < 3; a++) p.bkt_n[a] = first ? 0 : (p.n[a] + 7) / 8;
+  if (!first) {
+    const PatchDev &last = c->hp.back();
+    p.bkt_base = last.bkt_base + last.bkt_n[0] * last.bkt_n[1] * last.bkt_n[2];
+  }
   p.pitch = ((PW_OX + p.n[0] + PW_NG) + 7) / 8 * 8;
   p.rows = p.n[1] + 2 * PW_NG;
   p.slabs = p.n[2] + 2 * PW_NG;
@@ -792,7 +818,11 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     c->cover_cur = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
     c->cover_new = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
     c->efflist = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
+    c->effsorted = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
+    c->eBkt = (int *)dalloc(c, sizeof(int) * c->gcells);
+    c->eRank = (int *)dalloc(c, sizeof(int) * c->gcells);
     c->effcount = (int *)dalloc(c, sizeof(int));
+    if (!c->effsorted || !c->eBkt || !c->eRank) return fail(c, PW_ENOMEM, "device allocation failed");
     for (int m = 0; m < 2; m++) {
       bool used = false;
       for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) used = used || c->cfg.interp_points[sv] == 5 + m;
@@ -810,6 +840,7 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
   HIPCHK(c, hipGetLastError());
   c->hp.push_back(p);
   c->desc.push_back(*d);
+  c->nBuckets = p.bkt_base + p.bkt_n[0] * p.bkt_n[1] * p.bkt_n[2];
   c->layout_dirty = true;
   c->flags_valid = false;
   if (id_out) *id_out = (int32_t)c->hp.size() - 1;

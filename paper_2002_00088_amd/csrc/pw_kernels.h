@@ -61,6 +61,17 @@ struct PostFlagsArgs {
   int n[3];
 };
 
+struct L2GOrderArgs {
+  const PatchDev *P;
+  const PoseDev *pose;
+  const int32_t *list;
+  const int *count;
+  const int32_t *cover;
+  int nbuckets;
+  int *cnt, *off, *ebkt, *erank;
+  int32_t *sorted;
+};
+
 struct FlagsArgs {
   const PatchDev *P;
   const PoseDev *pose;
@@ -135,6 +146,7 @@ void launch_flags(hipStream_t s, const FlagsArgs &a);
 void launch_finalize(hipStream_t s, const FinalizeArgs &a);
 void launch_ghosts(hipStream_t s, const GhostArgs &a);
 void launch_post_flags(hipStream_t s, const PostFlagsArgs &a);
+void launch_l2g_order(hipStream_t s, const L2GOrderArgs &a);
 void launch_stage(hipStream_t s, const StageArgs &a);
 void launch_fill_f64(hipStream_t s, double *p, long long n, double v);
 void launch_fill_f32(hipStream_t s, float *p, long long n, float v);

@@ -50,7 +50,7 @@ __global__ void k_advance_time(double *tdev, double dt, long long *counters) {
 // centre of global cell c (Sec. 2.4.2: the covered test is done in the local
 // patch's numerical coordinates).  Each local patch scans the global cells of
 // the axis-aligned box around its bounding sphere.
-__global__ void k_cover(const PatchDev *P, const PoseDev *pose, const CoverJob *jobs, int njobs, int32_t *cover,
+__global__ void k_cover(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const CoverJob *jobs, int njobs, int32_t *cover,
                         int *err) {
   const CoverJob J = jobs[blockIdx.y];
   const PatchDev &g = P[0];
@@ -198,7 +198,7 @@ __device__ inline void unpack_ijk(uint32_t c, int &i, int &j, int &k) {
 // Lower-priority ghost data: periodic copy if the wrapped index is interior,
 // else the exact solution (analytic outer boundary) or the nearest interior cell.
 template <typename TB>
-__global__ void k_fill_lower(const PatchDev *P, const PoseDev *pose, const GhostRec *list, int count, int sv, int stage,
+__global__ void k_fill_lower(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const GhostRec *list, int count, int sv, int stage,
                              const ExactDev *ex, double v, const double *tdev, double tmul, double dt) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= count) return;
@@ -313,6 +313,67 @@ __global__ __launch_bounds__(256) void k_efflist(const uint8_t *flag, int n0, in
   }
 }
 
+// Ordering of the effective ghosts by donor position: a counting sort by
+// (covering local patch, 8^3-cell bucket of that patch holding the point), so
+// that the points a wavefront gathers share donor rows in the caches.
+__global__ void k_bucket_count(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list, const int *count,
+                               const int32_t *cover, int *cnt, int *ebkt, int *erank) {
+  const PatchDev &G0 = P[0];
+  const int n = count[0];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const long long c = list[q];
+    const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]), k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
+    const int d = cover[c];
+    int b = 0;
+    if (d >= 1) {
+      const PatchDev &D = P[d];
+      double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)}, xd[3];
+      inv_map(D, pose[d], X, xd);
+      int bi[3];
+      for (int a = 0; a < 3; a++) {
+        double qq = (xd[a] - D.lo[a]) * D.idx[a];
+        int ii = (qq > -1.0e6 && qq < 1.0e6) ? (int)floor(qq) : 0;
+        if (D.periodic[a]) ii = ((ii % D.n[a]) + D.n[a]) % D.n[a];
+        ii = ii < 0 ? 0 : (ii >= D.n[a] ? D.n[a] - 1 : ii);
+        bi[a] = ii >> 3;
+      }
+      b = D.bkt_base + (bi[2] * D.bkt_n[1] + bi[1]) * D.bkt_n[0] + bi[0];
+    }
+    ebkt[q] = b;
+    erank[q] = atomicAdd(&cnt[b], 1);
+  }
+}
+
+// Exclusive scan of nb bucket counts by one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_bucket_scan(const int *cnt, int *off, int nb) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = t * per, b1 = min(nb, b0 + per);
+  int s = 0;
+  for (int b = b0; b < b1; b++) s += cnt[b];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int b = b0; b < b1; b++) {
+    off[b] = run;
+    run += cnt[b];
+  }
+}
+
+__global__ void k_bucket_scatter(const int32_t *list, const int *count, const int *ebkt, const int *erank,
+                                 const int *off, int32_t *sorted) {
+  const int n = count[0];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
+    sorted[off[ebkt[q]] + erank[q]] = list[q];
+}
+
 // ---------------------------------------------------------------------------
 // Global -> local (Sec. 2.4.1).  One workgroup per brick of up to 8x8x3 ghost
 // cells of one face of a local patch.  Each thread locates its point in the
@@ -323,7 +384,7 @@ __global__ __launch_bounds__(256) void k_efflist(const uint8_t *flag, int n0, in
 // lower-priority value (analytic or nearest interior) and are counted.
 // ---------------------------------------------------------------------------
 template <typename TB, typename TC, int Pts>
-__global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *P, const PoseDev *pose,
+__global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose,
                                                              const GBrick *bricks, int sv, int stage,
                                                              const uint8_t *dvalid, unsigned long long *skips,
                                                              FallbackRec *fb, int *fb_count) {
@@ -392,33 +453,54 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *P, 
   for (int cc = 0; cc < Pts; cc++)
 #pragma unroll
     for (int b = 0; b < Pts; b++) wyzc[cc][b] = (TC)(wy[b] * wz[cc]);
-  if (vol > 0 && vol <= BRICK_LDS) {
+  const uint32_t gfs = (uint32_t)G0.fstride, gsy = (uint32_t)G0.pitch, gsz = (uint32_t)G0.slab;
+  if (vol > 0 && vol <= BRICK_LDS && e0 <= 32) {
     const int e01 = e0 * e1;
     const int nrows = e1 * e2;
     const int lane32 = tid & 31, row0 = tid >> 5;
+    constexpr int RSTEP = BRICK_THREADS / 32;
+    const uint32_t base0 = (uint32_t)(lo0 + PW_OX) + (uint32_t)(lo1 + PW_NG) * gsy + (uint32_t)(lo2 + PW_NG) * gsz;
     for (int f = 0; f < 5; f++) {
-      const TB *Tf = T + f * G0.fstride;
-      // rows of the donor box, 32 threads per row
-      for (int row = row0; row < nrows; row += BRICK_THREADS / 32) {
-        const int b = row % e1, cc = row / e1;
-        const TB *src = Tf + cell_index(G0, lo0, lo1 + b, lo2 + cc);
-        TC *dst = box + cc * e01 + b * e0;
-        for (int x = lane32; x < e0; x += 32) dst[x] = (TC)src[x];
+      // rows of the donor box, 32 threads per row, 8 rows in flight per thread
+      if (lane32 < e0) {
+        for (int rb = row0; rb < nrows; rb += 8 * RSTEP) {
+          TC tmp[8];
+#pragma unroll
+          for (int m = 0; m < 8; m++) {
+            const int row = rb + m * RSTEP;
+            if (row < nrows) {
+              const int b = row % e1, cc = row / e1;
+              tmp[m] = (TC)gld(T, f * gfs + base0 + (uint32_t)b * gsy + (uint32_t)cc * gsz + (uint32_t)lane32);
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < 8; m++) {
+            const int row = rb + m * RSTEP;
+            if (row < nrows) box[row * e0 + lane32] = tmp[m];
+          }
+        }
       }
       __syncthreads();
       if (valid) {
         TC sum = (TC)0;
         const TC *base = box + (s[2] - lo2) * e01 + (s[1] - lo1) * e0 + (s[0] - lo0);
 #pragma unroll
-        for (int cc = 0; cc < Pts; cc++)
+        for (int cc = 0; cc < Pts; cc++) {
+          // one z-layer: all Pts x Pts values read before the sums, so the LDS
+          // reads are issued back to back
+          TC v[Pts][Pts];
+#pragma unroll
+          for (int b = 0; b < Pts; b++)
+#pragma unroll
+            for (int a = 0; a < Pts; a++) v[b][a] = base[cc * e01 + b * e0 + a];
 #pragma unroll
           for (int b = 0; b < Pts; b++) {
-            const TC *row = base + cc * e01 + b * e0;
             TC part = (TC)0;
 #pragma unroll
-            for (int a = 0; a < Pts; a++) part += wxc[a] * row[a];
+            for (int a = 0; a < Pts; a++) part += wxc[a] * v[b][a];
             sum += wyzc[cc][b] * part;
           }
+        }
         acc[f] = sum;
       }
       __syncthreads();
@@ -428,11 +510,11 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *P, 
     for (int cc = 0; cc < Pts; cc++)
       for (int b = 0; b < Pts; b++) {
         TC part[5] = {0, 0, 0, 0, 0};
-        const long long x0 = cell_index(G0, s[0], s[1] + b, s[2] + cc);
+        const uint32_t x0 = (uint32_t)cell_index(G0, s[0], s[1] + b, s[2] + cc);
 #pragma unroll
         for (int a = 0; a < Pts; a++)
 #pragma unroll
-          for (int f = 0; f < 5; f++) part[f] += wxc[a] * (TC)T[f * G0.fstride + x0 + a];
+          for (int f = 0; f < 5; f++) part[f] += wxc[a] * (TC)gld(T, f * gfs + x0 + a);
         for (int f = 0; f < 5; f++) acc[f] += wyzc[cc][b] * part[f];
       }
   }
@@ -476,7 +558,7 @@ __device__ __forceinline__ double bcast_d(double v, int lane) {
 }
 
 template <typename TB, typename TC, int Pts>
-__global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *P, const PoseDev *pose, const int32_t *list,
+__global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list,
                                                   const int *count, const int32_t *cover, int sv, int stage,
                                                   unsigned long long *skips, FallbackRec *fb, int *fb_count) {
   const PatchDev &G0 = P[0];
@@ -531,25 +613,33 @@ __global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *P, const PoseD
         wyb = (m == lb) ? by : wyb;
         wzc[m] = bcast_d(wz[m], pnt);
       }
+      // donor parameters once per point (uniform: scalar loads)
       const PatchDev &D = P[dd];
       const TB *T = stage_buf<TB>(D, sv, stage);
-      const uint32_t fs = (uint32_t)D.fstride;
+      const uint32_t fs = (uint32_t)D.fstride, dsy = (uint32_t)D.pitch, dsz = (uint32_t)D.slab;
+      const int dn0 = D.n[0], dn1 = D.n[1], dn2 = D.n[2];
+      const bool per0 = D.periodic[0] != 0, per1 = D.periodic[1] != 0, per2 = D.periodic[2] != 0;
 #pragma unroll
       for (int f = 0; f < 5; f++) acc[f] = (TC)0;
       if (tap_lane) {
         const double wab = wxa * wyb;
         int ii = s0 + la, jj = s1 + lb;
-        if (D.periodic[0]) ii = ((ii % D.n[0]) + D.n[0]) % D.n[0];
-        if (D.periodic[1]) jj = ((jj % D.n[1]) + D.n[1]) % D.n[1];
+        if (per0) ii = ((ii % dn0) + dn0) % dn0;
+        if (per1) jj = ((jj % dn1) + dn1) % dn1;
+        const uint32_t xy = (uint32_t)(ii + PW_OX) + (uint32_t)(jj + PW_NG) * dsy;
+        uint32_t xs[Pts];
+        TC wv[Pts];
 #pragma unroll
         for (int cc = 0; cc < Pts; cc++) {
           int kk = s2 + cc;
-          if (D.periodic[2]) kk = ((kk % D.n[2]) + D.n[2]) % D.n[2];
-          const uint32_t x = (uint32_t)cell_index(D, ii, jj, kk);
-          const TC w = (TC)(wab * wzc[cc]);
-#pragma unroll
-          for (int f = 0; f < 5; f++) acc[f] += w * (TC)gld(T, f * fs + x);
+          if (per2) kk = ((kk % dn2) + dn2) % dn2;
+          xs[cc] = xy + (uint32_t)(kk + PW_NG) * dsz;
+          wv[cc] = (TC)(wab * wzc[cc]);
         }
+#pragma unroll
+        for (int cc = 0; cc < Pts; cc++)
+#pragma unroll
+          for (int f = 0; f < 5; f++) acc[f] += wv[cc] * (TC)gld(T, f * fs + xs[cc]);
       }
     };
     unsigned long long todo = vmask;
@@ -607,7 +697,7 @@ __global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *P, const PoseD
 // local ghost gets the exact solution (if registered) or a copy of the nearest
 // interior cell; a global effective ghost gets the exact solution or NaN.
 template <typename TB>
-__global__ void k_fallback(const PatchDev *P, const PoseDev *pose, const FallbackRec *fb, const int *fb_count, int sv,
+__global__ void k_fallback(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const FallbackRec *fb, const int *fb_count, int sv,
                            int stage, const ExactDev *ex, double v, const double *tdev, double tmul, double dt) {
   const int n = fb_count[0];
   const double t = tdev[0] + tmul * dt;
@@ -648,7 +738,7 @@ __global__ void k_fallback(const PatchDev *P, const PoseDev *pose, const Fallbac
 // End of step: cells live now but not live during the step get u_{n+1}
 // interpolated from the covering local patch; deactivated cells are poisoned;
 // the new flags become current.  mode 0: first flags (no uncover fill).
-__global__ void k_finalize(const PatchDev *P, const PoseDev *pose, uint8_t *flag_cur, const uint8_t *flag_new,
+__global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, uint8_t *flag_cur, const uint8_t *flag_new,
                            int32_t *cover_cur, int32_t *cover_new, int nsv, const int *Pts, const ExactDev *ex,
                            const double *vs, const double *tdev, int mode, unsigned long long *counters) {
   const PatchDev &G0 = P[0];
@@ -708,7 +798,7 @@ __global__ void k_finalize(const PatchDev *P, const PoseDev *pose, uint8_t *flag
 // for the x-y stencils.
 // ---------------------------------------------------------------------------
 template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD>
-__global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *P, const PoseDev *pose_slot, const TileRec *tiles,
+__global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose_slot, const TileRec *tiles,
                                                int ntiles, int chunk, const uint8_t *gflag, int sv, double dt,
                                                double v2, double eps) {
   __shared__ TC Bc[2][5][ST_PW];
@@ -1020,7 +1110,7 @@ __global__ void k_pack(const PatchDev *P, int pid, int sv, double *dst, int full
   dst[q] = p.u[sv][f * p.fstride + cell_index(p, i, j, k)];
 }
 
-__global__ void k_init_exact(const PatchDev *P, const PoseDev *pose, int pid, int sv, const ExactDev *ex, double v,
+__global__ void k_init_exact(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, int pid, int sv, const ExactDev *ex, double v,
                              double t) {
   const PatchDev &p = P[pid];
   long long per = (long long)p.n[0] * p.n[1] * p.n[2];
@@ -1034,7 +1124,7 @@ __global__ void k_init_exact(const PatchDev *P, const PoseDev *pose, int pid, in
 }
 
 // Per-block partial diagnostics: 23 doubles per block (see pw_diag).
-__global__ void k_diag(const PatchDev *P, const PoseDev *pose, int pid, int sv, const uint8_t *gflag,
+__global__ void k_diag(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, int pid, int sv, const uint8_t *gflag,
                        const ExactDev *ex, double v, double t, double *partial) {
   const PatchDev &p = P[pid];
   long long per = (long long)p.n[0] * p.n[1] * p.n[2];
@@ -1119,6 +1209,17 @@ void launch_flags(hipStream_t s, const FlagsArgs &a) {
                      a.flag_new, tot);
 }
 
+void launch_l2g_order(hipStream_t s, const L2GOrderArgs &a) {
+  if (a.nbuckets <= 0) return;
+  hipLaunchKernelGGL(k_fill_value<int>, dim3(nblk(a.nbuckets, 256) < 4096 ? nblk(a.nbuckets, 256) : 4096), dim3(256), 0,
+                     s, a.cnt, (long long)a.nbuckets, 0);
+  hipLaunchKernelGGL(k_bucket_count, dim3(1024), dim3(256), 0, s, a.P, a.pose, (const int32_t *)a.list, a.count,
+                     a.cover, a.cnt, a.ebkt, a.erank);
+  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, (const int *)a.cnt, a.off, a.nbuckets);
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(1024), dim3(256), 0, s, (const int32_t *)a.list, a.count,
+                     (const int *)a.ebkt, (const int *)a.erank, (const int *)a.off, a.sorted);
+}
+
 void launch_finalize(hipStream_t s, const FinalizeArgs &a) {
   long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
   hipLaunchKernelGGL(k_finalize, dim3(nblk(tot, 256)), dim3(256), 0, s, a.P, a.pose, a.flag_cur, a.flag_new,
@@ -1167,6 +1268,7 @@ void launch_ghosts(hipStream_t s, const GhostArgs &a) {
 }
 
 void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
+  // (the donor ordering of the list is done by launch_l2g_order after this)
   long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
   unsigned nb = nblk(tot, 256);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.effcount, 0);
