@@ -431,7 +431,7 @@ void enqueue_finalize(pw_context *c, const PoseDev *pose_slot, int mode) {
 
 // Ghost fill of the buffers of `stage` (0: u) at time tdev[0] + tmul*dt.
 void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const double *tdev, double tmul, double dt,
-                    int parts = GH_GLOBAL | GH_LOCAL, hipStream_t st = nullptr) {
+                    int parts = GH_GLOBAL | GH_LOCAL, hipStream_t st = nullptr, bool fill_u = false) {
   if (!st) st = c->stream;
   for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
     GhostArgs a;
@@ -451,7 +451,7 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     for (int d = 0; d < 3; d++) a.gn[d] = c->hp[0].n[d];
     a.sv = sv;
     a.stage = stage;
-    a.stage_fp64 = (stage == 0) || !mixed(c);
+    a.stage_fp64 = !mixed(c) || fill_u;
     a.mixed = mixed(c);
     a.Pts = c->cfg.interp_points[sv];
     a.ex = c->dEx;
@@ -801,6 +801,9 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     launch_fill_f64(c->stream, p.u[s], nel, NAN);
     launch_fill_f64(c->stream, p.acc[s], nel, NAN);
     if (mixed(c)) {
+      p.us[s] = (float *)dalloc(c, sizeof(float) * nel);
+      if (!p.us[s]) return fail(c, PW_ENOMEM, "device allocation failed");
+      launch_fill_f32(c->stream, p.us[s], nel, NAN);
       launch_fill_f32(c->stream, (float *)p.va[s], nel, NAN);
       launch_fill_f32(c->stream, (float *)p.vb[s], nel, NAN);
     } else {
@@ -972,7 +975,8 @@ pw_status pw_exchange_ghosts(pw_context *c, double t) {
   rc = set_time(c, c->dTx, t);
   if (rc) return rc;
   launch_pose_at(c->stream, c->dP, np, t, c->dPose + 3 * np);
-  enqueue_ghosts(c, 0, c->dPose + 3 * np, c->dTx, 0.0, 0.0);
+  // fills the ghosts of u itself (FP64) in both precision modes
+  enqueue_ghosts(c, 0, c->dPose + 3 * np, c->dTx, 0.0, 0.0, GH_GLOBAL | GH_LOCAL, nullptr, true);
   HIPCHK(c, hipGetLastError());
   return PW_OK;
 }

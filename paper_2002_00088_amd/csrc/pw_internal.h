@@ -37,6 +37,7 @@ struct PatchDev {
   double *acc[PW_MAXSV];
   void *va[PW_MAXSV];
   void *vb[PW_MAXSV];
+  float *us[PW_MAXSV];  // mixed precision: FP32 copy of u (stage-1 stencil input), else null
 };
 
 // Pose of a patch at one stage time: centre, its first and second time

@@ -8,8 +8,12 @@
 // stage-kernel tile: ST_TX x ST_TY columns, up to ST_TZ planes per workgroup
 #define ST_TX 32
 #define ST_TY 8
-#define ST_TZ 64
+#ifndef ST_TZ
+#define ST_TZ 16
+#endif
+#ifndef ST_MINB
 #define ST_MINB 1
+#endif
 #define ST_PX (ST_TX + 6)
 #define ST_PY (ST_TY + 6)
 #define ST_PW (ST_PX * ST_PY)

@@ -168,7 +168,8 @@ __device__ inline bool interp5(const PatchDev &p, const TB *T, const uint8_t *gf
 
 template <typename TB>
 __device__ inline TB *stage_buf(const PatchDev &p, int sv, int stage) {
-  if (stage == 0) return (TB *)p.u[sv];
+  // stage 1 reads u: FP64 in the FP64 path, its FP32 copy in the mixed path
+  if (stage == 0) return sizeof(TB) == 8 ? (TB *)p.u[sv] : (TB *)p.us[sv];
   return (TB *)((stage == 2) ? p.vb[sv] : p.va[sv]);
 }
 
@@ -765,12 +766,16 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
         else for (int f = 0; f < 5; f++) out[f] = NAN;
       }
       for (int f = 0; f < 5; f++) G0.u[sv][f * G0.fstride + x] = out[f];
+      if (G0.us[sv])
+        for (int f = 0; f < 5; f++) G0.us[sv][f * G0.fstride + x] = (float)out[f];
     }
   }
   if (fn == DEACT) {
     for (int sv = 0; sv < nsv; sv++) {
       if (!(G0.sv_mask & (1u << sv))) continue;
       for (int f = 0; f < 5; f++) G0.u[sv][f * G0.fstride + x] = NAN;
+      if (G0.us[sv])
+        for (int f = 0; f < 5; f++) G0.us[sv][f * G0.fstride + x] = NAN;
     }
   }
   flag_cur[c] = fn;
@@ -816,7 +821,9 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
   const bool icol = (i < p.n[0]) && (j < p.n[1]);
   const int z0 = tl.z0;
   const int nz = min(ST_TZ, p.n[2] - z0);
-  const TIN *in = (const TIN *)(STAGE == 0 ? (const void *)p.u[sv] : (STAGE == 2 ? p.vb[sv] : p.va[sv]));
+  const TIN *in = (const TIN *)(STAGE == 0 ? (sizeof(TIN) == 8 ? (const void *)p.u[sv] : (const void *)p.us[sv])
+                                            : (STAGE == 2 ? p.vb[sv] : p.va[sv]));
+  float *Us = p.us[sv];  // FP32 copy of u (mixed path): written with u_{n+1} by the last stage
   TOUT *vout = (TOUT *)(STAGE == 1 ? p.vb[sv] : p.va[sv]);
   double *U = p.u[sv];
   double *Acc = p.acc[sv];
@@ -1065,7 +1072,9 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
             gst(Acc, x, cu[f] + bdt * kf);
             gst(vout, x, (TOUT)(cu[f] + adt * kf));
           } else if (STAGE == 3) {
-            gst(U, x, ca[f] + bdt * kf);
+            const double un = ca[f] + bdt * kf;
+            gst(U, x, un);
+            if (sizeof(TOUT) == 4) gst(Us, x, (float)un);
           } else {
             gst(Acc, x, ca[f] + bdt * kf);
             gst(vout, x, (TOUT)(cu[f] + adt * kf));
@@ -1093,7 +1102,9 @@ __global__ void k_unpack(const PatchDev *P, int pid, int sv, const double *src) 
   int f = (int)(q / per);
   long long c = q % per;
   int i = (int)(c % p.n[0]), j = (int)((c / p.n[0]) % p.n[1]), k = (int)(c / ((long long)p.n[0] * p.n[1]));
-  p.u[sv][f * p.fstride + cell_index(p, i, j, k)] = src[q];
+  const long long x = f * p.fstride + cell_index(p, i, j, k);
+  p.u[sv][x] = src[q];
+  if (p.us[sv]) p.us[sv][x] = (float)src[q];
 }
 
 __global__ void k_pack(const PatchDev *P, int pid, int sv, double *dst, int full) {
@@ -1121,6 +1132,8 @@ __global__ void k_init_exact(const PatchDev *__restrict__ P, const PoseDev *__re
   exact_patch(ex[sv], v, p, pose[pid], t, xp, e);
   long long x = cell_index(p, i, j, k);
   for (int f = 0; f < 5; f++) p.u[sv][f * p.fstride + x] = e[f];
+  if (p.us[sv])
+    for (int f = 0; f < 5; f++) p.us[sv][f * p.fstride + x] = (float)e[f];
 }
 
 // Per-block partial diagnostics: 23 doubles per block (see pw_diag).
@@ -1310,7 +1323,7 @@ void launch_stage(hipStream_t s, const StageArgs &a) {
     }
   } else {
     switch (a.stage) {
-      case 0: PW_STAGE(double, float, float, 0); break;
+      case 0: PW_STAGE(float, float, float, 0); break;
       case 1: PW_STAGE(float, float, float, 1); break;
       case 2: PW_STAGE(float, float, float, 2); break;
       default: PW_STAGE(float, float, float, 3); break;
