@@ -52,7 +52,7 @@ struct pw_context {
   int32_t *efflist = nullptr, *effsorted = nullptr;
   int *effcount = nullptr;
   int nBuckets = 0;
-  int *bkCnt = nullptr, *bkOff = nullptr, *eBkt = nullptr, *eRank = nullptr;
+  int *bkCnt = nullptr, *bkOff = nullptr, *bkRank = nullptr, *eBkt = nullptr, *eRank = nullptr;
   FallbackRec *fbList[2] = {nullptr, nullptr};  // skipped points of the local / global part
   int *fbCount[2] = {nullptr, nullptr};
   long long fbCap = 0;
@@ -277,9 +277,32 @@ pw_status upload_layout(pw_context *c) {
     HIPCHK(c, hipMemcpy(c->dBricks, bricks.data(), sizeof(GBrick) * bricks.size(), hipMemcpyHostToDevice));
   dfree(c, c->bkCnt);
   dfree(c, c->bkOff);
+  dfree(c, c->bkRank);
   c->bkCnt = (int *)dalloc(c, sizeof(int) * std::max(1, c->nBuckets));
   c->bkOff = (int *)dalloc(c, sizeof(int) * std::max(1, c->nBuckets));
-  if (!c->bkCnt || !c->bkOff) return fail(c, PW_ENOMEM, "device allocation failed");
+  c->bkRank = (int *)dalloc(c, sizeof(int) * std::max(1, c->nBuckets));
+  if (!c->bkCnt || !c->bkOff || !c->bkRank) return fail(c, PW_ENOMEM, "device allocation failed");
+  {
+    // bucket ids of each local patch follow a Morton curve through its 8^3-cell
+    // buckets, so that consecutive buckets are spatial neighbours
+    std::vector<int> rank(std::max(1, c->nBuckets), 0);
+    for (int pid = 1; pid < np; pid++) {
+      const PatchDev &p = c->hp[pid];
+      const int nb = p.bkt_n[0] * p.bkt_n[1] * p.bkt_n[2];
+      std::vector<std::pair<uint64_t, int>> key(nb);
+      for (int b = 0; b < nb; b++) {
+        const int bx = b % p.bkt_n[0], by = (b / p.bkt_n[0]) % p.bkt_n[1], bz = b / (p.bkt_n[0] * p.bkt_n[1]);
+        uint64_t m = 0;
+        for (int bit = 0; bit < 20; bit++)
+          m |= ((uint64_t)((bx >> bit) & 1) << (3 * bit)) | ((uint64_t)((by >> bit) & 1) << (3 * bit + 1)) |
+               ((uint64_t)((bz >> bit) & 1) << (3 * bit + 2));
+        key[b] = {m, b};
+      }
+      std::sort(key.begin(), key.end());
+      for (int r = 0; r < nb; r++) rank[p.bkt_base + key[r].second] = r;
+    }
+    HIPCHK(c, hipMemcpy(c->bkRank, rank.data(), sizeof(int) * rank.size(), hipMemcpyHostToDevice));
+  }
   // fallback lists: every local ghost cell (local part) or every global cell (global part)
   long long nloc = 0;
   for (int pid = 1; pid < np; pid++) {
@@ -403,10 +426,12 @@ void enqueue_post_flags(pw_context *c, const PoseDev *pose_slot) {
   o.cover = c->cover_cur;
   o.nbuckets = c->nBuckets;
   o.cnt = c->bkCnt;
+  o.rank = c->bkRank;
   o.off = c->bkOff;
   o.ebkt = c->eBkt;
   o.erank = c->eRank;
   o.sorted = c->effsorted;
+  o.out = c->efflist;  // the unordered list is not needed once scattered
   launch_l2g_order(c->stream, o);
 }
 
@@ -444,7 +469,7 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.bricks = c->dBricks;
     a.n_bricks = has_locals(c) ? c->nBricks : 0;
     a.dvalid = c->dvalid[c->cfg.interp_points[sv] == 5 ? 0 : 1];
-    a.efflist = c->effsorted;
+    a.efflist = c->efflist;
     a.effcount = c->effcount;
     a.cover = c->cover_cur;
     a.has_locals = has_locals(c);

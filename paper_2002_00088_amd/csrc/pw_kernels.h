@@ -19,8 +19,11 @@
 #define ST_PW (ST_PX * ST_PY)
 #define DIAG_N 23
 #define BRICK_THREADS 192
-#define BRICK_LDS 6144
+#define BRICK_LDS_BYTES 40960
 #define L2G_BLOCKS 2048
+#define L2G_WAVES 3
+#define L2G_LDS_BYTES 36864
+#define BUCKET_SORT_LDS 4096
 
 namespace pw {
 
@@ -73,7 +76,9 @@ struct L2GOrderArgs {
   const int32_t *cover;
   int nbuckets;
   int *cnt, *off, *ebkt, *erank;
-  int32_t *sorted;
+  const int *rank;  // position of each bucket along its patch's Morton curve
+  int32_t *sorted;  // entries grouped by bucket (scratch)
+  int32_t *out;     // the same, ascending cell index within each bucket (may alias list)
 };
 
 struct FlagsArgs {
@@ -117,7 +122,7 @@ struct GhostArgs {
   const GBrick *bricks;
   int n_bricks;
   const uint8_t *dvalid;
-  const int32_t *efflist;
+  const int32_t *efflist;  // effective ghosts grouped by donor bucket
   const int *effcount;
   const int32_t *cover;
   int has_locals;

@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void k_efflist(const uint8_t *flag, int n0, in
 // (covering local patch, 8^3-cell bucket of that patch holding the point), so
 // that the points a wavefront gathers share donor rows in the caches.
 __global__ void k_bucket_count(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list, const int *count,
-                               const int32_t *cover, int *cnt, int *ebkt, int *erank) {
+                               const int32_t *cover, const int *rank, int *cnt, int *ebkt, int *erank) {
   const PatchDev &G0 = P[0];
   const int n = count[0];
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
@@ -338,7 +338,7 @@ __global__ void k_bucket_count(const PatchDev *__restrict__ P, const PoseDev *__
         ii = ii < 0 ? 0 : (ii >= D.n[a] ? D.n[a] - 1 : ii);
         bi[a] = ii >> 3;
       }
-      b = D.bkt_base + (bi[2] * D.bkt_n[1] + bi[1]) * D.bkt_n[0] + bi[0];
+      b = D.bkt_base + rank[D.bkt_base + (bi[2] * D.bkt_n[1] + bi[1]) * D.bkt_n[0] + bi[0]];
     }
     ebkt[q] = b;
     erank[q] = atomicAdd(&cnt[b], 1);
@@ -375,12 +375,44 @@ __global__ void k_bucket_scatter(const int32_t *list, const int *count, const in
     sorted[off[ebkt[q]] + erank[q]] = list[q];
 }
 
+// Each bucket's entries in ascending global cell index (rank by counting; one
+// workgroup per bucket, keys staged in LDS when they fit).  The list order, and
+// so the grouping of the local->global kernel, is then independent of the order
+// in which the atomics of the bucket count were served.
+__global__ __launch_bounds__(256) void k_bucket_sort(const int32_t *in, const int *cnt, const int *off, int nb,
+                                                     int32_t *out) {
+  __shared__ int32_t keys[BUCKET_SORT_LDS];
+  const int b = blockIdx.x;
+  if (b >= nb) return;
+  const int m = cnt[b];
+  if (m == 0) return;
+  const int o = off[b];
+  const int32_t *src = in + o;
+  if (m <= BUCKET_SORT_LDS) {
+    for (int t = threadIdx.x; t < m; t += blockDim.x) keys[t] = src[t];
+    __syncthreads();
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+      const int32_t mine = keys[t];
+      int r = 0;
+      for (int u = 0; u < m; u++) r += keys[u] < mine ? 1 : 0;
+      out[o + r] = mine;
+    }
+  } else {
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+      const int32_t mine = src[t];
+      int r = 0;
+      for (int u = 0; u < m; u++) r += src[u] < mine ? 1 : 0;
+      out[o + r] = mine;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Global -> local (Sec. 2.4.1).  One workgroup per brick of up to 8x8x3 ghost
 // cells of one face of a local patch.  Each thread locates its point in the
 // global patch (FP64) and forms its Lagrange weights (FP64); the union of the
-// donor stencils is staged in LDS one field at a time (coalesced rows) and every
-// thread sums its P^3 taps from LDS.  Validity is one byte: every cell of the
+// donor stencils (the donor box) is staged in LDS, as many fields at a time as
+// fit (all five for most bricks), and every thread sums its P^3 taps from LDS.  Validity is one byte: every cell of the
 // donor stencil must be live.  Points that cannot be interpolated keep the
 // lower-priority value (analytic or nearest interior) and are counted.
 // ---------------------------------------------------------------------------
@@ -389,7 +421,7 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__r
                                                              const GBrick *bricks, int sv, int stage,
                                                              const uint8_t *dvalid, unsigned long long *skips,
                                                              FallbackRec *fb, int *fb_count) {
-  __shared__ TC box[BRICK_LDS];
+  __shared__ TC box[BRICK_LDS_BYTES / sizeof(TC)];
   __shared__ int blo[3], bhi[3];
   const GBrick B = bricks[blockIdx.x];
   const PatchDev &r = P[B.patch];
@@ -455,69 +487,95 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__r
 #pragma unroll
     for (int b = 0; b < Pts; b++) wyzc[cc][b] = (TC)(wy[b] * wz[cc]);
   const uint32_t gfs = (uint32_t)G0.fstride, gsy = (uint32_t)G0.pitch, gsz = (uint32_t)G0.slab;
-  if (vol > 0 && vol <= BRICK_LDS && e0 <= 32) {
+  constexpr int CAP = BRICK_LDS_BYTES / sizeof(TC);
+  const int nfp = vol > 0 ? (int)(CAP / vol < 5 ? CAP / vol : 5) : 0;  // fields per LDS pass
+  if (nfp > 0) {
     const int e01 = e0 * e1;
-    const int nrows = e1 * e2;
-    const int lane32 = tid & 31, row0 = tid >> 5;
-    constexpr int RSTEP = BRICK_THREADS / 32;
+    const int v = (int)vol;
     const uint32_t base0 = (uint32_t)(lo0 + PW_OX) + (uint32_t)(lo1 + PW_NG) * gsy + (uint32_t)(lo2 + PW_NG) * gsz;
-    for (int f = 0; f < 5; f++) {
-      // rows of the donor box, 32 threads per row, 8 rows in flight per thread
-      if (lane32 < e0) {
-        for (int rb = row0; rb < nrows; rb += 8 * RSTEP) {
-          TC tmp[8];
+    // flat box index q -> (x, row), row -> (b, cc) with float reciprocals: exact,
+    // since (q + 0.5) / e lies at least 1/(2e) from an integer and q < 2^14
+    const float ie0 = 1.0f / (float)e0, ie1 = 1.0f / (float)e1;
+    for (int f0 = 0; f0 < 5; f0 += nfp) {
+      const int nf = 5 - f0 < nfp ? 5 - f0 : nfp;
+      for (int q0 = tid; q0 < v; q0 += 4 * BRICK_THREADS) {
+        TC tmp[4][5];
 #pragma unroll
-          for (int m = 0; m < 8; m++) {
-            const int row = rb + m * RSTEP;
-            if (row < nrows) {
-              const int b = row % e1, cc = row / e1;
-              tmp[m] = (TC)gld(T, f * gfs + base0 + (uint32_t)b * gsy + (uint32_t)cc * gsz + (uint32_t)lane32);
-            }
+        for (int m = 0; m < 4; m++) {
+          const int q = q0 + m * BRICK_THREADS;
+          if (q < v) {
+            const int row = (int)(((float)q + 0.5f) * ie0);
+            const int x = q - row * e0;
+            const int cc = (int)(((float)row + 0.5f) * ie1);
+            const int b = row - cc * e1;
+            const uint32_t g = base0 + (uint32_t)b * gsy + (uint32_t)cc * gsz + (uint32_t)x;
+#pragma unroll
+            for (int f = 0; f < 5; f++)
+              if (f < nf) tmp[m][f] = (TC)gld(T, (uint32_t)(f0 + f) * gfs + g);
           }
+        }
 #pragma unroll
-          for (int m = 0; m < 8; m++) {
-            const int row = rb + m * RSTEP;
-            if (row < nrows) box[row * e0 + lane32] = tmp[m];
+        for (int m = 0; m < 4; m++) {
+          const int q = q0 + m * BRICK_THREADS;
+          if (q < v) {
+#pragma unroll
+            for (int f = 0; f < 5; f++)
+              if (f < nf) box[f * v + q] = tmp[m][f];
           }
         }
       }
       __syncthreads();
       if (valid) {
-        TC sum = (TC)0;
         const TC *base = box + (s[2] - lo2) * e01 + (s[1] - lo1) * e0 + (s[0] - lo0);
+        for (int f = 0; f < nf; f++) {
+          TC sum = (TC)0;
+          const TC *bf = base + f * v;
 #pragma unroll
-        for (int cc = 0; cc < Pts; cc++) {
-          // one z-layer: all Pts x Pts values read before the sums, so the LDS
-          // reads are issued back to back
-          TC v[Pts][Pts];
+          for (int cc = 0; cc < Pts; cc++) {
+            // one z-layer: all Pts x Pts values read before the sums, so the LDS
+            // reads are issued back to back
+            TC w[Pts][Pts];
 #pragma unroll
-          for (int b = 0; b < Pts; b++)
+            for (int b = 0; b < Pts; b++)
 #pragma unroll
-            for (int a = 0; a < Pts; a++) v[b][a] = base[cc * e01 + b * e0 + a];
+              for (int a = 0; a < Pts; a++) w[b][a] = bf[cc * e01 + b * e0 + a];
 #pragma unroll
-          for (int b = 0; b < Pts; b++) {
-            TC part = (TC)0;
+            for (int b = 0; b < Pts; b++) {
+              TC part = (TC)0;
 #pragma unroll
-            for (int a = 0; a < Pts; a++) part += wxc[a] * v[b][a];
-            sum += wyzc[cc][b] * part;
+              for (int a = 0; a < Pts; a++) part += wxc[a] * w[b][a];
+              sum += wyzc[cc][b] * part;
+            }
           }
+#pragma unroll
+          for (int m = 0; m < 5; m++)
+            if (m == f0 + f) acc[m] = sum;
         }
-        acc[f] = sum;
       }
-      __syncthreads();
+      if (f0 + nfp < 5) __syncthreads();
     }
   } else if (valid) {
     // donor box larger than the LDS tile: gather straight from global memory
-    for (int cc = 0; cc < Pts; cc++)
+    // (weights picked by selects, so no array is indexed dynamically)
+    for (int cc = 0; cc < Pts; cc++) {
+      double wzd = 0.0;
+#pragma unroll
+      for (int m = 0; m < Pts; m++) wzd = (m == cc) ? wz[m] : wzd;
       for (int b = 0; b < Pts; b++) {
+        double wyd = 0.0;
+#pragma unroll
+        for (int m = 0; m < Pts; m++) wyd = (m == b) ? wy[m] : wyd;
         TC part[5] = {0, 0, 0, 0, 0};
         const uint32_t x0 = (uint32_t)cell_index(G0, s[0], s[1] + b, s[2] + cc);
 #pragma unroll
         for (int a = 0; a < Pts; a++)
 #pragma unroll
           for (int f = 0; f < 5; f++) part[f] += wxc[a] * (TC)gld(T, f * gfs + x0 + a);
-        for (int f = 0; f < 5; f++) acc[f] += wyzc[cc][b] * part[f];
+        const TC wyz = (TC)(wyd * wzd);
+#pragma unroll
+        for (int f = 0; f < 5; f++) acc[f] += wyz * part[f];
       }
+    }
   }
   if (!active) return;
   if (!valid) {
@@ -541,14 +599,20 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__r
 }
 
 // ---------------------------------------------------------------------------
-// Local -> global (Sec. 2.4.2).  A wavefront takes 64 effective ghost cells of
-// the compacted list, one per lane: each lane locates its point in the covering
-// local patch and forms its Lagrange weights (FP64).  The P^3 taps are then
-// summed cooperatively, one point at a time: the point's stencil start and
-// weights are broadcast with readlane, lane (a, b) reads the x-row element a of
-// row b for every z-layer c, and the five partial sums are reduced across the
-// wavefront with xor shuffles.  Each lane finally transforms its own point to
-// the global frame and stores it.
+// Local -> global (Sec. 2.4.2).  The effective ghost cells are ordered by the
+// 8^3-cell bucket of the covering local patch that holds their donor point
+// (buckets in Morton order), so consecutive entries have nearby donor stencils.
+// A workgroup of L2G_WAVES wavefronts takes 64 entries; every wave locates the
+// 64 points in the donor patch and forms their Lagrange weights (FP64, one point
+// per lane).  The group is cut into runs of 8-point octets, as long as the union
+// of a run's donor stencils (its donor box) lies in one donor patch and fits the
+// LDS tile; the box is staged in LDS (as many fields per pass as fit) and wave w
+// sums z-layers w, w + L2G_WAVES, ... of every stencil of the run.  An octet
+// whose box does not fit alone is summed cooperatively from global memory: one
+// point at a time per wave, the point's stencil start and weights broadcast with
+// readlane, lane (a, b) reading x-row element a of row b of every z-layer, and
+// the partial sums reduced with xor shuffles.  The per-wave partial sums meet in
+// LDS; wave 0 carries each point to the global frame and stores it.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int bcast_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 __device__ __forceinline__ double bcast_d(double v, int lane) {
@@ -557,35 +621,48 @@ __device__ __forceinline__ double bcast_d(double v, int lane) {
   int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+__device__ __forceinline__ double bcast_t(double v, int lane) { return bcast_d(v, lane); }
+__device__ __forceinline__ float bcast_t(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
 
 template <typename TB, typename TC, int Pts>
-__global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list,
-                                                  const int *count, const int32_t *cover, int sv, int stage,
-                                                  unsigned long long *skips, FallbackRec *fb, int *fb_count) {
+__global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_l2g_box(
+    const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list, const int *count,
+    const int32_t *cover, int sv, int stage, unsigned long long *skips, FallbackRec *fb, int *fb_count) {
+  constexpr int CAP = L2G_LDS_BYTES / sizeof(TC);
+  __shared__ TC box[CAP];
+  __shared__ TC red[L2G_WAVES - 1][5][64];
+  __shared__ int obox[8][8];  // per octet: lo[3], hi[3], lowest and highest donor id
   const PatchDev &G0 = P[0];
   if (!(G0.sv_mask & (1u << sv))) return;
-  const int lane = threadIdx.x & 63;
-  const long long wid = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const long long nw = ((long long)gridDim.x * blockDim.x) >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = count[0];
   const int la = lane % Pts, lb = lane / Pts;
   const bool tap_lane = lane < Pts * Pts;
   TB *TG = stage_buf<TB>(G0, sv, stage);
-  for (long long base = wid * 64; base < n; base += nw * 64) {
-    const long long qi = base + lane;
+  for (int g0 = blockIdx.x * 64; g0 < n; g0 += gridDim.x * 64) {
+    if (tid < 64) {
+      const int e = tid & 7;
+      obox[tid >> 3][e] = e < 3 ? (1 << 30) : (e < 6 ? -(1 << 30) : (e == 6 ? (1 << 30) : -1));
+    }
+    __syncthreads();
+    const int qi = g0 + lane;
     const bool have = qi < n;
     const long long c = have ? list[qi] : 0;
     const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]),
               k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
     const int d = have ? cover[c] : 0;
-    double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)}, xd[3] = {0, 0, 0};
+    double xd[3] = {0, 0, 0};
     bool valid = have && d >= 1 && (P[d].sv_mask & (1u << sv));
     int s[3] = {0, 0, 0};
-    double wx[Pts], wy[Pts], wz[Pts];
+    // Lagrange weights are formed in FP64 and kept in the compute type
+    TC wxc[Pts], wyc[Pts], wzc[Pts];
 #pragma unroll
-    for (int m = 0; m < Pts; m++) { wx[m] = 0.0; wy[m] = 0.0; wz[m] = 0.0; }
+    for (int m = 0; m < Pts; m++) { wxc[m] = (TC)0; wyc[m] = (TC)0; wzc[m] = (TC)0; }
     if (valid) {
       const PatchDev &D = P[d];
+      const double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
       inv_map(D, pose[d], X, xd);
       double q[3];
       for (int a = 0; a < 3; a++) {
@@ -593,95 +670,242 @@ __global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *__restrict__ P
         valid = valid && (q[a] > -1.0e6 && q[a] < 1.0e6);
       }
       if (valid) {
+        double wx[Pts], wy[Pts], wz[Pts];
         s[0] = lagrange_wt<Pts>(q[0], wx);
         s[1] = lagrange_wt<Pts>(q[1], wy);
         s[2] = lagrange_wt<Pts>(q[2], wz);
+#pragma unroll
+        for (int m = 0; m < Pts; m++) { wxc[m] = (TC)wx[m]; wyc[m] = (TC)wy[m]; wzc[m] = (TC)wz[m]; }
         for (int a = 0; a < 3; a++)
           if (!D.periodic[a] && (s[a] < 0 || s[a] + Pts - 1 > D.n[a] - 1)) valid = false;
       }
     }
-    TC res[5] = {0, 0, 0, 0, 0};
-    const unsigned long long vmask = __ballot(valid);
-    // taps of one point by the whole wavefront; two points in flight per pass
-    auto taps = [&](int pnt, TC acc[5]) {
-      const int dd = bcast_i(d, pnt);
-      const int s0 = bcast_i(s[0], pnt), s1 = bcast_i(s[1], pnt), s2 = bcast_i(s[2], pnt);
-      double wxa = 0.0, wyb = 0.0, wzc[Pts];
-#pragma unroll
-      for (int m = 0; m < Pts; m++) {
-        const double bx = bcast_d(wx[m], pnt), by = bcast_d(wy[m], pnt);
-        wxa = (m == la) ? bx : wxa;
-        wyb = (m == lb) ? by : wyb;
-        wzc[m] = bcast_d(wz[m], pnt);
+    if (valid && wv == 0) {
+      int *ob = obox[lane >> 3];
+      for (int a = 0; a < 3; a++) {
+        atomicMin(&ob[a], s[a]);
+        atomicMax(&ob[3 + a], s[a] + Pts - 1);
       }
-      // donor parameters once per point (uniform: scalar loads)
-      const PatchDev &D = P[dd];
-      const TB *T = stage_buf<TB>(D, sv, stage);
-      const uint32_t fs = (uint32_t)D.fstride, dsy = (uint32_t)D.pitch, dsz = (uint32_t)D.slab;
-      const int dn0 = D.n[0], dn1 = D.n[1], dn2 = D.n[2];
-      const bool per0 = D.periodic[0] != 0, per1 = D.periodic[1] != 0, per2 = D.periodic[2] != 0;
-#pragma unroll
-      for (int f = 0; f < 5; f++) acc[f] = (TC)0;
-      if (tap_lane) {
-        const double wab = wxa * wyb;
-        int ii = s0 + la, jj = s1 + lb;
-        if (per0) ii = ((ii % dn0) + dn0) % dn0;
-        if (per1) jj = ((jj % dn1) + dn1) % dn1;
-        const uint32_t xy = (uint32_t)(ii + PW_OX) + (uint32_t)(jj + PW_NG) * dsy;
-        uint32_t xs[Pts];
-        TC wv[Pts];
-#pragma unroll
-        for (int cc = 0; cc < Pts; cc++) {
-          int kk = s2 + cc;
-          if (per2) kk = ((kk % dn2) + dn2) % dn2;
-          xs[cc] = xy + (uint32_t)(kk + PW_NG) * dsz;
-          wv[cc] = (TC)(wab * wzc[cc]);
-        }
-#pragma unroll
-        for (int cc = 0; cc < Pts; cc++)
-#pragma unroll
-          for (int f = 0; f < 5; f++) acc[f] += wv[cc] * (TC)gld(T, f * fs + xs[cc]);
-      }
-    };
-    unsigned long long todo = vmask;
-    while (todo) {
-      const int p0 = __ffsll((long long)todo) - 1;
-      todo &= todo - 1ull;
-      int p1 = -1;
-      if (todo) {
-        p1 = __ffsll((long long)todo) - 1;
-        todo &= todo - 1ull;
-      }
-      TC a0[5], a1[5];
-      taps(p0, a0);
-      if (p1 >= 0) taps(p1, a1);
-      else {
-#pragma unroll
-        for (int f = 0; f < 5; f++) a1[f] = (TC)0;
-      }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-        for (int f = 0; f < 5; f++) {
-          a0[f] += __shfl_xor(a0[f], off);
-          a1[f] += __shfl_xor(a1[f], off);
-        }
-      if (lane == p0) {
-#pragma unroll
-        for (int f = 0; f < 5; f++) res[f] = a0[f];
-      }
-      if (lane == p1) {
-#pragma unroll
-        for (int f = 0; f < 5; f++) res[f] = a1[f];
-      }
+      atomicMin(&ob[6], d);
+      atomicMax(&ob[7], d);
     }
-    if (have) {
+    __syncthreads();
+    TC acc[5] = {0, 0, 0, 0, 0};
+    // runs of octets (the same on every thread: read from LDS)
+    for (int o0 = 0; o0 < 8;) {
+      int lo[3], hi[3], dmin, dmax;
+      for (int a = 0; a < 3; a++) {
+        lo[a] = obox[o0][a];
+        hi[a] = obox[o0][3 + a];
+      }
+      dmin = obox[o0][6];
+      dmax = obox[o0][7];
+      auto volume = [&](const int *l, const int *h) -> long long {
+        return (h[0] >= l[0] && h[1] >= l[1] && h[2] >= l[2])
+                   ? (long long)(h[0] - l[0] + 1) * (h[1] - l[1] + 1) * (h[2] - l[2] + 1)
+                   : 0;
+      };
+      auto fits = [&](const int *l, const int *h, int dl, int dh) {
+        return dh < 0 || (dl == dh && volume(l, h) <= CAP);
+      };
+      int o1 = o0 + 1;
+      if (fits(lo, hi, dmin, dmax)) {
+        while (o1 < 8) {
+          int l2[3], h2[3];
+          for (int a = 0; a < 3; a++) {
+            l2[a] = min(lo[a], obox[o1][a]);
+            h2[a] = max(hi[a], obox[o1][3 + a]);
+          }
+          const int dl = min(dmin, obox[o1][6]), dh = max(dmax, obox[o1][7]);
+          if (!fits(l2, h2, dl, dh)) break;
+          for (int a = 0; a < 3; a++) {
+            lo[a] = l2[a];
+            hi[a] = h2[a];
+          }
+          dmin = dl;
+          dmax = dh;
+          o1++;
+        }
+      }
+      const bool mine = valid && (lane >> 3) >= o0 && (lane >> 3) < o1;
+      const long long vol = volume(lo, hi);
+      if (dmax < 0) {
+        // no valid point in the run
+      } else if (dmin == dmax && vol <= CAP) {
+        const int nfp = (int)(CAP / vol < 5 ? CAP / vol : 5);  // fields per LDS pass
+        const PatchDev &D = P[dmin];  // uniform: scalar loads
+        const TB *T = stage_buf<TB>(D, sv, stage);
+        const uint32_t fs = (uint32_t)D.fstride, dsy = (uint32_t)D.pitch, dsz = (uint32_t)D.slab;
+        const int dn0 = D.n[0], dn1 = D.n[1], dn2 = D.n[2];
+        const bool per0 = D.periodic[0] != 0, per1 = D.periodic[1] != 0, per2 = D.periodic[2] != 0;
+        const int e0 = hi[0] - lo[0] + 1, e1 = hi[1] - lo[1] + 1;
+        const int e01 = e0 * e1;
+        const int v = (int)vol;
+        // flat box index q -> (x, row), row -> (b, cc) with float reciprocals: exact,
+        // since (q + 0.5) / e lies at least 1/(2e) from an integer and q < 2^14
+        const float ie0 = 1.0f / (float)e0, ie1 = 1.0f / (float)e1;
+        for (int f0 = 0; f0 < 5; f0 += nfp) {
+          const int nf = 5 - f0 < nfp ? 5 - f0 : nfp;
+          for (int q0 = tid; q0 < v; q0 += 4 * 64 * L2G_WAVES) {
+            TC tmp[4][5];
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+              const int q = q0 + m * 64 * L2G_WAVES;
+              if (q < v) {
+                const int row = (int)(((float)q + 0.5f) * ie0);
+                const int x = q - row * e0;
+                const int cc = (int)(((float)row + 0.5f) * ie1);
+                const int b = row - cc * e1;
+                // box cells lie inside [0, n) on every axis once periodic axes wrap
+                int ii = lo[0] + x, jj = lo[1] + b, kk = lo[2] + cc;
+                if (per0) ii = ((ii % dn0) + dn0) % dn0;
+                if (per1) jj = ((jj % dn1) + dn1) % dn1;
+                if (per2) kk = ((kk % dn2) + dn2) % dn2;
+                const uint32_t g =
+                    (uint32_t)(ii + PW_OX) + (uint32_t)(jj + PW_NG) * dsy + (uint32_t)(kk + PW_NG) * dsz;
+#pragma unroll
+                for (int f = 0; f < 5; f++)
+                  if (f < nf) tmp[m][f] = (TC)gld(T, (uint32_t)(f0 + f) * fs + g);
+              }
+            }
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+              const int q = q0 + m * 64 * L2G_WAVES;
+              if (q < v) {
+#pragma unroll
+                for (int f = 0; f < 5; f++)
+                  if (f < nf) box[f * v + q] = tmp[m][f];
+              }
+            }
+          }
+          __syncthreads();
+          if (mine) {
+            const TC *base = box + (s[2] - lo[2]) * e01 + (s[1] - lo[1]) * e0 + (s[0] - lo[0]);
+            for (int cc = wv; cc < Pts; cc += L2G_WAVES) {
+              TC wzv = (TC)0;
+#pragma unroll
+              for (int m = 0; m < Pts; m++) wzv = (m == cc) ? wzc[m] : wzv;
+              for (int f = 0; f < nf; f++) {
+                const TC *bl = base + f * v + cc * e01;
+                TC w[Pts][Pts];
+#pragma unroll
+                for (int b = 0; b < Pts; b++)
+#pragma unroll
+                  for (int a = 0; a < Pts; a++) w[b][a] = bl[b * e0 + a];
+                TC layer = (TC)0;
+#pragma unroll
+                for (int b = 0; b < Pts; b++) {
+                  TC part = (TC)0;
+#pragma unroll
+                  for (int a = 0; a < Pts; a++) part += wxc[a] * w[b][a];
+                  layer += wyc[b] * part;
+                }
+#pragma unroll
+                for (int m = 0; m < 5; m++)
+                  if (m == f0 + f) acc[m] += wzv * layer;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      } else {
+        // cooperative gather from global memory; wave wv takes every L2G_WAVES-th point
+        unsigned long long todo = __ballot(mine);
+        int rank = 0;
+        auto next_point = [&]() -> int {
+          while (todo) {
+            const int p = __ffsll((long long)todo) - 1;
+            todo &= todo - 1ull;
+            if (rank++ % L2G_WAVES == wv) return p;
+          }
+          return -1;
+        };
+        auto taps = [&](int pnt, TC out[5]) {
+          const int dd = bcast_i(d, pnt);
+          const int s0 = bcast_i(s[0], pnt), s1 = bcast_i(s[1], pnt), s2 = bcast_i(s[2], pnt);
+          TC wxa = (TC)0, wyb = (TC)0, wzp[Pts];
+#pragma unroll
+          for (int m = 0; m < Pts; m++) {
+            const TC bx = bcast_t(wxc[m], pnt), by = bcast_t(wyc[m], pnt);
+            wxa = (m == la) ? bx : wxa;
+            wyb = (m == lb) ? by : wyb;
+            wzp[m] = bcast_t(wzc[m], pnt);
+          }
+          const PatchDev &D = P[dd];
+          const TB *T = stage_buf<TB>(D, sv, stage);
+          const uint32_t fs = (uint32_t)D.fstride, dsy = (uint32_t)D.pitch, dsz = (uint32_t)D.slab;
+          const int dn0 = D.n[0], dn1 = D.n[1], dn2 = D.n[2];
+          const bool per0 = D.periodic[0] != 0, per1 = D.periodic[1] != 0, per2 = D.periodic[2] != 0;
+#pragma unroll
+          for (int f = 0; f < 5; f++) out[f] = (TC)0;
+          if (tap_lane) {
+            const TC wab = wxa * wyb;
+            int ii = s0 + la, jj = s1 + lb;
+            if (per0) ii = ((ii % dn0) + dn0) % dn0;
+            if (per1) jj = ((jj % dn1) + dn1) % dn1;
+            const uint32_t xy = (uint32_t)(ii + PW_OX) + (uint32_t)(jj + PW_NG) * dsy;
+            uint32_t xs[Pts];
+            TC wvv[Pts];
+#pragma unroll
+            for (int cc = 0; cc < Pts; cc++) {
+              int kk = s2 + cc;
+              if (per2) kk = ((kk % dn2) + dn2) % dn2;
+              xs[cc] = xy + (uint32_t)(kk + PW_NG) * dsz;
+              wvv[cc] = wab * wzp[cc];
+            }
+#pragma unroll
+            for (int cc = 0; cc < Pts; cc++)
+#pragma unroll
+              for (int f = 0; f < 5; f++) out[f] += wvv[cc] * (TC)gld(T, f * fs + xs[cc]);
+          }
+        };
+        for (;;) {
+          const int p0 = next_point();
+          if (p0 < 0) break;
+          const int p1 = next_point();
+          TC a0[5], a1[5];
+          taps(p0, a0);
+          if (p1 >= 0) taps(p1, a1);
+          else {
+#pragma unroll
+            for (int f = 0; f < 5; f++) a1[f] = (TC)0;
+          }
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+            for (int f = 0; f < 5; f++) {
+              a0[f] += __shfl_xor(a0[f], off);
+              a1[f] += __shfl_xor(a1[f], off);
+            }
+          if (lane == p0) {
+#pragma unroll
+            for (int f = 0; f < 5; f++) acc[f] = a0[f];
+          }
+          if (lane == p1) {
+#pragma unroll
+            for (int f = 0; f < 5; f++) acc[f] = a1[f];
+          }
+        }
+      }
+      o0 = o1;
+    }
+    // partial sums of waves 1.. meet those of wave 0 in LDS
+    if (wv > 0) {
+#pragma unroll
+      for (int f = 0; f < 5; f++) red[wv - 1][f][lane] = acc[f];
+    }
+    __syncthreads();
+    if (wv == 0 && have) {
+#pragma unroll
+      for (int f = 0; f < 5; f++)
+        for (int w2 = 0; w2 < L2G_WAVES - 1; w2++) acc[f] += red[w2][f][lane];
       if (valid) {
         const PatchDev &D = P[d];
-        double in4[4] = {(double)res[1], (double)res[2], (double)res[3], (double)res[4]}, G[3], pit, o4[4], out[5];
+        double in4[4] = {(double)acc[1], (double)acc[2], (double)acc[3], (double)acc[4]}, G[3], pit, o4[4], out[5];
+        const double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
         patch_to_bg(D, pose[d], xd, in4, pit, G);
         bg_to_patch(G0, pose[0], X, pit, G, o4);
-        out[0] = (double)res[0];
+        out[0] = (double)acc[0];
         for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
         const long long dst = cell_index(G0, i, j, k);
         for (int f = 0; f < 5; f++) TG[f * G0.fstride + dst] = (TB)out[f];
@@ -691,6 +915,7 @@ __global__ __launch_bounds__(256) void k_l2g_coop(const PatchDev *__restrict__ P
         fb[slot] = FallbackRec{0, 1, (uint32_t)c};
       }
     }
+    __syncthreads();
   }
 }
 
@@ -1227,10 +1452,12 @@ void launch_l2g_order(hipStream_t s, const L2GOrderArgs &a) {
   hipLaunchKernelGGL(k_fill_value<int>, dim3(nblk(a.nbuckets, 256) < 4096 ? nblk(a.nbuckets, 256) : 4096), dim3(256), 0,
                      s, a.cnt, (long long)a.nbuckets, 0);
   hipLaunchKernelGGL(k_bucket_count, dim3(1024), dim3(256), 0, s, a.P, a.pose, (const int32_t *)a.list, a.count,
-                     a.cover, a.cnt, a.ebkt, a.erank);
+                     a.cover, a.rank, a.cnt, a.ebkt, a.erank);
   hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, (const int *)a.cnt, a.off, a.nbuckets);
   hipLaunchKernelGGL(k_bucket_scatter, dim3(1024), dim3(256), 0, s, (const int32_t *)a.list, a.count,
                      (const int *)a.ebkt, (const int *)a.erank, (const int *)a.off, a.sorted);
+  hipLaunchKernelGGL(k_bucket_sort, dim3(a.nbuckets), dim3(256), 0, s, (const int32_t *)a.sorted, (const int *)a.cnt,
+                     (const int *)a.off, a.nbuckets, a.out);
 }
 
 void launch_finalize(hipStream_t s, const FinalizeArgs &a) {
@@ -1261,10 +1488,10 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
   }
   if (l2g) {
     if (a.Pts == 5)
-      hipLaunchKernelGGL((k_l2g_coop<TB, TC, 5>), dim3(L2G_BLOCKS), dim3(256), 0, s, a.P, a.pose, a.efflist,
+      hipLaunchKernelGGL((k_l2g_box<TB, TC, 5>), dim3(L2G_BLOCKS), dim3(64 * L2G_WAVES), 0, s, a.P, a.pose, a.efflist,
                          a.effcount, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count);
     else
-      hipLaunchKernelGGL((k_l2g_coop<TB, TC, 6>), dim3(L2G_BLOCKS), dim3(256), 0, s, a.P, a.pose, a.efflist,
+      hipLaunchKernelGGL((k_l2g_box<TB, TC, 6>), dim3(L2G_BLOCKS), dim3(64 * L2G_WAVES), 0, s, a.P, a.pose, a.efflist,
                          a.effcount, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count);
   }
   hipLaunchKernelGGL(k_fallback<TB>, dim3(64), dim3(256), 0, s, a.P, a.pose, a.fb, a.fb_count, a.sv, a.stage, a.ex,
