@@ -45,8 +45,10 @@ struct pw_context {
   GhostRec *dLower = nullptr;
   int nLower = 0, nLowerGlobal = 0;
   hipStream_t stream2 = nullptr;  // second branch of the overlapped step
+  hipStream_t stream3 = nullptr;  // third branch: the next step's cover flags and lists
   hipEvent_t evFork = nullptr, evG[4] = {nullptr, nullptr, nullptr, nullptr},
              evL[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t evGhL = nullptr, evGhG = nullptr, evNext = nullptr;
   GBrick *dBricks = nullptr;
   int nBricks = 0;
   int32_t *efflist = nullptr, *effsorted = nullptr;
@@ -387,7 +389,7 @@ pw_status set_time(pw_context *c, double *dptr, double t) {
   return PW_OK;
 }
 
-void enqueue_flags(pw_context *c, const PoseDev *pose_slot) {
+void enqueue_flags(pw_context *c, const PoseDev *pose_slot, hipStream_t st) {
   FlagsArgs a;
   a.P = c->dP;
   a.pose = pose_slot;
@@ -402,12 +404,16 @@ void enqueue_flags(pw_context *c, const PoseDev *pose_slot) {
   for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
   a.buffer = c->cfg.buffer_width;
   a.err = c->dErr;
-  launch_flags(c->stream, a);
+  launch_flags(st, a);
 }
 
-void enqueue_post_flags(pw_context *c, const PoseDev *pose_slot) {
+// Lists derived from the flags just computed (flag_new, cover_new): effective
+// ghosts in donor-bucket order and donor validity.  They replace the lists of
+// the running step, so they are enqueued after its last ghost fill and before
+// the flags are made current by the finalize kernel.
+void enqueue_post_flags(pw_context *c, const PoseDev *pose_slot, hipStream_t st) {
   PostFlagsArgs a;
-  a.flag = c->flag_cur;
+  a.flag = c->flag_new;
   a.efflist = c->efflist;
   a.effcount = c->effcount;
   a.dvalid[0] = c->dvalid[0];
@@ -417,13 +423,13 @@ void enqueue_post_flags(pw_context *c, const PoseDev *pose_slot) {
   a.t1 = c->t1;
   a.t2 = c->t2;
   for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
-  launch_post_flags(c->stream, a);
+  launch_post_flags(st, a);
   L2GOrderArgs o;
   o.P = c->dP;
   o.pose = pose_slot;
   o.list = c->efflist;
   o.count = c->effcount;
-  o.cover = c->cover_cur;
+  o.cover = c->cover_new;
   o.nbuckets = c->nBuckets;
   o.cnt = c->bkCnt;
   o.rank = c->bkRank;
@@ -432,7 +438,7 @@ void enqueue_post_flags(pw_context *c, const PoseDev *pose_slot) {
   o.erank = c->eRank;
   o.sorted = c->effsorted;
   o.out = c->efflist;  // the unordered list is not needed once scattered
-  launch_l2g_order(c->stream, o);
+  launch_l2g_order(st, o);
 }
 
 void enqueue_finalize(pw_context *c, const PoseDev *pose_slot, int mode) {
@@ -576,36 +582,47 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
 // One step as two interleaved chains on two streams: the local chain
 // (global->local fill, local stage kernels) and the global chain (local->global
 // fill, outer ghosts, global stage kernel).  Stage s of one chain waits for
-// stage s-1 of the other, whose output it interpolates from.
+// stage s-1 of the other, whose output it interpolates from.  A third stream
+// computes the cover flags of the next step (they depend on the poses at
+// t_{n+1} only) while the stages run, and their lists once the last ghost fill
+// of this step is done; the uncover fill and the swap of the flags follow the
+// last stage.
 void enqueue_step_overlap(pw_context *c, double dt) {
   int np = (int)c->hp.size();
-  hipStream_t X = c->stream, Y = c->stream2;
+  hipStream_t X = c->stream, Y = c->stream2, Z = c->stream3;
   launch_pose(X, c->dP, np, c->dT, dt, c->dPose);
   (void)hipEventRecord(c->evFork, X);
   (void)hipStreamWaitEvent(Y, c->evFork, 0);
+  (void)hipStreamWaitEvent(Z, c->evFork, 0);
+  enqueue_flags(c, c->dPose + 2 * np, Z);
   static const int slot_of_stage[4] = {0, 1, 1, 2};
   static const double tmul[4] = {0.0, 0.5, 0.5, 1.0};
   for (int s = 0; s < 4; s++) {
     const PoseDev *ps = c->dPose + slot_of_stage[s] * np;
     if (s > 0) (void)hipStreamWaitEvent(X, c->evG[s - 1], 0);
     enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X);
+    if (s == 3) (void)hipEventRecord(c->evGhL, X);
     enqueue_stage_part(c, s, ps, dt, 2, X);
     (void)hipEventRecord(c->evL[s], X);
     if (s > 0) (void)hipStreamWaitEvent(Y, c->evL[s - 1], 0);
     enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, Y);
+    if (s == 3) (void)hipEventRecord(c->evGhG, Y);
     enqueue_stage_part(c, s, ps, dt, 1, Y);
     (void)hipEventRecord(c->evG[s], Y);
   }
+  (void)hipStreamWaitEvent(Z, c->evGhL, 0);
+  (void)hipStreamWaitEvent(Z, c->evGhG, 0);
+  enqueue_post_flags(c, c->dPose + 2 * np, Z);
+  (void)hipEventRecord(c->evNext, Z);
   (void)hipStreamWaitEvent(X, c->evG[3], 0);
+  (void)hipStreamWaitEvent(X, c->evNext, 0);
   launch_advance_time(X, c->dT, dt, (long long *)c->dCounters);
-  enqueue_flags(c, c->dPose + 2 * np);
   enqueue_finalize(c, c->dPose + 2 * np, 1);
-  enqueue_post_flags(c, c->dPose + 2 * np);
 }
 
 void enqueue_step(pw_context *c, double dt) {
   int np = (int)c->hp.size();
-  if (has_locals(c) && c->cfg.schedule == PW_SCHED_BATCHED && !c->timing && c->stream2) {
+  if (has_locals(c) && c->cfg.schedule == PW_SCHED_BATCHED && !c->timing && c->stream2 && c->stream3) {
     enqueue_step_overlap(c, dt);
     return;
   }
@@ -630,11 +647,11 @@ void enqueue_step(pw_context *c, double dt) {
   if (has_locals(c)) {
     {
       Timed tm(c, PW_K_FLAGS);
-      enqueue_flags(c, c->dPose + 2 * np);
+      enqueue_flags(c, c->dPose + 2 * np, c->stream);
+      enqueue_post_flags(c, c->dPose + 2 * np, c->stream);
     }
     Timed tm(c, PW_K_FINALIZE);
     enqueue_finalize(c, c->dPose + 2 * np, 1);
-    enqueue_post_flags(c, c->dPose + 2 * np);
   }
 }
 
@@ -645,9 +662,9 @@ pw_status ensure_flags(pw_context *c) {
   int np = (int)c->hp.size();
   if (has_locals(c)) {
     launch_pose(c->stream, c->dP, np, c->dT, 0.0, c->dPose);
-    enqueue_flags(c, c->dPose);
+    enqueue_flags(c, c->dPose, c->stream);
+    enqueue_post_flags(c, c->dPose, c->stream);
     enqueue_finalize(c, c->dPose, 0);
-    enqueue_post_flags(c, c->dPose);
     int err = 0;
     HIPCHK(c, hipMemcpyAsync(&err, c->dErr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -703,7 +720,11 @@ pw_status pw_create(const pw_config *cfg, pw_context **out) {
     c->own_stream = true;
   }
   if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->evFork, hipEventDisableTiming) != hipSuccess) {
+      hipStreamCreateWithFlags(&c->stream3, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->evFork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->evGhL, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->evGhG, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->evNext, hipEventDisableTiming) != hipSuccess) {
     pw_destroy(c);
     return PW_EDEVICE;
   }
@@ -1144,6 +1165,8 @@ const char *pw_last_error(const pw_context *c) { return c ? c->err.c_str() : "nu
 void pw_destroy(pw_context *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->stream2) (void)hipStreamSynchronize(c->stream2);
+  if (c->stream3) (void)hipStreamSynchronize(c->stream3);
   if (c->gexec) {
     (void)hipGraphExecDestroy(c->gexec);
     (void)hipGraphDestroy(c->graph);
@@ -1156,7 +1179,11 @@ void pw_destroy(pw_context *c) {
     (void)hipStreamSynchronize(c->stream2);
     (void)hipStreamDestroy(c->stream2);
   }
+  if (c->stream3) (void)hipStreamDestroy(c->stream3);
   if (c->evFork) (void)hipEventDestroy(c->evFork);
+  if (c->evGhL) (void)hipEventDestroy(c->evGhL);
+  if (c->evGhG) (void)hipEventDestroy(c->evGhG);
+  if (c->evNext) (void)hipEventDestroy(c->evNext);
   for (int s = 0; s < 4; s++) {
     if (c->evG[s]) (void)hipEventDestroy(c->evG[s]);
     if (c->evL[s]) (void)hipEventDestroy(c->evL[s]);

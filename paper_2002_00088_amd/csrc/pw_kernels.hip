@@ -962,19 +962,19 @@ __global__ void k_fallback(const PatchDev *__restrict__ P, const PoseDev *__rest
 }
 
 // End of step: cells live now but not live during the step get u_{n+1}
-// interpolated from the covering local patch; deactivated cells are poisoned;
-// the new flags become current.  mode 0: first flags (no uncover fill).
-__global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, uint8_t *flag_cur, const uint8_t *flag_new,
-                           int32_t *cover_cur, int32_t *cover_new, int nsv, const int *Pts, const ExactDev *ex,
-                           const double *vs, const double *tdev, int mode, unsigned long long *counters) {
+// interpolated from the covering local patch; cells that become deactivated are
+// poisoned (nothing writes a deactivated cell, so it stays poisoned); the new
+// flags become current.  mode 0: first flags (no uncover fill, every deactivated
+// cell poisoned).  Four cells per thread: flags and cover ids move as 4-byte and
+// 16-byte words.
+__device__ inline void finalize_cell(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, long long c,
+                                     uint8_t fo, uint8_t fn, int32_t co, int32_t cn, int nsv, const int *Pts,
+                                     const ExactDev *ex, const double *vs, const double *tdev, int mode,
+                                     unsigned long long *counters) {
   const PatchDev &G0 = P[0];
-  long long total = (long long)G0.n[0] * G0.n[1] * G0.n[2];
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= total) return;
-  uint8_t fo = flag_cur[c], fn = flag_new[c];
-  int32_t cn = cover_new[c], co = cover_cur[c];
-  int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]), k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
-  long long x = cell_index(G0, i, j, k);
+  const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]),
+            k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
+  const long long x = cell_index(G0, i, j, k);
   if (mode == 1 && fo != LIVE && fn == LIVE) {
     int d = cn >= 1 ? cn : co;
     const PatchDev &D = P[d >= 1 ? d : 0];
@@ -995,7 +995,7 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
         for (int f = 0; f < 5; f++) G0.us[sv][f * G0.fstride + x] = (float)out[f];
     }
   }
-  if (fn == DEACT) {
+  if (fn == DEACT && (mode == 0 || fo != DEACT)) {
     for (int sv = 0; sv < nsv; sv++) {
       if (!(G0.sv_mask & (1u << sv))) continue;
       for (int f = 0; f < 5; f++) G0.u[sv][f * G0.fstride + x] = NAN;
@@ -1003,9 +1003,41 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
         for (int f = 0; f < 5; f++) G0.us[sv][f * G0.fstride + x] = NAN;
     }
   }
-  flag_cur[c] = fn;
-  cover_cur[c] = cn;
-  cover_new[c] = -1;
+}
+
+__global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, uint8_t *flag_cur,
+                           const uint8_t *flag_new, int32_t *cover_cur, int32_t *cover_new, int nsv, const int *Pts,
+                           const ExactDev *ex, const double *vs, const double *tdev, int mode,
+                           unsigned long long *counters) {
+  const PatchDev &G0 = P[0];
+  const long long total = (long long)G0.n[0] * G0.n[1] * G0.n[2];
+  const long long c0 = 4 * ((long long)blockIdx.x * blockDim.x + threadIdx.x);
+  if (c0 >= total) return;
+  if (c0 + 4 <= total) {
+    const uchar4 fo4 = *(const uchar4 *)(flag_cur + c0), fn4 = *(const uchar4 *)(flag_new + c0);
+    const int4 co4 = *(const int4 *)(cover_cur + c0), cn4 = *(const int4 *)(cover_new + c0);
+    const uint8_t fo[4] = {fo4.x, fo4.y, fo4.z, fo4.w}, fn[4] = {fn4.x, fn4.y, fn4.z, fn4.w};
+    const int32_t co[4] = {co4.x, co4.y, co4.z, co4.w}, cn[4] = {cn4.x, cn4.y, cn4.z, cn4.w};
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+      const bool uncover = mode == 1 && fo[m] != LIVE && fn[m] == LIVE;
+      const bool poison = fn[m] == DEACT && (mode == 0 || fo[m] != DEACT);
+      if (uncover || poison)
+        finalize_cell(P, pose, c0 + m, fo[m], fn[m], co[m], cn[m], nsv, Pts, ex, vs, tdev, mode, counters);
+    }
+    *(uchar4 *)(flag_cur + c0) = fn4;
+    *(int4 *)(cover_cur + c0) = cn4;
+    *(int4 *)(cover_new + c0) = make_int4(-1, -1, -1, -1);
+  } else {
+    for (long long c = c0; c < total; c++) {
+      const uint8_t fo = flag_cur[c], fn = flag_new[c];
+      const int32_t co = cover_cur[c], cn = cover_new[c];
+      finalize_cell(P, pose, c, fo, fn, co, cn, nsv, Pts, ex, vs, tdev, mode, counters);
+      flag_cur[c] = fn;
+      cover_cur[c] = cn;
+      cover_new[c] = -1;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1462,7 +1494,7 @@ void launch_l2g_order(hipStream_t s, const L2GOrderArgs &a) {
 
 void launch_finalize(hipStream_t s, const FinalizeArgs &a) {
   long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
-  hipLaunchKernelGGL(k_finalize, dim3(nblk(tot, 256)), dim3(256), 0, s, a.P, a.pose, a.flag_cur, a.flag_new,
+  hipLaunchKernelGGL(k_finalize, dim3(nblk((tot + 3) / 4, 256)), dim3(256), 0, s, a.P, a.pose, a.flag_cur, a.flag_new,
                      a.cover_cur, a.cover_new, a.nsv, a.Pts, a.ex, a.vs, a.tdev, a.mode, a.counters);
 }
 
