@@ -837,6 +837,13 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
   p.slab = (long long)p.pitch * p.rows;
   p.fstride = p.slab * p.slabs;
   long long nel = 5 * p.fstride;
+  if (p.coord != CART) {
+    const int nt = 2 * (p.n[1] + p.n[2] + 4 * PW_NG);
+    double *tab = (double *)dalloc(c, sizeof(double) * nt);
+    if (!tab) return fail(c, PW_ENOMEM, "device allocation failed");
+    launch_trig_table(c->stream, p.n[1], p.n[2], p.lo[1], p.dx[1], p.lo[2], p.dx[2], tab);
+    p.trig = tab;
+  }
   for (int s = 0; s < c->cfg.n_state_vectors; s++) {
     if (!(d->sv_mask & (1u << s))) continue;
     p.u[s] = (double *)dalloc(c, sizeof(double) * nel);

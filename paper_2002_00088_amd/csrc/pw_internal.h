@@ -38,6 +38,9 @@ struct PatchDev {
   void *va[PW_MAXSV];
   void *vb[PW_MAXSV];
   float *us[PW_MAXSV];  // mixed precision: FP32 copy of u (stage-1 stencil input), else null
+  // spherical patches: sin, cos of theta_j (j = -3 .. n1+2) and of phi_k
+  // (k = -3 .. n2+2), laid out [sin th][cos th][sin ph][cos ph]; null otherwise
+  const double *trig;
 };
 
 // Pose of a patch at one stage time: centre, its first and second time
@@ -107,6 +110,37 @@ __device__ inline void sph_basis(double th, double ph, SphBasis &B) {
   B.ep[0] = -B.sp; B.ep[1] = B.cp; B.ep[2] = 0.0;
 }
 
+// The same basis at the grid angles theta_j, phi_k of a spherical patch, from
+// its tables (filled with sincos of the same angles).
+__device__ inline void sph_basis_grid(const PatchDev &p, int j, int k, SphBasis &B) {
+  const int t1 = p.n[1] + 2 * PW_NG, t2 = p.n[2] + 2 * PW_NG;
+  B.st = p.trig[j + PW_NG];
+  B.ct = p.trig[t1 + j + PW_NG];
+  B.sp = p.trig[2 * t1 + k + PW_NG];
+  B.cp = p.trig[2 * t1 + t2 + k + PW_NG];
+  B.er[0] = B.st * B.cp; B.er[1] = B.st * B.sp; B.er[2] = B.ct;
+  B.et[0] = B.ct * B.cp; B.et[1] = B.ct * B.sp; B.et[2] = -B.st;
+  B.ep[0] = -B.sp; B.ep[1] = B.cp; B.ep[2] = 0.0;
+}
+
+// The basis at the point y (patch-frame Cartesian, |y| = r > 0) without
+// trigonometry: sin th = rho / r, cos th = y_z / r, (cos ph, sin ph) = (y_x, y_y) / rho.
+__device__ inline void sph_basis_cart(const double y[3], double r, SphBasis &B) {
+  const double rho = sqrt(y[0] * y[0] + y[1] * y[1]);
+  B.st = rho / r;
+  B.ct = y[2] / r;
+  if (rho > 0.0) {
+    B.cp = y[0] / rho;
+    B.sp = y[1] / rho;
+  } else {
+    B.cp = 1.0;
+    B.sp = 0.0;
+  }
+  B.er[0] = B.st * B.cp; B.er[1] = B.st * B.sp; B.er[2] = B.ct;
+  B.et[0] = B.ct * B.cp; B.et[1] = B.ct * B.sp; B.et[2] = -B.st;
+  B.ep[0] = -B.sp; B.ep[1] = B.cp; B.ep[2] = 0.0;
+}
+
 // Forward map: numerical x' of patch p -> background X at pose ps.
 __device__ inline void fwd_map(const PatchDev &p, const PoseDev &ps, const double xp[3], double X[3]) {
   double y[3];
@@ -139,36 +173,78 @@ __device__ inline void inv_map(const PatchDev &p, const PoseDev &ps, const doubl
 // frame of p at x', return Pi_t^B and the background gradient G = d phi/dX.
 // (Pi_mu transforms with dx'/dX; for the spherical map the spatial part is the
 // usual gradient in the orthonormal basis.)
-__device__ inline void patch_to_bg(const PatchDev &p, const PoseDev &ps, const double xp[3], const double in[4],
-                                   double &pit, double G[3]) {
+__device__ inline void patch_to_bg_b(const PatchDev &p, const PoseDev &ps, double r, const SphBasis &B,
+                                     const double in[4], double &pit, double G[3]) {
   double gy[3];
   if (p.coord == CART) {
     gy[0] = in[1]; gy[1] = in[2]; gy[2] = in[3];
   } else {
-    SphBasis B;
-    sph_basis(xp[1], xp[2], B);
-    double fr = in[1], ft = in[2] / xp[0], fp = in[3] / (xp[0] * B.st);
+    double fr = in[1], ft = in[2] / r, fp = in[3] / (r * B.st);
     for (int a = 0; a < 3; a++) gy[a] = fr * B.er[a] + ft * B.et[a] + fp * B.ep[a];
   }
   for (int a = 0; a < 3; a++) G[a] = p.R[3 * a] * gy[0] + p.R[3 * a + 1] * gy[1] + p.R[3 * a + 2] * gy[2];
   pit = in[0] - (ps.cd[0] * G[0] + ps.cd[1] * G[1] + ps.cd[2] * G[2]);
 }
+__device__ inline void patch_to_bg(const PatchDev &p, const PoseDev &ps, const double xp[3], const double in[4],
+                                   double &pit, double G[3]) {
+  SphBasis B;
+  if (p.coord != CART) sph_basis(xp[1], xp[2], B);
+  patch_to_bg_b(p, ps, xp[0], B, in, pit, G);
+}
+// The same at the point of p that maps to background X (x' = its inverse map):
+// the spherical basis comes from the patch-frame Cartesian offset.
+__device__ inline void patch_to_bg_at(const PatchDev &p, const PoseDev &ps, const double X[3], const double xp[3],
+                                      const double in[4], double &pit, double G[3]) {
+  SphBasis B;
+  if (p.coord != CART) {
+    const double d[3] = {X[0] - ps.c[0], X[1] - ps.c[1], X[2] - ps.c[2]};
+    double y[3];
+    for (int b = 0; b < 3; b++) y[b] = p.R[b] * d[0] + p.R[3 + b] * d[1] + p.R[6 + b] * d[2];
+    sph_basis_cart(y, xp[0], B);
+  }
+  patch_to_bg_b(p, ps, xp[0], B, in, pit, G);
+}
 
 // Background one-form (Pi_t^B, G) -> numerical frame of p at x'.
-__device__ inline void bg_to_patch(const PatchDev &p, const PoseDev &ps, const double xp[3], double pit,
-                                   const double G[3], double out[4]) {
+__device__ inline void bg_to_patch_b(const PatchDev &p, const PoseDev &ps, double r, const SphBasis &B, double pit,
+                                     const double G[3], double out[4]) {
   double gy[3];
   for (int b = 0; b < 3; b++) gy[b] = p.R[b] * G[0] + p.R[3 + b] * G[1] + p.R[6 + b] * G[2];
   out[0] = pit + ps.cd[0] * G[0] + ps.cd[1] * G[1] + ps.cd[2] * G[2];
   if (p.coord == CART) {
     out[1] = gy[0]; out[2] = gy[1]; out[3] = gy[2];
   } else {
-    SphBasis B;
-    sph_basis(xp[1], xp[2], B);
     out[1] = B.er[0] * gy[0] + B.er[1] * gy[1] + B.er[2] * gy[2];
-    out[2] = xp[0] * (B.et[0] * gy[0] + B.et[1] * gy[1] + B.et[2] * gy[2]);
-    out[3] = xp[0] * B.st * (B.ep[0] * gy[0] + B.ep[1] * gy[1]);
+    out[2] = r * (B.et[0] * gy[0] + B.et[1] * gy[1] + B.et[2] * gy[2]);
+    out[3] = r * B.st * (B.ep[0] * gy[0] + B.ep[1] * gy[1]);
   }
+}
+__device__ inline void bg_to_patch(const PatchDev &p, const PoseDev &ps, const double xp[3], double pit,
+                                   const double G[3], double out[4]) {
+  SphBasis B;
+  if (p.coord != CART) sph_basis(xp[1], xp[2], B);
+  bg_to_patch_b(p, ps, xp[0], B, pit, G, out);
+}
+
+// Grid point c (numerical indices, ghosts included) of p: its background
+// position, and a background one-form carried to p there (table basis).
+__device__ inline void fwd_map_grid(const PatchDev &p, const PoseDev &ps, const int c[3], double X[3]) {
+  double y[3];
+  if (p.coord == CART) {
+    for (int a = 0; a < 3; a++) y[a] = xnum(p, a, c[a]);
+  } else {
+    SphBasis B;
+    sph_basis_grid(p, c[1], c[2], B);
+    const double r = xnum(p, 0, c[0]);
+    for (int a = 0; a < 3; a++) y[a] = r * B.er[a];
+  }
+  for (int a = 0; a < 3; a++) X[a] = ps.c[a] + p.R[3 * a] * y[0] + p.R[3 * a + 1] * y[1] + p.R[3 * a + 2] * y[2];
+}
+__device__ inline void bg_to_patch_grid(const PatchDev &p, const PoseDev &ps, const int c[3], double pit,
+                                        const double G[3], double out[4]) {
+  SphBasis B;
+  if (p.coord != CART) sph_basis_grid(p, c[1], c[2], B);
+  bg_to_patch_b(p, ps, xnum(p, 0, c[0]), B, pit, G, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,7 +372,7 @@ __device__ inline int lagrange_wt(double q, double *w) {
 #pragma unroll
   for (int m = P - 2; m >= 0; m--) suf[m] = suf[m + 1] * (t - (double)(m + 1));
 #pragma unroll
-  for (int m = 0; m < P; m++) w[m] = pre[m] * suf[m] / lagrange_den<P>(m);
+  for (int m = 0; m < P; m++) w[m] = pre[m] * suf[m] * (1.0 / lagrange_den<P>(m));
   return s;
 }
 

@@ -20,7 +20,9 @@
 #define DIAG_N 23
 #define BRICK_THREADS 192
 #define BRICK_LDS_BYTES 40960
-#define L2G_BLOCKS 2048
+#define L2G_BLOCKS 2048  // a multiple of 8
+#define L2G_RUN 4
+#define G2L_RUN 8
 #define L2G_WAVES 3
 #define L2G_LDS_BYTES 36864
 #define BUCKET_SORT_LDS 4096
@@ -157,6 +159,7 @@ void launch_ghosts(hipStream_t s, const GhostArgs &a);
 void launch_post_flags(hipStream_t s, const PostFlagsArgs &a);
 void launch_l2g_order(hipStream_t s, const L2GOrderArgs &a);
 void launch_stage(hipStream_t s, const StageArgs &a);
+void launch_trig_table(hipStream_t s, int n1, int n2, double lo1, double dx1, double lo2, double dx2, double *tab);
 void launch_fill_f64(hipStream_t s, double *p, long long n, double v);
 void launch_fill_f32(hipStream_t s, float *p, long long n, float v);
 void launch_fill_i32(hipStream_t s, int32_t *p, long long n, int32_t v);

@@ -183,7 +183,7 @@ __device__ inline bool interp_transform(const PatchDev &d, const PoseDev &psd, c
   TC v[5];
   if (!interp5<TB, TC>(d, T, gflag, P, xd, v)) return false;
   double in4[4] = {(double)v[1], (double)v[2], (double)v[3], (double)v[4]}, G[3], pit, o4[4];
-  patch_to_bg(d, psd, xd, in4, pit, G);
+  patch_to_bg_at(d, psd, X, xd, in4, pit, G);
   bg_to_patch(r, psr, xr, pit, G, o4);
   out[0] = (double)v[0];
   for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
@@ -407,6 +407,15 @@ __global__ __launch_bounds__(256) void k_bucket_sort(const int32_t *in, const in
   }
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).  Map
+// workgroup v to a work item so that every XCD receives runs of K consecutive
+// items: item = ((j / K) * 8 + x) * K + j % K with x = v mod 8, j = v / 8.  A
+// bijection of [0, 8 K m) for every m.
+__device__ __forceinline__ int xcd_spread(int v, int K) {
+  const int x = v & 7, j = v >> 3;
+  return ((j / K) * 8 + x) * K + (j % K);
+}
+
 // ---------------------------------------------------------------------------
 // Global -> local (Sec. 2.4.1).  One workgroup per brick of up to 8x8x3 ghost
 // cells of one face of a local patch.  Each thread locates its point in the
@@ -418,12 +427,16 @@ __global__ __launch_bounds__(256) void k_bucket_sort(const int32_t *in, const in
 // ---------------------------------------------------------------------------
 template <typename TB, typename TC, int Pts>
 __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose,
-                                                             const GBrick *bricks, int sv, int stage,
-                                                             const uint8_t *dvalid, unsigned long long *skips,
-                                                             FallbackRec *fb, int *fb_count) {
+                                                             const GBrick *bricks, int nbricks, int sv,
+                                                             int stage, const uint8_t *dvalid,
+                                                             unsigned long long *skips, FallbackRec *fb,
+                                                             int *fb_count) {
   __shared__ TC box[BRICK_LDS_BYTES / sizeof(TC)];
   __shared__ int blo[3], bhi[3];
-  const GBrick B = bricks[blockIdx.x];
+  // runs of G2L_RUN consecutive bricks (which share donor cells) on one XCD
+  const int bidx = xcd_spread(blockIdx.x, G2L_RUN);
+  if (bidx >= nbricks) return;
+  const GBrick B = bricks[bidx];
   const PatchDev &r = P[B.patch];
   const PatchDev &G0 = P[0];
   const int tid = threadIdx.x;
@@ -447,11 +460,10 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__r
   bool valid = false;
   int s[3] = {0, 0, 0};
   double wx[Pts], wy[Pts], wz[Pts];
-  double xr[3] = {0, 0, 0}, xd[3] = {0, 0, 0};
+  double xd[3] = {0, 0, 0};
   if (active && has_donor) {
     double X[3];
-    for (int a = 0; a < 3; a++) xr[a] = xnum(r, a, c[a]);
-    fwd_map(r, pose[B.patch], xr, X);
+    fwd_map_grid(r, pose[B.patch], c, X);
     inv_map(G0, pose[0], X, xd);
     double q[3];
     bool fin = true;
@@ -589,7 +601,7 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__r
   {
     double in4[4] = {(double)acc[1], (double)acc[2], (double)acc[3], (double)acc[4]}, G[3], pit, o4[4];
     patch_to_bg(G0, pose[0], xd, in4, pit, G);
-    bg_to_patch(r, pose[B.patch], xr, pit, G, o4);
+    bg_to_patch_grid(r, pose[B.patch], c, pit, G, o4);
     out[0] = (double)acc[0];
     for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
   }
@@ -641,7 +653,13 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
   const int la = lane % Pts, lb = lane / Pts;
   const bool tap_lane = lane < Pts * Pts;
   TB *TG = stage_buf<TB>(G0, sv, stage);
-  for (int g0 = blockIdx.x * 64; g0 < n; g0 += gridDim.x * 64) {
+  // runs of L2G_RUN consecutive groups (neighbouring donor boxes) on one XCD
+  const int ngroups = (n + 63) / 64;
+  const int nv = (ngroups + 8 * L2G_RUN - 1) / (8 * L2G_RUN) * (8 * L2G_RUN);
+  for (int vb = blockIdx.x; vb < nv; vb += gridDim.x) {
+    const int grp = xcd_spread(vb, L2G_RUN);
+    if (grp >= ngroups) continue;
+    const int g0 = grp * 64;
     if (tid < 64) {
       const int e = tid & 7;
       obox[tid >> 3][e] = e < 3 ? (1 << 30) : (e < 6 ? -(1 << 30) : (e == 6 ? (1 << 30) : -1));
@@ -903,7 +921,7 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
         const PatchDev &D = P[d];
         double in4[4] = {(double)acc[1], (double)acc[2], (double)acc[3], (double)acc[4]}, G[3], pit, o4[4], out[5];
         const double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
-        patch_to_bg(D, pose[d], xd, in4, pit, G);
+        patch_to_bg_at(D, pose[d], X, xd, in4, pit, G);
         bg_to_patch(G0, pose[0], X, pit, G, o4);
         out[0] = (double)acc[0];
         for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
@@ -1228,10 +1246,8 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
           bb_[2] = (TC)(2.0 * ps.b[1] * ps.b[2]);
         } else {
           double r = p.lo[0] + (i + 0.5) * p.dx[0];
-          double th = p.lo[1] + (j + 0.5) * p.dx[1];
-          double ph = p.lo[2] + (k + 0.5) * p.dx[2];
           SphBasis Bs;
-          sph_basis(th, ph, Bs);
+          sph_basis_grid(p, j, k, Bs);
           double ir = 1.0 / r, irs = ir / Bs.st, cot = Bs.ct / Bs.st;
           double br = Bs.er[0] * ps.b[0] + Bs.er[1] * ps.b[1] + Bs.er[2] * ps.b[2];
           double bt = Bs.et[0] * ps.b[0] + Bs.et[1] * ps.b[1] + Bs.et[2] * ps.b[2];
@@ -1349,6 +1365,23 @@ template <typename T>
 __global__ void k_fill_value(T *ptr, long long n, T val) {
   long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (; q < n; q += (long long)gridDim.x * blockDim.x) ptr[q] = val;
+}
+
+// sin and cos of the grid angles of a spherical patch (see PatchDev::trig).
+__global__ void k_trig_table(int n1, int n2, double lo1, double dx1, double lo2, double dx2, double *tab) {
+  const int t1 = n1 + 2 * PW_NG, t2 = n2 + 2 * PW_NG;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < t1) {
+    double sn, cs;
+    sincos(lo1 + ((q - PW_NG) + 0.5) * dx1, &sn, &cs);
+    tab[q] = sn;
+    tab[t1 + q] = cs;
+  } else if (q < t1 + t2) {
+    double sn, cs;
+    sincos(lo2 + ((q - t1 - PW_NG) + 0.5) * dx2, &sn, &cs);
+    tab[2 * t1 + (q - t1)] = sn;
+    tab[2 * t1 + t2 + (q - t1)] = cs;
+  }
 }
 
 __global__ void k_unpack(const PatchDev *P, int pid, int sv, const double *src) {
@@ -1511,12 +1544,13 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
   if (!g2l && !l2g) return;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
   if (g2l) {
+    const int bchunk = (a.n_bricks + 8 * G2L_RUN - 1) / (8 * G2L_RUN);
     if (a.Pts == 5)
-      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 5>), dim3(a.n_bricks), dim3(BRICK_THREADS), 0, s, a.P, a.pose,
-                         a.bricks, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
+      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 5>), dim3(8 * G2L_RUN * bchunk), dim3(BRICK_THREADS), 0, s, a.P,
+                         a.pose, a.bricks, a.n_bricks, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
     else
-      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 6>), dim3(a.n_bricks), dim3(BRICK_THREADS), 0, s, a.P, a.pose,
-                         a.bricks, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
+      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 6>), dim3(8 * G2L_RUN * bchunk), dim3(BRICK_THREADS), 0, s, a.P,
+                         a.pose, a.bricks, a.n_bricks, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
   }
   if (l2g) {
     if (a.Pts == 5)
@@ -1591,6 +1625,10 @@ void launch_stage(hipStream_t s, const StageArgs &a) {
 #undef PW_STAGE
 }
 
+void launch_trig_table(hipStream_t s, int n1, int n2, double lo1, double dx1, double lo2, double dx2, double *tab) {
+  const int n = n1 + n2 + 4 * PW_NG;
+  hipLaunchKernelGGL(k_trig_table, dim3(nblk(n, 256)), dim3(256), 0, s, n1, n2, lo1, dx1, lo2, dx2, tab);
+}
 void launch_fill_f64(hipStream_t s, double *p, long long n, double v) {
   if (n > 0) hipLaunchKernelGGL(k_fill_value<double>, dim3(nblk(n, 256) < 4096 ? nblk(n, 256) : 4096), dim3(256), 0, s, p, n, v);
 }
