@@ -1179,8 +1179,45 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
         for (int f = 0; f < 5; f++) phB[m][f] = hval[m] ? (TC)gld(in, f * fs + hoff[m] + zb) : (TC)0;
     }
   };
-  prefetch(0);
-  for (int it = 0; it < nz + 6; it++) {
+  // Warm-up, all at once instead of six serial plane steps: the own-column
+  // values of planes z0-3 .. z0+2 go to the z-window, and D_x phi, D_y phi at
+  // planes z0-2 .. z0+1 are formed from phi planes staged with their halo rings
+  // (in the second centre-plane buffer, first written two iterations later).
+  {
+    TC wh[4][2];
+#pragma unroll
+    for (int w = 0; w < 6; w++) {
+      const uint32_t zo = (uint32_t)(z0 - 3 + w + PW_NG) * sz - PW_NG * sz;
+#pragma unroll
+      for (int f = 0; f < 5; f++) q[f][w + 1] = inpad ? (TC)gld(in, f * fs + col + zo) : (TC)0;
+    }
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      const uint32_t zo = (uint32_t)(z0 - 2 + w + PW_NG) * sz - PW_NG * sz;
+#pragma unroll
+      for (int m = 0; m < 2; m++) wh[w][m] = hval[m] ? (TC)gld(in, hoff[m] + zo) : (TC)0;
+    }
+    prefetch(6);
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      TC *A_ = Bc[1][w];
+      if (inpad) A_[own] = q[0][w + 2];
+#pragma unroll
+      for (int m = 0; m < 2; m++)
+        if (hval[m]) A_[hslot[m]] = wh[w][m];
+    }
+    __syncthreads();
+    if (icol) {
+#pragma unroll
+      for (int w = 0; w < 4; w++) {
+        const TC *A_ = Bc[1][w];
+        dqx[w + 1] = ((A_[own - 2] - A_[own + 2]) + (TC)8 * (A_[own + 1] - A_[own - 1])) * i12dx[0];
+        dqy[w + 1] =
+            ((A_[own - 2 * ST_PX] - A_[own + 2 * ST_PX]) + (TC)8 * (A_[own + ST_PX] - A_[own - ST_PX])) * i12dx[1];
+      }
+    }
+  }
+  for (int it = 6; it < nz + 6; it++) {
     const int zn = z0 - 3 + it;
     const int buf = it & 1;
 #pragma unroll
