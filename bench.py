@@ -26,11 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per live cell per stage kernel launch (five fields):
-# stage 1 reads u, writes acc and v2; stages 2-3 read v_s, u, acc and write acc,
-# v_{s+1}; stage 4 reads v4, acc and writes u.  FP64 state/accumulator always,
-# stage buffers FP64 (fp64) or FP32 (mixed).
-STAGE_BYTES = {"fp64": [120, 200, 200, 120], "mixed": [100, 160, 160, 100]}
+# Algorithmic bytes per live cell per stage kernel launch (five fields).
+# FP64 path: stage 1 reads u, writes acc and v2; stages 2-3 read v_s, u, acc and
+# write acc, v_{s+1}; stage 4 reads v4, acc and writes u (all 8-byte values).
+# Mixed path (4-byte stage values, 4-byte increment, FP64 state): stage 1 reads
+# the FP32 copy of u, writes the increment and v2; stages 2-3 read v_s, the copy
+# of u and the increment and write the increment and v_{s+1}; stage 4 reads v4,
+# the increment and u and writes u and its FP32 copy.
+STAGE_BYTES = {"fp64": [120, 200, 200, 120], "mixed": [60, 100, 100, 140]}
 
 
 def kernel_source_hash():

@@ -1102,6 +1102,10 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
   TOUT *vout = (TOUT *)(STAGE == 1 ? p.vb[sv] : p.va[sv]);
   double *U = p.u[sv];
   double *Acc = p.acc[sv];
+  // mixed path: the accumulator holds the FP32 increment dt sum_l b_l K_l, and
+  // the FP32 copy of u_n is the base of the stage values
+  constexpr bool MIX = sizeof(TOUT) == 4;
+  float *AccF = (float *)p.acc[sv];
   // 32-bit element offsets (a field of one patch holds < 2^31 elements)
   const uint32_t fs = (uint32_t)p.fstride, sz = (uint32_t)p.slab;
   const uint32_t col = (uint32_t)cell_index(p, i, j, 0);
@@ -1148,6 +1152,7 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
   const bool moving = (ps.b[0] != 0.0) || (ps.b[1] != 0.0) || (ps.b[2] != 0.0);
   const double bdt = STAGE == 0 ? dt / 6.0 : (STAGE == 3 ? dt / 6.0 : dt / 3.0);
   const double adt = STAGE == 2 ? dt : dt / 2.0;
+  const float bdtf = (float)bdt, adtf = (float)adt;
   TC q[5][7];
   TC dqx[5], dqy[5];
 #pragma unroll
@@ -1235,14 +1240,25 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
       for (int m = 0; m < 2; m++)
         if (hval[m]) A_[hslot[m]] = phA[m];
     }
-    // FP64 state of the centre cell for the RK update, issued before the barrier
+    // centre-cell data of the RK update, issued before the barrier.  FP64 path:
+    // u_n (stages 1-3) and the accumulator (stages 2-4).  Mixed path: the FP32
+    // copy of u_n (stages 2-3; stage 1 has it in the z-window), the FP32
+    // increment (stages 2-4), and u_n itself in stage 4 only.
     double cu[5], ca[5];
+    float cus[5], cd[5];
     if (do_c && icol) {
       const uint32_t xc = col + (uint32_t)(zn - 3) * sz;
 #pragma unroll
       for (int f = 0; f < 5; f++) {
-        cu[f] = STAGE != 3 ? gld(U, f * fs + xc) : 0.0;
-        ca[f] = STAGE != 0 ? gld(Acc, f * fs + xc) : 0.0;
+        if (MIX) {
+          cus[f] = (STAGE == 1 || STAGE == 2) ? gld((const float *)Us, f * fs + xc) : 0.0f;
+          cd[f] = STAGE != 0 ? gld((const float *)AccF, f * fs + xc) : 0.0f;
+          cu[f] = STAGE == 3 ? gld(U, f * fs + xc) : 0.0;
+          ca[f] = 0.0;
+        } else {
+          cu[f] = STAGE != 3 ? gld(U, f * fs + xc) : 0.0;
+          ca[f] = STAGE != 0 ? gld(Acc, f * fs + xc) : 0.0;
+        }
       }
     }
     if (do_c) {
@@ -1373,21 +1389,36 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
 #pragma unroll
         for (int a = 0; a < 3; a++) K[2 + a] = dpi[a] + kof[2 + a];
         const uint32_t x0 = col + (uint32_t)k * sz;
-        // classic RK4 (Table rk4): acc holds u_n + dt sum_l b_l K_l, v_{s+1} = u_n + a dt K_s
+        // classic RK4 (Table rk4): v_{s+1} = u_n + a_s dt K_s.  FP64 path: acc holds
+        // u_n + dt sum_l b_l K_l.  Mixed path: acc holds the FP32 increment
+        // dt sum_l b_l K_l, and u_{n+1} = u_n + increment + b_4 dt K_4 in FP64.
 #pragma unroll
         for (int f = 0; f < 5; f++) {
           const uint32_t x = f * fs + x0;
-          const double kf = (double)K[f];
-          if (STAGE == 0) {
-            gst(Acc, x, cu[f] + bdt * kf);
-            gst(vout, x, (TOUT)(cu[f] + adt * kf));
-          } else if (STAGE == 3) {
-            const double un = ca[f] + bdt * kf;
-            gst(U, x, un);
-            if (sizeof(TOUT) == 4) gst(Us, x, (float)un);
+          if (MIX) {
+            const float kf = (float)K[f];
+            if (STAGE == 0) {
+              gst(AccF, x, bdtf * kf);
+              gst(vout, x, (TOUT)((float)q[f][3] + adtf * kf));
+            } else if (STAGE == 3) {
+              const double un = cu[f] + ((double)cd[f] + bdt * (double)kf);
+              gst(U, x, un);
+              gst(Us, x, (float)un);
+            } else {
+              gst(AccF, x, cd[f] + bdtf * kf);
+              gst(vout, x, (TOUT)(cus[f] + adtf * kf));
+            }
           } else {
-            gst(Acc, x, ca[f] + bdt * kf);
-            gst(vout, x, (TOUT)(cu[f] + adt * kf));
+            const double kf = (double)K[f];
+            if (STAGE == 0) {
+              gst(Acc, x, cu[f] + bdt * kf);
+              gst(vout, x, (TOUT)(cu[f] + adt * kf));
+            } else if (STAGE == 3) {
+              gst(U, x, ca[f] + bdt * kf);
+            } else {
+              gst(Acc, x, ca[f] + bdt * kf);
+              gst(vout, x, (TOUT)(cu[f] + adt * kf));
+            }
           }
         }
       }
