@@ -234,7 +234,8 @@ enum {
   PW_K_STAGE_S1 = 5, /* RHS + RK update of stage s: PW_K_STAGE_S1 + s - 1 */
   PW_K_FLAGS = 9,    /* cover flags at t_{n+1} */
   PW_K_FINALIZE = 10, /* uncover fill, poison, flag swap */
-  PW_K_NCLASS = 11
+  PW_K_GSTAGE_S1 = 11, /* the global patch's launch within PW_K_STAGE_S1 + s - 1: PW_K_GSTAGE_S1 + s - 1 */
+  PW_K_NCLASS = 15
 };
 
 /* Enable (on != 0) or disable per-kernel-class timing.  While enabled, steps run

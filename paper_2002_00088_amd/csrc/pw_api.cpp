@@ -172,13 +172,13 @@ struct Timed {
   int cls;
   hipEvent_t a = nullptr;
   Timed(pw_context *c_, int cls_) : c(c_), cls(cls_) {
-    if (c->timing) {
+    if (c->timing && cls >= 0) {
       a = take_event(c);
       (void)hipEventRecord(a, c->stream);
     }
   }
   ~Timed() {
-    if (c->timing) {
+    if (c->timing && cls >= 0) {
       hipEvent_t b = take_event(c);
       (void)hipEventRecord(b, c->stream);
       c->marks.push_back(pw_context::Mark{cls, a, b});
@@ -518,13 +518,24 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
         a.tiles = c->dTiles + c->tileOff[pid];
         a.ntiles = c->tileCnt[pid];
         a.coord = c->hp[pid].coord;
+        a.global = pid == 0;
+        Timed tg(c, pid == 0 ? PW_K_GSTAGE_S1 + stage : -1);
         launch_stage(c->stream, a);
       }
     } else {
-      // batched: one launch over the tiles of all Cartesian patches, one over
-      // the tiles of all spherical patches
-      a.tiles = c->dTiles;
-      a.ntiles = c->nCartTiles;
+      // batched: one launch over the global patch's tiles, one over the tiles of
+      // all Cartesian local patches, one over those of all spherical patches
+      {
+        Timed tg(c, PW_K_GSTAGE_S1 + stage);
+        a.tiles = c->dTiles;
+        a.ntiles = c->nGlobalTiles;
+        a.coord = CART;
+        a.global = 1;
+        launch_stage(c->stream, a);
+      }
+      a.global = 0;
+      a.tiles = c->dTiles + c->nGlobalTiles;
+      a.ntiles = c->nCartTiles - c->nGlobalTiles;
       a.coord = CART;
       launch_stage(c->stream, a);
       a.tiles = c->dTiles + c->nCartTiles;
@@ -553,9 +564,11 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
       a.tiles = c->dTiles;
       a.ntiles = c->nGlobalTiles;
       a.coord = CART;
+      a.global = 1;
       launch_stage(st, a);
       continue;
     }
+    a.global = 0;
     bool all = true;
     for (size_t pid = 1; pid < c->hp.size(); pid++) all = all && (c->hp[pid].sv_mask & (1u << sv));
     if (all) {

@@ -145,6 +145,7 @@ struct StageArgs {
   const TileRec *tiles;  // all of one topology (coord)
   int ntiles;
   int coord;
+  int global;  // the tiles are those of the global patch (live-cell test applies)
   const uint8_t *gflag;
   int sv, stage, mixed;
   double dt, v2, eps;

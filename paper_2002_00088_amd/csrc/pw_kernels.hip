@@ -1077,7 +1077,7 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
 // and the plane two above it of phi are staged in LDS with a 3-cell x-y halo
 // for the x-y stencils.
 // ---------------------------------------------------------------------------
-template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD>
+template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD, bool GLOB>
 __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose_slot, const TileRec *tiles,
                                                int ntiles, int chunk, const uint8_t *gflag, int sv, double dt,
                                                double v2, double eps) {
@@ -1284,7 +1284,7 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
     if (do_c && icol) {
       const int k = zn - 3;
       bool live = true;
-      if (p.is_global && gflag) live = gflag[((long long)k * p.n[1] + j) * p.n[0] + i] == LIVE;
+      if (GLOB && gflag) live = gflag[((long long)k * p.n[1] + j) * p.n[0] + i] == LIVE;
       if (live) {
         TC m_[3], b2_[3], h_[3], bb_[3];
         if (COORD == CART) {
@@ -1666,14 +1666,17 @@ void launch_stage(hipStream_t s, const StageArgs &a) {
   const int chunk = (a.ntiles + 7) / 8;
   dim3 bs(256);
   dim3 g(8 * chunk);
-#define PW_STAGE(TIN, TOUT, TC, ST)                                                                         \
-  do {                                                                                                       \
-    if (a.coord == CART)                                                                                     \
-      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART>), g, bs, 0, s, a.P, a.pose, a.tiles, a.ntiles, chunk, \
-                         a.gflag, a.sv, a.dt, a.v2, a.eps);                                                  \
-    else                                                                                                     \
-      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH>), g, bs, 0, s, a.P, a.pose, a.tiles, a.ntiles, chunk,  \
-                         a.gflag, a.sv, a.dt, a.v2, a.eps);                                                  \
+#define PW_STAGE(TIN, TOUT, TC, ST)                                                                          \
+  do {                                                                                                        \
+    if (a.coord == CART && a.global)                                                                          \
+      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, true>), g, bs, 0, s, a.P, a.pose, a.tiles, a.ntiles, \
+                         chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);                                           \
+    else if (a.coord == CART)                                                                                 \
+      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, false>), g, bs, 0, s, a.P, a.pose, a.tiles,        \
+                         a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);                                 \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, false>), g, bs, 0, s, a.P, a.pose, a.tiles,         \
+                         a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);                                 \
   } while (0)
   if (!a.mixed) {
     switch (a.stage) {
