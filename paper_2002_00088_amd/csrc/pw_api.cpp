@@ -336,9 +336,12 @@ pw_status upload_layout(pw_context *c) {
   for (int pid : order) {
     const PatchDev &p = c->hp[pid];
     c->tileOff[pid] = (int)tiles.size();
-    for (int z = 0; z < p.n[2]; z += ST_TZ)
-      for (int y = 0; y < p.n[1]; y += ST_TY)
-        for (int x = 0; x < p.n[0]; x += ST_TX) tiles.push_back(TileRec{pid, x, y, z});
+    const int TX = pid == 0 ? StageTile<true>::TX : StageTile<false>::TX;
+    const int TY = pid == 0 ? StageTile<true>::TY : StageTile<false>::TY;
+    const int TZ = pid == 0 ? StageTile<true>::TZ : StageTile<false>::TZ;
+    for (int z = 0; z < p.n[2]; z += TZ)
+      for (int y = 0; y < p.n[1]; y += TY)
+        for (int x = 0; x < p.n[0]; x += TX) tiles.push_back(TileRec{pid, x, y, z});
     c->tileCnt[pid] = (int)tiles.size() - c->tileOff[pid];
     if (p.coord == CART) c->nCartTiles = (int)tiles.size();
   }

@@ -5,18 +5,27 @@
 
 #include "pw_internal.h"
 
-// stage-kernel tile: ST_TX x ST_TY columns, up to ST_TZ planes per workgroup
-#define ST_TX 32
-#define ST_TY 8
-#ifndef ST_TZ
-#define ST_TZ 16
+// Stage-kernel tiles: TX x TY columns, up to TZ planes per workgroup.  The
+// global patch (large, regular) takes deeper tiles: fewer re-read halo planes
+// per computed cell; local patches (a few tens of cells per side) take shorter
+// ones: better balance.
+#ifndef ST_TY_GLOBAL
+#define ST_TY_GLOBAL 8
 #endif
-#ifndef ST_MINB
-#define ST_MINB 1
+#ifndef ST_TZ_GLOBAL
+#define ST_TZ_GLOBAL 32
 #endif
-#define ST_PX (ST_TX + 6)
-#define ST_PY (ST_TY + 6)
-#define ST_PW (ST_PX * ST_PY)
+#ifndef ST_TZ_LOCAL
+#define ST_TZ_LOCAL 8
+#endif
+template <bool GLOB>
+struct StageTile {
+  static constexpr int TX = 32;
+  static constexpr int TY = GLOB ? ST_TY_GLOBAL : 8;
+  static constexpr int TZ = GLOB ? ST_TZ_GLOBAL : ST_TZ_LOCAL;
+  static constexpr int PX = TX + 6, PY = TY + 6, PW = PX * PY;  // LDS plane with a 3-cell halo
+  static constexpr int THREADS = TX * TY;
+};
 #define DIAG_N 23
 #define BRICK_THREADS 192
 #define BRICK_LDS_BYTES 40960

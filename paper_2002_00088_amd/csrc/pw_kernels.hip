@@ -1078,9 +1078,12 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
 // for the x-y stencils.
 // ---------------------------------------------------------------------------
 template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD, bool GLOB>
-__global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose_slot, const TileRec *tiles,
+__global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose_slot, const TileRec *tiles,
                                                int ntiles, int chunk, const uint8_t *gflag, int sv, double dt,
                                                double v2, double eps) {
+  using TL = StageTile<GLOB>;
+  constexpr int ST_TX = TL::TX, ST_TY = TL::TY, ST_TZ = TL::TZ, ST_PX = TL::PX, ST_PW = TL::PW;
+  constexpr int ST_THREADS = TL::THREADS;
   __shared__ TC Bc[2][5][ST_PW];
   __shared__ TC Ad[2][ST_PW];
   const int bid = blockIdx.x;
@@ -1109,15 +1112,16 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
   // 32-bit element offsets (a field of one patch holds < 2^31 elements)
   const uint32_t fs = (uint32_t)p.fstride, sz = (uint32_t)p.slab;
   const uint32_t col = (uint32_t)cell_index(p, i, j, 0);
-  // halo cells of the LDS planes: the ring of ST_PW - 256 cells around the
-  // tile, enumerated row by row; thread t takes ring cells t and t + 256
+  // halo cells of the LDS planes: the ring of ST_PW - ST_THREADS cells around
+  // the tile, enumerated row by row; thread t takes ring cells t, t + ST_THREADS
   constexpr int NHALO = ST_PW - ST_TX * ST_TY;
-  uint32_t hoff[2];
-  bool hval[2];
-  int hslot[2];
+  constexpr int NH = (NHALO + ST_THREADS - 1) / ST_THREADS;
+  uint32_t hoff[NH];
+  bool hval[NH];
+  int hslot[NH];
 #pragma unroll
-  for (int m = 0; m < 2; m++) {
-    const int h = tid + 256 * m;
+  for (int m = 0; m < NH; m++) {
+    const int h = tid + ST_THREADS * m;
     hval[m] = false;
     hoff[m] = 0;
     hslot[m] = 0;
@@ -1165,7 +1169,7 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
 
   // software pipeline: the loads of iteration it+1 are in flight while
   // iteration it computes
-  TC pown[5], phA[2], phB[2][5];
+  TC pown[5], phA[NH], phB[NH][5];
   auto prefetch = [&](int itp) {
     const int zn = z0 - 3 + itp;
     const uint32_t zo = (uint32_t)(zn + PW_NG) * sz;  // cell_index already holds the +NG of z = 0
@@ -1174,12 +1178,12 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
     if (itp >= 2) {
       const uint32_t za = zo - (PW_NG + 1) * sz;
 #pragma unroll
-      for (int m = 0; m < 2; m++) phA[m] = hval[m] ? (TC)gld(in, hoff[m] + za) : (TC)0;
+      for (int m = 0; m < NH; m++) phA[m] = hval[m] ? (TC)gld(in, hoff[m] + za) : (TC)0;
     }
     if (itp >= 6) {
       const uint32_t zb = zo - (PW_NG + 3) * sz;
 #pragma unroll
-      for (int m = 0; m < 2; m++)
+      for (int m = 0; m < NH; m++)
 #pragma unroll
         for (int f = 0; f < 5; f++) phB[m][f] = hval[m] ? (TC)gld(in, f * fs + hoff[m] + zb) : (TC)0;
     }
@@ -1189,7 +1193,7 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
   // planes z0-2 .. z0+1 are formed from phi planes staged with their halo rings
   // (in the second centre-plane buffer, first written two iterations later).
   {
-    TC wh[4][2];
+    TC wh[4][NH];
 #pragma unroll
     for (int w = 0; w < 6; w++) {
       const uint32_t zo = (uint32_t)(z0 - 3 + w + PW_NG) * sz - PW_NG * sz;
@@ -1200,7 +1204,7 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
     for (int w = 0; w < 4; w++) {
       const uint32_t zo = (uint32_t)(z0 - 2 + w + PW_NG) * sz - PW_NG * sz;
 #pragma unroll
-      for (int m = 0; m < 2; m++) wh[w][m] = hval[m] ? (TC)gld(in, hoff[m] + zo) : (TC)0;
+      for (int m = 0; m < NH; m++) wh[w][m] = hval[m] ? (TC)gld(in, hoff[m] + zo) : (TC)0;
     }
     prefetch(6);
 #pragma unroll
@@ -1208,7 +1212,7 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
       TC *A_ = Bc[1][w];
       if (inpad) A_[own] = q[0][w + 2];
 #pragma unroll
-      for (int m = 0; m < 2; m++)
+      for (int m = 0; m < NH; m++)
         if (hval[m]) A_[hslot[m]] = wh[w][m];
     }
     __syncthreads();
@@ -1237,7 +1241,7 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
     if (do_d) {
       if (inpad) A_[own] = q[0][5];
 #pragma unroll
-      for (int m = 0; m < 2; m++)
+      for (int m = 0; m < NH; m++)
         if (hval[m]) A_[hslot[m]] = phA[m];
     }
     // centre-cell data of the RK update, issued before the barrier.  FP64 path:
@@ -1267,7 +1271,7 @@ __global__ __launch_bounds__(256, ST_MINB) void k_stage(const PatchDev *__restri
         for (int f = 0; f < 5; f++) Bc[buf][f][own] = q[f][3];
       }
 #pragma unroll
-      for (int m = 0; m < 2; m++)
+      for (int m = 0; m < NH; m++)
         if (hval[m]) {
 #pragma unroll
           for (int f = 0; f < 5; f++) Bc[buf][f][hslot[m]] = phB[m][f];
@@ -1664,7 +1668,7 @@ void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
 void launch_stage(hipStream_t s, const StageArgs &a) {
   if (a.ntiles <= 0) return;
   const int chunk = (a.ntiles + 7) / 8;
-  dim3 bs(256);
+  dim3 bs(a.global ? StageTile<true>::THREADS : StageTile<false>::THREADS);
   dim3 g(8 * chunk);
 #define PW_STAGE(TIN, TOUT, TC, ST)                                                                          \
   do {                                                                                                        \
