@@ -11,9 +11,11 @@ synchronisations, timed with HIP events on the library's stream.
 
 Printed: one JSON line with the metric (live cell-updates per second), the
 roofline figure of the dominant kernel (algorithmic bytes per launch divided by
-its average duration, measured with HIP events in a separate eager pass), the
-batched-vs-per-patch-FP64 comparison with its accuracy, and the CPU oracle's
-rate on a bounded sample of the same workload.
+its average duration, measured with HIP events in a separate eager pass), a
+device-copy bandwidth measured in the same run, the batched mixed run against the
+plain per-patch FP64 run (speed, accuracy against each other and against the
+exact solution), the other mixed-precision variant, and the CPU oracle's rate on
+a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -29,11 +31,15 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per live cell per stage kernel launch (five fields).
 # FP64 path: stage 1 reads u, writes acc and v2; stages 2-3 read v_s, u, acc and
 # write acc, v_{s+1}; stage 4 reads v4, acc and writes u (all 8-byte values).
-# Mixed path (4-byte stage values, 4-byte increment, FP64 state): stage 1 reads
-# the FP32 copy of u, writes the increment and v2; stages 2-3 read v_s, the copy
-# of u and the increment and write the increment and v_{s+1}; stage 4 reads v4,
-# the increment and u and writes u and its FP32 copy.
-STAGE_BYTES = {"fp64": [120, 200, 200, 120], "mixed": [60, 100, 100, 140]}
+# Mixed path, FP64 accumulator: stage 1 reads the FP32 copy of u (stencil input)
+# and u, writes acc and v2; stages 2-3 read v_s, the FP32 copy of u and acc and
+# write acc and v_{s+1}; stage 4 reads v4 and acc and writes u and its FP32 copy.
+# Mixed path, FP32 increments: stage 1 reads the FP32 copy of u, writes the
+# increment and v2; stages 2-3 read v_s, the copy of u and the increment and
+# write the increment and v_{s+1}; stage 4 reads v4, the increment and u and
+# writes u and its FP32 copy.
+STAGE_BYTES = {"fp64": [120, 200, 200, 120], "mixed": [120, 140, 140, 120], "mixed_inc": [60, 100, 100, 140]}
+DTYPE = {"fp64": "f64", "mixed": "f32+f64", "mixed_inc": "f32+f64"}
 
 
 def kernel_source_hash():
@@ -95,13 +101,77 @@ def cpu_baseline(cfg, steps=1):
                     steps, cfg["name"], live, sec))
 
 
+def copy_bandwidth(torch, stream, nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes on the same stream: (read + write) bytes
+    per second, best of reps."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    best = 0.0
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dst.copy_(src)
+            e1.record(stream)
+            e1.synchronize()
+            best = max(best, 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    return best
+
+
+def timed_steps(torch, ctx, stream, dt, steps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.rk4_step(dt, steps)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def errors_vs_exact(np, ctx, cfg):
+    """Per field: max |u - exact| over live cells of every patch, relative to the
+    largest |exact| there (the library's diagnostics, state vector 0)."""
+    emax = np.zeros(5)
+    umax = np.zeros(5)
+    for pid in range(len(cfg["patches"])):
+        d = ctx.diagnostics(pid, 0)
+        emax = np.maximum(emax, d["err_max"])
+        umax = np.maximum(umax, d["max"])
+    return [float("%.3e" % x) for x in emax / np.maximum(umax, 1e-300)]
+
+
+def compare_states(np, a_ctx, b_ctx, cfg):
+    """Max and L2 differences of a against b over live cells of all patches,
+    relative to b's largest magnitude (max) and norm (L2), per field."""
+    f, _ = b_ctx.flags()
+    maxabs = np.zeros(5)
+    maxerr = np.zeros(5)
+    l2 = np.zeros(5)
+    nrm = np.zeros(5)
+    for pid in range(len(cfg["patches"])):
+        a, b = a_ctx.get_state(pid), b_ctx.get_state(pid)
+        m = (f == 0) if pid == 0 else np.ones(a.shape[1:], dtype=bool)
+        d = a[:, m] - b[:, m]
+        maxabs = np.maximum(maxabs, np.abs(b[:, m]).max(axis=1))
+        maxerr = np.maximum(maxerr, np.abs(d).max(axis=1))
+        l2 += (d * d).sum(axis=1)
+        nrm += (b[:, m] ** 2).sum(axis=1)
+    return ([float("%.3e" % x) for x in maxerr / np.maximum(maxabs, 1e-300)],
+            [float("%.3e" % x) for x in np.sqrt(l2 / np.maximum(nrm, 1e-300))])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched")
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "mixed_inc", "fp64"])
     ap.add_argument("--schedule", default="batched", choices=["batched", "per_patch"])
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -120,36 +190,29 @@ def main():
 
     from paper_2002_00088_amd import pw
 
+    PREC = {"mixed": pw.PW_MIXED, "mixed_inc": pw.PW_MIXED_INC, "fp64": pw.PW_FP64}
     torch.cuda.set_device(0)
     cfg = make_config(args.workload)
     print("bench: workload %s, %d patches, precision %s, schedule %s" % (cfg["name"], len(cfg["patches"]),
                                                                          args.precision, args.schedule),
           file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
-    prec = pw.PW_MIXED if args.precision == "mixed" else pw.PW_FP64
     sched = pw.PW_SCHED_BATCHED if args.schedule == "batched" else pw.PW_SCHED_PER_PATCH
-    ctx = pw.context_from_config(cfg, precision=prec, schedule=sched, use_graph=not args.no_graph,
+    ctx = pw.context_from_config(cfg, precision=PREC[args.precision], schedule=sched, use_graph=not args.no_graph,
                                  stream=stream.cuda_stream)
     ctx.init_exact(0.0)
     dt = cfg["dt"]
     ctx.rk4_step(dt, args.warmup)
     stream.synchronize()
     live0 = ctx.live_cells()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t_wall = time.perf_counter()
-    e0.record(stream)
-    ctx.rk4_step(dt, args.steps)
-    e1.record(stream)
-    e1.synchronize()
-    torch.cuda.synchronize()
+    ms = timed_steps(torch, ctx, stream, dt, args.steps) if args.steps > 0 else float("nan")
     t_wall = time.perf_counter() - t_wall
-    ms = e0.elapsed_time(e1)
     live1 = ctx.live_cells()
     live = 0.5 * (live0 + live1)
-    value = live * args.steps / (ms / 1e3)
-    print("bench: %.3f ms/step, %.3e cell-updates/s (wall %.3f s)" % (ms / args.steps, value, t_wall),
+    value = live * args.steps / (ms / 1e3) if args.steps > 0 else None
+    print("bench: %.3f ms/step, %s cell-updates/s (wall %.3f s)" % (ms / max(1, args.steps),
+                                                                     "%.3e" % value if value else "-", t_wall),
           file=sys.stderr, flush=True)
 
     # per-kernel-class durations (eager pass with HIP events on the same stream;
@@ -169,15 +232,18 @@ def main():
     g_ms = avg["gstage_s%d" % (dom + 1)]
     bytes_launch = live_global * sb[dom]
     achieved = bytes_launch / (g_ms * 1e-3) / 1e9
-    ty = "float, float, float" if args.precision == "mixed" else "double, double, double"
-    dominant_name = "k_stage<%s, %d, 0, true>" % (ty, dom)
+    ty = "double, double, double" if args.precision == "fp64" else "float, float, float"
+    am = 1 if args.precision == "mixed_inc" else 0
+    dominant_name = "k_stage<%s, %d, 0, true, %d>" % (ty, dom, am)
     traffic = load_traffic(cfg["name"], args.precision, dominant_name)
+    copy_gbs = copy_bandwidth(torch, stream)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dominant_name + " (RHS + RK stage %d, global patch)" % (dom + 1),
                 "avg_ms": round(g_ms, 5), "algorithmic_bytes_per_launch": int(bytes_launch),
                 "bytes_per_live_cell": sb[dom], "live_cells": int(live_global),
-                "eager_launches": int(kt["gstage_s%d" % (dom + 1)][1])}
+                "eager_launches": int(kt["gstage_s%d" % (dom + 1)][1]),
+                "measured_copy_GBps": round(copy_gbs, 1), "frac_of_measured_copy": round(achieved / copy_gbs, 4)}
     # all stage kernels of each stage (every patch), for reference
     stage_all = {"stage_s%d" % (s + 1): {"avg_ms": round(avg["stage_s%d" % (s + 1)], 5),
                                          "algorithmic_GBps": round(live * sb[s] / (avg["stage_s%d" % (s + 1)] * 1e-3) / 1e9, 1)}
@@ -187,8 +253,8 @@ def main():
 
     out = {"metric": "cell-updates/s per RK4 step (incl. ghost interp); HBM GB/s vs peak",
            "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
+           "ms_per_step": ms / max(1, args.steps), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": DTYPE[args.precision], "data": "synthetic",
            "config": {"workload": cfg["name"], "global_cells": cfg["patches"][0]["n"],
                       "local_patches": len(cfg["patches"]) - 1, "live_cells": int(live),
                       "precision": args.precision,
@@ -196,45 +262,44 @@ def main():
                       "dt": dt},
            "roofline": roofline,
            "stage_kernels_all_patches": stage_all,
-           "step_algorithmic_GBps": round(step_bytes / (ms / args.steps * 1e-3) / 1e9, 1),
+           "step_algorithmic_GBps": round(step_bytes / (ms / max(1, args.steps) * 1e-3) / 1e9, 1),
            "kernel_avg_ms": kinds}
+    n_total = args.warmup + args.steps + args.timing_steps
 
-    if not args.no_compare and args.precision == "mixed":
-        # plain per-patch FP64 on the same GPU, same steps, and the accuracy of the
-        # batched mixed run against it
+    if not args.no_compare and args.precision != "fp64":
+        # plain per-patch FP64 on the same GPU, same number of steps; the accuracy
+        # of the batched mixed run against it and of both against the exact solution
         ref = pw.context_from_config(cfg, precision=pw.PW_FP64, schedule=pw.PW_SCHED_PER_PATCH, use_graph=False,
                                      stream=stream.cuda_stream)
         ref.init_exact(0.0)
         ref.rk4_step(dt, args.warmup)
         stream.synchronize()
-        e0.record(stream)
-        ref.rk4_step(dt, args.steps)
-        e1.record(stream)
-        e1.synchronize()
-        ms_ref = e0.elapsed_time(e1)
+        ms_ref = timed_steps(torch, ref, stream, dt, args.steps)
         value_ref = ref.live_cells() * args.steps / (ms_ref / 1e3)
-        # same number of steps on both: mixed has taken warmup + steps + timing_steps
         ref.rk4_step(dt, args.timing_steps)
-        f, _ = ref.flags()
-        # errors over all live cells of all patches, relative to the field's
-        # largest magnitude over those cells
-        maxabs = np.zeros(5)
-        maxerr = np.zeros(5)
-        l2 = np.zeros(5)
-        nrm = np.zeros(5)
-        for pid in range(len(cfg["patches"])):
-            a, b = ctx.get_state(pid), ref.get_state(pid)
-            m = (f == 0) if pid == 0 else np.ones(a.shape[1:], dtype=bool)
-            d = a[:, m] - b[:, m]
-            maxabs = np.maximum(maxabs, np.abs(b[:, m]).max(axis=1))
-            maxerr = np.maximum(maxerr, np.abs(d).max(axis=1))
-            l2 += (d * d).sum(axis=1)
-            nrm += (b[:, m] ** 2).sum(axis=1)
-        errs = maxerr / np.maximum(maxabs, 1e-300)
-        out["compare"] = {"per_patch_fp64": {"value": value_ref, "ms_per_step": ms_ref / args.steps},
+        emax, el2 = compare_states(np, ctx, ref, cfg)
+        out["compare"] = {"per_patch_fp64": {"value": value_ref, "ms_per_step": ms_ref / args.steps,
+                                             "max_rel_err_vs_exact": errors_vs_exact(np, ref, cfg)},
+                          "batched_mixed_max_rel_err_vs_exact": errors_vs_exact(np, ctx, cfg),
                           "speedup_batched_mixed": value / value_ref,
-                          "mixed_vs_fp64_max_rel_err": [float("%.3e" % x) for x in errs],
-                          "mixed_vs_fp64_l2_rel_err": [float("%.3e" % x) for x in np.sqrt(l2 / np.maximum(nrm, 1e-300))]}
+                          "mixed_vs_fp64_max_rel_err": emax, "mixed_vs_fp64_l2_rel_err": el2,
+                          "steps_compared": n_total}
+        # the other mixed-precision variant, same steps, timed and compared the same way
+        other = "mixed_inc" if args.precision == "mixed" else "mixed"
+        var = pw.context_from_config(cfg, precision=PREC[other], schedule=sched, use_graph=not args.no_graph,
+                                     stream=stream.cuda_stream)
+        var.init_exact(0.0)
+        var.rk4_step(dt, args.warmup)
+        stream.synchronize()
+        ms_var = timed_steps(torch, var, stream, dt, args.steps)
+        var.rk4_step(dt, args.timing_steps)
+        vmax, vl2 = compare_states(np, var, ref, cfg)
+        out["variant_" + other] = {"value": var.live_cells() * args.steps / (ms_var / 1e3),
+                                   "ms_per_step": ms_var / args.steps,
+                                   "stage_bytes_per_live_cell": STAGE_BYTES[other],
+                                   "vs_fp64_max_rel_err": vmax, "vs_fp64_l2_rel_err": vl2,
+                                   "max_rel_err_vs_exact": errors_vs_exact(np, var, cfg)}
+        var.close()
         ref.close()
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")

@@ -48,7 +48,7 @@ enum {
                        covers at most one cell of motion per step (Sec. 2.4.2) */
 };
 
-enum { PW_FP64 = 0, PW_MIXED = 1 };       /* precision */
+enum { PW_FP64 = 0, PW_MIXED = 1, PW_MIXED_INC = 2 }; /* precision */
 enum { PW_CART = 0, PW_SPH = 1 };         /* patch topology */
 enum { PW_STATIC = 0, PW_LINEAR = 1, PW_CIRCLE = 2 }; /* patch motion */
 enum { PW_FLAG_LIVE = 0, PW_FLAG_EFFGHOST = 1, PW_FLAG_DEACT = 2 }; /* cover flags */
@@ -63,7 +63,10 @@ enum { PW_EXACT_NONE = 0, PW_EXACT_PLANE = 1, PW_EXACT_GAUSS = 2 };
  *   precision        PW_FP64: every array and operation FP64.  PW_MIXED: FP64 state
  *                    u_n, FP64 RK accumulator, FP64 donor location, Lagrange weights
  *                    and frame Jacobians; FP32 stage inputs, FP32 stencil and
- *                    interpolation sums.
+ *                    interpolation sums (an FP32 copy of u_n feeds the first stage).
+ *                    PW_MIXED_INC: as PW_MIXED, but the accumulator carries the
+ *                    increment dt sum_l b_l K_l (Table rk4) in FP32 and
+ *                    u_{n+1} = u_n + increment + b_4 dt K_4 is formed in FP64.
  *   n_state_vectors  1..4 independent state vectors sharing maps and cover flags
  *                    (multiple state vectors, Sec. 1.1); each has its own wave speed
  *                    (d'Alembertian Lap - v^-2 d_t^2) and interpolation order.

@@ -151,7 +151,7 @@ uint32_t pack_ijk(int i, int j, int k) {
   return (uint32_t)(i + PW_NG) | ((uint32_t)(j + PW_NG) << 10) | ((uint32_t)(k + PW_NG) << 20);
 }
 
-bool mixed(const pw_context *c) { return c->cfg.precision == PW_MIXED; }
+bool mixed(const pw_context *c) { return c->cfg.precision == PW_MIXED || c->cfg.precision == PW_MIXED_INC; }
 size_t stage_elem(const pw_context *c) { return mixed(c) ? sizeof(float) : sizeof(double); }
 bool has_locals(const pw_context *c) { return c->hp.size() > 1; }
 
@@ -510,6 +510,7 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
     a.sv = sv;
     a.stage = stage;
     a.mixed = mixed(c);
+    a.inc = c->cfg.precision == PW_MIXED_INC;
     a.dt = dt;
     a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
     a.eps = c->cfg.ko_eps;
@@ -559,6 +560,7 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
     a.sv = sv;
     a.stage = stage;
     a.mixed = mixed(c);
+    a.inc = c->cfg.precision == PW_MIXED_INC;
     a.dt = dt;
     a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
     a.eps = c->cfg.ko_eps;
@@ -716,7 +718,7 @@ pw_status pw_create(const pw_config *cfg, pw_context **out) {
   if (!cfg || !out) return PW_EINVAL;
   *out = nullptr;
   if (cfg->n_state_vectors < 1 || cfg->n_state_vectors > PW_MAX_SV) return PW_EINVAL;
-  if (cfg->precision != PW_FP64 && cfg->precision != PW_MIXED) return PW_EINVAL;
+  if (cfg->precision != PW_FP64 && cfg->precision != PW_MIXED && cfg->precision != PW_MIXED_INC) return PW_EINVAL;
   if (cfg->buffer_width < 4) return PW_EINVAL;
   for (int s = 0; s < cfg->n_state_vectors; s++) {
     if (cfg->interp_points[s] != 5 && cfg->interp_points[s] != 6) return PW_EINVAL;

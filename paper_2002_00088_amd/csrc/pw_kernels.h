@@ -157,6 +157,7 @@ struct StageArgs {
   int global;  // the tiles are those of the global patch (live-cell test applies)
   const uint8_t *gflag;
   int sv, stage, mixed;
+  int inc;  // mixed path: FP32 increments in the accumulator
   double dt, v2, eps;
 };
 

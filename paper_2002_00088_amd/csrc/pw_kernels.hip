@@ -1077,7 +1077,7 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
 // and the plane two above it of phi are staged in LDS with a 3-cell x-y halo
 // for the x-y stencils.
 // ---------------------------------------------------------------------------
-template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD, bool GLOB>
+template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD, bool GLOB, int AM>
 __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose_slot, const TileRec *tiles,
                                                int ntiles, int chunk, const uint8_t *gflag, int sv, double dt,
                                                double v2, double eps) {
@@ -1105,9 +1105,11 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
   TOUT *vout = (TOUT *)(STAGE == 1 ? p.vb[sv] : p.va[sv]);
   double *U = p.u[sv];
   double *Acc = p.acc[sv];
-  // mixed path: the accumulator holds the FP32 increment dt sum_l b_l K_l, and
-  // the FP32 copy of u_n is the base of the stage values
+  // mixed path (FP32 stage values): stages 2-3 build v_{s+1} on the FP32 copy of
+  // u_n; the accumulator is FP64 u_n + dt sum_l b_l K_l (AM = 0) or the FP32
+  // increment dt sum_l b_l K_l (AM = 1)
   constexpr bool MIX = sizeof(TOUT) == 4;
+  constexpr bool INC = MIX && AM == 1;
   float *AccF = (float *)p.acc[sv];
   // 32-bit element offsets (a field of one patch holds < 2^31 elements)
   const uint32_t fs = (uint32_t)p.fstride, sz = (uint32_t)p.slab;
@@ -1245,21 +1247,28 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
         if (hval[m]) A_[hslot[m]] = phA[m];
     }
     // centre-cell data of the RK update, issued before the barrier.  FP64 path:
-    // u_n (stages 1-3) and the accumulator (stages 2-4).  Mixed path: the FP32
-    // copy of u_n (stages 2-3; stage 1 has it in the z-window), the FP32
-    // increment (stages 2-4), and u_n itself in stage 4 only.
+    // u_n (stages 1-3) and the accumulator (stages 2-4).  Mixed path, FP64
+    // accumulator: u_n (stage 1), the FP32 copy of u_n (stages 2-3), the
+    // accumulator (stages 2-4).  Mixed path, FP32 increments: the FP32 copy of
+    // u_n (stages 2-3; stage 1 has it in the z-window), the increment (stages
+    // 2-4), u_n itself in stage 4 only.
     double cu[5], ca[5];
     float cus[5], cd[5];
     if (do_c && icol) {
       const uint32_t xc = col + (uint32_t)(zn - 3) * sz;
 #pragma unroll
       for (int f = 0; f < 5; f++) {
-        if (MIX) {
-          cus[f] = (STAGE == 1 || STAGE == 2) ? gld((const float *)Us, f * fs + xc) : 0.0f;
+        cus[f] = (MIX && (STAGE == 1 || STAGE == 2)) ? gld((const float *)Us, f * fs + xc) : 0.0f;
+        if (INC) {
           cd[f] = STAGE != 0 ? gld((const float *)AccF, f * fs + xc) : 0.0f;
           cu[f] = STAGE == 3 ? gld(U, f * fs + xc) : 0.0;
           ca[f] = 0.0;
+        } else if (MIX) {
+          cd[f] = 0.0f;
+          cu[f] = STAGE == 0 ? gld(U, f * fs + xc) : 0.0;
+          ca[f] = STAGE != 0 ? gld(Acc, f * fs + xc) : 0.0;
         } else {
+          cd[f] = 0.0f;
           cu[f] = STAGE != 3 ? gld(U, f * fs + xc) : 0.0;
           ca[f] = STAGE != 0 ? gld(Acc, f * fs + xc) : 0.0;
         }
@@ -1393,13 +1402,13 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
 #pragma unroll
         for (int a = 0; a < 3; a++) K[2 + a] = dpi[a] + kof[2 + a];
         const uint32_t x0 = col + (uint32_t)k * sz;
-        // classic RK4 (Table rk4): v_{s+1} = u_n + a_s dt K_s.  FP64 path: acc holds
-        // u_n + dt sum_l b_l K_l.  Mixed path: acc holds the FP32 increment
-        // dt sum_l b_l K_l, and u_{n+1} = u_n + increment + b_4 dt K_4 in FP64.
+        // classic RK4 (Table rk4): v_{s+1} = u_n + a_s dt K_s; acc holds
+        // u_n + dt sum_l b_l K_l in FP64, or (FP32 increments) dt sum_l b_l K_l in
+        // FP32 with u_{n+1} = u_n + increment + b_4 dt K_4 formed in FP64.
 #pragma unroll
         for (int f = 0; f < 5; f++) {
           const uint32_t x = f * fs + x0;
-          if (MIX) {
+          if (INC) {
             const float kf = (float)K[f];
             if (STAGE == 0) {
               gst(AccF, x, bdtf * kf);
@@ -1411,6 +1420,19 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
             } else {
               gst(AccF, x, cd[f] + bdtf * kf);
               gst(vout, x, (TOUT)(cus[f] + adtf * kf));
+            }
+          } else if (MIX) {
+            const double kd = (double)K[f];
+            if (STAGE == 0) {
+              gst(Acc, x, cu[f] + bdt * kd);
+              gst(vout, x, (TOUT)(cu[f] + adt * kd));
+            } else if (STAGE == 3) {
+              const double un = ca[f] + bdt * kd;
+              gst(U, x, un);
+              gst(Us, x, (float)un);
+            } else {
+              gst(Acc, x, ca[f] + bdt * kd);
+              gst(vout, x, (TOUT)(cus[f] + adtf * (float)K[f]));
             }
           } else {
             const double kf = (double)K[f];
@@ -1670,31 +1692,38 @@ void launch_stage(hipStream_t s, const StageArgs &a) {
   const int chunk = (a.ntiles + 7) / 8;
   dim3 bs(a.global ? StageTile<true>::THREADS : StageTile<false>::THREADS);
   dim3 g(8 * chunk);
-#define PW_STAGE(TIN, TOUT, TC, ST)                                                                          \
+#define PW_STAGE(TIN, TOUT, TC, ST, AM)                                                                      \
   do {                                                                                                        \
     if (a.coord == CART && a.global)                                                                          \
-      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, true>), g, bs, 0, s, a.P, a.pose, a.tiles, a.ntiles, \
-                         chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);                                           \
+      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, true, AM>), g, bs, 0, s, a.P, a.pose, a.tiles,     \
+                         a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);                                 \
     else if (a.coord == CART)                                                                                 \
-      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, false>), g, bs, 0, s, a.P, a.pose, a.tiles,        \
+      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, false, AM>), g, bs, 0, s, a.P, a.pose, a.tiles,    \
                          a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);                                 \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, false>), g, bs, 0, s, a.P, a.pose, a.tiles,         \
+      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, false, AM>), g, bs, 0, s, a.P, a.pose, a.tiles,     \
                          a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);                                 \
   } while (0)
   if (!a.mixed) {
     switch (a.stage) {
-      case 0: PW_STAGE(double, double, double, 0); break;
-      case 1: PW_STAGE(double, double, double, 1); break;
-      case 2: PW_STAGE(double, double, double, 2); break;
-      default: PW_STAGE(double, double, double, 3); break;
+      case 0: PW_STAGE(double, double, double, 0, 0); break;
+      case 1: PW_STAGE(double, double, double, 1, 0); break;
+      case 2: PW_STAGE(double, double, double, 2, 0); break;
+      default: PW_STAGE(double, double, double, 3, 0); break;
+    }
+  } else if (!a.inc) {
+    switch (a.stage) {
+      case 0: PW_STAGE(float, float, float, 0, 0); break;
+      case 1: PW_STAGE(float, float, float, 1, 0); break;
+      case 2: PW_STAGE(float, float, float, 2, 0); break;
+      default: PW_STAGE(float, float, float, 3, 0); break;
     }
   } else {
     switch (a.stage) {
-      case 0: PW_STAGE(float, float, float, 0); break;
-      case 1: PW_STAGE(float, float, float, 1); break;
-      case 2: PW_STAGE(float, float, float, 2); break;
-      default: PW_STAGE(float, float, float, 3); break;
+      case 0: PW_STAGE(float, float, float, 0, 1); break;
+      case 1: PW_STAGE(float, float, float, 1, 1); break;
+      case 2: PW_STAGE(float, float, float, 2, 1); break;
+      default: PW_STAGE(float, float, float, 3, 1); break;
     }
   }
 #undef PW_STAGE

@@ -2,9 +2,14 @@
 
 FP64 bar: per field, max |u_gpu - u_oracle| over live cells divided by
 max |u_oracle| over the same cells must be <= 1e-12; cover flags, cover ids and
-skip/uncover counts must match exactly.  The mixed path is compared to the
-oracle with a stated looser bound (FP32 stage inputs carry ~1e-7 relative
-rounding into every stage).
+skip/uncover counts must match exactly.  The mixed paths are compared to the
+oracle with a stated looser bound: their stage values are FP32 (relative rounding
+6e-8), and the 4th-order stencils amplify that rounding by about 10/h^2 (second
+derivatives, h the smallest spacing in cells of the coordinate) before dt ~ h/4
+scales it back, so one RK4 step carries O(1e-6) relative error into the state and
+a few steps O(1e-5); the bounds below are 2e-5 for a few steps on the two-patch
+case and 1e-4 for one step of the full batched workload (spherical patches with
+1/r^2 terms included).
 """
 import math
 import sys
@@ -65,21 +70,36 @@ def run_pair(cfg, steps, precision=pw.PW_FP64, schedule=pw.PW_SCHED_BATCHED, use
     return o, g
 
 
-def compare(cfg, o, g, tol, check_counts=True):
+def compare(cfg, o, g, tol, check_counts=True, norm="patch"):
+    """norm "patch": each patch's error relative to that patch's largest value
+    (stricter); norm "all": the error over the live cells of every patch relative
+    to the largest value over them (the tolerance's definition)."""
     worst = 0.0
     fo, co = o.flags() if len(cfg["patches"]) > 1 else (None, None)
     if fo is not None:
         fg, cg = g.flags()
         assert (fo == fg).all(), "cover flags differ in %d cells" % int((fo != fg).sum())
         assert (co == cg).all()
-    for pid, p in enumerate(cfg["patches"]):
-        for sv in range(len(cfg["wave_speed"])):
+    for sv in range(len(cfg["wave_speed"])):
+        dmax = np.zeros(5)
+        umax = np.zeros(5)
+        for pid, p in enumerate(cfg["patches"]):
             if not p["sv_mask"] & (1 << sv):
                 continue
             m = live_mask(cfg, pid, fo)
-            e = rel_err(g.get_state(pid, sv), o.get_state(pid, sv), m)
+            a, b = g.get_state(pid, sv), o.get_state(pid, sv)
+            if norm == "patch":
+                e = rel_err(a, b, m)
+                worst = max(worst, e.max())
+                assert (e <= tol).all(), (pid, sv, e)
+            else:
+                assert np.isfinite(a[:, m]).all()
+                dmax = np.maximum(dmax, np.abs(a[:, m] - b[:, m]).max(axis=1))
+                umax = np.maximum(umax, np.abs(b[:, m]).max(axis=1))
+        if norm == "all":
+            e = dmax / np.maximum(umax, 1e-300)
             worst = max(worst, e.max())
-            assert (e <= tol).all(), (pid, sv, e)
+            assert (e <= tol).all(), (sv, e)
     if check_counts:
         co_ = o.counters()
         cg_ = g.counters()
@@ -198,10 +218,11 @@ def test_schedules_and_graph_bitwise_identical():
         assert np.array_equal(o[1], outs[0][1], equal_nan=True)
 
 
-def test_mixed_precision_close_to_oracle():
+@pytest.mark.parametrize("prec", [pw.PW_MIXED, pw.PW_MIXED_INC])
+def test_mixed_precision_close_to_oracle(prec):
     cfg = W.two_patch(seed=2, ng=48, nl=40, P=6)
-    say("mixed precision")
-    o, g = run_pair(cfg, 4, precision=pw.PW_MIXED)
+    say("mixed precision", prec)
+    o, g = run_pair(cfg, 4, precision=prec)
     fo, _ = o.flags()
     worst = 0
     for pid in range(2):
@@ -209,6 +230,59 @@ def test_mixed_precision_close_to_oracle():
         say("  patch", pid, "rel err per field", e)
         worst = max(worst, e.max())
     assert worst < 2e-5
+
+
+def test_spherical_workload_reduced():
+    # the spherical workload (static spherical patch, quadrupolar pulse) at
+    # reduced resolution
+    cfg = W.spherical(seed=3, ng=48, nr=40, nth=16, nph=32)
+    say("spherical workload, reduced")
+    o, g = run_pair(cfg, 3)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def test_multimethod_workload_reduced():
+    # two state vectors (speeds 1 and 0.5), B on locals 1-4 only, 8 moving locals
+    cfg = W.multimethod(seed=5, ng=64, nl=24)
+    say("multimethod workload, reduced")
+    o, g = run_pair(cfg, 2)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def test_batched_workload_reduced():
+    # the batched generator (uneven Cartesian and spherical locals, linear motion)
+    # at reduced size, several steps
+    cfg = W.batched(seed=4, ng=64, nlocal=8, nmin=16, nmax=24)
+    say("batched workload, reduced")
+    o, g = run_pair(cfg, 3)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+_C4 = {}
+
+
+def _c4():
+    if "cfg" not in _C4:
+        _C4["cfg"] = W.batched(seed=4)
+        o = world_from_config(_C4["cfg"])
+        o.init_exact(0.0)
+        o.step(_C4["cfg"]["dt"], 1)
+        _C4["oracle"] = o
+    return _C4["cfg"], _C4["oracle"]
+
+
+@pytest.mark.parametrize("prec", [pw.PW_FP64, pw.PW_MIXED, pw.PW_MIXED_INC])
+def test_full_size_batched_one_step(prec):
+    # the benchmark workload at full size (256^3 + 64 locals) in the benchmark's
+    # launch configuration (batched schedule, graph), one step against the oracle
+    cfg, o = _c4()
+    say("full-size batched, 1 step, precision", prec)
+    g = pw.context_from_config(cfg, precision=prec, schedule=pw.PW_SCHED_BATCHED, use_graph=True)
+    g.init_exact(0.0)
+    g.rk4_step(cfg["dt"], 1)
+    tol = TOL64 if prec == pw.PW_FP64 else 1e-4
+    say("  worst rel err", compare(cfg, o, g, tol, norm="all"))
+    g.close()
 
 
 def test_full_size_two_patch_one_step():
