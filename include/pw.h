@@ -217,6 +217,30 @@ pw_status pw_exchange_ghosts(pw_context *ctx, double t);
  * cover one global cell. */
 pw_status pw_rk4_step(pw_context *ctx, double dt, int32_t nsteps);
 
+/* Run-time tuning parameters.  None changes a computed value: every setting
+ * evaluates the same arithmetic per cell and per ghost point. */
+typedef struct {
+  int32_t tile_z_global; /* planes per workgroup of the stage kernel, global patch (1..512) */
+  int32_t tile_z_local;  /* the same for local patches (1..512) */
+  int32_t g2l_run;       /* consecutive local-ghost bricks dealt to one XCD (1..64) */
+  int32_t l2g_run;       /* consecutive 64-entry effective-ghost groups dealt to one XCD (1..64) */
+} pw_tuning;
+
+/* Current tuning parameters. */
+pw_status pw_get_tuning(pw_context *ctx, pw_tuning *out);
+
+/* Set the tuning parameters (PW_EINVAL if one is out of range).  The tile lists
+ * are rebuilt and the next pw_rk4_step re-captures its graph. */
+pw_status pw_set_tuning(pw_context *ctx, const pw_tuning *t);
+
+/* Autotuner: times candidate settings on this context's own patches with HIP
+ * events over steps_per_trial steps of size dt each (after one untimed step),
+ * searching the two tile depths on a grid, then the two run lengths, and keeps
+ * the fastest (written to *best unless best is NULL).  It advances the state and
+ * the time by every step it takes, so call it before setting the initial data
+ * (or set it again afterwards).  On an error the previous settings are restored. */
+pw_status pw_autotune(pw_context *ctx, double dt, int32_t steps_per_trial, pw_tuning *best);
+
 /* Current coordinate time. */
 pw_status pw_get_time(const pw_context *ctx, double *t);
 

@@ -69,6 +69,7 @@ struct pw_context {
   long long stageCap = 0;
   double *dPartial = nullptr;
   bool layout_dirty = true, flags_valid = false;
+  pw_tuning tune = {TUNE_TZ_GLOBAL, TUNE_TZ_LOCAL, TUNE_G2L_RUN, TUNE_L2G_RUN};
   double t_host = 0.0;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -338,10 +339,10 @@ pw_status upload_layout(pw_context *c) {
     c->tileOff[pid] = (int)tiles.size();
     const int TX = pid == 0 ? StageTile<true>::TX : StageTile<false>::TX;
     const int TY = pid == 0 ? StageTile<true>::TY : StageTile<false>::TY;
-    const int TZ = pid == 0 ? StageTile<true>::TZ : StageTile<false>::TZ;
+    const int TZ = pid == 0 ? c->tune.tile_z_global : c->tune.tile_z_local;
     for (int z = 0; z < p.n[2]; z += TZ)
       for (int y = 0; y < p.n[1]; y += TY)
-        for (int x = 0; x < p.n[0]; x += TX) tiles.push_back(TileRec{pid, x, y, z});
+        for (int x = 0; x < p.n[0]; x += TX) tiles.push_back(TileRec{pid, x, y, z, std::min(TZ, p.n[2] - z)});
     c->tileCnt[pid] = (int)tiles.size() - c->tileOff[pid];
     if (p.coord == CART) c->nCartTiles = (int)tiles.size();
   }
@@ -497,6 +498,8 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     const int which = (parts & GH_LOCAL) ? 0 : 1;  // separate lists for concurrently running parts
     a.fb = c->fbList[which];
     a.fb_count = c->fbCount[which];
+    a.g2l_run = c->tune.g2l_run;
+    a.l2g_run = c->tune.l2g_run;
     launch_ghosts(st, a);
   }
 }
@@ -1088,6 +1091,86 @@ pw_status pw_rk4_step(pw_context *c, double dt, int32_t nsteps) {
   HIPCHK(c, hipGetLastError());
   c->steps_done += nsteps;
   return PW_OK;
+}
+
+pw_status pw_get_tuning(pw_context *c, pw_tuning *out) {
+  if (!c || !out) return PW_EINVAL;
+  *out = c->tune;
+  return PW_OK;
+}
+
+pw_status pw_set_tuning(pw_context *c, const pw_tuning *t) {
+  if (!c || !t) return PW_EINVAL;
+  if (t->tile_z_global < 1 || t->tile_z_global > 512 || t->tile_z_local < 1 || t->tile_z_local > 512 ||
+      t->g2l_run < 1 || t->g2l_run > 64 || t->l2g_run < 1 || t->l2g_run > 64)
+    return fail(c, PW_EINVAL, "tuning parameter out of range");
+  c->tune = *t;
+  c->layout_dirty = true;  // tile lists are rebuilt and the step graph re-captured
+  return PW_OK;
+}
+
+// Coordinate search over the tuning parameters, each candidate timed with HIP
+// events over steps_per_trial steps (after one untimed step, which also captures
+// the step graph): the tile depths on a global x local grid, then the brick run,
+// then the group run.
+pw_status pw_autotune(pw_context *c, double dt, int32_t steps_per_trial, pw_tuning *best) {
+  if (!c || !(dt > 0) || steps_per_trial < 1) return PW_EINVAL;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, PW_EDEVICE, "event creation failed");
+  }
+  pw_status rc = PW_OK;
+  auto trial = [&](const pw_tuning &t, float &ms) -> pw_status {
+    pw_status r = pw_set_tuning(c, &t);
+    if (r) return r;
+    r = pw_rk4_step(c, dt, 1);
+    if (r) return r;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(c, PW_EDEVICE, "event record failed");
+    r = pw_rk4_step(c, dt, steps_per_trial);
+    if (r) return r;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return fail(c, PW_EDEVICE, "event timing failed");
+    return check_error_flag(c);
+  };
+  pw_tuning cur = c->tune, bestT = cur;
+  float bestMs = 3.0e38f, ms = 0.0f;
+  static const int tzg[3] = {16, 32, 64}, tzl[3] = {4, 8, 16}, runs_g2l[3] = {4, 8, 16}, runs_l2g[3] = {2, 4, 8};
+  for (int a = 0; a < 3 && !rc; a++)
+    for (int b = 0; b < 3 && !rc; b++) {
+      pw_tuning t = bestT;
+      t.tile_z_global = tzg[a];
+      t.tile_z_local = tzl[b];
+      rc = trial(t, ms);
+      if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
+    }
+  if (has_locals(c)) {
+    const pw_tuning base = bestT;
+    for (int a = 0; a < 3 && !rc; a++) {
+      pw_tuning t = base;
+      t.g2l_run = runs_g2l[a];
+      rc = trial(t, ms);
+      if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
+    }
+    const pw_tuning base2 = bestT;
+    for (int a = 0; a < 3 && !rc; a++) {
+      pw_tuning t = base2;
+      t.l2g_run = runs_l2g[a];
+      rc = trial(t, ms);
+      if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    (void)pw_set_tuning(c, &cur);
+    return rc;
+  }
+  rc = pw_set_tuning(c, &bestT);
+  if (!rc && best) *best = bestT;
+  return rc;
 }
 
 pw_status pw_get_time(const pw_context *c, double *t) {

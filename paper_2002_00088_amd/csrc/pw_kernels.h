@@ -5,33 +5,25 @@
 
 #include "pw_internal.h"
 
-// Stage-kernel tiles: TX x TY columns, up to TZ planes per workgroup.  The
-// global patch (large, regular) takes deeper tiles: fewer re-read halo planes
-// per computed cell; local patches (a few tens of cells per side) take shorter
-// ones: better balance.
-#ifndef ST_TY_GLOBAL
-#define ST_TY_GLOBAL 8
-#endif
-#ifndef ST_TZ_GLOBAL
-#define ST_TZ_GLOBAL 32
-#endif
-#ifndef ST_TZ_LOCAL
-#define ST_TZ_LOCAL 8
-#endif
+// Stage-kernel tiles: TX x TY columns per workgroup; the number of planes a
+// workgroup marches through (the tile depth) is a run-time tuning parameter,
+// one for the global patch and one for local patches.
 template <bool GLOB>
 struct StageTile {
   static constexpr int TX = 32;
-  static constexpr int TY = GLOB ? ST_TY_GLOBAL : 8;
-  static constexpr int TZ = GLOB ? ST_TZ_GLOBAL : ST_TZ_LOCAL;
+  static constexpr int TY = 8;
   static constexpr int PX = TX + 6, PY = TY + 6, PW = PX * PY;  // LDS plane with a 3-cell halo
   static constexpr int THREADS = TX * TY;
 };
+// Tuning defaults (measured on the batched 256^3 + 64-patch workload).
+#define TUNE_TZ_GLOBAL 32
+#define TUNE_TZ_LOCAL 8
+#define TUNE_G2L_RUN 8
+#define TUNE_L2G_RUN 4
 #define DIAG_N 23
 #define BRICK_THREADS 192
 #define BRICK_LDS_BYTES 40960
 #define L2G_BLOCKS 2048  // a multiple of 8
-#define L2G_RUN 4
-#define G2L_RUN 8
 #define L2G_WAVES 3
 #define L2G_LDS_BYTES 36864
 #define BUCKET_SORT_LDS 4096
@@ -39,7 +31,7 @@ struct StageTile {
 namespace pw {
 
 struct TileRec {
-  int32_t patch, x0, y0, z0;
+  int32_t patch, x0, y0, z0, nz;  // nz planes from z0 (the tile depth is a tuning parameter)
 };
 
 // A ghost cell: patch id and packed padded coordinates (i+3) | (j+3) << 10 | (k+3) << 20.
@@ -146,6 +138,7 @@ struct GhostArgs {
   unsigned long long *skips;
   FallbackRec *fb;  // capacity: every interpatch target of this part
   int *fb_count;
+  int g2l_run, l2g_run;  // consecutive bricks / groups per XCD run
 };
 
 struct StageArgs {

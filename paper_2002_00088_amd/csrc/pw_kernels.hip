@@ -427,14 +427,14 @@ __device__ __forceinline__ int xcd_spread(int v, int K) {
 // ---------------------------------------------------------------------------
 template <typename TB, typename TC, int Pts>
 __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose,
-                                                             const GBrick *bricks, int nbricks, int sv,
+                                                             const GBrick *bricks, int nbricks, int run, int sv,
                                                              int stage, const uint8_t *dvalid,
                                                              unsigned long long *skips, FallbackRec *fb,
                                                              int *fb_count) {
   __shared__ TC box[BRICK_LDS_BYTES / sizeof(TC)];
   __shared__ int blo[3], bhi[3];
-  // runs of G2L_RUN consecutive bricks (which share donor cells) on one XCD
-  const int bidx = xcd_spread(blockIdx.x, G2L_RUN);
+  // runs of `run` consecutive bricks (which share donor cells) on one XCD
+  const int bidx = xcd_spread(blockIdx.x, run);
   if (bidx >= nbricks) return;
   const GBrick B = bricks[bidx];
   const PatchDev &r = P[B.patch];
@@ -641,7 +641,7 @@ __device__ __forceinline__ float bcast_t(float v, int lane) {
 template <typename TB, typename TC, int Pts>
 __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_l2g_box(
     const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list, const int *count,
-    const int32_t *cover, int sv, int stage, unsigned long long *skips, FallbackRec *fb, int *fb_count) {
+    int run, const int32_t *cover, int sv, int stage, unsigned long long *skips, FallbackRec *fb, int *fb_count) {
   constexpr int CAP = L2G_LDS_BYTES / sizeof(TC);
   __shared__ TC box[CAP];
   __shared__ TC red[L2G_WAVES - 1][5][64];
@@ -653,11 +653,11 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
   const int la = lane % Pts, lb = lane / Pts;
   const bool tap_lane = lane < Pts * Pts;
   TB *TG = stage_buf<TB>(G0, sv, stage);
-  // runs of L2G_RUN consecutive groups (neighbouring donor boxes) on one XCD
+  // runs of `run` consecutive groups (neighbouring donor boxes) on one XCD
   const int ngroups = (n + 63) / 64;
-  const int nv = (ngroups + 8 * L2G_RUN - 1) / (8 * L2G_RUN) * (8 * L2G_RUN);
+  const int nv = (ngroups + 8 * run - 1) / (8 * run) * (8 * run);
   for (int vb = blockIdx.x; vb < nv; vb += gridDim.x) {
-    const int grp = xcd_spread(vb, L2G_RUN);
+    const int grp = xcd_spread(vb, run);
     if (grp >= ngroups) continue;
     const int g0 = grp * 64;
     if (tid < 64) {
@@ -1082,7 +1082,7 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
                                                int ntiles, int chunk, const uint8_t *gflag, int sv, double dt,
                                                double v2, double eps) {
   using TL = StageTile<GLOB>;
-  constexpr int ST_TX = TL::TX, ST_TY = TL::TY, ST_TZ = TL::TZ, ST_PX = TL::PX, ST_PW = TL::PW;
+  constexpr int ST_TX = TL::TX, ST_TY = TL::TY, ST_PX = TL::PX, ST_PW = TL::PW;
   constexpr int ST_THREADS = TL::THREADS;
   __shared__ TC Bc[2][5][ST_PW];
   __shared__ TC Ad[2][ST_PW];
@@ -1098,7 +1098,7 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
   const bool inpad = (i < p.n[0] + PW_NG) && (j < p.n[1] + PW_NG);
   const bool icol = (i < p.n[0]) && (j < p.n[1]);
   const int z0 = tl.z0;
-  const int nz = min(ST_TZ, p.n[2] - z0);
+  const int nz = tl.nz;
   const TIN *in = (const TIN *)(STAGE == 0 ? (sizeof(TIN) == 8 ? (const void *)p.u[sv] : (const void *)p.us[sv])
                                             : (STAGE == 2 ? p.vb[sv] : p.va[sv]));
   float *Us = p.us[sv];  // FP32 copy of u (mixed path): written with u_{n+1} by the last stage
@@ -1638,21 +1638,22 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
   if (!g2l && !l2g) return;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
   if (g2l) {
-    const int bchunk = (a.n_bricks + 8 * G2L_RUN - 1) / (8 * G2L_RUN);
+    const int run = a.g2l_run;
+    const int bchunk = (a.n_bricks + 8 * run - 1) / (8 * run);
     if (a.Pts == 5)
-      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 5>), dim3(8 * G2L_RUN * bchunk), dim3(BRICK_THREADS), 0, s, a.P,
-                         a.pose, a.bricks, a.n_bricks, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
+      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 5>), dim3(8 * run * bchunk), dim3(BRICK_THREADS), 0, s, a.P,
+                         a.pose, a.bricks, a.n_bricks, run, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
     else
-      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 6>), dim3(8 * G2L_RUN * bchunk), dim3(BRICK_THREADS), 0, s, a.P,
-                         a.pose, a.bricks, a.n_bricks, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
+      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 6>), dim3(8 * run * bchunk), dim3(BRICK_THREADS), 0, s, a.P,
+                         a.pose, a.bricks, a.n_bricks, run, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
   }
   if (l2g) {
     if (a.Pts == 5)
       hipLaunchKernelGGL((k_l2g_box<TB, TC, 5>), dim3(L2G_BLOCKS), dim3(64 * L2G_WAVES), 0, s, a.P, a.pose, a.efflist,
-                         a.effcount, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count);
+                         a.effcount, a.l2g_run, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count);
     else
       hipLaunchKernelGGL((k_l2g_box<TB, TC, 6>), dim3(L2G_BLOCKS), dim3(64 * L2G_WAVES), 0, s, a.P, a.pose, a.efflist,
-                         a.effcount, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count);
+                         a.effcount, a.l2g_run, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count);
   }
   hipLaunchKernelGGL(k_fallback<TB>, dim3(64), dim3(256), 0, s, a.P, a.pose, a.fb, a.fb_count, a.sv, a.stage, a.ex,
                      a.v, a.tdev, a.tmul, a.dt);

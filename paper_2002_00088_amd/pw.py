@@ -34,7 +34,7 @@ STATUS = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EDEVICE", -4: "P
 EXPORTS = ["pw_create", "pw_create_patch", "pw_set_exact", "pw_init_exact", "pw_set_state", "pw_get_state",
            "pw_get_state_full", "pw_get_flags", "pw_exchange_ghosts", "pw_rk4_step", "pw_get_time",
            "pw_diagnostics", "pw_counters", "pw_live_cells", "pw_enable_timing", "pw_kernel_times",
-           "pw_last_error", "pw_destroy"]
+           "pw_get_tuning", "pw_set_tuning", "pw_autotune", "pw_last_error", "pw_destroy"]
 KERNEL_CLASSES = ["pose", "ghost_s1", "ghost_s2", "ghost_s3", "ghost_s4", "stage_s1", "stage_s2", "stage_s3",
                   "stage_s4", "flags", "finalize", "gstage_s1", "gstage_s2", "gstage_s3", "gstage_s4"]
 
@@ -66,6 +66,11 @@ class Diag(C.Structure):
     _fields_ = [("max_abs", C.c_double * 5), ("sum_sq", C.c_double * 5), ("err_max", C.c_double * 5),
                 ("err_sum_sq", C.c_double * 5), ("int_rel_err", C.c_double), ("live_cells", C.c_double),
                 ("volume", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("tile_z_global", C.c_int32), ("tile_z_local", C.c_int32), ("g2l_run", C.c_int32),
+                ("l2g_run", C.c_int32)]
 
 
 class Counters(C.Structure):
@@ -102,6 +107,9 @@ def load():
     L.pw_live_cells.argtypes = [vp, C.POINTER(C.c_int64)]
     L.pw_enable_timing.argtypes = [vp, C.c_int32]
     L.pw_kernel_times.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+    L.pw_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.pw_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.pw_autotune.argtypes = [vp, C.c_double, C.c_int32, C.POINTER(Tuning)]
     L.pw_last_error.restype = C.c_char_p
     L.pw_last_error.argtypes = [vp]
     L.pw_destroy.argtypes = [vp]
@@ -287,6 +295,22 @@ class Context:
         self._chk(self.L.pw_counters(self.h, C.byref(c)))
         return dict(skip_local=c.skip_local, skip_eff=c.skip_eff, skip_uncover=c.skip_uncover,
                     n_uncover=c.n_uncover, steps=c.steps)
+
+    def tuning(self):
+        t = Tuning()
+        self._chk(self.L.pw_get_tuning(self.h, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{**self.tuning(), **kw})
+        self._chk(self.L.pw_set_tuning(self.h, C.byref(t)))
+
+    def autotune(self, dt, steps_per_trial=3):
+        """Time candidate tunings on this context (advances the state; set the
+        initial data afterwards) and keep the fastest; returns it."""
+        t = Tuning()
+        self._chk(self.L.pw_autotune(self.h, dt, steps_per_trial, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in Tuning._fields_}
 
     def enable_timing(self, on=True):
         self._chk(self.L.pw_enable_timing(self.h, 1 if on else 0))

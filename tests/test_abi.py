@@ -37,6 +37,7 @@ def test_ctypes_layout_matches_header(tmp_path):
         "pw_exact_desc": [f for f, _ in pw.ExactDesc._fields_],
         "pw_diag": [f for f, _ in pw.Diag._fields_],
         "pw_counters_t": [f for f, _ in pw.Counters._fields_],
+        "pw_tuning": [f for f, _ in pw.Tuning._fields_],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pw.h"', "int main(void){"]
     for st, fs in fields.items():
@@ -50,7 +51,7 @@ def test_ctypes_layout_matches_header(tmp_path):
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     out = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
     cls = {"pw_config": pw.Config, "pw_patch_desc": pw.PatchDesc, "pw_exact_desc": pw.ExactDesc,
-           "pw_diag": pw.Diag, "pw_counters_t": pw.Counters}
+           "pw_diag": pw.Diag, "pw_counters_t": pw.Counters, "pw_tuning": pw.Tuning}
     for st, k in cls.items():
         assert int(out[st]) == C.sizeof(k), st
         for f, _ in k._fields_:

@@ -292,6 +292,45 @@ def test_full_size_two_patch_one_step():
     say("  worst rel err", compare(cfg, o, g, TOL64))
 
 
+def test_tuning_changes_no_value():
+    # tile depths and XCD run lengths only reorder work: the state after a few
+    # steps is bitwise the same
+    cfg = W.batched(seed=4, ng=64, nlocal=8, nmin=16, nmax=24)
+    outs = []
+    for tune in (None, dict(tile_z_global=16, tile_z_local=4, g2l_run=2, l2g_run=8),
+                 dict(tile_z_global=64, tile_z_local=3, g2l_run=16, l2g_run=1)):
+        g = pw.context_from_config(cfg, precision=pw.PW_MIXED)
+        if tune:
+            g.set_tuning(**tune)
+            assert g.tuning() == {**g.tuning(), **tune}
+        g.init_exact(0.0)
+        g.rk4_step(cfg["dt"], 3)
+        outs.append([g.get_state(pid) for pid in range(len(cfg["patches"]))])
+        g.close()
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b, equal_nan=True)
+
+
+def test_autotune_then_parity():
+    cfg = W.two_patch(seed=2, ng=48, nl=40, P=6)
+    g = pw.context_from_config(cfg)
+    g.init_exact(0.0)
+    best = g.autotune(cfg["dt"], 1)
+    say("autotuned", best)
+    assert best == g.tuning()
+    assert 1 <= best["tile_z_global"] <= 512 and 1 <= best["tile_z_local"] <= 512
+    with pytest.raises(pw.PwError):
+        g.set_tuning(tile_z_global=0)
+    assert g.tuning() == best
+    g.init_exact(0.0)
+    g.rk4_step(cfg["dt"], 2)
+    o = world_from_config(cfg)
+    o.init_exact(0.0)
+    o.step(cfg["dt"], 2)
+    say("  worst rel err", compare(cfg, o, g, TOL64, check_counts=False))
+
+
 def test_error_paths():
     cfg = W.two_patch(seed=2, ng=32, nl=24, P=6, motion=W.LINEAR)
     cfg["patches"][1]["vel"] = [40.0, 0, 0]
