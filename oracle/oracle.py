@@ -49,6 +49,8 @@ def lib():
         L.or_add_patch.restype = C.c_int
         L.or_add_patch.argtypes = [vp, C.c_int, C.c_int, ip, dp, dp, ip, dp, C.c_int, dp, dp,
                                    C.c_double, C.c_double, C.c_double, C.c_uint]
+        L.or_set_spin.restype = C.c_int
+        L.or_set_spin.argtypes = [vp, C.c_int, dp]
         L.or_set_exact_plane.argtypes = [vp, C.c_int, C.c_double, C.c_double, dp, C.c_double]
         L.or_set_exact_gauss.argtypes = [vp, C.c_int, C.c_int, dp, dp, dp]
         L.or_set_state.argtypes = [vp, C.c_int, C.c_int, dp, C.c_double]
@@ -133,6 +135,10 @@ class OracleWorld:
                                   int(d.get("sv_mask", 1)))
         if pid < 0:
             raise ValueError("oracle rejected patch")
+        if any(x != 0.0 for x in d.get("spin", (0.0, 0.0, 0.0))):
+            sp, spp = _d(d["spin"])
+            if self.L.or_set_spin(self.h, pid, spp) != 0:
+                raise ValueError("oracle rejected spin")
         self.patches.append(dict(d))
         return pid
 

@@ -86,7 +86,8 @@ typedef struct {
   int n[3], N[3];           /* interior cells, cells incl. ghosts (n + 2 NG) */
   double lo[3], hi[3], dx[3];
   int periodic[3];
-  double R[3][3];           /* ZYZ Euler rotation, fixed in time */
+  double R[3][3];           /* ZYZ Euler rotation at t = 0 */
+  double spin[3];           /* angular velocity of a rotation about the centre (background frame) */
   int motion;
   double c0[3], vel[3], radius, speed, phase;
   unsigned sv_mask;
@@ -144,6 +145,39 @@ static void center_hd(const or_patch *p, hd t, hd c[3]) {
   }
 }
 
+/* Orientation at time t: R(t) = Q(t) R(0), Q(t) the rotation by |w| t about the
+ * axis w/|w| of the patch's angular velocity w (Rodrigues' formula,
+ * Q = I + sin(th) K + (1 - cos(th)) K^2 with K the cross-product matrix of the
+ * unit axis).  Without spin R(t) = R(0). */
+static void orient_hd(const or_patch *p, hd t, hd Rt[3][3]) {
+  const double wn = sqrt(p->spin[0] * p->spin[0] + p->spin[1] * p->spin[1] + p->spin[2] * p->spin[2]);
+  if (wn == 0.0) {
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) Rt[a][b] = hd_const(p->R[a][b]);
+    return;
+  }
+  const double k[3] = {p->spin[0] / wn, p->spin[1] / wn, p->spin[2] / wn};
+  const double K[3][3] = {{0, -k[2], k[1]}, {k[2], 0, -k[0]}, {-k[1], k[0], 0}};
+  double K2[3][3];
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      K2[a][b] = 0.0;
+      for (int m = 0; m < 3; m++) K2[a][b] += K[a][m] * K[m][b];
+    }
+  hd th = hd_scale(wn, t);
+  hd sn = hd_sin(th), omc = hd_add(hd_const(1.0), hd_scale(-1.0, hd_cos(th)));
+  hd Q[3][3];
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++)
+      Q[a][b] = hd_add(hd_const(a == b ? 1.0 : 0.0), hd_add(hd_scale(K[a][b], sn), hd_scale(K2[a][b], omc)));
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      hd s = hd_const(0.0);
+      for (int m = 0; m < 3; m++) s = hd_add(s, hd_scale(p->R[m][b], Q[a][m]));
+      Rt[a][b] = s;
+    }
+}
+
 /* in = (t, x'1, x'2, x'3), out = (t, X, Y, Z) */
 static void map_hd(const or_patch *p, const hd in[4], hd out[4]) {
   hd y[3];
@@ -155,12 +189,13 @@ static void map_hd(const or_patch *p, const hd in[4], hd out[4]) {
     y[1] = hd_mul(r, hd_mul(st, sp));
     y[2] = hd_mul(r, ct);
   }
-  hd c[3];
+  hd c[3], Rt[3][3];
   center_hd(p, in[0], c);
+  orient_hd(p, in[0], Rt);
   out[0] = in[0];
   for (int a = 0; a < 3; a++) {
     hd s = c[a];
-    for (int b = 0; b < 3; b++) s = hd_add(s, hd_scale(p->R[a][b], y[b]));
+    for (int b = 0; b < 3; b++) s = hd_add(s, hd_mul(Rt[a][b], y[b]));
     out[1 + a] = s;
   }
 }
@@ -180,9 +215,11 @@ static void center_val(const or_patch *p, double t, double c[3]) {
 /* inverse map: background X -> numerical x' of patch p at time t */
 static void map_inv(const or_patch *p, double t, const double X[3], double xp[3]) {
   double c[3], d[3], y[3];
+  hd Rt[3][3];
   center_val(p, t, c);
+  orient_hd(p, hd_const(t), Rt);
   for (int a = 0; a < 3; a++) d[a] = X[a] - c[a];
-  for (int b = 0; b < 3; b++) y[b] = p->R[0][b] * d[0] + p->R[1][b] * d[1] + p->R[2][b] * d[2];
+  for (int b = 0; b < 3; b++) y[b] = Rt[0][b].a * d[0] + Rt[1][b].a * d[1] + Rt[2][b].a * d[2];
   if (p->coord == CART) {
     for (int a = 0; a < 3; a++) xp[a] = y[a];
   } else {
@@ -1113,6 +1150,14 @@ void or_jac_at(const or_world *w, int pi, double t, const double *xp, double *E1
 
 void or_map_fwd(const or_world *w, int pi, double t, const double *xp, double *X) { map_fwd(&w->p[pi], t, xp, X); }
 void or_map_inv(const or_world *w, int pi, double t, const double *X, double *xp) { map_inv(&w->p[pi], t, X, xp); }
+
+/* Angular velocity (background frame) of a rotation of patch pi about its centre. */
+int or_set_spin(or_world *w, int pi, const double *spin) {
+  if (pi < 1 || pi >= w->np) return -1;
+  for (int a = 0; a < 3; a++) w->p[pi].spin[a] = spin[a];
+  w->flags_valid = 0;
+  return 0;
+}
 
 void or_rotation(const or_world *w, int pi, double *R9) {
   for (int a = 0; a < 3; a++)

@@ -19,11 +19,15 @@ STATIC, LINEAR, CIRCLE = 0, 1, 2
 
 
 def patch(n, lo, hi, coord=CART, is_global=0, periodic=(0, 0, 0), euler=(0.0, 0.0, 0.0), motion=STATIC,
-          c0=(0.0, 0.0, 0.0), vel=(0.0, 0.0, 0.0), radius=0.0, speed=0.0, phase=0.0, sv_mask=1):
+          c0=(0.0, 0.0, 0.0), vel=(0.0, 0.0, 0.0), radius=0.0, speed=0.0, phase=0.0, sv_mask=1,
+          spin=(0.0, 0.0, 0.0)):
+    """spin: angular velocity (background frame) of a rotation of the patch about
+    its centre, R(t) = rotation by |spin| t about spin/|spin| composed with the
+    Euler rotation."""
     return dict(n=[int(x) for x in n], lo=[float(x) for x in lo], hi=[float(x) for x in hi], coord=int(coord),
                 is_global=int(is_global), periodic=[int(x) for x in periodic], euler=[float(x) for x in euler],
                 motion=int(motion), c0=[float(x) for x in c0], vel=[float(x) for x in vel], radius=float(radius),
-                speed=float(speed), phase=float(phase), sv_mask=int(sv_mask))
+                speed=float(speed), phase=float(phase), sv_mask=int(sv_mask), spin=[float(x) for x in spin])
 
 
 def random_euler(rng):

@@ -211,12 +211,51 @@ def test_circle_moving_cartesian_metric_closed_form():
         assert abs(C[0]) < 1e-14 and sg == pytest.approx(1.0, rel=1e-14)
 
 
-def test_metric_matches_inverse_map_finite_differences():
+def _rodrigues(w, t):
+    """Rotation by |w| t about w/|w| (scipy's rotation-vector form)."""
+    from scipy.spatial.transform import Rotation
+    return Rotation.from_rotvec(np.asarray(w, float) * t).as_matrix()
+
+
+def test_spinning_cartesian_metric_closed_form():
+    # a Cartesian patch on a circle and spinning about its centre: X = c(t) + R(t) y,
+    # R(t) = Q(w t) R0.  The shift is beta = b + w_p x y and
+    # C^i = (w_p x (w_p x y) + 2 w_p x b - a)^i / v^2, with b = R^T c', a = R^T c'',
+    # w_p = R^T w (second time derivative of y = R^T (X - c) at fixed X).
+    v = 0.9
+    eu = [0.4, 1.1, 2.3]
+    rho, speed, psi = 2.0, 0.3, 0.7
+    spin = np.array([0.2, -0.35, 0.5])
+    w = _world_with(W.patch([8] * 3, [-2] * 3, [2] * 3, euler=eu, motion=CIRCLE, radius=rho, speed=speed, phase=psi,
+                            spin=spin), v)
+    R0 = zyz(eu)
+    om = speed / rho
+    for t in (0.0, 1.3):
+        R = _rodrigues(spin, t) @ R0
+        c = rho * np.array([math.cos(om * t + psi), math.sin(om * t + psi), 0])
+        cd = rho * om * np.array([-math.sin(om * t + psi), math.cos(om * t + psi), 0])
+        cdd = -rho * om * om * np.array([math.cos(om * t + psi), math.sin(om * t + psi), 0])
+        y = np.array([0.3, -0.5, 1.2])
+        assert np.allclose(w.map_fwd(1, t, y), c + R @ y, atol=1e-13)
+        b, a, wp = R.T @ cd, R.T @ cdd, R.T @ spin
+        beta = b + np.cross(wp, y)
+        acc = np.cross(wp, np.cross(wp, y)) + 2 * np.cross(wp, b) - a
+        g, C, sg = w.metric(1, 0, t, y)
+        assert g[0, 0] == pytest.approx(-1 / v ** 2, rel=1e-14)
+        assert np.allclose(g[0, 1:], beta / v ** 2, atol=1e-13)
+        assert np.allclose(g[1:, 1:], np.eye(3) - np.outer(beta, beta) / v ** 2, atol=1e-13)
+        assert np.allclose(C[1:], acc / v ** 2, atol=1e-13)
+        assert abs(C[0]) < 1e-13 and sg == pytest.approx(1.0, rel=1e-13)
+
+
+@pytest.mark.parametrize("spin", [(0.0, 0.0, 0.0), (0.25, -0.4, 0.3)])
+def test_metric_matches_inverse_map_finite_differences(spin):
     """g^{mu nu} = Lam eta^{-1} Lam^T and C^l = -eta^{ab} d_a d_b x'^l, with
     Lam = d x'/d(t,X) taken by finite differences of the inverse map."""
     v = 0.7
     w = _world_with(W.patch([8] * 3, [0.5, 0.5, 0.0], [5, 2.6, 2 * math.pi], coord=SPH, periodic=(0, 0, 1),
-                            euler=[0.3, 0.9, -0.4], motion=LINEAR, c0=(0.2, -0.1, 0.3), vel=(0.15, -0.1, 0.05)), v)
+                            euler=[0.3, 0.9, -0.4], motion=LINEAR, c0=(0.2, -0.1, 0.3), vel=(0.15, -0.1, 0.05),
+                            spin=spin), v)
     t0 = 0.8
     xp0 = np.array([1.7, 1.2, 2.0])
     X0 = w.map_fwd(1, t0, xp0)
@@ -508,6 +547,11 @@ def _two_patch_plane(ng, motion):
     g = W.patch([ng] * 3, [-L] * 3, [L] * 3, is_global=1)
     if motion == "fixed":
         loc = W.patch([nl] * 3, [-half] * 3, [half] * 3, euler=[0.3, 0.8, 1.9], c0=(-0.5, -0.5, -0.5))
+    elif motion == "rotating":
+        # the paper's rotating case uses Omega = 0.01; a faster spin turns the patch
+        # by 0.2 rad over the run so the rotation terms matter at these resolutions
+        loc = W.patch([nl] * 3, [-half] * 3, [half] * 3, euler=[0.3, 0.8, 1.9], c0=(-0.5, -0.5, -0.5),
+                      spin=(0.0, 0.0, 0.1))
     else:
         loc = W.patch([nl] * 3, [-half] * 3, [half] * 3, euler=[0.3, 0.8, 1.9], motion=LINEAR, c0=(-0.5, -0.5, 0.0),
                       vel=(0.1, 0.1, 0.0))
@@ -516,7 +560,7 @@ def _two_patch_plane(ng, motion):
     return cfg, dxg / 2
 
 
-@pytest.mark.parametrize("motion", ["fixed", "translating"])
+@pytest.mark.parametrize("motion", ["fixed", "translating", "rotating"])
 def test_two_patch_convergence(motion):
     errs = []
     T = 2.0
