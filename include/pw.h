@@ -99,14 +99,17 @@ typedef struct {
 /*
  * Patch description (Secs. 2.1 and 2.4.1): numerical box [lo,hi] of n cells per axis
  * (cell-centred), topology map M (Cartesian identity, or spherical (r,theta,phi)),
- * fixed ZYZ Euler rotation R and centre motion c(t), so that the background
- * Cartesian coordinates are X_B = c(t) + R M(x').
+ * orientation R(t) and centre motion c(t), so that the background Cartesian
+ * coordinates are X_B = c(t) + R(t) M(x').
  *   motion PW_STATIC: c = c0; PW_LINEAR: c = c0 + vel t;
  *          PW_CIRCLE: c = c0 + radius (cos(w t + phase), sin(w t + phase), 0), w = speed/radius.
+ *   orientation R(t) = Q(t) R0: R0 the ZYZ Euler rotation euler_zyz, Q(t) the rotation
+ *          by |spin| t about spin/|spin| (a patch rotating about its centre with
+ *          angular velocity spin, background frame; spin = 0: R(t) = R0).
  *   periodic[a]: axis a wraps (the spherical phi axis; every axis of a periodic global box).
  *   sv_mask: bit s set if the patch carries state vector s.
  * The first patch created must be the global one (is_global = 1, Cartesian, static,
- * unrotated); every later patch is a local patch.
+ * unrotated, no spin); every later patch is a local patch.
  */
 typedef struct {
   int32_t coord;
@@ -119,6 +122,7 @@ typedef struct {
   double c0[3], vel[3];
   double radius, speed, phase;
   uint32_t sv_mask;
+  double spin[3];
 } pw_patch_desc;
 
 /*

@@ -804,7 +804,8 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
   if (d->motion == PW_CIRCLE && !(d->radius > 0)) return fail(c, PW_EINVAL, "circle motion needs radius > 0");
   if (first) {
     if (d->coord != PW_CART || d->motion != PW_STATIC || d->euler_zyz[0] != 0 || d->euler_zyz[1] != 0 ||
-        d->euler_zyz[2] != 0 || d->c0[0] != 0 || d->c0[1] != 0 || d->c0[2] != 0)
+        d->euler_zyz[2] != 0 || d->c0[0] != 0 || d->c0[1] != 0 || d->c0[2] != 0 || d->spin[0] != 0 ||
+        d->spin[1] != 0 || d->spin[2] != 0)
       return fail(c, PW_EINVAL, "the global patch is Cartesian, static and unrotated");
   } else {
     if (d->periodic[0] || d->periodic[1] || (d->periodic[2] && d->coord != PW_SPH))
@@ -840,6 +841,7 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     p.idx[a] = 1.0 / p.dx[a];
     p.c0[a] = d->c0[a];
     p.vel[a] = d->vel[a];
+    p.spin[a] = d->spin[a];
   }
   p.radius = d->radius;
   p.omega = d->motion == PW_CIRCLE ? d->speed / d->radius : 0.0;
@@ -1066,6 +1068,8 @@ pw_status pw_rk4_step(pw_context *c, double dt, int32_t nsteps) {
     double sp = 0;
     if (d.motion == PW_LINEAR) sp = sqrt(d.vel[0] * d.vel[0] + d.vel[1] * d.vel[1] + d.vel[2] * d.vel[2]);
     if (d.motion == PW_CIRCLE) sp = fabs(d.speed);
+    // a spinning patch: points at distance rho from the centre move at |spin| rho more
+    sp += sqrt(d.spin[0] * d.spin[0] + d.spin[1] * d.spin[1] + d.spin[2] * d.spin[2]) * bound_radius(d);
     if (sp * dt >= hmin) return fail(c, PW_EMOTION, "a patch moves one global cell or more within a step");
   }
   pw_status rc = ensure_flags(c);

@@ -41,12 +41,15 @@ struct PatchDev {
   // spherical patches: sin, cos of theta_j (j = -3 .. n1+2) and of phi_k
   // (k = -3 .. n2+2), laid out [sin th][cos th][sin ph][cos ph]; null otherwise
   const double *trig;
+  double spin[3];  // angular velocity of a rotation about the centre (background frame)
 };
 
 // Pose of a patch at one stage time: centre, its first and second time
-// derivatives, and their components along the patch axes (b = R^T c', a = R^T c'').
+// derivatives, orientation R(t), the angular velocity w, and the components of
+// c', c'' and w along the patch axes (b = R^T c', a = R^T c'', wp = R^T w).
 struct PoseDev {
   double c[3], cd[3], cdd[3], b[3], a[3];
+  double R[9], w[3], wp[3];
 };
 
 struct ExactDev {
@@ -89,10 +92,60 @@ __host__ __device__ inline void pose_at(const PatchDev &p, double t, PoseDev &o)
     o.cdd[0] = -p.radius * p.omega * p.omega * c;
     o.cdd[1] = -p.radius * p.omega * p.omega * s;
   }
-  for (int i = 0; i < 3; i++) {
-    o.b[i] = p.R[0 + i] * o.cd[0] + p.R[3 + i] * o.cd[1] + p.R[6 + i] * o.cd[2];
-    o.a[i] = p.R[0 + i] * o.cdd[0] + p.R[3 + i] * o.cdd[1] + p.R[6 + i] * o.cdd[2];
+  // orientation: R(t) = Q R(0), Q the rotation by |w| t about w / |w|
+  // (Rodrigues: Q = I + sin(th) K + (1 - cos(th)) K^2, K the cross-product matrix of the axis)
+  const double wn = sqrt(p.spin[0] * p.spin[0] + p.spin[1] * p.spin[1] + p.spin[2] * p.spin[2]);
+  for (int a = 0; a < 3; a++) o.w[a] = p.spin[a];
+  if (wn == 0.0) {
+    for (int m = 0; m < 9; m++) o.R[m] = p.R[m];
+  } else {
+    const double k[3] = {p.spin[0] / wn, p.spin[1] / wn, p.spin[2] / wn};
+    const double K[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+    const double sn = sin(wn * t), omc = 1.0 - cos(wn * t);
+    double Q[9];
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) {
+        double k2 = 0.0;
+        for (int m = 0; m < 3; m++) k2 += K[3 * a + m] * K[3 * m + b];
+        Q[3 * a + b] = (a == b ? 1.0 : 0.0) + sn * K[3 * a + b] + omc * k2;
+      }
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) {
+        double s = 0.0;
+        for (int m = 0; m < 3; m++) s += Q[3 * a + m] * p.R[3 * m + b];
+        o.R[3 * a + b] = s;
+      }
   }
+  for (int i = 0; i < 3; i++) {
+    o.b[i] = o.R[0 + i] * o.cd[0] + o.R[3 + i] * o.cd[1] + o.R[6 + i] * o.cd[2];
+    o.a[i] = o.R[0 + i] * o.cdd[0] + o.R[3 + i] * o.cdd[1] + o.R[6 + i] * o.cdd[2];
+    o.wp[i] = o.R[0 + i] * o.w[0] + o.R[3 + i] * o.w[1] + o.R[6 + i] * o.w[2];
+  }
+}
+
+// Frame terms at the patch-frame point y (Eqs. eom1-eom3 in the moving frame):
+// the shift beta = b + wp x y (minus the time derivative of y at fixed X) and
+// acc = a - 2 wp x b - wp x (wp x y) (minus the second time derivative of y at
+// fixed X).  Without spin these are b and a exactly.
+__host__ __device__ inline void frame_terms(const PoseDev &ps, const double y[3], double beta[3], double acc[3]) {
+  const double *w = ps.wp;
+  const double wy[3] = {w[1] * y[2] - w[2] * y[1], w[2] * y[0] - w[0] * y[2], w[0] * y[1] - w[1] * y[0]};
+  const double wb[3] = {w[1] * ps.b[2] - w[2] * ps.b[1], w[2] * ps.b[0] - w[0] * ps.b[2], w[0] * ps.b[1] - w[1] * ps.b[0]};
+  const double wwy[3] = {w[1] * wy[2] - w[2] * wy[1], w[2] * wy[0] - w[0] * wy[2], w[0] * wy[1] - w[1] * wy[0]};
+  for (int i = 0; i < 3; i++) {
+    beta[i] = ps.b[i] + wy[i];
+    acc[i] = ps.a[i] - 2.0 * wb[i] - wwy[i];
+  }
+}
+
+// Velocity of the patch frame at patch-frame point y, in the background frame:
+// V = c' + w x (R y).
+__device__ inline void frame_velocity(const PoseDev &ps, const double y[3], double V[3]) {
+  double Ry[3];
+  for (int a = 0; a < 3; a++) Ry[a] = ps.R[3 * a] * y[0] + ps.R[3 * a + 1] * y[1] + ps.R[3 * a + 2] * y[2];
+  V[0] = ps.cd[0] + (ps.w[1] * Ry[2] - ps.w[2] * Ry[1]);
+  V[1] = ps.cd[1] + (ps.w[2] * Ry[0] - ps.w[0] * Ry[2]);
+  V[2] = ps.cd[2] + (ps.w[0] * Ry[1] - ps.w[1] * Ry[0]);
 }
 
 __device__ inline double xnum(const PatchDev &p, int a, int i) { return p.lo[a] + (i + 0.5) * p.dx[a]; }
@@ -151,14 +204,14 @@ __device__ inline void fwd_map(const PatchDev &p, const PoseDev &ps, const doubl
     sph_basis(xp[1], xp[2], B);
     for (int a = 0; a < 3; a++) y[a] = xp[0] * B.er[a];
   }
-  for (int a = 0; a < 3; a++) X[a] = ps.c[a] + p.R[3 * a] * y[0] + p.R[3 * a + 1] * y[1] + p.R[3 * a + 2] * y[2];
+  for (int a = 0; a < 3; a++) X[a] = ps.c[a] + ps.R[3 * a] * y[0] + ps.R[3 * a + 1] * y[1] + ps.R[3 * a + 2] * y[2];
 }
 
 // Inverse map: background X -> numerical x' of patch p at pose ps.
 __device__ inline void inv_map(const PatchDev &p, const PoseDev &ps, const double X[3], double xp[3]) {
   double d[3] = {X[0] - ps.c[0], X[1] - ps.c[1], X[2] - ps.c[2]};
   double y[3];
-  for (int b = 0; b < 3; b++) y[b] = p.R[b] * d[0] + p.R[3 + b] * d[1] + p.R[6 + b] * d[2];
+  for (int b = 0; b < 3; b++) y[b] = ps.R[b] * d[0] + ps.R[3 + b] * d[1] + ps.R[6 + b] * d[2];
   if (p.coord == CART) {
     xp[0] = y[0]; xp[1] = y[1]; xp[2] = y[2];
   } else {
@@ -170,11 +223,12 @@ __device__ inline void inv_map(const PatchDev &p, const PoseDev &ps, const doubl
 }
 
 // One-form from patch frame to background: given (Pi_t, Pi_i) in the numerical
-// frame of p at x', return Pi_t^B and the background gradient G = d phi/dX.
-// (Pi_mu transforms with dx'/dX; for the spherical map the spatial part is the
-// usual gradient in the orthonormal basis.)
+// frame of p at x' (patch-frame Cartesian point y), return Pi_t^B and the
+// background gradient G = d phi/dX: G = R (spatial part in patch axes),
+// Pi_t^B = Pi_t - V.G with V the frame velocity at y.  For the spherical map the
+// spatial part is the usual gradient in the orthonormal basis.
 __device__ inline void patch_to_bg_b(const PatchDev &p, const PoseDev &ps, double r, const SphBasis &B,
-                                     const double in[4], double &pit, double G[3]) {
+                                     const double y[3], const double in[4], double &pit, double G[3]) {
   double gy[3];
   if (p.coord == CART) {
     gy[0] = in[1]; gy[1] = in[2]; gy[2] = in[3];
@@ -182,35 +236,47 @@ __device__ inline void patch_to_bg_b(const PatchDev &p, const PoseDev &ps, doubl
     double fr = in[1], ft = in[2] / r, fp = in[3] / (r * B.st);
     for (int a = 0; a < 3; a++) gy[a] = fr * B.er[a] + ft * B.et[a] + fp * B.ep[a];
   }
-  for (int a = 0; a < 3; a++) G[a] = p.R[3 * a] * gy[0] + p.R[3 * a + 1] * gy[1] + p.R[3 * a + 2] * gy[2];
-  pit = in[0] - (ps.cd[0] * G[0] + ps.cd[1] * G[1] + ps.cd[2] * G[2]);
+  for (int a = 0; a < 3; a++) G[a] = ps.R[3 * a] * gy[0] + ps.R[3 * a + 1] * gy[1] + ps.R[3 * a + 2] * gy[2];
+  double V[3];
+  frame_velocity(ps, y, V);
+  pit = in[0] - (V[0] * G[0] + V[1] * G[1] + V[2] * G[2]);
+}
+// patch-frame Cartesian point of numerical x' (basis B at x' for spherical patches)
+__device__ inline void patch_point(const PatchDev &p, const double xp[3], const SphBasis &B, double y[3]) {
+  if (p.coord == CART) {
+    y[0] = xp[0]; y[1] = xp[1]; y[2] = xp[2];
+  } else {
+    for (int a = 0; a < 3; a++) y[a] = xp[0] * B.er[a];
+  }
 }
 __device__ inline void patch_to_bg(const PatchDev &p, const PoseDev &ps, const double xp[3], const double in[4],
                                    double &pit, double G[3]) {
   SphBasis B;
   if (p.coord != CART) sph_basis(xp[1], xp[2], B);
-  patch_to_bg_b(p, ps, xp[0], B, in, pit, G);
+  double y[3];
+  patch_point(p, xp, B, y);
+  patch_to_bg_b(p, ps, xp[0], B, y, in, pit, G);
 }
 // The same at the point of p that maps to background X (x' = its inverse map):
-// the spherical basis comes from the patch-frame Cartesian offset.
+// the point y and the spherical basis come from the patch-frame Cartesian offset.
 __device__ inline void patch_to_bg_at(const PatchDev &p, const PoseDev &ps, const double X[3], const double xp[3],
                                       const double in[4], double &pit, double G[3]) {
   SphBasis B;
-  if (p.coord != CART) {
-    const double d[3] = {X[0] - ps.c[0], X[1] - ps.c[1], X[2] - ps.c[2]};
-    double y[3];
-    for (int b = 0; b < 3; b++) y[b] = p.R[b] * d[0] + p.R[3 + b] * d[1] + p.R[6 + b] * d[2];
-    sph_basis_cart(y, xp[0], B);
-  }
-  patch_to_bg_b(p, ps, xp[0], B, in, pit, G);
+  const double d[3] = {X[0] - ps.c[0], X[1] - ps.c[1], X[2] - ps.c[2]};
+  double y[3];
+  for (int b = 0; b < 3; b++) y[b] = ps.R[b] * d[0] + ps.R[3 + b] * d[1] + ps.R[6 + b] * d[2];
+  if (p.coord != CART) sph_basis_cart(y, xp[0], B);
+  patch_to_bg_b(p, ps, xp[0], B, y, in, pit, G);
 }
 
-// Background one-form (Pi_t^B, G) -> numerical frame of p at x'.
-__device__ inline void bg_to_patch_b(const PatchDev &p, const PoseDev &ps, double r, const SphBasis &B, double pit,
-                                     const double G[3], double out[4]) {
+// Background one-form (Pi_t^B, G) -> numerical frame of p at x' (point y).
+__device__ inline void bg_to_patch_b(const PatchDev &p, const PoseDev &ps, double r, const SphBasis &B,
+                                     const double y[3], double pit, const double G[3], double out[4]) {
   double gy[3];
-  for (int b = 0; b < 3; b++) gy[b] = p.R[b] * G[0] + p.R[3 + b] * G[1] + p.R[6 + b] * G[2];
-  out[0] = pit + ps.cd[0] * G[0] + ps.cd[1] * G[1] + ps.cd[2] * G[2];
+  for (int b = 0; b < 3; b++) gy[b] = ps.R[b] * G[0] + ps.R[3 + b] * G[1] + ps.R[6 + b] * G[2];
+  double V[3];
+  frame_velocity(ps, y, V);
+  out[0] = pit + V[0] * G[0] + V[1] * G[1] + V[2] * G[2];
   if (p.coord == CART) {
     out[1] = gy[0]; out[2] = gy[1]; out[3] = gy[2];
   } else {
@@ -223,28 +289,34 @@ __device__ inline void bg_to_patch(const PatchDev &p, const PoseDev &ps, const d
                                    const double G[3], double out[4]) {
   SphBasis B;
   if (p.coord != CART) sph_basis(xp[1], xp[2], B);
-  bg_to_patch_b(p, ps, xp[0], B, pit, G, out);
+  double y[3];
+  patch_point(p, xp, B, y);
+  bg_to_patch_b(p, ps, xp[0], B, y, pit, G, out);
 }
 
 // Grid point c (numerical indices, ghosts included) of p: its background
 // position, and a background one-form carried to p there (table basis).
-__device__ inline void fwd_map_grid(const PatchDev &p, const PoseDev &ps, const int c[3], double X[3]) {
-  double y[3];
+__device__ inline void grid_point(const PatchDev &p, const int c[3], SphBasis &B, double y[3]) {
   if (p.coord == CART) {
     for (int a = 0; a < 3; a++) y[a] = xnum(p, a, c[a]);
   } else {
-    SphBasis B;
     sph_basis_grid(p, c[1], c[2], B);
     const double r = xnum(p, 0, c[0]);
     for (int a = 0; a < 3; a++) y[a] = r * B.er[a];
   }
-  for (int a = 0; a < 3; a++) X[a] = ps.c[a] + p.R[3 * a] * y[0] + p.R[3 * a + 1] * y[1] + p.R[3 * a + 2] * y[2];
+}
+__device__ inline void fwd_map_grid(const PatchDev &p, const PoseDev &ps, const int c[3], double X[3]) {
+  double y[3];
+  SphBasis B;
+  grid_point(p, c, B, y);
+  for (int a = 0; a < 3; a++) X[a] = ps.c[a] + ps.R[3 * a] * y[0] + ps.R[3 * a + 1] * y[1] + ps.R[3 * a + 2] * y[2];
 }
 __device__ inline void bg_to_patch_grid(const PatchDev &p, const PoseDev &ps, const int c[3], double pit,
                                         const double G[3], double out[4]) {
   SphBasis B;
-  if (p.coord != CART) sph_basis_grid(p, c[1], c[2], B);
-  bg_to_patch_b(p, ps, xnum(p, 0, c[0]), B, pit, G, out);
+  double y[3];
+  grid_point(p, c, B, y);
+  bg_to_patch_b(p, ps, xnum(p, 0, c[0]), B, y, pit, G, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -1062,20 +1062,23 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
 // RHS of Eqs. eom1-eom3 (source S = 0) with Kreiss-Oliger dissipation on all
 // five fields, fused with the classic-RK4 stage update.
 //
-// Metric terms (flat background with wave speed v, patch map X = c(t) + R M(x')):
+// Metric terms (flat background with wave speed v, patch map X = c(t) + R(t) M(x')):
 //   b = R^T c', a = R^T c'' (patch axes), beta = K b with K = (dM/dx')^-1,
 //   dPi_t/dt = m.D phi + 2 beta.D Pi_t + sum_i (v^2 h_i - beta_i^2) D_ii phi
 //              - 2 sum_{i<j} beta_i beta_j D_ij phi
 // Cartesian: h = 1, m = a.  Spherical: h = (1, 1/r^2, 1/(r sin th)^2) and
 //   m = K a - Q(b) + v^2 (2/r, cot th / r^2, 0), Q the coordinate acceleration of
 //   straight-line motion in spherical coordinates.
+// A patch rotating with angular velocity w (wp = R^T w) has, at y = M(x'), the
+// position-dependent b + wp x y in place of b and a - 2 wp x b - wp x (wp x y)
+// in place of a (frame_terms).
 //
-// Tiling (2.5-D): a workgroup owns a 32 x 8 column tile and marches up to 32
-// planes in z.  Each thread keeps its column's 7-plane window of the 5 fields in
-// registers (z stencils) and a 5-plane window of D_x phi, D_y phi (mixed x-z and
-// y-z derivatives as D_z of D_x phi, D_y phi).  The centre plane of the 5 fields
-// and the plane two above it of phi are staged in LDS with a 3-cell x-y halo
-// for the x-y stencils.
+// Tiling (2.5-D): a workgroup owns a 32 x 8 column tile and marches through the
+// tile's planes in z (a tuning parameter).  Each thread keeps its column's
+// 7-plane window of the 5 fields in registers (z stencils) and a 5-plane window
+// of D_x phi, D_y phi (mixed x-z and y-z derivatives as D_z of D_x phi, D_y phi).
+// The centre plane of the 5 fields and the phi plane one below the newest are
+// staged in LDS with a 3-cell x-y halo for the x-y stencils.
 // ---------------------------------------------------------------------------
 template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD, bool GLOB, int AM>
 __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose_slot, const TileRec *tiles,
@@ -1155,7 +1158,9 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
   const TC i12dx2[3] = {(TC)(p.idx[0] * p.idx[0] / 12.0), (TC)(p.idx[1] * p.idx[1] / 12.0),
                         (TC)(p.idx[2] * p.idx[2] / 12.0)};
   const TC ko[3] = {(TC)(eps / 64.0 * p.idx[0]), (TC)(eps / 64.0 * p.idx[1]), (TC)(eps / 64.0 * p.idx[2])};
-  const bool moving = (ps.b[0] != 0.0) || (ps.b[1] != 0.0) || (ps.b[2] != 0.0);
+  // rotating patches: position-dependent shift and acceleration (frame_terms)
+  const bool spin = (ps.wp[0] != 0.0) || (ps.wp[1] != 0.0) || (ps.wp[2] != 0.0);
+  const bool moving = spin || (ps.b[0] != 0.0) || (ps.b[1] != 0.0) || (ps.b[2] != 0.0);
   const double bdt = STAGE == 0 ? dt / 6.0 : (STAGE == 3 ? dt / 6.0 : dt / 3.0);
   const double adt = STAGE == 2 ? dt : dt / 2.0;
   const float bdtf = (float)bdt, adtf = (float)adt;
@@ -1301,26 +1306,37 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
       if (live) {
         TC m_[3], b2_[3], h_[3], bb_[3];
         if (COORD == CART) {
+          double bv[3] = {ps.b[0], ps.b[1], ps.b[2]}, av[3] = {ps.a[0], ps.a[1], ps.a[2]};
+          if (spin) {
+            const double y[3] = {p.lo[0] + (i + 0.5) * p.dx[0], p.lo[1] + (j + 0.5) * p.dx[1],
+                                 p.lo[2] + (k + 0.5) * p.dx[2]};
+            frame_terms(ps, y, bv, av);
+          }
 #pragma unroll
           for (int a = 0; a < 3; a++) {
-            m_[a] = (TC)ps.a[a];
-            b2_[a] = (TC)(2.0 * ps.b[a]);
-            h_[a] = (TC)(v2 - ps.b[a] * ps.b[a]);
+            m_[a] = (TC)av[a];
+            b2_[a] = (TC)(2.0 * bv[a]);
+            h_[a] = (TC)(v2 - bv[a] * bv[a]);
           }
-          bb_[0] = (TC)(2.0 * ps.b[0] * ps.b[1]);
-          bb_[1] = (TC)(2.0 * ps.b[0] * ps.b[2]);
-          bb_[2] = (TC)(2.0 * ps.b[1] * ps.b[2]);
+          bb_[0] = (TC)(2.0 * bv[0] * bv[1]);
+          bb_[1] = (TC)(2.0 * bv[0] * bv[2]);
+          bb_[2] = (TC)(2.0 * bv[1] * bv[2]);
         } else {
           double r = p.lo[0] + (i + 0.5) * p.dx[0];
           SphBasis Bs;
           sph_basis_grid(p, j, k, Bs);
+          double bv[3] = {ps.b[0], ps.b[1], ps.b[2]}, av[3] = {ps.a[0], ps.a[1], ps.a[2]};
+          if (spin) {
+            const double y[3] = {r * Bs.er[0], r * Bs.er[1], r * Bs.er[2]};
+            frame_terms(ps, y, bv, av);
+          }
           double ir = 1.0 / r, irs = ir / Bs.st, cot = Bs.ct / Bs.st;
-          double br = Bs.er[0] * ps.b[0] + Bs.er[1] * ps.b[1] + Bs.er[2] * ps.b[2];
-          double bt = Bs.et[0] * ps.b[0] + Bs.et[1] * ps.b[1] + Bs.et[2] * ps.b[2];
-          double bp = Bs.ep[0] * ps.b[0] + Bs.ep[1] * ps.b[1];
-          double ar = Bs.er[0] * ps.a[0] + Bs.er[1] * ps.a[1] + Bs.er[2] * ps.a[2];
-          double at = Bs.et[0] * ps.a[0] + Bs.et[1] * ps.a[1] + Bs.et[2] * ps.a[2];
-          double ap = Bs.ep[0] * ps.a[0] + Bs.ep[1] * ps.a[1];
+          double br = Bs.er[0] * bv[0] + Bs.er[1] * bv[1] + Bs.er[2] * bv[2];
+          double bt = Bs.et[0] * bv[0] + Bs.et[1] * bv[1] + Bs.et[2] * bv[2];
+          double bp = Bs.ep[0] * bv[0] + Bs.ep[1] * bv[1];
+          double ar = Bs.er[0] * av[0] + Bs.er[1] * av[1] + Bs.er[2] * av[2];
+          double at = Bs.et[0] * av[0] + Bs.et[1] * av[1] + Bs.et[2] * av[2];
+          double ap = Bs.ep[0] * av[0] + Bs.ep[1] * av[1];
           double beta[3] = {br, bt * ir, bp * irs};
           double Q0 = (bt * bt + bp * bp) * ir;
           double Q1 = (-2.0 * br * bt + bp * bp * cot) * ir * ir;

@@ -53,7 +53,7 @@ class PatchDesc(C.Structure):
     _fields_ = [("coord", C.c_int32), ("is_global", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3),
                 ("hi", C.c_double * 3), ("periodic", C.c_int32 * 3), ("euler_zyz", C.c_double * 3),
                 ("motion", C.c_int32), ("c0", C.c_double * 3), ("vel", C.c_double * 3), ("radius", C.c_double),
-                ("speed", C.c_double), ("phase", C.c_double), ("sv_mask", C.c_uint32)]
+                ("speed", C.c_double), ("phase", C.c_double), ("sv_mask", C.c_uint32), ("spin", C.c_double * 3)]
 
 
 class ExactDesc(C.Structure):
@@ -139,6 +139,7 @@ def patch_desc(d):
         pd.euler_zyz[a] = float(d.get("euler", (0, 0, 0))[a])
         pd.c0[a] = float(d.get("c0", (0, 0, 0))[a])
         pd.vel[a] = float(d.get("vel", (0, 0, 0))[a])
+        pd.spin[a] = float(d.get("spin", (0, 0, 0))[a])
     pd.motion = int(d.get("motion", PW_STATIC))
     pd.radius = float(d.get("radius", 0.0))
     pd.speed = float(d.get("speed", 0.0))

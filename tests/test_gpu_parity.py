@@ -169,6 +169,32 @@ def test_spherical_local_patch(moving):
     say("  worst rel err", compare(cfg, o, g, TOL64))
 
 
+@pytest.mark.parametrize("init", ["exact", "random"])
+def test_rotating_cartesian_patch(init):
+    # a local patch on a circle that also spins about its centre (rotating frame:
+    # position-dependent shift and acceleration terms, frame velocity in the transforms)
+    cfg = W.two_patch(seed=6, ng=48, nl=40, P=6)
+    cfg["patches"][1]["spin"] = [0.15, -0.25, 0.3]
+    say("rotating Cartesian patch", init)
+    o, g = run_pair(cfg, 3, init=init, seed=13)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def test_rotating_spherical_patch():
+    cfg = _sph_cfg(True)
+    cfg["patches"][1]["spin"] = [0.0, 0.2, 0.35]
+    say("rotating spherical patch")
+    o, g = run_pair(cfg, 2)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def test_rotating_patch_mixed_precision():
+    cfg = W.two_patch(seed=6, ng=48, nl=40, P=6)
+    cfg["patches"][1]["spin"] = [0.15, -0.25, 0.3]
+    o, g = run_pair(cfg, 3, precision=pw.PW_MIXED)
+    say("rotating, mixed: worst rel err", compare(cfg, o, g, 2e-5))
+
+
 def test_two_state_vectors_with_membership():
     g0 = W.patch([40] * 3, [-8] * 3, [8] * 3, is_global=1, sv_mask=1)
     l1 = W.patch([32] * 3, [-3.2] * 3, [3.2] * 3, euler=[0.2, 0.7, 1.1], motion=W.LINEAR, c0=(-3.5, 0, 0),
