@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "pw_oracle.c")
 
-CART, SPH = 0, 1
+CART, SPH, CYL = 0, 1, 2
 STATIC, LINEAR, CIRCLE = 0, 1, 2
 FLAG_LIVE, FLAG_EFFGHOST, FLAG_DEACT = 0, 1, 2
 NG = 3

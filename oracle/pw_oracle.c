@@ -21,6 +21,8 @@
  *     frozen for the whole step                            (Sec. 2.4.2, Fig. cflag)
  *   - plane-wave exact solution, analytic outer BCs         (Sec. 3, Eq. wave_solution)
  *   - integrated relative error with the volume element    (Sec. 3.2)
+ *   - Cartesian, spherical and cylindrical patch topologies,
+ *     translating, circling and rotating patches            (Secs. 2.1, 3.4)
  *
  * Readings where the paper is silent or garbled (KO normalisation, mixed
  * derivative stencil, cell-centred grids, Chebyshev neighbourhoods for the
@@ -29,7 +31,9 @@
  *
  * Parity pins: see the "not gpu" tests (polynomial exactness of every stencil,
  * the closed-form discrete Fourier-mode evolution, measured convergence order,
- * Lagrange exactness, closed-form spherical metric, transform round trips,
+ * Lagrange exactness, closed-form spherical, cylindrical and spinning-patch
+ * metrics, metrics against finite differences of the inverse map, transform
+ * round trips, two-patch convergence order,
  * brute-force flag counts, energy and constraint behaviour).
  */
 #include <math.h>
@@ -44,7 +48,7 @@
 #define MAXSV 4
 #define MAXG 32
 
-enum { CART = 0, SPH = 1 };
+enum { CART = 0, SPH = 1, CYL = 2 };
 enum { STATIC = 0, LINEAR = 1, CIRCLE = 2 };
 enum { FLAG_LIVE = 0, FLAG_EFFGHOST = 1, FLAG_DEACT = 2 };
 enum { EX_NONE = 0, EX_PLANE = 1, EX_GAUSS = 2 };
@@ -183,6 +187,12 @@ static void map_hd(const or_patch *p, const hd in[4], hd out[4]) {
   hd y[3];
   if (p->coord == CART) {
     y[0] = in[1]; y[1] = in[2]; y[2] = in[3];
+  } else if (p->coord == CYL) {
+    /* cylindrical x' = (r, phi, z): y = (r cos phi, r sin phi, z) */
+    hd r = in[1], sp = hd_sin(in[2]), cp = hd_cos(in[2]);
+    y[0] = hd_mul(r, cp);
+    y[1] = hd_mul(r, sp);
+    y[2] = in[3];
   } else {
     hd r = in[1], st = hd_sin(in[2]), ct = hd_cos(in[2]), sp = hd_sin(in[3]), cp = hd_cos(in[3]);
     y[0] = hd_mul(r, hd_mul(st, cp));
@@ -222,6 +232,10 @@ static void map_inv(const or_patch *p, double t, const double X[3], double xp[3]
   for (int b = 0; b < 3; b++) y[b] = Rt[0][b].a * d[0] + Rt[1][b].a * d[1] + Rt[2][b].a * d[2];
   if (p->coord == CART) {
     for (int a = 0; a < 3; a++) xp[a] = y[a];
+  } else if (p->coord == CYL) {
+    xp[0] = sqrt(y[0] * y[0] + y[1] * y[1]);
+    xp[1] = atan2(y[1], y[0]);
+    xp[2] = y[2];
   } else {
     double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
     xp[0] = r;
@@ -573,6 +587,10 @@ static void transform(const or_patch *pd, const double xd[3], const or_patch *pr
 /* ------------------------------------------------------------------------ */
 static double bound_radius(const or_patch *p) {
   if (p->coord == SPH) return p->hi[0];
+  if (p->coord == CYL) {
+    double zm = fabs(p->lo[2]) > fabs(p->hi[2]) ? fabs(p->lo[2]) : fabs(p->hi[2]);
+    return sqrt(p->hi[0] * p->hi[0] + zm * zm);
+  }
   double m = 0;
   for (int c = 0; c < 8; c++) {
     double y0 = (c & 1) ? p->hi[0] : p->lo[0], y1 = (c & 2) ? p->hi[1] : p->lo[1], y2 = (c & 4) ? p->hi[2] : p->lo[2];

@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libpw.so")
 
 PW_FP64, PW_MIXED, PW_MIXED_INC = 0, 1, 2
-PW_CART, PW_SPH = 0, 1
+PW_CART, PW_SPH, PW_CYL = 0, 1, 2
 PW_STATIC, PW_LINEAR, PW_CIRCLE = 0, 1, 2
 PW_FLAG_LIVE, PW_FLAG_EFFGHOST, PW_FLAG_DEACT = 0, 1, 2
 PW_SCHED_BATCHED, PW_SCHED_PER_PATCH = 0, 1

@@ -14,7 +14,7 @@ import math
 
 import numpy as np
 
-CART, SPH = 0, 1
+CART, SPH, CYL = 0, 1, 2
 STATIC, LINEAR, CIRCLE = 0, 1, 2
 
 

@@ -12,7 +12,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle.oracle import (CART, CIRCLE, FLAG_DEACT, FLAG_EFFGHOST, FLAG_LIVE, LINEAR, NG, SPH, OracleWorld,
+from oracle.oracle import (CART, CIRCLE, CYL, FLAG_DEACT, FLAG_EFFGHOST, FLAG_LIVE, LINEAR, NG, SPH, OracleWorld,
                            lagrange, world_from_config)
 from paper_2002_00088_amd import workloads as W
 
@@ -184,6 +184,23 @@ def test_static_spherical_metric_closed_form():
         assert sg == pytest.approx(r * r * math.sin(th), rel=1e-13)
 
 
+def test_static_cylindrical_metric_closed_form():
+    # x' = (r, phi, z): the flat metric is diag(1, r^2, 1), so g^{ij} = diag(1, 1/r^2, 1),
+    # the only nonzero Christoffel contraction is C^r = -g^{jk} Gamma^r_jk = -(-r)/r^2 ... = -1/r,
+    # and the volume element is r
+    v = 0.6
+    w = _world_with(W.patch([8, 8, 8], [0.5, 0.0, -3.0], [6, 2 * math.pi, 3.0], coord=CYL, periodic=(0, 1, 0)), v)
+    for r, ph, z in [(1.0, 0.7, 0.3), (2.5, 4.0, -1.9), (0.6, 6.0, 2.5)]:
+        X = w.map_fwd(1, 0.3, [r, ph, z])
+        assert np.allclose(X, [r * math.cos(ph), r * math.sin(ph), z], atol=1e-14)
+        assert np.allclose(w.map_inv(1, 0.3, X), [r, ph if ph < math.pi else ph - 2 * math.pi, z], atol=1e-13)
+        g, C, sg = w.metric(1, 0, 0.3, [r, ph, z])
+        exp = np.diag([-1 / v ** 2, 1.0, 1 / r ** 2, 1.0])
+        assert np.allclose(g, exp, atol=1e-13)
+        assert np.allclose(C, [0.0, -1 / r, 0.0, 0.0], atol=1e-12)
+        assert sg == pytest.approx(r, rel=1e-13)
+
+
 def zyz(e):
     a, b, c = e
     Rz = lambda t: np.array([[math.cos(t), -math.sin(t), 0], [math.sin(t), math.cos(t), 0], [0, 0, 1]])
@@ -248,12 +265,17 @@ def test_spinning_cartesian_metric_closed_form():
         assert abs(C[0]) < 1e-13 and sg == pytest.approx(1.0, rel=1e-13)
 
 
-@pytest.mark.parametrize("spin", [(0.0, 0.0, 0.0), (0.25, -0.4, 0.3)])
-def test_metric_matches_inverse_map_finite_differences(spin):
+@pytest.mark.parametrize("coord,spin", [(SPH, (0.0, 0.0, 0.0)), (SPH, (0.25, -0.4, 0.3)),
+                                        (CYL, (0.0, 0.0, 0.0)), (CYL, (-0.3, 0.2, 0.45))])
+def test_metric_matches_inverse_map_finite_differences(coord, spin):
     """g^{mu nu} = Lam eta^{-1} Lam^T and C^l = -eta^{ab} d_a d_b x'^l, with
     Lam = d x'/d(t,X) taken by finite differences of the inverse map."""
     v = 0.7
-    w = _world_with(W.patch([8] * 3, [0.5, 0.5, 0.0], [5, 2.6, 2 * math.pi], coord=SPH, periodic=(0, 0, 1),
+    if coord == SPH:
+        lo, hi, per = [0.5, 0.5, 0.0], [5, 2.6, 2 * math.pi], (0, 0, 1)
+    else:
+        lo, hi, per = [0.5, 0.0, -3.0], [5, 2 * math.pi, 3.0], (0, 1, 0)
+    w = _world_with(W.patch([8] * 3, lo, hi, coord=coord, periodic=per,
                             euler=[0.3, 0.9, -0.4], motion=LINEAR, c0=(0.2, -0.1, 0.3), vel=(0.15, -0.1, 0.05),
                             spin=spin), v)
     t0 = 0.8
@@ -348,6 +370,8 @@ def _three_patch_world():
                         phase=0.2))
     w.add_patch(W.patch([8] * 3, [0.5, 0.6, 0.0], [4, 2.5, 2 * math.pi], coord=SPH, periodic=(0, 0, 1),
                         euler=[1.0, 0.4, -0.7], motion=LINEAR, c0=(1, -1, 0.5), vel=(0.1, 0.0, -0.12)))
+    w.add_patch(W.patch([8] * 3, [0.5, 0.0, -3.0], [4, 2 * math.pi, 3.0], coord=CYL, periodic=(0, 1, 0),
+                        euler=[-0.6, 1.3, 0.2], motion=CIRCLE, radius=1.5, speed=0.2, phase=1.0, spin=(0.1, 0.2, -0.3)))
     w.set_exact(0, dict(kind="gauss", amp=[1.0, -0.5], centers=[[0.5, 0.2, -0.3], [1.5, -1.0, 0.8]], widths=[0.8, 0.6]))
     return w
 
@@ -357,9 +381,9 @@ def test_transform_round_trip_and_exact_gradient():
     rng = np.random.default_rng(5)
     t = 0.7
     X = np.array([1.1, -0.6, 0.9])
-    xs = [w.map_inv(p, t, X) for p in range(3)]
-    for d in range(3):
-        for r in range(3):
+    xs = [w.map_inv(p, t, X) for p in range(4)]
+    for d in range(4):
+        for r in range(4):
             s = rng.normal(size=5)
             there = w.transform(d, xs[d], r, xs[r], t, s)
             back = w.transform(r, xs[r], d, xs[d], t, there)
@@ -552,6 +576,16 @@ def _two_patch_plane(ng, motion):
         # by 0.2 rad over the run so the rotation terms matter at these resolutions
         loc = W.patch([nl] * 3, [-half] * 3, [half] * 3, euler=[0.3, 0.8, 1.9], c0=(-0.5, -0.5, -0.5),
                       spin=(0.0, 0.0, 0.1))
+    elif motion == "cylindrical":
+        # a tilted cylindrical shell 2 <= r <= 6, |z| <= 4 with radial and axial spacing dxg/2
+        # and arc spacing dxg/2 at r = 4; the time step follows its smallest spacing (at r = 2)
+        nr, nz = int(round(4 / (dxg / 2))), int(round(8 / (dxg / 2)))
+        nph = 48 * ng // 32
+        loc = W.patch([nr, nph, nz], [2.0, 0.0, -4.0], [6.0, 2 * math.pi, 4.0], coord=CYL, periodic=(0, 1, 0),
+                      euler=[0.3, 0.8, 1.9], c0=(-0.5, -0.5, -0.5))
+        ex = dict(kind="plane", A=1.0, B=2.0, kappa=[2 * math.pi / 16 * x for x in (1.0, 0.6, 0.3)], psi=0.4)
+        cfg = dict(wave_speed=[1.0], interp_points=[6], patches=[g, loc], exact=[ex], ko_eps=0.005, buffer=4)
+        return cfg, min(dxg / 2, 2.0 * 2 * math.pi / nph)
     else:
         loc = W.patch([nl] * 3, [-half] * 3, [half] * 3, euler=[0.3, 0.8, 1.9], motion=LINEAR, c0=(-0.5, -0.5, 0.0),
                       vel=(0.1, 0.1, 0.0))
@@ -560,7 +594,7 @@ def _two_patch_plane(ng, motion):
     return cfg, dxg / 2
 
 
-@pytest.mark.parametrize("motion", ["fixed", "translating", "rotating"])
+@pytest.mark.parametrize("motion", ["fixed", "translating", "rotating", "cylindrical"])
 def test_two_patch_convergence(motion):
     errs = []
     T = 2.0
