@@ -45,6 +45,7 @@ def lib():
         vp = C.c_void_p
         L.or_new.restype = vp
         L.or_new.argtypes = [C.c_int, dp, ip, C.c_double, C.c_int]
+        L.or_set_form.argtypes = [vp, C.c_int]
         L.or_free.argtypes = [vp]
         L.or_add_patch.restype = C.c_int
         L.or_add_patch.argtypes = [vp, C.c_int, C.c_int, ip, dp, dp, ip, dp, C.c_int, dp, dp,
@@ -96,7 +97,7 @@ def _i(a):
 class OracleWorld:
     """One global patch (id 0) plus local patches, FP64 throughout."""
 
-    def __init__(self, wave_speed=(1.0,), interp_points=None, ko_eps=0.005, buffer=4):
+    def __init__(self, wave_speed=(1.0,), interp_points=None, ko_eps=0.005, buffer=4, pi_form=0):
         self.L = lib()
         nsv = len(wave_speed)
         if interp_points is None:
@@ -106,6 +107,8 @@ class OracleWorld:
         self.h = self.L.or_new(nsv, wsp, ipp, ko_eps, buffer)
         if not self.h:
             raise ValueError("bad oracle world parameters")
+        if self.L.or_set_form(self.h, pi_form) != 0:
+            raise ValueError("bad form of the Pi_t equation")
         self.nsv = nsv
         self.patches = []
 
@@ -322,7 +325,7 @@ def lagrange(P, q):
 def world_from_config(cfg):
     """Build an oracle world from a workload config (see workloads.py)."""
     w = OracleWorld(wave_speed=cfg["wave_speed"], interp_points=cfg["interp_points"],
-                    ko_eps=cfg.get("ko_eps", 0.005), buffer=cfg.get("buffer", 4))
+                    ko_eps=cfg.get("ko_eps", 0.005), buffer=cfg.get("buffer", 4), pi_form=cfg.get("pi_form", 0))
     for d in cfg["patches"]:
         w.add_patch(d)
     for sv, ex in enumerate(cfg.get("exact", [])):

@@ -111,6 +111,8 @@ typedef struct {
   int P[MAXSV];             /* interpolation points per axis per state vector */
   double eps;               /* KO strength */
   int buffer;               /* buffer width, NG + 1 in the paper */
+  int form;                 /* 0: the paper's Pi_t equation (second derivatives of phi);
+                               1: first-order form, Psi_i = Pi_i in place of d_i phi */
   or_patch p[MAXP];
   or_exact ex[MAXSV];
   double t;
@@ -486,6 +488,13 @@ static void rhs_cell(const or_world *w, const or_patch *p, int sv, const double 
   }
   for (int d = 0; d < 3; d++)
     for (int e = 0; e < 3; e++) ddphi[d][e] = (d == e) ? D2(p, T, 0, i, j, k, d) : D11(p, T, 0, i, j, k, d, e);
+  if (w->form == 1) {
+    /* first-order reduction: the evolved Psi_i = Pi_i stands for d_i phi, and
+     * d_a Psi_b for d_a d_b phi (the wave operator as a divergence of Psi) */
+    for (int d = 0; d < 3; d++) dphi[d] = T[IX(p, 2 + d, i, j, k)];
+    for (int d = 0; d < 3; d++)
+      for (int e = 0; e < 3; e++) ddphi[d][e] = D1(p, T, 2 + e, i, j, k, d);
+  }
   double br = C[0] * Pi;
   for (int j2 = 0; j2 < 3; j2++) br += C[1 + j2] * dphi[j2];
   for (int j2 = 0; j2 < 3; j2++) br -= 2.0 * gi[0][1 + j2] * dpi[j2];
@@ -903,6 +912,13 @@ or_world *or_new(int nsv, const double *wave_speed, const int *interp_points, do
   w->eps = ko_eps;
   w->buffer = buffer;
   return w;
+}
+
+/* form of the Pi_t equation: 0 the paper's (Eqs. eom1-eom3), 1 first-order */
+int or_set_form(or_world *w, int form) {
+  if (form != 0 && form != 1) return -1;
+  w->form = form;
+  return 0;
 }
 
 void or_free(or_world *w) {

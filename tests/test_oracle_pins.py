@@ -123,6 +123,83 @@ def test_single_mode_closed_form(v, eps):
     assert np.max(np.abs(got - exp)) < 1e-12 * np.max(np.abs(exp))
 
 
+def mode_matrix_first_order(kvec, dx, v, eps):
+    """The same mode under the first-order form: Pi_t' = v^2 sum_i D_i Psi_i."""
+    A = mode_matrix(kvec, dx, v, eps)
+    th = np.array(kvec) * np.array(dx)
+    kap = (8 * np.sin(th) - np.sin(2 * th)) / (6 * np.array(dx))
+    A[1, 0] = 0.0
+    for d in range(3):
+        A[1, 2 + d] = v * v * 1j * kap[d]
+    return A
+
+
+@pytest.mark.parametrize("v,eps", [(1.0, 0.005), (0.5, 0.0)])
+def test_single_mode_closed_form_first_order(v, eps):
+    n = [12, 10, 8]
+    Lb = [1.0, 1.25, 0.8]
+    p = W.patch(n, [0, 0, 0], Lb, is_global=1, periodic=(1, 1, 1))
+    w = OracleWorld(wave_speed=(v,), ko_eps=eps, pi_form=1)
+    w.add_patch(p)
+    dx = [Lb[a] / n[a] for a in range(3)]
+    kint = [1, 2, 1]
+    kvec = [2 * math.pi * kint[a] / Lb[a] for a in range(3)]
+    rng = np.random.default_rng(8)
+    uhat = rng.normal(size=5) + 1j * rng.normal(size=5)
+    x, y, z = cell_centers(p)
+    ph = np.exp(1j * (kvec[0] * x + kvec[1] * y + kvec[2] * z))
+    w.set_state(0, 0, np.real(uhat[:, None, None, None] * ph[None]))
+    dt = 0.02
+    M = mode_matrix_first_order(kvec, dx, v, eps)
+    u = uhat.copy()
+    for _ in range(3):
+        u = rk_tableau_step(M, dt, u)
+    w.step(dt, 3)
+    got = w.get_state(0)
+    exp = np.real(u[:, None, None, None] * ph[None])
+    assert np.max(np.abs(got - exp)) < 1e-12 * np.max(np.abs(exp))
+
+
+@pytest.mark.parametrize("coord", [CART, SPH, CYL])
+def test_first_order_form_reduces_to_paper_form(coord):
+    """With Psi_i = d_i phi exactly and data on which the stencils are exact
+    (phi quadratic, Psi linear in x'), both forms give the same Pi_t right-hand
+    side on a moving, spinning patch: the first-order form contracts the same
+    metric terms, only with Psi in place of the derivatives of phi."""
+    if coord == CART:
+        loc = W.patch([8] * 3, [-1.0] * 3, [1.0] * 3, euler=[0.3, 0.9, -0.4], motion=CIRCLE, radius=1.0,
+                      speed=0.2, spin=(0.1, -0.2, 0.3))
+    elif coord == SPH:
+        loc = W.patch([8] * 3, [1.0, 0.8, 0.0], [2.0, 2.2, 2 * math.pi], coord=SPH, periodic=(0, 0, 1),
+                      euler=[0.3, 0.9, -0.4], motion=LINEAR, c0=(0.2, -0.1, 0.3), vel=(0.15, -0.1, 0.05),
+                      spin=(0.2, 0.1, -0.3))
+    else:
+        loc = W.patch([8] * 3, [1.0, 0.0, -1.0], [2.0, 2 * math.pi, 1.0], coord=CYL, periodic=(0, 1, 0),
+                      euler=[0.3, 0.9, -0.4], motion=LINEAR, c0=(0.2, -0.1, 0.3), vel=(0.15, -0.1, 0.05),
+                      spin=(-0.1, 0.25, 0.2))
+    x, y, z = cell_centers(loc, with_ghosts=True)
+    full = np.zeros((5,) + x.shape)
+    c = np.array([0.3, -0.7, 0.45, 0.2, -0.35, 0.6, 0.25, -0.15, 0.4])
+    full[0] = c[0] * x * x + c[1] * y * y + c[2] * z * z + c[3] * x * y + c[4] * x * z + c[5] * y * z + c[6] * x
+    full[1] = 0.5 * x - 0.3 * y * z + 0.2
+    full[2] = 2 * c[0] * x + c[3] * y + c[4] * z + c[6]
+    full[3] = 2 * c[1] * y + c[3] * x + c[5] * z
+    full[4] = 2 * c[2] * z + c[4] * x + c[5] * y
+    out = []
+    for form in (0, 1):
+        w = OracleWorld(wave_speed=(0.8,), pi_form=form)
+        w.add_patch(W.patch([8] * 3, [-8] * 3, [8] * 3, is_global=1))
+        w.add_patch(loc)
+        w.set_full(1, 0, full)
+        out.append(w.rhs(1, 0, 0.6))
+    assert np.abs(out[1][1]).max() > 0.1
+    assert np.allclose(out[0], out[1], rtol=0, atol=1e-11 * np.abs(out[0]).max())
+    # and the forms differ once Psi departs from the gradient of phi
+    full[3] += 0.05 * x * z
+    w.set_full(1, 0, full)
+    assert np.abs(w.rhs(1, 0, 0.6)[1] - out[0][1]).max() > 1e-3
+
+
 # --------------------------------------------------------------------------
 # Continuum convergence on a periodic plane wave: 4th order
 # --------------------------------------------------------------------------
@@ -594,12 +671,13 @@ def _two_patch_plane(ng, motion):
     return cfg, dxg / 2
 
 
-@pytest.mark.parametrize("motion", ["fixed", "translating", "rotating", "cylindrical"])
+@pytest.mark.parametrize("motion", ["fixed", "translating", "rotating", "cylindrical", "first_order"])
 def test_two_patch_convergence(motion):
     errs = []
     T = 2.0
     for ng in (32, 64):
-        cfg, dxl = _two_patch_plane(ng, motion)
+        cfg, dxl = _two_patch_plane(ng, "translating" if motion == "first_order" else motion)
+        cfg["pi_form"] = 1 if motion == "first_order" else 0
         w = world_from_config(cfg)
         w.init_exact(0.0)
         steps = int(round(T / (0.5 * dxl)))
