@@ -78,6 +78,8 @@ def make_config(name):
         return W.single_periodic(seed=1)
     if name == "multimethod":
         return W.multimethod(seed=5)
+    if name == "three_topology":
+        return W.three_topology()
     raise SystemExit("unknown workload " + name)
 
 
@@ -241,7 +243,7 @@ def main():
     achieved = bytes_launch / (g_ms * 1e-3) / 1e9
     ty = "double, double, double" if args.precision == "fp64" else "float, float, float"
     am = 1 if args.precision == "mixed_inc" else 0
-    dominant_name = "k_stage<%s, %d, 0, true, %d>" % (ty, dom, am)
+    dominant_name = "k_stage<%s, %d, 0, true, %d, 0>" % (ty, dom, am)
     traffic = load_traffic(cfg["name"], args.precision, dominant_name)
     copy_gbs = copy_bandwidth(torch, stream)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -49,11 +49,14 @@ enum {
 };
 
 enum { PW_FP64 = 0, PW_MIXED = 1, PW_MIXED_INC = 2 }; /* precision */
-enum { PW_CART = 0, PW_SPH = 1 };         /* patch topology */
+enum { PW_CART = 0, PW_SPH = 1, PW_CYL = 2 };  /* patch topology */
 enum { PW_STATIC = 0, PW_LINEAR = 1, PW_CIRCLE = 2 }; /* patch motion */
 enum { PW_FLAG_LIVE = 0, PW_FLAG_EFFGHOST = 1, PW_FLAG_DEACT = 2 }; /* cover flags */
 enum { PW_SCHED_BATCHED = 0, PW_SCHED_PER_PATCH = 1 };
 enum { PW_EXACT_NONE = 0, PW_EXACT_PLANE = 1, PW_EXACT_GAUSS = 2 };
+
+enum { PW_FORM_PAPER = 0, PW_FORM_FIRST_ORDER = 1 };  /* form of the Pi_t equation */
+enum { PW_BC_EXACT = 0, PW_BC_SOMMERFELD = 1 };        /* outer boundary of the global patch */
 
 #define PW_MAX_SV 4
 #define PW_MAX_PULSES 32
@@ -80,6 +83,20 @@ enum { PW_EXACT_NONE = 0, PW_EXACT_PLANE = 1, PW_EXACT_GAUSS = 2 };
  *                    PW_SCHED_PER_PATCH: one stencil launch per patch per stage, no graph.
  *   stream           hipStream_t of the caller (NULL: a stream owned by the library).
  *   dev_alloc/free   optional device allocator; alloc_user is passed back unchanged.
+ *   pi_form          PW_FORM_PAPER (0): the Pi_t equation as in Sec. 2.2, Eqs. eom1-eom3,
+ *                    with second differences of phi (g^ij d_i d_j phi, C^i d_i phi).
+ *                    PW_FORM_FIRST_ORDER (1): its first-order reduction, the evolved
+ *                    Psi_i = Pi_i in place of d_i phi and d_i Psi_j in place of
+ *                    d_i d_j phi (Pi_t' = d_i Psi^i on a static Cartesian patch).
+ *   outer_bc         PW_BC_EXACT (0): the outer ghosts of the global patch hold the
+ *                    registered exact solution (the paper's analytic BCs, Sec. 3), or a
+ *                    copy of the nearest interior cell if none is registered.
+ *                    PW_BC_SOMMERFELD (1): the outer ghosts are evolved with the state by
+ *                    the radiative condition d_t u = -v (X.grad u + u)/r for waves leaving
+ *                    the origin (every field, asymptotic value 0; 4th-order centred
+ *                    derivatives along interior axes, 2nd-order one-sided inward along
+ *                    ghost axes).  They start from the PW_BC_EXACT value at the first
+ *                    step after the state is set.  Needs a non-periodic global patch.
  */
 typedef struct {
   int32_t precision;
@@ -94,11 +111,15 @@ typedef struct {
   void *(*dev_alloc)(uint64_t bytes, void *user);
   void (*dev_free)(void *ptr, void *user);
   void *alloc_user;
+  int32_t pi_form;
+  int32_t outer_bc;
 } pw_config;
 
 /*
  * Patch description (Secs. 2.1 and 2.4.1): numerical box [lo,hi] of n cells per axis
- * (cell-centred), topology map M (Cartesian identity, or spherical (r,theta,phi)),
+ * (cell-centred), topology map M (Cartesian identity; spherical x' = (r,theta,phi),
+ * M = r (sin th cos ph, sin th sin ph, cos th); cylindrical x' = (r,phi,z),
+ * M = (r cos ph, r sin ph, z); Secs. 2.1 and 3.4),
  * orientation R(t) and centre motion c(t), so that the background Cartesian
  * coordinates are X_B = c(t) + R(t) M(x').
  *   motion PW_STATIC: c = c0; PW_LINEAR: c = c0 + vel t;
@@ -106,7 +127,10 @@ typedef struct {
  *   orientation R(t) = Q(t) R0: R0 the ZYZ Euler rotation euler_zyz, Q(t) the rotation
  *          by |spin| t about spin/|spin| (a patch rotating about its centre with
  *          angular velocity spin, background frame; spin = 0: R(t) = R0).
- *   periodic[a]: axis a wraps (the spherical phi axis; every axis of a periodic global box).
+ *   periodic[a]: axis a wraps (the phi axis of a spherical or cylindrical patch, which
+ *          must then span 2 pi; every axis of a periodic global box).  A curvilinear
+ *          patch keeps its ghosts off r = 0 (and a spherical one off the poles);
+ *          phi values of a non-periodic phi axis lie in (-pi, pi].
  *   sv_mask: bit s set if the patch carries state vector s.
  * The first patch created must be the global one (is_global = 1, Cartesian, static,
  * unrotated, no spin); every later patch is a local patch.

@@ -46,6 +46,8 @@ def lib():
         L.or_new.restype = vp
         L.or_new.argtypes = [C.c_int, dp, ip, C.c_double, C.c_int]
         L.or_set_form.argtypes = [vp, C.c_int]
+        L.or_set_outer_bc.argtypes = [vp, C.c_int]
+        L.or_rhs_outer.argtypes = [vp, C.c_int, dp]
         L.or_free.argtypes = [vp]
         L.or_add_patch.restype = C.c_int
         L.or_add_patch.argtypes = [vp, C.c_int, C.c_int, ip, dp, dp, ip, dp, C.c_int, dp, dp,
@@ -97,7 +99,7 @@ def _i(a):
 class OracleWorld:
     """One global patch (id 0) plus local patches, FP64 throughout."""
 
-    def __init__(self, wave_speed=(1.0,), interp_points=None, ko_eps=0.005, buffer=4, pi_form=0):
+    def __init__(self, wave_speed=(1.0,), interp_points=None, ko_eps=0.005, buffer=4, pi_form=0, outer_bc=0):
         self.L = lib()
         nsv = len(wave_speed)
         if interp_points is None:
@@ -109,6 +111,7 @@ class OracleWorld:
             raise ValueError("bad oracle world parameters")
         if self.L.or_set_form(self.h, pi_form) != 0:
             raise ValueError("bad form of the Pi_t equation")
+        self.outer_bc = outer_bc
         self.nsv = nsv
         self.patches = []
 
@@ -142,6 +145,8 @@ class OracleWorld:
             sp, spp = _d(d["spin"])
             if self.L.or_set_spin(self.h, pid, spp) != 0:
                 raise ValueError("oracle rejected spin")
+        if pid == 0 and self.outer_bc != 0 and self.L.or_set_outer_bc(self.h, self.outer_bc) != 0:
+            raise ValueError("oracle rejected the outer boundary condition")
         self.patches.append(dict(d))
         return pid
 
@@ -310,6 +315,15 @@ class OracleWorld:
         self.L.or_rhs(self.h, pid, sv, t, op)
         return out
 
+    def rhs_outer(self, sv=0):
+        """Sommerfeld right-hand side at the outer ghost cells of the global
+        patch (full padded array [5][n2+6][n1+6][n0+6], NaN elsewhere)."""
+        out = np.full(self.full_shape(0), np.nan)
+        _, op = _d(out)
+        if self.L.or_rhs_outer(self.h, sv, op) != 0:
+            raise ValueError("no global patch or state vector")
+        return out
+
     def stencil(self, pid, op, d, e, i, j, k, sv=0):
         return self.L.or_stencil(self.h, pid, sv, op, d, e, i, j, k)
 
@@ -325,7 +339,8 @@ def lagrange(P, q):
 def world_from_config(cfg):
     """Build an oracle world from a workload config (see workloads.py)."""
     w = OracleWorld(wave_speed=cfg["wave_speed"], interp_points=cfg["interp_points"],
-                    ko_eps=cfg.get("ko_eps", 0.005), buffer=cfg.get("buffer", 4), pi_form=cfg.get("pi_form", 0))
+                    ko_eps=cfg.get("ko_eps", 0.005), buffer=cfg.get("buffer", 4), pi_form=cfg.get("pi_form", 0),
+                    outer_bc=cfg.get("outer_bc", 0))
     for d in cfg["patches"]:
         w.add_patch(d)
     for sv, ex in enumerate(cfg.get("exact", [])):

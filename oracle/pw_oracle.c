@@ -113,6 +113,9 @@ typedef struct {
   int buffer;               /* buffer width, NG + 1 in the paper */
   int form;                 /* 0: the paper's Pi_t equation (second derivatives of phi);
                                1: first-order form, Psi_i = Pi_i in place of d_i phi */
+  int outer_bc;             /* global outer ghosts: 0 the exact solution (analytic BC);
+                               1 evolved by the Sommerfeld radiative condition */
+  int outer_ready;          /* Sommerfeld: the outer ghosts of u hold evolved values */
   or_patch p[MAXP];
   or_exact ex[MAXSV];
   double t;
@@ -722,6 +725,8 @@ static void fill_ghosts(or_world *w, int which, double t) {
             for (int a = 0; a < 3; a++) cw[a] = p->periodic[a] ? wrapi(c[a], p->n[a]) : c[a];
             if (is_interior(p, cw)) {
               for (int f = 0; f < NF; f++) T[IX(p, f, i, j, k)] = T[IX(p, f, cw[0], cw[1], cw[2])];
+            } else if (p->is_global && w->outer_bc == 1) {
+              continue; /* evolved by the radiative condition */
             } else if (w->ex[sv].kind != EX_NONE) {
               double xp[3] = {xnum(p, 0, i), xnum(p, 1, j), xnum(p, 2, k)}, e[5];
               exact_patch(w, p, sv, t, xp, e);
@@ -787,6 +792,71 @@ static void fill_ghosts(or_world *w, int which, double t) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Sommerfeld outer boundary (variant; the paper lays the exact solution into */
+/* the outer ghosts).  Each outer ghost cell of the (non-periodic) global     */
+/* patch is evolved with the radiative condition for waves leaving the       */
+/* origin, d_t u = -v (X.grad u + u) / r, r = |X|, on every field (falloff    */
+/* u ~ f(r - vt)/r, asymptotic value 0).  Derivatives: 4th-order centred      */
+/* along axes where the cell is interior, 2nd-order one-sided (inward) along  */
+/* axes where it is a ghost.                                                  */
+/* ------------------------------------------------------------------------ */
+static int is_outer_ghost(const or_patch *p, int i, int j, int k) {
+  int c[3] = {i, j, k};
+  return !is_interior(p, c);
+}
+
+static void radiative_rhs(const or_world *w, const or_patch *p, int sv, const double *T, int i, int j, int k,
+                          double K[5]) {
+  const int c[3] = {i, j, k};
+  double X[3] = {xnum(p, 0, i), xnum(p, 1, j), xnum(p, 2, k)};
+  double r = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+  double v = w->vs[sv];
+  for (int f = 0; f < NF; f++) {
+    double xgrad = 0.0;
+    for (int a = 0; a < 3; a++) {
+      int e[3] = {0, 0, 0};
+      e[a] = 1;
+#define UAT(s) T[IX(p, f, c[0] + (s) * e[0], c[1] + (s) * e[1], c[2] + (s) * e[2])]
+      double d;
+      if (c[a] < 0)
+        d = (-3.0 * UAT(0) + 4.0 * UAT(1) - UAT(2)) / (2.0 * p->dx[a]);
+      else if (c[a] >= p->n[a])
+        d = (3.0 * UAT(0) - 4.0 * UAT(-1) + UAT(-2)) / (2.0 * p->dx[a]);
+      else
+        d = (UAT(-2) - 8.0 * UAT(-1) + 8.0 * UAT(1) - UAT(2)) / (12.0 * p->dx[a]);
+#undef UAT
+      xgrad += X[a] * d;
+    }
+    K[f] = -v * (xgrad + T[IX(p, f, i, j, k)]) / r;
+  }
+}
+
+/* one-time fill of the outer ghosts of u before the first Sommerfeld step:
+ * the exact solution if registered, else a copy of the nearest interior cell */
+static void init_outer_ghosts(or_world *w, double t) {
+  or_patch *p = &w->p[0];
+  for (int sv = 0; sv < w->nsv; sv++) {
+    if (!(p->sv_mask & (1u << sv))) continue;
+    double *U = p->u[sv];
+    for (int k = -NG; k < p->n[2] + NG; k++)
+      for (int j = -NG; j < p->n[1] + NG; j++)
+        for (int i = -NG; i < p->n[0] + NG; i++) {
+          if (!is_outer_ghost(p, i, j, k)) continue;
+          if (w->ex[sv].kind != EX_NONE) {
+            double xp[3] = {xnum(p, 0, i), xnum(p, 1, j), xnum(p, 2, k)}, e[5];
+            exact_patch(w, p, sv, t, xp, e);
+            for (int f = 0; f < NF; f++) U[IX(p, f, i, j, k)] = e[f];
+          } else {
+            int cc[3] = {i, j, k};
+            for (int a = 0; a < 3; a++) cc[a] = cc[a] < 0 ? 0 : (cc[a] >= p->n[a] ? p->n[a] - 1 : cc[a]);
+            for (int f = 0; f < NF; f++) U[IX(p, f, i, j, k)] = U[IX(p, f, cc[0], cc[1], cc[2])];
+          }
+        }
+  }
+  w->outer_ready = 1;
+}
+
+/* ------------------------------------------------------------------------ */
 /* RK4 step (Sec. 2.3)                                                       */
 /* ------------------------------------------------------------------------ */
 static void eval_rhs(or_world *w, int which, double t) {
@@ -805,6 +875,16 @@ static void eval_rhs(or_world *w, int which, double t) {
             rhs_cell(w, p, sv, T, t, i, j, k, Kc);
             for (int f = 0; f < NF; f++) K[IX(p, f, i, j, k)] = Kc[f];
           }
+      if (p->is_global && w->outer_bc == 1) {
+        for (int k = -NG; k < p->n[2] + NG; k++)
+          for (int j = -NG; j < p->n[1] + NG; j++)
+            for (int i = -NG; i < p->n[0] + NG; i++) {
+              if (!is_outer_ghost(p, i, j, k)) continue;
+              double Kc[5];
+              radiative_rhs(w, p, sv, T, i, j, k, Kc);
+              for (int f = 0; f < NF; f++) K[IX(p, f, i, j, k)] = Kc[f];
+            }
+      }
     }
   }
 }
@@ -831,6 +911,22 @@ static void stage_update(or_world *w, int first, double bdt, double adt, int las
               }
             }
           }
+      if (p->is_global && w->outer_bc == 1) {
+        for (int k = -NG; k < p->n[2] + NG; k++)
+          for (int j = -NG; j < p->n[1] + NG; j++)
+            for (int i = -NG; i < p->n[0] + NG; i++) {
+              if (!is_outer_ghost(p, i, j, k)) continue;
+              for (int f = 0; f < NF; f++) {
+                long long x = IX(p, f, i, j, k);
+                if (last) {
+                  U[x] = A[x] + bdt * K[x];
+                } else {
+                  A[x] = (first ? U[x] : A[x]) + bdt * K[x];
+                  V[x] = U[x] + adt * K[x];
+                }
+              }
+            }
+      }
     }
   }
 }
@@ -918,6 +1014,35 @@ or_world *or_new(int nsv, const double *wave_speed, const int *interp_points, do
 int or_set_form(or_world *w, int form) {
   if (form != 0 && form != 1) return -1;
   w->form = form;
+  return 0;
+}
+
+/* outer boundary of the global patch: 0 exact solution, 1 Sommerfeld (needs a
+ * non-periodic global patch) */
+int or_set_outer_bc(or_world *w, int bc) {
+  if (bc != 0 && bc != 1) return -1;
+  if (bc == 1 && w->np > 0)
+    for (int a = 0; a < 3; a++)
+      if (w->p[0].periodic[a]) return -1;
+  w->outer_bc = bc;
+  w->outer_ready = 0;
+  return 0;
+}
+
+/* right-hand side at every outer ghost cell of the global patch from u
+ * (Sommerfeld), into the full padded array dst (other cells untouched) */
+int or_rhs_outer(or_world *w, int sv, double *dst) {
+  if (w->np < 1) return -1;
+  or_patch *p = &w->p[0];
+  if (!p->u[sv]) return -1;
+  for (int k = -NG; k < p->n[2] + NG; k++)
+    for (int j = -NG; j < p->n[1] + NG; j++)
+      for (int i = -NG; i < p->n[0] + NG; i++) {
+        if (!is_outer_ghost(p, i, j, k)) continue;
+        double Kc[5];
+        radiative_rhs(w, p, sv, p->u[sv], i, j, k, Kc);
+        for (int f = 0; f < NF; f++) dst[IX(p, f, i, j, k)] = Kc[f];
+      }
   return 0;
 }
 
@@ -1030,6 +1155,7 @@ int or_set_state(or_world *w, int pi, int sv, const double *src, double t0) {
         for (int i = 0; i < p->n[0]; i++) p->u[sv][IX(p, f, i, j, k)] = src[x++];
   w->t = t0;
   w->flags_valid = 0;
+  w->outer_ready = 0;
   return 0;
 }
 
@@ -1069,6 +1195,7 @@ int or_init_exact(or_world *w, double t0) {
   }
   w->t = t0;
   w->flags_valid = 0;
+  w->outer_ready = 0;
   return 0;
 }
 
@@ -1094,6 +1221,7 @@ int or_step(or_world *w, double dt, int nsteps) {
   for (int n = 0; n < nsteps; n++) {
     if (!w->flags_valid) { int rc = refresh_flags(w); if (rc) return rc; }
     double tn = w->t;
+    if (w->outer_bc == 1 && !w->outer_ready) init_outer_ghosts(w, tn);
     /* K1 = f(t_n, u_n); u_{n+1/2} accumulates b1 K1 + b2 K2 + b3 K3 (Table rk4) */
     fill_ghosts(w, 0, tn);
     eval_rhs(w, 0, tn);

@@ -44,6 +44,10 @@ struct pw_context {
   // lists
   GhostRec *dLower = nullptr;
   int nLower = 0, nLowerGlobal = 0;
+  // Sommerfeld outer boundary: the global patch's outer ghost cells (evolved)
+  GhostRec *dRad = nullptr;
+  int nRad = 0;
+  bool outer_ready = false;  // their values in u are set (state changes clear it)
   hipStream_t stream2 = nullptr;  // second branch of the overlapped step
   hipStream_t stream3 = nullptr;  // third branch: the next step's cover flags and lists
   hipEvent_t evFork = nullptr, evG[4] = {nullptr, nullptr, nullptr, nullptr},
@@ -62,7 +66,8 @@ struct pw_context {
   TileRec *dTiles = nullptr;
   int nTiles = 0;
   std::vector<int> tileOff, tileCnt;
-  int nCartTiles = 0, nGlobalTiles = 0;
+  int nGlobalTiles = 0;
+  int coordTiles[4] = {0, 0, 0, 0};  // tiles grouped by topology: group t is [coordTiles[t], coordTiles[t+1])
   CoverJob *dJobs = nullptr;
   int nJobs = 0, coverBlocks = 1;
   double *dStage = nullptr;  // staging for host copies
@@ -140,6 +145,10 @@ void euler_zyz(const double e[3], double R[9]) {
 
 double bound_radius(const pw_patch_desc &d) {
   if (d.coord == PW_SPH) return d.hi[0];
+  if (d.coord == PW_CYL) {
+    const double zm = std::max(fabs(d.lo[2]), fabs(d.hi[2]));
+    return sqrt(d.hi[0] * d.hi[0] + zm * zm);
+  }
   double m = 0;
   for (int c = 0; c < 8; c++) {
     double y0 = (c & 1) ? d.hi[0] : d.lo[0], y1 = (c & 2) ? d.hi[1] : d.lo[1], y2 = (c & 4) ? d.hi[2] : d.lo[2];
@@ -215,8 +224,9 @@ pw_status upload_layout(pw_context *c) {
   // the interpatch targets of every local patch as bricks of at most 8x8x3 cells
   // on its six faces (z faces span the full padded x-y range, y faces the full
   // padded x range, x faces the interior y-z range, so the faces are disjoint).
-  std::vector<GhostRec> lower;
+  std::vector<GhostRec> lower, rad;
   std::vector<GBrick> bricks;
+  const bool somm = c->cfg.outer_bc == PW_BC_SOMMERFELD;
   for (int pid = 0; pid < np; pid++) {
     const PatchDev &p = c->hp[pid];
     for (int k = -PW_NG; k < p.n[2] + PW_NG; k++)
@@ -230,7 +240,10 @@ pw_status upload_layout(pw_context *c) {
             wrapped_inside = wrapped_inside && w >= 0 && w < p.n[a];
           }
           if (inside) continue;
-          if (wrapped_inside || p.is_global) lower.push_back(GhostRec{pid, pack_ijk(i, j, k)});
+          if (p.is_global && !wrapped_inside && somm)
+            rad.push_back(GhostRec{pid, pack_ijk(i, j, k)});
+          else if (wrapped_inside || p.is_global)
+            lower.push_back(GhostRec{pid, pack_ijk(i, j, k)});
         }
     if (p.is_global) {
       c->nLowerGlobal = (int)lower.size();
@@ -267,6 +280,12 @@ pw_status upload_layout(pw_context *c) {
     add(-g, 0, 0, n1, 0, n2, 3, 8, 8);                  // x- face
     add(n0, n0 + g, 0, n1, 0, n2, 3, 8, 8);             // x+ face
   }
+  dfree(c, c->dRad);
+  c->nRad = (int)rad.size();
+  c->dRad = (GhostRec *)dalloc(c, sizeof(GhostRec) * std::max<size_t>(1, rad.size()));
+  if (!c->dRad) return fail(c, PW_ENOMEM, "device allocation failed");
+  if (!rad.empty()) HIPCHK(c, hipMemcpy(c->dRad, rad.data(), sizeof(GhostRec) * rad.size(), hipMemcpyHostToDevice));
+  c->outer_ready = false;
   dfree(c, c->dLower);
   dfree(c, c->dBricks);
   c->nLower = (int)lower.size();
@@ -324,28 +343,27 @@ pw_status upload_layout(pw_context *c) {
     c->fbCap = cap;
   }
 
-  // Tiles of every patch, grouped by patch, Cartesian patches first.
+  // Tiles of every patch, grouped by patch and the patches by topology
+  // (Cartesian, spherical, cylindrical; the global patch first).
   std::vector<TileRec> tiles;
   c->tileOff.assign(np, 0);
   c->tileCnt.assign(np, 0);
-  std::vector<int> order;
-  for (int pid = 0; pid < np; pid++)
-    if (c->hp[pid].coord == CART) order.push_back(pid);
-  for (int pid = 0; pid < np; pid++)
-    if (c->hp[pid].coord != CART) order.push_back(pid);
-  c->nCartTiles = 0;
-  for (int pid : order) {
-    const PatchDev &p = c->hp[pid];
-    c->tileOff[pid] = (int)tiles.size();
-    const int TX = pid == 0 ? StageTile<true>::TX : StageTile<false>::TX;
-    const int TY = pid == 0 ? StageTile<true>::TY : StageTile<false>::TY;
-    const int TZ = pid == 0 ? c->tune.tile_z_global : c->tune.tile_z_local;
-    for (int z = 0; z < p.n[2]; z += TZ)
-      for (int y = 0; y < p.n[1]; y += TY)
-        for (int x = 0; x < p.n[0]; x += TX) tiles.push_back(TileRec{pid, x, y, z, std::min(TZ, p.n[2] - z)});
-    c->tileCnt[pid] = (int)tiles.size() - c->tileOff[pid];
-    if (p.coord == CART) c->nCartTiles = (int)tiles.size();
+  for (int t = 0; t < 3; t++) {
+    c->coordTiles[t] = (int)tiles.size();
+    for (int pid = 0; pid < np; pid++) {
+      const PatchDev &p = c->hp[pid];
+      if (p.coord != t) continue;
+      c->tileOff[pid] = (int)tiles.size();
+      const int TX = pid == 0 ? StageTile<true>::TX : StageTile<false>::TX;
+      const int TY = pid == 0 ? StageTile<true>::TY : StageTile<false>::TY;
+      const int TZ = pid == 0 ? c->tune.tile_z_global : c->tune.tile_z_local;
+      for (int z = 0; z < p.n[2]; z += TZ)
+        for (int y = 0; y < p.n[1]; y += TY)
+          for (int x = 0; x < p.n[0]; x += TX) tiles.push_back(TileRec{pid, x, y, z, std::min(TZ, p.n[2] - z)});
+      c->tileCnt[pid] = (int)tiles.size() - c->tileOff[pid];
+    }
   }
+  c->coordTiles[3] = (int)tiles.size();
   c->nGlobalTiles = c->tileCnt[0];  // the global patch is Cartesian and comes first
   dfree(c, c->dTiles);
   c->nTiles = (int)tiles.size();
@@ -504,6 +522,18 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
   }
 }
 
+// One stage launch per topology over the tiles of all local patches of that
+// topology (the global patch's tiles lead the Cartesian group).
+void launch_local_groups(pw_context *c, StageArgs a, hipStream_t st) {
+  for (int t = 0; t < 3; t++) {
+    const int b = t == CART ? c->nGlobalTiles : c->coordTiles[t];
+    a.tiles = c->dTiles + b;
+    a.ntiles = c->coordTiles[t + 1] - b;
+    a.coord = t;
+    launch_stage(st, a);
+  }
+}
+
 void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt) {
   for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
     StageArgs a;
@@ -514,6 +544,7 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
     a.stage = stage;
     a.mixed = mixed(c);
     a.inc = c->cfg.precision == PW_MIXED_INC;
+    a.form = c->cfg.pi_form;
     a.dt = dt;
     a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
     a.eps = c->cfg.ko_eps;
@@ -526,12 +557,15 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
         a.ntiles = c->tileCnt[pid];
         a.coord = c->hp[pid].coord;
         a.global = pid == 0;
-        Timed tg(c, pid == 0 ? PW_K_GSTAGE_S1 + stage : -1);
-        launch_stage(c->stream, a);
+        {
+          Timed tg(c, pid == 0 ? PW_K_GSTAGE_S1 + stage : -1);
+          launch_stage(c->stream, a);
+        }
+        if (pid == 0) launch_radiative(c->stream, c->dP, c->dRad, c->nRad, sv, stage, a.mixed, a.inc, dt, c->cfg.wave_speed[sv]);
       }
     } else {
-      // batched: one launch over the global patch's tiles, one over the tiles of
-      // all Cartesian local patches, one over those of all spherical patches
+      // batched: one launch over the global patch's tiles, then one over the
+      // tiles of all local patches of each topology
       {
         Timed tg(c, PW_K_GSTAGE_S1 + stage);
         a.tiles = c->dTiles;
@@ -540,15 +574,9 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
         a.global = 1;
         launch_stage(c->stream, a);
       }
+      launch_radiative(c->stream, c->dP, c->dRad, c->nRad, sv, stage, a.mixed, a.inc, dt, c->cfg.wave_speed[sv]);
       a.global = 0;
-      a.tiles = c->dTiles + c->nGlobalTiles;
-      a.ntiles = c->nCartTiles - c->nGlobalTiles;
-      a.coord = CART;
-      launch_stage(c->stream, a);
-      a.tiles = c->dTiles + c->nCartTiles;
-      a.ntiles = c->nTiles - c->nCartTiles;
-      a.coord = SPH;
-      launch_stage(c->stream, a);
+      launch_local_groups(c, a, c->stream);
     }
   }
 }
@@ -564,6 +592,7 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
     a.stage = stage;
     a.mixed = mixed(c);
     a.inc = c->cfg.precision == PW_MIXED_INC;
+    a.form = c->cfg.pi_form;
     a.dt = dt;
     a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
     a.eps = c->cfg.ko_eps;
@@ -574,20 +603,14 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
       a.coord = CART;
       a.global = 1;
       launch_stage(st, a);
+      launch_radiative(st, c->dP, c->dRad, c->nRad, sv, stage, a.mixed, a.inc, dt, c->cfg.wave_speed[sv]);
       continue;
     }
     a.global = 0;
     bool all = true;
     for (size_t pid = 1; pid < c->hp.size(); pid++) all = all && (c->hp[pid].sv_mask & (1u << sv));
     if (all) {
-      a.tiles = c->dTiles + c->nGlobalTiles;
-      a.ntiles = c->nCartTiles - c->nGlobalTiles;
-      a.coord = CART;
-      launch_stage(st, a);
-      a.tiles = c->dTiles + c->nCartTiles;
-      a.ntiles = c->nTiles - c->nCartTiles;
-      a.coord = SPH;
-      launch_stage(st, a);
+      launch_local_groups(c, a, st);
     } else {
       for (size_t pid = 1; pid < c->hp.size(); pid++) {
         if (!(c->hp[pid].sv_mask & (1u << sv))) continue;
@@ -723,6 +746,8 @@ pw_status pw_create(const pw_config *cfg, pw_context **out) {
   if (cfg->n_state_vectors < 1 || cfg->n_state_vectors > PW_MAX_SV) return PW_EINVAL;
   if (cfg->precision != PW_FP64 && cfg->precision != PW_MIXED && cfg->precision != PW_MIXED_INC) return PW_EINVAL;
   if (cfg->buffer_width < 4) return PW_EINVAL;
+  if (cfg->pi_form != PW_FORM_PAPER && cfg->pi_form != PW_FORM_FIRST_ORDER) return PW_EINVAL;
+  if (cfg->outer_bc != PW_BC_EXACT && cfg->outer_bc != PW_BC_SOMMERFELD) return PW_EINVAL;
   for (int s = 0; s < cfg->n_state_vectors; s++) {
     if (cfg->interp_points[s] != 5 && cfg->interp_points[s] != 6) return PW_EINVAL;
     if (!(cfg->wave_speed[s] > 0)) return PW_EINVAL;
@@ -799,7 +824,7 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     if (!(d->hi[a] > d->lo[a])) return fail(c, PW_EINVAL, "empty numerical box");
     if (d->periodic[a] && d->n[a] < PW_NG) return fail(c, PW_EINVAL, "periodic axis needs at least 3 cells");
   }
-  if (d->coord != PW_CART && d->coord != PW_SPH) return fail(c, PW_EINVAL, "unknown topology");
+  if (d->coord != PW_CART && d->coord != PW_SPH && d->coord != PW_CYL) return fail(c, PW_EINVAL, "unknown topology");
   if (d->motion < PW_STATIC || d->motion > PW_CIRCLE) return fail(c, PW_EINVAL, "unknown motion");
   if (d->motion == PW_CIRCLE && !(d->radius > 0)) return fail(c, PW_EINVAL, "circle motion needs radius > 0");
   if (first) {
@@ -807,10 +832,14 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
         d->euler_zyz[2] != 0 || d->c0[0] != 0 || d->c0[1] != 0 || d->c0[2] != 0 || d->spin[0] != 0 ||
         d->spin[1] != 0 || d->spin[2] != 0)
       return fail(c, PW_EINVAL, "the global patch is Cartesian, static and unrotated");
+    if (c->cfg.outer_bc == PW_BC_SOMMERFELD && (d->periodic[0] || d->periodic[1] || d->periodic[2]))
+      return fail(c, PW_EINVAL, "the Sommerfeld outer boundary needs a non-periodic global patch");
   } else {
-    if (d->periodic[0] || d->periodic[1] || (d->periodic[2] && d->coord != PW_SPH))
-      return fail(c, PW_EINVAL, "local patches are periodic only along the spherical phi axis");
-    if (d->coord == PW_SPH && !(d->lo[0] > 0)) return fail(c, PW_EINVAL, "spherical patch needs r_min > 0");
+    const int phi_axis = d->coord == PW_SPH ? 2 : d->coord == PW_CYL ? 1 : -1;
+    for (int a = 0; a < 3; a++)
+      if (d->periodic[a] && a != phi_axis)
+        return fail(c, PW_EINVAL, "local patches are periodic only along a spherical or cylindrical phi axis");
+    if (d->coord != PW_CART && !(d->lo[0] > 0)) return fail(c, PW_EINVAL, "curvilinear patch needs r_min > 0");
     const PatchDev &g = c->hp[0];
     if (g.periodic[0] || g.periodic[1] || g.periodic[2])
       return fail(c, PW_EINVAL, "local patches need a non-periodic global patch");
@@ -821,6 +850,12 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     double r_lo = d->lo[0] - PW_NG * (d->hi[0] - d->lo[0]) / d->n[0];
     if (!(th_lo > 0 && th_hi < M_PI && r_lo > 0)) return fail(c, PW_EINVAL, "spherical ghosts must avoid r=0 and the poles");
     if (d->periodic[2] && fabs(d->hi[2] - d->lo[2] - 2 * M_PI) > 1e-12)
+      return fail(c, PW_EINVAL, "periodic phi axis must span 2 pi");
+  }
+  if (d->coord == PW_CYL) {
+    double r_lo = d->lo[0] - PW_NG * (d->hi[0] - d->lo[0]) / d->n[0];
+    if (!(r_lo > 0)) return fail(c, PW_EINVAL, "cylindrical ghosts must avoid the axis r=0");
+    if (d->periodic[1] && fabs(d->hi[1] - d->lo[1] - 2 * M_PI) > 1e-12)
       return fail(c, PW_EINVAL, "periodic phi axis must span 2 pi");
   }
   unsigned mask_all = (1u << c->cfg.n_state_vectors) - 1u;
@@ -972,6 +1007,7 @@ pw_status pw_init_exact(pw_context *c, double t0) {
   HIPCHK(c, hipGetLastError());
   c->t_host = t0;
   c->flags_valid = false;
+  c->outer_ready = false;
   return PW_OK;
 }
 
@@ -997,6 +1033,7 @@ pw_status pw_set_state(pw_context *c, int32_t pid, int32_t sv, const double *src
   if (rc) return rc;
   c->t_host = t0;
   c->flags_valid = false;
+  c->outer_ready = false;
   return PW_OK;
 }
 
@@ -1043,9 +1080,32 @@ pw_status pw_get_flags(pw_context *c, uint8_t *flags, int32_t *cover, int64_t n)
   return PW_OK;
 }
 
+// Sommerfeld outer boundary: before the first step on a new state, the outer
+// ghosts of u (and of its FP32 copy) take the lower-priority value at the
+// current time; from then on they are evolved with the state.
+pw_status ensure_outer(pw_context *c) {
+  if (c->cfg.outer_bc != PW_BC_SOMMERFELD || c->outer_ready) return PW_OK;
+  pw_status rc = upload_layout(c);
+  if (rc) return rc;
+  const int np = (int)c->hp.size();
+  launch_pose_at(c->stream, c->dP, np, c->t_host, c->dPose + 3 * np);
+  for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
+    launch_fill_list(c->stream, c->dP, c->dPose + 3 * np, c->dRad, c->nRad, sv, 1, c->dEx, c->cfg.wave_speed[sv],
+                     c->dT);
+    if (mixed(c))
+      launch_fill_list(c->stream, c->dP, c->dPose + 3 * np, c->dRad, c->nRad, sv, 0, c->dEx,
+                       c->cfg.wave_speed[sv], c->dT);
+  }
+  HIPCHK(c, hipGetLastError());
+  c->outer_ready = true;
+  return PW_OK;
+}
+
 pw_status pw_exchange_ghosts(pw_context *c, double t) {
   if (!c) return PW_EINVAL;
   pw_status rc = ensure_flags(c);
+  if (rc) return rc;
+  rc = ensure_outer(c);
   if (rc) return rc;
   int np = (int)c->hp.size();
   rc = set_time(c, c->dTx, t);
@@ -1073,6 +1133,8 @@ pw_status pw_rk4_step(pw_context *c, double dt, int32_t nsteps) {
     if (sp * dt >= hmin) return fail(c, PW_EMOTION, "a patch moves one global cell or more within a step");
   }
   pw_status rc = ensure_flags(c);
+  if (rc) return rc;
+  rc = ensure_outer(c);
   if (rc) return rc;
   bool graph = c->cfg.use_graph && c->cfg.schedule == PW_SCHED_BATCHED && !c->timing;
   if (graph && (c->gexec == nullptr || c->graph_dt != dt)) {

@@ -14,7 +14,7 @@
 
 namespace pw {
 
-enum { CART = 0, SPH = 1 };
+enum { CART = 0, SPH = 1, CYL = 2 };
 enum { STATIC = 0, LINEAR = 1, CIRCLE = 2 };
 enum { LIVE = 0, EFFGHOST = 1, DEACT = 2 };
 enum { EX_NONE = 0, EX_PLANE = 1, EX_GAUSS = 2 };
@@ -39,7 +39,8 @@ struct PatchDev {
   void *vb[PW_MAXSV];
   float *us[PW_MAXSV];  // mixed precision: FP32 copy of u (stage-1 stencil input), else null
   // spherical patches: sin, cos of theta_j (j = -3 .. n1+2) and of phi_k
-  // (k = -3 .. n2+2), laid out [sin th][cos th][sin ph][cos ph]; null otherwise
+  // (k = -3 .. n2+2), laid out [sin th][cos th][sin ph][cos ph]; cylindrical
+  // patches: sin, cos of phi_j (j = -3 .. n1+2), [sin ph][cos ph]; null otherwise
   const double *trig;
   double spin[3];  // angular velocity of a rotation about the centre (background frame)
 };
@@ -148,50 +149,58 @@ __device__ inline void frame_velocity(const PoseDev &ps, const double y[3], doub
   V[2] = ps.cd[2] + (ps.w[0] * Ry[1] - ps.w[1] * Ry[0]);
 }
 
-__device__ inline double xnum(const PatchDev &p, int a, int i) { return p.lo[a] + (i + 0.5) * p.dx[a]; }
+// Cell centre along axis a, rounded as written (product, then sum; no fused
+// multiply-add), so that decisions taken on it (the closed-box cover test, a
+// centre exactly on a patch face) match a plain evaluation of the same formula.
+__device__ inline double xnum(const PatchDev &p, int a, int i) {
+#pragma clang fp contract(off)
+  return p.lo[a] + (i + 0.5) * p.dx[a];
+}
 
-// Orthonormal spherical basis at (theta, phi).
-struct SphBasis {
-  double st, ct, sp, cp;
-  double er[3], et[3], ep[3];
+// Orthonormal frame of the numerical axes of a curvilinear patch at one point:
+// e[a] = (dy/dx'^a) / h[a], h the scale factors, y the patch-frame Cartesian
+// point.  Spherical x' = (r, theta, phi): e = (e_r, e_theta, e_phi),
+// h = (1, r, r sin theta).  Cylindrical x' = (r, phi, z): e = (e_r, e_phi, e_z),
+// h = (1, r, 1).
+struct Basis {
+  double e[3][3];
+  double h[3];
 };
-__device__ inline void sph_basis(double th, double ph, SphBasis &B) {
-  sincos(th, &B.st, &B.ct);
-  sincos(ph, &B.sp, &B.cp);
-  B.er[0] = B.st * B.cp; B.er[1] = B.st * B.sp; B.er[2] = B.ct;
-  B.et[0] = B.ct * B.cp; B.et[1] = B.ct * B.sp; B.et[2] = -B.st;
-  B.ep[0] = -B.sp; B.ep[1] = B.cp; B.ep[2] = 0.0;
+__device__ inline void sph_frame(double r, double st, double ct, double sp, double cp, Basis &B) {
+  B.e[0][0] = st * cp; B.e[0][1] = st * sp; B.e[0][2] = ct;
+  B.e[1][0] = ct * cp; B.e[1][1] = ct * sp; B.e[1][2] = -st;
+  B.e[2][0] = -sp;     B.e[2][1] = cp;      B.e[2][2] = 0.0;
+  B.h[0] = 1.0; B.h[1] = r; B.h[2] = r * st;
+}
+__device__ inline void cyl_frame(double r, double sp, double cp, Basis &B) {
+  B.e[0][0] = cp;  B.e[0][1] = sp; B.e[0][2] = 0.0;
+  B.e[1][0] = -sp; B.e[1][1] = cp; B.e[1][2] = 0.0;
+  B.e[2][0] = 0.0; B.e[2][1] = 0.0; B.e[2][2] = 1.0;
+  B.h[0] = 1.0; B.h[1] = r; B.h[2] = 1.0;
 }
 
-// The same basis at the grid angles theta_j, phi_k of a spherical patch, from
-// its tables (filled with sincos of the same angles).
-__device__ inline void sph_basis_grid(const PatchDev &p, int j, int k, SphBasis &B) {
-  const int t1 = p.n[1] + 2 * PW_NG, t2 = p.n[2] + 2 * PW_NG;
-  B.st = p.trig[j + PW_NG];
-  B.ct = p.trig[t1 + j + PW_NG];
-  B.sp = p.trig[2 * t1 + k + PW_NG];
-  B.cp = p.trig[2 * t1 + t2 + k + PW_NG];
-  B.er[0] = B.st * B.cp; B.er[1] = B.st * B.sp; B.er[2] = B.ct;
-  B.et[0] = B.ct * B.cp; B.et[1] = B.ct * B.sp; B.et[2] = -B.st;
-  B.ep[0] = -B.sp; B.ep[1] = B.cp; B.ep[2] = 0.0;
+// Angle tables of a curvilinear patch (filled with sincos of the grid angles,
+// ghosts included).  Spherical: [sin th_j][cos th_j][sin ph_k][cos ph_k];
+// cylindrical: [sin ph_j][cos ph_j].
+__device__ inline void trig_axis(const PatchDev &p, int base, int len, int i, double &s, double &c) {
+  s = p.trig[base + i + PW_NG];
+  c = p.trig[base + len + i + PW_NG];
 }
 
-// The basis at the point y (patch-frame Cartesian, |y| = r > 0) without
-// trigonometry: sin th = rho / r, cos th = y_z / r, (cos ph, sin ph) = (y_x, y_y) / rho.
-__device__ inline void sph_basis_cart(const double y[3], double r, SphBasis &B) {
-  const double rho = sqrt(y[0] * y[0] + y[1] * y[1]);
-  B.st = rho / r;
-  B.ct = y[2] / r;
-  if (rho > 0.0) {
-    B.cp = y[0] / rho;
-    B.sp = y[1] / rho;
+// Patch-frame point y and frame B at numerical x' (curvilinear patches).
+__device__ inline void curv_point(const PatchDev &p, const double xp[3], Basis &B, double y[3]) {
+  if (p.coord == SPH) {
+    double st, ct, sp, cp;
+    sincos(xp[1], &st, &ct);
+    sincos(xp[2], &sp, &cp);
+    sph_frame(xp[0], st, ct, sp, cp, B);
+    for (int a = 0; a < 3; a++) y[a] = xp[0] * B.e[0][a];
   } else {
-    B.cp = 1.0;
-    B.sp = 0.0;
+    double sp, cp;
+    sincos(xp[1], &sp, &cp);
+    cyl_frame(xp[0], sp, cp, B);
+    y[0] = xp[0] * cp; y[1] = xp[0] * sp; y[2] = xp[2];
   }
-  B.er[0] = B.st * B.cp; B.er[1] = B.st * B.sp; B.er[2] = B.ct;
-  B.et[0] = B.ct * B.cp; B.et[1] = B.ct * B.sp; B.et[2] = -B.st;
-  B.ep[0] = -B.sp; B.ep[1] = B.cp; B.ep[2] = 0.0;
 }
 
 // Forward map: numerical x' of patch p -> background X at pose ps.
@@ -200,9 +209,8 @@ __device__ inline void fwd_map(const PatchDev &p, const PoseDev &ps, const doubl
   if (p.coord == CART) {
     y[0] = xp[0]; y[1] = xp[1]; y[2] = xp[2];
   } else {
-    SphBasis B;
-    sph_basis(xp[1], xp[2], B);
-    for (int a = 0; a < 3; a++) y[a] = xp[0] * B.er[a];
+    Basis B;
+    curv_point(p, xp, B, y);
   }
   for (int a = 0; a < 3; a++) X[a] = ps.c[a] + ps.R[3 * a] * y[0] + ps.R[3 * a + 1] * y[1] + ps.R[3 * a + 2] * y[2];
 }
@@ -214,64 +222,91 @@ __device__ inline void inv_map(const PatchDev &p, const PoseDev &ps, const doubl
   for (int b = 0; b < 3; b++) y[b] = ps.R[b] * d[0] + ps.R[3 + b] * d[1] + ps.R[6 + b] * d[2];
   if (p.coord == CART) {
     xp[0] = y[0]; xp[1] = y[1]; xp[2] = y[2];
-  } else {
+  } else if (p.coord == SPH) {
     double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
     xp[0] = r;
     xp[1] = acos(y[2] / r);
     xp[2] = atan2(y[1], y[0]);
+  } else {
+    xp[0] = sqrt(y[0] * y[0] + y[1] * y[1]);
+    xp[1] = atan2(y[1], y[0]);
+    xp[2] = y[2];
   }
 }
 
 // One-form from patch frame to background: given (Pi_t, Pi_i) in the numerical
-// frame of p at x' (patch-frame Cartesian point y), return Pi_t^B and the
-// background gradient G = d phi/dX: G = R (spatial part in patch axes),
-// Pi_t^B = Pi_t - V.G with V the frame velocity at y.  For the spherical map the
-// spatial part is the usual gradient in the orthonormal basis.
-__device__ inline void patch_to_bg_b(const PatchDev &p, const PoseDev &ps, double r, const SphBasis &B,
-                                     const double y[3], const double in[4], double &pit, double G[3]) {
+// frame of p at patch-frame point y (frame B for curvilinear patches), return
+// Pi_t^B and the background gradient G = d phi/dX: G = R gy with gy the
+// gradient along the patch axes (sum_a Pi_a / h_a e_a on a curvilinear patch),
+// and Pi_t^B = Pi_t - V.G with V the frame velocity at y.
+__device__ inline void patch_to_bg_b(const PatchDev &p, const PoseDev &ps, const Basis &B, const double y[3],
+                                     const double in[4], double &pit, double G[3]) {
   double gy[3];
   if (p.coord == CART) {
     gy[0] = in[1]; gy[1] = in[2]; gy[2] = in[3];
   } else {
-    double fr = in[1], ft = in[2] / r, fp = in[3] / (r * B.st);
-    for (int a = 0; a < 3; a++) gy[a] = fr * B.er[a] + ft * B.et[a] + fp * B.ep[a];
+    const double f0 = in[1] / B.h[0], f1 = in[2] / B.h[1], f2 = in[3] / B.h[2];
+    for (int a = 0; a < 3; a++) gy[a] = f0 * B.e[0][a] + f1 * B.e[1][a] + f2 * B.e[2][a];
   }
   for (int a = 0; a < 3; a++) G[a] = ps.R[3 * a] * gy[0] + ps.R[3 * a + 1] * gy[1] + ps.R[3 * a + 2] * gy[2];
   double V[3];
   frame_velocity(ps, y, V);
   pit = in[0] - (V[0] * G[0] + V[1] * G[1] + V[2] * G[2]);
 }
-// patch-frame Cartesian point of numerical x' (basis B at x' for spherical patches)
-__device__ inline void patch_point(const PatchDev &p, const double xp[3], const SphBasis &B, double y[3]) {
+__device__ inline void patch_to_bg(const PatchDev &p, const PoseDev &ps, const double xp[3], const double in[4],
+                                   double &pit, double G[3]) {
+  Basis B;
+  double y[3];
   if (p.coord == CART) {
     y[0] = xp[0]; y[1] = xp[1]; y[2] = xp[2];
   } else {
-    for (int a = 0; a < 3; a++) y[a] = xp[0] * B.er[a];
+    curv_point(p, xp, B, y);
   }
-}
-__device__ inline void patch_to_bg(const PatchDev &p, const PoseDev &ps, const double xp[3], const double in[4],
-                                   double &pit, double G[3]) {
-  SphBasis B;
-  if (p.coord != CART) sph_basis(xp[1], xp[2], B);
-  double y[3];
-  patch_point(p, xp, B, y);
-  patch_to_bg_b(p, ps, xp[0], B, y, in, pit, G);
+  patch_to_bg_b(p, ps, B, y, in, pit, G);
 }
 // The same at the point of p that maps to background X (x' = its inverse map):
-// the point y and the spherical basis come from the patch-frame Cartesian offset.
+// the point y comes from the patch-frame Cartesian offset, and the angles'
+// sines and cosines are ratios of y (no trigonometry).
 __device__ inline void patch_to_bg_at(const PatchDev &p, const PoseDev &ps, const double X[3], const double xp[3],
                                       const double in[4], double &pit, double G[3]) {
-  SphBasis B;
   const double d[3] = {X[0] - ps.c[0], X[1] - ps.c[1], X[2] - ps.c[2]};
   double y[3];
   for (int b = 0; b < 3; b++) y[b] = ps.R[b] * d[0] + ps.R[3 + b] * d[1] + ps.R[6 + b] * d[2];
-  if (p.coord != CART) sph_basis_cart(y, xp[0], B);
-  patch_to_bg_b(p, ps, xp[0], B, y, in, pit, G);
+  double gy[3];
+  if (p.coord == CART) {
+    gy[0] = in[1]; gy[1] = in[2]; gy[2] = in[3];
+  } else {
+    const double rho = sqrt(y[0] * y[0] + y[1] * y[1]);
+    double cp = 1.0, sp = 0.0;
+    if (rho > 0.0) {
+      cp = y[0] / rho;
+      sp = y[1] / rho;
+    }
+    if (p.coord == SPH) {
+      // gradient r-part + theta-part in the (rho, z) plane, phi-part along e_phi
+      const double ir = 1.0 / xp[0], st = rho * ir, ct = y[2] * ir;
+      const double ft = in[2] * ir, fp = rho > 0.0 ? in[3] / rho : 0.0;
+      const double fh = in[1] * st + ft * ct;  // horizontal (e_rho) component
+      gy[0] = fh * cp - fp * sp;
+      gy[1] = fh * sp + fp * cp;
+      gy[2] = in[1] * ct - ft * st;
+    } else {
+      const double fp = in[2] / xp[0];
+      gy[0] = in[1] * cp - fp * sp;
+      gy[1] = in[1] * sp + fp * cp;
+      gy[2] = in[3];
+    }
+  }
+  for (int a = 0; a < 3; a++) G[a] = ps.R[3 * a] * gy[0] + ps.R[3 * a + 1] * gy[1] + ps.R[3 * a + 2] * gy[2];
+  double V[3];
+  frame_velocity(ps, y, V);
+  pit = in[0] - (V[0] * G[0] + V[1] * G[1] + V[2] * G[2]);
 }
 
-// Background one-form (Pi_t^B, G) -> numerical frame of p at x' (point y).
-__device__ inline void bg_to_patch_b(const PatchDev &p, const PoseDev &ps, double r, const SphBasis &B,
-                                     const double y[3], double pit, const double G[3], double out[4]) {
+// Background one-form (Pi_t^B, G) -> numerical frame of p at point y:
+// Pi_a = h_a e_a . gy on a curvilinear patch.
+__device__ inline void bg_to_patch_b(const PatchDev &p, const PoseDev &ps, const Basis &B, const double y[3],
+                                     double pit, const double G[3], double out[4]) {
   double gy[3];
   for (int b = 0; b < 3; b++) gy[b] = ps.R[b] * G[0] + ps.R[3 + b] * G[1] + ps.R[6 + b] * G[2];
   double V[3];
@@ -280,43 +315,56 @@ __device__ inline void bg_to_patch_b(const PatchDev &p, const PoseDev &ps, doubl
   if (p.coord == CART) {
     out[1] = gy[0]; out[2] = gy[1]; out[3] = gy[2];
   } else {
-    out[1] = B.er[0] * gy[0] + B.er[1] * gy[1] + B.er[2] * gy[2];
-    out[2] = r * (B.et[0] * gy[0] + B.et[1] * gy[1] + B.et[2] * gy[2]);
-    out[3] = r * B.st * (B.ep[0] * gy[0] + B.ep[1] * gy[1]);
+    for (int a = 0; a < 3; a++) out[1 + a] = B.h[a] * (B.e[a][0] * gy[0] + B.e[a][1] * gy[1] + B.e[a][2] * gy[2]);
   }
 }
 __device__ inline void bg_to_patch(const PatchDev &p, const PoseDev &ps, const double xp[3], double pit,
                                    const double G[3], double out[4]) {
-  SphBasis B;
-  if (p.coord != CART) sph_basis(xp[1], xp[2], B);
+  Basis B;
   double y[3];
-  patch_point(p, xp, B, y);
-  bg_to_patch_b(p, ps, xp[0], B, y, pit, G, out);
+  if (p.coord == CART) {
+    y[0] = xp[0]; y[1] = xp[1]; y[2] = xp[2];
+  } else {
+    curv_point(p, xp, B, y);
+  }
+  bg_to_patch_b(p, ps, B, y, pit, G, out);
 }
 
-// Grid point c (numerical indices, ghosts included) of p: its background
-// position, and a background one-form carried to p there (table basis).
-__device__ inline void grid_point(const PatchDev &p, const int c[3], SphBasis &B, double y[3]) {
+// Grid point c (numerical indices, ghosts included) of p: its patch-frame
+// point and frame (angle tables), its background position, and a background
+// one-form carried to p there.
+__device__ inline void grid_point(const PatchDev &p, const int c[3], Basis &B, double y[3]) {
   if (p.coord == CART) {
     for (int a = 0; a < 3; a++) y[a] = xnum(p, a, c[a]);
-  } else {
-    sph_basis_grid(p, c[1], c[2], B);
+  } else if (p.coord == SPH) {
+    const int t1 = p.n[1] + 2 * PW_NG, t2 = p.n[2] + 2 * PW_NG;
+    double st, ct, sp, cp;
+    trig_axis(p, 0, t1, c[1], st, ct);
+    trig_axis(p, 2 * t1, t2, c[2], sp, cp);
     const double r = xnum(p, 0, c[0]);
-    for (int a = 0; a < 3; a++) y[a] = r * B.er[a];
+    sph_frame(r, st, ct, sp, cp, B);
+    for (int a = 0; a < 3; a++) y[a] = r * B.e[0][a];
+  } else {
+    const int t1 = p.n[1] + 2 * PW_NG;
+    double sp, cp;
+    trig_axis(p, 0, t1, c[1], sp, cp);
+    const double r = xnum(p, 0, c[0]);
+    cyl_frame(r, sp, cp, B);
+    y[0] = r * cp; y[1] = r * sp; y[2] = xnum(p, 2, c[2]);
   }
 }
 __device__ inline void fwd_map_grid(const PatchDev &p, const PoseDev &ps, const int c[3], double X[3]) {
   double y[3];
-  SphBasis B;
+  Basis B;
   grid_point(p, c, B, y);
   for (int a = 0; a < 3; a++) X[a] = ps.c[a] + ps.R[3 * a] * y[0] + ps.R[3 * a + 1] * y[1] + ps.R[3 * a + 2] * y[2];
 }
 __device__ inline void bg_to_patch_grid(const PatchDev &p, const PoseDev &ps, const int c[3], double pit,
                                         const double G[3], double out[4]) {
-  SphBasis B;
+  Basis B;
   double y[3];
   grid_point(p, c, B, y);
-  bg_to_patch_b(p, ps, xnum(p, 0, c[0]), B, y, pit, G, out);
+  bg_to_patch_b(p, ps, B, y, pit, G, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -150,7 +150,8 @@ struct StageArgs {
   int global;  // the tiles are those of the global patch (live-cell test applies)
   const uint8_t *gflag;
   int sv, stage, mixed;
-  int inc;  // mixed path: FP32 increments in the accumulator
+  int inc;   // mixed path: FP32 increments in the accumulator
+  int form;  // 0: the paper's Pi_t equation, 1: its first-order form
   double dt, v2, eps;
 };
 
@@ -163,6 +164,13 @@ void launch_ghosts(hipStream_t s, const GhostArgs &a);
 void launch_post_flags(hipStream_t s, const PostFlagsArgs &a);
 void launch_l2g_order(hipStream_t s, const L2GOrderArgs &a);
 void launch_stage(hipStream_t s, const StageArgs &a);
+// Sommerfeld outer boundary: RK stage of the global patch's outer ghost cells
+void launch_radiative(hipStream_t s, const PatchDev *P, const GhostRec *list, int count, int sv, int stage,
+                      int mixed, int inc, double dt, double v);
+// lower-priority fill (exact solution / nearest interior cell) of the listed
+// cells of u (fp64 = 1) or of its FP32 copy (fp64 = 0) at time tdev[0]
+void launch_fill_list(hipStream_t s, const PatchDev *P, const PoseDev *pose, const GhostRec *list, int count, int sv,
+                      int fp64, const ExactDev *ex, double v, const double *tdev);
 void launch_trig_table(hipStream_t s, int n1, int n2, double lo1, double dx1, double lo2, double dx2, double *tab);
 void launch_fill_f64(hipStream_t s, double *p, long long n, double v);
 void launch_fill_f32(hipStream_t s, float *p, long long n, float v);

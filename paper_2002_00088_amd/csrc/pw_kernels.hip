@@ -462,9 +462,8 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__r
   double wx[Pts], wy[Pts], wz[Pts];
   double xd[3] = {0, 0, 0};
   if (active && has_donor) {
-    double X[3];
-    fwd_map_grid(r, pose[B.patch], c, X);
-    inv_map(G0, pose[0], X, xd);
+    // background position; the global patch's numerical coordinates are X itself
+    fwd_map_grid(r, pose[B.patch], c, xd);
     double q[3];
     bool fin = true;
     for (int a = 0; a < 3; a++) {
@@ -599,9 +598,11 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__r
   }
   double out[5];
   {
-    double in4[4] = {(double)acc[1], (double)acc[2], (double)acc[3], (double)acc[4]}, G[3], pit, o4[4];
-    patch_to_bg(G0, pose[0], xd, in4, pit, G);
-    bg_to_patch_grid(r, pose[B.patch], c, pit, G, o4);
+    // the global patch's numerical frame is the background frame (Cartesian,
+    // static, unrotated): its one-form needs no transformation
+    const double G[3] = {(double)acc[2], (double)acc[3], (double)acc[4]};
+    double o4[4];
+    bg_to_patch_grid(r, pose[B.patch], c, (double)acc[1], G, o4);
     out[0] = (double)acc[0];
     for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
   }
@@ -919,12 +920,13 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
         for (int w2 = 0; w2 < L2G_WAVES - 1; w2++) acc[f] += red[w2][f][lane];
       if (valid) {
         const PatchDev &D = P[d];
-        double in4[4] = {(double)acc[1], (double)acc[2], (double)acc[3], (double)acc[4]}, G[3], pit, o4[4], out[5];
+        double in4[4] = {(double)acc[1], (double)acc[2], (double)acc[3], (double)acc[4]}, G[3], pit, out[5];
         const double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
         patch_to_bg_at(D, pose[d], X, xd, in4, pit, G);
-        bg_to_patch(G0, pose[0], X, pit, G, o4);
+        // the global patch's numerical frame is the background frame
         out[0] = (double)acc[0];
-        for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
+        out[1] = pit;
+        for (int m = 0; m < 3; m++) out[2 + m] = G[m];
         const long long dst = cell_index(G0, i, j, k);
         for (int f = 0; f < 5; f++) TG[f * G0.fstride + dst] = (TB)out[f];
       } else {
@@ -1068,10 +1070,15 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
 //              - 2 sum_{i<j} beta_i beta_j D_ij phi
 // Cartesian: h = 1, m = a.  Spherical: h = (1, 1/r^2, 1/(r sin th)^2) and
 //   m = K a - Q(b) + v^2 (2/r, cot th / r^2, 0), Q the coordinate acceleration of
-//   straight-line motion in spherical coordinates.
+//   straight-line motion in spherical coordinates.  Cylindrical (r, phi, z):
+//   h = (1, 1/r^2, 1), Q(b) = (b_phi^2 / r, -2 b_r b_phi / r^2, 0) with b_r, b_phi
+//   the components along e_r, e_phi, and m = K a - Q(b) + v^2 (1/r, 0, 0).
 // A patch rotating with angular velocity w (wp = R^T w) has, at y = M(x'), the
 // position-dependent b + wp x y in place of b and a - 2 wp x b - wp x (wp x y)
 // in place of a (frame_terms).
+// FORM = 1 is the first-order reduction of the same equation: the evolved
+// Psi_i = Pi_i stands for D_i phi and D_i Psi_j for D_ij phi (the off-diagonal
+// pairs as (D_i Psi_j + D_j Psi_i) / 2), so no second differences of phi enter.
 //
 // Tiling (2.5-D): a workgroup owns a 32 x 8 column tile and marches through the
 // tile's planes in z (a tuning parameter).  Each thread keeps its column's
@@ -1080,7 +1087,7 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
 // The centre plane of the 5 fields and the phi plane one below the newest are
 // staged in LDS with a 3-cell x-y halo for the x-y stencils.
 // ---------------------------------------------------------------------------
-template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD, bool GLOB, int AM>
+template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD, bool GLOB, int AM, int FORM>
 __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose_slot, const TileRec *tiles,
                                                int ntiles, int chunk, const uint8_t *gflag, int sv, double dt,
                                                double v2, double eps) {
@@ -1182,7 +1189,7 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
     const uint32_t zo = (uint32_t)(zn + PW_NG) * sz;  // cell_index already holds the +NG of z = 0
 #pragma unroll
     for (int f = 0; f < 5; f++) pown[f] = inpad ? (TC)gld(in, f * fs + col + zo - PW_NG * sz) : (TC)0;
-    if (itp >= 2) {
+    if (FORM == 0 && itp >= 2) {
       const uint32_t za = zo - (PW_NG + 1) * sz;
 #pragma unroll
       for (int m = 0; m < NH; m++) phA[m] = hval[m] ? (TC)gld(in, hoff[m] + za) : (TC)0;
@@ -1199,7 +1206,7 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
   // values of planes z0-3 .. z0+2 go to the z-window, and D_x phi, D_y phi at
   // planes z0-2 .. z0+1 are formed from phi planes staged with their halo rings
   // (in the second centre-plane buffer, first written two iterations later).
-  {
+  if (FORM == 0) {
     TC wh[4][NH];
 #pragma unroll
     for (int w = 0; w < 6; w++) {
@@ -1232,6 +1239,15 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
             ((A_[own - 2 * ST_PX] - A_[own + 2 * ST_PX]) + (TC)8 * (A_[own + ST_PX] - A_[own - ST_PX])) * i12dx[1];
       }
     }
+  } else {
+    // first-order form: no D_x phi, D_y phi window; the z-window and the prefetch only
+#pragma unroll
+    for (int w = 0; w < 6; w++) {
+      const uint32_t zo = (uint32_t)(z0 - 3 + w + PW_NG) * sz - PW_NG * sz;
+#pragma unroll
+      for (int f = 0; f < 5; f++) q[f][w + 1] = inpad ? (TC)gld(in, f * fs + col + zo) : (TC)0;
+    }
+    prefetch(6);
   }
   for (int it = 6; it < nz + 6; it++) {
     const int zn = z0 - 3 + it;
@@ -1242,7 +1258,7 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
       for (int d = 0; d < 6; d++) q[f][d] = q[f][d + 1];
       q[f][6] = pown[f];
     }
-    const bool do_d = it >= 2;  // phi plane zd = zn - 1 for D_x phi, D_y phi
+    const bool do_d = FORM == 0 && it >= 2;  // phi plane zd = zn - 1 for D_x phi, D_y phi
     const bool do_c = it >= 6;  // centre plane zc = zn - 3
     TC *A_ = Ad[buf];
     if (do_d) {
@@ -1321,22 +1337,24 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
           bb_[0] = (TC)(2.0 * bv[0] * bv[1]);
           bb_[1] = (TC)(2.0 * bv[0] * bv[2]);
           bb_[2] = (TC)(2.0 * bv[1] * bv[2]);
-        } else {
-          double r = p.lo[0] + (i + 0.5) * p.dx[0];
-          SphBasis Bs;
-          sph_basis_grid(p, j, k, Bs);
+        } else if (COORD == SPH) {
+          const double r = p.lo[0] + (i + 0.5) * p.dx[0];
+          double st, ct, sp, cp;
+          trig_axis(p, 0, p.n[1] + 2 * PW_NG, j, st, ct);
+          trig_axis(p, 2 * (p.n[1] + 2 * PW_NG), p.n[2] + 2 * PW_NG, k, sp, cp);
+          const double er[3] = {st * cp, st * sp, ct}, et[3] = {ct * cp, ct * sp, -st}, ep[2] = {-sp, cp};
           double bv[3] = {ps.b[0], ps.b[1], ps.b[2]}, av[3] = {ps.a[0], ps.a[1], ps.a[2]};
           if (spin) {
-            const double y[3] = {r * Bs.er[0], r * Bs.er[1], r * Bs.er[2]};
+            const double y[3] = {r * er[0], r * er[1], r * er[2]};
             frame_terms(ps, y, bv, av);
           }
-          double ir = 1.0 / r, irs = ir / Bs.st, cot = Bs.ct / Bs.st;
-          double br = Bs.er[0] * bv[0] + Bs.er[1] * bv[1] + Bs.er[2] * bv[2];
-          double bt = Bs.et[0] * bv[0] + Bs.et[1] * bv[1] + Bs.et[2] * bv[2];
-          double bp = Bs.ep[0] * bv[0] + Bs.ep[1] * bv[1];
-          double ar = Bs.er[0] * av[0] + Bs.er[1] * av[1] + Bs.er[2] * av[2];
-          double at = Bs.et[0] * av[0] + Bs.et[1] * av[1] + Bs.et[2] * av[2];
-          double ap = Bs.ep[0] * av[0] + Bs.ep[1] * av[1];
+          double ir = 1.0 / r, irs = ir / st, cot = ct / st;
+          double br = er[0] * bv[0] + er[1] * bv[1] + er[2] * bv[2];
+          double bt = et[0] * bv[0] + et[1] * bv[1] + et[2] * bv[2];
+          double bp = ep[0] * bv[0] + ep[1] * bv[1];
+          double ar = er[0] * av[0] + er[1] * av[1] + er[2] * av[2];
+          double at = et[0] * av[0] + et[1] * av[1] + et[2] * av[2];
+          double ap = ep[0] * av[0] + ep[1] * av[1];
           double beta[3] = {br, bt * ir, bp * irs};
           double Q0 = (bt * bt + bp * bp) * ir;
           double Q1 = (-2.0 * br * bt + bp * bp * cot) * ir * ir;
@@ -1352,10 +1370,50 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
           bb_[0] = (TC)(2.0 * beta[0] * beta[1]);
           bb_[1] = (TC)(2.0 * beta[0] * beta[2]);
           bb_[2] = (TC)(2.0 * beta[1] * beta[2]);
+        } else {
+          // cylindrical x' = (r, phi, z): phi along the numerical y axis
+          const double r = p.lo[0] + (i + 0.5) * p.dx[0];
+          double sp, cp;
+          trig_axis(p, 0, p.n[1] + 2 * PW_NG, j, sp, cp);
+          double bv[3] = {ps.b[0], ps.b[1], ps.b[2]}, av[3] = {ps.a[0], ps.a[1], ps.a[2]};
+          if (spin) {
+            const double y[3] = {r * cp, r * sp, p.lo[2] + (k + 0.5) * p.dx[2]};
+            frame_terms(ps, y, bv, av);
+          }
+          const double ir = 1.0 / r;
+          const double br = cp * bv[0] + sp * bv[1], bp = cp * bv[1] - sp * bv[0];
+          const double ar = cp * av[0] + sp * av[1], ap = cp * av[1] - sp * av[0];
+          const double beta[3] = {br, bp * ir, bv[2]};
+          const double Q0 = bp * bp * ir;
+          const double Q1 = -2.0 * br * bp * ir * ir;
+          const double mm[3] = {ar - Q0 + v2 * ir, ap * ir - Q1, av[2]};
+          const double hh[3] = {1.0, ir * ir, 1.0};
+#pragma unroll
+          for (int a = 0; a < 3; a++) {
+            m_[a] = (TC)mm[a];
+            b2_[a] = (TC)(2.0 * beta[a]);
+            h_[a] = (TC)(v2 * hh[a] - beta[a] * beta[a]);
+          }
+          bb_[0] = (TC)(2.0 * beta[0] * beta[1]);
+          bb_[1] = (TC)(2.0 * beta[0] * beta[2]);
+          bb_[2] = (TC)(2.0 * beta[1] * beta[2]);
         }
         const TC(*Bf)[ST_PW] = Bc[buf];
+        // first derivatives of LDS plane F along x, y and of z-window row f along z
+        auto ddx = [&](const TC *F) { return ((F[own - 2] - F[own + 2]) + (TC)8 * (F[own + 1] - F[own - 1])) * i12dx[0]; };
+        auto ddy = [&](const TC *F) {
+          return ((F[own - 2 * ST_PX] - F[own + 2 * ST_PX]) + (TC)8 * (F[own + ST_PX] - F[own - ST_PX])) * i12dx[1];
+        };
+        auto ddz = [&](int f) { return ((q[f][1] - q[f][5]) + (TC)8 * (q[f][4] - q[f][2])) * i12dx[2]; };
         TC dphi[3], d2phi[3], dpi[3], kof[5];
-        {
+        if (FORM == 1) {
+          // first-order form: Psi_a for D_a phi and D_a Psi_a for D_aa phi
+#pragma unroll
+          for (int a = 0; a < 3; a++) dphi[a] = q[2 + a][3];
+          d2phi[0] = ddx(Bf[2]);
+          d2phi[1] = ddy(Bf[3]);
+          d2phi[2] = ddz(4);
+        } else {
           const TC *F = Bf[0];
           TC u0 = F[own];
           TC xm1 = F[own - 1], xp1 = F[own + 1], xm2 = F[own - 2], xp2 = F[own + 2];
@@ -1388,7 +1446,13 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
         TC rhs_pi = (TC)0;
 #pragma unroll
         for (int a = 0; a < 3; a++) rhs_pi += m_[a] * dphi[a] + b2_[a] * dpi[a] + h_[a] * d2phi[a];
-        if (moving) {
+        if (moving && FORM == 1) {
+          // g^{ij} D_i Psi_j: the off-diagonal pairs enter as (D_i Psi_j + D_j Psi_i) / 2
+          const TC sxy = ddx(Bf[3]) + ddy(Bf[2]);
+          const TC sxz = ddx(Bf[4]) + ddz(2);
+          const TC syz = ddy(Bf[4]) + ddz(3);
+          rhs_pi -= (TC)0.5 * (bb_[0] * sxy + bb_[1] * sxz + bb_[2] * syz);
+        } else if (moving) {
           const TC *F = Bf[0];
           TC sxy = (TC)0;
 #pragma unroll
@@ -1469,6 +1533,99 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
 }
 
 // ---------------------------------------------------------------------------
+// Sommerfeld outer boundary (variant of the analytic outer boundary): every
+// outer ghost cell of the global patch is evolved, with the same RK4 stage
+// update as an interior cell, by the radiative condition for waves leaving the
+// origin, d_t u = -v (X.grad u + u) / r on each field.  Derivatives: 4th-order
+// centred along axes where the cell is interior, 2nd-order one-sided (inward)
+// along axes where it is a ghost.  One thread per cell of the list.
+// ---------------------------------------------------------------------------
+template <typename TIN, typename TOUT, int STAGE, int AM>
+__global__ void k_radiative(const PatchDev *__restrict__ P, const GhostRec *list, int count, int sv, double dt,
+                            double v) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const PatchDev &p = P[0];
+  if (!(p.sv_mask & (1u << sv))) return;
+  int c[3];
+  unpack_ijk(list[q].cell, c[0], c[1], c[2]);
+  const TIN *in = (const TIN *)(STAGE == 0 ? (sizeof(TIN) == 8 ? (const void *)p.u[sv] : (const void *)p.us[sv])
+                                           : (STAGE == 2 ? p.vb[sv] : p.va[sv]));
+  TOUT *vout = (TOUT *)(STAGE == 1 ? p.vb[sv] : p.va[sv]);
+  double *U = p.u[sv];
+  double *Acc = p.acc[sv];
+  float *AccF = (float *)p.acc[sv];
+  float *Us = p.us[sv];
+  constexpr bool MIX = sizeof(TOUT) == 4;
+  constexpr bool INC = MIX && AM == 1;
+  const double X[3] = {xnum(p, 0, c[0]), xnum(p, 1, c[1]), xnum(p, 2, c[2])};
+  const double r = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+  const long long x0 = cell_index(p, c[0], c[1], c[2]);
+  const long long st[3] = {1, p.pitch, p.slab};
+  double K[5], u0[5];
+  for (int f = 0; f < 5; f++) {
+    const TIN *F = in + f * p.fstride + x0;
+    u0[f] = (double)F[0];
+    double xgrad = 0.0;
+    for (int a = 0; a < 3; a++) {
+      const long long e = st[a];
+      double d;
+      if (c[a] < 0)
+        d = (-3.0 * (double)F[0] + 4.0 * (double)F[e] - (double)F[2 * e]) / (2.0 * p.dx[a]);
+      else if (c[a] >= p.n[a])
+        d = (3.0 * (double)F[0] - 4.0 * (double)F[-e] + (double)F[-2 * e]) / (2.0 * p.dx[a]);
+      else
+        d = ((double)F[-2 * e] - 8.0 * (double)F[-e] + 8.0 * (double)F[e] - (double)F[2 * e]) / (12.0 * p.dx[a]);
+      xgrad += X[a] * d;
+    }
+    K[f] = -v * (xgrad + u0[f]) / r;
+  }
+  // the stage update of k_stage (classic RK4, Table rk4) for this cell
+  const double bdt = STAGE == 0 ? dt / 6.0 : (STAGE == 3 ? dt / 6.0 : dt / 3.0);
+  const double adt = STAGE == 2 ? dt : dt / 2.0;
+  const float bdtf = (float)bdt, adtf = (float)adt;
+  for (int f = 0; f < 5; f++) {
+    const long long x = f * p.fstride + x0;
+    if (INC) {
+      const float kf = (float)K[f];
+      if (STAGE == 0) {
+        AccF[x] = bdtf * kf;
+        vout[x] = (TOUT)((float)u0[f] + adtf * kf);
+      } else if (STAGE == 3) {
+        const double un = U[x] + ((double)AccF[x] + bdt * (double)kf);
+        U[x] = un;
+        Us[x] = (float)un;
+      } else {
+        AccF[x] = AccF[x] + bdtf * kf;
+        vout[x] = (TOUT)(Us[x] + adtf * kf);
+      }
+    } else if (MIX) {
+      if (STAGE == 0) {
+        Acc[x] = U[x] + bdt * K[f];
+        vout[x] = (TOUT)(U[x] + adt * K[f]);
+      } else if (STAGE == 3) {
+        const double un = Acc[x] + bdt * K[f];
+        U[x] = un;
+        Us[x] = (float)un;
+      } else {
+        Acc[x] = Acc[x] + bdt * K[f];
+        vout[x] = (TOUT)(Us[x] + adtf * (float)K[f]);
+      }
+    } else {
+      if (STAGE == 0) {
+        Acc[x] = U[x] + bdt * K[f];
+        vout[x] = (TOUT)(U[x] + adt * K[f]);
+      } else if (STAGE == 3) {
+        U[x] = Acc[x] + bdt * K[f];
+      } else {
+        Acc[x] = Acc[x] + bdt * K[f];
+        vout[x] = (TOUT)(U[x] + adt * K[f]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Utilities: fills, interior pack/unpack, exact initial data, diagnostics
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1477,7 +1634,8 @@ __global__ void k_fill_value(T *ptr, long long n, T val) {
   for (; q < n; q += (long long)gridDim.x * blockDim.x) ptr[q] = val;
 }
 
-// sin and cos of the grid angles of a spherical patch (see PatchDev::trig).
+// sin and cos of the grid angles of a curvilinear patch (see PatchDev::trig;
+// a cylindrical patch uses the axis-1 entries only).
 __global__ void k_trig_table(int n1, int n2, double lo1, double dx1, double lo2, double dx2, double *tab) {
   const int t1 = n1 + 2 * PW_NG, t2 = n2 + 2 * PW_NG;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1564,7 +1722,7 @@ __global__ void k_diag(const PatchDev *__restrict__ P, const PoseDev *__restrict
         acc[15 + f] += d * d;
       }
     }
-    double sg = p.coord == CART ? 1.0 : xp[0] * xp[0] * fabs(sin(xp[1]));
+    double sg = p.coord == CART ? 1.0 : p.coord == SPH ? xp[0] * xp[0] * fabs(sin(xp[1])) : xp[0];
     if (has) acc[20] += fabs(phi - e[0]) / fabs(e[0]) * sg * cellvol;
     acc[21] += 1.0;
     acc[22] += sg * cellvol;
@@ -1704,46 +1862,92 @@ void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
   }
 }
 
-void launch_stage(hipStream_t s, const StageArgs &a) {
-  if (a.ntiles <= 0) return;
+// One stage launch over tiles of one topology (global patch or local patches).
+template <typename TIN, typename TOUT, typename TC, int ST, int AM, int FORM>
+static void launch_stage_t(hipStream_t s, const StageArgs &a) {
   const int chunk = (a.ntiles + 7) / 8;
-  dim3 bs(a.global ? StageTile<true>::THREADS : StageTile<false>::THREADS);
-  dim3 g(8 * chunk);
-#define PW_STAGE(TIN, TOUT, TC, ST, AM)                                                                      \
-  do {                                                                                                        \
-    if (a.coord == CART && a.global)                                                                          \
-      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, true, AM>), g, bs, 0, s, a.P, a.pose, a.tiles,     \
-                         a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);                                 \
-    else if (a.coord == CART)                                                                                 \
-      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, false, AM>), g, bs, 0, s, a.P, a.pose, a.tiles,    \
-                         a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);                                 \
-    else                                                                                                      \
-      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, false, AM>), g, bs, 0, s, a.P, a.pose, a.tiles,     \
-                         a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);                                 \
-  } while (0)
+  const dim3 bs(a.global ? StageTile<true>::THREADS : StageTile<false>::THREADS);
+  const dim3 g(8 * chunk);
+  if (a.coord == CART && a.global)
+    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, true, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+  else if (a.coord == CART)
+    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, false, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+  else if (a.coord == SPH)
+    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, false, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+  else
+    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CYL, false, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+}
+
+template <int FORM>
+static void launch_stage_f(hipStream_t s, const StageArgs &a) {
   if (!a.mixed) {
     switch (a.stage) {
-      case 0: PW_STAGE(double, double, double, 0, 0); break;
-      case 1: PW_STAGE(double, double, double, 1, 0); break;
-      case 2: PW_STAGE(double, double, double, 2, 0); break;
-      default: PW_STAGE(double, double, double, 3, 0); break;
+      case 0: launch_stage_t<double, double, double, 0, 0, FORM>(s, a); break;
+      case 1: launch_stage_t<double, double, double, 1, 0, FORM>(s, a); break;
+      case 2: launch_stage_t<double, double, double, 2, 0, FORM>(s, a); break;
+      default: launch_stage_t<double, double, double, 3, 0, FORM>(s, a); break;
     }
   } else if (!a.inc) {
     switch (a.stage) {
-      case 0: PW_STAGE(float, float, float, 0, 0); break;
-      case 1: PW_STAGE(float, float, float, 1, 0); break;
-      case 2: PW_STAGE(float, float, float, 2, 0); break;
-      default: PW_STAGE(float, float, float, 3, 0); break;
+      case 0: launch_stage_t<float, float, float, 0, 0, FORM>(s, a); break;
+      case 1: launch_stage_t<float, float, float, 1, 0, FORM>(s, a); break;
+      case 2: launch_stage_t<float, float, float, 2, 0, FORM>(s, a); break;
+      default: launch_stage_t<float, float, float, 3, 0, FORM>(s, a); break;
     }
   } else {
     switch (a.stage) {
-      case 0: PW_STAGE(float, float, float, 0, 1); break;
-      case 1: PW_STAGE(float, float, float, 1, 1); break;
-      case 2: PW_STAGE(float, float, float, 2, 1); break;
-      default: PW_STAGE(float, float, float, 3, 1); break;
+      case 0: launch_stage_t<float, float, float, 0, 1, FORM>(s, a); break;
+      case 1: launch_stage_t<float, float, float, 1, 1, FORM>(s, a); break;
+      case 2: launch_stage_t<float, float, float, 2, 1, FORM>(s, a); break;
+      default: launch_stage_t<float, float, float, 3, 1, FORM>(s, a); break;
     }
   }
-#undef PW_STAGE
+}
+
+void launch_stage(hipStream_t s, const StageArgs &a) {
+  if (a.ntiles <= 0) return;
+  if (a.form == 1)
+    launch_stage_f<1>(s, a);
+  else
+    launch_stage_f<0>(s, a);
+}
+
+template <typename TIN, typename TOUT, int AM>
+static void launch_radiative_t(hipStream_t s, const PatchDev *P, const GhostRec *list, int count, int sv, int stage,
+                               double dt, double v) {
+  const dim3 g(nblk(count, 256)), b(256);
+  switch (stage) {
+    case 0: hipLaunchKernelGGL((k_radiative<TIN, TOUT, 0, AM>), g, b, 0, s, P, list, count, sv, dt, v); break;
+    case 1: hipLaunchKernelGGL((k_radiative<TIN, TOUT, 1, AM>), g, b, 0, s, P, list, count, sv, dt, v); break;
+    case 2: hipLaunchKernelGGL((k_radiative<TIN, TOUT, 2, AM>), g, b, 0, s, P, list, count, sv, dt, v); break;
+    default: hipLaunchKernelGGL((k_radiative<TIN, TOUT, 3, AM>), g, b, 0, s, P, list, count, sv, dt, v); break;
+  }
+}
+
+void launch_radiative(hipStream_t s, const PatchDev *P, const GhostRec *list, int count, int sv, int stage,
+                      int mixed, int inc, double dt, double v) {
+  if (count <= 0) return;
+  if (!mixed)
+    launch_radiative_t<double, double, 0>(s, P, list, count, sv, stage, dt, v);
+  else if (!inc)
+    launch_radiative_t<float, float, 0>(s, P, list, count, sv, stage, dt, v);
+  else
+    launch_radiative_t<float, float, 1>(s, P, list, count, sv, stage, dt, v);
+}
+
+void launch_fill_list(hipStream_t s, const PatchDev *P, const PoseDev *pose, const GhostRec *list, int count, int sv,
+                      int fp64, const ExactDev *ex, double v, const double *tdev) {
+  if (count <= 0) return;
+  if (fp64)
+    hipLaunchKernelGGL(k_fill_lower<double>, dim3(nblk(count, 256)), dim3(256), 0, s, P, pose, list, count, sv, 0, ex,
+                       v, tdev, 0.0, 0.0);
+  else
+    hipLaunchKernelGGL(k_fill_lower<float>, dim3(nblk(count, 256)), dim3(256), 0, s, P, pose, list, count, sv, 0, ex,
+                       v, tdev, 0.0, 0.0);
 }
 
 void launch_trig_table(hipStream_t s, int n1, int n2, double lo1, double dx1, double lo2, double dx2, double *tab) {

@@ -24,6 +24,8 @@ LIB = os.path.join(HERE, "libpw.so")
 
 PW_FP64, PW_MIXED, PW_MIXED_INC = 0, 1, 2
 PW_CART, PW_SPH, PW_CYL = 0, 1, 2
+PW_FORM_PAPER, PW_FORM_FIRST_ORDER = 0, 1
+PW_BC_EXACT, PW_BC_SOMMERFELD = 0, 1
 PW_STATIC, PW_LINEAR, PW_CIRCLE = 0, 1, 2
 PW_FLAG_LIVE, PW_FLAG_EFFGHOST, PW_FLAG_DEACT = 0, 1, 2
 PW_SCHED_BATCHED, PW_SCHED_PER_PATCH = 0, 1
@@ -46,7 +48,8 @@ class Config(C.Structure):
     _fields_ = [("precision", C.c_int32), ("n_state_vectors", C.c_int32), ("wave_speed", C.c_double * 4),
                 ("interp_points", C.c_int32 * 4), ("buffer_width", C.c_int32), ("ko_eps", C.c_double),
                 ("schedule", C.c_int32), ("use_graph", C.c_int32), ("stream", C.c_void_p),
-                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", C.c_void_p)]
+                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", C.c_void_p), ("pi_form", C.c_int32),
+                ("outer_bc", C.c_int32)]
 
 
 class PatchDesc(C.Structure):
@@ -177,7 +180,7 @@ class Context:
     """One libpw context (one global patch plus local patches) on the current GPU."""
 
     def __init__(self, precision=PW_FP64, wave_speed=(1.0,), interp_points=None, buffer_width=4, ko_eps=0.005,
-                 schedule=PW_SCHED_BATCHED, use_graph=True, stream=None, torch_alloc=False):
+                 schedule=PW_SCHED_BATCHED, use_graph=True, stream=None, torch_alloc=False, pi_form=0, outer_bc=0):
         self.L = load()
         cfg = Config()
         cfg.precision = precision
@@ -191,6 +194,8 @@ class Context:
         cfg.ko_eps = ko_eps
         cfg.schedule = schedule
         cfg.use_graph = 1 if use_graph else 0
+        cfg.pi_form = pi_form
+        cfg.outer_bc = outer_bc
         cfg.stream = stream
         self._keep = []
         if torch_alloc:
@@ -333,7 +338,8 @@ def context_from_config(cfg, precision=PW_FP64, schedule=PW_SCHED_BATCHED, use_g
                         torch_alloc=False):
     ctx = Context(precision=precision, wave_speed=cfg["wave_speed"], interp_points=cfg["interp_points"],
                   buffer_width=cfg.get("buffer", 4), ko_eps=cfg.get("ko_eps", 0.005), schedule=schedule,
-                  use_graph=use_graph, stream=stream, torch_alloc=torch_alloc)
+                  use_graph=use_graph, stream=stream, torch_alloc=torch_alloc, pi_form=cfg.get("pi_form", 0),
+                  outer_bc=cfg.get("outer_bc", 0))
     for d in cfg["patches"]:
         ctx.create_patch(d)
     for sv, ex in enumerate(cfg.get("exact", [])):

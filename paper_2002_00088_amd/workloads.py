@@ -6,9 +6,9 @@ transforms): the GPU library and the CPU oracle each receive the same plain
 dictionaries and compute everything themselves.
 
 Patch dictionaries use the keys of the library's patch description:
-coord (0 Cartesian, 1 spherical), is_global, n (cells per numerical axis),
+coord (0 Cartesian, 1 spherical, 2 cylindrical), is_global, n (cells per numerical axis),
 lo/hi (numerical box faces), periodic, euler (ZYZ angles), motion
-(0 static, 1 linear, 2 circle), c0, vel, radius, speed, phase, sv_mask.
+(0 static, 1 linear, 2 circle), c0, vel, radius, speed, phase, sv_mask, spin.
 """
 import math
 
@@ -48,6 +48,8 @@ def spacing_min(p):
     if p["coord"] == CART:
         return min(dx)
     r_in = p["lo"][0]
+    if p["coord"] == CYL:
+        return min(dx[0], r_in * dx[1], dx[2])
     s_min = min(math.sin(p["lo"][1]), math.sin(p["hi"][1]))
     return min(dx[0], r_in * dx[1], r_in * s_min * dx[2])
 
@@ -97,6 +99,54 @@ def two_patch(seed=2, ng=128, nl=64, P=5, steps=200, motion=CIRCLE):
     cfg = dict(name="two_patch_%d_%d" % (ng, nl), wave_speed=[1.0], interp_points=[P], patches=[g, loc],
                exact=[ex], steps=steps)
     return _finish(cfg)
+
+
+def test_two(motion="fixed", ng=40, P=6, cfl=0.6, t_end=20.0):
+    """The paper's convergence test (Sec. 3.3, Test Two): global Cartesian cube
+    [-20, 20]^3 with ng^3 cells, a Cartesian local cube [-10, 10]^3 at twice the
+    resolution (2-to-1), plane wave phi = sin(2 pi (x - t)/20) + 2 (Eq.
+    wave_solution) with analytic outer ghosts, CFL 0.6 on the local spacing, up to
+    t = 20 (one wave period).  motion: "fixed" (centre (-1, -1, -1)), "rotating"
+    (centre at the origin, spin 0.01 about z, counter-clockwise) or "translating"
+    (from (-5, -5, 0) at velocity (0.1, 0.1, 0))."""
+    g = patch([ng] * 3, [-20.0] * 3, [20.0] * 3, is_global=1)
+    nl = ng
+    if motion == "fixed":
+        loc = patch([nl] * 3, [-10.0] * 3, [10.0] * 3, c0=(-1.0, -1.0, -1.0))
+    elif motion == "rotating":
+        loc = patch([nl] * 3, [-10.0] * 3, [10.0] * 3, spin=(0.0, 0.0, 0.01))
+    elif motion == "translating":
+        loc = patch([nl] * 3, [-10.0] * 3, [10.0] * 3, motion=LINEAR, c0=(-5.0, -5.0, 0.0), vel=(0.1, 0.1, 0.0))
+    else:
+        raise ValueError(motion)
+    ex = dict(kind="plane", A=1.0, B=2.0, kappa=[2 * math.pi / 20.0, 0.0, 0.0], psi=0.0)
+    dt0 = cfl * 20.0 / nl
+    steps = int(math.ceil(t_end / dt0 - 1e-9))
+    return dict(name="test_two_%s_%d" % (motion, ng), wave_speed=[1.0], interp_points=[P], patches=[g, loc],
+                exact=[ex], ko_eps=0.005, buffer=4, dt=t_end / steps, steps=steps)
+
+
+def three_topology(scale=1.0, steps=None, t_end=200.0, spin_sph=0.01, spin_cyl=-0.03, P=6):
+    """The paper's three-topology test (Sec. 3.4, Test Three) at `scale` times
+    its cell counts.  Global Cartesian 80 x 80 x 40 centred on the origin with
+    160 x 160 x 40 cells; a spherical patch at (-22, 0, 0), r in [5, 20],
+    theta in [pi/4, 3pi/4], phi periodic, 30 x 40 x 200 cells, spinning about
+    its z axis at spin_sph; a cylindrical patch at (22, 0, 0) with the same r and
+    phi ranges, z in [-10, 10], 30 x 200 x 20 cells, spinning at spin_cyl
+    (clockwise).  Plane wave phi = sin(2 pi (x - t) / 20) + 2 (Sec. 3); CFL 0.25
+    on the smallest spacing; `steps` defaults to reaching t_end."""
+    def nn(v):
+        return [max(4, int(round(x * scale))) for x in v]
+    g = patch(nn([160, 160, 40]), [-40, -40, -20], [40, 40, 20], is_global=1)
+    s = patch(nn([30, 40, 200]), [5.0, math.pi / 4, 0.0], [20.0, 3 * math.pi / 4, 2 * math.pi], coord=SPH,
+              periodic=(0, 0, 1), c0=(-22.0, 0.0, 0.0), spin=(0.0, 0.0, spin_sph))
+    c = patch(nn([30, 200, 20]), [5.0, 0.0, -10.0], [20.0, 2 * math.pi, 10.0], coord=CYL, periodic=(0, 1, 0),
+              c0=(22.0, 0.0, 0.0), spin=(0.0, 0.0, spin_cyl))
+    ex = dict(kind="plane", A=1.0, B=2.0, kappa=[2 * math.pi / 20.0, 0.0, 0.0], psi=0.0)
+    cfg = _finish(dict(name="three_topology_%g" % scale, wave_speed=[1.0], interp_points=[P], patches=[g, s, c],
+                       exact=[ex]))
+    cfg["steps"] = steps if steps is not None else int(math.ceil(t_end / cfg["dt"]))
+    return cfg
 
 
 def quadrupole_pulse(rng, d=1.0, w=0.6):

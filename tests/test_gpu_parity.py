@@ -188,6 +188,139 @@ def test_rotating_spherical_patch():
     say("  worst rel err", compare(cfg, o, g, TOL64))
 
 
+def _cyl_cfg(kind):
+    # a cylindrical shell (full 2 pi in phi, periodic) in a Cartesian global patch
+    g0 = W.patch([60] * 3, [-10] * 3, [10] * 3, is_global=1)
+    kw = dict(coord=W.CYL, periodic=(0, 1, 0))
+    if kind == "moving":
+        kw.update(euler=[0.4, 1.0, 2.2], motion=W.LINEAR, c0=(0.3, -0.2, 0.1), vel=(0.15, 0.1, -0.05))
+    elif kind == "rotating":
+        # the paper's cylindrical patch turns about its own z axis; here also tilted and circling
+        kw.update(euler=[0.3, 0.6, -0.5], motion=W.CIRCLE, radius=0.5, speed=0.1, phase=0.4,
+                  spin=[0.1, -0.05, -0.3])
+    c = W.patch([24, 48, 14], [1.0, 0.0, -2.5], [5.0, 2 * math.pi, 2.5], **kw)
+    ex = dict(kind="gauss", amp=[1.0, -0.6], centers=[[0.5, 0.2, -0.3], [-1.5, 1.0, 0.8]], widths=[0.9, 0.7])
+    return W._finish(dict(wave_speed=[1.0], interp_points=[6], patches=[g0, c], exact=[ex]))
+
+
+@pytest.mark.parametrize("kind", ["static", "moving", "rotating"])
+def test_cylindrical_local_patch(kind):
+    cfg = _cyl_cfg(kind)
+    say("cylindrical", kind)
+    o, g = run_pair(cfg, 2)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def test_cylindrical_patch_random_data_mixed_precision():
+    cfg = _cyl_cfg("rotating")
+    say("cylindrical, random data, FP64")
+    o, g = run_pair(cfg, 2, init="random", seed=17)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+    say("cylindrical, mixed")
+    o, g = run_pair(cfg, 2, precision=pw.PW_MIXED)
+    say("  worst rel err", compare(cfg, o, g, 2e-5))
+
+
+def test_three_topologies():
+    # one local patch of each topology, as in the paper's three-patch test: a
+    # spherical and a cylindrical patch spinning about their own z axes in
+    # opposite senses, and a Cartesian patch on a circle
+    g0 = W.patch([72, 72, 36], [-12, -12, -6], [12, 12, 6], is_global=1)
+    s = W.patch([20, 16, 40], [0.8, math.pi / 4, 0.0], [4.0, 3 * math.pi / 4, 2 * math.pi], coord=W.SPH,
+                periodic=(0, 0, 1), c0=(-6.0, 0.0, 0.0), spin=[0.0, 0.0, 0.05])
+    c = W.patch([20, 40, 14], [0.8, 0.0, -2.0], [4.0, 2 * math.pi, 2.0], coord=W.CYL, periodic=(0, 1, 0),
+                c0=(6.0, 0.0, 0.0), spin=[0.0, 0.0, -0.15])
+    q = W.patch([24] * 3, [-1.2] * 3, [1.2] * 3, euler=[0.3, 0.8, 1.9], motion=W.CIRCLE, radius=0.5, speed=0.1,
+                c0=(0.0, 6.5, 0.0))
+    ex = dict(kind="plane", A=1.0, B=2.0, kappa=[2 * math.pi / 10 * x for x in (1.0, 0.3, 0.2)], psi=0.4)
+    cfg = W._finish(dict(wave_speed=[1.0], interp_points=[6], patches=[g0, s, c, q], exact=[ex]))
+    say("three topologies")
+    o, g = run_pair(cfg, 3)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
+def test_three_topology_full_size_one_step():
+    # the paper's three-topology test at its full size: both local patches reach
+    # past the global domain, whose ghosts fall back to the exact solution
+    cfg = W.three_topology()
+    say("three-topology test, full size, one step")
+    o, g = run_pair(cfg, 1)
+    assert o.counters()["skip_local"] > 0
+    say("  worst rel err", compare(cfg, o, g, TOL64, norm="all"))
+
+
+@pytest.mark.parametrize("case", ["periodic", "rotating_cartesian", "spherical", "cylindrical"])
+def test_first_order_form(case):
+    # the first-order form of the Pi_t equation (Psi_i for d_i phi, d_i Psi_j for d_i d_j phi)
+    if case == "periodic":
+        cfg = W.single_periodic(seed=1, n=(40, 24, 16))
+    elif case == "rotating_cartesian":
+        cfg = W.two_patch(seed=6, ng=48, nl=40, P=6)
+        cfg["patches"][1]["spin"] = [0.15, -0.25, 0.3]
+    elif case == "spherical":
+        cfg = _sph_cfg(True)
+        cfg["patches"][1]["spin"] = [0.0, 0.2, 0.35]
+    else:
+        cfg = _cyl_cfg("rotating")
+    cfg["pi_form"] = 1
+    say("first-order form", case)
+    o, g = run_pair(cfg, 3, init="random", seed=23)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+    o, g = run_pair(cfg, 2, precision=pw.PW_MIXED)
+    say("  mixed, worst rel err", compare(cfg, o, g, 2e-5))
+
+
+@pytest.mark.parametrize("case", ["single", "two_patch", "random_mixed"])
+def test_sommerfeld_outer_boundary(case):
+    # the radiative outer boundary: the global patch's outer ghosts evolve with the state
+    if case == "single":
+        cfg = W._finish(dict(wave_speed=[0.8], interp_points=[6], patches=[W.patch([40, 32, 24], [-4, -3.2, -2.4],
+                                                                                     [4, 3.2, 2.4], is_global=1)],
+                             exact=[dict(kind="gauss", amp=[1.0], centers=[[2.5, -1.5, 1.0]], widths=[0.7])]))
+    else:
+        cfg = W.two_patch(seed=6, ng=48, nl=40, P=6)
+        cfg["exact"][0]["centers"] = [[5.5, -4.0, 3.0]]
+        cfg["exact"][0]["widths"] = [1.0]
+    cfg["outer_bc"] = 1
+    prec = pw.PW_MIXED if case == "random_mixed" else pw.PW_FP64
+    say("Sommerfeld", case)
+    o, g = run_pair(cfg, 4, precision=prec, init="random" if case == "random_mixed" else "exact", seed=29)
+    tol = 2e-5 if prec == pw.PW_MIXED else TOL64
+    say("  worst rel err", compare(cfg, o, g, tol))
+    # the evolved outer ghost cells themselves
+    a, b = g.get_state_full(0), o.get_full(0)
+    n = cfg["patches"][0]["n"]
+    ghost = np.ones(a.shape[1:], bool)
+    ghost[3:3 + n[2], 3:3 + n[1], 3:3 + n[0]] = False
+    scale = np.abs(b[:, ghost]).max(axis=1)
+    e = np.abs(a[:, ghost] - b[:, ghost]).max(axis=1) / np.maximum(scale, 1e-300)
+    say("  outer ghosts rel err", e.max())
+    assert np.isfinite(a[:, ghost]).all() and (e <= tol).all(), e
+
+
+@pytest.mark.parametrize("motion", ["fixed", "rotating", "translating"])
+def test_paper_test_two_convergence(motion):
+    # the paper's convergence test at its resolutions (global 40^3 .. 160^3 plus a
+    # 2-to-1 local cube, one wave period): parity with the oracle for a few steps
+    # at the lowest resolution, then the measured order of the integrated error
+    cfg = W.test_two(motion, ng=40)
+    o, g = run_pair(cfg, 4)
+    say("Test Two %s: worst rel err after 4 steps" % motion, compare(cfg, o, g, TOL64))
+    errs = []
+    for ng in (40, 80, 160):
+        cfg = W.test_two(motion, ng=ng)
+        g = pw.context_from_config(cfg)
+        g.init_exact(0.0)
+        g.rk4_step(cfg["dt"], cfg["steps"])
+        c = g.counters()
+        assert c["skip_local"] == 0 and c["skip_eff"] == 0 and c["skip_uncover"] == 0
+        errs.append(g.diagnostics(0)["int_rel_err"] + g.diagnostics(1)["int_rel_err"])
+        g.close()
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    say("  integrated relative errors", errs, "orders", slopes)
+    assert 3.7 < slopes[-1] < 4.4, (errs, slopes)
+
+
 def test_rotating_patch_mixed_precision():
     cfg = W.two_patch(seed=6, ng=48, nl=40, P=6)
     cfg["patches"][1]["spin"] = [0.15, -0.25, 0.3]

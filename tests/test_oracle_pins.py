@@ -688,3 +688,63 @@ def test_two_patch_convergence(motion):
         errs.append(e)
     slope = math.log2(errs[0] / errs[1])
     assert 3.5 < slope < 4.8, (errs, slope)
+
+
+# --------------------------------------------------------------------------
+# Sommerfeld outer boundary (variant; the paper uses the exact solution)
+# --------------------------------------------------------------------------
+def _outgoing_shell(p, v, t, r0=4.6, wd=0.9):
+    """phi = g(r - v t)/r, an exact outgoing solution, with Pi_t = d_t phi and
+    Psi_i = d_i phi, on every cell of p including ghosts."""
+    x, y, z = cell_centers(p, with_ghosts=True)
+    r = np.sqrt(x * x + y * y + z * z)
+    s = r - v * t - r0
+    g = np.exp(-s * s / wd ** 2)
+    gp = -2 * s / wd ** 2 * g
+    full = np.zeros((5,) + x.shape)
+    full[0] = g / r
+    full[1] = -v * gp / r
+    dr = gp / r - g / r ** 2
+    full[2], full[3], full[4] = dr * x / r, dr * y / r, dr * z / r
+    return full
+
+
+def test_sommerfeld_ghost_rhs_second_order():
+    # for phi = g(r - vt)/r the radiative condition holds exactly, so the ghost
+    # right-hand side of phi must approach d_t phi at second order
+    v, t = 0.8, 0.3
+    errs = []
+    for n in (32, 64):
+        p = W.patch([n] * 3, [-4] * 3, [4] * 3, is_global=1)
+        w = OracleWorld(wave_speed=(v,), outer_bc=1)
+        w.add_patch(p)
+        full = _outgoing_shell(p, v, t)
+        w.set_full(0, 0, full)
+        K = w.rhs_outer(0)
+        m = np.isfinite(K[0])
+        n_ghost = (n + 6) ** 3 - n ** 3
+        assert m.sum() == n_ghost
+        errs.append(np.abs(K[0][m] - full[1][m]).max())
+    assert errs[0] < 0.15 * np.abs(full[1]).max()
+    slope = math.log2(errs[0] / errs[1])
+    assert 1.7 < slope < 2.3, (errs, slope)
+
+
+def test_sommerfeld_pulse_leaves_the_domain():
+    # a Gaussian pulse crosses the outer boundary: with the radiative condition
+    # little of it comes back (the analytic boundary keeps the exact solution)
+    res = {}
+    for bc in (0, 1):
+        w = OracleWorld(wave_speed=(1.0,), outer_bc=bc)
+        w.add_patch(W.patch([32] * 3, [-4] * 3, [4] * 3, is_global=1))
+        w.set_exact(0, dict(kind="gauss", amp=[1.0], centers=[[0.2, -0.1, 0.3]], widths=[1.2]))
+        w.init_exact(0.0)
+        w.step(0.0625, 64)
+        early = w.diag(0)["err_max"][0]
+        w.step(0.0625, 128)
+        res[bc] = (early, w.diag(0)["max"][0])
+    assert res[0][1] < 1e-3 and res[1][0] < 5e-3
+    assert res[1][1] < 5e-3  # < 0.5% of the pulse amplitude is left in the box at t = 12
+    with pytest.raises(ValueError):
+        w = OracleWorld(outer_bc=1)
+        w.add_patch(W.patch([8] * 3, [0] * 3, [1] * 3, is_global=1, periodic=(1, 0, 0)))
