@@ -554,7 +554,10 @@ static int interp_donor(const or_world *w, int d, int sv, const double *T, doubl
           int ii = p->periodic[0] ? wrapi(s[0] + a, p->n[0]) : s[0] + a;
           int jj = p->periodic[1] ? wrapi(s[1] + b, p->n[1]) : s[1] + b;
           int kk = p->periodic[2] ? wrapi(s[2] + c, p->n[2]) : s[2] + c;
-          if (w->flag[GIX(p, ii, jj, kk)] != FLAG_LIVE) return 0;
+          uint8_t fl = w->flag[GIX(p, ii, jj, kk)];
+          /* paper's buffer: live donors only; narrower buffer: effective
+           * ghosts (already filled this stage) may serve as donors too */
+          if (w->buffer >= NG + 1 ? fl != FLAG_LIVE : fl == FLAG_DEACT) return 0;
         }
   }
   for (int f = 0; f < NF; f++) {
@@ -707,6 +710,64 @@ static int is_interior(const or_patch *p, const int c[3]) {
   return 1;
 }
 
+/* level 3a: global -> local, every non-periodic ghost cell of every local patch */
+static void fill_g2l(or_world *w, int which, double t, long long *skips) {
+  or_patch *g = &w->p[0];
+  long long sk_l = 0;
+  for (int pi = 1; pi < w->np; pi++) {
+    or_patch *p = &w->p[pi];
+    for (int sv = 0; sv < w->nsv; sv++) {
+      if (!(p->sv_mask & (1u << sv)) || !(g->sv_mask & (1u << sv))) continue;
+      double *T = bufsel(p, sv, which);
+      const double *TG = bufsel(g, sv, which);
+#pragma omp parallel for schedule(dynamic) reduction(+ : sk_l)
+      for (int k = -NG; k < p->n[2] + NG; k++)
+        for (int j = -NG; j < p->n[1] + NG; j++)
+          for (int i = -NG; i < p->n[0] + NG; i++) {
+            int c[3] = {i, j, k}, cw[3];
+            if (is_interior(p, c)) continue;
+            for (int a = 0; a < 3; a++) cw[a] = p->periodic[a] ? wrapi(c[a], p->n[a]) : c[a];
+            if (is_interior(p, cw)) continue;
+            double xr[3] = {xnum(p, 0, i), xnum(p, 1, j), xnum(p, 2, k)}, X[3], xd[3], ud[5], ur[5];
+            map_fwd(p, t, xr, X);
+            if (!interp_donor(w, 0, sv, TG, t, X, ud, xd)) { sk_l++; continue; }
+            transform(g, xd, p, xr, t, ud, ur);
+            for (int f = 0; f < NF; f++) T[IX(p, f, i, j, k)] = ur[f];
+          }
+    }
+  }
+  *skips += sk_l;
+}
+
+/* level 3b: local -> global, effective ghost cells of the global patch */
+static void fill_l2g(or_world *w, int which, double t, long long *skips) {
+  or_patch *g = &w->p[0];
+  long long sk_e = 0;
+  for (int sv = 0; sv < w->nsv; sv++) {
+    if (!(g->sv_mask & (1u << sv))) continue;
+    double *TG = bufsel(g, sv, which);
+#pragma omp parallel for schedule(dynamic) reduction(+ : sk_e)
+    for (int k = 0; k < g->n[2]; k++)
+      for (int j = 0; j < g->n[1]; j++)
+        for (int i = 0; i < g->n[0]; i++) {
+          long long c = GIX(g, i, j, k);
+          if (w->flag[c] != FLAG_EFFGHOST) continue;
+          or_patch *p = &w->p[w->cover[c]];
+          double xr[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)}, xd[3], ud[5], ur[5];
+          int ok = (p->sv_mask & (1u << sv)) && interp_donor(w, w->cover[c], sv, bufsel(p, sv, which), t, xr, ud, xd);
+          if (ok) {
+            transform(p, xd, g, xr, t, ud, ur);
+          } else {
+            sk_e++;
+            if (w->ex[sv].kind != EX_NONE) exact_patch(w, g, sv, t, xr, ur);
+            else for (int f = 0; f < NF; f++) ur[f] = NAN;
+          }
+          for (int f = 0; f < NF; f++) TG[IX(g, f, i, j, k)] = ur[f];
+        }
+  }
+  *skips += sk_e;
+}
+
 static void fill_ghosts(or_world *w, int which, double t) {
   long long sk_l = 0, sk_e = 0;
   for (int pi = 0; pi < w->np; pi++) {
@@ -740,52 +801,17 @@ static void fill_ghosts(or_world *w, int which, double t) {
     }
   }
   if (w->np == 1) return;
-  or_patch *g = &w->p[0];
-  /* level 3a: global -> local, every non-periodic ghost cell of every local patch */
-  for (int pi = 1; pi < w->np; pi++) {
-    or_patch *p = &w->p[pi];
-    for (int sv = 0; sv < w->nsv; sv++) {
-      if (!(p->sv_mask & (1u << sv)) || !(g->sv_mask & (1u << sv))) continue;
-      double *T = bufsel(p, sv, which);
-      const double *TG = bufsel(g, sv, which);
-#pragma omp parallel for schedule(dynamic) reduction(+ : sk_l)
-      for (int k = -NG; k < p->n[2] + NG; k++)
-        for (int j = -NG; j < p->n[1] + NG; j++)
-          for (int i = -NG; i < p->n[0] + NG; i++) {
-            int c[3] = {i, j, k}, cw[3];
-            if (is_interior(p, c)) continue;
-            for (int a = 0; a < 3; a++) cw[a] = p->periodic[a] ? wrapi(c[a], p->n[a]) : c[a];
-            if (is_interior(p, cw)) continue;
-            double xr[3] = {xnum(p, 0, i), xnum(p, 1, j), xnum(p, 2, k)}, X[3], xd[3], ud[5], ur[5];
-            map_fwd(p, t, xr, X);
-            if (!interp_donor(w, 0, sv, TG, t, X, ud, xd)) { sk_l++; continue; }
-            transform(g, xd, p, xr, t, ud, ur);
-            for (int f = 0; f < NF; f++) T[IX(p, f, i, j, k)] = ur[f];
-          }
-    }
-  }
-  /* level 3b: local -> global, effective ghost cells of the global patch */
-  for (int sv = 0; sv < w->nsv; sv++) {
-    if (!(g->sv_mask & (1u << sv))) continue;
-    double *TG = bufsel(g, sv, which);
-#pragma omp parallel for schedule(dynamic) reduction(+ : sk_e)
-    for (int k = 0; k < g->n[2]; k++)
-      for (int j = 0; j < g->n[1]; j++)
-        for (int i = 0; i < g->n[0]; i++) {
-          long long c = GIX(g, i, j, k);
-          if (w->flag[c] != FLAG_EFFGHOST) continue;
-          or_patch *p = &w->p[w->cover[c]];
-          double xr[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)}, xd[3], ud[5], ur[5];
-          int ok = (p->sv_mask & (1u << sv)) && interp_donor(w, w->cover[c], sv, bufsel(p, sv, which), t, xr, ud, xd);
-          if (ok) {
-            transform(p, xd, g, xr, t, ud, ur);
-          } else {
-            sk_e++;
-            if (w->ex[sv].kind != EX_NONE) exact_patch(w, g, sv, t, xr, ur);
-            else for (int f = 0; f < NF; f++) ur[f] = NAN;
-          }
-          for (int f = 0; f < NF; f++) TG[IX(g, f, i, j, k)] = ur[f];
-        }
+  /* level 3: interpatch.  With the paper's buffer (NG + 1 live cells) neither
+   * direction reads the other's output, and global -> local comes first.  With
+   * a narrower buffer (the ablation of the original Patchwork flags) the
+   * global -> local stencils may reach effective ghosts, which therefore are
+   * filled first (interpolation of interpolated data). */
+  if (w->buffer >= NG + 1) {
+    fill_g2l(w, which, t, &sk_l);
+    fill_l2g(w, which, t, &sk_e);
+  } else {
+    fill_l2g(w, which, t, &sk_e);
+    fill_g2l(w, which, t, &sk_l);
   }
   w->skip_local += sk_l;
   w->skip_eff += sk_e;

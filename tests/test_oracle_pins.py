@@ -748,3 +748,34 @@ def test_sommerfeld_pulse_leaves_the_domain():
     with pytest.raises(ValueError):
         w = OracleWorld(outer_bc=1)
         w.add_patch(W.patch([8] * 3, [0] * 3, [1] * 3, is_global=1, periodic=(1, 0, 0)))
+
+
+# --------------------------------------------------------------------------
+# Ablation of the buffer: the original Patchwork flags (no NG+1 buffer), where
+# global -> local stencils read effective ghosts filled in the same stage
+# (interpolation of interpolated data).  The paper motivates the buffer by the
+# order this costs with low-order interpolation.
+# --------------------------------------------------------------------------
+def _ablation_slope(P, B):
+    errs = []
+    for ng in (32, 64):
+        cfg, dxl = _two_patch_plane(ng, "translating")
+        cfg["buffer"] = B
+        cfg["interp_points"] = [P]
+        w = world_from_config(cfg)
+        w.init_exact(0.0)
+        steps = int(round(2.0 / (0.5 * dxl)))
+        w.step(2.0 / steps, steps)
+        c = w.counters()
+        assert c["skip_local"] == 0 and c["skip_eff"] == 0 and c["skip_uncover"] == 0
+        errs.append(w.diag(0)["int_rel_err"] + w.diag(1)["int_rel_err"])
+    return math.log2(errs[0] / errs[1]), errs
+
+
+def test_buffer_ablation_convergence():
+    s_lin_buf, _ = _ablation_slope(2, 4)
+    s_lin_nobuf, _ = _ablation_slope(2, 1)
+    s_six_nobuf, e6 = _ablation_slope(6, 1)
+    assert 1.8 < s_lin_buf < 2.2            # linear interpolation, buffered: second order
+    assert s_lin_nobuf < s_lin_buf - 0.3    # interpolating interpolated data costs order
+    assert 3.5 < s_six_nobuf < 4.8          # the paper's 6-point stencil keeps fourth order
