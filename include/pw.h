@@ -73,10 +73,16 @@ enum { PW_BC_EXACT = 0, PW_BC_SOMMERFELD = 1 };        /* outer boundary of the 
  *   n_state_vectors  1..4 independent state vectors sharing maps and cover flags
  *                    (multiple state vectors, Sec. 1.1); each has its own wave speed
  *                    (d'Alembertian Lap - v^-2 d_t^2) and interpolation order.
- *   interp_points    points per axis of the tensor-product Lagrange stencil: 6 is the
- *                    paper's stencil i_c-2..i_c+3 (Sec. 2.4, Eq. Pijk); 5 centres on the
- *                    nearest node.
- *   buffer_width     live buffer under each local patch edge, >= 4 (NG+1, Sec. 2.4.2).
+ *   interp_points    points P per axis of the tensor-product Lagrange stencil, 2..6
+ *                    (order P-1).  6 is the paper's stencil i_c-2..i_c+3 (Sec. 2.4,
+ *                    Eq. Pijk); the stencil starts at floor(q - (P-2)/2) for the
+ *                    fractional cell index q, so 5 centres on the nearest node and 2 is
+ *                    linear interpolation between the two neighbouring nodes.
+ *   buffer_width     live buffer under each local patch edge: 4 = NG+1 is the paper's
+ *                    (Sec. 2.4.2).  1..3 is the ablation of the original Patchwork flags:
+ *                    global->local stencils may then reach effective ghost cells, so each
+ *                    stage fills the effective ghosts first and the local ghosts from them
+ *                    (interpolation of interpolated data).  At most 16.
  *   ko_eps           Kreiss-Oliger strength (0.005 in the paper, Sec. 2.3).
  *   schedule         PW_SCHED_BATCHED: each RK stage is one launch over all patches
  *                    and the step is captured in a HIP graph when use_graph != 0.

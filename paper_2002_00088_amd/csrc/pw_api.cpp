@@ -51,7 +51,7 @@ struct pw_context {
   hipStream_t stream2 = nullptr;  // second branch of the overlapped step
   hipStream_t stream3 = nullptr;  // third branch: the next step's cover flags and lists
   hipEvent_t evFork = nullptr, evG[4] = {nullptr, nullptr, nullptr, nullptr},
-             evL[4] = {nullptr, nullptr, nullptr, nullptr};
+             evL[4] = {nullptr, nullptr, nullptr, nullptr}, evE[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t evGhL = nullptr, evGhG = nullptr, evNext = nullptr;
   GBrick *dBricks = nullptr;
   int nBricks = 0;
@@ -62,7 +62,7 @@ struct pw_context {
   FallbackRec *fbList[2] = {nullptr, nullptr};  // skipped points of the local / global part
   int *fbCount[2] = {nullptr, nullptr};
   long long fbCap = 0;
-  uint8_t *dvalid[2] = {nullptr, nullptr};  // donor-valid bytes for P = 5, 6
+  uint8_t *dvalid[PW_NPTS] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // donor-valid bytes, P = 2 .. 6
   TileRec *dTiles = nullptr;
   int nTiles = 0;
   std::vector<int> tileOff, tileCnt;
@@ -164,6 +164,9 @@ uint32_t pack_ijk(int i, int j, int k) {
 bool mixed(const pw_context *c) { return c->cfg.precision == PW_MIXED || c->cfg.precision == PW_MIXED_INC; }
 size_t stage_elem(const pw_context *c) { return mixed(c) ? sizeof(float) : sizeof(double); }
 bool has_locals(const pw_context *c) { return c->hp.size() > 1; }
+// a buffer narrower than NG + 1 cells (the original Patchwork flags as an
+// ablation): global->local stencils may reach effective ghosts
+bool narrow_buffer(const pw_context *c) { return c->cfg.buffer_width < PW_NG + 1; }
 
 hipEvent_t take_event(pw_context *c) {
   if (!c->ev_free.empty()) {
@@ -438,10 +441,11 @@ void enqueue_post_flags(pw_context *c, const PoseDev *pose_slot, hipStream_t st)
   a.flag = c->flag_new;
   a.efflist = c->efflist;
   a.effcount = c->effcount;
-  a.dvalid[0] = c->dvalid[0];
-  a.dvalid[1] = c->dvalid[1];
-  a.Pvals[0] = 5;
-  a.Pvals[1] = 6;
+  for (int m = 0; m < PW_NPTS; m++) {
+    a.dvalid[m] = c->dvalid[m];
+    a.Pvals[m] = 2 + m;
+  }
+  a.donor_effghost = narrow_buffer(c);
   a.t1 = c->t1;
   a.t2 = c->t2;
   for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
@@ -496,7 +500,7 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.n_lower_global = c->nLowerGlobal;
     a.bricks = c->dBricks;
     a.n_bricks = has_locals(c) ? c->nBricks : 0;
-    a.dvalid = c->dvalid[c->cfg.interp_points[sv] == 5 ? 0 : 1];
+    a.dvalid = c->dvalid[c->cfg.interp_points[sv] - 2];
     a.efflist = c->efflist;
     a.effcount = c->effcount;
     a.cover = c->cover_cur;
@@ -518,6 +522,7 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.fb_count = c->fbCount[which];
     a.g2l_run = c->tune.g2l_run;
     a.l2g_run = c->tune.l2g_run;
+    a.l2g_first = narrow_buffer(c);
     launch_ghosts(st, a);
   }
 }
@@ -641,8 +646,26 @@ void enqueue_step_overlap(pw_context *c, double dt) {
   enqueue_flags(c, c->dPose + 2 * np, Z);
   static const int slot_of_stage[4] = {0, 1, 1, 2};
   static const double tmul[4] = {0.0, 0.5, 0.5, 1.0};
+  const bool narrow = narrow_buffer(c);
   for (int s = 0; s < 4; s++) {
     const PoseDev *ps = c->dPose + slot_of_stage[s] * np;
+    if (narrow) {
+      // the global chain's local->global fill of this stage goes first; the
+      // local chain's global->local stencils read the effective ghosts it wrote
+      if (s > 0) (void)hipStreamWaitEvent(Y, c->evL[s - 1], 0);
+      enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, Y);
+      if (s == 3) (void)hipEventRecord(c->evGhG, Y);
+      (void)hipEventRecord(c->evE[s], Y);
+      if (s > 0) (void)hipStreamWaitEvent(X, c->evG[s - 1], 0);
+      (void)hipStreamWaitEvent(X, c->evE[s], 0);
+      enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X);
+      if (s == 3) (void)hipEventRecord(c->evGhL, X);
+      enqueue_stage_part(c, s, ps, dt, 2, X);
+      (void)hipEventRecord(c->evL[s], X);
+      enqueue_stage_part(c, s, ps, dt, 1, Y);
+      (void)hipEventRecord(c->evG[s], Y);
+      continue;
+    }
     if (s > 0) (void)hipStreamWaitEvent(X, c->evG[s - 1], 0);
     enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X);
     if (s == 3) (void)hipEventRecord(c->evGhL, X);
@@ -745,11 +768,11 @@ pw_status pw_create(const pw_config *cfg, pw_context **out) {
   *out = nullptr;
   if (cfg->n_state_vectors < 1 || cfg->n_state_vectors > PW_MAX_SV) return PW_EINVAL;
   if (cfg->precision != PW_FP64 && cfg->precision != PW_MIXED && cfg->precision != PW_MIXED_INC) return PW_EINVAL;
-  if (cfg->buffer_width < 4) return PW_EINVAL;
+  if (cfg->buffer_width < 1 || cfg->buffer_width > 16) return PW_EINVAL;
   if (cfg->pi_form != PW_FORM_PAPER && cfg->pi_form != PW_FORM_FIRST_ORDER) return PW_EINVAL;
   if (cfg->outer_bc != PW_BC_EXACT && cfg->outer_bc != PW_BC_SOMMERFELD) return PW_EINVAL;
   for (int s = 0; s < cfg->n_state_vectors; s++) {
-    if (cfg->interp_points[s] != 5 && cfg->interp_points[s] != 6) return PW_EINVAL;
+    if (cfg->interp_points[s] < 2 || cfg->interp_points[s] > 6) return PW_EINVAL;
     if (!(cfg->wave_speed[s] > 0)) return PW_EINVAL;
   }
   if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return PW_EINVAL;
@@ -776,7 +799,8 @@ pw_status pw_create(const pw_config *cfg, pw_context **out) {
   }
   for (int s = 0; s < 4; s++)
     if (hipEventCreateWithFlags(&c->evG[s], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->evL[s], hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->evL[s], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evE[s], hipEventDisableTiming) != hipSuccess) {
       pw_destroy(c);
       return PW_EDEVICE;
     }
@@ -937,9 +961,9 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     c->eRank = (int *)dalloc(c, sizeof(int) * c->gcells);
     c->effcount = (int *)dalloc(c, sizeof(int));
     if (!c->effsorted || !c->eBkt || !c->eRank) return fail(c, PW_ENOMEM, "device allocation failed");
-    for (int m = 0; m < 2; m++) {
+    for (int m = 0; m < PW_NPTS; m++) {
       bool used = false;
-      for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) used = used || c->cfg.interp_points[sv] == 5 + m;
+      for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) used = used || c->cfg.interp_points[sv] == 2 + m;
       c->dvalid[m] = used ? (uint8_t *)dalloc(c, c->gcells) : nullptr;
       if (used && !c->dvalid[m]) return fail(c, PW_ENOMEM, "device allocation failed");
     }
@@ -1361,6 +1385,7 @@ void pw_destroy(pw_context *c) {
   for (int s = 0; s < 4; s++) {
     if (c->evG[s]) (void)hipEventDestroy(c->evG[s]);
     if (c->evL[s]) (void)hipEventDestroy(c->evL[s]);
+    if (c->evE[s]) (void)hipEventDestroy(c->evE[s]);
   }
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;

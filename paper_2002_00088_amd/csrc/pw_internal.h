@@ -11,6 +11,7 @@
 #define PW_OX 8          // row offset of interior cell i = 0
 #define PW_MAXSV 4
 #define PW_MAXPULSE 32
+#define PW_NPTS 5    // interpolation widths P = 2 .. 6
 
 namespace pw {
 

@@ -65,8 +65,9 @@ struct PostFlagsArgs {
   const uint8_t *flag;
   int32_t *efflist;
   int *effcount;
-  uint8_t *dvalid[2];
-  int Pvals[2];
+  uint8_t *dvalid[PW_NPTS];  // per interpolation width P = 2 .. 6 in use (else null)
+  int Pvals[PW_NPTS];
+  int donor_effghost;  // narrow buffer: effective ghosts count as valid donors
   uint8_t *t1, *t2;
   int n[3];
 };
@@ -139,6 +140,7 @@ struct GhostArgs {
   FallbackRec *fb;  // capacity: every interpatch target of this part
   int *fb_count;
   int g2l_run, l2g_run;  // consecutive bricks / groups per XCD run
+  int l2g_first;         // narrow buffer: local->global (and its fallbacks) before global->local
 };
 
 struct StageArgs {

@@ -250,7 +250,9 @@ __global__ void k_window_min(const uint8_t *in, uint8_t *out, int n0, int n1, in
   int m = 1;
   for (int d = 0; d < P; d++) {
     int v = 0;
-    if (pos + d < len) v = from_flags ? (in[c + d * stride] == LIVE) : in[c + d * stride];
+    if (pos + d < len)
+      v = from_flags == 1 ? (in[c + d * stride] == LIVE)
+                          : (from_flags == 2 ? (in[c + d * stride] != DEACT) : in[c + d * stride]);
     m = v < m ? v : m;
   }
   out[c] = (uint8_t)m;
@@ -1810,27 +1812,55 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
     hipLaunchKernelGGL(k_fill_lower<TB>, dim3(nblk(l1 - l0, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower + l0, l1 - l0,
                        a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
   if (!g2l && !l2g) return;
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
-  if (g2l) {
+  auto run_g2l = [&]() {
     const int run = a.g2l_run;
     const int bchunk = (a.n_bricks + 8 * run - 1) / (8 * run);
-    if (a.Pts == 5)
-      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 5>), dim3(8 * run * bchunk), dim3(BRICK_THREADS), 0, s, a.P,
-                         a.pose, a.bricks, a.n_bricks, run, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
-    else
-      hipLaunchKernelGGL((k_g2l_brick<TB, TC, 6>), dim3(8 * run * bchunk), dim3(BRICK_THREADS), 0, s, a.P,
-                         a.pose, a.bricks, a.n_bricks, run, a.sv, a.stage, a.dvalid, a.skips, a.fb, a.fb_count);
+    const dim3 g(8 * run * bchunk), b(BRICK_THREADS);
+#define PW_G2L(PP)                                                                                           \
+  hipLaunchKernelGGL((k_g2l_brick<TB, TC, PP>), g, b, 0, s, a.P, a.pose, a.bricks, a.n_bricks, run, a.sv, a.stage, \
+                     a.dvalid, a.skips, a.fb, a.fb_count)
+    switch (a.Pts) {
+      case 2: PW_G2L(2); break;
+      case 3: PW_G2L(3); break;
+      case 4: PW_G2L(4); break;
+      case 5: PW_G2L(5); break;
+      default: PW_G2L(6); break;
+    }
+#undef PW_G2L
+  };
+  auto run_l2g = [&]() {
+    const dim3 g(L2G_BLOCKS), b(64 * L2G_WAVES);
+#define PW_L2G(PP)                                                                                                \
+  hipLaunchKernelGGL((k_l2g_box<TB, TC, PP>), g, b, 0, s, a.P, a.pose, a.efflist, a.effcount, a.l2g_run, a.cover, a.sv, \
+                     a.stage, a.skips + 1, a.fb, a.fb_count)
+    switch (a.Pts) {
+      case 2: PW_L2G(2); break;
+      case 3: PW_L2G(3); break;
+      case 4: PW_L2G(4); break;
+      case 5: PW_L2G(5); break;
+      default: PW_L2G(6); break;
+    }
+#undef PW_L2G
+  };
+  auto fallback = [&]() {
+    hipLaunchKernelGGL(k_fallback<TB>, dim3(64), dim3(256), 0, s, a.P, a.pose, a.fb, a.fb_count, a.sv, a.stage, a.ex,
+                       a.v, a.tdev, a.tmul, a.dt);
+  };
+  if (a.l2g_first && g2l && l2g) {
+    // narrow buffer: the effective ghosts (with their fallbacks) are complete
+    // before the global -> local stencils read them
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
+    run_l2g();
+    fallback();
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
+    run_g2l();
+    fallback();
+    return;
   }
-  if (l2g) {
-    if (a.Pts == 5)
-      hipLaunchKernelGGL((k_l2g_box<TB, TC, 5>), dim3(L2G_BLOCKS), dim3(64 * L2G_WAVES), 0, s, a.P, a.pose, a.efflist,
-                         a.effcount, a.l2g_run, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count);
-    else
-      hipLaunchKernelGGL((k_l2g_box<TB, TC, 6>), dim3(L2G_BLOCKS), dim3(64 * L2G_WAVES), 0, s, a.P, a.pose, a.efflist,
-                         a.effcount, a.l2g_run, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count);
-  }
-  hipLaunchKernelGGL(k_fallback<TB>, dim3(64), dim3(256), 0, s, a.P, a.pose, a.fb, a.fb_count, a.sv, a.stage, a.ex,
-                     a.v, a.tdev, a.tmul, a.dt);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
+  if (g2l) run_g2l();
+  if (l2g) run_l2g();
+  fallback();
 }
 
 void launch_ghosts(hipStream_t s, const GhostArgs &a) {
@@ -1850,11 +1880,11 @@ void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
   const long long tot_bricks = (long long)((a.n[0] + 3) / 4) * ((a.n[1] + 3) / 4) * ((a.n[2] + 3) / 4) * 64;
   hipLaunchKernelGGL(k_efflist, dim3(nblk(tot_bricks, 256 * EFF_PER_THREAD)), dim3(256), 0, s,
                      (const uint8_t *)a.flag, a.n[0], a.n[1], a.n[2], a.efflist, a.effcount);
-  for (int m = 0; m < 2; m++) {
+  for (int m = 0; m < PW_NPTS; m++) {
     if (!a.dvalid[m]) continue;
     int P = a.Pvals[m];
     hipLaunchKernelGGL(k_window_min<0>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.flag, a.t1, a.n[0], a.n[1],
-                       a.n[2], P, 1);
+                       a.n[2], P, a.donor_effghost ? 2 : 1);
     hipLaunchKernelGGL(k_window_min<1>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.t1, a.t2, a.n[0], a.n[1],
                        a.n[2], P, 0);
     hipLaunchKernelGGL(k_window_min<2>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.t2, a.dvalid[m], a.n[0],
