@@ -616,6 +616,26 @@ static double bound_radius(const or_patch *p) {
 }
 
 /* is background point X inside the closed numerical box of local patch p at t? */
+/* background position of global cell (i,j,k): the global patch is static and
+ * unrotated at the origin, so a Cartesian global's numerical coordinates are X */
+static void global_X(const or_patch *g, double t, int i, int j, int k, double X[3]) {
+  double xp[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)};
+  if (g->coord == CART) {
+    for (int a = 0; a < 3; a++) X[a] = xp[a];
+  } else {
+    map_fwd(g, t, xp, X);
+  }
+}
+
+/* neighbour index along axis a of the global patch: wraps a periodic axis;
+ * returns 0 if the index leaves a non-periodic axis */
+static int gneighbour(const or_patch *g, int a, int i, int *out) {
+  if (g->periodic[a]) { *out = wrapi(i, g->n[a]); return 1; }
+  if (i < 0 || i >= g->n[a]) return 0;
+  *out = i;
+  return 1;
+}
+
 static int covers(const or_patch *p, double t, const double c[3], const double X[3]) {
   double d2 = 0, xp[3];
   for (int a = 0; a < 3; a++) d2 += (X[a] - c[a]) * (X[a] - c[a]);
@@ -635,25 +655,28 @@ static int covers(const or_patch *p, double t, const double c[3], const double X
 static int compute_flags(or_world *w, double t, uint8_t *flag, int32_t *cover) {
   const or_patch *g = &w->p[0];
   long long ncell = (long long)g->n[0] * g->n[1] * g->n[2];
-  int overlap = 0;
+  /* a cell covered by two local patches keeps the lower patch id; such
+   * overlaps are allowed where the cell stays live (the buffers), and are an
+   * error anywhere else */
+  uint8_t *dbl = (uint8_t *)calloc(ncell, 1);
   for (long long c = 0; c < ncell; c++) cover[c] = -1;
   for (int pi = 1; pi < w->np; pi++) {
     const or_patch *p = &w->p[pi];
     double cp[3];
     center_val(p, t, cp);
-#pragma omp parallel for reduction(| : overlap) schedule(static)
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < g->n[2]; k++)
       for (int j = 0; j < g->n[1]; j++)
         for (int i = 0; i < g->n[0]; i++) {
-          double X[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)};
+          double X[3];
+          global_X(g, t, i, j, k, X);
           if (covers(p, t, cp, X)) {
             long long c = GIX(g, i, j, k);
-            if (cover[c] != -1) overlap = 1;
-            cover[c] = pi;
+            if (cover[c] != -1) dbl[c] = 1;
+            else cover[c] = pi;
           }
         }
   }
-  if (overlap) return -5;
   int B = w->buffer;
 #pragma omp parallel for schedule(static)
   for (int k = 0; k < g->n[2]; k++)
@@ -664,9 +687,11 @@ static int compute_flags(or_world *w, double t, uint8_t *flag, int32_t *cover) {
         for (int dk = -B; dk <= B && !live; dk++)
           for (int dj = -B; dj <= B && !live; dj++)
             for (int di = -B; di <= B && !live; di++) {
-              int ii = i + di, jj = j + dj, kk = k + dk;
-              if (ii < 0 || jj < 0 || kk < 0 || ii >= g->n[0] || jj >= g->n[1] || kk >= g->n[2]) live = 1;
-              else if (cover[GIX(g, ii, jj, kk)] == -1) live = 1;
+              int ii, jj, kk;
+              if (!gneighbour(g, 0, i + di, &ii) || !gneighbour(g, 1, j + dj, &jj) || !gneighbour(g, 2, k + dk, &kk))
+                live = 1;
+              else if (cover[GIX(g, ii, jj, kk)] == -1)
+                live = 1;
             }
         flag[c] = live ? FLAG_LIVE : FLAG_DEACT;
       }
@@ -681,16 +706,21 @@ static int compute_flags(or_world *w, double t, uint8_t *flag, int32_t *cover) {
         for (int dk = -NG; dk <= NG && !near; dk++)
           for (int dj = -NG; dj <= NG && !near; dj++)
             for (int di = -NG; di <= NG && !near; di++) {
-              int ii = i + di, jj = j + dj, kk = k + dk;
-              if (ii < 0 || jj < 0 || kk < 0 || ii >= g->n[0] || jj >= g->n[1] || kk >= g->n[2]) continue;
+              int ii, jj, kk;
+              if (!gneighbour(g, 0, i + di, &ii) || !gneighbour(g, 1, j + dj, &jj) || !gneighbour(g, 2, k + dk, &kk))
+                continue;
               if (flag[GIX(g, ii, jj, kk)] == FLAG_LIVE) near = 1;
             }
         eff[c] = (uint8_t)near;
       }
-  for (long long c = 0; c < ncell; c++)
+  int overlap = 0;
+  for (long long c = 0; c < ncell; c++) {
     if (eff[c]) flag[c] = FLAG_EFFGHOST;
+    if (dbl[c] && flag[c] != FLAG_LIVE) overlap = 1;
+  }
   free(eff);
-  return 0;
+  free(dbl);
+  return overlap ? -5 : 0;
 }
 
 static int is_live(const or_world *w, const or_patch *p, int i, int j, int k) {
@@ -753,8 +783,9 @@ static void fill_l2g(or_world *w, int which, double t, long long *skips) {
           long long c = GIX(g, i, j, k);
           if (w->flag[c] != FLAG_EFFGHOST) continue;
           or_patch *p = &w->p[w->cover[c]];
-          double xr[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)}, xd[3], ud[5], ur[5];
-          int ok = (p->sv_mask & (1u << sv)) && interp_donor(w, w->cover[c], sv, bufsel(p, sv, which), t, xr, ud, xd);
+          double xr[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)}, X[3], xd[3], ud[5], ur[5];
+          global_X(g, t, i, j, k, X);
+          int ok = (p->sv_mask & (1u << sv)) && interp_donor(w, w->cover[c], sv, bufsel(p, sv, which), t, X, ud, xd);
           if (ok) {
             transform(p, xd, g, xr, t, ud, ur);
           } else {
@@ -1001,8 +1032,9 @@ static int end_of_step_flags(or_world *w) {
           nu++;
           int d = nc[c] >= 0 ? nc[c] : w->cover[c];
           or_patch *p = &w->p[d];
-          double xr[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)}, xd[3], ud[5], ur[5];
-          int ok = (p->sv_mask & (1u << sv)) && interp_donor(w, d, sv, p->u[sv], w->t, xr, ud, xd);
+          double xr[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)}, X[3], xd[3], ud[5], ur[5];
+          global_X(g, w->t, i, j, k, X);
+          int ok = (p->sv_mask & (1u << sv)) && interp_donor(w, d, sv, p->u[sv], w->t, X, ud, xd);
           if (ok) {
             transform(p, xd, g, xr, w->t, ud, ur);
           } else {

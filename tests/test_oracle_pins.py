@@ -779,3 +779,93 @@ def test_buffer_ablation_convergence():
     assert 1.8 < s_lin_buf < 2.2            # linear interpolation, buffered: second order
     assert s_lin_nobuf < s_lin_buf - 0.3    # interpolating interpolated data costs order
     assert 3.5 < s_six_nobuf < 4.8          # the paper's 6-point stencil keeps fourth order
+
+
+# --------------------------------------------------------------------------
+# Spherical global patch (the paper's fourth test): cover flags over the
+# global's (r, theta, phi) index space with a periodic phi axis; local
+# patches may overlap where the global cells stay live (the buffers)
+# --------------------------------------------------------------------------
+def _sph_global(n=(20, 16, 48), lo=(1.0, 0.6, 0.0), hi=(12.0, math.pi - 0.6, 2 * math.pi)):
+    return W.patch(list(n), list(lo), list(hi), coord=SPH, is_global=1, periodic=(0, 0, 1))
+
+
+def _brute_flags_sph(g, locs, B=4):
+    from scipy import ndimage
+    nr, nt, nph = g["n"]
+    r = g["lo"][0] + (np.arange(nr) + 0.5) * (g["hi"][0] - g["lo"][0]) / nr
+    th = g["lo"][1] + (np.arange(nt) + 0.5) * (g["hi"][1] - g["lo"][1]) / nt
+    ph = g["lo"][2] + (np.arange(nph) + 0.5) * (g["hi"][2] - g["lo"][2]) / nph
+    P, T, R = np.meshgrid(ph, th, r, indexing="ij")  # [phi][theta][r] = [k][j][i]
+    X = np.stack([R * np.sin(T) * np.cos(P), R * np.sin(T) * np.sin(P), R * np.cos(T)])
+    cover = np.full(R.shape, -1)
+    dbl = np.zeros(R.shape, bool)
+    for pid, d in enumerate(locs, start=1):
+        Rm = zyz(d["euler"])
+        y = np.einsum("ba,b...->a...", Rm, X - np.array(d["c0"])[:, None, None, None])
+        inside = np.ones(R.shape, bool)
+        for a in range(3):
+            inside &= (y[a] >= d["lo"][a]) & (y[a] <= d["hi"][a])
+        dbl |= inside & (cover >= 0)
+        cover = np.where(inside & (cover < 0), pid, cover)
+    unc = cover < 0
+    # Chebyshev neighbourhoods: wrap along phi (axis 0), outside the domain is uncovered along r, theta
+    pad = np.pad(unc, ((0, 0), (B, B), (B, B)), constant_values=True)
+    live = ndimage.maximum_filter(pad, size=2 * B + 1, mode="wrap")[:, B:-B, B:-B]
+    pad = np.pad(live, ((0, 0), (3, 3), (3, 3)), constant_values=False)
+    eff = ndimage.maximum_filter(pad, size=7, mode="wrap")[:, 3:-3, 3:-3] & ~live
+    flags = np.where(live, FLAG_LIVE, np.where(eff, FLAG_EFFGHOST, FLAG_DEACT))
+    return flags, cover, dbl
+
+
+def test_spherical_global_flags_match_brute_force():
+    g = _sph_global(n=(40, 40, 160))
+    # a large rotated box across the phi = 0 seam, and a second one overlapping
+    # it only where the global cells stay live
+    a = W.patch([8] * 3, [-3.5, -3.5, -3.2], [3.5, 3.5, 3.2], euler=[0.3, 0.2, 0.1], c0=(6.5, 0.2, -0.1))
+    b = W.patch([8] * 3, [-1.5] * 3, [1.5] * 3, euler=[1.0, 0.4, 0.2], c0=(6.5, 5.4, 0.0))
+    w = OracleWorld()
+    w.add_patch(g)
+    w.add_patch(a)
+    w.add_patch(b)
+    w.prepare()
+    f, c = w.flags()
+    ef, ec, dbl = _brute_flags_sph(g, [a, b])
+    assert (ec == c).all() and (ef == f).all()
+    assert (f == FLAG_DEACT).sum() > 0 and (f == FLAG_EFFGHOST).sum() > 0
+    assert dbl.any() and (f[dbl] == FLAG_LIVE).all()
+    # the covered region crosses the periodic seam of phi
+    k_cov = np.nonzero((c >= 1).any(axis=(1, 2)))[0]
+    assert 0 in k_cov and g["n"][2] - 1 in k_cov
+
+
+def test_overlap_outside_the_buffers_is_an_error():
+    w = OracleWorld()
+    w.add_patch(W.patch([40] * 3, [-8] * 3, [8] * 3, is_global=1))
+    w.add_patch(W.patch([24] * 3, [-3] * 3, [3] * 3, c0=(-1.0, 0.0, 0.0)))
+    w.add_patch(W.patch([24] * 3, [-3] * 3, [3] * 3, c0=(1.0, 0.0, 0.0)))
+    with pytest.raises(Exception):
+        w.prepare()
+
+
+def test_spherical_global_convergence():
+    # a rotated Cartesian local patch straddling the phi seam of a spherical
+    # global shell; fourth order with the global's own (curvilinear) stencils,
+    # analytic ghosts at r and theta, periodic phi
+    errs = []
+    for res in (1, 2):
+        g = _sph_global(n=(16 * res, 16 * res, 48 * res))
+        loc = W.patch([20 * res, 20 * res, 10 * res], [-2.5, -2.5, -1.25], [2.5, 2.5, 1.25], euler=[0.3, 0.2, 0.1],
+                      c0=(6.0, 0.3, -0.2))
+        ex = dict(kind="plane", A=1.0, B=2.0, kappa=[2 * math.pi / 8, 2 * math.pi / 16, 0.0], psi=0.3)
+        cfg = W._finish(dict(wave_speed=[1.0], interp_points=[6], patches=[g, loc], exact=[ex]))
+        T = 0.5
+        steps = int(math.ceil(T / cfg["dt"]))
+        w = world_from_config(cfg)
+        w.init_exact(0.0)
+        w.step(T / steps, steps)
+        if res == 2:
+            assert w.counters()["skip_local"] == 0
+        errs.append(w.diag(0)["int_rel_err"] + w.diag(1)["int_rel_err"])
+    slope = math.log2(errs[0] / errs[1])
+    assert 3.5 < slope < 4.8, (errs, slope)
