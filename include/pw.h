@@ -43,7 +43,7 @@ enum {
   PW_ENOMEM = -2,   /* device or host allocation failed */
   PW_EDEVICE = -3,  /* a HIP runtime call failed */
   PW_ESTATE = -4,   /* call not valid in the current state (e.g. no global patch) */
-  PW_EOVERLAP = -5, /* a global cell is covered by two local patches (Sec. 2.4.2 assumes none) */
+  PW_EOVERLAP = -5, /* two local patches cover a global cell that is not live (Sec. 2.4.2) */
   PW_EMOTION = -6   /* a patch moves one global cell or more within a step: the NG+1 buffer
                        covers at most one cell of motion per step (Sec. 2.4.2) */
 };
@@ -102,7 +102,7 @@ enum { PW_BC_EXACT = 0, PW_BC_SOMMERFELD = 1 };        /* outer boundary of the 
  *                    the origin (every field, asymptotic value 0; 4th-order centred
  *                    derivatives along interior axes, 2nd-order one-sided inward along
  *                    ghost axes).  They start from the PW_BC_EXACT value at the first
- *                    step after the state is set.  Needs a non-periodic global patch.
+ *                    step after the state is set.  Needs a non-periodic Cartesian global patch.
  */
 typedef struct {
   int32_t precision;
@@ -125,7 +125,7 @@ typedef struct {
  * Patch description (Secs. 2.1 and 2.4.1): numerical box [lo,hi] of n cells per axis
  * (cell-centred), topology map M (Cartesian identity; spherical x' = (r,theta,phi),
  * M = r (sin th cos ph, sin th sin ph, cos th); cylindrical x' = (r,phi,z),
- * M = (r cos ph, r sin ph, z); Secs. 2.1 and 3.4),
+ * M = (r cos ph, r sin ph, z); Secs. 2.1, 3.3 and 3.4),
  * orientation R(t) and centre motion c(t), so that the background Cartesian
  * coordinates are X_B = c(t) + R(t) M(x').
  *   motion PW_STATIC: c = c0; PW_LINEAR: c = c0 + vel t;
@@ -138,8 +138,12 @@ typedef struct {
  *          patch keeps its ghosts off r = 0 (and a spherical one off the poles);
  *          phi values of a non-periodic phi axis lie in (-pi, pi].
  *   sv_mask: bit s set if the patch carries state vector s.
- * The first patch created must be the global one (is_global = 1, Cartesian, static,
- * unrotated, no spin); every later patch is a local patch.
+ * The first patch created must be the global one (is_global = 1, static, unrotated,
+ * centred at the origin, no spin): Cartesian, or spherical with phi as its only
+ * periodic axis (Sec. 3.4).  Every later patch is a local patch.  Local patches may
+ * overlap where the global cells stay live (in the buffers); a global cell covered
+ * by two local patches keeps the lower id, and an overlap that reaches a non-live
+ * global cell is PW_EOVERLAP.
  */
 typedef struct {
   int32_t coord;

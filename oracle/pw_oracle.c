@@ -22,7 +22,7 @@
  *   - plane-wave exact solution, analytic outer BCs         (Sec. 3, Eq. wave_solution)
  *   - integrated relative error with the volume element    (Sec. 3.2)
  *   - Cartesian, spherical and cylindrical patch topologies,
- *     translating, circling and rotating patches            (Secs. 2.1, 3.4)
+ *     translating, circling and rotating patches            (Secs. 2.1, 3.2-3.4)
  *
  * Readings where the paper is silent or garbled (KO normalisation, mixed
  * derivative stencil, cell-centred grids, Chebyshev neighbourhoods for the
@@ -816,6 +816,9 @@ static void fill_ghosts(or_world *w, int which, double t) {
             int cw[3];
             for (int a = 0; a < 3; a++) cw[a] = p->periodic[a] ? wrapi(c[a], p->n[a]) : c[a];
             if (is_interior(p, cw)) {
+              /* a periodic global patch with local patches copies after the
+               * interpatch fill, so its copies carry the effective ghosts' values */
+              if (p->is_global && w->np > 1) continue;
               for (int f = 0; f < NF; f++) T[IX(p, f, i, j, k)] = T[IX(p, f, cw[0], cw[1], cw[2])];
             } else if (p->is_global && w->outer_bc == 1) {
               continue; /* evolved by the radiative condition */
@@ -843,6 +846,21 @@ static void fill_ghosts(or_world *w, int which, double t) {
   } else {
     fill_l2g(w, which, t, &sk_e);
     fill_g2l(w, which, t, &sk_l);
+  }
+  /* periodic copies of the global patch (a spherical global's phi axis) */
+  or_patch *g = &w->p[0];
+  for (int sv = 0; sv < w->nsv; sv++) {
+    if (!(g->sv_mask & (1u << sv))) continue;
+    double *T = bufsel(g, sv, which);
+    for (int k = -NG; k < g->n[2] + NG; k++)
+      for (int j = -NG; j < g->n[1] + NG; j++)
+        for (int i = -NG; i < g->n[0] + NG; i++) {
+          int c[3] = {i, j, k}, cw[3];
+          if (is_interior(g, c)) continue;
+          for (int a = 0; a < 3; a++) cw[a] = g->periodic[a] ? wrapi(c[a], g->n[a]) : c[a];
+          if (!is_interior(g, cw)) continue;
+          for (int f = 0; f < NF; f++) T[IX(g, f, i, j, k)] = T[IX(g, f, cw[0], cw[1], cw[2])];
+        }
   }
   w->skip_local += sk_l;
   w->skip_eff += sk_e;

@@ -40,6 +40,7 @@ struct pw_context {
   // flags of the global patch
   long long gcells = 0;
   uint8_t *flag_cur = nullptr, *flag_new = nullptr, *t1 = nullptr, *t2 = nullptr, *live = nullptr;
+  uint8_t *dbl = nullptr;  // cells claimed by two local patches (k_cover)
   int32_t *cover_cur = nullptr, *cover_new = nullptr;
   // lists
   GhostRec *dLower = nullptr;
@@ -67,7 +68,7 @@ struct pw_context {
   int nTiles = 0;
   std::vector<int> tileOff, tileCnt;
   int nGlobalTiles = 0;
-  int coordTiles[4] = {0, 0, 0, 0};  // tiles grouped by topology: group t is [coordTiles[t], coordTiles[t+1])
+  int coordTiles[4] = {0, 0, 0, 0};  // local-patch tiles by topology: group t is [coordTiles[t], coordTiles[t+1])
   CoverJob *dJobs = nullptr;
   int nJobs = 0, coverBlocks = 1;
   double *dStage = nullptr;  // staging for host copies
@@ -351,23 +352,27 @@ pw_status upload_layout(pw_context *c) {
   std::vector<TileRec> tiles;
   c->tileOff.assign(np, 0);
   c->tileCnt.assign(np, 0);
+  // the global patch's tiles first, then those of the local patches grouped
+  // by topology (Cartesian, spherical, cylindrical)
+  auto add_tiles = [&](int pid) {
+    const PatchDev &p = c->hp[pid];
+    c->tileOff[pid] = (int)tiles.size();
+    const int TX = pid == 0 ? StageTile<true>::TX : StageTile<false>::TX;
+    const int TY = pid == 0 ? StageTile<true>::TY : StageTile<false>::TY;
+    const int TZ = pid == 0 ? c->tune.tile_z_global : c->tune.tile_z_local;
+    for (int z = 0; z < p.n[2]; z += TZ)
+      for (int y = 0; y < p.n[1]; y += TY)
+        for (int x = 0; x < p.n[0]; x += TX) tiles.push_back(TileRec{pid, x, y, z, std::min(TZ, p.n[2] - z)});
+    c->tileCnt[pid] = (int)tiles.size() - c->tileOff[pid];
+  };
+  add_tiles(0);
+  c->nGlobalTiles = c->tileCnt[0];
   for (int t = 0; t < 3; t++) {
     c->coordTiles[t] = (int)tiles.size();
-    for (int pid = 0; pid < np; pid++) {
-      const PatchDev &p = c->hp[pid];
-      if (p.coord != t) continue;
-      c->tileOff[pid] = (int)tiles.size();
-      const int TX = pid == 0 ? StageTile<true>::TX : StageTile<false>::TX;
-      const int TY = pid == 0 ? StageTile<true>::TY : StageTile<false>::TY;
-      const int TZ = pid == 0 ? c->tune.tile_z_global : c->tune.tile_z_local;
-      for (int z = 0; z < p.n[2]; z += TZ)
-        for (int y = 0; y < p.n[1]; y += TY)
-          for (int x = 0; x < p.n[0]; x += TX) tiles.push_back(TileRec{pid, x, y, z, std::min(TZ, p.n[2] - z)});
-      c->tileCnt[pid] = (int)tiles.size() - c->tileOff[pid];
-    }
+    for (int pid = 1; pid < np; pid++)
+      if (c->hp[pid].coord == t) add_tiles(pid);
   }
   c->coordTiles[3] = (int)tiles.size();
-  c->nGlobalTiles = c->tileCnt[0];  // the global patch is Cartesian and comes first
   dfree(c, c->dTiles);
   c->nTiles = (int)tiles.size();
   c->dTiles = (TileRec *)dalloc(c, sizeof(TileRec) * tiles.size());
@@ -384,7 +389,8 @@ pw_status upload_layout(pw_context *c) {
     J.radius = bound_radius(c->desc[pid]) * (1.0 + 1e-12) + 1e-12;
     long long tot = 1;
     for (int a = 0; a < 3; a++) {
-      J.ext[a] = (int)ceil(2.0 * J.radius * g.idx[a]) + 3;
+      // a curvilinear global is scanned whole (its index box of a sphere is not simple)
+      J.ext[a] = g.coord == CART ? (int)ceil(2.0 * J.radius * g.idx[a]) + 3 : g.n[a];
       tot *= J.ext[a];
     }
     maxcells = std::max(maxcells, tot);
@@ -426,7 +432,11 @@ void enqueue_flags(pw_context *c, const PoseDev *pose_slot, hipStream_t st) {
   a.t2 = c->t2;
   a.live = c->live;
   a.flag_new = c->flag_new;
-  for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
+  for (int d = 0; d < 3; d++) {
+    a.n[d] = c->hp[0].n[d];
+    a.wrap[d] = c->hp[0].periodic[d];
+  }
+  a.dbl = c->dbl;
   a.buffer = c->cfg.buffer_width;
   a.err = c->dErr;
   launch_flags(st, a);
@@ -448,7 +458,10 @@ void enqueue_post_flags(pw_context *c, const PoseDev *pose_slot, hipStream_t st)
   a.donor_effghost = narrow_buffer(c);
   a.t1 = c->t1;
   a.t2 = c->t2;
-  for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
+  for (int d = 0; d < 3; d++) {
+    a.n[d] = c->hp[0].n[d];
+    a.wrap[d] = c->hp[0].periodic[d];
+  }
   launch_post_flags(st, a);
   L2GOrderArgs o;
   o.P = c->dP;
@@ -523,17 +536,18 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.g2l_run = c->tune.g2l_run;
     a.l2g_run = c->tune.l2g_run;
     a.l2g_first = narrow_buffer(c);
+    a.global_curv = c->hp[0].coord != CART;
+    a.gflag = c->flag_cur;
     launch_ghosts(st, a);
   }
 }
 
 // One stage launch per topology over the tiles of all local patches of that
-// topology (the global patch's tiles lead the Cartesian group).
+// topology.
 void launch_local_groups(pw_context *c, StageArgs a, hipStream_t st) {
   for (int t = 0; t < 3; t++) {
-    const int b = t == CART ? c->nGlobalTiles : c->coordTiles[t];
-    a.tiles = c->dTiles + b;
-    a.ntiles = c->coordTiles[t + 1] - b;
+    a.tiles = c->dTiles + c->coordTiles[t];
+    a.ntiles = c->coordTiles[t + 1] - c->coordTiles[t];
     a.coord = t;
     launch_stage(st, a);
   }
@@ -575,7 +589,7 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
         Timed tg(c, PW_K_GSTAGE_S1 + stage);
         a.tiles = c->dTiles;
         a.ntiles = c->nGlobalTiles;
-        a.coord = CART;
+        a.coord = c->hp[0].coord;
         a.global = 1;
         launch_stage(c->stream, a);
       }
@@ -605,7 +619,7 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
       if (!(c->hp[0].sv_mask & (1u << sv))) continue;
       a.tiles = c->dTiles;
       a.ntiles = c->nGlobalTiles;
-      a.coord = CART;
+      a.coord = c->hp[0].coord;
       a.global = 1;
       launch_stage(st, a);
       launch_radiative(st, c->dP, c->dRad, c->nRad, sv, stage, a.mixed, a.inc, dt, c->cfg.wave_speed[sv]);
@@ -852,12 +866,15 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
   if (d->motion < PW_STATIC || d->motion > PW_CIRCLE) return fail(c, PW_EINVAL, "unknown motion");
   if (d->motion == PW_CIRCLE && !(d->radius > 0)) return fail(c, PW_EINVAL, "circle motion needs radius > 0");
   if (first) {
-    if (d->coord != PW_CART || d->motion != PW_STATIC || d->euler_zyz[0] != 0 || d->euler_zyz[1] != 0 ||
-        d->euler_zyz[2] != 0 || d->c0[0] != 0 || d->c0[1] != 0 || d->c0[2] != 0 || d->spin[0] != 0 ||
-        d->spin[1] != 0 || d->spin[2] != 0)
-      return fail(c, PW_EINVAL, "the global patch is Cartesian, static and unrotated");
-    if (c->cfg.outer_bc == PW_BC_SOMMERFELD && (d->periodic[0] || d->periodic[1] || d->periodic[2]))
-      return fail(c, PW_EINVAL, "the Sommerfeld outer boundary needs a non-periodic global patch");
+    if ((d->coord != PW_CART && d->coord != PW_SPH) || d->motion != PW_STATIC || d->euler_zyz[0] != 0 ||
+        d->euler_zyz[1] != 0 || d->euler_zyz[2] != 0 || d->c0[0] != 0 || d->c0[1] != 0 || d->c0[2] != 0 ||
+        d->spin[0] != 0 || d->spin[1] != 0 || d->spin[2] != 0)
+      return fail(c, PW_EINVAL, "the global patch is Cartesian or spherical, static, unrotated and at the origin");
+    if (d->coord == PW_SPH && (d->periodic[0] || d->periodic[1]))
+      return fail(c, PW_EINVAL, "a spherical global patch is periodic only along phi");
+    if (c->cfg.outer_bc == PW_BC_SOMMERFELD &&
+        (d->coord != PW_CART || d->periodic[0] || d->periodic[1] || d->periodic[2]))
+      return fail(c, PW_EINVAL, "the Sommerfeld outer boundary needs a non-periodic Cartesian global patch");
   } else {
     const int phi_axis = d->coord == PW_SPH ? 2 : d->coord == PW_CYL ? 1 : -1;
     for (int a = 0; a < 3; a++)
@@ -865,8 +882,8 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
         return fail(c, PW_EINVAL, "local patches are periodic only along a spherical or cylindrical phi axis");
     if (d->coord != PW_CART && !(d->lo[0] > 0)) return fail(c, PW_EINVAL, "curvilinear patch needs r_min > 0");
     const PatchDev &g = c->hp[0];
-    if (g.periodic[0] || g.periodic[1] || g.periodic[2])
-      return fail(c, PW_EINVAL, "local patches need a non-periodic global patch");
+    if (g.coord == CART && (g.periodic[0] || g.periodic[1] || g.periodic[2]))
+      return fail(c, PW_EINVAL, "local patches need a non-periodic Cartesian global patch");
   }
   if (d->coord == PW_SPH) {
     double th_lo = d->lo[1] - PW_NG * (d->hi[1] - d->lo[1]) / d->n[1];
@@ -950,6 +967,7 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     c->gcells = (long long)p.n[0] * p.n[1] * p.n[2];
     c->flag_cur = (uint8_t *)dalloc(c, c->gcells);
     c->flag_new = (uint8_t *)dalloc(c, c->gcells);
+    c->dbl = (uint8_t *)dalloc(c, c->gcells);
     c->t1 = (uint8_t *)dalloc(c, c->gcells);
     c->t2 = (uint8_t *)dalloc(c, c->gcells);
     c->live = (uint8_t *)dalloc(c, c->gcells);
@@ -967,7 +985,7 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
       c->dvalid[m] = used ? (uint8_t *)dalloc(c, c->gcells) : nullptr;
       if (used && !c->dvalid[m]) return fail(c, PW_ENOMEM, "device allocation failed");
     }
-    if (!c->flag_cur || !c->flag_new || !c->t1 || !c->t2 || !c->live || !c->cover_cur || !c->cover_new ||
+    if (!c->flag_cur || !c->flag_new || !c->dbl || !c->t1 || !c->t2 || !c->live || !c->cover_cur || !c->cover_new ||
         !c->efflist || !c->effcount)
       return fail(c, PW_ENOMEM, "device allocation failed");
     launch_fill_u8(c->stream, c->flag_cur, c->gcells, LIVE);
@@ -1147,6 +1165,8 @@ pw_status pw_rk4_step(pw_context *c, double dt, int32_t nsteps) {
   // The NG+1 buffer lets a patch cross at most one global cell per step.
   const PatchDev &g = c->hp[0];
   double hmin = std::min(g.dx[0], std::min(g.dx[1], g.dx[2]));
+  if (g.coord == SPH)  // smallest physical cell edge of a spherical shell
+    hmin = std::min(g.dx[0], g.lo[0] * std::min(g.dx[1], std::min(sin(g.lo[1]), sin(g.hi[1])) * g.dx[2]));
   for (size_t pid = 1; pid < c->hp.size(); pid++) {
     const pw_patch_desc &d = c->desc[pid];
     double sp = 0;

@@ -368,6 +368,18 @@ __device__ inline void bg_to_patch_grid(const PatchDev &p, const PoseDev &ps, co
   bg_to_patch_b(p, ps, B, y, pit, G, out);
 }
 
+// Background position of cell (i,j,k) of the global patch, which is static and
+// unrotated at the origin: a Cartesian global's numerical coordinates are X,
+// a spherical global maps through its angle tables.
+__device__ inline void global_X(const PatchDev &g, const PoseDev &ps0, int i, int j, int k, double X[3]) {
+  if (g.coord == CART) {
+    X[0] = xnum(g, 0, i); X[1] = xnum(g, 1, j); X[2] = xnum(g, 2, k);
+  } else {
+    const int c[3] = {i, j, k};
+    fwd_map_grid(g, ps0, c, X);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Exact solutions in the background frame: phi, d_t phi, grad phi.
 // ---------------------------------------------------------------------------

@@ -70,6 +70,7 @@ struct PostFlagsArgs {
   int donor_effghost;  // narrow buffer: effective ghosts count as valid donors
   uint8_t *t1, *t2;
   int n[3];
+  int wrap[3];  // periodic axes of the global patch
 };
 
 struct L2GOrderArgs {
@@ -92,9 +93,11 @@ struct FlagsArgs {
   int njobs, cover_blocks;
   int32_t *cover_new;
   uint8_t *t1, *t2, *live, *flag_new;
+  uint8_t *dbl;  // cells claimed by two local patches
   int n[3];
+  int wrap[3];   // periodic axes of the global patch
   int buffer;
-  int *err;
+  int *err;      // set if an overlap reaches a non-live cell
 };
 
 struct FinalizeArgs {
@@ -141,6 +144,8 @@ struct GhostArgs {
   int *fb_count;
   int g2l_run, l2g_run;  // consecutive bricks / groups per XCD run
   int l2g_first;         // narrow buffer: local->global (and its fallbacks) before global->local
+  int global_curv;       // curvilinear global patch: one-point-per-thread interpatch kernels
+  const uint8_t *gflag;  // cover flags of the global patch (donor test of those kernels)
 };
 
 struct StageArgs {

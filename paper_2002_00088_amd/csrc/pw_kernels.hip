@@ -49,9 +49,11 @@ __global__ void k_advance_time(double *tdev, double dt, long long *counters) {
 // cover[c] = id of the local patch whose closed numerical box contains the
 // centre of global cell c (Sec. 2.4.2: the covered test is done in the local
 // patch's numerical coordinates).  Each local patch scans the global cells of
-// the axis-aligned box around its bounding sphere.
+// the axis-aligned box around its bounding sphere (a Cartesian global), or all
+// global cells (a curvilinear global: the host sets the extents to the grid).
+// A cell claimed by two patches keeps the lower id and is marked in dbl.
 __global__ void k_cover(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const CoverJob *jobs, int njobs, int32_t *cover,
-                        int *err) {
+                        uint8_t *dbl) {
   const CoverJob J = jobs[blockIdx.y];
   const PatchDev &g = P[0];
   const PatchDev &p = P[J.patch];
@@ -59,7 +61,7 @@ __global__ void k_cover(const PatchDev *__restrict__ P, const PoseDev *__restric
   int lo[3], ext[3];
   for (int a = 0; a < 3; a++) {
     double c = (ps.c[a] - J.radius - g.lo[a]) * g.idx[a] - 0.5;
-    lo[a] = (int)floor(c);
+    lo[a] = g.coord == CART ? (int)floor(c) : 0;
     ext[a] = J.ext[a];
   }
   long long total = (long long)ext[0] * ext[1] * ext[2];
@@ -68,7 +70,10 @@ __global__ void k_cover(const PatchDev *__restrict__ P, const PoseDev *__restric
     int j = lo[1] + (int)((q / ext[0]) % ext[1]);
     int k = lo[2] + (int)(q / ((long long)ext[0] * ext[1]));
     if (i < 0 || j < 0 || k < 0 || i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) continue;
-    double X[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)}, xp[3];
+    double X[3], xp[3];
+    global_X(g, pose[0], i, j, k, X);
+    const double d0 = X[0] - ps.c[0], d1 = X[1] - ps.c[1], d2 = X[2] - ps.c[2];
+    if (d0 * d0 + d1 * d1 + d2 * d2 > J.radius * J.radius) continue;
     inv_map(p, ps, X, xp);
     bool in = true;
     for (int a = 0; a < 3; a++) {
@@ -78,7 +83,10 @@ __global__ void k_cover(const PatchDev *__restrict__ P, const PoseDev *__restric
     if (!in) continue;
     long long c = ((long long)k * g.n[1] + j) * g.n[0] + i;
     int old = atomicCAS(&cover[c], -1, J.patch);
-    if (old != -1 && old != J.patch) atomicExch(err, 1);
+    if (old != -1 && old != J.patch) {
+      dbl[c] = 1;
+      atomicMin(&cover[c], J.patch);
+    }
   }
 }
 
@@ -86,7 +94,7 @@ __global__ void k_cover(const PatchDev *__restrict__ P, const PoseDev *__restric
 // cells outside the domain read as `oob`.  With SRC_COVER the input is
 // "uncovered" = (cover == -1).
 template <int AXIS, bool SRC_COVER>
-__global__ void k_dilate(const void *in_, uint8_t *out, int n0, int n1, int n2, int R, int oob) {
+__global__ void k_dilate(const void *in_, uint8_t *out, int n0, int n1, int n2, int R, int oob, int wrap) {
   long long total = (long long)n0 * n1 * n2;
   long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= total) return;
@@ -97,13 +105,14 @@ __global__ void k_dilate(const void *in_, uint8_t *out, int n0, int n1, int n2, 
   int m = 0;
   for (int d = -R; d <= R; d++) {
     int q = pos + d;
+    if (wrap) q = ((q % len) + len) % len;  // periodic axis of the global patch
     int v;
     if (q < 0 || q >= len) {
       v = oob;
     } else if (SRC_COVER) {
-      v = ((const int32_t *)in_)[c + d * stride] == -1;
+      v = ((const int32_t *)in_)[c + (long long)(q - pos) * stride] == -1;
     } else {
-      v = ((const uint8_t *)in_)[c + d * stride];
+      v = ((const uint8_t *)in_)[c + (long long)(q - pos) * stride];
     }
     m = v > m ? v : m;
   }
@@ -111,10 +120,14 @@ __global__ void k_dilate(const void *in_, uint8_t *out, int n0, int n1, int n2, 
 }
 
 // flag = live ? LIVE : (near a live cell ? EFFGHOST : DEACT)
-__global__ void k_combine_flags(const uint8_t *live, const uint8_t *near, uint8_t *flag, long long total) {
+// A cell covered by two local patches must stay live (overlap only in the
+// buffers); otherwise the overlap error is raised.
+__global__ void k_combine_flags(const uint8_t *live, const uint8_t *near, const uint8_t *dbl, uint8_t *flag,
+                                long long total, int *err) {
   long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= total) return;
   flag[c] = live[c] ? LIVE : (near[c] ? EFFGHOST : DEACT);
+  if (dbl[c] && !live[c]) err[0] = 1;
 }
 
 // Tensor-product Lagrange interpolation of the 5 fields of buffer T of donor
@@ -123,7 +136,7 @@ __global__ void k_combine_flags(const uint8_t *live, const uint8_t *near, uint8_
 // periodic axes).  Returns false if the point cannot be interpolated.
 template <typename TB, typename TC>
 __device__ inline bool interp5(const PatchDev &p, const TB *T, const uint8_t *gflag, int P, const double xd[3],
-                               TC out[5]) {
+                               TC out[5], bool effghost_ok = false) {
   double wx[8], wy[8], wz[8];
   int s[3];
   double q[3];
@@ -137,12 +150,17 @@ __device__ inline bool interp5(const PatchDev &p, const TB *T, const uint8_t *gf
   for (int a = 0; a < 3; a++)
     if (!p.periodic[a] && (s[a] < 0 || s[a] + P - 1 > p.n[a] - 1)) return false;
   if (p.is_global && gflag) {
-    for (int c = 0; c < P; c++)
-      for (int b = 0; b < P; b++)
+    for (int c = 0; c < P; c++) {
+      const int kk = p.periodic[2] ? ((s[2] + c) % p.n[2] + p.n[2]) % p.n[2] : s[2] + c;
+      for (int b = 0; b < P; b++) {
+        const int jj = p.periodic[1] ? ((s[1] + b) % p.n[1] + p.n[1]) % p.n[1] : s[1] + b;
         for (int a = 0; a < P; a++) {
-          long long gi = ((long long)(s[2] + c) * p.n[1] + (s[1] + b)) * p.n[0] + (s[0] + a);
-          if (gflag[gi] != LIVE) return false;
+          const int ii = p.periodic[0] ? ((s[0] + a) % p.n[0] + p.n[0]) % p.n[0] : s[0] + a;
+          const uint8_t fl = gflag[((long long)kk * p.n[1] + jj) * p.n[0] + ii];
+          if (effghost_ok ? fl == DEACT : fl != LIVE) return false;
         }
+      }
+    }
   }
   for (int f = 0; f < 5; f++) out[f] = (TC)0;
   for (int c = 0; c < P; c++) {
@@ -188,6 +206,93 @@ __device__ inline bool interp_transform(const PatchDev &d, const PoseDev &psd, c
   out[0] = (double)v[0];
   for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
   return true;
+}
+
+// Interpatch fills with a curvilinear global patch, one thread per point:
+// the stencils gather straight from global memory (periodic axes wrap), so no
+// donor box has to be contiguous in the global's index space.
+// Global -> local: the ghost cells of the brick list.
+template <typename TB, typename TC>
+__global__ __launch_bounds__(BRICK_THREADS) void k_g2l_point(const PatchDev *__restrict__ P,
+                                                             const PoseDev *__restrict__ pose, const GBrick *bricks,
+                                                             int nbricks, int sv, int stage, const uint8_t *gflag,
+                                                             int effghost_ok, int Pts, unsigned long long *skips,
+                                                             FallbackRec *fb, int *fb_count) {
+  const int bidx = blockIdx.x;
+  if (bidx >= nbricks) return;
+  const GBrick B = bricks[bidx];
+  const PatchDev &r = P[B.patch];
+  const PatchDev &G0 = P[0];
+  const int tid = threadIdx.x;
+  if (tid >= B.di * B.dj * B.dk) return;
+  const int c[3] = {B.i0 + tid % B.di, B.j0 + (tid / B.di) % B.dj, B.k0 + tid / (B.di * B.dj)};
+  bool inside = true, winside = true;
+  for (int a = 0; a < 3; a++) {
+    inside = inside && c[a] >= 0 && c[a] < r.n[a];
+    const int w = r.periodic[a] ? ((c[a] % r.n[a]) + r.n[a]) % r.n[a] : c[a];
+    winside = winside && w >= 0 && w < r.n[a];
+  }
+  if (!(r.sv_mask & (1u << sv)) || inside || winside) return;
+  const bool has_donor = (G0.sv_mask & (1u << sv)) != 0;
+  bool ok = false;
+  double out[5];
+  if (has_donor) {
+    double X[3], xd[3];
+    fwd_map_grid(r, pose[B.patch], c, X);
+    inv_map(G0, pose[0], X, xd);
+    TC v[5];
+    if (interp5<TB, TC>(G0, stage_buf<TB>(G0, sv, stage), gflag, Pts, xd, v, effghost_ok != 0)) {
+      double in4[4] = {(double)v[1], (double)v[2], (double)v[3], (double)v[4]}, G[3], pit, o4[4];
+      patch_to_bg(G0, pose[0], xd, in4, pit, G);
+      bg_to_patch_grid(r, pose[B.patch], c, pit, G, o4);
+      out[0] = (double)v[0];
+      for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
+      ok = true;
+    }
+  }
+  if (!ok) {
+    if (has_donor) atomicAdd(skips, 1ull);
+    const int slot = atomicAdd(fb_count, 1);
+    fb[slot] = FallbackRec{B.patch, 0, (uint32_t)((c[0] + PW_NG) | ((c[1] + PW_NG) << 10) | ((c[2] + PW_NG) << 20))};
+    return;
+  }
+  TB *TR = stage_buf<TB>(r, sv, stage);
+  const long long dst = cell_index(r, c[0], c[1], c[2]);
+  for (int f = 0; f < 5; f++) TR[f * r.fstride + dst] = (TB)out[f];
+}
+
+// Local -> global: the effective ghosts of the global patch.
+template <typename TB, typename TC>
+__global__ void k_l2g_point(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list,
+                            const int *count, const int32_t *cover, int sv, int stage, int Pts,
+                            unsigned long long *skips, FallbackRec *fb, int *fb_count) {
+  const PatchDev &G0 = P[0];
+  if (!(G0.sv_mask & (1u << sv))) return;
+  const int n = count[0];
+  TB *TG = stage_buf<TB>(G0, sv, stage);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const long long c = list[q];
+    const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]),
+              k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
+    const int d = cover[c];
+    double out[5];
+    bool ok = false;
+    if (d >= 1 && (P[d].sv_mask & (1u << sv))) {
+      const double xr[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
+      double X[3];
+      global_X(G0, pose[0], i, j, k, X);
+      ok = interp_transform<TB, TC>(P[d], pose[d], stage_buf<TB>(P[d], sv, stage), nullptr, Pts, X, G0, pose[0], xr,
+                                    out);
+    }
+    if (ok) {
+      const long long dst = cell_index(G0, i, j, k);
+      for (int f = 0; f < 5; f++) TG[f * G0.fstride + dst] = (TB)out[f];
+    } else {
+      atomicAdd(skips, 1ull);
+      const int slot = atomicAdd(fb_count, 1);
+      fb[slot] = FallbackRec{0, 1, (uint32_t)c};
+    }
+  }
 }
 
 __device__ inline void unpack_ijk(uint32_t c, int &i, int &j, int &k) {
@@ -239,7 +344,8 @@ __global__ void k_fill_lower(const PatchDev *__restrict__ P, const PoseDev *__re
 // cells beyond the domain read 0.  Applied along x (from the flags, LIVE -> 1),
 // y and z it gives dvalid[c] = 1 iff the P^3 donor box starting at c is all live.
 template <int AXIS>
-__global__ void k_window_min(const uint8_t *in, uint8_t *out, int n0, int n1, int n2, int P, int from_flags) {
+__global__ void k_window_min(const uint8_t *in, uint8_t *out, int n0, int n1, int n2, int P, int from_flags,
+                             int wrap) {
   long long total = (long long)n0 * n1 * n2;
   long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= total) return;
@@ -250,9 +356,12 @@ __global__ void k_window_min(const uint8_t *in, uint8_t *out, int n0, int n1, in
   int m = 1;
   for (int d = 0; d < P; d++) {
     int v = 0;
-    if (pos + d < len)
-      v = from_flags == 1 ? (in[c + d * stride] == LIVE)
-                          : (from_flags == 2 ? (in[c + d * stride] != DEACT) : in[c + d * stride]);
+    int q = pos + d;
+    if (wrap) q = q % len;  // periodic axis of the global patch
+    if (q < len) {
+      const uint8_t x = in[c + (long long)(q - pos) * stride];
+      v = from_flags == 1 ? (x == LIVE) : (from_flags == 2 ? (x != DEACT) : x);
+    }
     m = v < m ? v : m;
   }
   out[c] = (uint8_t)m;
@@ -330,7 +439,8 @@ __global__ void k_bucket_count(const PatchDev *__restrict__ P, const PoseDev *__
     int b = 0;
     if (d >= 1) {
       const PatchDev &D = P[d];
-      double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)}, xd[3];
+      double X[3], xd[3];
+      global_X(G0, pose[0], i, j, k, X);
       inv_map(D, pose[d], X, xd);
       int bi[3];
       for (int a = 0; a < 3; a++) {
@@ -1000,16 +1110,18 @@ __device__ inline void finalize_cell(const PatchDev *__restrict__ P, const PoseD
   if (mode == 1 && fo != LIVE && fn == LIVE) {
     int d = cn >= 1 ? cn : co;
     const PatchDev &D = P[d >= 1 ? d : 0];
-    double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
+    const double xr[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
+    double X[3];
+    global_X(G0, pose[0], i, j, k, X);
     atomicAdd(&counters[3], 1ull);
     for (int sv = 0; sv < nsv; sv++) {
       if (!(G0.sv_mask & (1u << sv))) continue;
       double out[5];
       bool ok = d >= 1 && (D.sv_mask & (1u << sv)) &&
-                interp_transform<double, double>(D, pose[d], D.u[sv], nullptr, Pts[sv], X, G0, pose[0], X, out);
+                interp_transform<double, double>(D, pose[d], D.u[sv], nullptr, Pts[sv], X, G0, pose[0], xr, out);
       if (!ok) {
         atomicAdd(&counters[2], 1ull);
-        if (ex[sv].kind != EX_NONE) exact_patch(ex[sv], vs[sv], G0, pose[0], tdev[0], X, out);
+        if (ex[sv].kind != EX_NONE) exact_patch(ex[sv], vs[sv], G0, pose[0], tdev[0], xr, out);
         else for (int f = 0; f < 5; f++) out[f] = NAN;
       }
       for (int f = 0; f < 5; f++) G0.u[sv][f * G0.fstride + x] = out[f];
@@ -1761,25 +1873,26 @@ void launch_advance_time(hipStream_t s, double *tdev, double dt, long long *coun
 
 void launch_flags(hipStream_t s, const FlagsArgs &a) {
   const int bs = 256;
-  if (a.njobs > 0)
-    hipLaunchKernelGGL(k_cover, dim3(a.cover_blocks, a.njobs), dim3(bs), 0, s, a.P, a.pose, a.jobs, a.njobs,
-                       a.cover_new, a.err);
   long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
   unsigned nb = nblk(tot, bs);
+  hipLaunchKernelGGL(k_fill_value<uint8_t>, dim3(nb < 4096 ? nb : 4096), dim3(bs), 0, s, a.dbl, tot, (uint8_t)0);
+  if (a.njobs > 0)
+    hipLaunchKernelGGL(k_cover, dim3(a.cover_blocks, a.njobs), dim3(bs), 0, s, a.P, a.pose, a.jobs, a.njobs,
+                       a.cover_new, a.dbl);
   hipLaunchKernelGGL((k_dilate<0, true>), dim3(nb), dim3(bs), 0, s, (const void *)a.cover_new, a.t1, a.n[0], a.n[1],
-                     a.n[2], a.buffer, 1);
+                     a.n[2], a.buffer, 1, a.wrap[0]);
   hipLaunchKernelGGL((k_dilate<1, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t1, a.t2, a.n[0], a.n[1], a.n[2],
-                     a.buffer, 1);
+                     a.buffer, 1, a.wrap[1]);
   hipLaunchKernelGGL((k_dilate<2, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t2, a.live, a.n[0], a.n[1],
-                     a.n[2], a.buffer, 1);
+                     a.n[2], a.buffer, 1, a.wrap[2]);
   hipLaunchKernelGGL((k_dilate<0, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.live, a.t1, a.n[0], a.n[1],
-                     a.n[2], PW_NG, 0);
+                     a.n[2], PW_NG, 0, a.wrap[0]);
   hipLaunchKernelGGL((k_dilate<1, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t1, a.t2, a.n[0], a.n[1], a.n[2],
-                     PW_NG, 0);
+                     PW_NG, 0, a.wrap[1]);
   hipLaunchKernelGGL((k_dilate<2, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t2, a.t1, a.n[0], a.n[1], a.n[2],
-                     PW_NG, 0);
+                     PW_NG, 0, a.wrap[2]);
   hipLaunchKernelGGL(k_combine_flags, dim3(nb), dim3(bs), 0, s, (const uint8_t *)a.live, (const uint8_t *)a.t1,
-                     a.flag_new, tot);
+                     (const uint8_t *)a.dbl, a.flag_new, tot, a.err);
 }
 
 void launch_l2g_order(hipStream_t s, const L2GOrderArgs &a) {
@@ -1808,11 +1921,24 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
   const int l1 = (a.parts & GH_LOCAL) ? a.n_lower : a.n_lower_global;
   const bool g2l = a.n_bricks > 0 && (a.parts & GH_LOCAL);
   const bool l2g = a.has_locals && (a.parts & GH_GLOBAL);
-  if (l1 > l0)
-    hipLaunchKernelGGL(k_fill_lower<TB>, dim3(nblk(l1 - l0, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower + l0, l1 - l0,
-                       a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
-  if (!g2l && !l2g) return;
+  // the lower-priority fill (outer ghosts, periodic copies) comes last: the
+  // periodic copies of a spherical global then carry the effective ghosts'
+  // interpolated values; nothing in the interpatch fills reads these cells
+  auto lower = [&]() {
+    if (l1 > l0)
+      hipLaunchKernelGGL(k_fill_lower<TB>, dim3(nblk(l1 - l0, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower + l0,
+                         l1 - l0, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
+  };
+  if (!g2l && !l2g) {
+    lower();
+    return;
+  }
   auto run_g2l = [&]() {
+    if (a.global_curv) {
+      hipLaunchKernelGGL((k_g2l_point<TB, TC>), dim3(a.n_bricks), dim3(BRICK_THREADS), 0, s, a.P, a.pose, a.bricks,
+                         a.n_bricks, a.sv, a.stage, a.gflag, a.l2g_first, a.Pts, a.skips, a.fb, a.fb_count);
+      return;
+    }
     const int run = a.g2l_run;
     const int bchunk = (a.n_bricks + 8 * run - 1) / (8 * run);
     const dim3 g(8 * run * bchunk), b(BRICK_THREADS);
@@ -1829,6 +1955,11 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
 #undef PW_G2L
   };
   auto run_l2g = [&]() {
+    if (a.global_curv) {
+      hipLaunchKernelGGL((k_l2g_point<TB, TC>), dim3(1024), dim3(256), 0, s, a.P, a.pose, a.efflist, a.effcount,
+                         a.cover, a.sv, a.stage, a.Pts, a.skips + 1, a.fb, a.fb_count);
+      return;
+    }
     const dim3 g(L2G_BLOCKS), b(64 * L2G_WAVES);
 #define PW_L2G(PP)                                                                                                \
   hipLaunchKernelGGL((k_l2g_box<TB, TC, PP>), g, b, 0, s, a.P, a.pose, a.efflist, a.effcount, a.l2g_run, a.cover, a.sv, \
@@ -1855,12 +1986,14 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
     run_g2l();
     fallback();
+    lower();
     return;
   }
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
   if (g2l) run_g2l();
   if (l2g) run_l2g();
   fallback();
+  lower();
 }
 
 void launch_ghosts(hipStream_t s, const GhostArgs &a) {
@@ -1884,11 +2017,11 @@ void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
     if (!a.dvalid[m]) continue;
     int P = a.Pvals[m];
     hipLaunchKernelGGL(k_window_min<0>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.flag, a.t1, a.n[0], a.n[1],
-                       a.n[2], P, a.donor_effghost ? 2 : 1);
+                       a.n[2], P, a.donor_effghost ? 2 : 1, a.wrap[0]);
     hipLaunchKernelGGL(k_window_min<1>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.t1, a.t2, a.n[0], a.n[1],
-                       a.n[2], P, 0);
+                       a.n[2], P, 0, a.wrap[1]);
     hipLaunchKernelGGL(k_window_min<2>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.t2, a.dvalid[m], a.n[0],
-                       a.n[1], a.n[2], P, 0);
+                       a.n[1], a.n[2], P, 0, a.wrap[2]);
   }
 }
 
@@ -1900,6 +2033,9 @@ static void launch_stage_t(hipStream_t s, const StageArgs &a) {
   const dim3 g(8 * chunk);
   if (a.coord == CART && a.global)
     hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, true, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+  else if (a.global)  // a spherical global patch
+    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, true, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
                        a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
   else if (a.coord == CART)
     hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, false, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,

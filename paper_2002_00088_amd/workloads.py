@@ -102,7 +102,7 @@ def two_patch(seed=2, ng=128, nl=64, P=5, steps=200, motion=CIRCLE):
 
 
 def test_two(motion="fixed", ng=40, P=6, cfl=0.6, t_end=20.0):
-    """The paper's convergence test (Sec. 3.3, Test Two): global Cartesian cube
+    """The paper's convergence test (Sec. 3.2, Test Two): global Cartesian cube
     [-20, 20]^3 with ng^3 cells, a Cartesian local cube [-10, 10]^3 at twice the
     resolution (2-to-1), plane wave phi = sin(2 pi (x - t)/20) + 2 (Eq.
     wave_solution) with analytic outer ghosts, CFL 0.6 on the local spacing, up to
@@ -127,7 +127,7 @@ def test_two(motion="fixed", ng=40, P=6, cfl=0.6, t_end=20.0):
 
 
 def three_topology(scale=1.0, steps=None, t_end=200.0, spin_sph=0.01, spin_cyl=-0.03, P=6):
-    """The paper's three-topology test (Sec. 3.4, Test Three) at `scale` times
+    """The paper's three-topology test (Sec. 3.3, Test Three) at `scale` times
     its cell counts.  Global Cartesian 80 x 80 x 40 centred on the origin with
     160 x 160 x 40 cells; a spherical patch at (-22, 0, 0), r in [5, 20],
     theta in [pi/4, 3pi/4], phi periodic, 30 x 40 x 200 cells, spinning about
@@ -146,6 +146,30 @@ def three_topology(scale=1.0, steps=None, t_end=200.0, spin_sph=0.01, spin_cyl=-
     cfg = _finish(dict(name="three_topology_%g" % scale, wave_speed=[1.0], interp_points=[P], patches=[g, s, c],
                        exact=[ex]))
     cfg["steps"] = steps if steps is not None else int(math.ceil(t_end / cfg["dt"]))
+    return cfg
+
+
+def test_four(scale=1.0, steps=None, t_end=200.0, P=6):
+    """The paper's fourth test (Sec. 3.4, Test Four) at `scale` times its cell
+    counts: a spherical global shell r in [5, 100], theta in [pi/4, 3pi/4], phi
+    periodic, 100 x 100 x 300 cells; a Cartesian patch over the radial cutout,
+    30 x 30 x 20 with 80 x 80 x 20 cells, spinning at 0.03 about z; a cylindrical
+    patch r in [5, 25], z in [-10, 10], phi periodic, 40 x 200 x 20 cells (the
+    paper gives no cell counts for it), starting at (45, 45, 0) and translating
+    at -0.5 along x.  Plane wave phi = sin(2 pi (x - t)/20) + 2; dt = 0.05 / scale.
+    Below scale 0.6 the global's radial ghosts would reach r <= 0."""
+    def nn(v):
+        return [max(4, int(round(x * scale))) for x in v]
+    g = patch(nn([100, 100, 300]), [5.0, math.pi / 4, 0.0], [100.0, 3 * math.pi / 4, 2 * math.pi], coord=SPH,
+              is_global=1, periodic=(0, 0, 1))
+    q = patch(nn([80, 80, 20]), [-15.0, -15.0, -10.0], [15.0, 15.0, 10.0], spin=(0.0, 0.0, 0.03))
+    c = patch(nn([40, 200, 20]), [5.0, 0.0, -10.0], [25.0, 2 * math.pi, 10.0], coord=CYL, periodic=(0, 1, 0),
+              motion=LINEAR, c0=(45.0, 45.0, 0.0), vel=(-0.5, 0.0, 0.0))
+    ex = dict(kind="plane", A=1.0, B=2.0, kappa=[2 * math.pi / 20.0, 0.0, 0.0], psi=0.0)
+    dt = 0.05 / scale
+    cfg = dict(name="test_four_%g" % scale, wave_speed=[1.0], interp_points=[P], patches=[g, q, c], exact=[ex],
+               ko_eps=0.005, buffer=4, dt=dt)
+    cfg["steps"] = steps if steps is not None else int(math.ceil(t_end / dt - 1e-9))
     return cfg
 
 

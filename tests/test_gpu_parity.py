@@ -384,6 +384,54 @@ def test_narrow_buffer_ablation(B):
         say("  mixed, schedule %d: worst rel err" % sched, compare(cfg, o, g, 2e-5))
 
 
+def _sph_global_cfg(with_overlap):
+    # a spherical global shell with a rotated Cartesian patch across its phi seam
+    # and (optionally) a second patch overlapping the first one's buffer
+    g0 = W.patch([40, 40, 160], [1.0, 0.6, 0.0], [12.0, math.pi - 0.6, 2 * math.pi], coord=W.SPH, is_global=1,
+                 periodic=(0, 0, 1))
+    a = W.patch([28, 28, 26], [-3.5, -3.5, -3.2], [3.5, 3.5, 3.2], euler=[0.3, 0.2, 0.1], c0=(6.5, 0.2, -0.1),
+                motion=W.LINEAR, vel=(0.02, -0.03, 0.01))
+    pats = [g0, a]
+    if with_overlap:
+        pats.append(W.patch([12] * 3, [-1.5] * 3, [1.5] * 3, euler=[1.0, 0.4, 0.2], c0=(6.5, 5.4, 0.0)))
+    ex = dict(kind="plane", A=1.0, B=2.0, kappa=[2 * math.pi / 8, 2 * math.pi / 16, 0.0], psi=0.3)
+    return W._finish(dict(wave_speed=[1.0], interp_points=[6], patches=pats, exact=[ex]))
+
+
+@pytest.mark.parametrize("case", ["fp64", "random", "mixed", "overlap"])
+def test_spherical_global_patch(case):
+    cfg = _sph_global_cfg(case == "overlap")
+    say("spherical global", case)
+    o = world_from_config(cfg)
+    o.prepare()
+    fo, co = o.flags()
+    assert (fo == 1).sum() > 0 and (fo == 2).sum() > 0
+    prec = pw.PW_MIXED if case == "mixed" else pw.PW_FP64
+    o, g = run_pair(cfg, 3, precision=prec, init="random" if case == "random" else "exact", seed=41)
+    say("  worst rel err", compare(cfg, o, g, 2e-5 if case == "mixed" else TOL64))
+
+
+def test_paper_test_four_reduced():
+    # the paper's fourth test at 0.6 of its cell counts (the coarsest whose radial
+    # ghosts stay off r = 0): spherical global shell,
+    # spinning Cartesian patch over the radial cutout, translating cylinder
+    cfg = W.test_four(scale=0.6)
+    say("Test Four, scale 0.6")
+    o, g = run_pair(cfg, 3)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+    o, g = run_pair(cfg, 2, precision=pw.PW_MIXED, init="random", seed=43)
+    say("  mixed, worst rel err", compare(cfg, o, g, 2e-5))
+
+
+def test_paper_test_four_full_size_one_step():
+    cfg = W.test_four()
+    say("Test Four, full size, one step")
+    o, g = run_pair(cfg, 1)
+    fo, _ = o.flags()
+    assert (fo == 2).sum() > 0 and o.counters()["skip_local"] > 0
+    say("  worst rel err", compare(cfg, o, g, TOL64, norm="all"))
+
+
 def test_rotating_patch_mixed_precision():
     cfg = W.two_patch(seed=6, ng=48, nl=40, P=6)
     cfg["patches"][1]["spin"] = [0.15, -0.25, 0.3]
@@ -562,7 +610,8 @@ def test_error_paths():
         g.rk4_step(cfg["dt"], 1)
     assert e.value.code == -6
     g.close()
-    cfg = W.two_patch(seed=2, ng=32, nl=24, P=6, motion=W.STATIC)
+    # two identical local patches: their overlap reaches deactivated cells
+    cfg = W.two_patch(seed=2, ng=32, nl=40, P=6, motion=W.STATIC)
     cfg["patches"].append(dict(cfg["patches"][1]))
     g = pw.context_from_config(cfg)
     g.init_exact(0.0)
