@@ -95,10 +95,10 @@ __global__ void k_cover(const PatchDev *__restrict__ P, const PoseDev *__restric
 // "uncovered" = (cover == -1).
 template <int AXIS, bool SRC_COVER>
 __global__ void k_dilate(const void *in_, uint8_t *out, int n0, int n1, int n2, int R, int oob, int wrap) {
-  long long total = (long long)n0 * n1 * n2;
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= total) return;
-  int i = (int)(c % n0), j = (int)((c / n0) % n1), k = (int)(c / ((long long)n0 * n1));
+  // grid (x blocks, n1, n2): no integer division for the cell coordinates
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= n0) return;
+  const long long c = ((long long)k * n1 + j) * n0 + i;
   int pos = AXIS == 0 ? i : (AXIS == 1 ? j : k);
   int len = AXIS == 0 ? n0 : (AXIS == 1 ? n1 : n2);
   long long stride = AXIS == 0 ? 1 : (AXIS == 1 ? (long long)n0 : (long long)n0 * n1);
@@ -346,10 +346,10 @@ __global__ void k_fill_lower(const PatchDev *__restrict__ P, const PoseDev *__re
 template <int AXIS>
 __global__ void k_window_min(const uint8_t *in, uint8_t *out, int n0, int n1, int n2, int P, int from_flags,
                              int wrap) {
-  long long total = (long long)n0 * n1 * n2;
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= total) return;
-  int i = (int)(c % n0), j = (int)((c / n0) % n1), k = (int)(c / ((long long)n0 * n1));
+  // grid (x blocks, n1, n2): no integer division for the cell coordinates
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= n0) return;
+  const long long c = ((long long)k * n1 + j) * n0 + i;
   int pos = AXIS == 0 ? i : (AXIS == 1 ? j : k);
   int len = AXIS == 0 ? n0 : (AXIS == 1 ? n1 : n2);
   long long stride = AXIS == 0 ? 1 : (AXIS == 1 ? (long long)n0 : (long long)n0 * n1);
@@ -1875,21 +1875,22 @@ void launch_flags(hipStream_t s, const FlagsArgs &a) {
   const int bs = 256;
   long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
   unsigned nb = nblk(tot, bs);
+  const dim3 g3(nblk(a.n[0], bs), a.n[1], a.n[2]);
   hipLaunchKernelGGL(k_fill_value<uint8_t>, dim3(nb < 4096 ? nb : 4096), dim3(bs), 0, s, a.dbl, tot, (uint8_t)0);
   if (a.njobs > 0)
     hipLaunchKernelGGL(k_cover, dim3(a.cover_blocks, a.njobs), dim3(bs), 0, s, a.P, a.pose, a.jobs, a.njobs,
                        a.cover_new, a.dbl);
-  hipLaunchKernelGGL((k_dilate<0, true>), dim3(nb), dim3(bs), 0, s, (const void *)a.cover_new, a.t1, a.n[0], a.n[1],
+  hipLaunchKernelGGL((k_dilate<0, true>), g3, dim3(bs), 0, s, (const void *)a.cover_new, a.t1, a.n[0], a.n[1],
                      a.n[2], a.buffer, 1, a.wrap[0]);
-  hipLaunchKernelGGL((k_dilate<1, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t1, a.t2, a.n[0], a.n[1], a.n[2],
+  hipLaunchKernelGGL((k_dilate<1, false>), g3, dim3(bs), 0, s, (const void *)a.t1, a.t2, a.n[0], a.n[1], a.n[2],
                      a.buffer, 1, a.wrap[1]);
-  hipLaunchKernelGGL((k_dilate<2, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t2, a.live, a.n[0], a.n[1],
+  hipLaunchKernelGGL((k_dilate<2, false>), g3, dim3(bs), 0, s, (const void *)a.t2, a.live, a.n[0], a.n[1],
                      a.n[2], a.buffer, 1, a.wrap[2]);
-  hipLaunchKernelGGL((k_dilate<0, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.live, a.t1, a.n[0], a.n[1],
+  hipLaunchKernelGGL((k_dilate<0, false>), g3, dim3(bs), 0, s, (const void *)a.live, a.t1, a.n[0], a.n[1],
                      a.n[2], PW_NG, 0, a.wrap[0]);
-  hipLaunchKernelGGL((k_dilate<1, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t1, a.t2, a.n[0], a.n[1], a.n[2],
+  hipLaunchKernelGGL((k_dilate<1, false>), g3, dim3(bs), 0, s, (const void *)a.t1, a.t2, a.n[0], a.n[1], a.n[2],
                      PW_NG, 0, a.wrap[1]);
-  hipLaunchKernelGGL((k_dilate<2, false>), dim3(nb), dim3(bs), 0, s, (const void *)a.t2, a.t1, a.n[0], a.n[1], a.n[2],
+  hipLaunchKernelGGL((k_dilate<2, false>), g3, dim3(bs), 0, s, (const void *)a.t2, a.t1, a.n[0], a.n[1], a.n[2],
                      PW_NG, 0, a.wrap[2]);
   hipLaunchKernelGGL(k_combine_flags, dim3(nb), dim3(bs), 0, s, (const uint8_t *)a.live, (const uint8_t *)a.t1,
                      (const uint8_t *)a.dbl, a.flag_new, tot, a.err);
@@ -2007,8 +2008,7 @@ void launch_ghosts(hipStream_t s, const GhostArgs &a) {
 
 void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
   // (the donor ordering of the list is done by launch_l2g_order after this)
-  long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
-  unsigned nb = nblk(tot, 256);
+  const dim3 g3(nblk(a.n[0], 256), a.n[1], a.n[2]);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.effcount, 0);
   const long long tot_bricks = (long long)((a.n[0] + 3) / 4) * ((a.n[1] + 3) / 4) * ((a.n[2] + 3) / 4) * 64;
   hipLaunchKernelGGL(k_efflist, dim3(nblk(tot_bricks, 256 * EFF_PER_THREAD)), dim3(256), 0, s,
@@ -2016,11 +2016,11 @@ void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
   for (int m = 0; m < PW_NPTS; m++) {
     if (!a.dvalid[m]) continue;
     int P = a.Pvals[m];
-    hipLaunchKernelGGL(k_window_min<0>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.flag, a.t1, a.n[0], a.n[1],
+    hipLaunchKernelGGL(k_window_min<0>, g3, dim3(256), 0, s, (const uint8_t *)a.flag, a.t1, a.n[0], a.n[1],
                        a.n[2], P, a.donor_effghost ? 2 : 1, a.wrap[0]);
-    hipLaunchKernelGGL(k_window_min<1>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.t1, a.t2, a.n[0], a.n[1],
+    hipLaunchKernelGGL(k_window_min<1>, g3, dim3(256), 0, s, (const uint8_t *)a.t1, a.t2, a.n[0], a.n[1],
                        a.n[2], P, 0, a.wrap[1]);
-    hipLaunchKernelGGL(k_window_min<2>, dim3(nb), dim3(256), 0, s, (const uint8_t *)a.t2, a.dvalid[m], a.n[0],
+    hipLaunchKernelGGL(k_window_min<2>, g3, dim3(256), 0, s, (const uint8_t *)a.t2, a.dvalid[m], a.n[0],
                        a.n[1], a.n[2], P, 0, a.wrap[2]);
   }
 }
