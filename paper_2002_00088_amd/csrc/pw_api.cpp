@@ -70,7 +70,8 @@ struct pw_context {
   int nGlobalTiles = 0;
   int coordTiles[4] = {0, 0, 0, 0};  // local-patch tiles by topology: group t is [coordTiles[t], coordTiles[t+1])
   CoverJob *dJobs = nullptr;
-  int nJobs = 0, coverBlocks = 1;
+  CoverBlk *dCoverBlk = nullptr;
+  int nJobs = 0, nCoverBlk = 0;
   double *dStage = nullptr;  // staging for host copies
   long long stageCap = 0;
   double *dPartial = nullptr;
@@ -382,7 +383,7 @@ pw_status upload_layout(pw_context *c) {
   // Cover scans of the local patches.
   std::vector<CoverJob> jobs;
   const PatchDev &g = c->hp[0];
-  long long maxcells = 0;
+  std::vector<CoverBlk> cblk;
   for (int pid = 1; pid < np; pid++) {
     CoverJob J;
     J.patch = pid;
@@ -393,15 +394,22 @@ pw_status upload_layout(pw_context *c) {
       J.ext[a] = g.coord == CART ? (int)ceil(2.0 * J.radius * g.idx[a]) + 3 : g.n[a];
       tot *= J.ext[a];
     }
-    maxcells = std::max(maxcells, tot);
+    if (tot >= (1LL << 31) - 256LL * COVER_CPT)
+      return fail(c, PW_EINVAL, "the bounding box of a local patch spans 2^31 global cells or more");
+    // workgroups of COVER_CPT x 256 consecutive box cells
+    for (long long f = 0; f < tot; f += 256LL * COVER_CPT) cblk.push_back(CoverBlk{(int32_t)jobs.size(), (uint32_t)f});
     jobs.push_back(J);
   }
   dfree(c, c->dJobs);
+  dfree(c, c->dCoverBlk);
   c->nJobs = (int)jobs.size();
-  c->coverBlocks = (int)std::min<long long>(std::max<long long>(1, (maxcells + 255) / 256), 2048);
+  c->nCoverBlk = (int)cblk.size();
   c->dJobs = (CoverJob *)dalloc(c, sizeof(CoverJob) * std::max<size_t>(1, jobs.size()));
-  if (!c->dJobs) return fail(c, PW_ENOMEM, "device allocation failed");
+  c->dCoverBlk = (CoverBlk *)dalloc(c, sizeof(CoverBlk) * std::max<size_t>(1, cblk.size()));
+  if (!c->dJobs || !c->dCoverBlk) return fail(c, PW_ENOMEM, "device allocation failed");
   if (!jobs.empty()) HIPCHK(c, hipMemcpy(c->dJobs, jobs.data(), sizeof(CoverJob) * jobs.size(), hipMemcpyHostToDevice));
+  if (!cblk.empty())
+    HIPCHK(c, hipMemcpy(c->dCoverBlk, cblk.data(), sizeof(CoverBlk) * cblk.size(), hipMemcpyHostToDevice));
 
   if (c->gexec) {
     (void)hipGraphExecDestroy(c->gexec);
@@ -426,7 +434,8 @@ void enqueue_flags(pw_context *c, const PoseDev *pose_slot, hipStream_t st) {
   a.pose = pose_slot;
   a.jobs = c->dJobs;
   a.njobs = c->nJobs;
-  a.cover_blocks = c->coverBlocks;
+  a.blks = c->dCoverBlk;
+  a.nblks = c->nCoverBlk;
   a.cover_new = c->cover_new;
   a.t1 = c->t1;
   a.t2 = c->t2;

@@ -47,6 +47,13 @@ struct CoverJob {
   int32_t ext[3];
   double radius;
 };
+// One workgroup of the cover scan: COVER_CPT x 256 consecutive cells of the
+// box of one job, starting at cell `first` of that box.
+#define COVER_CPT 4
+struct CoverBlk {
+  int32_t job;
+  uint32_t first;
+};
 
 // A brick of ghost cells of one local patch: box [i0,i0+di) x [j0,j0+dj) x [k0,k0+dk)
 // in interior-relative cell indices, at most BRICK_THREADS cells.
@@ -90,7 +97,8 @@ struct FlagsArgs {
   const PatchDev *P;
   const PoseDev *pose;
   const CoverJob *jobs;
-  int njobs, cover_blocks;
+  const CoverBlk *blks;
+  int njobs, nblks;
   int32_t *cover_new;
   uint8_t *t1, *t2, *live, *flag_new;
   uint8_t *dbl;  // cells claimed by two local patches

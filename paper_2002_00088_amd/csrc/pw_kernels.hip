@@ -12,6 +12,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <initializer_list>
+
 #include "pw_internal.h"
 #include "pw_kernels.h"
 
@@ -52,23 +54,31 @@ __global__ void k_advance_time(double *tdev, double dt, long long *counters) {
 // the axis-aligned box around its bounding sphere (a Cartesian global), or all
 // global cells (a curvilinear global: the host sets the extents to the grid).
 // A cell claimed by two patches keeps the lower id and is marked in dbl.
-__global__ void k_cover(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const CoverJob *jobs, int njobs, int32_t *cover,
-                        uint8_t *dbl) {
-  const CoverJob J = jobs[blockIdx.y];
+__global__ __launch_bounds__(256) void k_cover(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose,
+                                               const CoverJob *jobs, const CoverBlk *blks, int32_t *cover,
+                                               uint8_t *dbl) {
+  const CoverBlk B = blks[blockIdx.x];
+  const CoverJob J = jobs[B.job];
   const PatchDev &g = P[0];
   const PatchDev &p = P[J.patch];
   const PoseDev &ps = pose[J.patch];
-  int lo[3], ext[3];
+  int lo[3];
   for (int a = 0; a < 3; a++) {
     double c = (ps.c[a] - J.radius - g.lo[a]) * g.idx[a] - 0.5;
+    c = c < -1.0e9 ? -1.0e9 : (c > 1.0e9 ? 1.0e9 : c);
     lo[a] = g.coord == CART ? (int)floor(c) : 0;
-    ext[a] = J.ext[a];
   }
-  long long total = (long long)ext[0] * ext[1] * ext[2];
-  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (long long)gridDim.x * blockDim.x) {
-    int i = lo[0] + (int)(q % ext[0]);
-    int j = lo[1] + (int)((q / ext[0]) % ext[1]);
-    int k = lo[2] + (int)(q / ((long long)ext[0] * ext[1]));
+  // the host keeps every box below 2^31 cells: 32-bit index arithmetic
+  const unsigned e0 = (unsigned)J.ext[0], e1 = (unsigned)J.ext[1];
+  const unsigned total = e0 * e1 * (unsigned)J.ext[2];
+#pragma unroll
+  for (int m = 0; m < COVER_CPT; m++) {
+    const unsigned q = B.first + m * 256u + threadIdx.x;
+    if (q >= total) break;
+    const unsigned r = q / e0, kk = r / e1;
+    const int i = lo[0] + (int)(q - r * e0);
+    const int j = lo[1] + (int)(r - kk * e1);
+    const int k = lo[2] + (int)kk;
     if (i < 0 || j < 0 || k < 0 || i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) continue;
     double X[3], xp[3];
     global_X(g, pose[0], i, j, k, X);
@@ -128,6 +138,177 @@ __global__ void k_combine_flags(const uint8_t *live, const uint8_t *near, const 
   if (c >= total) return;
   flag[c] = live[c] ? LIVE : (near[c] ? EFFGHOST : DEACT);
   if (dbl[c] && !live[c]) err[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// The same filters on 16-cell chunks (rows of a multiple of 16 cells, arrays
+// 16-byte aligned): one thread per chunk, the chunk and its neighbours moved
+// as 16-byte words.  Along x the cells of a 24-cell window become bits of a
+// mask (radius <= 4); along y and z whole chunks of 0/1 bytes combine by OR
+// (max) or AND (min).
+// ---------------------------------------------------------------------------
+static_assert(LIVE == 0 && EFFGHOST == 1 && DEACT == 2, "flag encoding used by the chunked filters");
+// four bytes in {0, 1} -> four bits (byte m -> bit m)
+__device__ __forceinline__ uint32_t bits4(uint32_t w) { return ((w * 0x01020408u) >> 24) & 0xFu; }
+// four bits -> four bytes in {0, 1}
+__device__ __forceinline__ uint32_t bytes4(uint32_t n) { return (n * 0x00204081u) & 0x01010101u; }
+__device__ __forceinline__ uint32_t bits16(uint4 v) {
+  return bits4(v.x) | (bits4(v.y) << 4) | (bits4(v.z) << 8) | (bits4(v.w) << 12);
+}
+__device__ __forceinline__ uint4 bytes16(uint32_t m) {
+  return make_uint4(bytes4(m & 0xFu), bytes4((m >> 4) & 0xFu), bytes4((m >> 8) & 0xFu), bytes4((m >> 12) & 0xFu));
+}
+__device__ __forceinline__ uint32_t uncovered4(int4 v) {
+  return (uint32_t)(v.x == -1) | ((uint32_t)(v.y == -1) << 1) | ((uint32_t)(v.z == -1) << 2) |
+         ((uint32_t)(v.w == -1) << 3);
+}
+// chunk coordinates: grid (x blocks over the chunks of a plane, n2 planes)
+struct Chunk {
+  int ch, j, k, nch;
+  long long row;  // first cell of the row
+  bool ok;
+};
+__device__ __forceinline__ Chunk chunk_of(int n0, int n1) {
+  Chunk q;
+  q.nch = n0 >> 4;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  q.k = blockIdx.y;
+  q.ok = t < (unsigned)(q.nch * n1);
+  q.j = (int)(t / (unsigned)q.nch);
+  q.ch = (int)t - q.j * q.nch;
+  q.row = ((long long)q.k * n1 + q.j) * n0;
+  return q;
+}
+
+// Dilation along x with radius R <= 4 (same result as k_dilate<0, SRC_COVER>).
+template <bool SRC_COVER>
+__global__ __launch_bounds__(256) void k_dilate_x16(const void *in_, uint8_t *out, int n0, int n1, int R, int oob,
+                                                    int wrap) {
+  const Chunk q = chunk_of(n0, n1);
+  if (!q.ok) return;
+  int chp = q.ch - 1, chn = q.ch + 1;
+  bool hp = chp >= 0, hn = chn < q.nch;
+  if (wrap) {
+    if (!hp) chp = q.nch - 1;
+    if (!hn) chn = 0;
+    hp = hn = true;
+  }
+  const long long c = q.row + 16 * q.ch;
+  uint32_t mid, pre = oob ? 0xFu : 0u, nxt = oob ? 0xFu : 0u;
+  if (SRC_COVER) {
+    const int32_t *in = (const int32_t *)in_;
+    const int4 *v = (const int4 *)(in + c);
+    mid = uncovered4(v[0]) | (uncovered4(v[1]) << 4) | (uncovered4(v[2]) << 8) | (uncovered4(v[3]) << 12);
+    if (hp) pre = uncovered4(*(const int4 *)(in + q.row + 16 * chp + 12));
+    if (hn) nxt = uncovered4(*(const int4 *)(in + q.row + 16 * chn));
+  } else {
+    const uint8_t *in = (const uint8_t *)in_;
+    mid = bits16(*(const uint4 *)(in + c));
+    if (hp) pre = bits4(*(const uint32_t *)(in + q.row + 16 * chp + 12));
+    if (hn) nxt = bits4(*(const uint32_t *)(in + q.row + 16 * chn));
+  }
+  // bit t of M is cell x0 - 4 + t
+  const uint32_t M = pre | (mid << 4) | (nxt << 20);
+  uint32_t D = 0;
+  for (int d = -R; d <= R; d++) D |= M >> (4 + d);
+  *(uint4 *)(out + c) = bytes16(D & 0xFFFFu);
+}
+
+// Dilation along y (AXIS 1) or z (AXIS 2) of 0/1 bytes (k_dilate<AXIS, false>).
+// With COMBINE the result is the "near a live cell" mask and the kernel writes
+// the flags instead (k_combine_flags): flag = (1 - live) (2 - near) per byte.
+template <int AXIS, bool COMBINE>
+__global__ __launch_bounds__(256) void k_dilate_yz16(const uint8_t *in, uint8_t *out, int n0, int n1, int n2, int R,
+                                                     int oob, int wrap, const uint8_t *live, const uint8_t *dbl,
+                                                     int *err) {
+  const Chunk q = chunk_of(n0, n1);
+  if (!q.ok) return;
+  const long long c = q.row + 16 * q.ch;
+  const int pos = AXIS == 1 ? q.j : q.k, len = AXIS == 1 ? n1 : n2;
+  const long long stride = AXIS == 1 ? (long long)n0 : (long long)n0 * n1;
+  uint4 m = make_uint4(0, 0, 0, 0);
+  for (int d = -R; d <= R; d++) {
+    int p = pos + d;
+    if (wrap) p = ((p % len) + len) % len;
+    if (p < 0 || p >= len) {
+      if (oob) m = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+    } else {
+      const uint4 v = *(const uint4 *)(in + c + (long long)(p - pos) * stride);
+      m.x |= v.x;
+      m.y |= v.y;
+      m.z |= v.z;
+      m.w |= v.w;
+    }
+  }
+  if (!COMBINE) {
+    *(uint4 *)(out + c) = m;
+    return;
+  }
+  const uint4 l = *(const uint4 *)(live + c), b = *(const uint4 *)(dbl + c);
+  const uint4 nl = make_uint4(l.x ^ 0x01010101u, l.y ^ 0x01010101u, l.z ^ 0x01010101u, l.w ^ 0x01010101u);
+  uint4 f;
+  f.x = (0x02020202u - m.x) & (nl.x * 0xFFu);
+  f.y = (0x02020202u - m.y) & (nl.y * 0xFFu);
+  f.z = (0x02020202u - m.z) & (nl.z * 0xFFu);
+  f.w = (0x02020202u - m.w) & (nl.w * 0xFFu);
+  *(uint4 *)(out + c) = f;
+  if ((b.x & nl.x) | (b.y & nl.y) | (b.z & nl.z) | (b.w & nl.w)) err[0] = 1;
+}
+
+// Forward window minimum along x, P <= 8 (k_window_min<0>): from the flags
+// (from_flags 1: LIVE -> 1; 2: not DEACT -> 1) or from 0/1 bytes (0).
+__device__ __forceinline__ uint32_t flagbits4(uint32_t w, int from_flags) {
+  const uint32_t nw = ~w;
+  const uint32_t b = from_flags == 1 ? (nw & (nw >> 1)) : (from_flags == 2 ? (nw >> 1) : w);
+  return bits4(b & 0x01010101u);
+}
+__global__ __launch_bounds__(256) void k_window_x16(const uint8_t *in, uint8_t *out, int n0, int n1, int P,
+                                                    int from_flags, int wrap) {
+  const Chunk q = chunk_of(n0, n1);
+  if (!q.ok) return;
+  const long long c = q.row + 16 * q.ch;
+  int chn = q.ch + 1;
+  bool hn = chn < q.nch;
+  if (wrap && !hn) {
+    chn = 0;
+    hn = true;
+  }
+  const uint4 v = *(const uint4 *)(in + c);
+  uint32_t M = flagbits4(v.x, from_flags) | (flagbits4(v.y, from_flags) << 4) | (flagbits4(v.z, from_flags) << 8) |
+               (flagbits4(v.w, from_flags) << 12);
+  if (hn) {
+    const uint2 w = *(const uint2 *)(in + q.row + 16 * chn);
+    M |= (flagbits4(w.x, from_flags) << 16) | (flagbits4(w.y, from_flags) << 20);
+  }
+  uint32_t A = 0xFFFFFFFFu;
+  for (int d = 0; d < P; d++) A &= M >> d;
+  *(uint4 *)(out + c) = bytes16(A & 0xFFFFu);
+}
+
+// Forward window minimum along y (AXIS 1) or z (AXIS 2) of 0/1 bytes.
+template <int AXIS>
+__global__ __launch_bounds__(256) void k_window_yz16(const uint8_t *in, uint8_t *out, int n0, int n1, int n2, int P,
+                                                     int wrap) {
+  const Chunk q = chunk_of(n0, n1);
+  if (!q.ok) return;
+  const long long c = q.row + 16 * q.ch;
+  const int pos = AXIS == 1 ? q.j : q.k, len = AXIS == 1 ? n1 : n2;
+  const long long stride = AXIS == 1 ? (long long)n0 : (long long)n0 * n1;
+  uint4 m = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+  for (int d = 0; d < P; d++) {
+    int p = pos + d;
+    if (wrap) p = p % len;
+    if (p >= len) {
+      m = make_uint4(0, 0, 0, 0);
+    } else {
+      const uint4 v = *(const uint4 *)(in + c + (long long)(p - pos) * stride);
+      m.x &= v.x;
+      m.y &= v.y;
+      m.z &= v.z;
+      m.w &= v.w;
+    }
+  }
+  *(uint4 *)(out + c) = m;
 }
 
 // Tensor-product Lagrange interpolation of the 5 fields of buffer T of donor
@@ -1097,7 +1278,7 @@ __global__ void k_fallback(const PatchDev *__restrict__ P, const PoseDev *__rest
 // interpolated from the covering local patch; cells that become deactivated are
 // poisoned (nothing writes a deactivated cell, so it stays poisoned); the new
 // flags become current.  mode 0: first flags (no uncover fill, every deactivated
-// cell poisoned).  Four cells per thread: flags and cover ids move as 4-byte and
+// cell poisoned).  Sixteen cells per thread: flags and cover ids move as
 // 16-byte words.
 __device__ inline void finalize_cell(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, long long c,
                                      uint8_t fo, uint8_t fn, int32_t co, int32_t cn, int nsv, const int *Pts,
@@ -1139,29 +1320,43 @@ __device__ inline void finalize_cell(const PatchDev *__restrict__ P, const PoseD
   }
 }
 
+#define FIN_CELLS 16
 __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, uint8_t *flag_cur,
                            const uint8_t *flag_new, int32_t *cover_cur, int32_t *cover_new, int nsv, const int *Pts,
                            const ExactDev *ex, const double *vs, const double *tdev, int mode,
                            unsigned long long *counters) {
   const PatchDev &G0 = P[0];
   const long long total = (long long)G0.n[0] * G0.n[1] * G0.n[2];
-  const long long c0 = 4 * ((long long)blockIdx.x * blockDim.x + threadIdx.x);
+  const long long c0 = (long long)FIN_CELLS * ((long long)blockIdx.x * blockDim.x + threadIdx.x);
   if (c0 >= total) return;
-  if (c0 + 4 <= total) {
-    const uchar4 fo4 = *(const uchar4 *)(flag_cur + c0), fn4 = *(const uchar4 *)(flag_new + c0);
-    const int4 co4 = *(const int4 *)(cover_cur + c0), cn4 = *(const int4 *)(cover_new + c0);
-    const uint8_t fo[4] = {fo4.x, fo4.y, fo4.z, fo4.w}, fn[4] = {fn4.x, fn4.y, fn4.z, fn4.w};
-    const int32_t co[4] = {co4.x, co4.y, co4.z, co4.w}, cn[4] = {cn4.x, cn4.y, cn4.z, cn4.w};
+  if (c0 + FIN_CELLS <= total) {
+    const uint4 fo16 = *(const uint4 *)(flag_cur + c0), fn16 = *(const uint4 *)(flag_new + c0);
+    const uint32_t fow[4] = {fo16.x, fo16.y, fo16.z, fo16.w}, fnw[4] = {fn16.x, fn16.y, fn16.z, fn16.w};
+    // cells to fill (uncovered) or poison (newly deactivated), as a bit mask
+    uint32_t need = 0;
 #pragma unroll
-    for (int m = 0; m < 4; m++) {
-      const bool uncover = mode == 1 && fo[m] != LIVE && fn[m] == LIVE;
-      const bool poison = fn[m] == DEACT && (mode == 0 || fo[m] != DEACT);
-      if (uncover || poison)
-        finalize_cell(P, pose, c0 + m, fo[m], fn[m], co[m], cn[m], nsv, Pts, ex, vs, tdev, mode, counters);
+    for (int m = 0; m < FIN_CELLS; m++) {
+      const uint8_t fo = (uint8_t)(fow[m >> 2] >> (8 * (m & 3))), fn = (uint8_t)(fnw[m >> 2] >> (8 * (m & 3)));
+      const bool uncover = mode == 1 && fo != LIVE && fn == LIVE;
+      const bool poison = fn == DEACT && (mode == 0 || fo != DEACT);
+      need |= (uint32_t)(uncover || poison) << m;
     }
-    *(uchar4 *)(flag_cur + c0) = fn4;
-    *(int4 *)(cover_cur + c0) = cn4;
-    *(int4 *)(cover_new + c0) = make_int4(-1, -1, -1, -1);
+    // rare: one call site, the cover ids read before they are overwritten
+    while (need) {
+      const int m = __ffs(need) - 1;
+      need &= need - 1;
+      const uint32_t wo = m < 4 ? fow[0] : (m < 8 ? fow[1] : (m < 12 ? fow[2] : fow[3]));
+      const uint32_t wn = m < 4 ? fnw[0] : (m < 8 ? fnw[1] : (m < 12 ? fnw[2] : fnw[3]));
+      const long long c = c0 + m;
+      finalize_cell(P, pose, c, (uint8_t)(wo >> (8 * (m & 3))), (uint8_t)(wn >> (8 * (m & 3))), cover_cur[c],
+                    cover_new[c], nsv, Pts, ex, vs, tdev, mode, counters);
+    }
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      *(int4 *)(cover_cur + c0 + 4 * w) = *(const int4 *)(cover_new + c0 + 4 * w);
+      *(int4 *)(cover_new + c0 + 4 * w) = make_int4(-1, -1, -1, -1);
+    }
+    *(uint4 *)(flag_cur + c0) = fn16;
   } else {
     for (long long c = c0; c < total; c++) {
       const uint8_t fo = flag_cur[c], fn = flag_new[c];
@@ -1871,15 +2066,40 @@ void launch_advance_time(hipStream_t s, double *tdev, double dt, long long *coun
   hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, s, tdev, dt, counters);
 }
 
+// The chunked filters apply: rows of a multiple of 16 cells, arrays 16-byte aligned.
+static bool chunked(int n0, std::initializer_list<const void *> ptrs) {
+  if (n0 % 16 != 0) return false;
+  for (const void *p : ptrs)
+    if ((uintptr_t)p % 16 != 0) return false;
+  return true;
+}
+
 void launch_flags(hipStream_t s, const FlagsArgs &a) {
   const int bs = 256;
   long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
   unsigned nb = nblk(tot, bs);
   const dim3 g3(nblk(a.n[0], bs), a.n[1], a.n[2]);
   hipLaunchKernelGGL(k_fill_value<uint8_t>, dim3(nb < 4096 ? nb : 4096), dim3(bs), 0, s, a.dbl, tot, (uint8_t)0);
-  if (a.njobs > 0)
-    hipLaunchKernelGGL(k_cover, dim3(a.cover_blocks, a.njobs), dim3(bs), 0, s, a.P, a.pose, a.jobs, a.njobs,
-                       a.cover_new, a.dbl);
+  if (a.nblks > 0)
+    hipLaunchKernelGGL(k_cover, dim3(a.nblks), dim3(256), 0, s, a.P, a.pose, a.jobs, a.blks, a.cover_new,
+                       a.dbl);
+  if (chunked(a.n[0], {a.cover_new, a.t1, a.t2, a.live, a.flag_new, a.dbl}) && a.buffer <= 4 && PW_NG <= 4) {
+    // live = buffer-dilation of the uncovered cells, near = NG-dilation of live
+    const dim3 gc(nblk((long long)(a.n[0] / 16) * a.n[1], bs), a.n[2]);
+    hipLaunchKernelGGL(k_dilate_x16<true>, gc, dim3(bs), 0, s, (const void *)a.cover_new, a.t1, a.n[0], a.n[1],
+                       a.buffer, 1, a.wrap[0]);
+    hipLaunchKernelGGL((k_dilate_yz16<1, false>), gc, dim3(bs), 0, s, (const uint8_t *)a.t1, a.t2, a.n[0], a.n[1],
+                       a.n[2], a.buffer, 1, a.wrap[1], nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_dilate_yz16<2, false>), gc, dim3(bs), 0, s, (const uint8_t *)a.t2, a.live, a.n[0], a.n[1],
+                       a.n[2], a.buffer, 1, a.wrap[2], nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_dilate_x16<false>, gc, dim3(bs), 0, s, (const void *)a.live, a.t1, a.n[0], a.n[1], PW_NG,
+                       0, a.wrap[0]);
+    hipLaunchKernelGGL((k_dilate_yz16<1, false>), gc, dim3(bs), 0, s, (const uint8_t *)a.t1, a.t2, a.n[0], a.n[1],
+                       a.n[2], PW_NG, 0, a.wrap[1], nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_dilate_yz16<2, true>), gc, dim3(bs), 0, s, (const uint8_t *)a.t2, a.flag_new, a.n[0],
+                       a.n[1], a.n[2], PW_NG, 0, a.wrap[2], (const uint8_t *)a.live, (const uint8_t *)a.dbl, a.err);
+    return;
+  }
   hipLaunchKernelGGL((k_dilate<0, true>), g3, dim3(bs), 0, s, (const void *)a.cover_new, a.t1, a.n[0], a.n[1],
                      a.n[2], a.buffer, 1, a.wrap[0]);
   hipLaunchKernelGGL((k_dilate<1, false>), g3, dim3(bs), 0, s, (const void *)a.t1, a.t2, a.n[0], a.n[1], a.n[2],
@@ -1911,7 +2131,7 @@ void launch_l2g_order(hipStream_t s, const L2GOrderArgs &a) {
 
 void launch_finalize(hipStream_t s, const FinalizeArgs &a) {
   long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
-  hipLaunchKernelGGL(k_finalize, dim3(nblk((tot + 3) / 4, 256)), dim3(256), 0, s, a.P, a.pose, a.flag_cur, a.flag_new,
+  hipLaunchKernelGGL(k_finalize, dim3(nblk((tot + FIN_CELLS - 1) / FIN_CELLS, 256)), dim3(256), 0, s, a.P, a.pose, a.flag_cur, a.flag_new,
                      a.cover_cur, a.cover_new, a.nsv, a.Pts, a.ex, a.vs, a.tdev, a.mode, a.counters);
 }
 
@@ -2013,9 +2233,20 @@ void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
   const long long tot_bricks = (long long)((a.n[0] + 3) / 4) * ((a.n[1] + 3) / 4) * ((a.n[2] + 3) / 4) * 64;
   hipLaunchKernelGGL(k_efflist, dim3(nblk(tot_bricks, 256 * EFF_PER_THREAD)), dim3(256), 0, s,
                      (const uint8_t *)a.flag, a.n[0], a.n[1], a.n[2], a.efflist, a.effcount);
+  const bool ck = chunked(a.n[0], {a.flag, a.t1, a.t2});
+  const dim3 gc(nblk((long long)(a.n[0] / 16) * a.n[1], 256), a.n[2]);
   for (int m = 0; m < PW_NPTS; m++) {
     if (!a.dvalid[m]) continue;
     int P = a.Pvals[m];
+    if (ck && P <= 8 && chunked(a.n[0], {a.dvalid[m]})) {
+      hipLaunchKernelGGL(k_window_x16, gc, dim3(256), 0, s, (const uint8_t *)a.flag, a.t1, a.n[0], a.n[1], P,
+                         a.donor_effghost ? 2 : 1, a.wrap[0]);
+      hipLaunchKernelGGL(k_window_yz16<1>, gc, dim3(256), 0, s, (const uint8_t *)a.t1, a.t2, a.n[0], a.n[1], a.n[2],
+                         P, a.wrap[1]);
+      hipLaunchKernelGGL(k_window_yz16<2>, gc, dim3(256), 0, s, (const uint8_t *)a.t2, a.dvalid[m], a.n[0], a.n[1],
+                         a.n[2], P, a.wrap[2]);
+      continue;
+    }
     hipLaunchKernelGGL(k_window_min<0>, g3, dim3(256), 0, s, (const uint8_t *)a.flag, a.t1, a.n[0], a.n[1],
                        a.n[2], P, a.donor_effghost ? 2 : 1, a.wrap[0]);
     hipLaunchKernelGGL(k_window_min<1>, g3, dim3(256), 0, s, (const uint8_t *)a.t1, a.t2, a.n[0], a.n[1],
