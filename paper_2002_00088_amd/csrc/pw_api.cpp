@@ -42,6 +42,8 @@ struct pw_context {
   uint8_t *flag_cur = nullptr, *flag_new = nullptr, *t1 = nullptr, *t2 = nullptr, *live = nullptr;
   uint8_t *dbl = nullptr;  // cells claimed by two local patches (k_cover)
   int32_t *cover_cur = nullptr, *cover_new = nullptr;
+  int2 *ulist = nullptr;  // cells that become live at the end of a step
+  int *ucount = nullptr;
   // lists
   GhostRec *dLower = nullptr;
   int nLower = 0, nLowerGlobal = 0;
@@ -505,18 +507,22 @@ void enqueue_finalize(pw_context *c, const PoseDev *pose_slot, int mode) {
   a.mode = mode;
   a.counters = c->dCounters;
   for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
+  a.ulist = c->ulist;
+  a.ucount = c->ucount;
   launch_finalize(c->stream, a);
 }
 
 // Ghost fill of the buffers of `stage` (0: u) at time tdev[0] + tmul*dt.
 void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const double *tdev, double tmul, double dt,
-                    int parts = GH_GLOBAL | GH_LOCAL, hipStream_t st = nullptr, bool fill_u = false) {
+                    int parts = GH_GLOBAL | GH_LOCAL, hipStream_t st = nullptr, bool fill_u = false,
+                    int phases = PH_ALL) {
   if (!st) st = c->stream;
   for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
     GhostArgs a;
     a.P = c->dP;
     a.pose = pose_slot;
     a.parts = parts;
+    a.phases = phases;
     a.lower = c->dLower;
     a.n_lower = c->nLower;
     a.n_lower_global = c->nLowerGlobal;
@@ -652,8 +658,9 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
 }
 
 // One step as two interleaved chains on two streams: the local chain
-// (global->local fill, local stage kernels) and the global chain (local->global
-// fill, outer ghosts, global stage kernel).  Stage s of one chain waits for
+// (global->local fill, local stage kernels) and the global chain (periodic
+// copies of the local patches, local->global fill, outer ghosts, global stage
+// kernel).  Stage s of one chain waits for
 // stage s-1 of the other, whose output it interpolates from.  A third stream
 // computes the cover flags of the next step (they depend on the poses at
 // t_{n+1} only) while the stages run, and their lists once the last ghost fill
@@ -689,12 +696,20 @@ void enqueue_step_overlap(pw_context *c, double dt) {
       (void)hipEventRecord(c->evG[s], Y);
       continue;
     }
+    // X: global -> local interpolation and its skipped points
     if (s > 0) (void)hipStreamWaitEvent(X, c->evG[s - 1], 0);
-    enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X);
+    enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X, false, PH_INTERP | PH_FALLBACK);
     if (s == 3) (void)hipEventRecord(c->evGhL, X);
+    // Y: the periodic copies of the local patches (they read the local stage
+    // s-1 output; the global chain has time to spare, the local chain has not)
+    if (s > 0) (void)hipStreamWaitEvent(Y, c->evL[s - 1], 0);
+    enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, Y, false, PH_LOWER);
+    (void)hipEventRecord(c->evE[s], Y);
+    // X: local stage kernels
+    (void)hipStreamWaitEvent(X, c->evE[s], 0);
     enqueue_stage_part(c, s, ps, dt, 2, X);
     (void)hipEventRecord(c->evL[s], X);
-    if (s > 0) (void)hipStreamWaitEvent(Y, c->evL[s - 1], 0);
+    // Y: local -> global interpolation, outer ghosts, global stage
     enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, Y);
     if (s == 3) (void)hipEventRecord(c->evGhG, Y);
     enqueue_stage_part(c, s, ps, dt, 1, Y);
@@ -982,6 +997,8 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     c->live = (uint8_t *)dalloc(c, c->gcells);
     c->cover_cur = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
     c->cover_new = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
+    c->ulist = (int2 *)dalloc(c, sizeof(int2) * c->gcells);
+    c->ucount = (int *)dalloc(c, sizeof(int));
     c->efflist = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
     c->effsorted = (int32_t *)dalloc(c, sizeof(int32_t) * c->gcells);
     c->eBkt = (int *)dalloc(c, sizeof(int) * c->gcells);
@@ -994,7 +1011,7 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
       c->dvalid[m] = used ? (uint8_t *)dalloc(c, c->gcells) : nullptr;
       if (used && !c->dvalid[m]) return fail(c, PW_ENOMEM, "device allocation failed");
     }
-    if (!c->flag_cur || !c->flag_new || !c->dbl || !c->t1 || !c->t2 || !c->live || !c->cover_cur || !c->cover_new ||
+    if (!c->flag_cur || !c->flag_new || !c->dbl || !c->t1 || !c->t2 || !c->live || !c->cover_cur || !c->cover_new || !c->ulist || !c->ucount ||
         !c->efflist || !c->effcount)
       return fail(c, PW_ENOMEM, "device allocation failed");
     launch_fill_u8(c->stream, c->flag_cur, c->gcells, LIVE);

@@ -22,7 +22,9 @@ struct StageTile {
 #define TUNE_L2G_RUN 4
 #define DIAG_N 23
 #define BRICK_THREADS 192
+#ifndef BRICK_LDS_BYTES
 #define BRICK_LDS_BYTES 40960
+#endif
 #define L2G_BLOCKS 2048  // a multiple of 8
 #define L2G_WAVES 3
 #define L2G_LDS_BYTES 36864
@@ -122,16 +124,22 @@ struct FinalizeArgs {
   int mode;
   unsigned long long *counters;
   int n[3];
+  int2 *ulist;  // cells that become live: (cell, previous cover id); capacity n0 n1 n2
+  int *ucount;
 };
 
 // Parts of a ghost fill: the global patch's (outer ghosts, effective ghosts)
 // and the local patches' (periodic copies, interpatch bricks).
 enum { GH_GLOBAL = 1, GH_LOCAL = 2 };
+// Phases of one ghost fill (any subset, in this order): the interpatch kernels,
+// the lower-priority value of their skipped points, the outer and periodic fill.
+enum { PH_INTERP = 1, PH_FALLBACK = 2, PH_LOWER = 4, PH_ALL = 7 };
 
 struct GhostArgs {
   const PatchDev *P;
   const PoseDev *pose;
   int parts;
+  int phases;  // PH_* bits (the narrow-buffer order runs them all)
   const GhostRec *lower;  // global-patch entries first, then local-patch entries
   int n_lower, n_lower_global;
   const GBrick *bricks;

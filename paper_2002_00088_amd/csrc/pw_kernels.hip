@@ -1278,53 +1278,25 @@ __global__ void k_fallback(const PatchDev *__restrict__ P, const PoseDev *__rest
 // interpolated from the covering local patch; cells that become deactivated are
 // poisoned (nothing writes a deactivated cell, so it stays poisoned); the new
 // flags become current.  mode 0: first flags (no uncover fill, every deactivated
-// cell poisoned).  Sixteen cells per thread: flags and cover ids move as
-// 16-byte words.
-__device__ inline void finalize_cell(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, long long c,
-                                     uint8_t fo, uint8_t fn, int32_t co, int32_t cn, int nsv, const int *Pts,
-                                     const ExactDev *ex, const double *vs, const double *tdev, int mode,
-                                     unsigned long long *counters) {
-  const PatchDev &G0 = P[0];
+// cell poisoned).  Two kernels: k_finalize streams the flags and cover ids
+// (sixteen cells per thread, 16-byte words), poisons in place and lists the
+// cells that become live; k_uncover fills the listed cells.
+__device__ inline void poison_cell(const PatchDev &G0, long long c, int nsv) {
   const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]),
             k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
   const long long x = cell_index(G0, i, j, k);
-  if (mode == 1 && fo != LIVE && fn == LIVE) {
-    int d = cn >= 1 ? cn : co;
-    const PatchDev &D = P[d >= 1 ? d : 0];
-    const double xr[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
-    double X[3];
-    global_X(G0, pose[0], i, j, k, X);
-    atomicAdd(&counters[3], 1ull);
-    for (int sv = 0; sv < nsv; sv++) {
-      if (!(G0.sv_mask & (1u << sv))) continue;
-      double out[5];
-      bool ok = d >= 1 && (D.sv_mask & (1u << sv)) &&
-                interp_transform<double, double>(D, pose[d], D.u[sv], nullptr, Pts[sv], X, G0, pose[0], xr, out);
-      if (!ok) {
-        atomicAdd(&counters[2], 1ull);
-        if (ex[sv].kind != EX_NONE) exact_patch(ex[sv], vs[sv], G0, pose[0], tdev[0], xr, out);
-        else for (int f = 0; f < 5; f++) out[f] = NAN;
-      }
-      for (int f = 0; f < 5; f++) G0.u[sv][f * G0.fstride + x] = out[f];
-      if (G0.us[sv])
-        for (int f = 0; f < 5; f++) G0.us[sv][f * G0.fstride + x] = (float)out[f];
-    }
-  }
-  if (fn == DEACT && (mode == 0 || fo != DEACT)) {
-    for (int sv = 0; sv < nsv; sv++) {
-      if (!(G0.sv_mask & (1u << sv))) continue;
-      for (int f = 0; f < 5; f++) G0.u[sv][f * G0.fstride + x] = NAN;
-      if (G0.us[sv])
-        for (int f = 0; f < 5; f++) G0.us[sv][f * G0.fstride + x] = NAN;
-    }
+  for (int sv = 0; sv < nsv; sv++) {
+    if (!(G0.sv_mask & (1u << sv))) continue;
+    for (int f = 0; f < 5; f++) G0.u[sv][f * G0.fstride + x] = NAN;
+    if (G0.us[sv])
+      for (int f = 0; f < 5; f++) G0.us[sv][f * G0.fstride + x] = NAN;
   }
 }
 
 #define FIN_CELLS 16
-__global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, uint8_t *flag_cur,
-                           const uint8_t *flag_new, int32_t *cover_cur, int32_t *cover_new, int nsv, const int *Pts,
-                           const ExactDev *ex, const double *vs, const double *tdev, int mode,
-                           unsigned long long *counters) {
+__global__ __launch_bounds__(256) void k_finalize(const PatchDev *__restrict__ P, uint8_t *flag_cur,
+                                                  const uint8_t *flag_new, int32_t *cover_cur, int32_t *cover_new,
+                                                  int nsv, int mode, int2 *ulist, int *ucount) {
   const PatchDev &G0 = P[0];
   const long long total = (long long)G0.n[0] * G0.n[1] * G0.n[2];
   const long long c0 = (long long)FIN_CELLS * ((long long)blockIdx.x * blockDim.x + threadIdx.x);
@@ -1332,24 +1304,22 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
   if (c0 + FIN_CELLS <= total) {
     const uint4 fo16 = *(const uint4 *)(flag_cur + c0), fn16 = *(const uint4 *)(flag_new + c0);
     const uint32_t fow[4] = {fo16.x, fo16.y, fo16.z, fo16.w}, fnw[4] = {fn16.x, fn16.y, fn16.z, fn16.w};
-    // cells to fill (uncovered) or poison (newly deactivated), as a bit mask
-    uint32_t need = 0;
+    uint32_t up = 0, pz = 0;  // cells to fill (become live) and to poison (become deactivated)
 #pragma unroll
     for (int m = 0; m < FIN_CELLS; m++) {
       const uint8_t fo = (uint8_t)(fow[m >> 2] >> (8 * (m & 3))), fn = (uint8_t)(fnw[m >> 2] >> (8 * (m & 3)));
-      const bool uncover = mode == 1 && fo != LIVE && fn == LIVE;
-      const bool poison = fn == DEACT && (mode == 0 || fo != DEACT);
-      need |= (uint32_t)(uncover || poison) << m;
+      up |= (uint32_t)(mode == 1 && fo != LIVE && fn == LIVE) << m;
+      pz |= (uint32_t)(fn == DEACT && (mode == 0 || fo != DEACT)) << m;
     }
-    // rare: one call site, the cover ids read before they are overwritten
-    while (need) {
-      const int m = __ffs(need) - 1;
-      need &= need - 1;
-      const uint32_t wo = m < 4 ? fow[0] : (m < 8 ? fow[1] : (m < 12 ? fow[2] : fow[3]));
-      const uint32_t wn = m < 4 ? fnw[0] : (m < 8 ? fnw[1] : (m < 12 ? fnw[2] : fnw[3]));
-      const long long c = c0 + m;
-      finalize_cell(P, pose, c, (uint8_t)(wo >> (8 * (m & 3))), (uint8_t)(wn >> (8 * (m & 3))), cover_cur[c],
-                    cover_new[c], nsv, Pts, ex, vs, tdev, mode, counters);
+    while (up) {
+      const int m = __ffs(up) - 1;
+      up &= up - 1;
+      ulist[atomicAdd(ucount, 1)] = make_int2((int)(c0 + m), cover_cur[c0 + m]);
+    }
+    while (pz) {
+      const int m = __ffs(pz) - 1;
+      pz &= pz - 1;
+      poison_cell(G0, c0 + m, nsv);
     }
 #pragma unroll
     for (int w = 0; w < 4; w++) {
@@ -1360,11 +1330,102 @@ __global__ void k_finalize(const PatchDev *__restrict__ P, const PoseDev *__rest
   } else {
     for (long long c = c0; c < total; c++) {
       const uint8_t fo = flag_cur[c], fn = flag_new[c];
-      const int32_t co = cover_cur[c], cn = cover_new[c];
-      finalize_cell(P, pose, c, fo, fn, co, cn, nsv, Pts, ex, vs, tdev, mode, counters);
+      if (mode == 1 && fo != LIVE && fn == LIVE) ulist[atomicAdd(ucount, 1)] = make_int2((int)c, cover_cur[c]);
+      if (fn == DEACT && (mode == 0 || fo != DEACT)) poison_cell(G0, c, nsv);
       flag_cur[c] = fn;
-      cover_cur[c] = cn;
+      cover_cur[c] = cover_new[c];
       cover_new[c] = -1;
+    }
+  }
+}
+
+// Weight of node m of the P-point Lagrange stencil at position t from its first
+// node (the same product as lagrange_w).
+__device__ inline double lagrange_node(int P, double t, int m) {
+  double num = 1.0, den = 1.0;
+  for (int l = 0; l < P; l++) {
+    if (l == m) continue;
+    num *= (t - (double)l);
+    den *= (double)(m - l);
+  }
+  return num / den;
+}
+
+// The uncover fill of the listed cells (after k_finalize: cover_cur holds the
+// new cover ids).  The donor is the patch covering the cell now, else the one
+// that covered it during the step.  One wavefront per cell: every lane locates
+// the point (FP64), lane (a, b) < P^2 sums x-node a of row b over the z-layers
+// of the stencil, and the five partial sums are reduced across the wavefront.
+__global__ __launch_bounds__(256) void k_uncover(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose,
+                                                 const int2 *ulist, const int *ucount, const int32_t *cover_cur,
+                                                 int nsv, const int *Pts, const ExactDev *ex, const double *vs,
+                                                 const double *tdev, unsigned long long *counters) {
+  const PatchDev &G0 = P[0];
+  const int n = ucount[0];
+  const int lane = threadIdx.x & 63;
+  const int nwaves = gridDim.x * (blockDim.x >> 6);
+  for (int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < n; q += nwaves) {
+    const long long c = ulist[q].x;
+    const int co = ulist[q].y, cn = cover_cur[c];
+    const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]),
+              k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
+    const long long x = cell_index(G0, i, j, k);
+    const int d = cn >= 1 ? cn : co;
+    const PatchDev &D = P[d >= 1 ? d : 0];
+    const double xr[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
+    double X[3], xd[3];
+    global_X(G0, pose[0], i, j, k, X);
+    if (d >= 1) inv_map(D, pose[d], X, xd);
+    if (lane == 0) atomicAdd(&counters[3], 1ull);
+    for (int sv = 0; sv < nsv; sv++) {
+      if (!(G0.sv_mask & (1u << sv))) continue;
+      const int Pn = Pts[sv];
+      bool ok = d >= 1 && (D.sv_mask & (1u << sv));
+      int s[3] = {0, 0, 0};
+      double t[3] = {0, 0, 0};
+      for (int a = 0; a < 3 && ok; a++) {
+        const double qa = (xd[a] - D.lo[a]) * D.idx[a] - 0.5;
+        ok = qa > -1.0e6 && qa < 1.0e6;
+        if (!ok) break;
+        s[a] = (int)floor(qa - 0.5 * (Pn - 2));
+        t[a] = qa - (double)s[a];
+        ok = D.periodic[a] || (s[a] >= 0 && s[a] + Pn - 1 <= D.n[a] - 1);
+      }
+      double out[5];
+      if (ok) {
+        double acc[5] = {0, 0, 0, 0, 0};
+        if (lane < Pn * Pn) {
+          const int a = lane % Pn, b = lane / Pn;
+          int ii = s[0] + a, jj = s[1] + b;
+          if (D.periodic[0]) ii = ((ii % D.n[0]) + D.n[0]) % D.n[0];
+          if (D.periodic[1]) jj = ((jj % D.n[1]) + D.n[1]) % D.n[1];
+          const double wxy = lagrange_node(Pn, t[0], a) * lagrange_node(Pn, t[1], b);
+          const double *U = D.u[sv];
+          for (int cz = 0; cz < Pn; cz++) {
+            int kk = s[2] + cz;
+            if (D.periodic[2]) kk = ((kk % D.n[2]) + D.n[2]) % D.n[2];
+            const long long xs = cell_index(D, ii, jj, kk);
+            const double w = wxy * lagrange_node(Pn, t[2], cz);
+            for (int f = 0; f < 5; f++) acc[f] += w * U[f * D.fstride + xs];
+          }
+        }
+        for (int f = 0; f < 5; f++)
+          for (int m = 32; m >= 1; m >>= 1) acc[f] += __shfl_xor(acc[f], m);
+        double in4[4] = {acc[1], acc[2], acc[3], acc[4]}, G[3], pit, o4[4];
+        patch_to_bg_at(D, pose[d], X, xd, in4, pit, G);
+        bg_to_patch(G0, pose[0], xr, pit, G, o4);
+        out[0] = acc[0];
+        for (int m = 0; m < 4; m++) out[1 + m] = o4[m];
+      } else {
+        if (lane == 0) atomicAdd(&counters[2], 1ull);
+        if (ex[sv].kind != EX_NONE) exact_patch(ex[sv], vs[sv], G0, pose[0], tdev[0], xr, out);
+        else for (int f = 0; f < 5; f++) out[f] = NAN;
+      }
+      if (lane == 0) {
+        for (int f = 0; f < 5; f++) G0.u[sv][f * G0.fstride + x] = out[f];
+        if (G0.us[sv])
+          for (int f = 0; f < 5; f++) G0.us[sv][f * G0.fstride + x] = (float)out[f];
+      }
     }
   }
 }
@@ -2131,8 +2192,13 @@ void launch_l2g_order(hipStream_t s, const L2GOrderArgs &a) {
 
 void launch_finalize(hipStream_t s, const FinalizeArgs &a) {
   long long tot = (long long)a.n[0] * a.n[1] * a.n[2];
-  hipLaunchKernelGGL(k_finalize, dim3(nblk((tot + FIN_CELLS - 1) / FIN_CELLS, 256)), dim3(256), 0, s, a.P, a.pose, a.flag_cur, a.flag_new,
-                     a.cover_cur, a.cover_new, a.nsv, a.Pts, a.ex, a.vs, a.tdev, a.mode, a.counters);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.ucount, 0);
+  hipLaunchKernelGGL(k_finalize, dim3(nblk((tot + FIN_CELLS - 1) / FIN_CELLS, 256)), dim3(256), 0, s, a.P, a.flag_cur,
+                     a.flag_new, a.cover_cur, a.cover_new, a.nsv, a.mode, a.ulist, a.ucount);
+  if (a.mode == 1)
+    hipLaunchKernelGGL(k_uncover, dim3(64), dim3(256), 0, s, a.P, a.pose, (const int2 *)a.ulist,
+                       (const int *)a.ucount, (const int32_t *)a.cover_cur, a.nsv, a.Pts, a.ex, a.vs, a.tdev,
+                       a.counters);
 }
 
 template <typename TB, typename TC>
@@ -2151,7 +2217,7 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
                          l1 - l0, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
   };
   if (!g2l && !l2g) {
-    lower();
+    if (a.phases & PH_LOWER) lower();
     return;
   }
   auto run_g2l = [&]() {
@@ -2210,11 +2276,13 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
     lower();
     return;
   }
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
-  if (g2l) run_g2l();
-  if (l2g) run_l2g();
-  fallback();
-  lower();
+  if (a.phases & PH_INTERP) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.fb_count, 0);
+    if (g2l) run_g2l();
+    if (l2g) run_l2g();
+  }
+  if (a.phases & PH_FALLBACK) fallback();
+  if (a.phases & PH_LOWER) lower();
 }
 
 void launch_ghosts(hipStream_t s, const GhostArgs &a) {
