@@ -423,11 +423,16 @@ __device__ inline void pulse_eval(double A, const double xc[3], double w, double
     }
     pt *= v;
   } else {
-    double gp = gpulse_der(0, tau + rho, w), gm = gpulse_der(0, tau - rho, w);
-    double g1p = gpulse_der(1, tau + rho, w), g1m = gpulse_der(1, tau - rho, w);
-    phi = (gp - gm) / (2.0 * rho);
-    pt = v * (g1p - g1m) / (2.0 * rho);
-    gf = ((g1p + g1m) / (2.0 * rho) - phi / rho) / rho;
+    // g(s) = s e^{-u^2} and g'(s) = (1 - 2 u^2) e^{-u^2} with u = s / w: one
+    // exponential per sign, reciprocals instead of divisions
+    const double iw = 1.0 / w, up = (tau + rho) * iw, um = (tau - rho) * iw;
+    const double ep = exp(-up * up), em = exp(-um * um);
+    const double gp = (tau + rho) * ep, gm = (tau - rho) * em;
+    const double g1p = (1.0 - 2.0 * up * up) * ep, g1m = (1.0 - 2.0 * um * um) * em;
+    const double irho = 1.0 / rho, i2r = 0.5 * irho;
+    phi = (gp - gm) * i2r;
+    pt = v * (g1p - g1m) * i2r;
+    gf = ((g1p + g1m) * i2r - phi * irho) * irho;
   }
   out[0] = A * phi;
   out[1] = A * pt;
