@@ -384,10 +384,10 @@ def test_narrow_buffer_ablation(B):
         say("  mixed, schedule %d: worst rel err" % sched, compare(cfg, o, g, 2e-5))
 
 
-def _sph_global_cfg(with_overlap):
+def _sph_global_cfg(with_overlap, nr=40):
     # a spherical global shell with a rotated Cartesian patch across its phi seam
     # and (optionally) a second patch overlapping the first one's buffer
-    g0 = W.patch([40, 40, 160], [1.0, 0.6, 0.0], [12.0, math.pi - 0.6, 2 * math.pi], coord=W.SPH, is_global=1,
+    g0 = W.patch([nr, 40, 160], [1.0, 0.6, 0.0], [12.0, math.pi - 0.6, 2 * math.pi], coord=W.SPH, is_global=1,
                  periodic=(0, 0, 1))
     a = W.patch([28, 28, 26], [-3.5, -3.5, -3.2], [3.5, 3.5, 3.2], euler=[0.3, 0.2, 0.1], c0=(6.5, 0.2, -0.1),
                 motion=W.LINEAR, vel=(0.02, -0.03, 0.01))
@@ -398,9 +398,12 @@ def _sph_global_cfg(with_overlap):
     return W._finish(dict(wave_speed=[1.0], interp_points=[6], patches=pats, exact=[ex]))
 
 
-@pytest.mark.parametrize("case", ["fp64", "random", "mixed", "overlap"])
+@pytest.mark.parametrize("case", ["fp64", "random", "mixed", "overlap", "chunked"])
 def test_spherical_global_patch(case):
-    cfg = _sph_global_cfg(case == "overlap")
+    # "chunked": 48 radial cells, a multiple of 16, so the flag filters run on
+    # 16-cell chunks (with the phi axis wrapped); the other cases take the
+    # per-cell filters
+    cfg = _sph_global_cfg(case in ("overlap", "chunked"), nr=48 if case == "chunked" else 40)
     say("spherical global", case)
     o = world_from_config(cfg)
     o.prepare()
