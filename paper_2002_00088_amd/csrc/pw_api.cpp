@@ -54,7 +54,8 @@ struct pw_context {
   hipStream_t stream2 = nullptr;  // second branch of the overlapped step
   hipStream_t stream3 = nullptr;  // third branch: the next step's cover flags and lists
   hipEvent_t evFork = nullptr, evG[4] = {nullptr, nullptr, nullptr, nullptr},
-             evL[4] = {nullptr, nullptr, nullptr, nullptr}, evE[4] = {nullptr, nullptr, nullptr, nullptr};
+             evL[4] = {nullptr, nullptr, nullptr, nullptr}, evE[4] = {nullptr, nullptr, nullptr, nullptr},
+             evGL[4] = {nullptr, nullptr, nullptr, nullptr}, evS[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t evGhL = nullptr, evGhG = nullptr, evNext = nullptr;
   GBrick *dBricks = nullptr;
   int nBricks = 0;
@@ -515,9 +516,10 @@ void enqueue_finalize(pw_context *c, const PoseDev *pose_slot, int mode) {
 // Ghost fill of the buffers of `stage` (0: u) at time tdev[0] + tmul*dt.
 void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const double *tdev, double tmul, double dt,
                     int parts = GH_GLOBAL | GH_LOCAL, hipStream_t st = nullptr, bool fill_u = false,
-                    int phases = PH_ALL) {
+                    int phases = PH_ALL, int sv_only = -1) {
   if (!st) st = c->stream;
   for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
+    if (sv_only >= 0 && sv != sv_only) continue;
     GhostArgs a;
     a.P = c->dP;
     a.pose = pose_slot;
@@ -559,8 +561,9 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
 
 // One stage launch per topology over the tiles of all local patches of that
 // topology.
-void launch_local_groups(pw_context *c, StageArgs a, hipStream_t st) {
+void launch_local_groups(pw_context *c, StageArgs a, hipStream_t st, int topo_mask = 7) {
   for (int t = 0; t < 3; t++) {
+    if (!((topo_mask >> t) & 1)) continue;
     a.tiles = c->dTiles + c->coordTiles[t];
     a.ntiles = c->coordTiles[t + 1] - c->coordTiles[t];
     a.coord = t;
@@ -615,8 +618,10 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
   }
 }
 
-// Stage kernels of the global patch (which = 1) or of the local patches (which = 2).
-void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, double dt, int which, hipStream_t st) {
+// Stage kernels of the global patch (which = 1) or of the local patches (which =
+// 2) of the topologies in topo_mask (bit 0 Cartesian, 1 spherical, 2 cylindrical).
+void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, double dt, int which, hipStream_t st,
+                        int topo_mask = 7) {
   for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
     StageArgs a;
     a.P = c->dP;
@@ -644,10 +649,10 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
     bool all = true;
     for (size_t pid = 1; pid < c->hp.size(); pid++) all = all && (c->hp[pid].sv_mask & (1u << sv));
     if (all) {
-      launch_local_groups(c, a, st);
+      launch_local_groups(c, a, st, topo_mask);
     } else {
       for (size_t pid = 1; pid < c->hp.size(); pid++) {
-        if (!(c->hp[pid].sv_mask & (1u << sv))) continue;
+        if (!(c->hp[pid].sv_mask & (1u << sv)) || !((topo_mask >> c->hp[pid].coord) & 1)) continue;
         a.tiles = c->dTiles + c->tileOff[pid];
         a.ntiles = c->tileCnt[pid];
         a.coord = c->hp[pid].coord;
@@ -657,15 +662,21 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
   }
 }
 
-// One step as two interleaved chains on two streams: the local chain
-// (global->local fill, local stage kernels) and the global chain (periodic
-// copies of the local patches, local->global fill, outer ghosts, global stage
-// kernel).  Stage s of one chain waits for
-// stage s-1 of the other, whose output it interpolates from.  A third stream
-// computes the cover flags of the next step (they depend on the poses at
-// t_{n+1} only) while the stages run, and their lists once the last ghost fill
-// of this step is done; the uncover fill and the swap of the flags follow the
-// last stage.
+// One step as two interleaved chains on two streams plus one for the flags.
+//   X, the local chain: global -> local interpolation of stage s (it reads the
+//     global stage s-1 output), its skipped points, the stage kernels of the
+//     Cartesian local patches.
+//   Y, the global chain: periodic copies of the local patches, local -> global
+//     interpolation of stage s (it reads the local stage s-1 output), outer
+//     ghosts, the global stage kernel, then the stage kernels of the
+//     curvilinear local patches (which need the global -> local fill of X).
+//     The two chains are about equally long this way.
+//   Z: the cover flags of the next step (they depend on the poses at t_{n+1}
+//     only) while the stages run, and their lists once the last ghost fill of
+//     this step is done.
+// The uncover fill and the swap of the flags follow the last stage.  A buffer
+// written at stage s was last read at stage s-2, by kernels that precede the
+// writer through the global stage s-1 or the local stages s-1.
 void enqueue_step_overlap(pw_context *c, double dt) {
   int np = (int)c->hp.size();
   hipStream_t X = c->stream, Y = c->stream2, Z = c->stream3;
@@ -696,30 +707,43 @@ void enqueue_step_overlap(pw_context *c, double dt) {
       (void)hipEventRecord(c->evG[s], Y);
       continue;
     }
-    // X: global -> local interpolation and its skipped points
+    // X: global -> local interpolation (it reads the global stage s-1 output)
+    // and its skipped points (they may copy interior cells of the curvilinear
+    // local patches, written by their stage s-1 kernels on Y)
+    // (state vector by state vector: they share the list of skipped points)
     if (s > 0) (void)hipStreamWaitEvent(X, c->evG[s - 1], 0);
-    enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X, false, PH_INTERP | PH_FALLBACK);
+    for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
+      enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X, false, PH_INTERP, sv);
+      if (sv == 0 && s > 0) (void)hipStreamWaitEvent(X, c->evS[s - 1], 0);
+      enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X, false, PH_FALLBACK, sv);
+    }
+    (void)hipEventRecord(c->evGL[s], X);
     if (s == 3) (void)hipEventRecord(c->evGhL, X);
     // Y: the periodic copies of the local patches (they read the local stage
-    // s-1 output; the global chain has time to spare, the local chain has not)
+    // s-1 output)
     if (s > 0) (void)hipStreamWaitEvent(Y, c->evL[s - 1], 0);
     enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, Y, false, PH_LOWER);
     (void)hipEventRecord(c->evE[s], Y);
-    // X: local stage kernels
+    // X: stage kernels of the Cartesian local patches
     (void)hipStreamWaitEvent(X, c->evE[s], 0);
-    enqueue_stage_part(c, s, ps, dt, 2, X);
+    enqueue_stage_part(c, s, ps, dt, 2, X, 1);
     (void)hipEventRecord(c->evL[s], X);
-    // Y: local -> global interpolation, outer ghosts, global stage
+    // Y: local -> global interpolation, outer ghosts, global stage, then the
+    // stage kernels of the curvilinear local patches (the global chain has time
+    // to spare; the local chain is the longer one)
     enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, Y);
     if (s == 3) (void)hipEventRecord(c->evGhG, Y);
     enqueue_stage_part(c, s, ps, dt, 1, Y);
     (void)hipEventRecord(c->evG[s], Y);
+    (void)hipStreamWaitEvent(Y, c->evGL[s], 0);
+    enqueue_stage_part(c, s, ps, dt, 2, Y, 6);
+    (void)hipEventRecord(c->evS[s], Y);
   }
   (void)hipStreamWaitEvent(Z, c->evGhL, 0);
   (void)hipStreamWaitEvent(Z, c->evGhG, 0);
   enqueue_post_flags(c, c->dPose + 2 * np, Z);
   (void)hipEventRecord(c->evNext, Z);
-  (void)hipStreamWaitEvent(X, c->evG[3], 0);
+  (void)hipStreamWaitEvent(X, narrow ? c->evG[3] : c->evS[3], 0);
   (void)hipStreamWaitEvent(X, c->evNext, 0);
   launch_advance_time(X, c->dT, dt, (long long *)c->dCounters);
   enqueue_finalize(c, c->dPose + 2 * np, 1);
@@ -838,7 +862,9 @@ pw_status pw_create(const pw_config *cfg, pw_context **out) {
   for (int s = 0; s < 4; s++)
     if (hipEventCreateWithFlags(&c->evG[s], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->evL[s], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->evE[s], hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->evE[s], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evGL[s], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evS[s], hipEventDisableTiming) != hipSuccess) {
       pw_destroy(c);
       return PW_EDEVICE;
     }
@@ -1432,6 +1458,8 @@ void pw_destroy(pw_context *c) {
     if (c->evG[s]) (void)hipEventDestroy(c->evG[s]);
     if (c->evL[s]) (void)hipEventDestroy(c->evL[s]);
     if (c->evE[s]) (void)hipEventDestroy(c->evE[s]);
+    if (c->evGL[s]) (void)hipEventDestroy(c->evGL[s]);
+    if (c->evS[s]) (void)hipEventDestroy(c->evS[s]);
   }
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
