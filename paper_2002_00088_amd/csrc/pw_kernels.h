@@ -8,10 +8,16 @@
 // Stage-kernel tiles: TX x TY columns per workgroup; the number of planes a
 // workgroup marches through (the tile depth) is a run-time tuning parameter,
 // one for the global patch and one for local patches.
+#ifndef STAGE_GTX
+#define STAGE_GTX 32
+#endif
+#ifndef STAGE_GTY
+#define STAGE_GTY 8
+#endif
 template <bool GLOB>
 struct StageTile {
-  static constexpr int TX = 32;
-  static constexpr int TY = 8;
+  static constexpr int TX = GLOB ? STAGE_GTX : 32;
+  static constexpr int TY = GLOB ? STAGE_GTY : 8;
   static constexpr int PX = TX + 6, PY = TY + 6, PW = PX * PY;  // LDS plane with a 3-cell halo
   static constexpr int THREADS = TX * TY;
 };
