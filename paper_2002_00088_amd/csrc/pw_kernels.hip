@@ -613,39 +613,69 @@ __global__ void k_bucket_count(const PatchDev *__restrict__ P, const PoseDev *__
                                const int32_t *cover, const int *rank, int *cnt, int *ebkt, int *erank) {
   const PatchDev &G0 = P[0];
   const int n = count[0];
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-    const long long c = list[q];
-    const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]), k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
-    const int d = cover[c];
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int stride = gridDim.x * blockDim.x;
+  // whole wavefronts step through the list together (the ballots below need
+  // every lane)
+  for (int q0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); q0 < n; q0 += stride) {
+    const int q = q0 + lane;
+    const bool act = q < n;
     int b = 0;
-    if (d >= 1) {
-      const PatchDev &D = P[d];
-      double X[3], xd[3];
-      global_X(G0, pose[0], i, j, k, X);
-      inv_map(D, pose[d], X, xd);
-      int bi[3];
-      for (int a = 0; a < 3; a++) {
-        double qq = (xd[a] - D.lo[a]) * D.idx[a];
-        int ii = (qq > -1.0e6 && qq < 1.0e6) ? (int)floor(qq) : 0;
-        if (D.periodic[a]) ii = ((ii % D.n[a]) + D.n[a]) % D.n[a];
-        ii = ii < 0 ? 0 : (ii >= D.n[a] ? D.n[a] - 1 : ii);
-        bi[a] = ii >> 3;
+    if (act) {
+      const long long c = list[q];
+      const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]),
+                k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
+      const int d = cover[c];
+      if (d >= 1) {
+        const PatchDev &D = P[d];
+        double X[3], xd[3];
+        global_X(G0, pose[0], i, j, k, X);
+        inv_map(D, pose[d], X, xd);
+        int bi[3];
+        for (int a = 0; a < 3; a++) {
+          double qq = (xd[a] - D.lo[a]) * D.idx[a];
+          int ii = (qq > -1.0e6 && qq < 1.0e6) ? (int)floor(qq) : 0;
+          if (D.periodic[a]) ii = ((ii % D.n[a]) + D.n[a]) % D.n[a];
+          ii = ii < 0 ? 0 : (ii >= D.n[a] ? D.n[a] - 1 : ii);
+          bi[a] = ii >> 3;
+        }
+        b = D.bkt_base + rank[D.bkt_base + (bi[2] * D.bkt_n[1] + bi[1]) * D.bkt_n[0] + bi[0]];
       }
-      b = D.bkt_base + rank[D.bkt_base + (bi[2] * D.bkt_n[1] + bi[1]) * D.bkt_n[0] + bi[0]];
+      ebkt[q] = b;
     }
-    ebkt[q] = b;
-    erank[q] = atomicAdd(&cnt[b], 1);
+    // neighbouring entries mostly share a bucket: one atomic per distinct bucket
+    // of the wavefront, the lanes ranked in lane order behind its old count
+    unsigned long long todo = __ballot(act);
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int lb = __shfl(b, leader);
+      const unsigned long long same = __ballot(act && b == lb) & todo;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&cnt[lb], __popcll(same));
+      base = __shfl(base, leader);
+      if ((same >> lane) & 1ull) erank[q] = base + __popcll(same & below);
+      todo &= ~same;
+    }
   }
 }
 
 // Exclusive scan of nb bucket counts by one workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_bucket_scan(const int *cnt, int *off, int nb) {
+  // thread t owns a contiguous segment of `per` buckets; its counts are loaded
+  // eight at a time so that the loads are in flight together
   __shared__ int part[1024];
   const int t = threadIdx.x;
   const int per = (nb + 1023) / 1024;
   const int b0 = t * per, b1 = min(nb, b0 + per);
   int s = 0;
-  for (int b = b0; b < b1; b++) s += cnt[b];
+  for (int b = b0; b < b1; b += 8) {
+    int v[8];
+#pragma unroll
+    for (int m = 0; m < 8; m++) v[m] = b + m < b1 ? cnt[b + m] : 0;
+#pragma unroll
+    for (int m = 0; m < 8; m++) s += v[m];
+  }
   part[t] = s;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -655,9 +685,16 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const int *cnt, int *off, 
     __syncthreads();
   }
   int run = part[t] - s;
-  for (int b = b0; b < b1; b++) {
-    off[b] = run;
-    run += cnt[b];
+  for (int b = b0; b < b1; b += 8) {
+    int v[8];
+#pragma unroll
+    for (int m = 0; m < 8; m++) v[m] = b + m < b1 ? cnt[b + m] : 0;
+#pragma unroll
+    for (int m = 0; m < 8; m++)
+      if (b + m < b1) {
+        off[b + m] = run;
+        run += v[m];
+      }
   }
 }
 
@@ -681,23 +718,32 @@ __global__ __launch_bounds__(256) void k_bucket_sort(const int32_t *in, const in
   if (m == 0) return;
   const int o = off[b];
   const int32_t *src = in + o;
-  if (m <= BUCKET_SORT_LDS) {
-    for (int t = threadIdx.x; t < m; t += blockDim.x) keys[t] = src[t];
-    __syncthreads();
-    for (int t = threadIdx.x; t < m; t += blockDim.x) {
-      const int32_t mine = keys[t];
-      int r = 0;
-      for (int u = 0; u < m; u++) r += keys[u] < mine ? 1 : 0;
-      out[o + r] = mine;
-    }
-  } else {
-    for (int t = threadIdx.x; t < m; t += blockDim.x) {
-      const int32_t mine = src[t];
-      int r = 0;
-      for (int u = 0; u < m; u++) r += src[u] < mine ? 1 : 0;
-      out[o + r] = mine;
-    }
+  if (m > BUCKET_SORT_LDS) {
+    // a bucket larger than the LDS tile keeps the scatter order (the order of
+    // the list affects no value, only the locality of the gathers)
+    for (int t = threadIdx.x; t < m; t += blockDim.x) out[o + t] = src[t];
+    return;
   }
+  // bitonic sort of the bucket's cell indices (unique) in LDS, padded to a power of two
+  int m2 = 1;
+  while (m2 < m) m2 <<= 1;
+  for (int t = threadIdx.x; t < m2; t += blockDim.x) keys[t] = t < m ? src[t] : INT32_MAX;
+  __syncthreads();
+  for (int k = 2; k <= m2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < m2; t += blockDim.x) {
+        const int u = t ^ j;
+        if (u > t) {
+          const int32_t x = keys[t], y = keys[u];
+          if ((x > y) == ((t & k) == 0)) {
+            keys[t] = y;
+            keys[u] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int t = threadIdx.x; t < m; t += blockDim.x) out[o + t] = keys[t];
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).  Map
