@@ -565,6 +565,15 @@ def test_full_size_two_patch_one_step():
     say("  worst rel err", compare(cfg, o, g, TOL64))
 
 
+def test_full_size_spherical_one_step():
+    # the spherical workload at full size (256^3 global + a 64 x 64 x 128
+    # spherical shell): its effective ghosts crowd into few donor buckets
+    cfg = W.spherical(seed=3)
+    say("full-size spherical 1 step")
+    o, g = run_pair(cfg, 1)
+    say("  worst rel err", compare(cfg, o, g, TOL64))
+
+
 def test_tuning_changes_no_value():
     # tile depths and XCD run lengths only reorder work: the state after a few
     # steps is bitwise the same
