@@ -742,8 +742,8 @@ void enqueue_step_overlap(pw_context *c, double dt) {
     enqueue_stage_part(c, s, ps, dt, 2, X, 1);
     (void)hipEventRecord(c->evL[s], X);
     // Y: local -> global interpolation, outer ghosts, global stage, then the
-    // stage kernels of the curvilinear local patches (the global chain has time
-    // to spare; the local chain is the longer one)
+    // stage kernels of the curvilinear local patches (they wait for X's fill;
+    // placed here they even out the lengths of the two chains)
     enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, Y);
     if (s == 3) (void)hipEventRecord(c->evGhG, Y);
     enqueue_stage_part(c, s, ps, dt, 1, Y);
