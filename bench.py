@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_GFLOPS = 157300.0  # MI355X vector FP32 (dense)
+FP64_PEAK_GFLOPS = 78600.0  # MI355X vector FP64
 # Algorithmic bytes per live cell per stage kernel launch (five fields).
 # FP64 path: stage 1 reads u, writes acc and v2; stages 2-3 read v_s, u, acc and
 # write acc, v_{s+1}; stage 4 reads v4, acc and writes u (all 8-byte values).
@@ -64,6 +66,22 @@ def load_traffic(workload, precision, dominant):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("kernels", {}).get(dominant)
+
+
+def g2l_points(cfg):
+    """Ghost cells of the local patches filled from the global patch in one
+    stage for the first state vector: the cells of the padded box outside the
+    interior along a non-periodic axis."""
+    tot = 0
+    for p in cfg["patches"][1:]:
+        if not (p["sv_mask"] & 1):
+            continue
+        full = inner = 1
+        for a in range(3):
+            full *= p["n"][a] + 6
+            inner *= p["n"][a] + 6 if p["periodic"][a] else p["n"][a]
+        tot += full - inner
+    return tot
 
 
 def make_config(name):
@@ -253,6 +271,25 @@ def main():
                 "bytes_per_live_cell": sb[dom], "live_cells": int(live_global),
                 "eager_launches": int(kt["gstage_s%d" % (dom + 1)][1]),
                 "measured_copy_GBps": round(copy_gbs, 1), "frac_of_measured_copy": round(achieved / copy_gbs, 4)}
+    # the global -> local interpolation kernel: its algorithmic work per launch
+    # (one state vector, one stage) against the FP32 vector peak; it sums P^3
+    # taps of 5 fields per ghost point out of LDS, so it is bound by LDS and
+    # VALU issue, not by HBM
+    roof_g2l = None
+    if kt["g2l"][1] > 0 and len(cfg["patches"]) > 1:
+        P = cfg["interp_points"][0]
+        pts = g2l_points(cfg)
+        g2l_ms = kt["g2l"][0] / kt["g2l"][1]
+        tc_bytes = 8 if args.precision == "fp64" else 4
+        flops = pts * 2 * 5 * (P ** 3 + P ** 2)
+        peak = FP64_PEAK_GFLOPS if args.precision == "fp64" else FP32_PEAK_GFLOPS
+        roof_g2l = {"bound": "alu", "kernel": "k_g2l_brick (global -> local interpolation)",
+                    "achieved": round(flops / (g2l_ms * 1e-3) / 1e9, 1), "peak": peak, "unit": "GFLOP/s",
+                    "frac": round(flops / (g2l_ms * 1e-3) / 1e9 / peak, 4), "avg_ms": round(g2l_ms, 5),
+                    "points": int(pts), "flops_per_point": 2 * 5 * (P ** 3 + P ** 2),
+                    "lds_bytes_per_point": 5 * P ** 3 * tc_bytes,
+                    "lds_GBps": round(pts * 5 * P ** 3 * tc_bytes / (g2l_ms * 1e-3) / 1e9, 1),
+                    "l2g_avg_ms": round(kt["l2g"][0] / max(1, kt["l2g"][1]), 5)}
     # all stage kernels of each stage (every patch), for reference
     stage_all = {"stage_s%d" % (s + 1): {"avg_ms": round(avg["stage_s%d" % (s + 1)], 5),
                                          "algorithmic_GBps": round(live * sb[s] / (avg["stage_s%d" % (s + 1)] * 1e-3) / 1e9, 1)}
@@ -270,6 +307,7 @@ def main():
                       "schedule": args.schedule + ("" if args.no_graph or args.schedule != "batched" else "+graph"),
                       "dt": dt, "tuning": ctx.tuning()},
            "roofline": roofline,
+           "roofline_interpatch": roof_g2l,
            "stage_kernels_all_patches": stage_all,
            "step_algorithmic_GBps": round(step_bytes / (ms / max(1, args.steps) * 1e-3) / 1e9, 1),
            "kernel_avg_ms": kinds}

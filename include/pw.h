@@ -300,7 +300,9 @@ enum {
   PW_K_FLAGS = 9,    /* cover flags at t_{n+1} */
   PW_K_FINALIZE = 10, /* uncover fill, poison, flag swap */
   PW_K_GSTAGE_S1 = 11, /* the global patch's launch within PW_K_STAGE_S1 + s - 1: PW_K_GSTAGE_S1 + s - 1 */
-  PW_K_NCLASS = 15
+  PW_K_G2L = 15,       /* the global -> local interpolation kernel within a ghost fill (every stage) */
+  PW_K_L2G = 16,       /* the local -> global interpolation kernel within a ghost fill (every stage) */
+  PW_K_NCLASS = 17
 };
 
 /* Enable (on != 0) or disable per-kernel-class timing.  While enabled, steps run

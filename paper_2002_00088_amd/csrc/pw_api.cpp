@@ -778,7 +778,24 @@ void enqueue_step(pw_context *c, double dt) {
     const PoseDev *ps = c->dPose + slot_of_stage[s] * np;
     {
       Timed tm(c, PW_K_GHOST_S1 + s);
-      enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt);
+      if (c->timing && has_locals(c) && !narrow_buffer(c)) {
+        // the interpatch kernels bracketed on their own (their skipped points and
+        // the lower-priority fills follow each part, as in the overlapped step)
+        for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
+          {
+            Timed tg(c, PW_K_G2L);
+            enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, nullptr, false, PH_INTERP, sv);
+          }
+          enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, nullptr, false, PH_FALLBACK | PH_LOWER, sv);
+          {
+            Timed tl(c, PW_K_L2G);
+            enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, nullptr, false, PH_INTERP, sv);
+          }
+          enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, nullptr, false, PH_FALLBACK | PH_LOWER, sv);
+        }
+      } else {
+        enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt);
+      }
     }
     {
       Timed tm(c, PW_K_STAGE_S1 + s);

@@ -38,7 +38,7 @@ EXPORTS = ["pw_create", "pw_create_patch", "pw_set_exact", "pw_init_exact", "pw_
            "pw_diagnostics", "pw_counters", "pw_live_cells", "pw_enable_timing", "pw_kernel_times",
            "pw_get_tuning", "pw_set_tuning", "pw_autotune", "pw_last_error", "pw_destroy"]
 KERNEL_CLASSES = ["pose", "ghost_s1", "ghost_s2", "ghost_s3", "ghost_s4", "stage_s1", "stage_s2", "stage_s3",
-                  "stage_s4", "flags", "finalize", "gstage_s1", "gstage_s2", "gstage_s3", "gstage_s4"]
+                  "stage_s4", "flags", "finalize", "gstage_s1", "gstage_s2", "gstage_s3", "gstage_s4", "g2l", "l2g"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
