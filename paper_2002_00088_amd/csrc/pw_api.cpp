@@ -723,7 +723,10 @@ void enqueue_step_overlap(pw_context *c, double dt) {
     // X: global -> local interpolation (it reads the global stage s-1 output)
     // and its skipped points (they may copy interior cells of the curvilinear
     // local patches, written by their stage s-1 kernels on Y)
-    // (state vector by state vector: they share the list of skipped points)
+    // (state vector by state vector: they share the list of skipped points).
+    // The periodic copies of stage 0 read the previous step's output only: they
+    // go first on X, before the interpolation fills the GPU
+    if (s == 0) enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X, false, PH_LOWER);
     if (s > 0) (void)hipStreamWaitEvent(X, c->evG[s - 1], 0);
     for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
       enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X, false, PH_INTERP, sv);
@@ -734,11 +737,13 @@ void enqueue_step_overlap(pw_context *c, double dt) {
     if (s == 3) (void)hipEventRecord(c->evGhL, X);
     // Y: the periodic copies of the local patches (they read the local stage
     // s-1 output)
-    if (s > 0) (void)hipStreamWaitEvent(Y, c->evL[s - 1], 0);
-    enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, Y, false, PH_LOWER);
-    (void)hipEventRecord(c->evE[s], Y);
+    if (s > 0) {
+      (void)hipStreamWaitEvent(Y, c->evL[s - 1], 0);
+      enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, Y, false, PH_LOWER);
+      (void)hipEventRecord(c->evE[s], Y);
+      (void)hipStreamWaitEvent(X, c->evE[s], 0);
+    }
     // X: stage kernels of the Cartesian local patches
-    (void)hipStreamWaitEvent(X, c->evE[s], 0);
     enqueue_stage_part(c, s, ps, dt, 2, X, 1);
     (void)hipEventRecord(c->evL[s], X);
     // Y: local -> global interpolation, outer ghosts, global stage, then the
