@@ -538,6 +538,13 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.pose = pose_slot;
     a.parts = parts;
     a.phases = phases;
+    // the outer ghosts of a Cartesian, non-periodic global patch with an exact
+    // solution are analytic: the two midpoint stages (same time) share them
+    const PatchDev &g0 = c->hp[0];
+    const bool analytic_outer = g0.coord == CART && !g0.periodic[0] && !g0.periodic[1] && !g0.periodic[2] &&
+                                c->hex[sv].kind != PW_EXACT_NONE && !fill_u;
+    a.lower_dup = analytic_outer && stage == 1 ? 2 : -1;
+    a.lower_skip_global = analytic_outer && stage == 2 ? 1 : 0;
     a.lower = c->dLower;
     a.n_lower = c->nLower;
     a.n_lower_global = c->nLowerGlobal;

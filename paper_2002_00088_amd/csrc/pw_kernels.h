@@ -146,6 +146,10 @@ struct GhostArgs {
   const PoseDev *pose;
   int parts;
   int phases;  // PH_* bits (the narrow-buffer order runs them all)
+  // analytic outer ghosts of the global patch: the first midpoint stage also
+  // writes them into the second one's buffer (lower_dup = that stage, else -1),
+  // and the second skips them (lower_skip_global)
+  int lower_dup, lower_skip_global;
   const GhostRec *lower;  // global-patch entries first, then local-patch entries
   int n_lower, n_lower_global;
   const GBrick *bricks;

@@ -486,7 +486,7 @@ __device__ inline void unpack_ijk(uint32_t c, int &i, int &j, int &k) {
 // else the exact solution (analytic outer boundary) or the nearest interior cell.
 template <typename TB>
 __global__ void k_fill_lower(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const GhostRec *list, int count, int sv, int stage,
-                             const ExactDev *ex, double v, const double *tdev, double tmul, double dt) {
+                             const ExactDev *ex, double v, const double *tdev, double tmul, double dt, int stage2) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= count) return;
   const double t = tdev[0] + tmul * dt;
@@ -511,6 +511,11 @@ __global__ void k_fill_lower(const PatchDev *__restrict__ P, const PoseDev *__re
     double xp[3] = {xnum(p, 0, c[0]), xnum(p, 1, c[1]), xnum(p, 2, c[2])}, e[5];
     exact_patch(ex[sv], v, p, pose[g.patch], t, xp, e);
     for (int f = 0; f < 5; f++) T[f * p.fstride + dst] = (TB)e[f];
+    if (stage2 >= 0) {
+      // a second stage at the same time (the two midpoint stages) gets the same values
+      TB *T2 = stage_buf<TB>(p, sv, stage2);
+      for (int f = 0; f < 5; f++) T2[f * p.fstride + dst] = (TB)e[f];
+    }
   } else {
     for (int a = 0; a < 3; a++) w[a] = w[a] < 0 ? 0 : (w[a] >= p.n[a] ? p.n[a] - 1 : w[a]);
     long long src = cell_index(p, w[0], w[1], w[2]);
@@ -2258,9 +2263,11 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
   // periodic copies of a spherical global then carry the effective ghosts'
   // interpolated values; nothing in the interpatch fills reads these cells
   auto lower = [&]() {
-    if (l1 > l0)
-      hipLaunchKernelGGL(k_fill_lower<TB>, dim3(nblk(l1 - l0, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower + l0,
-                         l1 - l0, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
+    // the global entries are skipped when an earlier stage at the same time wrote them already
+    const int lb = a.lower_skip_global && l0 < a.n_lower_global ? a.n_lower_global : l0;
+    if (l1 > lb)
+      hipLaunchKernelGGL(k_fill_lower<TB>, dim3(nblk(l1 - lb, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower + lb,
+                         l1 - lb, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt, a.lower_dup);
   };
   if (!g2l && !l2g) {
     if (a.phases & PH_LOWER) lower();
@@ -2455,10 +2462,10 @@ void launch_fill_list(hipStream_t s, const PatchDev *P, const PoseDev *pose, con
   if (count <= 0) return;
   if (fp64)
     hipLaunchKernelGGL(k_fill_lower<double>, dim3(nblk(count, 256)), dim3(256), 0, s, P, pose, list, count, sv, 0, ex,
-                       v, tdev, 0.0, 0.0);
+                       v, tdev, 0.0, 0.0, -1);
   else
     hipLaunchKernelGGL(k_fill_lower<float>, dim3(nblk(count, 256)), dim3(256), 0, s, P, pose, list, count, sv, 0, ex,
-                       v, tdev, 0.0, 0.0);
+                       v, tdev, 0.0, 0.0, -1);
 }
 
 void launch_trig_table(hipStream_t s, int n1, int n2, double lo1, double dx1, double lo2, double dx2, double *tab) {
