@@ -51,6 +51,10 @@ struct pw_context {
   GhostRec *dRad = nullptr;
   int nRad = 0;
   bool outer_ready = false;  // their values in u are set (state changes clear it)
+  // analytic outer ghosts of the stage-0 buffer hold the exact solution at the
+  // current time (each step's last stage writes them for the next step; state
+  // changes clear it)
+  bool outer0_ready = false;
   hipStream_t stream2 = nullptr;  // second branch of the overlapped step
   hipStream_t stream3 = nullptr;  // third branch: the next step's cover flags and lists
   hipEvent_t evFork = nullptr, evG[4] = {nullptr, nullptr, nullptr, nullptr},
@@ -294,6 +298,7 @@ pw_status upload_layout(pw_context *c) {
   if (!c->dRad) return fail(c, PW_ENOMEM, "device allocation failed");
   if (!rad.empty()) HIPCHK(c, hipMemcpy(c->dRad, rad.data(), sizeof(GhostRec) * rad.size(), hipMemcpyHostToDevice));
   c->outer_ready = false;
+  c->outer0_ready = false;
   dfree(c, c->dLower);
   dfree(c, c->dBricks);
   c->nLower = (int)lower.size();
@@ -526,6 +531,12 @@ void enqueue_finalize(pw_context *c, const PoseDev *pose_slot, int mode) {
   launch_finalize(c->stream, a);
 }
 
+bool analytic_outer_sv(const pw_context *c, int sv) {
+  const PatchDev &g0 = c->hp[0];
+  return g0.coord == CART && !g0.periodic[0] && !g0.periodic[1] && !g0.periodic[2] &&
+         c->hex[sv].kind != PW_EXACT_NONE;
+}
+
 // Ghost fill of the buffers of `stage` (0: u) at time tdev[0] + tmul*dt.
 void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const double *tdev, double tmul, double dt,
                     int parts = GH_GLOBAL | GH_LOCAL, hipStream_t st = nullptr, bool fill_u = false,
@@ -539,12 +550,11 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.parts = parts;
     a.phases = phases;
     // the outer ghosts of a Cartesian, non-periodic global patch with an exact
-    // solution are analytic: the two midpoint stages (same time) share them
-    const PatchDev &g0 = c->hp[0];
-    const bool analytic_outer = g0.coord == CART && !g0.periodic[0] && !g0.periodic[1] && !g0.periodic[2] &&
-                                c->hex[sv].kind != PW_EXACT_NONE && !fill_u;
-    a.lower_dup = analytic_outer && stage == 1 ? 2 : -1;
-    a.lower_skip_global = analytic_outer && stage == 2 ? 1 : 0;
+    // solution are analytic: the two midpoint stages (same time) share them, and
+    // the last stage (time t_{n+1}) also writes those of the next step's first
+    const bool analytic_outer = analytic_outer_sv(c, sv) && !fill_u;
+    a.lower_dup = analytic_outer && stage == 1 ? 2 : (analytic_outer && stage == 3 ? 0 : -1);
+    a.lower_skip_global = analytic_outer && (stage == 2 || stage == 0) ? 1 : 0;
     a.lower = c->dLower;
     a.n_lower = c->nLower;
     a.n_lower_global = c->nLowerGlobal;
@@ -1121,6 +1131,9 @@ pw_status pw_set_exact(pw_context *c, int32_t sv, const pw_exact_desc *ex) {
     return fail(c, PW_EINVAL, "unknown exact-solution kind");
   }
   c->hex[sv] = e;
+  // whether the outer ghosts are analytic is part of the captured step: recapture
+  c->layout_dirty = true;
+  c->outer0_ready = false;
   HIPCHK(c, hipMemcpyAsync(c->dEx + sv, &c->hex[sv], sizeof(ExactDev), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return PW_OK;
@@ -1144,6 +1157,7 @@ pw_status pw_init_exact(pw_context *c, double t0) {
   c->t_host = t0;
   c->flags_valid = false;
   c->outer_ready = false;
+  c->outer0_ready = false;
   return PW_OK;
 }
 
@@ -1170,6 +1184,7 @@ pw_status pw_set_state(pw_context *c, int32_t pid, int32_t sv, const double *src
   c->t_host = t0;
   c->flags_valid = false;
   c->outer_ready = false;
+  c->outer0_ready = false;
   return PW_OK;
 }
 
@@ -1237,8 +1252,24 @@ pw_status ensure_outer(pw_context *c) {
   return PW_OK;
 }
 
+// The analytic outer ghosts of the stage-0 buffer at the current time, unless
+// the last step wrote them (the step itself does not: its first stage reads them).
+pw_status ensure_outer0(pw_context *c) {
+  if (c->outer0_ready) return PW_OK;
+  const int np = (int)c->hp.size();
+  launch_pose_at(c->stream, c->dP, np, c->t_host, c->dPose + 3 * np);
+  for (int sv = 0; sv < c->cfg.n_state_vectors; sv++)
+    if (analytic_outer_sv(c, sv) && (c->hp[0].sv_mask & (1u << sv)))
+      launch_fill_list(c->stream, c->dP, c->dPose + 3 * np, c->dLower, c->nLowerGlobal, sv, mixed(c) ? 0 : 1, c->dEx,
+                       c->cfg.wave_speed[sv], c->dT);
+  HIPCHK(c, hipGetLastError());
+  c->outer0_ready = true;
+  return PW_OK;
+}
+
 pw_status pw_exchange_ghosts(pw_context *c, double t) {
   if (!c) return PW_EINVAL;
+  c->outer0_ready = false;  // it writes u, not the FP32 copy, at a time of the caller's choosing
   pw_status rc = ensure_flags(c);
   if (rc) return rc;
   rc = ensure_outer(c);
@@ -1273,6 +1304,8 @@ pw_status pw_rk4_step(pw_context *c, double dt, int32_t nsteps) {
   pw_status rc = ensure_flags(c);
   if (rc) return rc;
   rc = ensure_outer(c);
+  if (rc) return rc;
+  rc = ensure_outer0(c);
   if (rc) return rc;
   bool graph = c->cfg.use_graph && c->cfg.schedule == PW_SCHED_BATCHED && !c->timing;
   if (graph && (c->gexec == nullptr || c->graph_dt != dt)) {
