@@ -68,6 +68,7 @@ def lib():
         L.or_time.restype = C.c_double
         L.or_time.argtypes = [vp]
         L.or_counters.argtypes = [vp, C.POINTER(C.c_longlong)]
+        L.or_cover_full.argtypes = [vp, C.POINTER(C.c_int32)]
         L.or_diag.argtypes = [vp, C.c_int, C.c_int, dp]
         L.or_metric_at.argtypes = [vp, C.c_int, C.c_int, C.c_double, dp, dp, dp, dp]
         L.or_jac_at.argtypes = [vp, C.c_int, C.c_double, dp, dp]
@@ -227,9 +228,22 @@ class OracleWorld:
         return self.L.or_time(self.h)
 
     def counters(self):
-        out = (C.c_longlong * 4)()
+        out = (C.c_longlong * 6)()
         self.L.or_counters(self.h, out)
-        return dict(skip_local=out[0], skip_eff=out[1], skip_uncover=out[2], n_uncover=out[3])
+        return dict(skip_local=out[0], skip_eff=out[1], skip_uncover=out[2], n_uncover=out[3],
+                    skip_outer=out[4], n_outer=out[5])
+
+    def cover_full(self):
+        """Covering local patch (or -1) of every cell of the global patch's padded
+        array [n2+6][n1+6][n0+6]: interior cells as in flags(), physical ghost
+        cells (outer ghosts that are not periodic copies) from the covered-ghost
+        list of the current step."""
+        n = self.patches[0]["n"]
+        c = np.empty((n[2] + 2 * NG, n[1] + 2 * NG, n[0] + 2 * NG), dtype=np.int32)
+        rc = self.L.or_cover_full(self.h, c.ctypes.data_as(C.POINTER(C.c_int32)))
+        if rc:
+            raise RuntimeError("oracle flags failed rc=%d" % rc)
+        return c
 
     def diag(self, pid, sv=0):
         out = np.zeros(23)

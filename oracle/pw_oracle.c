@@ -17,6 +17,8 @@
  *   - global->local and local->global exchange via the
  *     background Cartesian frame, skip of uninterpolatable
  *     points                                               (Secs. 2.4.1, 2.4.2)
+ *   - covered physical ghost cells of the global patch
+ *     filled from the covering local patch                 (Sec. 2.4.2, last paragraph)
  *   - cover flags with a buffer of NG+1 live cells, flags
  *     frozen for the whole step                            (Sec. 2.4.2, Fig. cflag)
  *   - plane-wave exact solution, analytic outer BCs         (Sec. 3, Eq. wave_solution)
@@ -34,7 +36,10 @@
  * Lagrange exactness, closed-form spherical, cylindrical and spinning-patch
  * metrics, metrics against finite differences of the inverse map, transform
  * round trips, two-patch convergence order,
- * brute-force flag counts, energy and constraint behaviour).
+ * brute-force flag counts, energy and constraint behaviour; covered physical
+ * ghosts against a brute-force cover test and exact polynomial interpolation,
+ * several state vectors against one-vector worlds, the uncover fill against
+ * polynomial fits through the stencil nodes).
  */
 #include <math.h>
 #include <stdint.h>
@@ -122,7 +127,13 @@ typedef struct {
   int flags_valid;
   uint8_t *flag;            /* global interior cells */
   int32_t *cover;           /* covering local patch or -1 */
+  /* physical ghost cells of the global patch (outer ghosts whose periodic
+   * wrap is not interior), and the local patch covering each one or -1 */
+  int nghost;
+  int32_t *ghost_ijk;       /* 3 per cell */
+  int32_t *gcover;
   long long skip_local, skip_eff, skip_uncover, n_uncover;
+  long long skip_outer, n_outer;
 } or_world;
 
 static long long pcells(const or_patch *p) { return (long long)p->N[0] * p->N[1] * p->N[2]; }
@@ -531,6 +542,12 @@ static void lagrange(int P, double q, int *s, double wts[8]) {
 
 static int wrapi(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
 
+static int is_interior(const or_patch *p, const int c[3]) {
+  for (int a = 0; a < 3; a++)
+    if (c[a] < 0 || c[a] >= p->n[a]) return 0;
+  return 1;
+}
+
 /* Interpolate all fields of buffer T of donor d at background point X, time t.
  * Returns 1 if every stencil cell is a live interior cell, else 0 (skip). */
 static int interp_donor(const or_world *w, int d, int sv, const double *T, double t,
@@ -649,12 +666,50 @@ static int covers(const or_patch *p, double t, const double c[3], const double X
   return 1;
 }
 
+/* list of the physical ghost cells of the global patch: ghost cells whose
+ * periodic wrap is not an interior cell (the outer boundary, not a periodic copy) */
+static void list_physical_ghosts(or_world *w) {
+  if (w->ghost_ijk) return;
+  const or_patch *g = &w->p[0];
+  long long cap = pcells(g), m = 0;
+  w->ghost_ijk = (int32_t *)malloc(3 * cap * sizeof(int32_t));
+  for (int k = -NG; k < g->n[2] + NG; k++)
+    for (int j = -NG; j < g->n[1] + NG; j++)
+      for (int i = -NG; i < g->n[0] + NG; i++) {
+        int c[3] = {i, j, k}, cw[3];
+        if (is_interior(g, c)) continue;
+        for (int a = 0; a < 3; a++) cw[a] = g->periodic[a] ? wrapi(c[a], g->n[a]) : c[a];
+        if (is_interior(g, cw)) continue;
+        w->ghost_ijk[3 * m] = i;
+        w->ghost_ijk[3 * m + 1] = j;
+        w->ghost_ijk[3 * m + 2] = k;
+        m++;
+      }
+  w->nghost = (int)m;
+  w->gcover = (int32_t *)malloc((m > 0 ? m : 1) * sizeof(int32_t));
+  for (long long q = 0; q < m; q++) w->gcover[q] = -1;
+}
+
 /* covered -> live if within `buffer` cells (Chebyshev) of an uncovered cell,
  * else effective ghost if within NG cells of a live cell, else deactivated.
- * Cells outside the global domain count as uncovered. */
-static int compute_flags(or_world *w, double t, uint8_t *flag, int32_t *cover) {
+ * Cells outside the global domain count as uncovered.  Also: the local patch
+ * covering each physical ghost cell of the global patch (gcover, lower id
+ * first), the targets of the covered-ghost fill (Sec. 2.4.2, last paragraph). */
+static int compute_flags(or_world *w, double t, uint8_t *flag, int32_t *cover, int32_t *gcover) {
   const or_patch *g = &w->p[0];
   long long ncell = (long long)g->n[0] * g->n[1] * g->n[2];
+  for (int q = 0; q < w->nghost; q++) gcover[q] = -1;
+  for (int pi = 1; pi < w->np; pi++) {
+    const or_patch *p = &w->p[pi];
+    double cp[3];
+    center_val(p, t, cp);
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < w->nghost; q++) {
+      double X[3];
+      global_X(g, t, w->ghost_ijk[3 * q], w->ghost_ijk[3 * q + 1], w->ghost_ijk[3 * q + 2], X);
+      if (gcover[q] == -1 && covers(p, t, cp, X)) gcover[q] = pi;
+    }
+  }
   /* a cell covered by two local patches keeps the lower patch id; such
    * overlaps are allowed where the cell stays live (the buffers), and are an
    * error anywhere else */
@@ -734,11 +789,6 @@ static int is_live(const or_world *w, const or_patch *p, int i, int j, int k) {
 /* ------------------------------------------------------------------------ */
 static double *bufsel(or_patch *p, int sv, int which) { return which == 0 ? p->u[sv] : p->v[sv]; }
 
-static int is_interior(const or_patch *p, const int c[3]) {
-  for (int a = 0; a < 3; a++)
-    if (c[a] < 0 || c[a] >= p->n[a]) return 0;
-  return 1;
-}
 
 /* level 3a: global -> local, every non-periodic ghost cell of every local patch */
 static void fill_g2l(or_world *w, int which, double t, long long *skips) {
@@ -799,6 +849,37 @@ static void fill_l2g(or_world *w, int which, double t, long long *skips) {
   *skips += sk_e;
 }
 
+/* level 3c: local -> global, covered physical ghost cells of the global patch
+ * (Sec. 2.4.2, last paragraph): an outer ghost cell of the global patch that
+ * lies in a local patch takes the value interpolated from that patch; where
+ * the stencil leaves the local interior the boundary value of levels 1-2
+ * stays (skip).  The Sommerfeld variant evolves its outer ghosts instead. */
+static void fill_outer_covered(or_world *w, int which, double t, long long *skips, long long *targets) {
+  if (w->outer_bc != 0) return;
+  or_patch *g = &w->p[0];
+  long long sk = 0, nt = 0;
+  for (int sv = 0; sv < w->nsv; sv++) {
+    if (!(g->sv_mask & (1u << sv))) continue;
+    double *TG = bufsel(g, sv, which);
+#pragma omp parallel for schedule(dynamic) reduction(+ : sk, nt)
+    for (int q = 0; q < w->nghost; q++) {
+      int d = w->gcover[q];
+      if (d < 0) continue;
+      nt++;
+      int i = w->ghost_ijk[3 * q], j = w->ghost_ijk[3 * q + 1], k = w->ghost_ijk[3 * q + 2];
+      or_patch *p = &w->p[d];
+      double xr[3] = {xnum(g, 0, i), xnum(g, 1, j), xnum(g, 2, k)}, X[3], xd[3], ud[5], ur[5];
+      global_X(g, t, i, j, k, X);
+      int ok = (p->sv_mask & (1u << sv)) && interp_donor(w, d, sv, bufsel(p, sv, which), t, X, ud, xd);
+      if (!ok) { sk++; continue; }
+      transform(p, xd, g, xr, t, ud, ur);
+      for (int f = 0; f < NF; f++) TG[IX(g, f, i, j, k)] = ur[f];
+    }
+  }
+  *skips += sk;
+  *targets += nt;
+}
+
 static void fill_ghosts(or_world *w, int which, double t) {
   long long sk_l = 0, sk_e = 0;
   for (int pi = 0; pi < w->np; pi++) {
@@ -847,6 +928,7 @@ static void fill_ghosts(or_world *w, int which, double t) {
     fill_l2g(w, which, t, &sk_e);
     fill_g2l(w, which, t, &sk_l);
   }
+  fill_outer_covered(w, which, t, &w->skip_outer, &w->n_outer);
   /* periodic copies of the global patch (a spherical global's phi axis) */
   or_patch *g = &w->p[0];
   for (int sv = 0; sv < w->nsv; sv++) {
@@ -1021,7 +1103,8 @@ static void poison_deactivated(or_world *w) {
 
 static int refresh_flags(or_world *w) {
   if (w->np == 1) { w->flags_valid = 1; return 0; }
-  int rc = compute_flags(w, w->t, w->flag, w->cover);
+  list_physical_ghosts(w);
+  int rc = compute_flags(w, w->t, w->flag, w->cover, w->gcover);
   if (rc) return rc;
   poison_deactivated(w);
   w->flags_valid = 1;
@@ -1036,8 +1119,10 @@ static int end_of_step_flags(or_world *w) {
   long long ncell = (long long)g->n[0] * g->n[1] * g->n[2];
   uint8_t *nf = (uint8_t *)malloc(ncell);
   int32_t *nc = (int32_t *)malloc(ncell * sizeof(int32_t));
-  int rc = compute_flags(w, w->t, nf, nc);
-  if (rc) { free(nf); free(nc); return rc; }
+  list_physical_ghosts(w);
+  int32_t *ngc = (int32_t *)malloc((w->nghost > 0 ? w->nghost : 1) * sizeof(int32_t));
+  int rc = compute_flags(w, w->t, nf, nc, ngc);
+  if (rc) { free(nf); free(nc); free(ngc); return rc; }
   long long sk = 0, nu = 0;
   for (int sv = 0; sv < w->nsv; sv++) {
     if (!(g->sv_mask & (1u << sv))) continue;
@@ -1067,8 +1152,10 @@ static int end_of_step_flags(or_world *w) {
   w->n_uncover += nu;
   memcpy(w->flag, nf, ncell);
   memcpy(w->cover, nc, ncell * sizeof(int32_t));
+  memcpy(w->gcover, ngc, (w->nghost > 0 ? w->nghost : 1) * sizeof(int32_t));
   free(nf);
   free(nc);
+  free(ngc);
   poison_deactivated(w);
   return 0;
 }
@@ -1130,6 +1217,8 @@ void or_free(or_world *w) {
     }
   free(w->flag);
   free(w->cover);
+  free(w->ghost_ijk);
+  free(w->gcover);
   free(w);
 }
 
@@ -1321,9 +1410,26 @@ int or_step(or_world *w, double dt, int nsteps) {
 
 double or_time(const or_world *w) { return w->t; }
 
-/* counters: skip_local, skip_eff, skip_uncover, n_uncover */
+/* counters: skip_local, skip_eff, skip_uncover, n_uncover, skip_outer, n_outer */
 void or_counters(const or_world *w, long long *out) {
   out[0] = w->skip_local; out[1] = w->skip_eff; out[2] = w->skip_uncover; out[3] = w->n_uncover;
+  out[4] = w->skip_outer; out[5] = w->n_outer;
+}
+
+/* covering local patch (or -1) of every cell of the global patch's padded
+ * array, [N2][N1][N0]: interior cells from the cover flags, physical ghost
+ * cells from the covered-ghost list, periodic ghost copies -1 */
+int or_cover_full(or_world *w, int32_t *dst) {
+  if (w->np < 1) return -1;
+  if (!w->flags_valid) { int rc = refresh_flags(w); if (rc) return rc; }
+  const or_patch *g = &w->p[0];
+  for (long long x = 0; x < pcells(g); x++) dst[x] = -1;
+  for (int k = 0; k < g->n[2]; k++)
+    for (int j = 0; j < g->n[1]; j++)
+      for (int i = 0; i < g->n[0]; i++) dst[IX(g, 0, i, j, k)] = w->cover[GIX(g, i, j, k)];
+  for (int q = 0; q < w->nghost; q++)
+    dst[IX(g, 0, w->ghost_ijk[3 * q], w->ghost_ijk[3 * q + 1], w->ghost_ijk[3 * q + 2])] = w->gcover[q];
+  return 0;
 }
 
 /*
