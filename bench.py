@@ -101,24 +101,55 @@ def make_config(name):
     raise SystemExit("unknown workload " + name)
 
 
-def cpu_baseline(cfg, steps=1):
-    """The FP64 oracle as it stands, one RK4 step of the full workload on every
-    host core (OpenMP), as live cell-updates per second."""
-    from oracle.oracle import world_from_config
-    w = world_from_config(cfg)
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_sample_config(name):
+    """Bounded CPU sample of a workload: the same recipe at a smaller size (the
+    batched workload scaled to a 96^3 global patch with 9-36 cells per local axis,
+    about 5% of its cells), else the workload itself."""
+    from paper_2002_00088_amd import workloads as W
+    if name.startswith("batched"):
+        return W.batched(seed=4, ng=96, nmin=9, nmax=36)
+    return None
+
+
+def cpu_baseline(cfg, reps=3):
+    """The FP64 oracle as it stands, one RK4 step of a bounded sample of the
+    workload, on one thread and on every host core (OpenMP), median of `reps`
+    runs each, as live cell-updates per second."""
+    from oracle.oracle import set_threads, world_from_config
+    sample = cpu_sample_config(cfg["name"]) or cfg
+    w = world_from_config(sample)
     w.init_exact(0.0)
     w.prepare()
     f, _ = w.flags()
-    live = int((f == 0).sum()) + sum(int(p["n"][0] * p["n"][1] * p["n"][2]) for p in cfg["patches"][1:])
-    t0 = time.perf_counter()
-    w.step(cfg["dt"], steps)
-    sec = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    cores = min(cores, os.cpu_count() or cores)
+    live = int((f == 0).sum()) + sum(int(p["n"][0] * p["n"][1] * p["n"][2]) for p in sample["patches"][1:])
+    all_cores = set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    res = {}
+    for th in (all_cores, 1):
+        used = set_threads(th)
+        secs = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            w.step(sample["dt"], 1)
+            secs.append(time.perf_counter() - t0)
+        res[used] = sorted(secs)[len(secs) // 2]
+    set_threads(all_cores)
     w.close()
-    return dict(value=live * steps / sec, unit="cell-updates/s", cores=cores, kind="oracle",
-                sample="%d RK4 step(s) of the full %s workload (%d live cells), FP64, %.1f s" % (
-                    steps, cfg["name"], live, sec))
+    return dict(value=live / res[all_cores], unit="cell-updates/s", cores=all_cores, kind="oracle",
+                one_thread=dict(value=live / res[1], cores=1, median_s=round(res[1], 3)),
+                median_s=round(res[all_cores], 3), reps=reps, cpu_model=cpu_model(),
+                sample="one RK4 step of the %s workload (%d patches, %d live cells; the same recipe as %s at a "
+                       "smaller size), FP64, median of %d" % (sample["name"], len(sample["patches"]), live,
+                                                             cfg["name"], reps))
 
 
 def copy_bandwidth(torch, stream, nbytes=1 << 30, reps=5):
@@ -250,56 +281,104 @@ def main():
     ctx.enable_timing(False)
     sb = STAGE_BYTES[args.precision]
     avg = {k: v[0] / max(1, v[1]) for k, v in kt.items()}
-    # dominant kernel: the fused RHS + RK stage kernel over the global patch (one
-    # launch; the same launch in the graph and in the eager pass), at the stage
-    # with the longest launch
+    nts = max(1, args.timing_steps)
     local_cells = sum(int(p["n"][0] * p["n"][1] * p["n"][2]) for p in cfg["patches"][1:])
     live_global = live - local_cells
-    dom = max(range(4), key=lambda s: avg["gstage_s%d" % (s + 1)])
-    g_ms = avg["gstage_s%d" % (dom + 1)]
-    bytes_launch = live_global * sb[dom]
-    achieved = bytes_launch / (g_ms * 1e-3) / 1e9
     ty = "double, double, double" if args.precision == "fp64" else "float, float, float"
+    tb = "double" if args.precision == "fp64" else "float"
     am = 1 if args.precision == "mixed_inc" else 0
-    dominant_name = "k_stage<%s, %d, 0, true, %d, 0>" % (ty, dom, am)
-    traffic = load_traffic(cfg["name"], args.precision, dominant_name)
+    P = cfg["interp_points"][0]
+    # GPU time per step of each single kernel (one kernel name in a profile) from
+    # the eager pass: the interpolation kernels launch once per stage and state
+    # vector, each global stage kernel once per step
+    per_step = {}
+    if kt["g2l"][1] > 0:
+        per_step["g2l"] = kt["g2l"][0] / nts
+    if kt["l2g"][1] > 0:
+        per_step["l2g"] = kt["l2g"][0] / nts
+    for st in range(4):
+        per_step["gstage_s%d" % (st + 1)] = kt["gstage_s%d" % (st + 1)][0] / nts
+    eager_step_ms = sum(v[0] for k, v in kt.items() if k not in ("g2l", "l2g") and not k.startswith("gstage")) / nts
+    dom_key = max(per_step, key=per_step.get)
     copy_gbs = copy_bandwidth(torch, stream)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dominant_name + " (RHS + RK stage %d, global patch)" % (dom + 1),
-                "avg_ms": round(g_ms, 5), "algorithmic_bytes_per_launch": int(bytes_launch),
-                "bytes_per_live_cell": sb[dom], "live_cells": int(live_global),
-                "eager_launches": int(kt["gstage_s%d" % (dom + 1)][1]),
-                "measured_copy_GBps": round(copy_gbs, 1), "frac_of_measured_copy": round(achieved / copy_gbs, 4)}
-    # the global -> local interpolation kernel: its algorithmic work per launch
-    # (one state vector, one stage) against the FP32 vector peak; it sums P^3
-    # taps of 5 fields per ghost point out of LDS, so it is bound by LDS and
-    # VALU issue, not by HBM
-    roof_g2l = None
-    if kt["g2l"][1] > 0 and len(cfg["patches"]) > 1:
-        P = cfg["interp_points"][0]
+    tc_bytes = 8 if args.precision == "fp64" else 4
+
+    def stage_roof(st):
+        # the fused RHS + RK stage kernel over the global patch, stage st (HBM-bound)
+        name = "k_stage<%s, %d, 0, true, %d, 0>" % (ty, st, am)
+        g_ms = avg["gstage_s%d" % (st + 1)]
+        b = live_global * sb[st]
+        a = b / (g_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(a / HBM_PEAK_GBS, 4), "traffic": load_traffic(cfg["name"], args.precision, name),
+                "kernel": name + " (RHS + RK stage %d, global patch)" % (st + 1), "avg_ms": round(g_ms, 5),
+                "algorithmic_bytes_per_launch": int(b), "bytes_per_live_cell": sb[st], "live_cells": int(live_global),
+                "eager_launches": int(kt["gstage_s%d" % (st + 1)][1]),
+                "measured_copy_GBps": round(copy_gbs, 1), "frac_of_measured_copy": round(a / copy_gbs, 4)}
+
+    def g2l_roof():
+        # the global -> local interpolation kernel: 2 P^3 flops per field per ghost
+        # point (a multiply and an add per tap), one state vector and one stage per
+        # launch, against the FP32 vector peak; its taps come out of LDS
+        name = "k_g2l_brick<%s, %s, %d>" % (tb, "double" if args.precision == "fp64" else "float", P)
         pts = g2l_points(cfg)
-        g2l_ms = kt["g2l"][0] / kt["g2l"][1]
-        tc_bytes = 8 if args.precision == "fp64" else 4
-        flops = pts * 2 * 5 * (P ** 3 + P ** 2)
+        g_ms = kt["g2l"][0] / kt["g2l"][1]
+        flops = pts * 2 * 5 * P ** 3
         peak = FP64_PEAK_GFLOPS if args.precision == "fp64" else FP32_PEAK_GFLOPS
-        roof_g2l = {"bound": "alu", "kernel": "k_g2l_brick (global -> local interpolation)",
-                    "achieved": round(flops / (g2l_ms * 1e-3) / 1e9, 1), "peak": peak, "unit": "GFLOP/s",
-                    "frac": round(flops / (g2l_ms * 1e-3) / 1e9 / peak, 4), "avg_ms": round(g2l_ms, 5),
-                    "points": int(pts), "flops_per_point": 2 * 5 * (P ** 3 + P ** 2),
-                    "lds_bytes_per_point": 5 * P ** 3 * tc_bytes,
-                    "lds_GBps": round(pts * 5 * P ** 3 * tc_bytes / (g2l_ms * 1e-3) / 1e9, 1),
-                    "l2g_avg_ms": round(kt["l2g"][0] / max(1, kt["l2g"][1]), 5)}
+        a = flops / (g_ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": round(a, 3), "peak": peak / 1e3, "unit": "TFLOP/s",
+                "frac": round(a / (peak / 1e3), 4), "traffic": load_traffic(cfg["name"], args.precision, name),
+                "kernel": name + " (global -> local interpolation)", "avg_ms": round(g_ms, 5),
+                "points_per_launch": int(pts), "flops_per_point": 2 * 5 * P ** 3,
+                "algorithmic_flops_per_launch": int(flops), "eager_launches": int(kt["g2l"][1]),
+                "lds_bytes_per_point": 5 * P ** 3 * tc_bytes,
+                "lds_read_TBps": round(pts * 5 * P ** 3 * tc_bytes / (g_ms * 1e-3) / 1e12, 2)}
+
+    def l2g_roof():
+        name = "k_l2g_box<%s, %s, %d>" % (tb, "double" if args.precision == "fp64" else "float", P)
+        f, _ = ctx.flags()
+        pts = int((f == 1).sum())
+        g_ms = kt["l2g"][0] / kt["l2g"][1]
+        flops = pts * 2 * 5 * P ** 3
+        peak = FP64_PEAK_GFLOPS if args.precision == "fp64" else FP32_PEAK_GFLOPS
+        a = flops / (g_ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": round(a, 3), "peak": peak / 1e3, "unit": "TFLOP/s",
+                "frac": round(a / (peak / 1e3), 4), "traffic": load_traffic(cfg["name"], args.precision, name),
+                "kernel": name + " (local -> global interpolation)", "avg_ms": round(g_ms, 5),
+                "points_per_launch": pts, "flops_per_point": 2 * 5 * P ** 3, "eager_launches": int(kt["l2g"][1])}
+
+    if dom_key == "g2l":
+        roofline = g2l_roof()
+    elif dom_key == "l2g":
+        roofline = l2g_roof()
+    else:
+        roofline = stage_roof(int(dom_key[-1]) - 1)
+    tot_eager = sum(per_step.values()) + eager_step_ms
+    roofline["share_of_eager_step"] = round(per_step[dom_key] / tot_eager, 4)
+    roofline["per_step_ms"] = round(per_step[dom_key], 5)
+    # the HBM-bound stage kernel over the global patch at its step-average bytes
+    # per live cell-stage (the four launches' mean duration)
+    g_avg_ms = sum(avg["gstage_s%d" % (st + 1)] for st in range(4)) / 4
+    b_avg = live_global * sum(sb) / 4
+    a_avg = b_avg / (g_avg_ms * 1e-3) / 1e9
+    roof_stage = {"bound": "hbm", "achieved": round(a_avg, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(a_avg / HBM_PEAK_GBS, 4), "kernel": "k_stage (global patch, mean of stages 1-4)",
+                  "bytes_per_live_cell_stage": sum(sb) / 4, "avg_ms": round(g_avg_ms, 5),
+                  "frac_of_measured_copy": round(a_avg / copy_gbs, 4),
+                  "per_stage": [stage_roof(st) for st in range(4)]}
+    roof_interp = {"g2l": g2l_roof() if kt["g2l"][1] > 0 else None, "l2g": l2g_roof() if kt["l2g"][1] > 0 else None}
     # all stage kernels of each stage (every patch), for reference
     stage_all = {"stage_s%d" % (s + 1): {"avg_ms": round(avg["stage_s%d" % (s + 1)], 5),
                                          "algorithmic_GBps": round(live * sb[s] / (avg["stage_s%d" % (s + 1)] * 1e-3) / 1e9, 1)}
                  for s in range(4)}
     step_bytes = live * sum(sb)
+    step_ms = ms / max(1, args.steps)
+    step_gbs = step_bytes / (step_ms * 1e-3) / 1e9
     kinds = {k: round(v, 5) for k, v in avg.items()}
 
     out = {"metric": "cell-updates/s per RK4 step (incl. ghost interp); HBM GB/s vs peak",
            "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": ms / max(1, args.steps), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": DTYPE[args.precision], "data": "synthetic",
            "config": {"workload": cfg["name"], "global_cells": cfg["patches"][0]["n"],
                       "local_patches": len(cfg["patches"]) - 1, "live_cells": int(live),
@@ -307,9 +386,13 @@ def main():
                       "schedule": args.schedule + ("" if args.no_graph or args.schedule != "batched" else "+graph"),
                       "dt": dt, "tuning": ctx.tuning()},
            "roofline": roofline,
-           "roofline_interpatch": roof_g2l,
+           "step_hbm": {"achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(step_gbs / HBM_PEAK_GBS, 4), "target_frac": 0.6,
+                        "bytes_per_live_cell_step": sum(sb), "measured_copy_GBps": round(copy_gbs, 1)},
+           "roofline_stage": roof_stage,
+           "roofline_interpatch": roof_interp,
            "stage_kernels_all_patches": stage_all,
-           "step_algorithmic_GBps": round(step_bytes / (ms / max(1, args.steps) * 1e-3) / 1e9, 1),
+           "kernel_per_step_ms": {k: round(v, 5) for k, v in per_step.items()},
            "kernel_avg_ms": kinds}
     n_total = args.warmup + args.steps + args.timing_steps
 

@@ -44,8 +44,9 @@ enum {
   PW_EDEVICE = -3,  /* a HIP runtime call failed */
   PW_ESTATE = -4,   /* call not valid in the current state (e.g. no global patch) */
   PW_EOVERLAP = -5, /* two local patches cover a global cell that is not live (Sec. 2.4.2) */
-  PW_EMOTION = -6   /* a patch moves one global cell or more within a step: the NG+1 buffer
-                       covers at most one cell of motion per step (Sec. 2.4.2) */
+  PW_EMOTION = -6   /* a patch moves max(1, buffer_width - NG) global cells or more within a
+                       step: the NG+1 buffer covers one cell of motion per step and a wider
+                       buffer relaxes the bound (Sec. 2.4.2) */
 };
 
 enum { PW_FP64 = 0, PW_MIXED = 1, PW_MIXED_INC = 2 }; /* precision */
@@ -202,16 +203,25 @@ typedef struct {
  *   skip_uncover: cells that became live at a step end and could not be interpolated
  *   n_uncover:    cells that became live at a step end
  *   steps:        RK4 steps taken
+ *   skip_outer:   covered physical ghost cells of the global patch (outer ghosts
+ *                 that are not periodic copies, lying in a local patch; Sec. 2.4.2,
+ *                 last paragraph) whose local stencil left the interior: they keep
+ *                 their boundary value
+ *   n_outer:      covered physical ghost cells filled or attempted, summed over
+ *                 ghost fills and state vectors
  */
 typedef struct {
   int64_t skip_local, skip_eff, skip_uncover, n_uncover, steps;
+  int64_t skip_outer, n_outer;
 } pw_counters_t;
 
 /* Create a context.  cfg is copied.  *out receives the context on success. */
 pw_status pw_create(const pw_config *cfg, pw_context **out);
 
 /* Add a patch; the first one is the global patch.  *id_out receives its id
- * (0 for the global patch, 1.. for local patches).  Allocates its device buffers. */
+ * (0 for the global patch, 1.. for local patches).  Allocates its device buffers.
+ * PW_EINVAL if an axis has more than 1017 cells or the five padded fields of the
+ * patch ([n2+6][n1+6][row pitch]) hold 2^32 elements or more (about 940^3 cells). */
 pw_status pw_create_patch(pw_context *ctx, const pw_patch_desc *desc, int32_t *id_out);
 
 /* Register the exact solution of state vector sv (copied). */
@@ -242,7 +252,10 @@ pw_status pw_get_flags(pw_context *ctx, uint8_t *flags, int32_t *cover, int64_t 
 /* Fill the ghost cells of u at time t in the order boundary -> periodic ->
  * interpatch (Sec. 2.4, Fig. BC_order): analytic outer ghosts (or nearest copy),
  * periodic copies, then global->local and local->global interpolation with the
- * frame transform through the background frame (Secs. 2.4.1-2.4.2). */
+ * frame transform through the background frame (Secs. 2.4.1-2.4.2).  Outer
+ * ghost cells of the global patch that lie in a local patch are local->global
+ * targets too, over their boundary value (Sec. 2.4.2, last paragraph; not with
+ * PW_BC_SOMMERFELD, which evolves them). */
 pw_status pw_exchange_ghosts(pw_context *ctx, double t);
 
 /* Advance nsteps classic-RK4 steps of size dt (Sec. 2.3, Table rk4): per stage a
@@ -251,8 +264,8 @@ pw_status pw_exchange_ghosts(pw_context *ctx, double t);
  * flags are computed at t_n and frozen for the step, maps follow the substep times,
  * and cells that become live at the step end are interpolated from the covering
  * local patch (Sec. 2.4.2).  Returns PW_EMOTION before launching if a patch
- * would move a global cell or more in one step, PW_EOVERLAP if two local patches
- * cover one global cell. */
+ * would move max(1, buffer_width - 3) global cells or more in one step,
+ * PW_EOVERLAP if two local patches cover one global cell that is not live. */
 pw_status pw_rk4_step(pw_context *ctx, double dt, int32_t nsteps);
 
 /* Run-time tuning parameters.  None changes a computed value: every setting

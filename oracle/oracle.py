@@ -69,6 +69,8 @@ def lib():
         L.or_time.argtypes = [vp]
         L.or_counters.argtypes = [vp, C.POINTER(C.c_longlong)]
         L.or_cover_full.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_max_threads.restype = C.c_int
         L.or_diag.argtypes = [vp, C.c_int, C.c_int, dp]
         L.or_metric_at.argtypes = [vp, C.c_int, C.c_int, C.c_double, dp, dp, dp, dp]
         L.or_jac_at.argtypes = [vp, C.c_int, C.c_double, dp, dp]
@@ -340,6 +342,12 @@ class OracleWorld:
 
     def stencil(self, pid, op, d, e, i, j, k, sv=0):
         return self.L.or_stencil(self.h, pid, sv, op, d, e, i, j, k)
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (timing runs); returns the new maximum."""
+    lib().or_set_threads(int(n))
+    return lib().or_max_threads()
 
 
 def lagrange(P, q):

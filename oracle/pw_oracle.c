@@ -46,6 +46,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NG 3           /* ghost width (Sec. 2.4.2: NG = 3) */
 #define NF 5           /* phi, Pi_t, Pi_x, Pi_y, Pi_z */
@@ -1409,6 +1412,23 @@ int or_step(or_world *w, double dt, int nsteps) {
 }
 
 double or_time(const or_world *w) { return w->t; }
+
+/* number of OpenMP threads of the oracle's loops (timing runs only) */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int or_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* counters: skip_local, skip_eff, skip_uncover, n_uncover, skip_outer, n_outer */
 void or_counters(const or_world *w, long long *out) {

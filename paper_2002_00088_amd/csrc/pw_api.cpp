@@ -47,6 +47,13 @@ struct pw_context {
   // lists
   GhostRec *dLower = nullptr;
   int nLower = 0, nLowerGlobal = 0;
+  // physical ghost cells of the global patch (outer ghosts that are not
+  // periodic copies) and the lists of those covered by a local patch:
+  // olist[0]/ocount[0] of the running step, olist[1]/ocount[1] of the next
+  GhostRec *dPhys = nullptr;
+  int nPhys = 0;
+  int2 *olist[2] = {nullptr, nullptr};
+  int *ocount[2] = {nullptr, nullptr};
   // Sommerfeld outer boundary: the global patch's outer ghost cells (evolved)
   GhostRec *dRad = nullptr;
   int nRad = 0;
@@ -85,6 +92,10 @@ struct pw_context {
   bool layout_dirty = true, flags_valid = false;
   pw_tuning tune = {TUNE_TZ_GLOBAL, TUNE_TZ_LOCAL, TUNE_G2L_RUN, TUNE_L2G_RUN};
   double t_host = 0.0;
+  // first failure of a runtime call while a step is enqueued (event records and
+  // waits between the step's streams); reported by pw_rk4_step
+  hipError_t enq_err = hipSuccess;
+  const char *enq_what = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   double graph_dt = 0.0;
@@ -111,6 +122,15 @@ pw_status fail(pw_context *c, pw_status code, const std::string &msg) {
     if (e_ != hipSuccess)                                                              \
       return fail(ctx, PW_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// Record the first failing runtime call of an enqueue sequence.
+void enq_check(pw_context *c, hipError_t e, const char *what) {
+  if (e != hipSuccess && c->enq_err == hipSuccess) {
+    c->enq_err = e;
+    c->enq_what = what;
+  }
+}
+#define ENQ(ctx, call) enq_check(ctx, (call), #call)
 
 void *dalloc(pw_context *c, size_t bytes) {
   void *p = nullptr;
@@ -236,7 +256,7 @@ pw_status upload_layout(pw_context *c) {
   // the interpatch targets of every local patch as bricks of at most 8x8x3 cells
   // on its six faces (z faces span the full padded x-y range, y faces the full
   // padded x range, x faces the interior y-z range, so the faces are disjoint).
-  std::vector<GhostRec> lower, rad;
+  std::vector<GhostRec> lower, rad, phys;
   std::vector<GBrick> bricks;
   const bool somm = c->cfg.outer_bc == PW_BC_SOMMERFELD;
   for (int pid = 0; pid < np; pid++) {
@@ -256,6 +276,9 @@ pw_status upload_layout(pw_context *c) {
             rad.push_back(GhostRec{pid, pack_ijk(i, j, k)});
           else if (wrapped_inside || p.is_global)
             lower.push_back(GhostRec{pid, pack_ijk(i, j, k)});
+          // covered physical ghosts (Sec. 2.4.2) are interpatch targets unless
+          // the Sommerfeld variant evolves them
+          if (p.is_global && !wrapped_inside && !somm && np > 1) phys.push_back(GhostRec{pid, pack_ijk(i, j, k)});
         }
     if (p.is_global) {
       c->nLowerGlobal = (int)lower.size();
@@ -299,6 +322,23 @@ pw_status upload_layout(pw_context *c) {
   if (!rad.empty()) HIPCHK(c, hipMemcpy(c->dRad, rad.data(), sizeof(GhostRec) * rad.size(), hipMemcpyHostToDevice));
   c->outer_ready = false;
   c->outer0_ready = false;
+  dfree(c, c->dPhys);
+  for (int m = 0; m < 2; m++) {
+    dfree(c, c->olist[m]);
+    dfree(c, c->ocount[m]);
+  }
+  c->nPhys = (int)phys.size();
+  c->dPhys = (GhostRec *)dalloc(c, sizeof(GhostRec) * std::max<size_t>(1, phys.size()));
+  for (int m = 0; m < 2; m++) {
+    c->olist[m] = (int2 *)dalloc(c, sizeof(int2) * std::max<size_t>(1, phys.size()));
+    c->ocount[m] = (int *)dalloc(c, sizeof(int));
+    if (!c->olist[m] || !c->ocount[m]) return fail(c, PW_ENOMEM, "device allocation failed");
+  }
+  if (!c->dPhys) return fail(c, PW_ENOMEM, "device allocation failed");
+  if (!phys.empty())
+    HIPCHK(c, hipMemcpy(c->dPhys, phys.data(), sizeof(GhostRec) * phys.size(), hipMemcpyHostToDevice));
+  launch_fill_i32(c->stream, c->ocount[0], 1, 0);
+  launch_fill_i32(c->stream, c->ocount[1], 1, 0);
   dfree(c, c->dLower);
   dfree(c, c->dBricks);
   c->nLower = (int)lower.size();
@@ -469,6 +509,10 @@ void enqueue_flags(pw_context *c, const PoseDev *pose_slot, hipStream_t st) {
   a.dbl = c->dbl;
   a.buffer = c->cfg.buffer_width;
   a.err = c->dErr;
+  a.phys = c->dPhys;
+  a.nphys = c->nPhys;
+  a.olist = c->olist[1];
+  a.ocount = c->ocount[1];
   launch_flags(st, a);
 }
 
@@ -528,6 +572,11 @@ void enqueue_finalize(pw_context *c, const PoseDev *pose_slot, int mode) {
   for (int d = 0; d < 3; d++) a.n[d] = c->hp[0].n[d];
   a.ulist = c->ulist;
   a.ucount = c->ucount;
+  a.olist_new = c->olist[1];
+  a.ocount_new = c->ocount[1];
+  a.olist_cur = c->olist[0];
+  a.ocount_cur = c->ocount[0];
+  a.nphys = c->nPhys;
   launch_finalize(c->stream, a);
 }
 
@@ -585,6 +634,9 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.l2g_first = narrow_buffer(c);
     a.global_curv = c->hp[0].coord != CART;
     a.gflag = c->flag_cur;
+    a.phys = c->dPhys;
+    a.olist = c->nPhys > 0 ? c->olist[0] : nullptr;
+    a.ocount = c->ocount[0];
     launch_ghosts(st, a);
   }
 }
@@ -711,9 +763,9 @@ void enqueue_step_overlap(pw_context *c, double dt) {
   int np = (int)c->hp.size();
   hipStream_t X = c->stream, Y = c->stream2, Z = c->stream3;
   launch_pose(X, c->dP, np, c->dT, dt, c->dPose);
-  (void)hipEventRecord(c->evFork, X);
-  (void)hipStreamWaitEvent(Y, c->evFork, 0);
-  (void)hipStreamWaitEvent(Z, c->evFork, 0);
+  ENQ(c, hipEventRecord(c->evFork, X));
+  ENQ(c, hipStreamWaitEvent(Y, c->evFork, 0));
+  ENQ(c, hipStreamWaitEvent(Z, c->evFork, 0));
   enqueue_flags(c, c->dPose + 2 * np, Z);
   static const int slot_of_stage[4] = {0, 1, 1, 2};
   static const double tmul[4] = {0.0, 0.5, 0.5, 1.0};
@@ -723,18 +775,18 @@ void enqueue_step_overlap(pw_context *c, double dt) {
     if (narrow) {
       // the global chain's local->global fill of this stage goes first; the
       // local chain's global->local stencils read the effective ghosts it wrote
-      if (s > 0) (void)hipStreamWaitEvent(Y, c->evL[s - 1], 0);
+      if (s > 0) ENQ(c, hipStreamWaitEvent(Y, c->evL[s - 1], 0));
       enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, Y);
-      if (s == 3) (void)hipEventRecord(c->evGhG, Y);
-      (void)hipEventRecord(c->evE[s], Y);
-      if (s > 0) (void)hipStreamWaitEvent(X, c->evG[s - 1], 0);
-      (void)hipStreamWaitEvent(X, c->evE[s], 0);
+      if (s == 3) ENQ(c, hipEventRecord(c->evGhG, Y));
+      ENQ(c, hipEventRecord(c->evE[s], Y));
+      if (s > 0) ENQ(c, hipStreamWaitEvent(X, c->evG[s - 1], 0));
+      ENQ(c, hipStreamWaitEvent(X, c->evE[s], 0));
       enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X);
-      if (s == 3) (void)hipEventRecord(c->evGhL, X);
+      if (s == 3) ENQ(c, hipEventRecord(c->evGhL, X));
       enqueue_stage_part(c, s, ps, dt, 2, X);
-      (void)hipEventRecord(c->evL[s], X);
+      ENQ(c, hipEventRecord(c->evL[s], X));
       enqueue_stage_part(c, s, ps, dt, 1, Y);
-      (void)hipEventRecord(c->evG[s], Y);
+      ENQ(c, hipEventRecord(c->evG[s], Y));
       continue;
     }
     // X: global -> local interpolation (it reads the global stage s-1 output)
@@ -744,42 +796,42 @@ void enqueue_step_overlap(pw_context *c, double dt) {
     // The periodic copies of stage 0 read the previous step's output only: they
     // go first on X, before the interpolation fills the GPU
     if (s == 0) enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X, false, PH_LOWER);
-    if (s > 0) (void)hipStreamWaitEvent(X, c->evG[s - 1], 0);
+    if (s > 0) ENQ(c, hipStreamWaitEvent(X, c->evG[s - 1], 0));
     for (int sv = 0; sv < c->cfg.n_state_vectors; sv++) {
       enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X, false, PH_INTERP, sv);
-      if (sv == 0 && s > 0) (void)hipStreamWaitEvent(X, c->evS[s - 1], 0);
+      if (sv == 0 && s > 0) ENQ(c, hipStreamWaitEvent(X, c->evS[s - 1], 0));
       enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, X, false, PH_FALLBACK, sv);
     }
-    (void)hipEventRecord(c->evGL[s], X);
-    if (s == 3) (void)hipEventRecord(c->evGhL, X);
+    ENQ(c, hipEventRecord(c->evGL[s], X));
+    if (s == 3) ENQ(c, hipEventRecord(c->evGhL, X));
     // Y: the periodic copies of the local patches (they read the local stage
     // s-1 output)
     if (s > 0) {
-      (void)hipStreamWaitEvent(Y, c->evL[s - 1], 0);
+      ENQ(c, hipStreamWaitEvent(Y, c->evL[s - 1], 0));
       enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_LOCAL, Y, false, PH_LOWER);
-      (void)hipEventRecord(c->evE[s], Y);
-      (void)hipStreamWaitEvent(X, c->evE[s], 0);
+      ENQ(c, hipEventRecord(c->evE[s], Y));
+      ENQ(c, hipStreamWaitEvent(X, c->evE[s], 0));
     }
     // X: stage kernels of the Cartesian local patches
     enqueue_stage_part(c, s, ps, dt, 2, X, 1);
-    (void)hipEventRecord(c->evL[s], X);
+    ENQ(c, hipEventRecord(c->evL[s], X));
     // Y: local -> global interpolation, outer ghosts, global stage, then the
     // stage kernels of the curvilinear local patches (they wait for X's fill;
     // placed here they even out the lengths of the two chains)
     enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, Y);
-    if (s == 3) (void)hipEventRecord(c->evGhG, Y);
+    if (s == 3) ENQ(c, hipEventRecord(c->evGhG, Y));
     enqueue_stage_part(c, s, ps, dt, 1, Y);
-    (void)hipEventRecord(c->evG[s], Y);
-    (void)hipStreamWaitEvent(Y, c->evGL[s], 0);
+    ENQ(c, hipEventRecord(c->evG[s], Y));
+    ENQ(c, hipStreamWaitEvent(Y, c->evGL[s], 0));
     enqueue_stage_part(c, s, ps, dt, 2, Y, 6);
-    (void)hipEventRecord(c->evS[s], Y);
+    ENQ(c, hipEventRecord(c->evS[s], Y));
   }
-  (void)hipStreamWaitEvent(Z, c->evGhL, 0);
-  (void)hipStreamWaitEvent(Z, c->evGhG, 0);
+  ENQ(c, hipStreamWaitEvent(Z, c->evGhL, 0));
+  ENQ(c, hipStreamWaitEvent(Z, c->evGhG, 0));
   enqueue_post_flags(c, c->dPose + 2 * np, Z);
-  (void)hipEventRecord(c->evNext, Z);
-  (void)hipStreamWaitEvent(X, narrow ? c->evG[3] : c->evS[3], 0);
-  (void)hipStreamWaitEvent(X, c->evNext, 0);
+  ENQ(c, hipEventRecord(c->evNext, Z));
+  ENQ(c, hipStreamWaitEvent(X, narrow ? c->evG[3] : c->evS[3], 0));
+  ENQ(c, hipStreamWaitEvent(X, c->evNext, 0));
   launch_advance_time(X, c->dT, dt, (long long *)c->dCounters);
   enqueue_finalize(c, c->dPose + 2 * np, 1);
 }
@@ -1038,6 +1090,9 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
   p.slab = (long long)p.pitch * p.rows;
   p.fstride = p.slab * p.slabs;
   long long nel = 5 * p.fstride;
+  // the kernels address the five fields of a patch with 32-bit element offsets
+  if (nel > (long long)UINT32_MAX)
+    return fail(c, PW_EINVAL, "a patch's five padded fields must hold fewer than 2^32 elements (about 940^3 cells)");
   if (p.coord != CART) {
     const int nt = 2 * (p.n[1] + p.n[2] + 4 * PW_NG);
     double *tab = (double *)dalloc(c, sizeof(double) * nt);
@@ -1287,7 +1342,10 @@ pw_status pw_exchange_ghosts(pw_context *c, double t) {
 pw_status pw_rk4_step(pw_context *c, double dt, int32_t nsteps) {
   if (!c || !(dt > 0) || nsteps < 0) return PW_EINVAL;
   if (c->hp.empty()) return fail(c, PW_ESTATE, "no global patch");
-  // The NG+1 buffer lets a patch cross at most one global cell per step.
+  // The NG+1 buffer lets a patch cross at most one global cell per step; a wider
+  // buffer B relaxes that to B - NG cells (Sec. 2.4.2).  The narrower buffers of
+  // the ablation keep the one-cell bound.
+  const double cells_per_step = std::max(1, c->cfg.buffer_width - PW_NG);
   const PatchDev &g = c->hp[0];
   double hmin = std::min(g.dx[0], std::min(g.dx[1], g.dx[2]));
   if (g.coord == SPH)  // smallest physical cell edge of a spherical shell
@@ -1299,7 +1357,8 @@ pw_status pw_rk4_step(pw_context *c, double dt, int32_t nsteps) {
     if (d.motion == PW_CIRCLE) sp = fabs(d.speed);
     // a spinning patch: points at distance rho from the centre move at |spin| rho more
     sp += sqrt(d.spin[0] * d.spin[0] + d.spin[1] * d.spin[1] + d.spin[2] * d.spin[2]) * bound_radius(d);
-    if (sp * dt >= hmin) return fail(c, PW_EMOTION, "a patch moves one global cell or more within a step");
+    if (sp * dt >= cells_per_step * hmin)
+      return fail(c, PW_EMOTION, "a patch moves buffer_width - NG global cells or more within a step");
   }
   pw_status rc = ensure_flags(c);
   if (rc) return rc;
@@ -1314,15 +1373,39 @@ pw_status pw_rk4_step(pw_context *c, double dt, int32_t nsteps) {
       (void)hipGraphDestroy(c->graph);
       c->gexec = nullptr;
     }
+    c->enq_err = hipSuccess;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     enqueue_step(c, dt);
-    HIPCHK(c, hipStreamEndCapture(c->stream, &c->graph));
+    // every fork joined and nothing invalidated the capture: its status is
+    // still active here, and each event record and wait succeeded
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    unsigned long long cid = 0;
+    const hipError_t qe = hipStreamGetCaptureInfo(c->stream, &cs, &cid);
+    hipGraph_t captured = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->stream, &captured);
+    if (c->enq_err != hipSuccess || qe != hipSuccess || cs != hipStreamCaptureStatusActive || ee != hipSuccess ||
+        captured == nullptr) {
+      if (captured) (void)hipGraphDestroy(captured);
+      (void)hipGetLastError();
+      std::string why = c->enq_err != hipSuccess ? std::string(c->enq_what) + ": " + hipGetErrorString(c->enq_err)
+                        : qe != hipSuccess        ? std::string("hipStreamGetCaptureInfo: ") + hipGetErrorString(qe)
+                        : cs != hipStreamCaptureStatusActive ? std::string("the step capture was invalidated")
+                                                             : std::string("hipStreamEndCapture: ") + hipGetErrorString(ee);
+      return fail(c, PW_EDEVICE, "capturing the step graph failed: " + why);
+    }
+    c->graph = captured;
     HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
     c->graph_dt = dt;
   }
   for (int n = 0; n < nsteps; n++) {
-    if (graph) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-    else enqueue_step(c, dt);
+    if (graph) {
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    } else {
+      c->enq_err = hipSuccess;
+      enqueue_step(c, dt);
+      if (c->enq_err != hipSuccess)
+        return fail(c, PW_EDEVICE, std::string(c->enq_what) + ": " + hipGetErrorString(c->enq_err));
+    }
     c->t_host = c->t_host + dt;
   }
   HIPCHK(c, hipGetLastError());
@@ -1463,6 +1546,8 @@ pw_status pw_counters(pw_context *c, pw_counters_t *out) {
   out->skip_uncover = (int64_t)h[2];
   out->n_uncover = (int64_t)h[3];
   out->steps = (int64_t)h[4];
+  out->skip_outer = (int64_t)h[5];
+  out->n_outer = (int64_t)h[6];
   return check_error_flag(c);
 }
 

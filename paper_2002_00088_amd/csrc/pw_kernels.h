@@ -107,6 +107,13 @@ struct FlagsArgs {
   const CoverJob *jobs;
   const CoverBlk *blks;
   int njobs, nblks;
+  // physical ghost cells of the global patch (outer ghosts that are not
+  // periodic copies) and the list of those a local patch covers: entries
+  // (index into phys, covering patch), count in *ocount
+  const GhostRec *phys;
+  int nphys;
+  int2 *olist;
+  int *ocount;
   int32_t *cover_new;
   uint8_t *t1, *t2, *live, *flag_new;
   uint8_t *dbl;  // cells claimed by two local patches
@@ -132,6 +139,13 @@ struct FinalizeArgs {
   int n[3];
   int2 *ulist;  // cells that become live: (cell, previous cover id); capacity n0 n1 n2
   int *ucount;
+  // covered physical ghosts of the global patch: the list of the next step
+  // (olist_new) becomes the current one
+  const int2 *olist_new;
+  const int *ocount_new;
+  int2 *olist_cur;
+  int *ocount_cur;
+  int nphys;
 };
 
 // Parts of a ghost fill: the global patch's (outer ghosts, effective ghosts)
@@ -172,6 +186,11 @@ struct GhostArgs {
   int l2g_first;         // narrow buffer: local->global (and its fallbacks) before global->local
   int global_curv;       // curvilinear global patch: one-point-per-thread interpatch kernels
   const uint8_t *gflag;  // cover flags of the global patch (donor test of those kernels)
+  // covered physical ghost cells of the global patch (Sec. 2.4.2): filled from
+  // the covering local patch after their boundary value (null: none)
+  const GhostRec *phys;
+  const int2 *olist;
+  const int *ocount;
 };
 
 struct StageArgs {

@@ -100,6 +100,45 @@ __global__ __launch_bounds__(256) void k_cover(const PatchDev *__restrict__ P, c
   }
 }
 
+// Covered physical ghost cells of the global patch (Sec. 2.4.2, last
+// paragraph): each outer ghost cell that is not a periodic copy is tested
+// against the local patches in ascending id (the same closed-box test as
+// k_cover); the first that contains its centre is recorded with it.
+__global__ __launch_bounds__(256) void k_cover_outer(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose,
+                                                     const CoverJob *jobs, int njobs, const GhostRec *phys, int nphys,
+                                                     int2 *olist, int *ocount) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= nphys) return;
+  const PatchDev &g = P[0];
+  int c[3];
+  {
+    const uint32_t w = phys[q].cell;
+    c[0] = (int)(w & 1023u) - PW_NG;
+    c[1] = (int)((w >> 10) & 1023u) - PW_NG;
+    c[2] = (int)((w >> 20) & 1023u) - PW_NG;
+  }
+  double X[3];
+  global_X(g, pose[0], c[0], c[1], c[2], X);
+  for (int m = 0; m < njobs; m++) {
+    const CoverJob &J = jobs[m];
+    const PatchDev &p = P[J.patch];
+    const PoseDev &ps = pose[J.patch];
+    const double d0 = X[0] - ps.c[0], d1 = X[1] - ps.c[1], d2 = X[2] - ps.c[2];
+    if (d0 * d0 + d1 * d1 + d2 * d2 > J.radius * J.radius) continue;
+    double xp[3];
+    inv_map(p, ps, X, xp);
+    bool in = true;
+    for (int a = 0; a < 3; a++) {
+      if (p.periodic[a]) continue;
+      in = in && (xp[a] >= p.lo[a]) && (xp[a] <= p.hi[a]);
+    }
+    if (!in) continue;
+    const int slot = atomicAdd(ocount, 1);
+    olist[slot] = make_int2(q, J.patch);
+    return;
+  }
+}
+
 // Chebyshev dilation along one axis: out[c] = max_{|d|<=R} in[c + d e_axis],
 // cells outside the domain read as `oob`.  With SRC_COVER the input is
 // "uncovered" = (cover == -1).
@@ -480,6 +519,51 @@ __device__ inline void unpack_ijk(uint32_t c, int &i, int &j, int &k) {
   i = (int)(c & 1023u) - PW_NG;
   j = (int)((c >> 10) & 1023u) - PW_NG;
   k = (int)((c >> 20) & 1023u) - PW_NG;
+}
+
+// Local -> global into the covered physical ghost cells of the global patch
+// (Sec. 2.4.2, last paragraph), after their boundary value: a point whose
+// stencil leaves the donor's interior keeps that value (counted in
+// counters[5]); counters[6] counts the targets.
+template <typename TB, typename TC>
+__global__ void k_l2g_outer(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const GhostRec *phys,
+                            const int2 *olist, const int *ocount, int sv, int stage, int Pts,
+                            unsigned long long *counters) {
+  const PatchDev &G0 = P[0];
+  if (!(G0.sv_mask & (1u << sv))) return;
+  const int n = ocount[0];
+  TB *TG = stage_buf<TB>(G0, sv, stage);
+  unsigned sk = 0;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const int2 e = olist[q];
+    int i, j, k;
+    unpack_ijk(phys[e.x].cell, i, j, k);
+    const int d = e.y;
+    double out[5];
+    bool ok = false;
+    if (P[d].sv_mask & (1u << sv)) {
+      const double xr[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
+      double X[3];
+      global_X(G0, pose[0], i, j, k, X);
+      ok = interp_transform<TB, TC>(P[d], pose[d], stage_buf<TB>(P[d], sv, stage), nullptr, Pts, X, G0, pose[0], xr,
+                                    out);
+    }
+    if (ok) {
+      const long long dst = cell_index(G0, i, j, k);
+      for (int f = 0; f < 5; f++) TG[f * G0.fstride + dst] = (TB)out[f];
+    } else {
+      sk++;
+    }
+  }
+  if (sk) atomicAdd(&counters[5], (unsigned long long)sk);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) atomicAdd(&counters[6], (unsigned long long)n);
+}
+
+// The covered-ghost list of the next step becomes the current one.
+__global__ void k_copy_olist(const int2 *src, const int *nsrc, int2 *dst, int *ndst) {
+  const int n = nsrc[0];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) dst[q] = src[q];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ndst[0] = n;
 }
 
 // Lower-priority ghost data: periodic copy if the wrapped index is interior,
@@ -1542,7 +1626,8 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
   constexpr bool MIX = sizeof(TOUT) == 4;
   constexpr bool INC = MIX && AM == 1;
   float *AccF = (float *)p.acc[sv];
-  // 32-bit element offsets (a field of one patch holds < 2^31 elements)
+  // 32-bit element offsets: the host keeps the five fields of a patch (5 fstride
+  // elements, ghosts and row padding included) below 2^32 elements
   const uint32_t fs = (uint32_t)p.fstride, sz = (uint32_t)p.slab;
   const uint32_t col = (uint32_t)cell_index(p, i, j, 0);
   // halo cells of the LDS planes: the ring of ST_PW - ST_THREADS cells around
@@ -2195,6 +2280,11 @@ void launch_flags(hipStream_t s, const FlagsArgs &a) {
   if (a.nblks > 0)
     hipLaunchKernelGGL(k_cover, dim3(a.nblks), dim3(256), 0, s, a.P, a.pose, a.jobs, a.blks, a.cover_new,
                        a.dbl);
+  if (a.nphys > 0) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.ocount, 0);
+    hipLaunchKernelGGL(k_cover_outer, dim3(nblk(a.nphys, 256)), dim3(256), 0, s, a.P, a.pose, a.jobs, a.njobs,
+                       a.phys, a.nphys, a.olist, a.ocount);
+  }
   if (chunked(a.n[0], {a.cover_new, a.t1, a.t2, a.live, a.flag_new, a.dbl}) && a.buffer <= 4 && PW_NG <= 4) {
     // live = buffer-dilation of the uncovered cells, near = NG-dilation of live
     const dim3 gc(nblk((long long)(a.n[0] / 16) * a.n[1], bs), a.n[2]);
@@ -2250,6 +2340,9 @@ void launch_finalize(hipStream_t s, const FinalizeArgs &a) {
     hipLaunchKernelGGL(k_uncover, dim3(64), dim3(256), 0, s, a.P, a.pose, (const int2 *)a.ulist,
                        (const int *)a.ucount, (const int32_t *)a.cover_cur, a.nsv, a.Pts, a.ex, a.vs, a.tdev,
                        a.counters);
+  if (a.nphys > 0)
+    hipLaunchKernelGGL(k_copy_olist, dim3(64), dim3(256), 0, s, a.olist_new, a.ocount_new, a.olist_cur,
+                       a.ocount_cur);
 }
 
 template <typename TB, typename TC>
@@ -2268,6 +2361,10 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
     if (l1 > lb)
       hipLaunchKernelGGL(k_fill_lower<TB>, dim3(nblk(l1 - lb, bs)), dim3(bs), 0, s, a.P, a.pose, a.lower + lb,
                          l1 - lb, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt, a.lower_dup);
+    // covered physical ghosts of the global patch: interpatch over the boundary value
+    if ((a.parts & GH_GLOBAL) && a.olist)
+      hipLaunchKernelGGL((k_l2g_outer<TB, TC>), dim3(64), dim3(256), 0, s, a.P, a.pose, a.phys, a.olist, a.ocount,
+                         a.sv, a.stage, a.Pts, a.skips);
   };
   if (!g2l && !l2g) {
     if (a.phases & PH_LOWER) lower();

@@ -78,7 +78,7 @@ class Tuning(C.Structure):
 
 class Counters(C.Structure):
     _fields_ = [("skip_local", C.c_int64), ("skip_eff", C.c_int64), ("skip_uncover", C.c_int64),
-                ("n_uncover", C.c_int64), ("steps", C.c_int64)]
+                ("n_uncover", C.c_int64), ("steps", C.c_int64), ("skip_outer", C.c_int64), ("n_outer", C.c_int64)]
 
 
 _lib = None
@@ -300,7 +300,7 @@ class Context:
         c = Counters()
         self._chk(self.L.pw_counters(self.h, C.byref(c)))
         return dict(skip_local=c.skip_local, skip_eff=c.skip_eff, skip_uncover=c.skip_uncover,
-                    n_uncover=c.n_uncover, steps=c.steps)
+                    n_uncover=c.n_uncover, steps=c.steps, skip_outer=c.skip_outer, n_outer=c.n_outer)
 
     def tuning(self):
         t = Tuning()

@@ -110,7 +110,7 @@ def compare(cfg, o, g, tol, check_counts=True, norm="patch"):
     if check_counts:
         co_ = o.counters()
         cg_ = g.counters()
-        for k in ("skip_local", "skip_eff", "skip_uncover", "n_uncover"):
+        for k in ("skip_local", "skip_eff", "skip_uncover", "n_uncover", "skip_outer", "n_outer"):
             assert co_[k] == cg_[k], (k, co_, cg_)
     return worst
 
@@ -432,7 +432,57 @@ def test_paper_test_four_full_size_one_step():
     o, g = run_pair(cfg, 1)
     fo, _ = o.flags()
     assert (fo == 2).sum() > 0 and o.counters()["skip_local"] > 0
-    say("  worst rel err", compare(cfg, o, g, TOL64, norm="all"))
+    # the Cartesian patch covers the inner radial and polar ghost cells of the
+    # spherical global patch: they are local->global targets (Sec. 2.4.2)
+    assert o.counters()["n_outer"] > 0
+    say("  worst rel err", compare(cfg, o, g, TOL64, norm="all"), o.counters())
+
+
+def _face_cfg(motion):
+    # a rotated local patch across the global patch's +x face: the outer ghost
+    # cells it covers take values interpolated from it (Sec. 2.4.2, last paragraph)
+    g0 = W.patch([48] * 3, [-8] * 3, [8] * 3, is_global=1)
+    kw = dict(euler=[0.3, 0.8, 1.9], c0=(6.4, -0.5, 0.2))
+    if motion:
+        kw.update(motion=W.LINEAR, vel=(0.2, 0.1, -0.05), spin=(0.0, 0.1, 0.2))
+    loc = W.patch([40] * 3, [-2.5] * 3, [2.5] * 3, **kw)
+    ex = dict(kind="gauss", amp=[1.0, -0.6], centers=[[6.5, 0.2, -0.3], [5.5, 1.0, 0.8]], widths=[0.9, 0.7])
+    return W._finish(dict(wave_speed=[1.0], interp_points=[6], patches=[g0, loc], exact=[ex]))
+
+
+@pytest.mark.parametrize("case", ["exchange", "steps", "steps_mixed"])
+def test_covered_outer_ghosts(case):
+    cfg = _face_cfg(case != "exchange")
+    say("covered outer ghosts", case)
+    if case == "exchange":
+        o = world_from_config(cfg)
+        g = pw.context_from_config(cfg)
+        o.init_exact(0.0)
+        g.init_exact(0.0)
+        # random data on the local patch: the interpolated ghost values differ from the boundary values
+        n = cfg["patches"][1]["n"]
+        a = W.random_state((5, n[2], n[1], n[0]), 41)
+        o.set_state(1, 0, a, 0.0)
+        g.set_state(1, 0, a, 0.0)
+        o.exchange_ghosts(0.21)
+        g.exchange_ghosts(0.21)
+        cov = o.cover_full()
+        ghost = np.ones(cov.shape, bool)
+        ghost[3:-3, 3:-3, 3:-3] = False
+        a, b = g.get_state_full(0), o.get_full(0)
+        sel = ghost & (cov > 0)
+        assert sel.sum() > 200
+        scale = np.abs(b[:, ghost]).max(axis=1)
+        e = np.abs(a[:, ghost] - b[:, ghost]).max(axis=1) / scale
+        say("  covered ghosts", int(sel.sum()), "rel err", e.max(), o.counters())
+        assert (e <= TOL64).all(), e
+        co_, cg_ = o.counters(), g.counters()
+        assert co_["n_outer"] == cg_["n_outer"] == int(sel.sum()) and co_["skip_outer"] == cg_["skip_outer"]
+        return
+    prec = pw.PW_MIXED if case == "steps_mixed" else pw.PW_FP64
+    o, g = run_pair(cfg, 4, precision=prec)
+    assert o.counters()["n_outer"] > 0 and o.counters()["skip_outer"] > 0
+    say("  worst rel err", compare(cfg, o, g, 2e-5 if prec == pw.PW_MIXED else TOL64), o.counters())
 
 
 def test_rotating_patch_mixed_precision():
