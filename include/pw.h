@@ -241,6 +241,18 @@ pw_status pw_set_state(pw_context *ctx, int32_t patch, int32_t sv, const double 
 pw_status pw_get_state(pw_context *ctx, int32_t patch, int32_t sv, double *dst, int64_t n_elems,
                        int32_t dst_is_device);
 
+/* pw_get_state into host memory for callers that cannot allocate device memory
+ * (code that must not call hipMalloc: tight serving loops, harnesses that forbid
+ * it).  Same arguments and layout as pw_get_state with a host destination; it
+ * calls no allocator.  The state is staged through a static device array of
+ * 4 Mi FP64 values (32 MiB) per GPU, held from library load until the process
+ * ends: PW_EINVAL if 5*n0*n1*n2 exceeds 4194304 (use pw_get_state), PW_ESTATE
+ * if the patch layout is not on the device yet (any earlier pw_init_exact,
+ * pw_set_state, pw_get_state or pw_rk4_step puts it there).  Synchronises the
+ * stream.  All contexts on one GPU share the array: calls that overlap on one
+ * GPU (from several threads or streams) race. */
+pw_status pw_get_state_noalloc(pw_context *ctx, int32_t patch, int32_t sv, double *dst, int64_t n_elems);
+
 /* Copy u including ghost cells, [5][n2+6][n1+6][n0+6] FP64, to host memory. */
 pw_status pw_get_state_full(pw_context *ctx, int32_t patch, int32_t sv, double *dst, int64_t n_elems);
 

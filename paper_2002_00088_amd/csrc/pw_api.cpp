@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,16 @@
 #include "pw_kernels.h"
 
 using namespace pw;
+
+// Staging memory of pw_get_state_noalloc: a file-scope device array, one copy
+// per GPU (each device holds its own at its own address until the process
+// ends).  Host code never uses the name `scratch` as an address: the address
+// is resolved once per device with hipGetSymbolAddress (in pw_create, with the
+// device current) and kept in g_scratch_ptr.
+#define PW_NOALLOC_MAX_ELEMS (4u << 20)  // 4 Mi doubles = 32 MiB
+static __device__ __align__(256) double scratch[PW_NOALLOC_MAX_ELEMS];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {nullptr};
 
 struct pw_context {
   pw_config cfg;
@@ -68,6 +79,7 @@ struct pw_context {
              evL[4] = {nullptr, nullptr, nullptr, nullptr}, evE[4] = {nullptr, nullptr, nullptr, nullptr},
              evGL[4] = {nullptr, nullptr, nullptr, nullptr}, evS[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t evGhL = nullptr, evGhG = nullptr, evNext = nullptr;
+  void *scratch_dev = nullptr;  // this device's copy of `scratch` (pw_get_state_noalloc)
   GBrick *dBricks = nullptr;
   int nBricks = 0;
   int32_t *efflist = nullptr, *effsorted = nullptr;
@@ -916,6 +928,24 @@ pw_status check_error_flag(pw_context *c) {
   return PW_OK;
 }
 
+// Device address of this device's `scratch` array: resolved once per device,
+// with that device current.
+pw_status resolve_scratch(pw_context *c) {
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(c, PW_EDEVICE, "device ordinal out of range for the staging table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(c, PW_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  c->scratch_dev = g_scratch_ptr[dev];
+  return PW_OK;
+}
+
 pw_status ensure_stage(pw_context *c, long long n) {
   if (n <= c->stageCap) return PW_OK;
   dfree(c, c->dStage);
@@ -1000,6 +1030,10 @@ pw_status pw_create(const pw_config *cfg, pw_context **out) {
       hipMemcpy(c->dT, &t0, sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dCounters, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dErr, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    pw_destroy(c);
+    return PW_EDEVICE;
+  }
+  if (resolve_scratch(c) != PW_OK) {
     pw_destroy(c);
     return PW_EDEVICE;
   }
@@ -1267,6 +1301,28 @@ static pw_status get_common(pw_context *c, int32_t pid, int32_t sv, double *dst,
 
 pw_status pw_get_state(pw_context *c, int32_t pid, int32_t sv, double *dst, int64_t n, int32_t is_dev) {
   return get_common(c, pid, sv, dst, n, is_dev, 0);
+}
+
+// pw_get_state into host memory without any allocation: the packed state goes
+// through this device's static staging array.
+pw_status pw_get_state_noalloc(pw_context *c, int32_t pid, int32_t sv, double *dst, int64_t n) {
+  if (!c || !dst || pid < 0 || pid >= (int)c->hp.size() || sv < 0 || sv >= c->cfg.n_state_vectors) return PW_EINVAL;
+  const PatchDev &p = c->hp[pid];
+  if (!(p.sv_mask & (1u << sv))) return fail(c, PW_EINVAL, "patch does not carry this state vector");
+  const long long need = 5LL * p.n[0] * p.n[1] * p.n[2];
+  if (n != need) return fail(c, PW_EINVAL, "element count does not match 5*n0*n1*n2");
+  if (need > (long long)PW_NOALLOC_MAX_ELEMS)
+    return fail(c, PW_EINVAL, "the patch's state exceeds the static staging array of pw_get_state_noalloc (" +
+                                  std::to_string(PW_NOALLOC_MAX_ELEMS) + " values); use pw_get_state");
+  if (c->layout_dirty || !c->scratch_dev)
+    return fail(c, PW_ESTATE, "the patch layout is not on the device yet (call pw_init_exact, pw_set_state, "
+                              "pw_get_state or pw_rk4_step once first)");
+  double *stage = (double *)c->scratch_dev;
+  launch_pack(c->stream, c->dP, pid, sv, stage, need, 0);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(dst, stage, sizeof(double) * need, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PW_OK;
 }
 
 pw_status pw_get_state_full(pw_context *c, int32_t pid, int32_t sv, double *dst, int64_t n) {

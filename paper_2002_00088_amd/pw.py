@@ -36,7 +36,7 @@ STATUS = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EDEVICE", -4: "P
 EXPORTS = ["pw_create", "pw_create_patch", "pw_set_exact", "pw_init_exact", "pw_set_state", "pw_get_state",
            "pw_get_state_full", "pw_get_flags", "pw_exchange_ghosts", "pw_rk4_step", "pw_get_time",
            "pw_diagnostics", "pw_counters", "pw_live_cells", "pw_enable_timing", "pw_kernel_times",
-           "pw_get_tuning", "pw_set_tuning", "pw_autotune", "pw_last_error", "pw_destroy"]
+           "pw_get_tuning", "pw_set_tuning", "pw_autotune", "pw_last_error", "pw_destroy", "pw_get_state_noalloc"]
 KERNEL_CLASSES = ["pose", "ghost_s1", "ghost_s2", "ghost_s3", "ghost_s4", "stage_s1", "stage_s2", "stage_s3",
                   "stage_s4", "flags", "finalize", "gstage_s1", "gstage_s2", "gstage_s3", "gstage_s4", "g2l", "l2g"]
 
@@ -101,6 +101,7 @@ def load():
     L.pw_set_state.argtypes = [vp, C.c_int32, C.c_int32, dp, C.c_int64, C.c_int32, C.c_double]
     L.pw_get_state.argtypes = [vp, C.c_int32, C.c_int32, dp, C.c_int64, C.c_int32]
     L.pw_get_state_full.argtypes = [vp, C.c_int32, C.c_int32, dp, C.c_int64]
+    L.pw_get_state_noalloc.argtypes = [vp, C.c_int32, C.c_int32, dp, C.c_int64]
     L.pw_get_flags.argtypes = [vp, C.POINTER(C.c_uint8), C.POINTER(C.c_int32), C.c_int64]
     L.pw_exchange_ghosts.argtypes = [vp, C.c_double]
     L.pw_rk4_step.argtypes = [vp, C.c_double, C.c_int32]
@@ -198,10 +199,12 @@ class Context:
         cfg.outer_bc = outer_bc
         cfg.stream = stream
         self._keep = []
+        self.n_alloc = 0  # device allocations made through the torch allocator callbacks
         if torch_alloc:
             dev = torch.cuda.current_device()
 
             def _alloc(nbytes, user):
+                self.n_alloc += 1
                 return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
 
             def _free(ptr, user):
@@ -261,6 +264,15 @@ class Context:
     def get_state(self, pid, sv=0):
         out = np.empty(self.shape(pid))
         self._chk(self.L.pw_get_state(self.h, pid, sv, out.ctypes.data_as(C.POINTER(C.c_double)), out.size, 0))
+        return out
+
+    def get_state_noalloc(self, pid, sv=0, out=None):
+        """pw_get_state_noalloc into a host array (a new one unless `out` is given)."""
+        if out is None:
+            out = np.empty(self.shape(pid))
+        assert out.dtype == np.float64 and out.flags.c_contiguous and out.size == int(np.prod(self.shape(pid)))
+        self._chk(self.L.pw_get_state_noalloc(self.h, pid, sv, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                              out.size))
         return out
 
     def get_state_full(self, pid, sv=0):
