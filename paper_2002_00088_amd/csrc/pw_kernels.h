@@ -29,7 +29,7 @@ struct StageTile {
 #define DIAG_N 23
 #define BRICK_THREADS 192
 #ifndef BRICK_LDS_BYTES
-#define BRICK_LDS_BYTES 40960
+#define BRICK_LDS_BYTES 30720
 #endif
 #define L2G_BLOCKS 2048  // a multiple of 8
 #define L2G_WAVES 3

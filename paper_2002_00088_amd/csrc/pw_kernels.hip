@@ -13,6 +13,7 @@
 #include <stdint.h>
 
 #include <initializer_list>
+#include <type_traits>
 
 #include "pw_internal.h"
 #include "pw_kernels.h"
@@ -354,9 +355,11 @@ __global__ __launch_bounds__(256) void k_window_yz16(const uint8_t *in, uint8_t 
 // patch p at numerical point xd.  For a global donor every stencil cell must be
 // live (gflag); for a local donor the stencil must lie in the interior (wrapping
 // periodic axes).  Returns false if the point cannot be interpolated.
+// The x-sums run in the compute type TC (x weights rounded to it); the outer
+// sums over rows, with the FP64 weights wy[b] wz[c], in FP64.
 template <typename TB, typename TC>
 __device__ inline bool interp5(const PatchDev &p, const TB *T, const uint8_t *gflag, int P, const double xd[3],
-                               TC out[5], bool effghost_ok = false) {
+                               double out[5], bool effghost_ok = false) {
   double wx[8], wy[8], wz[8];
   int s[3];
   double q[3];
@@ -382,14 +385,14 @@ __device__ inline bool interp5(const PatchDev &p, const TB *T, const uint8_t *gf
       }
     }
   }
-  for (int f = 0; f < 5; f++) out[f] = (TC)0;
+  for (int f = 0; f < 5; f++) out[f] = 0.0;
   for (int c = 0; c < P; c++) {
     int kk = s[2] + c;
     if (p.periodic[2]) kk = ((kk % p.n[2]) + p.n[2]) % p.n[2];
     for (int b = 0; b < P; b++) {
       int jj = s[1] + b;
       if (p.periodic[1]) jj = ((jj % p.n[1]) + p.n[1]) % p.n[1];
-      TC wyz = (TC)(wy[b] * wz[c]);
+      const double wyz = wy[b] * wz[c];
       TC part[5] = {0, 0, 0, 0, 0};
       for (int a = 0; a < P; a++) {
         int ii = s[0] + a;
@@ -398,7 +401,7 @@ __device__ inline bool interp5(const PatchDev &p, const TB *T, const uint8_t *gf
         TC w = (TC)wx[a];
         for (int f = 0; f < 5; f++) part[f] += w * (TC)T[f * p.fstride + x];
       }
-      for (int f = 0; f < 5; f++) out[f] += wyz * part[f];
+      for (int f = 0; f < 5; f++) out[f] += wyz * (double)part[f];
     }
   }
   return true;
@@ -418,7 +421,7 @@ __device__ inline bool interp_transform(const PatchDev &d, const PoseDev &psd, c
                                         const double xr[3], double out[5]) {
   double xd[3];
   inv_map(d, psd, X, xd);
-  TC v[5];
+  double v[5];
   if (!interp5<TB, TC>(d, T, gflag, P, xd, v)) return false;
   double in4[4] = {(double)v[1], (double)v[2], (double)v[3], (double)v[4]}, G[3], pit, o4[4];
   patch_to_bg_at(d, psd, X, xd, in4, pit, G);
@@ -460,7 +463,7 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_point(const PatchDev *__r
     double X[3], xd[3];
     fwd_map_grid(r, pose[B.patch], c, X);
     inv_map(G0, pose[0], X, xd);
-    TC v[5];
+    double v[5];
     if (interp5<TB, TC>(G0, stage_buf<TB>(G0, sv, stage), gflag, Pts, xd, v, effghost_ok != 0)) {
       double in4[4] = {(double)v[1], (double)v[2], (double)v[3], (double)v[4]}, G[3], pit, o4[4];
       patch_to_bg(G0, pose[0], xd, in4, pit, G);
@@ -848,18 +851,30 @@ __device__ __forceinline__ int xcd_spread(int v, int K) {
 // Global -> local (Sec. 2.4.1).  One workgroup per brick of up to 8x8x3 ghost
 // cells of one face of a local patch.  Each thread locates its point in the
 // global patch (FP64) and forms its Lagrange weights (FP64); the union of the
-// donor stencils (the donor box) is staged in LDS, as many fields at a time as
-// fit (all five for most bricks), and every thread sums its P^3 taps from LDS.  Validity is one byte: every cell of the
-// donor stencil must be live.  Points that cannot be interpolated keep the
-// lower-priority value (analytic or nearest interior) and are counted.
+// donor stencils (the donor box) is staged in LDS and every thread sums its P^3
+// taps from LDS.  FP32 sums: one float4 (fields 0-3) and one float (field 4)
+// per box cell, staged in chunks of whole z-layers, so a tap is one 128-bit LDS
+// read plus half of a two-dword read, and the taps of a row are immediate
+// offsets from one row address; 30 KB of LDS and at most 128 VGPRs keep four
+// waves per SIMD.  FP64 sums: the box field after field.  Validity is one
+// byte: every cell of the donor stencil must be live.  Points that cannot be
+// interpolated keep the lower-priority value (analytic or nearest interior)
+// and are counted.
 // ---------------------------------------------------------------------------
 template <typename TB, typename TC, int Pts>
-__global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose,
+__global__ __launch_bounds__(BRICK_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_g2l_brick(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose,
                                                              const GBrick *bricks, int nbricks, int run, int sv,
                                                              int stage, const uint8_t *dvalid,
                                                              unsigned long long *skips, FallbackRec *fb,
                                                              int *fb_count) {
-  __shared__ TC box[BRICK_LDS_BYTES / sizeof(TC)];
+  // FP32 sums: the donor box as one float4 (fields 0-3) plus one float (field
+  // 4) per cell, 20 bytes a cell, so a tap is one 128-bit LDS read and half of a
+  // two-dword read; FP64 sums: field after field
+  constexpr bool VEC = sizeof(TC) == 4;
+  constexpr int INFLIGHT = 4;  // box cells per thread with their loads in flight together
+  typedef TC TO;               // type of the outer sums
+  constexpr int CAPV = BRICK_LDS_BYTES / 20;  // cells of a float4 + float box
+  __shared__ __align__(16) unsigned char lds_raw[BRICK_LDS_BYTES];
   __shared__ int blo[3], bhi[3];
   // runs of `run` consecutive bricks (which share donor cells) on one XCD
   const int bidx = xcd_spread(blockIdx.x, run);
@@ -917,83 +932,175 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__r
   const int e0 = bhi[0] - lo0 + 1, e1 = bhi[1] - lo1 + 1, e2 = bhi[2] - lo2 + 1;
   const long long vol = (e0 > 0 && e1 > 0 && e2 > 0) ? (long long)e0 * e1 * e2 : 0;
   const TB *T = stage_buf<TB>(G0, sv, stage);
-  TC acc[5] = {0, 0, 0, 0, 0};
-  TC wxc[Pts], wyzc[Pts][Pts];
+  // the sums run in the compute type: FP64 weights rounded to it once (the x
+  // weights, and the products wy[b] wz[c] of the outer sums)
+  TO acc[5] = {0, 0, 0, 0, 0};
+  TC wxc[Pts];
 #pragma unroll
   for (int a = 0; a < Pts; a++) wxc[a] = (TC)wx[a];
-#pragma unroll
-  for (int cc = 0; cc < Pts; cc++)
-#pragma unroll
-    for (int b = 0; b < Pts; b++) wyzc[cc][b] = (TC)(wy[b] * wz[cc]);
   const uint32_t gfs = (uint32_t)G0.fstride, gsy = (uint32_t)G0.pitch, gsz = (uint32_t)G0.slab;
-  constexpr int CAP = BRICK_LDS_BYTES / sizeof(TC);
-  const int nfp = vol > 0 ? (int)(CAP / vol < 5 ? CAP / vol : 5) : 0;  // fields per LDS pass
-  if (nfp > 0) {
-    const int e01 = e0 * e1;
-    const int v = (int)vol;
-    const uint32_t base0 = (uint32_t)(lo0 + PW_OX) + (uint32_t)(lo1 + PW_NG) * gsy + (uint32_t)(lo2 + PW_NG) * gsz;
-    // flat box index q -> (x, row), row -> (b, cc) with float reciprocals: exact,
-    // since (q + 0.5) / e lies at least 1/(2e) from an integer and q < 2^14
-    const float ie0 = 1.0f / (float)e0, ie1 = 1.0f / (float)e1;
-    for (int f0 = 0; f0 < 5; f0 += nfp) {
-      const int nf = 5 - f0 < nfp ? 5 - f0 : nfp;
-      for (int q0 = tid; q0 < v; q0 += 4 * BRICK_THREADS) {
-        TC tmp[4][5];
+  const int e01 = e0 * e1;
+  bool staged = false;
+  if constexpr (VEC) {
+    // z-chunks of whole layers, all five fields at once
+    float4 *box4 = (float4 *)lds_raw;
+    float *box1 = (float *)(lds_raw + 16 * CAPV);
+    const int nzc = e01 > 0 ? CAPV / e01 : 0;
+    if (vol > 0 && nzc > 0) {
+      staged = true;
+      const float ie0 = 1.0f / (float)e0, ie1 = 1.0f / (float)e1;
+      for (int z0 = 0; z0 < e2; z0 += nzc) {
+        const int nz = e2 - z0 < nzc ? e2 - z0 : nzc;
+        const int v = e01 * nz;
+        const uint32_t base0 =
+            (uint32_t)(lo0 + PW_OX) + (uint32_t)(lo1 + PW_NG) * gsy + (uint32_t)(lo2 + z0 + PW_NG) * gsz;
+        // flat index q -> (x, row), row -> (b, layer) with float reciprocals:
+        // exact, since (q + 0.5) / e lies at least 1/(2e) from an integer, q < 2^14
+        for (int q0 = tid; q0 < v; q0 += INFLIGHT * BRICK_THREADS) {
+          float tmp[INFLIGHT][5];
 #pragma unroll
-        for (int m = 0; m < 4; m++) {
-          const int q = q0 + m * BRICK_THREADS;
-          if (q < v) {
-            const int row = (int)(((float)q + 0.5f) * ie0);
-            const int x = q - row * e0;
-            const int cc = (int)(((float)row + 0.5f) * ie1);
-            const int b = row - cc * e1;
-            const uint32_t g = base0 + (uint32_t)b * gsy + (uint32_t)cc * gsz + (uint32_t)x;
+          for (int m = 0; m < INFLIGHT; m++) {
+            const int q = q0 + m * BRICK_THREADS;
+            if (q < v) {
+              const int row = (int)(((float)q + 0.5f) * ie0);
+              const int x = q - row * e0;
+              const int cc = (int)(((float)row + 0.5f) * ie1);
+              const int b = row - cc * e1;
+              const uint32_t g = base0 + (uint32_t)b * gsy + (uint32_t)cc * gsz + (uint32_t)x;
 #pragma unroll
-            for (int f = 0; f < 5; f++)
-              if (f < nf) tmp[m][f] = (TC)gld(T, (uint32_t)(f0 + f) * gfs + g);
-          }
-        }
-#pragma unroll
-        for (int m = 0; m < 4; m++) {
-          const int q = q0 + m * BRICK_THREADS;
-          if (q < v) {
-#pragma unroll
-            for (int f = 0; f < 5; f++)
-              if (f < nf) box[f * v + q] = tmp[m][f];
-          }
-        }
-      }
-      __syncthreads();
-      if (valid) {
-        const TC *base = box + (s[2] - lo2) * e01 + (s[1] - lo1) * e0 + (s[0] - lo0);
-        for (int f = 0; f < nf; f++) {
-          TC sum = (TC)0;
-          const TC *bf = base + f * v;
-#pragma unroll
-          for (int cc = 0; cc < Pts; cc++) {
-            // one z-layer: all Pts x Pts values read before the sums, so the LDS
-            // reads are issued back to back
-            TC w[Pts][Pts];
-#pragma unroll
-            for (int b = 0; b < Pts; b++)
-#pragma unroll
-              for (int a = 0; a < Pts; a++) w[b][a] = bf[cc * e01 + b * e0 + a];
-#pragma unroll
-            for (int b = 0; b < Pts; b++) {
-              TC part = (TC)0;
-#pragma unroll
-              for (int a = 0; a < Pts; a++) part += wxc[a] * w[b][a];
-              sum += wyzc[cc][b] * part;
+              for (int f = 0; f < 5; f++) tmp[m][f] = (float)gld(T, (uint32_t)f * gfs + g);
             }
           }
 #pragma unroll
-          for (int m = 0; m < 5; m++)
-            if (m == f0 + f) acc[m] = sum;
+          for (int m = 0; m < INFLIGHT; m++) {
+            const int q = q0 + m * BRICK_THREADS;
+            if (q < v) {
+              box4[q] = make_float4(tmp[m][0], tmp[m][1], tmp[m][2], tmp[m][3]);
+              box1[q] = tmp[m][4];
+            }
+          }
         }
+        __syncthreads();
+        if (valid) {
+          // row pointers advance by e0 cells per row and e01 per layer, so every
+          // tap of a row is an immediate offset from one address
+          const int first = (s[2] - lo2 - z0) * e01 + (s[1] - lo1) * e0 + (s[0] - lo0);
+          const float4 *r4 = box4 + first;
+          const float *r1 = box1 + first;
+          const int skip = e01 - Pts * e0;  // from the end of one layer's rows to the next layer
+#pragma unroll
+          for (int cc = 0; cc < Pts; cc++) {
+            const int lz = s[2] - lo2 + cc - z0;  // layer of the chunk
+            if (lz < 0 || lz >= nz) {
+              r4 += e01;
+              r1 += e01;
+              continue;
+            }
+#pragma unroll
+            for (int b = 0; b < Pts; b++) {
+              float4 w4[Pts];
+              float w1[Pts];
+#pragma unroll
+              for (int a = 0; a < Pts; a++) {
+                w4[a] = r4[a];
+                w1[a] = r1[a];
+              }
+              r4 += e0;
+              r1 += e0;
+              float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f;
+#pragma unroll
+              for (int a = 0; a < Pts; a++) {
+                p0 += wxc[a] * w4[a].x;
+                p1 += wxc[a] * w4[a].y;
+                p2 += wxc[a] * w4[a].z;
+                p3 += wxc[a] * w4[a].w;
+                p4 += wxc[a] * w1[a];
+              }
+              const TO wyz = (TO)(wy[b] * wz[cc]);
+              acc[0] += wyz * (TO)p0;
+              acc[1] += wyz * (TO)p1;
+              acc[2] += wyz * (TO)p2;
+              acc[3] += wyz * (TO)p3;
+              acc[4] += wyz * (TO)p4;
+            }
+            r4 += skip;
+            r1 += skip;
+          }
+        }
+        if (z0 + nzc < e2) __syncthreads();
       }
-      if (f0 + nfp < 5) __syncthreads();
     }
-  } else if (valid) {
+  } else {
+    // FP64: as many fields per pass as fit, field after field
+    TC *box = (TC *)lds_raw;
+    constexpr int CAP = BRICK_LDS_BYTES / sizeof(TC);
+    const int nfp = vol > 0 ? (int)(CAP / vol < 5 ? CAP / vol : 5) : 0;  // fields per LDS pass
+    if (nfp > 0) {
+      staged = true;
+      const int v = (int)vol;
+      const uint32_t base0 = (uint32_t)(lo0 + PW_OX) + (uint32_t)(lo1 + PW_NG) * gsy + (uint32_t)(lo2 + PW_NG) * gsz;
+      const float ie0 = 1.0f / (float)e0, ie1 = 1.0f / (float)e1;
+      for (int f0 = 0; f0 < 5; f0 += nfp) {
+        const int nf = 5 - f0 < nfp ? 5 - f0 : nfp;
+        for (int q0 = tid; q0 < v; q0 += 4 * BRICK_THREADS) {
+          TC tmp[4][5];
+#pragma unroll
+          for (int m = 0; m < 4; m++) {
+            const int q = q0 + m * BRICK_THREADS;
+            if (q < v) {
+              const int row = (int)(((float)q + 0.5f) * ie0);
+              const int x = q - row * e0;
+              const int cc = (int)(((float)row + 0.5f) * ie1);
+              const int b = row - cc * e1;
+              const uint32_t g = base0 + (uint32_t)b * gsy + (uint32_t)cc * gsz + (uint32_t)x;
+#pragma unroll
+              for (int f = 0; f < 5; f++)
+                if (f < nf) tmp[m][f] = (TC)gld(T, (uint32_t)(f0 + f) * gfs + g);
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < 4; m++) {
+            const int q = q0 + m * BRICK_THREADS;
+            if (q < v) {
+#pragma unroll
+              for (int f = 0; f < 5; f++)
+                if (f < nf) box[f * v + q] = tmp[m][f];
+            }
+          }
+        }
+        __syncthreads();
+        if (valid) {
+          const TC *base = box + (s[2] - lo2) * e01 + (s[1] - lo1) * e0 + (s[0] - lo0);
+          for (int f = 0; f < nf; f++) {
+            TO sum = (TO)0;
+            const TC *bf = base + f * v;
+#pragma unroll
+            for (int cc = 0; cc < Pts; cc++) {
+              // one z-layer: all Pts x Pts values read before the sums, so the LDS
+              // reads are issued back to back
+              TC w[Pts][Pts];
+#pragma unroll
+              for (int b = 0; b < Pts; b++)
+#pragma unroll
+                for (int a = 0; a < Pts; a++) w[b][a] = bf[cc * e01 + b * e0 + a];
+#pragma unroll
+              for (int b = 0; b < Pts; b++) {
+                TC part = (TC)0;
+#pragma unroll
+                for (int a = 0; a < Pts; a++) part += wxc[a] * w[b][a];
+                sum += (TO)(wy[b] * wz[cc]) * (TO)part;
+              }
+            }
+#pragma unroll
+            for (int m = 0; m < 5; m++)
+              if (m == f0 + f) acc[m] = sum;
+          }
+        }
+        if (f0 + nfp < 5) __syncthreads();
+      }
+    }
+  }
+  if (!staged && valid) {
     // donor box larger than the LDS tile: gather straight from global memory
     // (weights picked by selects, so no array is indexed dynamically)
     for (int cc = 0; cc < Pts; cc++) {
@@ -1010,9 +1117,9 @@ __global__ __launch_bounds__(BRICK_THREADS) void k_g2l_brick(const PatchDev *__r
         for (int a = 0; a < Pts; a++)
 #pragma unroll
           for (int f = 0; f < 5; f++) part[f] += wxc[a] * (TC)gld(T, f * gfs + x0 + a);
-        const TC wyz = (TC)(wyd * wzd);
+        const TO wyz = (TO)(wyd * wzd);
 #pragma unroll
-        for (int f = 0; f < 5; f++) acc[f] += wyz * part[f];
+        for (int f = 0; f < 5; f++) acc[f] += wyz * (TO)part[f];
       }
     }
   }
@@ -1071,8 +1178,15 @@ template <typename TB, typename TC, int Pts>
 __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_l2g_box(
     const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list, const int *count,
     int run, const int32_t *cover, int sv, int stage, unsigned long long *skips, FallbackRec *fb, int *fb_count) {
-  constexpr int CAP = L2G_LDS_BYTES / sizeof(TC);
-  __shared__ TC box[CAP];
+  // the donor box: five fields per cell, 20 (FP32) or 40 (FP64) bytes a cell
+  constexpr int CAPC = L2G_LDS_BYTES / (5 * sizeof(TC));
+  constexpr int CAP = CAPC;
+  __shared__ __align__(16) unsigned char lds_box[L2G_LDS_BYTES];
+  float4 *b4f = (float4 *)lds_box;
+  float *b1f = (float *)(lds_box + 16 * CAPC);
+  double2 *b01d = (double2 *)lds_box;
+  double2 *b23d = (double2 *)(lds_box + 16 * CAPC);
+  double *b4d = (double *)(lds_box + 32 * CAPC);
   __shared__ TC red[L2G_WAVES - 1][5][64];
   __shared__ int obox[8][8];  // per octet: lo[3], hi[3], lowest and highest donor id
   const PatchDev &G0 = P[0];
@@ -1178,21 +1292,25 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
       const long long vol = volume(lo, hi);
       if (dmax < 0) {
         // no valid point in the run
-      } else if (dmin == dmax && vol <= CAP) {
-        const int nfp = (int)(CAP / vol < 5 ? CAP / vol : 5);  // fields per LDS pass
+      } else if (dmin == dmax && (vol <= CAPC || o1 == o0 + 1) &&
+                 (long long)(hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) <= CAPC) {
+        // the run's donor box in LDS, whole z-layers at a time, all five fields
+        // per cell (a run of several octets fits at once; a lone octet may take
+        // several chunks)
         const PatchDev &D = P[dmin];  // uniform: scalar loads
         const TB *T = stage_buf<TB>(D, sv, stage);
         const uint32_t fs = (uint32_t)D.fstride, dsy = (uint32_t)D.pitch, dsz = (uint32_t)D.slab;
         const int dn0 = D.n[0], dn1 = D.n[1], dn2 = D.n[2];
         const bool per0 = D.periodic[0] != 0, per1 = D.periodic[1] != 0, per2 = D.periodic[2] != 0;
-        const int e0 = hi[0] - lo[0] + 1, e1 = hi[1] - lo[1] + 1;
+        const int e0 = hi[0] - lo[0] + 1, e1 = hi[1] - lo[1] + 1, e2 = hi[2] - lo[2] + 1;
         const int e01 = e0 * e1;
-        const int v = (int)vol;
-        // flat box index q -> (x, row), row -> (b, cc) with float reciprocals: exact,
-        // since (q + 0.5) / e lies at least 1/(2e) from an integer and q < 2^14
+        const int nzc = CAPC / e01;
+        // flat box index q -> (x, row), row -> (b, layer) with float reciprocals:
+        // exact, since (q + 0.5) / e lies at least 1/(2e) from an integer and q < 2^14
         const float ie0 = 1.0f / (float)e0, ie1 = 1.0f / (float)e1;
-        for (int f0 = 0; f0 < 5; f0 += nfp) {
-          const int nf = 5 - f0 < nfp ? 5 - f0 : nfp;
+        for (int z0 = 0; z0 < e2; z0 += nzc) {
+          const int nz = e2 - z0 < nzc ? e2 - z0 : nzc;
+          const int v = e01 * nz;
           for (int q0 = tid; q0 < v; q0 += 4 * 64 * L2G_WAVES) {
             TC tmp[4][5];
 #pragma unroll
@@ -1204,53 +1322,84 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
                 const int cc = (int)(((float)row + 0.5f) * ie1);
                 const int b = row - cc * e1;
                 // box cells lie inside [0, n) on every axis once periodic axes wrap
-                int ii = lo[0] + x, jj = lo[1] + b, kk = lo[2] + cc;
+                int ii = lo[0] + x, jj = lo[1] + b, kk = lo[2] + z0 + cc;
                 if (per0) ii = ((ii % dn0) + dn0) % dn0;
                 if (per1) jj = ((jj % dn1) + dn1) % dn1;
                 if (per2) kk = ((kk % dn2) + dn2) % dn2;
                 const uint32_t g =
                     (uint32_t)(ii + PW_OX) + (uint32_t)(jj + PW_NG) * dsy + (uint32_t)(kk + PW_NG) * dsz;
 #pragma unroll
-                for (int f = 0; f < 5; f++)
-                  if (f < nf) tmp[m][f] = (TC)gld(T, (uint32_t)(f0 + f) * fs + g);
+                for (int f = 0; f < 5; f++) tmp[m][f] = (TC)gld(T, (uint32_t)f * fs + g);
               }
             }
 #pragma unroll
             for (int m = 0; m < 4; m++) {
               const int q = q0 + m * 64 * L2G_WAVES;
               if (q < v) {
-#pragma unroll
-                for (int f = 0; f < 5; f++)
-                  if (f < nf) box[f * v + q] = tmp[m][f];
+                if constexpr (sizeof(TC) == 4) {
+                  b4f[q] = make_float4(tmp[m][0], tmp[m][1], tmp[m][2], tmp[m][3]);
+                  b1f[q] = tmp[m][4];
+                } else {
+                  b01d[q] = make_double2(tmp[m][0], tmp[m][1]);
+                  b23d[q] = make_double2(tmp[m][2], tmp[m][3]);
+                  b4d[q] = tmp[m][4];
+                }
               }
             }
           }
           __syncthreads();
           if (mine) {
-            const TC *base = box + (s[2] - lo[2]) * e01 + (s[1] - lo[1]) * e0 + (s[0] - lo[0]);
-            for (int cc = wv; cc < Pts; cc += L2G_WAVES) {
-              TC wzv = (TC)0;
+            // wave wv sums the layers wv, wv + L2G_WAVES, ... of each stencil
+            // that lie in this chunk; the taps of a row are immediate offsets
+            // from one row address
+            const int first = (s[1] - lo[1]) * e0 + (s[0] - lo[0]);
 #pragma unroll
-              for (int m = 0; m < Pts; m++) wzv = (m == cc) ? wzc[m] : wzv;
-              for (int f = 0; f < nf; f++) {
-                const TC *bl = base + f * v + cc * e01;
-                TC w[Pts][Pts];
+            for (int cc = 0; cc < Pts; cc++) {
+              if (cc % L2G_WAVES != wv) continue;
+              const int lz = s[2] - lo[2] + cc - z0;
+              if (lz < 0 || lz >= nz) continue;
+              const int o = lz * e01 + first;
+              TC layer[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-                for (int b = 0; b < Pts; b++)
+              for (int b = 0; b < Pts; b++) {
+                TC p5[5] = {0, 0, 0, 0, 0};
+                if constexpr (sizeof(TC) == 4) {
+                  const float4 *r4 = b4f + o + b * e0;
+                  const float *r1 = b1f + o + b * e0;
+                  float4 w4[Pts];
+                  float w1[Pts];
 #pragma unroll
-                  for (int a = 0; a < Pts; a++) w[b][a] = bl[b * e0 + a];
-                TC layer = (TC)0;
+                  for (int a = 0; a < Pts; a++) {
+                    w4[a] = r4[a];
+                    w1[a] = r1[a];
+                  }
 #pragma unroll
-                for (int b = 0; b < Pts; b++) {
-                  TC part = (TC)0;
+                  for (int a = 0; a < Pts; a++) {
+                    p5[0] += wxc[a] * w4[a].x;
+                    p5[1] += wxc[a] * w4[a].y;
+                    p5[2] += wxc[a] * w4[a].z;
+                    p5[3] += wxc[a] * w4[a].w;
+                    p5[4] += wxc[a] * w1[a];
+                  }
+                } else {
+                  const double2 *ra = b01d + o + b * e0;
+                  const double2 *rb = b23d + o + b * e0;
+                  const double *rc = b4d + o + b * e0;
 #pragma unroll
-                  for (int a = 0; a < Pts; a++) part += wxc[a] * w[b][a];
-                  layer += wyc[b] * part;
+                  for (int a = 0; a < Pts; a++) {
+                    const double2 x01 = ra[a], x23 = rb[a];
+                    p5[0] += wxc[a] * x01.x;
+                    p5[1] += wxc[a] * x01.y;
+                    p5[2] += wxc[a] * x23.x;
+                    p5[3] += wxc[a] * x23.y;
+                    p5[4] += wxc[a] * rc[a];
+                  }
                 }
 #pragma unroll
-                for (int m = 0; m < 5; m++)
-                  if (m == f0 + f) acc[m] += wzv * layer;
+                for (int f = 0; f < 5; f++) layer[f] += wyc[b] * p5[f];
               }
+#pragma unroll
+              for (int f = 0; f < 5; f++) acc[f] += wzc[cc] * layer[f];
             }
           }
           __syncthreads();

@@ -687,3 +687,64 @@ def test_error_paths():
     with pytest.raises(pw.PwError):
         g.rk4_step(0.1, 1)
     g.close()
+
+
+# --------------------------------------------------------------------------
+# Full-size workloads over the prefixes the oracle is timed on: the GPU path in
+# the benchmark's launch configuration (batched schedule, graph replayed every
+# step, flags swapped and outer ghosts reused across steps) against the oracle's
+# stored state (tests/golden/make_prefix_golden.py): FP64, element by element
+# at 1e-12 on the sampled cells, per-field maxima and sums of squares over all
+# live cells, cover flags and ids bitwise, counters exact.
+# --------------------------------------------------------------------------
+PREFIX = {
+    "two_patch_200": lambda: W.two_patch(seed=2),
+    "spherical_50": lambda: W.spherical(seed=3),
+    "batched_3": lambda: W.batched(seed=4),
+    "multimethod_256_96_3": lambda: W.multimethod(seed=5, ng=256, nl=96),
+}
+
+
+@pytest.mark.parametrize("name", list(PREFIX))
+def test_full_size_prefix(name):
+    import hashlib
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "prefix_%s.npz" % name)
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated: " + path)
+    gold = np.load(path)
+    cfg = PREFIX[name]()
+    steps = int(gold["steps"])
+    assert float(gold["dt"]) == cfg["dt"]
+    say("full-size prefix %s: %d steps" % (name, steps))
+    g = pw.context_from_config(cfg)
+    g.init_exact(0.0)
+    for s0 in range(0, steps, 50):
+        g.rk4_step(cfg["dt"], min(50, steps - s0))
+    assert g.t == float(gold["time"])
+    f, c = g.flags()
+    assert hashlib.sha256(f.tobytes()).hexdigest() == gold["flags_sha256"].item().decode()
+    assert hashlib.sha256(c.astype(np.int32).tobytes()).hexdigest() == gold["cover_sha256"].item().decode()
+    cg = g.counters()
+    for k in ("skip_local", "skip_eff", "skip_uncover", "n_uncover", "skip_outer", "n_outer"):
+        assert cg[k] == int(gold["counter_" + k]), (k, cg[k], int(gold["counter_" + k]))
+    worst = 0.0
+    for pid, p in enumerate(cfg["patches"]):
+        n = p["n"]
+        live = (f == 0).reshape(-1) if pid == 0 else np.ones(n[0] * n[1] * n[2], dtype=bool)
+        idx = gold["idx_%d" % pid]
+        for sv in range(len(cfg["wave_speed"])):
+            if not p["sv_mask"] & (1 << sv):
+                continue
+            u = g.get_state(pid, sv).reshape(5, -1)
+            assert np.isfinite(u[:, live]).all()
+            mx = gold["max_%d_%d" % (pid, sv)]
+            scale = np.array([mx[0]] + [mx[1:].max()] * 4)
+            e = np.abs(u[:, idx] - gold["val_%d_%d" % (pid, sv)]).max(axis=1) / np.maximum(scale, 1e-300)
+            worst = max(worst, e.max())
+            assert (e <= TOL64).all(), (pid, sv, e)
+            assert np.allclose(np.abs(u[:, live]).max(axis=1), mx, rtol=1e-11, atol=0)
+            assert np.allclose((u[:, live] ** 2).sum(axis=1), gold["sumsq_%d_%d" % (pid, sv)], rtol=1e-11, atol=0)
+    say("  worst rel err on sampled cells", worst, cg)
+    g.close()
