@@ -184,6 +184,13 @@ typedef struct {
  *   int_rel_err:             sum over live cells of |phi - phi_e| / |phi_e| sqrt(gamma) d^3x'
  *                            (Sec. 3.2, with sqrt(gamma) = |det dX/dx'| the volume element)
  *   live_cells, volume:      live cell count and sum of sqrt(gamma) d^3x'
+ *   energy:                  1/2 sum (Pi_t^2 - v^2 phi L phi) dx0 dx1 dx2, L the sum of the
+ *                            4th-order second differences along the numerical axes (the
+ *                            discrete energy of a static Cartesian patch)
+ *   constraint_max:          max |Pi_a - D_a phi|, a = 1..3 (the constraint Psi_a = d_a phi
+ *                            of the first-order system, 4th-order D_a)
+ *   energy and constraint_max run over the live cells whose +-2 stencils along each
+ *   numerical axis reach live interior cells only (periodic axes wrap).
  */
 typedef struct {
   double max_abs[5];
@@ -193,6 +200,8 @@ typedef struct {
   double int_rel_err;
   double live_cells;
   double volume;
+  double energy;
+  double constraint_max[3];
 } pw_diag;
 
 /*

@@ -248,11 +248,12 @@ class OracleWorld:
         return c
 
     def diag(self, pid, sv=0):
-        out = np.zeros(23)
+        out = np.zeros(27)
         _, op = _d(out)
         self.L.or_diag(self.h, pid, sv, op)
         return dict(max=out[0:5].copy(), sumsq=out[5:10].copy(), err_max=out[10:15].copy(),
-                    err_sumsq=out[15:20].copy(), int_rel_err=out[20], live=int(out[21]), volume=out[22])
+                    err_sumsq=out[15:20].copy(), int_rel_err=out[20], live=int(out[21]), volume=out[22],
+                    energy=out[23], constraint=out[24:27].copy())
 
     # --- unit entry points -------------------------------------------------
     def metric(self, pid, sv, t, xp):

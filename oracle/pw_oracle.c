@@ -1461,12 +1461,26 @@ int or_cover_full(or_world *w, int32_t *dst) {
  * out[20]     integrated relative error of phi, sum |phi-phi_e|/|phi_e| sqrt(gamma) d^3x' (Sec. 3.2)
  * out[21]     number of live cells
  * out[22]     sum sqrt(gamma) d^3x' over live cells (covered volume)
+ * out[23]     discrete energy 1/2 sum (Pi_t^2 - v^2 phi L phi) dx dy dz, L the sum of the
+ *             4th-order second differences along the numerical axes
+ * out[24..26] max |Pi_a - D_a phi|, a = 1..3 (the constraint Psi_a = d_a phi)
+ *             out[23..26] over the live cells whose +-2 axis stencils reach live
+ *             interior cells only (periodic axes wrap)
  */
+/* live interior cell (i,j,k) + o e_a with a periodic axis wrapped; 0 if none */
+static int star_cell(const or_world *w, const or_patch *p, int i, int j, int k, int a, int o, int c[3]) {
+  c[0] = i; c[1] = j; c[2] = k;
+  c[a] += o;
+  if (p->periodic[a]) c[a] = wrapi(c[a], p->n[a]);
+  if (c[a] < 0 || c[a] >= p->n[a]) return 0;
+  return is_live(w, p, c[0], c[1], c[2]);
+}
+
 int or_diag(or_world *w, int pi, int sv, double *out) {
   or_patch *p = &w->p[pi];
   if (!p->u[sv]) return -1;
   if (!w->flags_valid) { int rc = refresh_flags(w); if (rc) return rc; }
-  for (int x = 0; x < 23; x++) out[x] = 0;
+  for (int x = 0; x < 27; x++) out[x] = 0;
   double cellvol = p->dx[0] * p->dx[1] * p->dx[2];
   for (int k = 0; k < p->n[2]; k++)
     for (int j = 0; j < p->n[1]; j++)
@@ -1490,6 +1504,25 @@ int or_diag(or_world *w, int pi, int sv, double *out) {
         if (has) out[20] += fabs(p->u[sv][IX(p, 0, i, j, k)] - e[0]) / fabs(e[0]) * sg * cellvol;
         out[21] += 1;
         out[22] += sg * cellvol;
+        /* energy density and constraint where the axis stencils stay on live cells */
+        double ph[3][5];
+        int ok = 1;
+        for (int a = 0; a < 3 && ok; a++)
+          for (int o = -2; o <= 2 && ok; o++) {
+            int c[3];
+            if (!star_cell(w, p, i, j, k, a, o, c)) ok = 0;
+            else ph[a][o + 2] = p->u[sv][IX(p, 0, c[0], c[1], c[2])];
+          }
+        if (!ok) continue;
+        double lap = 0;
+        for (int a = 0; a < 3; a++) {
+          lap += (-ph[a][0] + 16 * ph[a][1] - 30 * ph[a][2] + 16 * ph[a][3] - ph[a][4]) / (12 * p->dx[a] * p->dx[a]);
+          double d1 = (ph[a][0] - 8 * ph[a][1] + 8 * ph[a][3] - ph[a][4]) / (12 * p->dx[a]);
+          double c = fabs(p->u[sv][IX(p, 2 + a, i, j, k)] - d1);
+          if (c > out[24 + a]) out[24 + a] = c;
+        }
+        double pit = p->u[sv][IX(p, 1, i, j, k)], phi = ph[0][2];
+        out[23] += 0.5 * cellvol * (pit * pit - w->vs[sv] * w->vs[sv] * phi * lap);
       }
   return 0;
 }

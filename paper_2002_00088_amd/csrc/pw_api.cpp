@@ -1576,7 +1576,7 @@ pw_status pw_diagnostics(pw_context *c, int32_t pid, int32_t sv, pw_diag *out) {
   for (int b = 0; b < nb; b++)
     for (int x = 0; x < DIAG_N; x++) {
       double v = h[(size_t)b * DIAG_N + x];
-      bool mx = (x < 5) || (x >= 10 && x < 15);
+      bool mx = (x < 5) || (x >= 10 && x < 15) || x >= 24;
       acc[x] = mx ? std::max(acc[x], v) : acc[x] + v;
     }
   for (int f = 0; f < 5; f++) {
@@ -1588,6 +1588,8 @@ pw_status pw_diagnostics(pw_context *c, int32_t pid, int32_t sv, pw_diag *out) {
   out->int_rel_err = acc[20];
   out->live_cells = acc[21];
   out->volume = acc[22];
+  out->energy = acc[23];
+  for (int a = 0; a < 3; a++) out->constraint_max[a] = acc[24 + a];
   return PW_OK;
 }
 

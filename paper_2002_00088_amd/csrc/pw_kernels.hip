@@ -2381,13 +2381,44 @@ __global__ void k_diag(const PatchDev *__restrict__ P, const PoseDev *__restrict
     if (has) acc[20] += fabs(phi - e[0]) / fabs(e[0]) * sg * cellvol;
     acc[21] += 1.0;
     acc[22] += sg * cellvol;
+    // energy density 1/2 (Pi_t^2 - v^2 phi L phi) and the constraint Psi_a - D_a phi,
+    // where the +-2 axis stencils reach live interior cells only (periodic axes wrap)
+    double ph[3][5];
+    bool ok = true;
+    const int ci[3] = {i, j, k};
+    for (int a = 0; a < 3 && ok; a++)
+      for (int o = -2; o <= 2 && ok; o++) {
+        int cc[3] = {ci[0], ci[1], ci[2]};
+        cc[a] += o;
+        if (p.periodic[a]) cc[a] = ((cc[a] % p.n[a]) + p.n[a]) % p.n[a];
+        if (cc[a] < 0 || cc[a] >= p.n[a]) {
+          ok = false;
+          break;
+        }
+        if (p.is_global && gflag && gflag[((long long)cc[2] * p.n[1] + cc[1]) * p.n[0] + cc[0]] != LIVE) {
+          ok = false;
+          break;
+        }
+        ph[a][o + 2] = p.u[sv][cell_index(p, cc[0], cc[1], cc[2])];
+      }
+    if (ok) {
+      double lap = 0.0;
+      for (int a = 0; a < 3; a++) {
+        lap += (-ph[a][0] + 16.0 * ph[a][1] - 30.0 * ph[a][2] + 16.0 * ph[a][3] - ph[a][4]) /
+               (12.0 * p.dx[a] * p.dx[a]);
+        const double d1 = (ph[a][0] - 8.0 * ph[a][1] + 8.0 * ph[a][3] - ph[a][4]) / (12.0 * p.dx[a]);
+        acc[24 + a] = fmax(acc[24 + a], fabs(p.u[sv][(2 + a) * p.fstride + x] - d1));
+      }
+      const double pit = p.u[sv][p.fstride + x];
+      acc[23] += 0.5 * cellvol * (pit * pit - v * v * ph[0][2] * lap);
+    }
   }
   for (int x = 0; x < DIAG_N; x++) red[threadIdx.x][x] = acc[x];
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
       for (int x = 0; x < DIAG_N; x++) {
-        bool mx = (x < 5) || (x >= 10 && x < 15);
+        bool mx = (x < 5) || (x >= 10 && x < 15) || x >= 24;
         double o = red[threadIdx.x + s][x];
         red[threadIdx.x][x] = mx ? fmax(red[threadIdx.x][x], o) : red[threadIdx.x][x] + o;
       }

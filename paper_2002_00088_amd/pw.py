@@ -68,7 +68,7 @@ class ExactDesc(C.Structure):
 class Diag(C.Structure):
     _fields_ = [("max_abs", C.c_double * 5), ("sum_sq", C.c_double * 5), ("err_max", C.c_double * 5),
                 ("err_sum_sq", C.c_double * 5), ("int_rel_err", C.c_double), ("live_cells", C.c_double),
-                ("volume", C.c_double)]
+                ("volume", C.c_double), ("energy", C.c_double), ("constraint_max", C.c_double * 3)]
 
 
 class Tuning(C.Structure):
@@ -306,7 +306,7 @@ class Context:
         self._chk(self.L.pw_diagnostics(self.h, pid, sv, C.byref(d)))
         return dict(max=np.array(d.max_abs[:]), sumsq=np.array(d.sum_sq[:]), err_max=np.array(d.err_max[:]),
                     err_sumsq=np.array(d.err_sum_sq[:]), int_rel_err=d.int_rel_err, live=int(d.live_cells),
-                    volume=d.volume)
+                    volume=d.volume, energy=d.energy, constraint=np.array(d.constraint_max[:]))
 
     def counters(self):
         c = Counters()

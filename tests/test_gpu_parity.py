@@ -748,3 +748,49 @@ def test_full_size_prefix(name):
             assert np.allclose((u[:, live] ** 2).sum(axis=1), gold["sumsq_%d_%d" % (pid, sv)], rtol=1e-11, atol=0)
     say("  worst rel err on sampled cells", worst, cg)
     g.close()
+
+
+@pytest.mark.parametrize("case", ["periodic", "two_patch"])
+def test_diagnostics_energy_and_constraint(case):
+    # the energy and constraint diagnostics of the library against the oracle's
+    cfg = W.single_periodic(seed=1, n=(24, 20, 16)) if case == "periodic" else W.two_patch(seed=3, ng=48, nl=40, P=6)
+    say("diagnostics", case)
+    o, g = run_pair(cfg, 3, init="random", seed=61)
+    for pid in range(len(cfg["patches"])):
+        do, dg = o.diag(pid), g.diagnostics(pid)
+        assert dg["live"] == do["live"]
+        assert dg["energy"] == pytest.approx(do["energy"], rel=1e-11, abs=1e-12 * abs(do["energy"]) + 1e-300)
+        scale = max(np.max(do["max"][1:]), 1e-300)
+        assert np.all(np.abs(dg["constraint"] - do["constraint"]) <= 1e-11 * scale + 1e-12 * do["constraint"])
+        say("  patch", pid, "energy", dg["energy"], do["energy"], "constraint", dg["constraint"])
+
+
+@pytest.mark.parametrize("prec", [pw.PW_FP64, pw.PW_MIXED])
+def test_save_restore_bitwise(prec):
+    # resuming from a saved state (pw_get_state -> a new context -> pw_set_state)
+    # continues bitwise like the uninterrupted run
+    cfg = W.batched(seed=4, ng=96, nmin=16, nmax=36)
+    say("save/restore", prec, len(cfg["patches"]), "patches")
+    a = pw.context_from_config(cfg, precision=prec)
+    a.init_exact(0.0)
+    a.rk4_step(cfg["dt"], 6)
+    b = pw.context_from_config(cfg, precision=prec)
+    b.init_exact(0.0)
+    b.rk4_step(cfg["dt"], 3)
+    saved = [b.get_state(pid) for pid in range(len(cfg["patches"]))]
+    t = b.t
+    b.close()
+    c = pw.context_from_config(cfg, precision=prec)
+    for pid, s in enumerate(saved):
+        c.set_state(pid, 0, s, t)
+    c.rk4_step(cfg["dt"], 3)
+    assert c.t == a.t
+    fa, ca = a.flags()
+    fc, cc = c.flags()
+    assert (fa == fc).all() and (ca == cc).all()
+    for pid in range(len(cfg["patches"])):
+        x, y = a.get_state(pid), c.get_state(pid)
+        m = (fa == 0) if pid == 0 else np.ones(x.shape[1:], dtype=bool)
+        assert np.array_equal(x[:, m], y[:, m]), pid
+    a.close()
+    c.close()

@@ -869,3 +869,37 @@ def test_spherical_global_convergence():
         errs.append(w.diag(0)["int_rel_err"] + w.diag(1)["int_rel_err"])
     slope = math.log2(errs[0] / errs[1])
     assert 3.5 < slope < 4.8, (errs, slope)
+
+
+def test_diag_energy_and_constraint_match_numpy():
+    """The oracle's diagnostics: the discrete energy E = 1/2 sum (Pi_t^2 - v^2 phi L phi) h^3
+    and max |Psi_a - D_a phi| over the cells whose +-2 axis stencils stay in the
+    patch (every cell on a periodic patch), against the same quantities formed
+    here with numpy (periodic rolls; interior slices on a non-periodic box)."""
+    v = 0.8
+    n = [12, 10, 14]
+    dx = [1.0 / n[a] for a in range(3)]
+    axes = {0: 2, 1: 1, 2: 0}
+    u = smooth_random(n, 21)
+    w = OracleWorld(wave_speed=(v,))
+    w.add_patch(W.patch(n, [0, 0, 0], [1, 1, 1], is_global=1, periodic=(1, 1, 1)))
+    w.set_state(0, 0, u)
+    d = w.diag(0)
+    assert d["energy"] == pytest.approx(energy(u, dx, v), rel=1e-12)
+    for a in range(3):
+        c = np.max(np.abs(u[2 + a] - periodic_D1(u[0], dx[a], axes[a])))
+        assert d["constraint"][a] == pytest.approx(c, rel=1e-12)
+    # non-periodic box: only cells at least two cells from every face count
+    w2 = OracleWorld(wave_speed=(v,))
+    lo, hi = [-0.5, 0.2, -1.0], [1.0, 1.4, 0.6]
+    w2.add_patch(W.patch(n, lo, hi, is_global=1))
+    w2.set_state(0, 0, u)
+    d2 = w2.diag(0)
+    h = [(hi[a] - lo[a]) / n[a] for a in range(3)]
+    inner = (slice(2, -2), slice(2, -2), slice(2, -2))
+    lap = sum(periodic_D2(u[0], h[a], axes[a]) for a in range(3))[inner]
+    e = 0.5 * np.prod(h) * np.sum(u[1][inner] ** 2 - v * v * u[0][inner] * lap)
+    assert d2["energy"] == pytest.approx(e, rel=1e-12)
+    for a in range(3):
+        c = np.max(np.abs(u[2 + a][inner] - periodic_D1(u[0], h[a], axes[a])[inner]))
+        assert d2["constraint"][a] == pytest.approx(c, rel=1e-12)
