@@ -31,9 +31,15 @@ struct StageTile {
 #ifndef BRICK_LDS_BYTES
 #define BRICK_LDS_BYTES 30720
 #endif
+#ifndef L2G_BLOCKS
 #define L2G_BLOCKS 2048  // a multiple of 8
+#endif
+#ifndef L2G_WAVES
 #define L2G_WAVES 3
+#endif
+#ifndef L2G_LDS_BYTES
 #define L2G_LDS_BYTES 36864
+#endif
 #define BUCKET_SORT_LDS 4096
 
 namespace pw {

@@ -105,12 +105,44 @@ __global__ __launch_bounds__(256) void k_cover(const PatchDev *__restrict__ P, c
 // paragraph): each outer ghost cell that is not a periodic copy is tested
 // against the local patches in ascending id (the same closed-box test as
 // k_cover); the first that contains its centre is recorded with it.
+// Candidates first: with a Cartesian global only patches whose bounding
+// sphere reaches past a face of the domain can cover an outer ghost centre;
+// each workgroup lists them in LDS (ascending id) and exits if there are none.
+#define COVER_OUTER_MAXJOBS 4096
 __global__ __launch_bounds__(256) void k_cover_outer(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose,
                                                      const CoverJob *jobs, int njobs, const GhostRec *phys, int nphys,
                                                      int2 *olist, int *ocount) {
+  __shared__ short cand[COVER_OUTER_MAXJOBS];
+  __shared__ int ncand;
+  __shared__ int wcnt[4];
+  const PatchDev &g = P[0];
+  if (threadIdx.x == 0) ncand = 0;
+  __syncthreads();
+  // one pass of 256 jobs at a time keeps the list in ascending id order
+  for (int m0 = 0; m0 < njobs && m0 < COVER_OUTER_MAXJOBS; m0 += 256) {
+    const int m = m0 + (int)threadIdx.x;
+    bool c = false;
+    if (m < njobs) {
+      const CoverJob &J = jobs[m];
+      const PoseDev &ps = pose[J.patch];
+      c = g.coord != CART;
+      for (int a = 0; a < 3 && !c; a++) c = ps.c[a] - J.radius < g.lo[a] || ps.c[a] + J.radius > g.hi[a];
+    }
+    const unsigned long long bal = __ballot(c);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) wcnt[wv] = __popcll(bal);
+    __syncthreads();
+    int base = ncand;
+    for (int w = 0; w < wv; w++) base += wcnt[w];
+    if (c) cand[base + __popcll(bal & ((1ull << lane) - 1ull))] = (short)m;
+    __syncthreads();
+    if (threadIdx.x == 0) ncand += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  const int nc = ncand;
+  if (nc == 0) return;
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= nphys) return;
-  const PatchDev &g = P[0];
   int c[3];
   {
     const uint32_t w = phys[q].cell;
@@ -120,8 +152,8 @@ __global__ __launch_bounds__(256) void k_cover_outer(const PatchDev *__restrict_
   }
   double X[3];
   global_X(g, pose[0], c[0], c[1], c[2], X);
-  for (int m = 0; m < njobs; m++) {
-    const CoverJob &J = jobs[m];
+  for (int mc = 0; mc < nc; mc++) {
+    const CoverJob &J = jobs[cand[mc]];
     const PatchDev &p = P[J.patch];
     const PoseDev &ps = pose[J.patch];
     const double d0 = X[0] - ps.c[0], d1 = X[1] - ps.c[1], d2 = X[2] - ps.c[2];
