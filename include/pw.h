@@ -296,7 +296,12 @@ typedef struct {
   int32_t tile_z_local;  /* the same for local patches (1..512) */
   int32_t g2l_run;       /* consecutive local-ghost bricks dealt to one XCD (1..64) */
   int32_t l2g_run;       /* consecutive 64-entry effective-ghost groups dealt to one XCD (1..64) */
+  int32_t global_order;  /* how the global patch's stage tiles are dealt to the eight XCDs
+                            (each has its own L2): PW_ORDER_BANDS (0) eight bands of tile
+                            rows, PW_ORDER_OCTANTS (1) the eight octants of the index box,
+                            whose shared faces, read from two L2s, are smaller */
 } pw_tuning;
+enum { PW_ORDER_BANDS = 0, PW_ORDER_OCTANTS = 1 };
 
 /* Current tuning parameters. */
 pw_status pw_get_tuning(pw_context *ctx, pw_tuning *out);
@@ -307,7 +312,8 @@ pw_status pw_set_tuning(pw_context *ctx, const pw_tuning *t);
 
 /* Autotuner: times candidate settings on this context's own patches with HIP
  * events over steps_per_trial steps of size dt each (after one untimed step),
- * searching the two tile depths on a grid, then the two run lengths, and keeps
+ * searching the two tile depths and the global tile order on a grid, then the
+ * two run lengths, and keeps
  * the fastest (written to *best unless best is NULL).  It advances the state and
  * the time by every step it takes, so call it before setting the initial data
  * (or set it again afterwards).  On an error the previous settings are restored. */

@@ -102,7 +102,7 @@ struct pw_context {
   long long stageCap = 0;
   double *dPartial = nullptr;
   bool layout_dirty = true, flags_valid = false;
-  pw_tuning tune = {TUNE_TZ_GLOBAL, TUNE_TZ_LOCAL, TUNE_G2L_RUN, TUNE_L2G_RUN};
+  pw_tuning tune = {TUNE_TZ_GLOBAL, TUNE_TZ_LOCAL, TUNE_G2L_RUN, TUNE_L2G_RUN, PW_ORDER_BANDS};
   double t_host = 0.0;
   // first failure of a runtime call while a step is enqueued (event records and
   // waits between the step's streams); reported by pw_rk4_step
@@ -421,6 +421,23 @@ pw_status upload_layout(pw_context *c) {
     const int TX = pid == 0 ? StageTile<true>::TX : StageTile<false>::TX;
     const int TY = pid == 0 ? StageTile<true>::TY : StageTile<false>::TY;
     const int TZ = pid == 0 ? c->tune.tile_z_global : c->tune.tile_z_local;
+    if (pid == 0 && c->tune.global_order == PW_ORDER_OCTANTS) {
+      // the global patch in its eight octants (halves of the tile counts along
+      // each axis), each z-chunk by z-chunk: the stage kernel hands each XCD a
+      // contiguous eighth of the tiles, so every XCD works through one octant,
+      // and only three faces of it are shared with another XCD's L2
+      const int nx = (p.n[0] + TX - 1) / TX, ny = (p.n[1] + TY - 1) / TY, nzc = (p.n[2] + TZ - 1) / TZ;
+      const int hx = (nx + 1) / 2, hy = (ny + 1) / 2, hz = (nzc + 1) / 2;
+      for (int oz = 0; oz < 2; oz++)
+        for (int oy = 0; oy < 2; oy++)
+          for (int ox = 0; ox < 2; ox++)
+            for (int zc = oz * hz; zc < std::min(nzc, (oz + 1) * hz); zc++)
+              for (int yt = oy * hy; yt < std::min(ny, (oy + 1) * hy); yt++)
+                for (int xt = ox * hx; xt < std::min(nx, (ox + 1) * hx); xt++)
+                  tiles.push_back(TileRec{pid, xt * TX, yt * TY, zc * TZ, std::min(TZ, p.n[2] - zc * TZ)});
+      c->tileCnt[pid] = (int)tiles.size() - c->tileOff[pid];
+      return;
+    }
     if (pid == 0) {
       // the global patch in eight bands of tile rows, each band z-chunk by
       // z-chunk: the stage kernel hands each XCD a contiguous run of tiles, so
@@ -1477,6 +1494,8 @@ pw_status pw_get_tuning(pw_context *c, pw_tuning *out) {
 
 pw_status pw_set_tuning(pw_context *c, const pw_tuning *t) {
   if (!c || !t) return PW_EINVAL;
+  if (t->global_order != PW_ORDER_BANDS && t->global_order != PW_ORDER_OCTANTS)
+    return fail(c, PW_EINVAL, "tuning parameter out of range");
   if (t->tile_z_global < 1 || t->tile_z_global > 512 || t->tile_z_local < 1 || t->tile_z_local > 512 ||
       t->g2l_run < 1 || t->g2l_run > 64 || t->l2g_run < 1 || t->l2g_run > 64)
     return fail(c, PW_EINVAL, "tuning parameter out of range");
@@ -1514,14 +1533,17 @@ pw_status pw_autotune(pw_context *c, double dt, int32_t steps_per_trial, pw_tuni
   pw_tuning cur = c->tune, bestT = cur;
   float bestMs = 3.0e38f, ms = 0.0f;
   static const int tzg[3] = {16, 32, 64}, tzl[3] = {4, 8, 16}, runs_g2l[3] = {4, 8, 16}, runs_l2g[3] = {2, 4, 8};
-  for (int a = 0; a < 3 && !rc; a++)
-    for (int b = 0; b < 3 && !rc; b++) {
-      pw_tuning t = bestT;
-      t.tile_z_global = tzg[a];
-      t.tile_z_local = tzl[b];
-      rc = trial(t, ms);
-      if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
-    }
+  const pw_tuning base0 = bestT;
+  for (int o = 0; o < 2 && !rc; o++)
+    for (int a = 0; a < 3 && !rc; a++)
+      for (int b = 0; b < 3 && !rc; b++) {
+        pw_tuning t = base0;
+        t.global_order = o;
+        t.tile_z_global = tzg[a];
+        t.tile_z_local = tzl[b];
+        rc = trial(t, ms);
+        if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
+      }
   if (has_locals(c)) {
     const pw_tuning base = bestT;
     for (int a = 0; a < 3 && !rc; a++) {

@@ -630,7 +630,8 @@ def test_tuning_changes_no_value():
     cfg = W.batched(seed=4, ng=64, nlocal=8, nmin=16, nmax=24)
     outs = []
     for tune in (None, dict(tile_z_global=16, tile_z_local=4, g2l_run=2, l2g_run=8),
-                 dict(tile_z_global=64, tile_z_local=3, g2l_run=16, l2g_run=1)):
+                 dict(tile_z_global=64, tile_z_local=3, g2l_run=16, l2g_run=1, global_order=pw.PW_ORDER_OCTANTS),
+                 dict(tile_z_global=8, global_order=pw.PW_ORDER_OCTANTS)):
         g = pw.context_from_config(cfg, precision=pw.PW_MIXED)
         if tune:
             g.set_tuning(**tune)
