@@ -11,8 +11,12 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "pw_oracle.c")
+# PW_ORACLE_SANITIZE=1 selects a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the process must preload libasan; see
+# tests/test_oracle_sanitized.py)
+SANITIZE = os.environ.get("PW_ORACLE_SANITIZE") == "1"
+LIB = os.path.join(HERE, "liboracle_asan.so" if SANITIZE else "liboracle.so")
 
 CART, SPH, CYL = 0, 1, 2
 STATIC, LINEAR, CIRCLE = 0, 1, 2
@@ -25,8 +29,10 @@ def build(force=True):
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp"
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"] \
+        if SANITIZE else []
     subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-                           "-Wall", "-o", tmp, SRC, "-lm"])
+                           "-Wall"] + san + ["-o", tmp, SRC, "-lm"])
     os.replace(tmp, LIB)
     return LIB
 
