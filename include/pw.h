@@ -300,8 +300,14 @@ typedef struct {
                             (each has its own L2): PW_ORDER_BANDS (0) eight bands of tile
                             rows, PW_ORDER_OCTANTS (1) the eight octants of the index box,
                             whose shared faces, read from two L2s, are smaller */
+  int32_t chain;         /* where the stage kernels of the curvilinear local patches run in
+                            the two-stream step: PW_CHAIN_GLOBAL (0) on the global chain
+                            after the global stage kernel, PW_CHAIN_LOCAL_AFTER (1) on the
+                            local chain after the Cartesian local patches,
+                            PW_CHAIN_LOCAL_BEFORE (2) on the local chain before them */
 } pw_tuning;
 enum { PW_ORDER_BANDS = 0, PW_ORDER_OCTANTS = 1 };
+enum { PW_CHAIN_GLOBAL = 0, PW_CHAIN_LOCAL_AFTER = 1, PW_CHAIN_LOCAL_BEFORE = 2 };
 
 /* Current tuning parameters. */
 pw_status pw_get_tuning(pw_context *ctx, pw_tuning *out);
@@ -313,7 +319,7 @@ pw_status pw_set_tuning(pw_context *ctx, const pw_tuning *t);
 /* Autotuner: times candidate settings on this context's own patches with HIP
  * events over steps_per_trial steps of size dt each (after one untimed step),
  * searching the two tile depths and the global tile order on a grid, then the
- * two run lengths, and keeps
+ * place of the curvilinear local stage kernels, then the two run lengths, and keeps
  * the fastest (written to *best unless best is NULL).  It advances the state and
  * the time by every step it takes, so call it before setting the initial data
  * (or set it again afterwards).  On an error the previous settings are restored. */

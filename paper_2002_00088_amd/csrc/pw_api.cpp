@@ -102,7 +102,7 @@ struct pw_context {
   long long stageCap = 0;
   double *dPartial = nullptr;
   bool layout_dirty = true, flags_valid = false;
-  pw_tuning tune = {TUNE_TZ_GLOBAL, TUNE_TZ_LOCAL, TUNE_G2L_RUN, TUNE_L2G_RUN, PW_ORDER_BANDS};
+  pw_tuning tune = {TUNE_TZ_GLOBAL, TUNE_TZ_LOCAL, TUNE_G2L_RUN, TUNE_L2G_RUN, PW_ORDER_BANDS, TUNE_CHAIN};
   double t_host = 0.0;
   // first failure of a runtime call while a step is enqueued (event records and
   // waits between the step's streams); reported by pw_rk4_step
@@ -779,9 +779,11 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
 //     Cartesian local patches.
 //   Y, the global chain: periodic copies of the local patches, local -> global
 //     interpolation of stage s (it reads the local stage s-1 output), outer
-//     ghosts, the global stage kernel, then the stage kernels of the
-//     curvilinear local patches (which need the global -> local fill of X).
-//     The two chains are about equally long this way.
+//     ghosts, the global stage kernel.
+//   The stage kernels of the curvilinear local patches (which need the global
+//   -> local fill of X) go at the end of Y or before or after the Cartesian
+//   ones on X (tuning parameter `chain`): which of them keeps the two chains
+//   best overlapped depends on the mix of patches.
 //   Z: the cover flags of the next step (they depend on the poses at t_{n+1}
 //     only) while the stages run, and their lists once the last ghost fill of
 //     this step is done.
@@ -841,25 +843,33 @@ void enqueue_step_overlap(pw_context *c, double dt) {
       ENQ(c, hipEventRecord(c->evE[s], Y));
       ENQ(c, hipStreamWaitEvent(X, c->evE[s], 0));
     }
-    // X: stage kernels of the Cartesian local patches
+    // X: stage kernels of the Cartesian local patches, and of the curvilinear
+    // ones before or after them unless they go on Y
+    const int chain = c->tune.chain;
+    if (chain == PW_CHAIN_LOCAL_BEFORE) enqueue_stage_part(c, s, ps, dt, 2, X, 6);
     enqueue_stage_part(c, s, ps, dt, 2, X, 1);
+    if (chain == PW_CHAIN_LOCAL_AFTER) enqueue_stage_part(c, s, ps, dt, 2, X, 6);
     ENQ(c, hipEventRecord(c->evL[s], X));
-    // Y: local -> global interpolation, outer ghosts, global stage, then the
-    // stage kernels of the curvilinear local patches (they wait for X's fill;
-    // placed here they even out the lengths of the two chains)
+    if (chain != PW_CHAIN_GLOBAL) ENQ(c, hipEventRecord(c->evS[s], X));
+    // Y: local -> global interpolation, outer ghosts, global stage, then (if
+    // they go here) the stage kernels of the curvilinear local patches, which
+    // wait for X's fill
     enqueue_ghosts(c, s, ps, c->dT, tmul[s], dt, GH_GLOBAL, Y);
     if (s == 3) ENQ(c, hipEventRecord(c->evGhG, Y));
     enqueue_stage_part(c, s, ps, dt, 1, Y);
     ENQ(c, hipEventRecord(c->evG[s], Y));
-    ENQ(c, hipStreamWaitEvent(Y, c->evGL[s], 0));
-    enqueue_stage_part(c, s, ps, dt, 2, Y, 6);
-    ENQ(c, hipEventRecord(c->evS[s], Y));
+    if (chain == PW_CHAIN_GLOBAL) {
+      ENQ(c, hipStreamWaitEvent(Y, c->evGL[s], 0));
+      enqueue_stage_part(c, s, ps, dt, 2, Y, 6);
+      ENQ(c, hipEventRecord(c->evS[s], Y));
+    }
   }
   ENQ(c, hipStreamWaitEvent(Z, c->evGhL, 0));
   ENQ(c, hipStreamWaitEvent(Z, c->evGhG, 0));
   enqueue_post_flags(c, c->dPose + 2 * np, Z);
   ENQ(c, hipEventRecord(c->evNext, Z));
-  ENQ(c, hipStreamWaitEvent(X, narrow ? c->evG[3] : c->evS[3], 0));
+  ENQ(c, hipStreamWaitEvent(X, c->evG[3], 0));
+  if (!narrow) ENQ(c, hipStreamWaitEvent(X, c->evS[3], 0));
   ENQ(c, hipStreamWaitEvent(X, c->evNext, 0));
   launch_advance_time(X, c->dT, dt, (long long *)c->dCounters);
   enqueue_finalize(c, c->dPose + 2 * np, 1);
@@ -1496,6 +1506,8 @@ pw_status pw_set_tuning(pw_context *c, const pw_tuning *t) {
   if (!c || !t) return PW_EINVAL;
   if (t->global_order != PW_ORDER_BANDS && t->global_order != PW_ORDER_OCTANTS)
     return fail(c, PW_EINVAL, "tuning parameter out of range");
+  if (t->chain < PW_CHAIN_GLOBAL || t->chain > PW_CHAIN_LOCAL_BEFORE)
+    return fail(c, PW_EINVAL, "tuning parameter out of range");
   if (t->tile_z_global < 1 || t->tile_z_global > 512 || t->tile_z_local < 1 || t->tile_z_local > 512 ||
       t->g2l_run < 1 || t->g2l_run > 64 || t->l2g_run < 1 || t->l2g_run > 64)
     return fail(c, PW_EINVAL, "tuning parameter out of range");
@@ -1506,8 +1518,8 @@ pw_status pw_set_tuning(pw_context *c, const pw_tuning *t) {
 
 // Coordinate search over the tuning parameters, each candidate timed with HIP
 // events over steps_per_trial steps (after one untimed step, which also captures
-// the step graph): the tile depths on a global x local grid, then the brick run,
-// then the group run.
+// the step graph): the tile depths and the global tile order on a grid, then the
+// chain of the curvilinear local stages, then the brick run, then the group run.
 pw_status pw_autotune(pw_context *c, double dt, int32_t steps_per_trial, pw_tuning *best) {
   if (!c || !(dt > 0) || steps_per_trial < 1) return PW_EINVAL;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1545,6 +1557,14 @@ pw_status pw_autotune(pw_context *c, double dt, int32_t steps_per_trial, pw_tuni
         if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
       }
   if (has_locals(c)) {
+    const pw_tuning base1 = bestT;
+    for (int a = 0; a < 3 && !rc; a++) {
+      if (a == base1.chain) continue;
+      pw_tuning t = base1;
+      t.chain = a;
+      rc = trial(t, ms);
+      if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
+    }
     const pw_tuning base = bestT;
     for (int a = 0; a < 3 && !rc; a++) {
       pw_tuning t = base;

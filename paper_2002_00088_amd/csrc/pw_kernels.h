@@ -26,6 +26,7 @@ struct StageTile {
 #define TUNE_TZ_LOCAL 8
 #define TUNE_G2L_RUN 8
 #define TUNE_L2G_RUN 4
+#define TUNE_CHAIN 0
 #define DIAG_N 27
 #define BRICK_THREADS 192
 #ifndef BRICK_LDS_BYTES

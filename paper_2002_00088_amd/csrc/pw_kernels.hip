@@ -904,10 +904,11 @@ __global__ __launch_bounds__(BRICK_THREADS) __attribute__((amdgpu_waves_per_eu(4
   // two-dword read; FP64 sums: field after field
   constexpr bool VEC = sizeof(TC) == 4;
   constexpr int INFLIGHT = 4;  // box cells per thread with their loads in flight together
-  typedef TC TO;               // type of the outer sums
+  typedef double TO;           // type of the outer (y, z) sums: FP64 weights, FP64 accumulation
   constexpr int CAPV = BRICK_LDS_BYTES / 20;  // cells of a float4 + float box
   __shared__ __align__(16) unsigned char lds_raw[BRICK_LDS_BYTES];
-  __shared__ int blo[3], bhi[3];
+  constexpr int NWAVE = BRICK_THREADS / 64;
+  __shared__ int wbox[NWAVE][6];  // per wavefront: lowest and highest donor index per axis
   // runs of `run` consecutive bricks (which share donor cells) on one XCD
   const int bidx = xcd_spread(blockIdx.x, run);
   if (bidx >= nbricks) return;
@@ -915,11 +916,6 @@ __global__ __launch_bounds__(BRICK_THREADS) __attribute__((amdgpu_waves_per_eu(4
   const PatchDev &r = P[B.patch];
   const PatchDev &G0 = P[0];
   const int tid = threadIdx.x;
-  if (tid < 3) {
-    blo[tid] = 1 << 30;
-    bhi[tid] = -(1 << 30);
-  }
-  __syncthreads();
   const int c[3] = {B.i0 + tid % B.di, B.j0 + (tid / B.di) % B.dj, B.k0 + tid / (B.di * B.dj)};
   bool active = tid < B.di * B.dj * B.dk;
   if (active) {
@@ -953,19 +949,49 @@ __global__ __launch_bounds__(BRICK_THREADS) __attribute__((amdgpu_waves_per_eu(4
       for (int a = 0; a < 3; a++) inr = inr && s[a] >= 0 && s[a] + Pts - 1 <= G0.n[a] - 1;
       if (inr) valid = dvalid[((long long)s[2] * G0.n[1] + s[1]) * G0.n[0] + s[0]] != 0;
     }
-    if (valid)
+  }
+  // the donor box: the union of the valid points' stencils, reduced within each
+  // wavefront by xor shuffles, the wavefronts' boxes combined through LDS
+  // (contended LDS atomics on six words cost more than the interpolation sums)
+  {
+    int bl[3], bh[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      bl[a] = valid ? s[a] : (1 << 30);
+      bh[a] = valid ? s[a] + Pts - 1 : -(1 << 30);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
       for (int a = 0; a < 3; a++) {
-        atomicMin(&blo[a], s[a]);
-        atomicMax(&bhi[a], s[a] + Pts - 1);
+        bl[a] = min(bl[a], __shfl_xor(bl[a], off));
+        bh[a] = max(bh[a], __shfl_xor(bh[a], off));
+      }
+    if ((tid & 63) == 0)
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        wbox[tid >> 6][a] = bl[a];
+        wbox[tid >> 6][3 + a] = bh[a];
       }
   }
   __syncthreads();
+  int blo[3], bhi[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    blo[a] = wbox[0][a];
+    bhi[a] = wbox[0][3 + a];
+#pragma unroll
+    for (int w = 1; w < NWAVE; w++) {
+      blo[a] = min(blo[a], wbox[w][a]);
+      bhi[a] = max(bhi[a], wbox[w][3 + a]);
+    }
+  }
   const int lo0 = blo[0], lo1 = blo[1], lo2 = blo[2];
   const int e0 = bhi[0] - lo0 + 1, e1 = bhi[1] - lo1 + 1, e2 = bhi[2] - lo2 + 1;
   const long long vol = (e0 > 0 && e1 > 0 && e2 > 0) ? (long long)e0 * e1 * e2 : 0;
   const TB *T = stage_buf<TB>(G0, sv, stage);
-  // the sums run in the compute type: FP64 weights rounded to it once (the x
-  // weights, and the products wy[b] wz[c] of the outer sums)
+  // the x-row sums run in the compute type with the x weights rounded to it
+  // once; the row sums are combined with the FP64 products wy[b] wz[c] in FP64
   TO acc[5] = {0, 0, 0, 0, 0};
   TC wxc[Pts];
 #pragma unroll
@@ -1028,6 +1054,9 @@ __global__ __launch_bounds__(BRICK_THREADS) __attribute__((amdgpu_waves_per_eu(4
               r1 += e01;
               continue;
             }
+            // the layer's rows combined with the FP64 y weights, the layers
+            // with the FP64 z weights
+            TO ly[5] = {0, 0, 0, 0, 0};
 #pragma unroll
             for (int b = 0; b < Pts; b++) {
               float4 w4[Pts];
@@ -1048,13 +1077,15 @@ __global__ __launch_bounds__(BRICK_THREADS) __attribute__((amdgpu_waves_per_eu(4
                 p3 += wxc[a] * w4[a].w;
                 p4 += wxc[a] * w1[a];
               }
-              const TO wyz = (TO)(wy[b] * wz[cc]);
-              acc[0] += wyz * (TO)p0;
-              acc[1] += wyz * (TO)p1;
-              acc[2] += wyz * (TO)p2;
-              acc[3] += wyz * (TO)p3;
-              acc[4] += wyz * (TO)p4;
+              const TO wb = (TO)wy[b];
+              ly[0] += wb * (TO)p0;
+              ly[1] += wb * (TO)p1;
+              ly[2] += wb * (TO)p2;
+              ly[3] += wb * (TO)p3;
+              ly[4] += wb * (TO)p4;
             }
+#pragma unroll
+            for (int f = 0; f < 5; f++) acc[f] += (TO)wz[cc] * ly[f];
             r4 += skip;
             r1 += skip;
           }
@@ -1219,7 +1250,9 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
   double2 *b01d = (double2 *)lds_box;
   double2 *b23d = (double2 *)(lds_box + 16 * CAPC);
   double *b4d = (double *)(lds_box + 32 * CAPC);
-  __shared__ TC red[L2G_WAVES - 1][5][64];
+  // partial sums of waves 1.. for wave 0, in the box's LDS once the sums are done
+  static_assert((L2G_WAVES - 1) * 5 * 64 * sizeof(double) <= L2G_LDS_BYTES, "reduction fits the box LDS");
+  double(*red)[5][64] = (double(*)[5][64])lds_box;
   __shared__ int obox[8][8];  // per octet: lo[3], hi[3], lowest and highest donor id
   const PatchDev &G0 = P[0];
   if (!(G0.sv_mask & (1u << sv))) return;
@@ -1249,10 +1282,13 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
     double xd[3] = {0, 0, 0};
     bool valid = have && d >= 1 && (P[d].sv_mask & (1u << sv));
     int s[3] = {0, 0, 0};
-    // Lagrange weights are formed in FP64 and kept in the compute type
-    TC wxc[Pts], wyc[Pts], wzc[Pts];
+    // Lagrange weights are formed in FP64; the x weights are rounded to the
+    // compute type for the x-row sums, the y and z weights stay FP64 for the
+    // outer sums, which accumulate in FP64
+    TC wxc[Pts];
+    double wyc[Pts], wzc[Pts];
 #pragma unroll
-    for (int m = 0; m < Pts; m++) { wxc[m] = (TC)0; wyc[m] = (TC)0; wzc[m] = (TC)0; }
+    for (int m = 0; m < Pts; m++) { wxc[m] = (TC)0; wyc[m] = 0.0; wzc[m] = 0.0; }
     if (valid) {
       const PatchDev &D = P[d];
       const double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
@@ -1268,7 +1304,7 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
         s[1] = lagrange_wt<Pts>(q[1], wy);
         s[2] = lagrange_wt<Pts>(q[2], wz);
 #pragma unroll
-        for (int m = 0; m < Pts; m++) { wxc[m] = (TC)wx[m]; wyc[m] = (TC)wy[m]; wzc[m] = (TC)wz[m]; }
+        for (int m = 0; m < Pts; m++) { wxc[m] = (TC)wx[m]; wyc[m] = wy[m]; wzc[m] = wz[m]; }
         for (int a = 0; a < 3; a++)
           if (!D.periodic[a] && (s[a] < 0 || s[a] + Pts - 1 > D.n[a] - 1)) valid = false;
       }
@@ -1283,7 +1319,7 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
       atomicMax(&ob[7], d);
     }
     __syncthreads();
-    TC acc[5] = {0, 0, 0, 0, 0};
+    double acc[5] = {0, 0, 0, 0, 0};
     // runs of octets (the same on every thread: read from LDS)
     for (int o0 = 0; o0 < 8;) {
       int lo[3], hi[3], dmin, dmax;
@@ -1391,7 +1427,7 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
               const int lz = s[2] - lo[2] + cc - z0;
               if (lz < 0 || lz >= nz) continue;
               const int o = lz * e01 + first;
-              TC layer[5] = {0, 0, 0, 0, 0};
+              double layer[5] = {0, 0, 0, 0, 0};
 #pragma unroll
               for (int b = 0; b < Pts; b++) {
                 TC p5[5] = {0, 0, 0, 0, 0};
@@ -1428,7 +1464,7 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
                   }
                 }
 #pragma unroll
-                for (int f = 0; f < 5; f++) layer[f] += wyc[b] * p5[f];
+                for (int f = 0; f < 5; f++) layer[f] += wyc[b] * (double)p5[f];
               }
 #pragma unroll
               for (int f = 0; f < 5; f++) acc[f] += wzc[cc] * layer[f];
@@ -1448,16 +1484,17 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
           }
           return -1;
         };
-        auto taps = [&](int pnt, TC out[5]) {
+        // (rare) the tap weights w_x w_y w_z in FP64, the sums in FP64
+        auto taps = [&](int pnt, double out[5]) {
           const int dd = bcast_i(d, pnt);
           const int s0 = bcast_i(s[0], pnt), s1 = bcast_i(s[1], pnt), s2 = bcast_i(s[2], pnt);
-          TC wxa = (TC)0, wyb = (TC)0, wzp[Pts];
+          double wxa = 0.0, wyb = 0.0, wzp[Pts];
 #pragma unroll
           for (int m = 0; m < Pts; m++) {
-            const TC bx = bcast_t(wxc[m], pnt), by = bcast_t(wyc[m], pnt);
+            const double bx = (double)bcast_t(wxc[m], pnt), by = bcast_d(wyc[m], pnt);
             wxa = (m == la) ? bx : wxa;
             wyb = (m == lb) ? by : wyb;
-            wzp[m] = bcast_t(wzc[m], pnt);
+            wzp[m] = bcast_d(wzc[m], pnt);
           }
           const PatchDev &D = P[dd];
           const TB *T = stage_buf<TB>(D, sv, stage);
@@ -1465,15 +1502,15 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
           const int dn0 = D.n[0], dn1 = D.n[1], dn2 = D.n[2];
           const bool per0 = D.periodic[0] != 0, per1 = D.periodic[1] != 0, per2 = D.periodic[2] != 0;
 #pragma unroll
-          for (int f = 0; f < 5; f++) out[f] = (TC)0;
+          for (int f = 0; f < 5; f++) out[f] = 0.0;
           if (tap_lane) {
-            const TC wab = wxa * wyb;
+            const double wab = wxa * wyb;
             int ii = s0 + la, jj = s1 + lb;
             if (per0) ii = ((ii % dn0) + dn0) % dn0;
             if (per1) jj = ((jj % dn1) + dn1) % dn1;
             const uint32_t xy = (uint32_t)(ii + PW_OX) + (uint32_t)(jj + PW_NG) * dsy;
             uint32_t xs[Pts];
-            TC wvv[Pts];
+            double wvv[Pts];
 #pragma unroll
             for (int cc = 0; cc < Pts; cc++) {
               int kk = s2 + cc;
@@ -1484,19 +1521,19 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
             for (int cc = 0; cc < Pts; cc++)
 #pragma unroll
-              for (int f = 0; f < 5; f++) out[f] += wvv[cc] * (TC)gld(T, f * fs + xs[cc]);
+              for (int f = 0; f < 5; f++) out[f] += wvv[cc] * (double)gld(T, f * fs + xs[cc]);
           }
         };
         for (;;) {
           const int p0 = next_point();
           if (p0 < 0) break;
           const int p1 = next_point();
-          TC a0[5], a1[5];
+          double a0[5], a1[5];
           taps(p0, a0);
           if (p1 >= 0) taps(p1, a1);
           else {
 #pragma unroll
-            for (int f = 0; f < 5; f++) a1[f] = (TC)0;
+            for (int f = 0; f < 5; f++) a1[f] = 0.0;
           }
 #pragma unroll
           for (int off = 32; off >= 1; off >>= 1)
@@ -1517,7 +1554,9 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
       }
       o0 = o1;
     }
-    // partial sums of waves 1.. meet those of wave 0 in LDS
+    // partial sums of waves 1.. meet those of wave 0 in LDS (the box's, once
+    // every wave is done with it)
+    __syncthreads();
     if (wv > 0) {
 #pragma unroll
       for (int f = 0; f < 5; f++) red[wv - 1][f][lane] = acc[f];
