@@ -339,7 +339,7 @@ def main():
                 "lds_read_TBps": round(pts * 5 * P ** 3 * tc_bytes / (g_ms * 1e-3) / 1e12, 2)}
 
     def l2g_roof():
-        name = "k_l2g_box<%s, %s, %d>" % (tb, "double" if args.precision == "fp64" else "float", P)
+        name = "k_l2g_bucket<%s, %s, %d>" % (tb, "double" if args.precision == "fp64" else "float", P)
         f, _ = ctx.flags()
         pts = int((f == 1).sum())
         g_ms = kt["l2g"][0] / kt["l2g"][1]

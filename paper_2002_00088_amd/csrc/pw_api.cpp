@@ -86,6 +86,8 @@ struct pw_context {
   int *effcount = nullptr;
   int nBuckets = 0;
   int *bkCnt = nullptr, *bkOff = nullptr, *bkRank = nullptr, *eBkt = nullptr, *eRank = nullptr;
+  int2 *l2gItems = nullptr;  // local -> global work items (bucket runs), rebuilt with the flags
+  int *l2gNItems = nullptr;
   FallbackRec *fbList[2] = {nullptr, nullptr};  // skipped points of the local / global part
   int *fbCount[2] = {nullptr, nullptr};
   long long fbCap = 0;
@@ -369,9 +371,16 @@ pw_status upload_layout(pw_context *c) {
   c->bkOff = (int *)dalloc(c, sizeof(int) * std::max(1, c->nBuckets));
   c->bkRank = (int *)dalloc(c, sizeof(int) * std::max(1, c->nBuckets));
   if (!c->bkCnt || !c->bkOff || !c->bkRank) return fail(c, PW_ENOMEM, "device allocation failed");
+  dfree(c, c->l2gItems);
+  dfree(c, c->l2gNItems);
+  // at most one partial item per bucket plus one per L2G_ITEM effective ghosts
+  c->l2gItems = (int2 *)dalloc(c, sizeof(int2) * ((size_t)std::max(1, c->nBuckets) + (size_t)(c->gcells / L2G_ITEM) + 1));
+  c->l2gNItems = (int *)dalloc(c, sizeof(int));
+  if (!c->l2gItems || !c->l2gNItems) return fail(c, PW_ENOMEM, "device allocation failed");
+  launch_fill_i32(c->stream, c->l2gNItems, 1, 0);
   {
-    // bucket ids of each local patch follow a Morton curve through its 8^3-cell
-    // buckets, so that consecutive buckets are spatial neighbours
+    // bucket ids of each local patch follow a Morton curve through its
+    // 8 x 8 x 4-cell buckets, so that consecutive buckets are spatial neighbours
     std::vector<int> rank(std::max(1, c->nBuckets), 0);
     for (int pid = 1; pid < np; pid++) {
       const PatchDev &p = c->hp[pid];
@@ -580,6 +589,8 @@ void enqueue_post_flags(pw_context *c, const PoseDev *pose_slot, hipStream_t st)
   o.erank = c->eRank;
   o.sorted = c->effsorted;
   o.out = c->efflist;  // the unordered list is not needed once scattered
+  o.items = c->l2gItems;
+  o.nitems = c->l2gNItems;
   launch_l2g_order(st, o);
 }
 
@@ -641,6 +652,8 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.dvalid = c->dvalid[c->cfg.interp_points[sv] - 2];
     a.efflist = c->efflist;
     a.effcount = c->effcount;
+    a.l2g_items = c->l2gItems;
+    a.l2g_nitems = c->l2gNItems;
     a.cover = c->cover_cur;
     a.has_locals = has_locals(c);
     for (int d = 0; d < 3; d++) a.gn[d] = c->hp[0].n[d];
@@ -1140,7 +1153,7 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
   euler_zyz(d->euler_zyz, p.R);
   p.sv_mask = d->sv_mask;
   p.bkt_base = 0;
-  for (int a = 0; a < 3; a++) p.bkt_n[a] = first ? 0 : (p.n[a] + 7) / 8;
+  for (int a = 0; a < 3; a++) p.bkt_n[a] = first ? 0 : (a == 2 ? (p.n[a] + 3) / 4 : (p.n[a] + 7) / 8);
   if (!first) {
     const PatchDev &last = c->hp.back();
     p.bkt_base = last.bkt_base + last.bkt_n[0] * last.bkt_n[1] * last.bkt_n[2];

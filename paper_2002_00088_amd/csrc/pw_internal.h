@@ -33,7 +33,7 @@ struct PatchDev {
   double R[9];          // row-major rotation, X = c + R y
   double c0[3], vel[3], radius, omega, phase;
   unsigned sv_mask;
-  int bkt_base, bkt_n[3];  // donor buckets of 8^3 cells (local patches): first id, counts per axis
+  int bkt_base, bkt_n[3];  // donor buckets of 8 x 8 x 4 cells (local patches): first id, counts per axis
   double *u[PW_MAXSV];
   double *acc[PW_MAXSV];
   void *va[PW_MAXSV];

@@ -33,13 +33,12 @@ struct StageTile {
 #define BRICK_LDS_BYTES 30720
 #endif
 #ifndef L2G_BLOCKS
-#define L2G_BLOCKS 2048  // a multiple of 8
+#define L2G_BLOCKS 4096  // workgroups of the local -> global kernel (a multiple of 8)
 #endif
-#ifndef L2G_WAVES
-#define L2G_WAVES 3
-#endif
+#define L2G_THREADS 192  // threads of a local -> global workgroup
+#define L2G_ITEM 64      // entries of a local -> global work item (at most one donor bucket)
 #ifndef L2G_LDS_BYTES
-#define L2G_LDS_BYTES 36864
+#define L2G_LDS_BYTES 39424  // donor box: 1971 cells of five FP32 values (a 14 x 14 x 10 box fits)
 #endif
 #define BUCKET_SORT_LDS 4096
 
@@ -106,6 +105,8 @@ struct L2GOrderArgs {
   const int *rank;  // position of each bucket along its patch's Morton curve
   int32_t *sorted;  // entries grouped by bucket (scratch)
   int32_t *out;     // the same, ascending cell index within each bucket (may alias list)
+  int2 *items;      // work items of the local -> global kernel: runs of <= L2G_ITEM entries of one bucket
+  int *nitems;
 };
 
 struct FlagsArgs {
@@ -178,6 +179,8 @@ struct GhostArgs {
   const uint8_t *dvalid;
   const int32_t *efflist;  // effective ghosts grouped by donor bucket
   const int *effcount;
+  const int2 *l2g_items;  // work items of the local -> global kernel (first entry, count)
+  const int *l2g_nitems;
   const int32_t *cover;
   int has_locals;
   int gn[3];

@@ -731,8 +731,9 @@ __global__ __launch_bounds__(256) void k_efflist(const uint8_t *flag, int n0, in
 }
 
 // Ordering of the effective ghosts by donor position: a counting sort by
-// (covering local patch, 8^3-cell bucket of that patch holding the point), so
-// that the points a wavefront gathers share donor rows in the caches.
+// (covering local patch, 8 x 8 x 4-cell bucket of that patch holding the
+// point), so that the points of a local -> global work item share one donor
+// box.
 __global__ void k_bucket_count(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list, const int *count,
                                const int32_t *cover, const int *rank, int *cnt, int *ebkt, int *erank) {
   const PatchDev &G0 = P[0];
@@ -762,7 +763,7 @@ __global__ void k_bucket_count(const PatchDev *__restrict__ P, const PoseDev *__
           int ii = (qq > -1.0e6 && qq < 1.0e6) ? (int)floor(qq) : 0;
           if (D.periodic[a]) ii = ((ii % D.n[a]) + D.n[a]) % D.n[a];
           ii = ii < 0 ? 0 : (ii >= D.n[a] ? D.n[a] - 1 : ii);
-          bi[a] = ii >> 3;
+          bi[a] = ii >> (a == 2 ? 2 : 3);
         }
         b = D.bkt_base + rank[D.bkt_base + (bi[2] * D.bkt_n[1] + bi[1]) * D.bkt_n[0] + bi[0]];
       }
@@ -1210,85 +1211,135 @@ __global__ __launch_bounds__(BRICK_THREADS) __attribute__((amdgpu_waves_per_eu(4
 }
 
 // ---------------------------------------------------------------------------
-// Local -> global (Sec. 2.4.2).  The effective ghost cells are ordered by the
-// 8^3-cell bucket of the covering local patch that holds their donor point
-// (buckets in Morton order), so consecutive entries have nearby donor stencils.
-// A workgroup of L2G_WAVES wavefronts takes 64 entries; every wave locates the
-// 64 points in the donor patch and forms their Lagrange weights (FP64, one point
-// per lane).  The group is cut into runs of 8-point octets, as long as the union
-// of a run's donor stencils (its donor box) lies in one donor patch and fits the
-// LDS tile; the box is staged in LDS (as many fields per pass as fit) and wave w
-// sums z-layers w, w + L2G_WAVES, ... of every stencil of the run.  An octet
-// whose box does not fit alone is summed cooperatively from global memory: one
-// point at a time per wave, the point's stencil start and weights broadcast with
-// readlane, lane (a, b) reading x-row element a of row b of every z-layer, and
-// the partial sums reduced with xor shuffles.  The per-wave partial sums meet in
-// LDS; wave 0 carries each point to the global frame and stores it.
+// Local -> global (Sec. 2.4.2).  The effective ghost cells are sorted by the
+// donor bucket (8 x 8 x 4 cells of the covering local patch) that holds their
+// donor point, and each bucket is cut into work items of at most L2G_ITEM
+// consecutive entries (k_l2g_items).  The donor stencils of an item's points
+// start within its bucket, so their union (the donor box) spans at most
+// 14 x 14 x 10 cells (P = 6) and is staged in LDS once, all five fields per
+// cell.  Each point is summed by K threads (K = 3, or 6 for items of at most
+// 32 points), thread g of a point taking its z-layers g, g + K, ...; the layer
+// sums l_c meet as (l_0 + l_3) + (l_1 + l_4) + (l_2 + l_5) whatever K is, so a
+// point's value does not depend on how the list was cut.  The x-row sums run
+// in the compute type with the x weights rounded to it, the y and z sums in
+// FP64 with FP64 weights (explicit FMAs and roundings, so the staged and the
+// direct path below agree bitwise).  Points whose box does not fit the LDS
+// tile gather their stencil from global memory with the same arithmetic.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int bcast_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
-__device__ __forceinline__ double bcast_d(double v, int lane) {
-  long long b = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-  int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+template <typename TC, int Pts>
+__device__ __forceinline__ void l2g_rows_lds(const unsigned char *lds, int capc, int o, int e0, const TC *wxc,
+                                             const double *wy, double ly[5]) {
+#pragma unroll
+  for (int b = 0; b < Pts; b++) {
+    TC p5[5] = {0, 0, 0, 0, 0};
+    if constexpr (sizeof(TC) == 4) {
+      const float4 *r4 = (const float4 *)lds + o + b * e0;
+      const float *r1 = (const float *)(lds + 16 * capc) + o + b * e0;
+      float4 w4[Pts];
+      float w1[Pts];
+#pragma unroll
+      for (int a = 0; a < Pts; a++) {
+        w4[a] = r4[a];
+        w1[a] = r1[a];
+      }
+#pragma unroll
+      for (int a = 0; a < Pts; a++) {
+        p5[0] = fmaf(wxc[a], w4[a].x, p5[0]);
+        p5[1] = fmaf(wxc[a], w4[a].y, p5[1]);
+        p5[2] = fmaf(wxc[a], w4[a].z, p5[2]);
+        p5[3] = fmaf(wxc[a], w4[a].w, p5[3]);
+        p5[4] = fmaf(wxc[a], w1[a], p5[4]);
+      }
+    } else {
+      const double2 *ra = (const double2 *)lds + o + b * e0;
+      const double2 *rb = (const double2 *)(lds + 16 * capc) + o + b * e0;
+      const double *rc = (const double *)(lds + 32 * capc) + o + b * e0;
+#pragma unroll
+      for (int a = 0; a < Pts; a++) {
+        const double2 x01 = ra[a], x23 = rb[a];
+        p5[0] = fma(wxc[a], x01.x, p5[0]);
+        p5[1] = fma(wxc[a], x01.y, p5[1]);
+        p5[2] = fma(wxc[a], x23.x, p5[2]);
+        p5[3] = fma(wxc[a], x23.y, p5[3]);
+        p5[4] = fma(wxc[a], rc[a], p5[4]);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 5; f++) ly[f] = fma(wy[b], (double)p5[f], ly[f]);
+  }
 }
-__device__ __forceinline__ double bcast_t(double v, int lane) { return bcast_d(v, lane); }
-__device__ __forceinline__ float bcast_t(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+
+// One z-layer of a stencil straight from global memory (rare: a donor box that
+// does not fit the LDS tile): the same arithmetic as l2g_rows_lds, in loops
+// that are not unrolled (the weights picked by selects).
+template <typename TB, typename TC, int Pts>
+__device__ __noinline__ void l2g_rows_global(const PatchDev &D, const TB *T, int s0, int s1, int kk,
+                                             const TC *wxc, const double *wy, double ly[5]) {
+  const uint32_t fs = (uint32_t)D.fstride;
+  for (int b = 0; b < Pts; b++) {
+    int jj = s1 + b;
+    if (D.periodic[1]) jj = ((jj % D.n[1]) + D.n[1]) % D.n[1];
+    TC p5[5] = {0, 0, 0, 0, 0};
+    for (int a = 0; a < Pts; a++) {
+      int ii = s0 + a;
+      if (D.periodic[0]) ii = ((ii % D.n[0]) + D.n[0]) % D.n[0];
+      const uint32_t x = (uint32_t)cell_index(D, ii, jj, kk);
+      TC w = (TC)0;
+#pragma unroll
+      for (int m = 0; m < Pts; m++) w = (m == a) ? wxc[m] : w;
+#pragma unroll
+      for (int f = 0; f < 5; f++) {
+        const TC u = (TC)gld(T, f * fs + x);
+        if constexpr (sizeof(TC) == 4) p5[f] = fmaf(w, u, p5[f]);
+        else p5[f] = fma(w, u, p5[f]);
+      }
+    }
+    double wb = 0.0;
+#pragma unroll
+    for (int m = 0; m < Pts; m++) wb = (m == b) ? wy[m] : wb;
+#pragma unroll
+    for (int f = 0; f < 5; f++) ly[f] = fma(wb, (double)p5[f], ly[f]);
+  }
 }
 
 template <typename TB, typename TC, int Pts>
-__global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_l2g_box(
-    const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list, const int *count,
-    int run, const int32_t *cover, int sv, int stage, unsigned long long *skips, FallbackRec *fb, int *fb_count) {
-  // the donor box: five fields per cell, 20 (FP32) or 40 (FP64) bytes a cell
-  constexpr int CAPC = L2G_LDS_BYTES / (5 * sizeof(TC));
-  constexpr int CAP = CAPC;
+__global__ __launch_bounds__(L2G_THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_l2g_bucket(
+    const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list, const int2 *items,
+    const int *nitems, int run, const int32_t *cover, int sv, int stage, unsigned long long *skips, FallbackRec *fb,
+    int *fb_count) {
+  constexpr int NW = L2G_THREADS / 64;
+  constexpr int CAPC = L2G_LDS_BYTES / (5 * sizeof(TC));  // box cells: five fields a cell
+  static_assert(L2G_ITEM * 3 <= L2G_THREADS && L2G_ITEM <= 64, "three threads per point of an item");
+  static_assert(5 * L2G_THREADS * sizeof(double) <= L2G_LDS_BYTES, "partial sums fit the box LDS");
   __shared__ __align__(16) unsigned char lds_box[L2G_LDS_BYTES];
-  float4 *b4f = (float4 *)lds_box;
-  float *b1f = (float *)(lds_box + 16 * CAPC);
-  double2 *b01d = (double2 *)lds_box;
-  double2 *b23d = (double2 *)(lds_box + 16 * CAPC);
-  double *b4d = (double *)(lds_box + 32 * CAPC);
-  // partial sums of waves 1.. for wave 0, in the box's LDS once the sums are done
-  static_assert((L2G_WAVES - 1) * 5 * 64 * sizeof(double) <= L2G_LDS_BYTES, "reduction fits the box LDS");
-  double(*red)[5][64] = (double(*)[5][64])lds_box;
-  __shared__ int obox[8][8];  // per octet: lo[3], hi[3], lowest and highest donor id
+  __shared__ int wbox[NW][8];  // per wavefront: lowest / highest donor index per axis, donor patch range
+  double(*red)[L2G_THREADS] = (double(*)[L2G_THREADS])lds_box;  // partial sums, once the box is done
   const PatchDev &G0 = P[0];
   if (!(G0.sv_mask & (1u << sv))) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int n = count[0];
-  const int la = lane % Pts, lb = lane / Pts;
-  const bool tap_lane = lane < Pts * Pts;
   TB *TG = stage_buf<TB>(G0, sv, stage);
-  // runs of `run` consecutive groups (neighbouring donor boxes) on one XCD
-  const int ngroups = (n + 63) / 64;
-  const int nv = (ngroups + 8 * run - 1) / (8 * run) * (8 * run);
+  const int tid = threadIdx.x;
+  const int ni = nitems[0];
+  const int nv = (ni + 8 * run - 1) / (8 * run) * (8 * run);
   for (int vb = blockIdx.x; vb < nv; vb += gridDim.x) {
-    const int grp = xcd_spread(vb, run);
-    if (grp >= ngroups) continue;
-    const int g0 = grp * 64;
-    if (tid < 64) {
-      const int e = tid & 7;
-      obox[tid >> 3][e] = e < 3 ? (1 << 30) : (e < 6 ? -(1 << 30) : (e == 6 ? (1 << 30) : -1));
-    }
-    __syncthreads();
-    const int qi = g0 + lane;
-    const bool have = qi < n;
-    const long long c = have ? list[qi] : 0;
+    // runs of `run` consecutive items (neighbouring donor buckets) on one XCD
+    const int item = xcd_spread(vb, run);
+    if (item >= ni) continue;
+    const int2 it = items[item];
+    const int npts = it.y;
+    const int K = npts <= L2G_THREADS / 6 ? 6 : 3;
+    const bool act = tid < K * npts;
+    const int pi = act ? tid % npts : 0, g = act ? tid / npts : 0;
+    const long long c = act ? list[it.x + pi] : 0;
     const int i = (int)(c % G0.n[0]), j = (int)((c / G0.n[0]) % G0.n[1]),
               k = (int)(c / ((long long)G0.n[0] * G0.n[1]));
-    const int d = have ? cover[c] : 0;
-    double xd[3] = {0, 0, 0};
-    bool valid = have && d >= 1 && (P[d].sv_mask & (1u << sv));
+    const int d = act ? cover[c] : 0;
+    bool valid = act && d >= 1 && (P[d].sv_mask & (1u << sv));
     int s[3] = {0, 0, 0};
-    // Lagrange weights are formed in FP64; the x weights are rounded to the
-    // compute type for the x-row sums, the y and z weights stay FP64 for the
-    // outer sums, which accumulate in FP64
+    double xd[3] = {0, 0, 0};
     TC wxc[Pts];
-    double wyc[Pts], wzc[Pts];
+    double wy[Pts], wz[Pts];
 #pragma unroll
-    for (int m = 0; m < Pts; m++) { wxc[m] = (TC)0; wyc[m] = 0.0; wzc[m] = 0.0; }
+    for (int m = 0; m < Pts; m++) { wxc[m] = (TC)0; wy[m] = 0.0; wz[m] = 0.0; }
     if (valid) {
       const PatchDev &D = P[d];
       const double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
@@ -1299,280 +1350,182 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
         valid = valid && (q[a] > -1.0e6 && q[a] < 1.0e6);
       }
       if (valid) {
-        double wx[Pts], wy[Pts], wz[Pts];
+        double wx[Pts];
         s[0] = lagrange_wt<Pts>(q[0], wx);
         s[1] = lagrange_wt<Pts>(q[1], wy);
         s[2] = lagrange_wt<Pts>(q[2], wz);
 #pragma unroll
-        for (int m = 0; m < Pts; m++) { wxc[m] = (TC)wx[m]; wyc[m] = wy[m]; wzc[m] = wz[m]; }
+        for (int m = 0; m < Pts; m++) wxc[m] = (TC)wx[m];
         for (int a = 0; a < 3; a++)
           if (!D.periodic[a] && (s[a] < 0 || s[a] + Pts - 1 > D.n[a] - 1)) valid = false;
       }
     }
-    if (valid && wv == 0) {
-      int *ob = obox[lane >> 3];
+    // the item's donor box and donor patch: reduced within each wavefront by
+    // xor shuffles, the wavefronts' results combined through LDS
+    {
+      int v8[8];
+#pragma unroll
       for (int a = 0; a < 3; a++) {
-        atomicMin(&ob[a], s[a]);
-        atomicMax(&ob[3 + a], s[a] + Pts - 1);
+        v8[a] = valid ? s[a] : (1 << 30);
+        v8[3 + a] = valid ? s[a] + Pts - 1 : -(1 << 30);
       }
-      atomicMin(&ob[6], d);
-      atomicMax(&ob[7], d);
+      v8[6] = valid ? d : (1 << 30);
+      v8[7] = valid ? d : -1;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) v8[a] = min(v8[a], __shfl_xor(v8[a], off));
+#pragma unroll
+        for (int a = 3; a < 6; a++) v8[a] = max(v8[a], __shfl_xor(v8[a], off));
+        v8[6] = min(v8[6], __shfl_xor(v8[6], off));
+        v8[7] = max(v8[7], __shfl_xor(v8[7], off));
+      }
+      if ((tid & 63) == 0)
+#pragma unroll
+        for (int a = 0; a < 8; a++) wbox[tid >> 6][a] = v8[a];
     }
     __syncthreads();
-    double acc[5] = {0, 0, 0, 0, 0};
-    // runs of octets (the same on every thread: read from LDS)
-    for (int o0 = 0; o0 < 8;) {
-      int lo[3], hi[3], dmin, dmax;
+    int lo[3], hi[3], dmin, dmax;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      lo[a] = wbox[0][a];
+      hi[a] = wbox[0][3 + a];
+    }
+    dmin = wbox[0][6];
+    dmax = wbox[0][7];
+#pragma unroll
+    for (int w = 1; w < NW; w++) {
+#pragma unroll
       for (int a = 0; a < 3; a++) {
-        lo[a] = obox[o0][a];
-        hi[a] = obox[o0][3 + a];
+        lo[a] = min(lo[a], wbox[w][a]);
+        hi[a] = max(hi[a], wbox[w][3 + a]);
       }
-      dmin = obox[o0][6];
-      dmax = obox[o0][7];
-      auto volume = [&](const int *l, const int *h) -> long long {
-        return (h[0] >= l[0] && h[1] >= l[1] && h[2] >= l[2])
-                   ? (long long)(h[0] - l[0] + 1) * (h[1] - l[1] + 1) * (h[2] - l[2] + 1)
-                   : 0;
-      };
-      auto fits = [&](const int *l, const int *h, int dl, int dh) {
-        return dh < 0 || (dl == dh && volume(l, h) <= CAP);
-      };
-      int o1 = o0 + 1;
-      if (fits(lo, hi, dmin, dmax)) {
-        while (o1 < 8) {
-          int l2[3], h2[3];
-          for (int a = 0; a < 3; a++) {
-            l2[a] = min(lo[a], obox[o1][a]);
-            h2[a] = max(hi[a], obox[o1][3 + a]);
-          }
-          const int dl = min(dmin, obox[o1][6]), dh = max(dmax, obox[o1][7]);
-          if (!fits(l2, h2, dl, dh)) break;
-          for (int a = 0; a < 3; a++) {
-            lo[a] = l2[a];
-            hi[a] = h2[a];
-          }
-          dmin = dl;
-          dmax = dh;
-          o1++;
-        }
-      }
-      const bool mine = valid && (lane >> 3) >= o0 && (lane >> 3) < o1;
-      const long long vol = volume(lo, hi);
-      if (dmax < 0) {
-        // no valid point in the run
-      } else if (dmin == dmax && (vol <= CAPC || o1 == o0 + 1) &&
-                 (long long)(hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) <= CAPC) {
-        // the run's donor box in LDS, whole z-layers at a time, all five fields
-        // per cell (a run of several octets fits at once; a lone octet may take
-        // several chunks)
-        const PatchDev &D = P[dmin];  // uniform: scalar loads
-        const TB *T = stage_buf<TB>(D, sv, stage);
-        const uint32_t fs = (uint32_t)D.fstride, dsy = (uint32_t)D.pitch, dsz = (uint32_t)D.slab;
-        const int dn0 = D.n[0], dn1 = D.n[1], dn2 = D.n[2];
-        const bool per0 = D.periodic[0] != 0, per1 = D.periodic[1] != 0, per2 = D.periodic[2] != 0;
-        const int e0 = hi[0] - lo[0] + 1, e1 = hi[1] - lo[1] + 1, e2 = hi[2] - lo[2] + 1;
-        const int e01 = e0 * e1;
-        const int nzc = CAPC / e01;
-        // flat box index q -> (x, row), row -> (b, layer) with float reciprocals:
-        // exact, since (q + 0.5) / e lies at least 1/(2e) from an integer and q < 2^14
-        const float ie0 = 1.0f / (float)e0, ie1 = 1.0f / (float)e1;
-        for (int z0 = 0; z0 < e2; z0 += nzc) {
-          const int nz = e2 - z0 < nzc ? e2 - z0 : nzc;
-          const int v = e01 * nz;
-          for (int q0 = tid; q0 < v; q0 += 4 * 64 * L2G_WAVES) {
-            TC tmp[4][5];
+      dmin = min(dmin, wbox[w][6]);
+      dmax = max(dmax, wbox[w][7]);
+    }
+    const int e0 = hi[0] - lo[0] + 1, e1 = hi[1] - lo[1] + 1, e2 = hi[2] - lo[2] + 1;
+    const int e01 = e0 * e1;
+    const bool boxed = dmax >= 1 && dmin == dmax && e01 <= CAPC;
+    // this thread's layers g, g + K of its point, summed into part in the
+    // fixed grouping (each layer sum rounded on its own before the add)
+    double part[5] = {0, 0, 0, 0, 0};
+    double wzl[2] = {0.0, 0.0};  // z weights of the thread's two layers
 #pragma unroll
-            for (int m = 0; m < 4; m++) {
-              const int q = q0 + m * 64 * L2G_WAVES;
-              if (q < v) {
-                const int row = (int)(((float)q + 0.5f) * ie0);
-                const int x = q - row * e0;
-                const int cc = (int)(((float)row + 0.5f) * ie1);
-                const int b = row - cc * e1;
-                // box cells lie inside [0, n) on every axis once periodic axes wrap
-                int ii = lo[0] + x, jj = lo[1] + b, kk = lo[2] + z0 + cc;
-                if (per0) ii = ((ii % dn0) + dn0) % dn0;
-                if (per1) jj = ((jj % dn1) + dn1) % dn1;
-                if (per2) kk = ((kk % dn2) + dn2) % dn2;
-                const uint32_t g =
-                    (uint32_t)(ii + PW_OX) + (uint32_t)(jj + PW_NG) * dsy + (uint32_t)(kk + PW_NG) * dsz;
+    for (int m = 0; m < Pts; m++) {
+      wzl[0] = (m == g) ? wz[m] : wzl[0];
+      wzl[1] = (m == g + 3) ? wz[m] : wzl[1];
+    }
+    if (boxed) {
+      const PatchDev &D = P[dmin];  // uniform: scalar loads
+      const TB *T = stage_buf<TB>(D, sv, stage);
+      const uint32_t fs = (uint32_t)D.fstride, dsy = (uint32_t)D.pitch, dsz = (uint32_t)D.slab;
+      const int dn0 = D.n[0], dn1 = D.n[1], dn2 = D.n[2];
+      const bool per0 = D.periodic[0] != 0, per1 = D.periodic[1] != 0, per2 = D.periodic[2] != 0;
+      const int nzc = CAPC / e01;
+      // flat box index q -> (x, row), row -> (b, layer) with float reciprocals:
+      // exact, since (q + 0.5) / e lies at least 1/(2e) from an integer and q < 2^14
+      const float ie0 = 1.0f / (float)e0, ie1 = 1.0f / (float)e1;
+      for (int z0 = 0; z0 < e2; z0 += nzc) {
+        const int nz = e2 - z0 < nzc ? e2 - z0 : nzc;
+        const int v = e01 * nz;
+        for (int q0 = tid; q0 < v; q0 += 4 * L2G_THREADS) {
+          TC tmp[4][5];
 #pragma unroll
-                for (int f = 0; f < 5; f++) tmp[m][f] = (TC)gld(T, (uint32_t)f * fs + g);
-              }
-            }
-#pragma unroll
-            for (int m = 0; m < 4; m++) {
-              const int q = q0 + m * 64 * L2G_WAVES;
-              if (q < v) {
-                if constexpr (sizeof(TC) == 4) {
-                  b4f[q] = make_float4(tmp[m][0], tmp[m][1], tmp[m][2], tmp[m][3]);
-                  b1f[q] = tmp[m][4];
-                } else {
-                  b01d[q] = make_double2(tmp[m][0], tmp[m][1]);
-                  b23d[q] = make_double2(tmp[m][2], tmp[m][3]);
-                  b4d[q] = tmp[m][4];
-                }
-              }
-            }
-          }
-          __syncthreads();
-          if (mine) {
-            // wave wv sums the layers wv, wv + L2G_WAVES, ... of each stencil
-            // that lie in this chunk; the taps of a row are immediate offsets
-            // from one row address
-            const int first = (s[1] - lo[1]) * e0 + (s[0] - lo[0]);
-#pragma unroll
-            for (int cc = 0; cc < Pts; cc++) {
-              if (cc % L2G_WAVES != wv) continue;
-              const int lz = s[2] - lo[2] + cc - z0;
-              if (lz < 0 || lz >= nz) continue;
-              const int o = lz * e01 + first;
-              double layer[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-              for (int b = 0; b < Pts; b++) {
-                TC p5[5] = {0, 0, 0, 0, 0};
-                if constexpr (sizeof(TC) == 4) {
-                  const float4 *r4 = b4f + o + b * e0;
-                  const float *r1 = b1f + o + b * e0;
-                  float4 w4[Pts];
-                  float w1[Pts];
-#pragma unroll
-                  for (int a = 0; a < Pts; a++) {
-                    w4[a] = r4[a];
-                    w1[a] = r1[a];
-                  }
-#pragma unroll
-                  for (int a = 0; a < Pts; a++) {
-                    p5[0] += wxc[a] * w4[a].x;
-                    p5[1] += wxc[a] * w4[a].y;
-                    p5[2] += wxc[a] * w4[a].z;
-                    p5[3] += wxc[a] * w4[a].w;
-                    p5[4] += wxc[a] * w1[a];
-                  }
-                } else {
-                  const double2 *ra = b01d + o + b * e0;
-                  const double2 *rb = b23d + o + b * e0;
-                  const double *rc = b4d + o + b * e0;
-#pragma unroll
-                  for (int a = 0; a < Pts; a++) {
-                    const double2 x01 = ra[a], x23 = rb[a];
-                    p5[0] += wxc[a] * x01.x;
-                    p5[1] += wxc[a] * x01.y;
-                    p5[2] += wxc[a] * x23.x;
-                    p5[3] += wxc[a] * x23.y;
-                    p5[4] += wxc[a] * rc[a];
-                  }
-                }
-#pragma unroll
-                for (int f = 0; f < 5; f++) layer[f] += wyc[b] * (double)p5[f];
-              }
-#pragma unroll
-              for (int f = 0; f < 5; f++) acc[f] += wzc[cc] * layer[f];
-            }
-          }
-          __syncthreads();
-        }
-      } else {
-        // cooperative gather from global memory; wave wv takes every L2G_WAVES-th point
-        unsigned long long todo = __ballot(mine);
-        int rank = 0;
-        auto next_point = [&]() -> int {
-          while (todo) {
-            const int p = __ffsll((long long)todo) - 1;
-            todo &= todo - 1ull;
-            if (rank++ % L2G_WAVES == wv) return p;
-          }
-          return -1;
-        };
-        // (rare) the tap weights w_x w_y w_z in FP64, the sums in FP64
-        auto taps = [&](int pnt, double out[5]) {
-          const int dd = bcast_i(d, pnt);
-          const int s0 = bcast_i(s[0], pnt), s1 = bcast_i(s[1], pnt), s2 = bcast_i(s[2], pnt);
-          double wxa = 0.0, wyb = 0.0, wzp[Pts];
-#pragma unroll
-          for (int m = 0; m < Pts; m++) {
-            const double bx = (double)bcast_t(wxc[m], pnt), by = bcast_d(wyc[m], pnt);
-            wxa = (m == la) ? bx : wxa;
-            wyb = (m == lb) ? by : wyb;
-            wzp[m] = bcast_d(wzc[m], pnt);
-          }
-          const PatchDev &D = P[dd];
-          const TB *T = stage_buf<TB>(D, sv, stage);
-          const uint32_t fs = (uint32_t)D.fstride, dsy = (uint32_t)D.pitch, dsz = (uint32_t)D.slab;
-          const int dn0 = D.n[0], dn1 = D.n[1], dn2 = D.n[2];
-          const bool per0 = D.periodic[0] != 0, per1 = D.periodic[1] != 0, per2 = D.periodic[2] != 0;
-#pragma unroll
-          for (int f = 0; f < 5; f++) out[f] = 0.0;
-          if (tap_lane) {
-            const double wab = wxa * wyb;
-            int ii = s0 + la, jj = s1 + lb;
-            if (per0) ii = ((ii % dn0) + dn0) % dn0;
-            if (per1) jj = ((jj % dn1) + dn1) % dn1;
-            const uint32_t xy = (uint32_t)(ii + PW_OX) + (uint32_t)(jj + PW_NG) * dsy;
-            uint32_t xs[Pts];
-            double wvv[Pts];
-#pragma unroll
-            for (int cc = 0; cc < Pts; cc++) {
-              int kk = s2 + cc;
+          for (int m = 0; m < 4; m++) {
+            const int q = q0 + m * L2G_THREADS;
+            if (q < v) {
+              const int row = (int)(((float)q + 0.5f) * ie0);
+              const int x = q - row * e0;
+              const int cc = (int)(((float)row + 0.5f) * ie1);
+              const int b = row - cc * e1;
+              // box cells lie inside [0, n) on every axis once periodic axes wrap
+              int ii = lo[0] + x, jj = lo[1] + b, kk = lo[2] + z0 + cc;
+              if (per0) ii = ((ii % dn0) + dn0) % dn0;
+              if (per1) jj = ((jj % dn1) + dn1) % dn1;
               if (per2) kk = ((kk % dn2) + dn2) % dn2;
-              xs[cc] = xy + (uint32_t)(kk + PW_NG) * dsz;
-              wvv[cc] = wab * wzp[cc];
+              const uint32_t gi = (uint32_t)(ii + PW_OX) + (uint32_t)(jj + PW_NG) * dsy + (uint32_t)(kk + PW_NG) * dsz;
+#pragma unroll
+              for (int f = 0; f < 5; f++) tmp[m][f] = (TC)gld(T, (uint32_t)f * fs + gi);
             }
-#pragma unroll
-            for (int cc = 0; cc < Pts; cc++)
-#pragma unroll
-              for (int f = 0; f < 5; f++) out[f] += wvv[cc] * (double)gld(T, f * fs + xs[cc]);
-          }
-        };
-        for (;;) {
-          const int p0 = next_point();
-          if (p0 < 0) break;
-          const int p1 = next_point();
-          double a0[5], a1[5];
-          taps(p0, a0);
-          if (p1 >= 0) taps(p1, a1);
-          else {
-#pragma unroll
-            for (int f = 0; f < 5; f++) a1[f] = 0.0;
           }
 #pragma unroll
-          for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-            for (int f = 0; f < 5; f++) {
-              a0[f] += __shfl_xor(a0[f], off);
-              a1[f] += __shfl_xor(a1[f], off);
+          for (int m = 0; m < 4; m++) {
+            const int q = q0 + m * L2G_THREADS;
+            if (q < v) {
+              if constexpr (sizeof(TC) == 4) {
+                ((float4 *)lds_box)[q] = make_float4(tmp[m][0], tmp[m][1], tmp[m][2], tmp[m][3]);
+                ((float *)(lds_box + 16 * CAPC))[q] = tmp[m][4];
+              } else {
+                ((double2 *)lds_box)[q] = make_double2(tmp[m][0], tmp[m][1]);
+                ((double2 *)(lds_box + 16 * CAPC))[q] = make_double2(tmp[m][2], tmp[m][3]);
+                ((double *)(lds_box + 32 * CAPC))[q] = tmp[m][4];
+              }
             }
-          if (lane == p0) {
-#pragma unroll
-            for (int f = 0; f < 5; f++) acc[f] = a0[f];
-          }
-          if (lane == p1) {
-#pragma unroll
-            for (int f = 0; f < 5; f++) acc[f] = a1[f];
           }
         }
+        __syncthreads();
+        if (valid) {
+          const int first = (s[1] - lo[1]) * e0 + (s[0] - lo[0]);
+#pragma unroll
+          for (int m = 0; m < 2; m++) {
+            const int cc = g + 3 * m;
+            if (cc >= Pts || (K == 6 && m > 0)) break;
+            const int lz = s[2] - lo[2] + cc - z0;
+            if (lz < 0 || lz >= nz) continue;
+            double ly[5] = {0, 0, 0, 0, 0};
+            l2g_rows_lds<TC, Pts>(lds_box, CAPC, lz * e01 + first, e0, wxc, wy, ly);
+#pragma unroll
+            for (int f = 0; f < 5; f++) part[f] = __dadd_rn(part[f], __dmul_rn(wzl[m], ly[f]));
+          }
+        }
+        __syncthreads();
       }
-      o0 = o1;
-    }
-    // partial sums of waves 1.. meet those of wave 0 in LDS (the box's, once
-    // every wave is done with it)
-    __syncthreads();
-    if (wv > 0) {
+    } else if (valid) {
+      // (rare) the stencil straight from global memory, same arithmetic
+      const PatchDev &D = P[d];
+      const TB *T = stage_buf<TB>(D, sv, stage);
 #pragma unroll
-      for (int f = 0; f < 5; f++) red[wv - 1][f][lane] = acc[f];
+      for (int m = 0; m < 2; m++) {
+        const int cc = g + 3 * m;
+        if (cc >= Pts || (K == 6 && m > 0)) break;
+        int kk = s[2] + cc;
+        if (D.periodic[2]) kk = ((kk % D.n[2]) + D.n[2]) % D.n[2];
+        double ly[5] = {0, 0, 0, 0, 0};
+        l2g_rows_global<TB, TC, Pts>(D, T, s[0], s[1], kk, wxc, wy, ly);
+#pragma unroll
+        for (int f = 0; f < 5; f++) part[f] = __dadd_rn(part[f], __dmul_rn(wzl[m], ly[f]));
+      }
+    }
+    // the partial sums of a point's threads meet in its g = 0 thread (in the
+    // box's LDS, which every thread is done with)
+    __syncthreads();
+    if (act && g > 0) {
+#pragma unroll
+      for (int f = 0; f < 5; f++) red[f][tid] = part[f];
     }
     __syncthreads();
-    if (wv == 0 && have) {
-#pragma unroll
-      for (int f = 0; f < 5; f++)
-        for (int w2 = 0; w2 < L2G_WAVES - 1; w2++) acc[f] += red[w2][f][lane];
+    if (act && g == 0) {
       if (valid) {
+        double acc[5];
+        if (K == 3) {
+#pragma unroll
+          for (int f = 0; f < 5; f++)
+            acc[f] = __dadd_rn(__dadd_rn(part[f], red[f][tid + npts]), red[f][tid + 2 * npts]);
+        } else {
+#pragma unroll
+          for (int f = 0; f < 5; f++) {
+            const double p0 = __dadd_rn(part[f], red[f][tid + 3 * npts]);
+            const double p1 = __dadd_rn(red[f][tid + npts], red[f][tid + 4 * npts]);
+            const double p2 = __dadd_rn(red[f][tid + 2 * npts], red[f][tid + 5 * npts]);
+            acc[f] = __dadd_rn(__dadd_rn(p0, p1), p2);
+          }
+        }
         const PatchDev &D = P[d];
-        double in4[4] = {(double)acc[1], (double)acc[2], (double)acc[3], (double)acc[4]}, G[3], pit, out[5];
+        double in4[4] = {acc[1], acc[2], acc[3], acc[4]}, G[3], pit, out[5];
         const double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
         patch_to_bg_at(D, pose[d], X, xd, in4, pit, G);
         // the global patch's numerical frame is the background frame
-        out[0] = (double)acc[0];
+        out[0] = acc[0];
         out[1] = pit;
         for (int m = 0; m < 3; m++) out[2 + m] = G[m];
         const long long dst = cell_index(G0, i, j, k);
@@ -1585,6 +1538,29 @@ __global__ __launch_bounds__(64 * L2G_WAVES) __attribute__((amdgpu_waves_per_eu(
     }
     __syncthreads();
   }
+}
+
+// Work items of the local -> global kernel: every non-empty donor bucket cut
+// into runs of at most L2G_ITEM consecutive entries of the sorted list
+// (x: first entry, y: count).  The order of the items follows the atomics, the
+// values they give do not depend on it.
+__global__ void k_l2g_items(const int *cnt, const int *off, int nb, int2 *items, int *nitems) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int m = b < nb ? cnt[b] : 0;
+  const int nch = (m + L2G_ITEM - 1) / L2G_ITEM;
+  // the wavefront reserves its slots with one atomic (inclusive scan by shuffles)
+  int incl = nch;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  int base = 0;
+  if (lane == 63 && incl > 0) base = atomicAdd(nitems, incl);
+  base = __shfl(base, 63);
+  const int slot = base + incl - nch;
+  for (int q = 0; q < nch; q++) items[slot + q] = make_int2(off[b] + q * L2G_ITEM, min(L2G_ITEM, m - q * L2G_ITEM));
 }
 
 // Points that could not be interpolated keep their lower-priority value: a
@@ -2580,6 +2556,9 @@ void launch_l2g_order(hipStream_t s, const L2GOrderArgs &a) {
                      (const int *)a.ebkt, (const int *)a.erank, (const int *)a.off, a.sorted);
   hipLaunchKernelGGL(k_bucket_sort, dim3(a.nbuckets), dim3(256), 0, s, (const int32_t *)a.sorted, (const int *)a.cnt,
                      (const int *)a.off, a.nbuckets, a.out);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, a.nitems, 0);
+  hipLaunchKernelGGL(k_l2g_items, dim3(nblk(a.nbuckets, 256)), dim3(256), 0, s, (const int *)a.cnt,
+                     (const int *)a.off, a.nbuckets, a.items, a.nitems);
 }
 
 void launch_finalize(hipStream_t s, const FinalizeArgs &a) {
@@ -2648,10 +2627,10 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
                          a.cover, a.sv, a.stage, a.Pts, a.skips + 1, a.fb, a.fb_count);
       return;
     }
-    const dim3 g(L2G_BLOCKS), b(64 * L2G_WAVES);
+    const dim3 g(L2G_BLOCKS), b(L2G_THREADS);
 #define PW_L2G(PP)                                                                                                \
-  hipLaunchKernelGGL((k_l2g_box<TB, TC, PP>), g, b, 0, s, a.P, a.pose, a.efflist, a.effcount, a.l2g_run, a.cover, a.sv, \
-                     a.stage, a.skips + 1, a.fb, a.fb_count)
+  hipLaunchKernelGGL((k_l2g_bucket<TB, TC, PP>), g, b, 0, s, a.P, a.pose, a.efflist, a.l2g_items, a.l2g_nitems,   \
+                     a.l2g_run, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count)
     switch (a.Pts) {
       case 2: PW_L2G(2); break;
       case 3: PW_L2G(3); break;
