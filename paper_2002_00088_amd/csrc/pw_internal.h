@@ -217,21 +217,27 @@ __device__ inline void fwd_map(const PatchDev &p, const PoseDev &ps, const doubl
 }
 
 // Inverse map: background X -> numerical x' of patch p at pose ps.
+// Numerical coordinates of a curvilinear patch at patch-frame point y: (r,
+// theta, phi) or (r, phi, z).  Not inlined: the inverse trigonometric
+// functions stay out of the (register-bound) interpolation kernels that call
+// it for a few of their points.
+__device__ __noinline__ double3 curv_coords(int coord, double y0, double y1, double y2) {
+  if (coord == SPH) {
+    const double r = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
+    return make_double3(r, acos(y2 / r), atan2(y1, y0));
+  }
+  return make_double3(sqrt(y0 * y0 + y1 * y1), atan2(y1, y0), y2);
+}
+
 __device__ inline void inv_map(const PatchDev &p, const PoseDev &ps, const double X[3], double xp[3]) {
   double d[3] = {X[0] - ps.c[0], X[1] - ps.c[1], X[2] - ps.c[2]};
   double y[3];
   for (int b = 0; b < 3; b++) y[b] = ps.R[b] * d[0] + ps.R[3 + b] * d[1] + ps.R[6 + b] * d[2];
   if (p.coord == CART) {
     xp[0] = y[0]; xp[1] = y[1]; xp[2] = y[2];
-  } else if (p.coord == SPH) {
-    double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-    xp[0] = r;
-    xp[1] = acos(y[2] / r);
-    xp[2] = atan2(y[1], y[0]);
   } else {
-    xp[0] = sqrt(y[0] * y[0] + y[1] * y[1]);
-    xp[1] = atan2(y[1], y[0]);
-    xp[2] = y[2];
+    const double3 v = curv_coords(p.coord, y[0], y[1], y[2]);
+    xp[0] = v.x; xp[1] = v.y; xp[2] = v.z;
   }
 }
 
