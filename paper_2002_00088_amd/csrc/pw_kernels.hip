@@ -1867,9 +1867,12 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
   const TC i12dx2[3] = {(TC)(p.idx[0] * p.idx[0] / 12.0), (TC)(p.idx[1] * p.idx[1] / 12.0),
                         (TC)(p.idx[2] * p.idx[2] / 12.0)};
   const TC ko[3] = {(TC)(eps / 64.0 * p.idx[0]), (TC)(eps / 64.0 * p.idx[1]), (TC)(eps / 64.0 * p.idx[2])};
-  // rotating patches: position-dependent shift and acceleration (frame_terms)
-  const bool spin = (ps.wp[0] != 0.0) || (ps.wp[1] != 0.0) || (ps.wp[2] != 0.0);
-  const bool moving = spin || (ps.b[0] != 0.0) || (ps.b[1] != 0.0) || (ps.b[2] != 0.0);
+  // rotating patches: position-dependent shift and acceleration (frame_terms).
+  // The global patch is the static background frame: no shift, no mixed
+  // derivatives, so it needs no D_x phi, D_y phi window (DWIN)
+  const bool spin = !GLOB && ((ps.wp[0] != 0.0) || (ps.wp[1] != 0.0) || (ps.wp[2] != 0.0));
+  const bool moving = !GLOB && (spin || (ps.b[0] != 0.0) || (ps.b[1] != 0.0) || (ps.b[2] != 0.0));
+  constexpr bool DWIN = FORM == 0 && !GLOB;
   const double bdt = STAGE == 0 ? dt / 6.0 : (STAGE == 3 ? dt / 6.0 : dt / 3.0);
   const double adt = STAGE == 2 ? dt : dt / 2.0;
   const float bdtf = (float)bdt, adtf = (float)adt;
@@ -1891,7 +1894,7 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
     const uint32_t zo = (uint32_t)(zn + PW_NG) * sz;  // cell_index already holds the +NG of z = 0
 #pragma unroll
     for (int f = 0; f < 5; f++) pown[f] = inpad ? (TC)gld(in, f * fs + col + zo - PW_NG * sz) : (TC)0;
-    if (FORM == 0 && itp >= 2) {
+    if (DWIN && itp >= 2) {
       const uint32_t za = zo - (PW_NG + 1) * sz;
 #pragma unroll
       for (int m = 0; m < NH; m++) phA[m] = hval[m] ? (TC)gld(in, hoff[m] + za) : (TC)0;
@@ -1908,7 +1911,7 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
   // values of planes z0-3 .. z0+2 go to the z-window, and D_x phi, D_y phi at
   // planes z0-2 .. z0+1 are formed from phi planes staged with their halo rings
   // (in the second centre-plane buffer, first written two iterations later).
-  if (FORM == 0) {
+  if (DWIN) {
     TC wh[4][NH];
 #pragma unroll
     for (int w = 0; w < 6; w++) {
@@ -1942,7 +1945,8 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
       }
     }
   } else {
-    // first-order form: no D_x phi, D_y phi window; the z-window and the prefetch only
+    // first-order form or the static global patch: no D_x phi, D_y phi window;
+    // the z-window and the prefetch only
 #pragma unroll
     for (int w = 0; w < 6; w++) {
       const uint32_t zo = (uint32_t)(z0 - 3 + w + PW_NG) * sz - PW_NG * sz;
@@ -1960,7 +1964,7 @@ __global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchD
       for (int d = 0; d < 6; d++) q[f][d] = q[f][d + 1];
       q[f][6] = pown[f];
     }
-    const bool do_d = FORM == 0 && it >= 2;  // phi plane zd = zn - 1 for D_x phi, D_y phi
+    const bool do_d = DWIN && it >= 2;  // phi plane zd = zn - 1 for D_x phi, D_y phi
     const bool do_c = it >= 6;  // centre plane zc = zn - 3
     TC *A_ = Ad[buf];
     if (do_d) {
