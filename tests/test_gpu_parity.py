@@ -688,6 +688,12 @@ def test_error_paths():
         g.create_patch(W.patch([8] * 3, [0] * 3, [1] * 3, is_global=0))
     with pytest.raises(pw.PwError):
         g.rk4_step(0.1, 1)
+    # the kernels address a patch's five padded fields with 32-bit offsets: a
+    # 1000^3 patch (5 x 1006 x 1006 x 1016 elements > 2^32) is rejected before
+    # anything is allocated, a 900^3 one would fit
+    with pytest.raises(pw.PwError) as e:
+        g.create_patch(W.patch([1000] * 3, [0] * 3, [1] * 3, is_global=1))
+    assert e.value.code == -1 and "2^32" in str(e.value)
     g.close()
 
 
@@ -765,6 +771,33 @@ def test_diagnostics_energy_and_constraint(case):
         scale = max(np.max(do["max"][1:]), 1e-300)
         assert np.all(np.abs(dg["constraint"] - do["constraint"]) <= 1e-11 * scale + 1e-12 * do["constraint"])
         say("  patch", pid, "energy", dg["energy"], do["energy"], "constraint", dg["constraint"])
+
+
+@pytest.mark.parametrize("prec", [pw.PW_FP64, pw.PW_MIXED])
+def test_torch_caching_allocator(prec):
+    # the library's device memory from torch's caching allocator (dev_alloc /
+    # dev_free callbacks) on a torch stream: the same values as with hipMalloc,
+    # and FP64 parity with the oracle
+    import torch
+
+    cfg = W.batched(seed=4, ng=64, nlocal=8, nmin=16, nmax=24)
+    say("torch caching allocator", prec)
+    st = torch.cuda.Stream()
+    a = pw.context_from_config(cfg, precision=prec, torch_alloc=True, stream=st.cuda_stream)
+    b = pw.context_from_config(cfg, precision=prec)
+    for g in (a, b):
+        g.init_exact(0.0)
+        g.rk4_step(cfg["dt"], 3)
+    assert a.n_alloc > 0 and b.n_alloc == 0
+    for pid in range(len(cfg["patches"])):
+        assert np.array_equal(a.get_state(pid), b.get_state(pid), equal_nan=True), pid
+    if prec == pw.PW_FP64:
+        o = world_from_config(cfg)
+        o.init_exact(0.0)
+        o.step(cfg["dt"], 3)
+        say("  worst rel err", compare(cfg, o, a, TOL64))
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("prec", [pw.PW_FP64, pw.PW_MIXED])
