@@ -675,6 +675,7 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.l2g_run = c->tune.l2g_run;
     a.l2g_first = narrow_buffer(c);
     a.global_curv = c->hp[0].coord != CART;
+    a.g2l_exact_only = !(c->hp[0].sv_mask & (1u << sv)) && c->hex[sv].kind != PW_EXACT_NONE;
     a.gflag = c->flag_cur;
     a.phys = c->dPhys;
     a.olist = c->nPhys > 0 ? c->olist[0] : nullptr;

@@ -1563,6 +1563,36 @@ __global__ void k_l2g_items(const int *cnt, const int *off, int nb, int2 *items,
   for (int q = 0; q < nch; q++) items[slot + q] = make_int2(off[b] + q * L2G_ITEM, min(L2G_ITEM, m - q * L2G_ITEM));
 }
 
+// Local ghost cells of a state vector that the global patch does not carry
+// have no donor: they keep their lower-priority value, the registered exact
+// solution, written here directly (one thread per ghost cell of the brick
+// list) instead of through a fallback record per point.
+template <typename TB>
+__global__ __launch_bounds__(BRICK_THREADS) void k_g2l_exact(const PatchDev *__restrict__ P,
+                                                           const PoseDev *__restrict__ pose, const GBrick *bricks,
+                                                           int nbricks, int sv, int stage, const ExactDev *ex,
+                                                           double v, const double *tdev, double tmul, double dt) {
+  if ((int)blockIdx.x >= nbricks) return;
+  const GBrick B = bricks[blockIdx.x];
+  const PatchDev &r = P[B.patch];
+  const int tid = threadIdx.x;
+  if (tid >= B.di * B.dj * B.dk || !(r.sv_mask & (1u << sv))) return;
+  const int c[3] = {B.i0 + tid % B.di, B.j0 + (tid / B.di) % B.dj, B.k0 + tid / (B.di * B.dj)};
+  bool inside = true, winside = true;
+  for (int a = 0; a < 3; a++) {
+    inside = inside && c[a] >= 0 && c[a] < r.n[a];
+    const int w = r.periodic[a] ? ((c[a] % r.n[a]) + r.n[a]) % r.n[a] : c[a];
+    winside = winside && w >= 0 && w < r.n[a];
+  }
+  if (inside || winside) return;
+  const double xr[3] = {xnum(r, 0, c[0]), xnum(r, 1, c[1]), xnum(r, 2, c[2])};
+  double out[5];
+  exact_patch(ex[sv], v, r, pose[B.patch], tdev[0] + tmul * dt, xr, out);
+  TB *TR = stage_buf<TB>(r, sv, stage);
+  const long long dst = cell_index(r, c[0], c[1], c[2]);
+  for (int f = 0; f < 5; f++) TR[f * r.fstride + dst] = (TB)out[f];
+}
+
 // Points that could not be interpolated keep their lower-priority value: a
 // local ghost gets the exact solution (if registered) or a copy of the nearest
 // interior cell; a global effective ghost gets the exact solution or NaN.
@@ -2605,6 +2635,11 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
     return;
   }
   auto run_g2l = [&]() {
+    if (a.g2l_exact_only) {
+      hipLaunchKernelGGL(k_g2l_exact<TB>, dim3(a.n_bricks), dim3(BRICK_THREADS), 0, s, a.P, a.pose, a.bricks,
+                         a.n_bricks, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt);
+      return;
+    }
     if (a.global_curv) {
       hipLaunchKernelGGL((k_g2l_point<TB, TC>), dim3(a.n_bricks), dim3(BRICK_THREADS), 0, s, a.P, a.pose, a.bricks,
                          a.n_bricks, a.sv, a.stage, a.gflag, a.l2g_first, a.Pts, a.skips, a.fb, a.fb_count);
