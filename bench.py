@@ -309,7 +309,7 @@ def main():
 
     def stage_roof(st):
         # the fused RHS + RK stage kernel over the global patch, stage st (HBM-bound)
-        name = "k_stage<%s, %d, 0, true, %d, 0>" % (ty, st, am)
+        name = "k_stage<%s, %d, 0, true, %d, 0, 0>" % (ty, st, am)
         g_ms = avg["gstage_s%d" % (st + 1)]
         b = live_global * sb[st]
         a = b / (g_ms * 1e-3) / 1e9

@@ -1818,11 +1818,11 @@ __global__ __launch_bounds__(256) void k_uncover(const PatchDev *__restrict__ P,
 // The centre plane of the 5 fields and the phi plane one below the newest are
 // staged in LDS with a 3-cell x-y halo for the x-y stencils.
 // ---------------------------------------------------------------------------
-template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD, bool GLOB, int AM, int FORM>
-__global__ __launch_bounds__(StageTile<GLOB>::THREADS) void k_stage(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose_slot, const TileRec *tiles,
+template <typename TIN, typename TOUT, typename TC, int STAGE, int COORD, bool GLOB, int AM, int FORM, int SH>
+__global__ __launch_bounds__((StageTile<GLOB, SH>::THREADS)) void k_stage(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose_slot, const TileRec *tiles,
                                                int ntiles, int chunk, const uint8_t *gflag, int sv, double dt,
                                                double v2, double eps) {
-  using TL = StageTile<GLOB>;
+  using TL = StageTile<GLOB, SH>;
   constexpr int ST_TX = TL::TX, ST_TY = TL::TY, ST_PX = TL::PX, ST_PW = TL::PW;
   constexpr int ST_THREADS = TL::THREADS;
   __shared__ TC Bc[2][5][ST_PW];
@@ -2744,26 +2744,37 @@ void launch_post_flags(hipStream_t s, const PostFlagsArgs &a) {
 }
 
 // One stage launch over tiles of one topology (global patch or local patches).
+template <typename TIN, typename TOUT, typename TC, int ST, int AM, int FORM, int SH>
+static void launch_stage_local(hipStream_t s, const StageArgs &a, dim3 g, int chunk) {
+  const dim3 bs(StageTile<false, SH>::THREADS);
+  if (a.coord == CART)
+    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, false, AM, FORM, SH>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+  else if (a.coord == SPH)
+    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, false, AM, FORM, SH>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+  else
+    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CYL, false, AM, FORM, SH>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+}
+
 template <typename TIN, typename TOUT, typename TC, int ST, int AM, int FORM>
 static void launch_stage_t(hipStream_t s, const StageArgs &a) {
   const int chunk = (a.ntiles + 7) / 8;
-  const dim3 bs(a.global ? StageTile<true>::THREADS : StageTile<false>::THREADS);
   const dim3 g(8 * chunk);
-  if (a.coord == CART && a.global)
-    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, true, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
-                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
-  else if (a.global)  // a spherical global patch
-    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, true, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
-                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
-  else if (a.coord == CART)
-    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, false, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
-                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
-  else if (a.coord == SPH)
-    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, false, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
-                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
-  else
-    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CYL, false, AM, FORM>), g, bs, 0, s, a.P, a.pose, a.tiles,
-                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+  if (a.global) {
+    const dim3 bs(StageTile<true>::THREADS);
+    if (a.coord == CART)
+      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, true, AM, FORM, 0>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                         a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+    else  // a spherical global patch
+      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, true, AM, FORM, 0>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                         a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+  } else if (a.local_tile == 1) {
+    launch_stage_local<TIN, TOUT, TC, ST, AM, FORM, 1>(s, a, g, chunk);
+  } else {
+    launch_stage_local<TIN, TOUT, TC, ST, AM, FORM, 0>(s, a, g, chunk);
+  }
 }
 
 template <int FORM>

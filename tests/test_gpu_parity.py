@@ -625,14 +625,15 @@ def test_full_size_spherical_one_step():
 
 
 def test_tuning_changes_no_value():
-    # tile depths, XCD run lengths and the chain of the curvilinear local stages
-    # only reorder work: the state after a few steps is bitwise the same
+    # tile depths and shapes, XCD run lengths and the chain of the curvilinear
+    # local stages only reorder work: the state after a few steps is bitwise the same
     cfg = W.batched(seed=4, ng=64, nlocal=8, nmin=16, nmax=24)
     outs = []
     for tune in (None, dict(tile_z_global=16, tile_z_local=4, g2l_run=2, l2g_run=8),
                  dict(tile_z_global=64, tile_z_local=3, g2l_run=16, l2g_run=1, global_order=pw.PW_ORDER_OCTANTS),
                  dict(tile_z_global=8, global_order=pw.PW_ORDER_OCTANTS),
-                 dict(chain=pw.PW_CHAIN_LOCAL_AFTER), dict(chain=pw.PW_CHAIN_LOCAL_BEFORE, tile_z_local=6)):
+                 dict(chain=pw.PW_CHAIN_LOCAL_AFTER), dict(chain=pw.PW_CHAIN_LOCAL_BEFORE, tile_z_local=6),
+                 dict(local_tile=pw.PW_TILE_16X16), dict(local_tile=pw.PW_TILE_16X16, tile_z_local=3)):
         g = pw.context_from_config(cfg, precision=pw.PW_MIXED)
         if tune:
             g.set_tuning(**tune)
