@@ -66,8 +66,17 @@ enum { PW_BC_EXACT = 0, PW_BC_SOMMERFELD = 1 };        /* outer boundary of the 
  * Library configuration.
  *   precision        PW_FP64: every array and operation FP64.  PW_MIXED: FP64 state
  *                    u_n, FP64 RK accumulator, FP64 donor location, Lagrange weights
- *                    and frame Jacobians; FP32 stage inputs, FP32 stencil and
- *                    interpolation sums (an FP32 copy of u_n feeds the first stage).
+ *                    and frame Jacobians; FP32 stage inputs, FP32 stencil arithmetic
+ *                    (an FP32 copy of u_n feeds the first stage).  Interpolation: the
+ *                    weights are formed in FP64; the x-row sums run in FP32 with the x
+ *                    weights rounded to FP32 once, and the rows and layers are combined
+ *                    with the FP64 y and z weights in FP64.
+ *                    Accuracy of PW_FP64 against a plain FP64 evaluation of the same
+ *                    scheme: per field, max |difference| over live cells below 1e-12
+ *                    of the field's largest magnitude there; the one-form components
+ *                    Pi_t, Pi_x, Pi_y, Pi_z, which the frame transforms mix, share one
+ *                    magnitude (their largest), since a component that is small next
+ *                    to the others carries their rounding.
  *                    PW_MIXED_INC: as PW_MIXED, but the accumulator carries the
  *                    increment dt sum_l b_l K_l (Table rk4) in FP32 and
  *                    u_{n+1} = u_n + increment + b_4 dt K_4 is formed in FP64.
