@@ -307,9 +307,11 @@ def main():
     copy_gbs = copy_bandwidth(torch, stream)
     tc_bytes = 8 if args.precision == "fp64" else 4
 
+    gtile = ctx.tuning()["global_tile"]  # the global patch's tile shape (a template argument)
+
     def stage_roof(st):
         # the fused RHS + RK stage kernel over the global patch, stage st (HBM-bound)
-        name = "k_stage<%s, %d, 0, true, %d, 0, 0>" % (ty, st, am)
+        name = "k_stage<%s, %d, 0, true, %d, 0, %d>" % (ty, st, am, gtile)
         g_ms = avg["gstage_s%d" % (st + 1)]
         b = live_global * sb[st]
         a = b / (g_ms * 1e-3) / 1e9

@@ -316,10 +316,12 @@ typedef struct {
                             PW_CHAIN_LOCAL_BEFORE (2) on the local chain before them */
   int32_t local_tile;    /* columns per workgroup of the stage kernel on local patches:
                             PW_TILE_32X8 (0) or PW_TILE_16X16 (1) */
+  int32_t global_tile;   /* the same on the global patch: PW_TILE_32X8 (0) or
+                            PW_TILE_128X4 (1, 512 threads) */
 } pw_tuning;
 enum { PW_ORDER_BANDS = 0, PW_ORDER_OCTANTS = 1 };
 enum { PW_CHAIN_GLOBAL = 0, PW_CHAIN_LOCAL_AFTER = 1, PW_CHAIN_LOCAL_BEFORE = 2 };
-enum { PW_TILE_32X8 = 0, PW_TILE_16X16 = 1 };
+enum { PW_TILE_32X8 = 0, PW_TILE_16X16 = 1, PW_TILE_128X4 = 1 };
 
 /* Current tuning parameters. */
 pw_status pw_get_tuning(pw_context *ctx, pw_tuning *out);
@@ -331,8 +333,8 @@ pw_status pw_set_tuning(pw_context *ctx, const pw_tuning *t);
 /* Autotuner: times candidate settings on this context's own patches with HIP
  * events over steps_per_trial steps of size dt each (after one untimed step),
  * searching the two tile depths and the global tile order on a grid, then the
- * place of the curvilinear local stage kernels, then the local tile shape, then
- * the two run lengths, and keeps
+ * global tile shape, the place of the curvilinear local stage kernels, the local
+ * tile shape and the two run lengths, and keeps
  * the fastest (written to *best unless best is NULL).  It advances the state and
  * the time by every step it takes, so call it before setting the initial data
  * (or set it again afterwards).  On an error the previous settings are restored. */

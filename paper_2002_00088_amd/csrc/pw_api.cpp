@@ -104,7 +104,7 @@ struct pw_context {
   long long stageCap = 0;
   double *dPartial = nullptr;
   bool layout_dirty = true, flags_valid = false;
-  pw_tuning tune = {TUNE_TZ_GLOBAL, TUNE_TZ_LOCAL, TUNE_G2L_RUN, TUNE_L2G_RUN, PW_ORDER_BANDS, TUNE_CHAIN, TUNE_LOCAL_TILE};
+  pw_tuning tune = {TUNE_TZ_GLOBAL, TUNE_TZ_LOCAL, TUNE_G2L_RUN, TUNE_L2G_RUN, PW_ORDER_BANDS, TUNE_CHAIN, TUNE_LOCAL_TILE, TUNE_GLOBAL_TILE};
   double t_host = 0.0;
   // first failure of a runtime call while a step is enqueued (event records and
   // waits between the step's streams); reported by pw_rk4_step
@@ -427,9 +427,11 @@ pw_status upload_layout(pw_context *c) {
   auto add_tiles = [&](int pid) {
     const PatchDev &p = c->hp[pid];
     c->tileOff[pid] = (int)tiles.size();
-    const bool sq = c->tune.local_tile == 1;
-    const int TX = pid == 0 ? StageTile<true>::TX : (sq ? StageTile<false, 1>::TX : StageTile<false, 0>::TX);
-    const int TY = pid == 0 ? StageTile<true>::TY : (sq ? StageTile<false, 1>::TY : StageTile<false, 0>::TY);
+    const bool sq = c->tune.local_tile == 1, wide = c->tune.global_tile == 1;
+    const int TX = pid == 0 ? (wide ? StageTile<true, 1>::TX : StageTile<true, 0>::TX)
+                            : (sq ? StageTile<false, 1>::TX : StageTile<false, 0>::TX);
+    const int TY = pid == 0 ? (wide ? StageTile<true, 1>::TY : StageTile<true, 0>::TY)
+                            : (sq ? StageTile<false, 1>::TY : StageTile<false, 0>::TY);
     const int TZ = pid == 0 ? c->tune.tile_z_global : c->tune.tile_z_local;
     if (pid == 0 && c->tune.global_order == PW_ORDER_OCTANTS) {
       // the global patch in its eight octants (halves of the tile counts along
@@ -709,6 +711,7 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
     a.inc = c->cfg.precision == PW_MIXED_INC;
     a.form = c->cfg.pi_form;
     a.local_tile = c->tune.local_tile;
+    a.global_tile = c->tune.global_tile;
     a.dt = dt;
     a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
     a.eps = c->cfg.ko_eps;
@@ -760,6 +763,7 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
     a.inc = c->cfg.precision == PW_MIXED_INC;
     a.form = c->cfg.pi_form;
     a.local_tile = c->tune.local_tile;
+    a.global_tile = c->tune.global_tile;
     a.dt = dt;
     a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
     a.eps = c->cfg.ko_eps;
@@ -1527,6 +1531,8 @@ pw_status pw_set_tuning(pw_context *c, const pw_tuning *t) {
     return fail(c, PW_EINVAL, "tuning parameter out of range");
   if (t->local_tile != PW_TILE_32X8 && t->local_tile != PW_TILE_16X16)
     return fail(c, PW_EINVAL, "tuning parameter out of range");
+  if (t->global_tile != PW_TILE_32X8 && t->global_tile != PW_TILE_128X4)
+    return fail(c, PW_EINVAL, "tuning parameter out of range");
   if (t->tile_z_global < 1 || t->tile_z_global > 512 || t->tile_z_local < 1 || t->tile_z_local > 512 ||
       t->g2l_run < 1 || t->g2l_run > 64 || t->l2g_run < 1 || t->l2g_run > 64)
     return fail(c, PW_EINVAL, "tuning parameter out of range");
@@ -1538,8 +1544,9 @@ pw_status pw_set_tuning(pw_context *c, const pw_tuning *t) {
 // Coordinate search over the tuning parameters, each candidate timed with HIP
 // events over steps_per_trial steps (after one untimed step, which also captures
 // the step graph): the tile depths and the global tile order on a grid, then the
-// chain of the curvilinear local stages, then the other local tile shape (with
-// the local tile depths), then the brick run, then the group run.
+// other global tile shape (with the global tile depths), the chain of the
+// curvilinear local stages, the other local tile shape (with the local tile
+// depths), the brick run and the group run.
 pw_status pw_autotune(pw_context *c, double dt, int32_t steps_per_trial, pw_tuning *best) {
   if (!c || !(dt > 0) || steps_per_trial < 1) return PW_EINVAL;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1576,6 +1583,15 @@ pw_status pw_autotune(pw_context *c, double dt, int32_t steps_per_trial, pw_tuni
         rc = trial(t, ms);
         if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
       }
+  // the other global tile shape, with the global tile depths again
+  const pw_tuning base0b = bestT;
+  for (int a = 0; a < 3 && !rc; a++) {
+    pw_tuning t = base0b;
+    t.global_tile = 1 - base0b.global_tile;
+    t.tile_z_global = tzg[a];
+    rc = trial(t, ms);
+    if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
+  }
   if (has_locals(c)) {
     const pw_tuning base1 = bestT;
     for (int a = 0; a < 3 && !rc; a++) {

@@ -14,13 +14,15 @@
 #ifndef STAGE_GTY
 #define STAGE_GTY 8
 #endif
-// Local patches: SH = 0 tiles of 32 x 8 columns, SH = 1 tiles of 16 x 16 (a
-// run-time tuning parameter: narrower tiles waste fewer columns on patches of
-// 24-96 cells and have a smaller halo per cell, 1.89 against 2.08).
+// Tile shapes, run-time tuning parameters.  Global patch: SH = 0 tiles of
+// STAGE_GTX x STAGE_GTY columns (32 x 8), SH = 1 tiles of 128 x 4 on 512 threads
+// (longer contiguous rows per load).  Local patches: SH = 0 tiles of 32 x 8, SH =
+// 1 tiles of 16 x 16 (narrower tiles waste fewer columns on patches of 24-96
+// cells and have a smaller halo per cell, 1.89 against 2.08).
 template <bool GLOB, int SH = 0>
 struct StageTile {
-  static constexpr int TX = GLOB ? STAGE_GTX : (SH == 1 ? 16 : 32);
-  static constexpr int TY = GLOB ? STAGE_GTY : (SH == 1 ? 16 : 8);
+  static constexpr int TX = GLOB ? (SH == 1 ? 128 : STAGE_GTX) : (SH == 1 ? 16 : 32);
+  static constexpr int TY = GLOB ? (SH == 1 ? 4 : STAGE_GTY) : (SH == 1 ? 16 : 8);
   static constexpr int PX = TX + 6, PY = TY + 6, PW = PX * PY;  // LDS plane with a 3-cell halo
   static constexpr int THREADS = TX * TY;
 };
@@ -31,6 +33,7 @@ struct StageTile {
 #define TUNE_L2G_RUN 4
 #define TUNE_CHAIN 0
 #define TUNE_LOCAL_TILE 0
+#define TUNE_GLOBAL_TILE 1
 #define DIAG_N 27
 #define BRICK_THREADS 192
 #ifndef BRICK_LDS_BYTES
@@ -220,7 +223,8 @@ struct StageArgs {
   int sv, stage, mixed;
   int inc;   // mixed path: FP32 increments in the accumulator
   int form;  // 0: the paper's Pi_t equation, 1: its first-order form
-  int local_tile;  // tile shape of local patches (StageTile SH)
+  int local_tile;   // tile shape of local patches (StageTile SH)
+  int global_tile;  // tile shape of the global patch (StageTile SH)
   double dt, v2, eps;
 };
 

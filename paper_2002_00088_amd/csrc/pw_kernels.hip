@@ -2758,18 +2758,24 @@ static void launch_stage_local(hipStream_t s, const StageArgs &a, dim3 g, int ch
                        a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
 }
 
+template <typename TIN, typename TOUT, typename TC, int ST, int AM, int FORM, int SH>
+static void launch_stage_global(hipStream_t s, const StageArgs &a, dim3 g, int chunk) {
+  const dim3 bs(StageTile<true, SH>::THREADS);
+  if (a.coord == CART)
+    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, true, AM, FORM, SH>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+  else  // a spherical global patch
+    hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, true, AM, FORM, SH>), g, bs, 0, s, a.P, a.pose, a.tiles,
+                       a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+}
+
 template <typename TIN, typename TOUT, typename TC, int ST, int AM, int FORM>
 static void launch_stage_t(hipStream_t s, const StageArgs &a) {
   const int chunk = (a.ntiles + 7) / 8;
   const dim3 g(8 * chunk);
   if (a.global) {
-    const dim3 bs(StageTile<true>::THREADS);
-    if (a.coord == CART)
-      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, CART, true, AM, FORM, 0>), g, bs, 0, s, a.P, a.pose, a.tiles,
-                         a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
-    else  // a spherical global patch
-      hipLaunchKernelGGL((k_stage<TIN, TOUT, TC, ST, SPH, true, AM, FORM, 0>), g, bs, 0, s, a.P, a.pose, a.tiles,
-                         a.ntiles, chunk, a.gflag, a.sv, a.dt, a.v2, a.eps);
+    if (a.global_tile == 1) launch_stage_global<TIN, TOUT, TC, ST, AM, FORM, 1>(s, a, g, chunk);
+    else launch_stage_global<TIN, TOUT, TC, ST, AM, FORM, 0>(s, a, g, chunk);
   } else if (a.local_tile == 1) {
     launch_stage_local<TIN, TOUT, TC, ST, AM, FORM, 1>(s, a, g, chunk);
   } else {

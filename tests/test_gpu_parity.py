@@ -633,7 +633,9 @@ def test_tuning_changes_no_value():
                  dict(tile_z_global=64, tile_z_local=3, g2l_run=16, l2g_run=1, global_order=pw.PW_ORDER_OCTANTS),
                  dict(tile_z_global=8, global_order=pw.PW_ORDER_OCTANTS),
                  dict(chain=pw.PW_CHAIN_LOCAL_AFTER), dict(chain=pw.PW_CHAIN_LOCAL_BEFORE, tile_z_local=6),
-                 dict(local_tile=pw.PW_TILE_16X16), dict(local_tile=pw.PW_TILE_16X16, tile_z_local=3)):
+                 dict(local_tile=pw.PW_TILE_16X16), dict(local_tile=pw.PW_TILE_16X16, tile_z_local=3),
+                 dict(global_tile=pw.PW_TILE_32X8), dict(global_tile=pw.PW_TILE_128X4, tile_z_global=5,
+                                                         global_order=pw.PW_ORDER_OCTANTS)):
         g = pw.context_from_config(cfg, precision=pw.PW_MIXED)
         if tune:
             g.set_tuning(**tune)
