@@ -682,6 +682,7 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.gflag = c->flag_cur;
     a.phys = c->dPhys;
     a.olist = c->nPhys > 0 ? c->olist[0] : nullptr;
+    a.nphys = c->nPhys;
     a.ocount = c->ocount[0];
     launch_ghosts(st, a);
   }

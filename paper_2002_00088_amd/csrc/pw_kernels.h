@@ -210,6 +210,7 @@ struct GhostArgs {
   const GhostRec *phys;
   const int2 *olist;
   const int *ocount;
+  int nphys;  // physical ghost cells of the global patch (bound of the covered list)
 };
 
 struct StageArgs {

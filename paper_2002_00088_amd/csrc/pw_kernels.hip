@@ -2627,7 +2627,8 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
                          l1 - lb, a.sv, a.stage, a.ex, a.v, a.tdev, a.tmul, a.dt, a.lower_dup);
     // covered physical ghosts of the global patch: interpatch over the boundary value
     if ((a.parts & GH_GLOBAL) && a.olist)
-      hipLaunchKernelGGL((k_l2g_outer<TB, TC>), dim3(64), dim3(256), 0, s, a.P, a.pose, a.phys, a.olist, a.ocount,
+      hipLaunchKernelGGL((k_l2g_outer<TB, TC>), dim3(std::min(1024u, nblk(a.nphys, 256))), dim3(256), 0, s, a.P,
+                         a.pose, a.phys, a.olist, a.ocount,
                          a.sv, a.stage, a.Pts, a.skips);
   };
   if (!g2l && !l2g) {
