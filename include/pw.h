@@ -239,7 +239,7 @@ pw_status pw_create(const pw_config *cfg, pw_context **out);
 /* Add a patch; the first one is the global patch.  *id_out receives its id
  * (0 for the global patch, 1.. for local patches).  Allocates its device buffers.
  * PW_EINVAL if an axis has more than 1017 cells or the five padded fields of the
- * patch ([n2+6][n1+6][row pitch]) hold 2^32 elements or more (about 940^3 cells). */
+ * patch ([n2+6][n1+6][row pitch]) hold 2^32 elements or more (about 925^3 cells). */
 pw_status pw_create_patch(pw_context *ctx, const pw_patch_desc *desc, int32_t *id_out);
 
 /* Register the exact solution of state vector sv (copied). */

@@ -1167,7 +1167,7 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
     const PatchDev &last = c->hp.back();
     p.bkt_base = last.bkt_base + last.bkt_n[0] * last.bkt_n[1] * last.bkt_n[2];
   }
-  p.pitch = ((PW_OX + p.n[0] + PW_NG) + 7) / 8 * 8;
+  p.pitch = ((PW_OX + p.n[0] + PW_NG) + 31) / 32 * 32;
   p.rows = p.n[1] + 2 * PW_NG;
   p.slabs = p.n[2] + 2 * PW_NG;
   p.slab = (long long)p.pitch * p.rows;
@@ -1175,7 +1175,7 @@ pw_status pw_create_patch(pw_context *c, const pw_patch_desc *d, int32_t *id_out
   long long nel = 5 * p.fstride;
   // the kernels address the five fields of a patch with 32-bit element offsets
   if (nel > (long long)UINT32_MAX)
-    return fail(c, PW_EINVAL, "a patch's five padded fields must hold fewer than 2^32 elements (about 940^3 cells)");
+    return fail(c, PW_EINVAL, "a patch's five padded fields must hold fewer than 2^32 elements (about 925^3 cells)");
   if (p.coord != CART) {
     const int nt = 2 * (p.n[1] + p.n[2] + 4 * PW_NG);
     double *tab = (double *)dalloc(c, sizeof(double) * nt);

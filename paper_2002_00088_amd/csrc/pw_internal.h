@@ -1,14 +1,15 @@
 // Internal device-side data structures and math of libpw (gfx950).
 //
 // Patch arrays are padded by NG = 3 ghost cells per side; each x-row is laid out
-// [5 alignment pad][3 ghosts][n0 interior][3 ghosts][pad to a multiple of 8], so
-// the first interior element of every row starts 64-byte aligned in FP64.
+// [29 alignment pad][3 ghosts][n0 interior][3 ghosts][pad to a multiple of 32],
+// so the first interior element of every row starts 128-byte aligned in FP32
+// (256 in FP64): a tile row of 32 or 128 cells then writes whole cache lines.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #define PW_NG 3
-#define PW_OX 8          // row offset of interior cell i = 0
+#define PW_OX 32         // row offset of interior cell i = 0
 #define PW_MAXSV 4
 #define PW_MAXPULSE 32
 #define PW_NPTS 5    // interpolation widths P = 2 .. 6

@@ -1269,37 +1269,74 @@ __device__ __forceinline__ void l2g_rows_lds(const unsigned char *lds, int capc,
   }
 }
 
-// One z-layer of a stencil straight from global memory (rare: a donor box that
-// does not fit the LDS tile): the same arithmetic as l2g_rows_lds, in loops
-// that are not unrolled (the weights picked by selects).
+// A point's stencil straight from global memory (rare: an item whose donor box
+// does not fit the LDS tile).  The thread's z-layers (g and g + 3, or g alone
+// for K = 6), each summed as in l2g_rows_lds and combined as in the staged
+// path, in loops that are not unrolled (the weights picked by selects).  The
+// point is located and weighted again here with the same functions as the
+// kernel's setup, so only scalars cross the call: an array argument of a
+// function that is not inlined lives in scratch memory, and the kernel would
+// store its weights there for every item, whichever path the item takes.
+struct Sum5 {
+  double v[5];
+};
+
 template <typename TB, typename TC, int Pts>
-__device__ __noinline__ void l2g_rows_global(const PatchDev &D, const TB *T, int s0, int s1, int kk,
-                                             const TC *wxc, const double *wy, double ly[5]) {
+__device__ __noinline__ Sum5 l2g_point_global(const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose,
+                                              int d, int i, int j, int k, int sv, int stage, int g, int K) {
+  const PatchDev &G0 = P[0];
+  const PatchDev &D = P[d];
+  const double X[3] = {xnum(G0, 0, i), xnum(G0, 1, j), xnum(G0, 2, k)};
+  double xd[3], q[3];
+  inv_map(D, pose[d], X, xd);
+  for (int a = 0; a < 3; a++) q[a] = (xd[a] - D.lo[a]) * D.idx[a] - 0.5;
+  double wx[Pts], wy[Pts], wz[Pts];
+  const int s0 = lagrange_wt<Pts>(q[0], wx);
+  const int s1 = lagrange_wt<Pts>(q[1], wy);
+  const int s2 = lagrange_wt<Pts>(q[2], wz);
+  TC wxc[Pts];
+#pragma unroll
+  for (int m = 0; m < Pts; m++) wxc[m] = (TC)wx[m];
+  const TB *T = stage_buf<TB>(D, sv, stage);
   const uint32_t fs = (uint32_t)D.fstride;
-  for (int b = 0; b < Pts; b++) {
-    int jj = s1 + b;
-    if (D.periodic[1]) jj = ((jj % D.n[1]) + D.n[1]) % D.n[1];
-    TC p5[5] = {0, 0, 0, 0, 0};
-    for (int a = 0; a < Pts; a++) {
-      int ii = s0 + a;
-      if (D.periodic[0]) ii = ((ii % D.n[0]) + D.n[0]) % D.n[0];
-      const uint32_t x = (uint32_t)cell_index(D, ii, jj, kk);
-      TC w = (TC)0;
+  Sum5 part = {{0, 0, 0, 0, 0}};
+  for (int m = 0; m < 2; m++) {
+    const int cc = g + 3 * m;
+    if (cc >= Pts || (K == 6 && m > 0)) break;
+    int kk = s2 + cc;
+    if (D.periodic[2]) kk = ((kk % D.n[2]) + D.n[2]) % D.n[2];
+    double ly[5] = {0, 0, 0, 0, 0};
+    for (int b = 0; b < Pts; b++) {
+      int jj = s1 + b;
+      if (D.periodic[1]) jj = ((jj % D.n[1]) + D.n[1]) % D.n[1];
+      TC p5[5] = {0, 0, 0, 0, 0};
+      for (int a = 0; a < Pts; a++) {
+        int ii = s0 + a;
+        if (D.periodic[0]) ii = ((ii % D.n[0]) + D.n[0]) % D.n[0];
+        const uint32_t x = (uint32_t)cell_index(D, ii, jj, kk);
+        TC w = (TC)0;
 #pragma unroll
-      for (int m = 0; m < Pts; m++) w = (m == a) ? wxc[m] : w;
+        for (int e = 0; e < Pts; e++) w = (e == a) ? wxc[e] : w;
 #pragma unroll
-      for (int f = 0; f < 5; f++) {
-        const TC u = (TC)gld(T, f * fs + x);
-        if constexpr (sizeof(TC) == 4) p5[f] = fmaf(w, u, p5[f]);
-        else p5[f] = fma(w, u, p5[f]);
+        for (int f = 0; f < 5; f++) {
+          const TC u = (TC)gld(T, f * fs + x);
+          if constexpr (sizeof(TC) == 4) p5[f] = fmaf(w, u, p5[f]);
+          else p5[f] = fma(w, u, p5[f]);
+        }
       }
+      double wb = 0.0;
+#pragma unroll
+      for (int e = 0; e < Pts; e++) wb = (e == b) ? wy[e] : wb;
+#pragma unroll
+      for (int f = 0; f < 5; f++) ly[f] = fma(wb, (double)p5[f], ly[f]);
     }
-    double wb = 0.0;
+    double wzc = 0.0;
 #pragma unroll
-    for (int m = 0; m < Pts; m++) wb = (m == b) ? wy[m] : wb;
+    for (int e = 0; e < Pts; e++) wzc = (e == cc) ? wz[e] : wzc;
 #pragma unroll
-    for (int f = 0; f < 5; f++) ly[f] = fma(wb, (double)p5[f], ly[f]);
+    for (int f = 0; f < 5; f++) part.v[f] = __dadd_rn(part.v[f], __dmul_rn(wzc, ly[f]));
   }
+  return part;
 }
 
 template <typename TB, typename TC, int Pts>
@@ -1482,19 +1519,9 @@ __global__ __launch_bounds__(L2G_THREADS) __attribute__((amdgpu_waves_per_eu(3))
       }
     } else if (valid) {
       // (rare) the stencil straight from global memory, same arithmetic
-      const PatchDev &D = P[d];
-      const TB *T = stage_buf<TB>(D, sv, stage);
+      const Sum5 r = l2g_point_global<TB, TC, Pts>(P, pose, d, i, j, k, sv, stage, g, K);
 #pragma unroll
-      for (int m = 0; m < 2; m++) {
-        const int cc = g + 3 * m;
-        if (cc >= Pts || (K == 6 && m > 0)) break;
-        int kk = s[2] + cc;
-        if (D.periodic[2]) kk = ((kk % D.n[2]) + D.n[2]) % D.n[2];
-        double ly[5] = {0, 0, 0, 0, 0};
-        l2g_rows_global<TB, TC, Pts>(D, T, s[0], s[1], kk, wxc, wy, ly);
-#pragma unroll
-        for (int f = 0; f < 5; f++) part[f] = __dadd_rn(part[f], __dmul_rn(wzl[m], ly[f]));
-      }
+      for (int f = 0; f < 5; f++) part[f] = r.v[f];
     }
     // the partial sums of a point's threads meet in its g = 0 thread (in the
     // box's LDS, which every thread is done with)
