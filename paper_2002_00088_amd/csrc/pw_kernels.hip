@@ -1140,18 +1140,16 @@ __global__ __launch_bounds__(BRICK_THREADS) __attribute__((amdgpu_waves_per_eu(4
             const TC *bf = base + f * v;
 #pragma unroll
             for (int cc = 0; cc < Pts; cc++) {
-              // one z-layer: all Pts x Pts values read before the sums, so the LDS
-              // reads are issued back to back
-              TC w[Pts][Pts];
-#pragma unroll
-              for (int b = 0; b < Pts; b++)
-#pragma unroll
-                for (int a = 0; a < Pts; a++) w[b][a] = bf[cc * e01 + b * e0 + a];
+              // row by row (a whole layer held in registers, 2 P^2 VGPRs in
+              // FP64, spilled to scratch memory)
 #pragma unroll
               for (int b = 0; b < Pts; b++) {
+                TC w[Pts];
+#pragma unroll
+                for (int a = 0; a < Pts; a++) w[a] = bf[cc * e01 + b * e0 + a];
                 TC part = (TC)0;
 #pragma unroll
-                for (int a = 0; a < Pts; a++) part += wxc[a] * w[b][a];
+                for (int a = 0; a < Pts; a++) part += wxc[a] * w[a];
                 sum += (TO)(wy[b] * wz[cc]) * (TO)part;
               }
             }
