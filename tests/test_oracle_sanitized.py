@@ -51,7 +51,10 @@ def test_oracle_under_address_and_ub_sanitizers():
     asan = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True, text=True).stdout.strip()
     if not asan or not os.path.isabs(asan) or not os.path.exists(asan):
         pytest.skip("gcc's libasan is not installed")
-    env = dict(os.environ, PW_ORACLE_SANITIZE="1", LD_PRELOAD=asan, OMP_NUM_THREADS="4",
+    # the sanitizer runtime must come first; whatever the environment already
+    # preloads stays preloaded after it
+    pre = os.environ.get("LD_PRELOAD", "")
+    env = dict(os.environ, PW_ORACLE_SANITIZE="1", LD_PRELOAD=asan + (":" + pre if pre else ""), OMP_NUM_THREADS="4",
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=0:halt_on_error=1",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([sys.executable, "-c", SCRIPT % {"root": ROOT}], env=env, capture_output=True, text=True,
