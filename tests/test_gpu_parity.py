@@ -692,7 +692,7 @@ def test_error_paths():
     with pytest.raises(pw.PwError):
         g.rk4_step(0.1, 1)
     # the kernels address a patch's five padded fields with 32-bit offsets: a
-    # 1000^3 patch (5 x 1006 x 1006 x 1016 elements > 2^32) is rejected before
+    # 1000^3 patch (5 x 1006 x 1006 x 1056 elements > 2^32) is rejected before
     # anything is allocated, a 900^3 one would fit
     with pytest.raises(pw.PwError) as e:
         g.create_patch(W.patch([1000] * 3, [0] * 3, [1] * 3, is_global=1))
