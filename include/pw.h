@@ -233,7 +233,12 @@ typedef struct {
   int64_t skip_outer, n_outer;
 } pw_counters_t;
 
-/* Create a context.  cfg is copied.  *out receives the context on success. */
+/* Create a context.  cfg is copied.  *out receives the context on success.
+ * Validation switch: with the environment variable PW_L2G_DIRECT set to "1"
+ * when the context is created, every local->global interpolation point gathers
+ * its stencil straight from global memory (the path otherwise taken only by a
+ * work item whose donor box cannot be staged in LDS); the results are the same
+ * bitwise, the step is slower. */
 pw_status pw_create(const pw_config *cfg, pw_context **out);
 
 /* Add a patch; the first one is the global patch.  *id_out receives its id

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -34,6 +35,10 @@ struct pw_context {
   pw_config cfg;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // validation switch (environment variable PW_L2G_DIRECT=1 when the context is
+  // created): every local->global point takes the direct gather from global
+  // memory instead of the staged donor box; the values are the same bitwise
+  bool l2g_direct = false;
   std::string err;
   std::vector<pw_patch_desc> desc;
   std::vector<PatchDev> hp;
@@ -679,6 +684,7 @@ void enqueue_ghosts(pw_context *c, int stage, const PoseDev *pose_slot, const do
     a.l2g_first = narrow_buffer(c);
     a.global_curv = c->hp[0].coord != CART;
     a.g2l_exact_only = !(c->hp[0].sv_mask & (1u << sv)) && c->hex[sv].kind != PW_EXACT_NONE;
+    a.l2g_direct = c->l2g_direct ? 1 : 0;
     a.gflag = c->flag_cur;
     a.phys = c->dPhys;
     a.olist = c->nPhys > 0 ? c->olist[0] : nullptr;
@@ -1024,6 +1030,10 @@ pw_status pw_create(const pw_config *cfg, pw_context **out) {
   pw_context *c = new (std::nothrow) pw_context();
   if (!c) return PW_ENOMEM;
   c->cfg = *cfg;
+  {
+    const char *e = getenv("PW_L2G_DIRECT");
+    c->l2g_direct = e && e[0] == '1' && e[1] == 0;
+  }
   if (cfg->stream) {
     c->stream = (hipStream_t)cfg->stream;
   } else {

@@ -204,6 +204,7 @@ struct GhostArgs {
   int global_curv;       // curvilinear global patch: one-point-per-thread interpatch kernels
   int g2l_exact_only;    // the global patch does not carry sv and an exact solution is registered:
                          // the local ghosts take it directly (no donor, no fallback records)
+  int l2g_direct;        // validation: every local->global point takes the direct gather
   const uint8_t *gflag;  // cover flags of the global patch (donor test of those kernels)
   // covered physical ghost cells of the global patch (Sec. 2.4.2): filled from
   // the covering local patch after their boundary value (null: none)

@@ -1341,7 +1341,7 @@ template <typename TB, typename TC, int Pts>
 __global__ __launch_bounds__(L2G_THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_l2g_bucket(
     const PatchDev *__restrict__ P, const PoseDev *__restrict__ pose, const int32_t *list, const int2 *items,
     const int *nitems, int run, const int32_t *cover, int sv, int stage, unsigned long long *skips, FallbackRec *fb,
-    int *fb_count) {
+    int *fb_count, int force_direct) {
   constexpr int NW = L2G_THREADS / 64;
   constexpr int CAPC = L2G_LDS_BYTES / (5 * sizeof(TC));  // box cells: five fields a cell
   static_assert(L2G_ITEM * 3 <= L2G_THREADS && L2G_ITEM <= 64, "three threads per point of an item");
@@ -1440,7 +1440,7 @@ __global__ __launch_bounds__(L2G_THREADS) __attribute__((amdgpu_waves_per_eu(3))
     }
     const int e0 = hi[0] - lo[0] + 1, e1 = hi[1] - lo[1] + 1, e2 = hi[2] - lo[2] + 1;
     const int e01 = e0 * e1;
-    const bool boxed = dmax >= 1 && dmin == dmax && e01 <= CAPC;
+    const bool boxed = !force_direct && dmax >= 1 && dmin == dmax && e01 <= CAPC;
     // this thread's layers g, g + K of its point, summed into part in the
     // fixed grouping (each layer sum rounded on its own before the add)
     double part[5] = {0, 0, 0, 0, 0};
@@ -2695,7 +2695,7 @@ static void ghosts_typed(hipStream_t s, const GhostArgs &a) {
     const dim3 g(L2G_BLOCKS), b(L2G_THREADS);
 #define PW_L2G(PP)                                                                                                \
   hipLaunchKernelGGL((k_l2g_bucket<TB, TC, PP>), g, b, 0, s, a.P, a.pose, a.efflist, a.l2g_items, a.l2g_nitems,   \
-                     a.l2g_run, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count)
+                     a.l2g_run, a.cover, a.sv, a.stage, a.skips + 1, a.fb, a.fb_count, a.l2g_direct)
     switch (a.Pts) {
       case 2: PW_L2G(2); break;
       case 3: PW_L2G(3); break;

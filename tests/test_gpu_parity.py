@@ -541,6 +541,42 @@ def test_schedules_and_graph_bitwise_identical():
         assert np.array_equal(o[1], outs[0][1], equal_nan=True)
 
 
+@pytest.mark.parametrize("prec", [pw.PW_FP64, pw.PW_MIXED])
+def test_l2g_direct_gather_bitwise(prec, monkeypatch):
+    # The local->global kernel gathers a point's stencil straight from global
+    # memory when its work item's donor box cannot be staged in LDS (no
+    # configuration reaches it: an item lies in one donor bucket).  The
+    # validation switch sends every point down that path: the states after
+    # three graph steps and the counters must be the same bitwise.
+    cfg = W.batched(seed=4, ng=96, nlocal=12, nmin=16, nmax=32)
+
+    def run(direct):
+        if direct:
+            monkeypatch.setenv("PW_L2G_DIRECT", "1")
+        else:
+            monkeypatch.delenv("PW_L2G_DIRECT", raising=False)
+        g = pw.context_from_config(cfg, precision=prec)
+        monkeypatch.delenv("PW_L2G_DIRECT", raising=False)  # read once, when the context is created
+        g.init_exact(0.0)
+        g.rk4_step(cfg["dt"], 2)
+        g.enable_timing(True)  # eager pass, kernel by kernel
+        g.rk4_step(cfg["dt"], 1)
+        g.enable_timing(False)
+        kt = g.kernel_times()["l2g"]
+        st = [g.get_state(pid, 0) for pid in range(len(cfg["patches"]))]
+        cnt = g.counters()
+        g.close()
+        return st, cnt, kt[0] / max(1, kt[1])
+
+    say("local->global direct gather against the staged path, precision %d" % prec)
+    a, ca, ta = run(False)
+    b, cb, tb = run(True)
+    say("  local->global kernel: staged %.4f ms, direct %.4f ms per launch" % (ta, tb))
+    assert ca == cb
+    for pid, (x, y) in enumerate(zip(a, b)):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), pid
+
+
 @pytest.mark.parametrize("prec", [pw.PW_MIXED, pw.PW_MIXED_INC])
 def test_mixed_precision_close_to_oracle(prec):
     cfg = W.two_patch(seed=2, ng=48, nl=40, P=6)
