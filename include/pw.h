@@ -321,12 +321,14 @@ typedef struct {
                             PW_CHAIN_LOCAL_BEFORE (2) on the local chain before them */
   int32_t local_tile;    /* columns per workgroup of the stage kernel on local patches:
                             PW_TILE_32X8 (0) or PW_TILE_16X16 (1) */
-  int32_t global_tile;   /* the same on the global patch: PW_TILE_32X8 (0) or
-                            PW_TILE_128X4 (1, 512 threads) */
+  int32_t global_tile;   /* the same on the global patch: PW_TILE_32X8 (0),
+                            PW_TILE_128X4 (1, 512 threads) or PW_TILE_128X8 (2, 512
+                            threads, two rows of the tile per thread; PW_MIXED and
+                            PW_MIXED_INC only, PW_EINVAL under PW_FP64) */
 } pw_tuning;
 enum { PW_ORDER_BANDS = 0, PW_ORDER_OCTANTS = 1 };
 enum { PW_CHAIN_GLOBAL = 0, PW_CHAIN_LOCAL_AFTER = 1, PW_CHAIN_LOCAL_BEFORE = 2 };
-enum { PW_TILE_32X8 = 0, PW_TILE_16X16 = 1, PW_TILE_128X4 = 1 };
+enum { PW_TILE_32X8 = 0, PW_TILE_16X16 = 1, PW_TILE_128X4 = 1, PW_TILE_128X8 = 2 };
 
 /* Current tuning parameters. */
 pw_status pw_get_tuning(pw_context *ctx, pw_tuning *out);

@@ -432,10 +432,11 @@ pw_status upload_layout(pw_context *c) {
   auto add_tiles = [&](int pid) {
     const PatchDev &p = c->hp[pid];
     c->tileOff[pid] = (int)tiles.size();
-    const bool sq = c->tune.local_tile == 1, wide = c->tune.global_tile == 1;
-    const int TX = pid == 0 ? (wide ? StageTile<true, 1>::TX : StageTile<true, 0>::TX)
+    const bool sq = c->tune.local_tile == 1;
+    const int gt = c->tune.global_tile;
+    const int TX = pid == 0 ? (gt == 2 ? StageTile<true, 2>::TX : gt == 1 ? StageTile<true, 1>::TX : StageTile<true, 0>::TX)
                             : (sq ? StageTile<false, 1>::TX : StageTile<false, 0>::TX);
-    const int TY = pid == 0 ? (wide ? StageTile<true, 1>::TY : StageTile<true, 0>::TY)
+    const int TY = pid == 0 ? (gt == 2 ? StageTile<true, 2>::TY : gt == 1 ? StageTile<true, 1>::TY : StageTile<true, 0>::TY)
                             : (sq ? StageTile<false, 1>::TY : StageTile<false, 0>::TY);
     const int TZ = pid == 0 ? c->tune.tile_z_global : c->tune.tile_z_local;
     if (pid == 0 && c->tune.global_order == PW_ORDER_OCTANTS) {
@@ -1542,8 +1543,10 @@ pw_status pw_set_tuning(pw_context *c, const pw_tuning *t) {
     return fail(c, PW_EINVAL, "tuning parameter out of range");
   if (t->local_tile != PW_TILE_32X8 && t->local_tile != PW_TILE_16X16)
     return fail(c, PW_EINVAL, "tuning parameter out of range");
-  if (t->global_tile != PW_TILE_32X8 && t->global_tile != PW_TILE_128X4)
+  if (t->global_tile != PW_TILE_32X8 && t->global_tile != PW_TILE_128X4 && t->global_tile != PW_TILE_128X8)
     return fail(c, PW_EINVAL, "tuning parameter out of range");
+  if (t->global_tile == PW_TILE_128X8 && !mixed(c))
+    return fail(c, PW_EINVAL, "global tile 128x8 (two rows per thread) exists in the mixed modes only");
   if (t->tile_z_global < 1 || t->tile_z_global > 512 || t->tile_z_local < 1 || t->tile_z_local > 512 ||
       t->g2l_run < 1 || t->g2l_run > 64 || t->l2g_run < 1 || t->l2g_run > 64)
     return fail(c, PW_EINVAL, "tuning parameter out of range");
@@ -1594,14 +1597,17 @@ pw_status pw_autotune(pw_context *c, double dt, int32_t steps_per_trial, pw_tuni
         rc = trial(t, ms);
         if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
       }
-  // the other global tile shape, with the global tile depths again
+  // the other global tile shapes, with the global tile depths again
   const pw_tuning base0b = bestT;
-  for (int a = 0; a < 3 && !rc; a++) {
-    pw_tuning t = base0b;
-    t.global_tile = 1 - base0b.global_tile;
-    t.tile_z_global = tzg[a];
-    rc = trial(t, ms);
-    if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
+  for (int sh = 0; sh < 3 && !rc; sh++) {
+    if (sh == base0b.global_tile || (sh == PW_TILE_128X8 && !mixed(c))) continue;
+    for (int a = 0; a < 3 && !rc; a++) {
+      pw_tuning t = base0b;
+      t.global_tile = sh;
+      t.tile_z_global = tzg[a];
+      rc = trial(t, ms);
+      if (!rc && ms < bestMs) { bestMs = ms; bestT = t; }
+    }
   }
   if (has_locals(c)) {
     const pw_tuning base1 = bestT;

@@ -16,15 +16,19 @@
 #endif
 // Tile shapes, run-time tuning parameters.  Global patch: SH = 0 tiles of
 // STAGE_GTX x STAGE_GTY columns (32 x 8), SH = 1 tiles of 128 x 4 on 512 threads
-// (longer contiguous rows per load).  Local patches: SH = 0 tiles of 32 x 8, SH =
-// 1 tiles of 16 x 16 (narrower tiles waste fewer columns on patches of 24-96
-// cells and have a smaller halo per cell, 1.89 against 2.08).
+// (longer contiguous rows per load), SH = 2 tiles of 128 x 8 on 512 threads, each
+// thread holding two rows of the tile (RY = 2: half the halo cells per cell of
+// SH = 1, twice the loads in flight per thread).  Local patches: SH = 0 tiles of
+// 32 x 8, SH = 1 tiles of 16 x 16 (narrower tiles waste fewer columns on patches
+// of 24-96 cells and have a smaller halo per cell, 1.89 against 2.08).
 template <bool GLOB, int SH = 0>
 struct StageTile {
-  static constexpr int TX = GLOB ? (SH == 1 ? 128 : STAGE_GTX) : (SH == 1 ? 16 : 32);
-  static constexpr int TY = GLOB ? (SH == 1 ? 4 : STAGE_GTY) : (SH == 1 ? 16 : 8);
+  static constexpr int TX = GLOB ? (SH >= 1 ? 128 : STAGE_GTX) : (SH == 1 ? 16 : 32);
+  static constexpr int TY = GLOB ? (SH == 1 ? 4 : SH == 2 ? 8 : STAGE_GTY) : (SH == 1 ? 16 : 8);
+  static constexpr int RY = (GLOB && SH == 2) ? 2 : 1;  // tile rows per thread
   static constexpr int PX = TX + 6, PY = TY + 6, PW = PX * PY;  // LDS plane with a 3-cell halo
-  static constexpr int THREADS = TX * TY;
+  static constexpr int THREADS = TX * TY / RY;
+  static_assert(TY % RY == 0, "whole rows per thread");
 };
 // Tuning defaults (measured on the batched 256^3 + 64-patch workload).
 #define TUNE_TZ_GLOBAL 32

@@ -1859,10 +1859,13 @@ __global__ __launch_bounds__((StageTile<GLOB, SH>::THREADS)) void k_stage(const 
   const PatchDev &p = P[tl.patch];
   const PoseDev &ps = pose_slot[tl.patch];
   const int tid = threadIdx.x;
+  // a thread owns column tx of RY tile rows: ty, ty + TYH, ...
+  constexpr int RY = TL::RY, TYH = ST_TY / RY;
   const int tx = tid % ST_TX, ty = tid / ST_TX;
-  const int i = tl.x0 + tx, j = tl.y0 + ty;
-  const bool inpad = (i < p.n[0] + PW_NG) && (j < p.n[1] + PW_NG);
-  const bool icol = (i < p.n[0]) && (j < p.n[1]);
+  const int i = tl.x0 + tx;
+  int jr[RY], ownr[RY];
+  bool inpadr[RY], icolr[RY];
+  uint32_t colr[RY];
   const int z0 = tl.z0;
   const int nz = tl.nz;
   const TIN *in = (const TIN *)(STAGE == 0 ? (sizeof(TIN) == 8 ? (const void *)p.u[sv] : (const void *)p.us[sv])
@@ -1880,7 +1883,14 @@ __global__ __launch_bounds__((StageTile<GLOB, SH>::THREADS)) void k_stage(const 
   // 32-bit element offsets: the host keeps the five fields of a patch (5 fstride
   // elements, ghosts and row padding included) below 2^32 elements
   const uint32_t fs = (uint32_t)p.fstride, sz = (uint32_t)p.slab;
-  const uint32_t col = (uint32_t)cell_index(p, i, j, 0);
+#pragma unroll
+  for (int r = 0; r < RY; r++) {
+    jr[r] = tl.y0 + ty + r * TYH;
+    inpadr[r] = (i < p.n[0] + PW_NG) && (jr[r] < p.n[1] + PW_NG);
+    icolr[r] = (i < p.n[0]) && (jr[r] < p.n[1]);
+    colr[r] = (uint32_t)cell_index(p, i, jr[r], 0);
+    ownr[r] = (ty + r * TYH + 3) * ST_PX + (tx + 3);
+  }
   // halo cells of the LDS planes: the ring of ST_PW - ST_THREADS cells around
   // the tile, enumerated row by row; thread t takes ring cells t, t + ST_THREADS
   constexpr int NHALO = ST_PW - ST_TX * ST_TY;
@@ -1917,7 +1927,6 @@ __global__ __launch_bounds__((StageTile<GLOB, SH>::THREADS)) void k_stage(const 
       }
     }
   }
-  const int own = (ty + 3) * ST_PX + (tx + 3);
   const TC i12dx[3] = {(TC)(p.idx[0] / 12.0), (TC)(p.idx[1] / 12.0), (TC)(p.idx[2] / 12.0)};
   const TC i12dx2[3] = {(TC)(p.idx[0] * p.idx[0] / 12.0), (TC)(p.idx[1] * p.idx[1] / 12.0),
                         (TC)(p.idx[2] * p.idx[2] / 12.0)};
@@ -1928,27 +1937,32 @@ __global__ __launch_bounds__((StageTile<GLOB, SH>::THREADS)) void k_stage(const 
   const bool spin = !GLOB && ((ps.wp[0] != 0.0) || (ps.wp[1] != 0.0) || (ps.wp[2] != 0.0));
   const bool moving = !GLOB && (spin || (ps.b[0] != 0.0) || (ps.b[1] != 0.0) || (ps.b[2] != 0.0));
   constexpr bool DWIN = FORM == 0 && !GLOB;
+  static_assert(RY == 1 || !DWIN, "several rows per thread only without the D_x phi, D_y phi window");
   const double bdt = STAGE == 0 ? dt / 6.0 : (STAGE == 3 ? dt / 6.0 : dt / 3.0);
   const double adt = STAGE == 2 ? dt : dt / 2.0;
   const float bdtf = (float)bdt, adtf = (float)adt;
-  TC q[5][7];
+  TC qr[RY][5][7];
   TC dqx[5], dqy[5];
 #pragma unroll
-  for (int f = 0; f < 5; f++)
+  for (int r = 0; r < RY; r++)
 #pragma unroll
-    for (int d = 0; d < 7; d++) q[f][d] = (TC)0;
+    for (int f = 0; f < 5; f++)
+#pragma unroll
+      for (int d = 0; d < 7; d++) qr[r][f][d] = (TC)0;
 #pragma unroll
   for (int d = 0; d < 5; d++) { dqx[d] = (TC)0; dqy[d] = (TC)0; }
   const TC w1[5] = {(TC)1, (TC)-8, (TC)0, (TC)8, (TC)-1};
 
   // software pipeline: the loads of iteration it+1 are in flight while
   // iteration it computes
-  TC pown[5], phA[NH], phB[NH][5];
+  TC pown[RY][5], phA[NH], phB[NH][5];
   auto prefetch = [&](int itp) {
     const int zn = z0 - 3 + itp;
     const uint32_t zo = (uint32_t)(zn + PW_NG) * sz;  // cell_index already holds the +NG of z = 0
 #pragma unroll
-    for (int f = 0; f < 5; f++) pown[f] = inpad ? (TC)gld(in, f * fs + col + zo - PW_NG * sz) : (TC)0;
+    for (int r = 0; r < RY; r++)
+#pragma unroll
+      for (int f = 0; f < 5; f++) pown[r][f] = inpadr[r] ? (TC)gld(in, f * fs + colr[r] + zo - PW_NG * sz) : (TC)0;
     if (DWIN && itp >= 2) {
       const uint32_t za = zo - (PW_NG + 1) * sz;
 #pragma unroll
@@ -1967,6 +1981,10 @@ __global__ __launch_bounds__((StageTile<GLOB, SH>::THREADS)) void k_stage(const 
   // planes z0-2 .. z0+1 are formed from phi planes staged with their halo rings
   // (in the second centre-plane buffer, first written two iterations later).
   if (DWIN) {
+    TC(&q)[5][7] = qr[0];  // RY == 1 with the window
+    const int own = ownr[0];
+    const bool inpad = inpadr[0], icol = icolr[0];
+    const uint32_t col = colr[0];
     TC wh[4][NH];
 #pragma unroll
     for (int w = 0; w < 6; w++) {
@@ -2006,7 +2024,9 @@ __global__ __launch_bounds__((StageTile<GLOB, SH>::THREADS)) void k_stage(const 
     for (int w = 0; w < 6; w++) {
       const uint32_t zo = (uint32_t)(z0 - 3 + w + PW_NG) * sz - PW_NG * sz;
 #pragma unroll
-      for (int f = 0; f < 5; f++) q[f][w + 1] = inpad ? (TC)gld(in, f * fs + col + zo) : (TC)0;
+      for (int r = 0; r < RY; r++)
+#pragma unroll
+        for (int f = 0; f < 5; f++) qr[r][f][w + 1] = inpadr[r] ? (TC)gld(in, f * fs + colr[r] + zo) : (TC)0;
     }
     prefetch(6);
   }
@@ -2014,16 +2034,18 @@ __global__ __launch_bounds__((StageTile<GLOB, SH>::THREADS)) void k_stage(const 
     const int zn = z0 - 3 + it;
     const int buf = it & 1;
 #pragma unroll
-    for (int f = 0; f < 5; f++) {
+    for (int r = 0; r < RY; r++)
 #pragma unroll
-      for (int d = 0; d < 6; d++) q[f][d] = q[f][d + 1];
-      q[f][6] = pown[f];
-    }
+      for (int f = 0; f < 5; f++) {
+#pragma unroll
+        for (int d = 0; d < 6; d++) qr[r][f][d] = qr[r][f][d + 1];
+        qr[r][f][6] = pown[r][f];
+      }
     const bool do_d = DWIN && it >= 2;  // phi plane zd = zn - 1 for D_x phi, D_y phi
     const bool do_c = it >= 6;  // centre plane zc = zn - 3
     TC *A_ = Ad[buf];
     if (do_d) {
-      if (inpad) A_[own] = q[0][5];
+      if (inpadr[0]) A_[ownr[0]] = qr[0][0][5];  // RY == 1 with the window
 #pragma unroll
       for (int m = 0; m < NH; m++)
         if (hval[m]) A_[hslot[m]] = phA[m];
@@ -2034,33 +2056,37 @@ __global__ __launch_bounds__((StageTile<GLOB, SH>::THREADS)) void k_stage(const 
     // accumulator (stages 2-4).  Mixed path, FP32 increments: the FP32 copy of
     // u_n (stages 2-3; stage 1 has it in the z-window), the increment (stages
     // 2-4), u_n itself in stage 4 only.
-    double cu[5], ca[5];
-    float cus[5], cd[5];
-    if (do_c && icol) {
-      const uint32_t xc = col + (uint32_t)(zn - 3) * sz;
+    double cur_[RY][5], car_[RY][5];
+    float cusr_[RY][5], cdr_[RY][5];
 #pragma unroll
-      for (int f = 0; f < 5; f++) {
-        cus[f] = (MIX && (STAGE == 1 || STAGE == 2)) ? gld((const float *)Us, f * fs + xc) : 0.0f;
-        if (INC) {
-          cd[f] = STAGE != 0 ? gld((const float *)AccF, f * fs + xc) : 0.0f;
-          cu[f] = STAGE == 3 ? gld(U, f * fs + xc) : 0.0;
-          ca[f] = 0.0;
-        } else if (MIX) {
-          cd[f] = 0.0f;
-          cu[f] = STAGE == 0 ? gld(U, f * fs + xc) : 0.0;
-          ca[f] = STAGE != 0 ? gld(Acc, f * fs + xc) : 0.0;
-        } else {
-          cd[f] = 0.0f;
-          cu[f] = STAGE != 3 ? gld(U, f * fs + xc) : 0.0;
-          ca[f] = STAGE != 0 ? gld(Acc, f * fs + xc) : 0.0;
+    for (int r = 0; r < RY; r++)
+      if (do_c && icolr[r]) {
+        const uint32_t xc = colr[r] + (uint32_t)(zn - 3) * sz;
+#pragma unroll
+        for (int f = 0; f < 5; f++) {
+          cusr_[r][f] = (MIX && (STAGE == 1 || STAGE == 2)) ? gld((const float *)Us, f * fs + xc) : 0.0f;
+          if (INC) {
+            cdr_[r][f] = STAGE != 0 ? gld((const float *)AccF, f * fs + xc) : 0.0f;
+            cur_[r][f] = STAGE == 3 ? gld(U, f * fs + xc) : 0.0;
+            car_[r][f] = 0.0;
+          } else if (MIX) {
+            cdr_[r][f] = 0.0f;
+            cur_[r][f] = STAGE == 0 ? gld(U, f * fs + xc) : 0.0;
+            car_[r][f] = STAGE != 0 ? gld(Acc, f * fs + xc) : 0.0;
+          } else {
+            cdr_[r][f] = 0.0f;
+            cur_[r][f] = STAGE != 3 ? gld(U, f * fs + xc) : 0.0;
+            car_[r][f] = STAGE != 0 ? gld(Acc, f * fs + xc) : 0.0;
+          }
         }
       }
-    }
     if (do_c) {
-      if (inpad) {
 #pragma unroll
-        for (int f = 0; f < 5; f++) Bc[buf][f][own] = q[f][3];
-      }
+      for (int r = 0; r < RY; r++)
+        if (inpadr[r]) {
+#pragma unroll
+          for (int f = 0; f < 5; f++) Bc[buf][f][ownr[r]] = qr[r][f][3];
+        }
 #pragma unroll
       for (int m = 0; m < NH; m++)
         if (hval[m]) {
@@ -2070,221 +2096,234 @@ __global__ __launch_bounds__((StageTile<GLOB, SH>::THREADS)) void k_stage(const 
     }
     __syncthreads();
     if (it + 1 < nz + 6) prefetch(it + 1);
-    if (do_d && icol) {
+    if (do_d && icolr[0]) {
+      const int own = ownr[0];  // RY == 1 with the window
 #pragma unroll
       for (int d = 0; d < 4; d++) { dqx[d] = dqx[d + 1]; dqy[d] = dqy[d + 1]; }
       dqx[4] = ((A_[own - 2] - A_[own + 2]) + (TC)8 * (A_[own + 1] - A_[own - 1])) * i12dx[0];
       dqy[4] = ((A_[own - 2 * ST_PX] - A_[own + 2 * ST_PX]) + (TC)8 * (A_[own + ST_PX] - A_[own - ST_PX])) * i12dx[1];
     }
-    if (do_c && icol) {
-      const int k = zn - 3;
-      bool live = true;
-      if (GLOB && gflag) live = gflag[((long long)k * p.n[1] + j) * p.n[0] + i] == LIVE;
-      if (live) {
-        TC m_[3], b2_[3], h_[3], bb_[3];
-        if (COORD == CART) {
-          double bv[3] = {ps.b[0], ps.b[1], ps.b[2]}, av[3] = {ps.a[0], ps.a[1], ps.a[2]};
-          if (spin) {
-            const double y[3] = {p.lo[0] + (i + 0.5) * p.dx[0], p.lo[1] + (j + 0.5) * p.dx[1],
-                                 p.lo[2] + (k + 0.5) * p.dx[2]};
-            frame_terms(ps, y, bv, av);
-          }
 #pragma unroll
-          for (int a = 0; a < 3; a++) {
-            m_[a] = (TC)av[a];
-            b2_[a] = (TC)(2.0 * bv[a]);
-            h_[a] = (TC)(v2 - bv[a] * bv[a]);
-          }
-          bb_[0] = (TC)(2.0 * bv[0] * bv[1]);
-          bb_[1] = (TC)(2.0 * bv[0] * bv[2]);
-          bb_[2] = (TC)(2.0 * bv[1] * bv[2]);
-        } else if (COORD == SPH) {
-          const double r = p.lo[0] + (i + 0.5) * p.dx[0];
-          double st, ct, sp, cp;
-          trig_axis(p, 0, p.n[1] + 2 * PW_NG, j, st, ct);
-          trig_axis(p, 2 * (p.n[1] + 2 * PW_NG), p.n[2] + 2 * PW_NG, k, sp, cp);
-          const double er[3] = {st * cp, st * sp, ct}, et[3] = {ct * cp, ct * sp, -st}, ep[2] = {-sp, cp};
-          double bv[3] = {ps.b[0], ps.b[1], ps.b[2]}, av[3] = {ps.a[0], ps.a[1], ps.a[2]};
-          if (spin) {
-            const double y[3] = {r * er[0], r * er[1], r * er[2]};
-            frame_terms(ps, y, bv, av);
-          }
-          double ir = 1.0 / r, irs = ir / st, cot = ct / st;
-          double br = er[0] * bv[0] + er[1] * bv[1] + er[2] * bv[2];
-          double bt = et[0] * bv[0] + et[1] * bv[1] + et[2] * bv[2];
-          double bp = ep[0] * bv[0] + ep[1] * bv[1];
-          double ar = er[0] * av[0] + er[1] * av[1] + er[2] * av[2];
-          double at = et[0] * av[0] + et[1] * av[1] + et[2] * av[2];
-          double ap = ep[0] * av[0] + ep[1] * av[1];
-          double beta[3] = {br, bt * ir, bp * irs};
-          double Q0 = (bt * bt + bp * bp) * ir;
-          double Q1 = (-2.0 * br * bt + bp * bp * cot) * ir * ir;
-          double Q2 = -2.0 * bp * (br + bt * cot) * ir * irs;
-          double mm[3] = {ar - Q0 + v2 * 2.0 * ir, at * ir - Q1 + v2 * cot * ir * ir, ap * irs - Q2};
-          double hh[3] = {1.0, ir * ir, irs * irs};
-#pragma unroll
-          for (int a = 0; a < 3; a++) {
-            m_[a] = (TC)mm[a];
-            b2_[a] = (TC)(2.0 * beta[a]);
-            h_[a] = (TC)(v2 * hh[a] - beta[a] * beta[a]);
-          }
-          bb_[0] = (TC)(2.0 * beta[0] * beta[1]);
-          bb_[1] = (TC)(2.0 * beta[0] * beta[2]);
-          bb_[2] = (TC)(2.0 * beta[1] * beta[2]);
-        } else {
-          // cylindrical x' = (r, phi, z): phi along the numerical y axis
-          const double r = p.lo[0] + (i + 0.5) * p.dx[0];
-          double sp, cp;
-          trig_axis(p, 0, p.n[1] + 2 * PW_NG, j, sp, cp);
-          double bv[3] = {ps.b[0], ps.b[1], ps.b[2]}, av[3] = {ps.a[0], ps.a[1], ps.a[2]};
-          if (spin) {
-            const double y[3] = {r * cp, r * sp, p.lo[2] + (k + 0.5) * p.dx[2]};
-            frame_terms(ps, y, bv, av);
-          }
-          const double ir = 1.0 / r;
-          const double br = cp * bv[0] + sp * bv[1], bp = cp * bv[1] - sp * bv[0];
-          const double ar = cp * av[0] + sp * av[1], ap = cp * av[1] - sp * av[0];
-          const double beta[3] = {br, bp * ir, bv[2]};
-          const double Q0 = bp * bp * ir;
-          const double Q1 = -2.0 * br * bp * ir * ir;
-          const double mm[3] = {ar - Q0 + v2 * ir, ap * ir - Q1, av[2]};
-          const double hh[3] = {1.0, ir * ir, 1.0};
-#pragma unroll
-          for (int a = 0; a < 3; a++) {
-            m_[a] = (TC)mm[a];
-            b2_[a] = (TC)(2.0 * beta[a]);
-            h_[a] = (TC)(v2 * hh[a] - beta[a] * beta[a]);
-          }
-          bb_[0] = (TC)(2.0 * beta[0] * beta[1]);
-          bb_[1] = (TC)(2.0 * beta[0] * beta[2]);
-          bb_[2] = (TC)(2.0 * beta[1] * beta[2]);
-        }
-        const TC(*Bf)[ST_PW] = Bc[buf];
-        // first derivatives of LDS plane F along x, y and of z-window row f along z
-        auto ddx = [&](const TC *F) { return ((F[own - 2] - F[own + 2]) + (TC)8 * (F[own + 1] - F[own - 1])) * i12dx[0]; };
-        auto ddy = [&](const TC *F) {
-          return ((F[own - 2 * ST_PX] - F[own + 2 * ST_PX]) + (TC)8 * (F[own + ST_PX] - F[own - ST_PX])) * i12dx[1];
-        };
-        auto ddz = [&](int f) { return ((q[f][1] - q[f][5]) + (TC)8 * (q[f][4] - q[f][2])) * i12dx[2]; };
-        TC dphi[3], d2phi[3], dpi[3], kof[5];
-        if (FORM == 1) {
-          // first-order form: Psi_a for D_a phi and D_a Psi_a for D_aa phi
-#pragma unroll
-          for (int a = 0; a < 3; a++) dphi[a] = q[2 + a][3];
-          d2phi[0] = ddx(Bf[2]);
-          d2phi[1] = ddy(Bf[3]);
-          d2phi[2] = ddz(4);
-        } else {
-          const TC *F = Bf[0];
-          TC u0 = F[own];
-          TC xm1 = F[own - 1], xp1 = F[own + 1], xm2 = F[own - 2], xp2 = F[own + 2];
-          TC ym1 = F[own - ST_PX], yp1 = F[own + ST_PX], ym2 = F[own - 2 * ST_PX], yp2 = F[own + 2 * ST_PX];
-          TC zm1 = q[0][2], zp1 = q[0][4], zm2 = q[0][1], zp2 = q[0][5];
-          dphi[0] = ((xm2 - xp2) + (TC)8 * (xp1 - xm1)) * i12dx[0];
-          dphi[1] = ((ym2 - yp2) + (TC)8 * (yp1 - ym1)) * i12dx[1];
-          dphi[2] = ((zm2 - zp2) + (TC)8 * (zp1 - zm1)) * i12dx[2];
-          d2phi[0] = ((TC)16 * (xm1 + xp1) - (xm2 + xp2) - (TC)30 * u0) * i12dx2[0];
-          d2phi[1] = ((TC)16 * (ym1 + yp1) - (ym2 + yp2) - (TC)30 * u0) * i12dx2[1];
-          d2phi[2] = ((TC)16 * (zm1 + zp1) - (zm2 + zp2) - (TC)30 * u0) * i12dx2[2];
-        }
-        {
-          const TC *F = Bf[1];
-          dpi[0] = ((F[own - 2] - F[own + 2]) + (TC)8 * (F[own + 1] - F[own - 1])) * i12dx[0];
-          dpi[1] = ((F[own - 2 * ST_PX] - F[own + 2 * ST_PX]) + (TC)8 * (F[own + ST_PX] - F[own - ST_PX])) * i12dx[1];
-          dpi[2] = ((q[1][1] - q[1][5]) + (TC)8 * (q[1][4] - q[1][2])) * i12dx[2];
-        }
-#pragma unroll
-        for (int f = 0; f < 5; f++) {
-          const TC *F = Bf[f];
-          const TC u0 = q[f][3];
-          TC kx = (F[own - 3] + F[own + 3]) - (TC)6 * (F[own - 2] + F[own + 2]) + (TC)15 * (F[own - 1] + F[own + 1]) -
-                  (TC)20 * u0;
-          TC kyv = (F[own - 3 * ST_PX] + F[own + 3 * ST_PX]) - (TC)6 * (F[own - 2 * ST_PX] + F[own + 2 * ST_PX]) +
-                   (TC)15 * (F[own - ST_PX] + F[own + ST_PX]) - (TC)20 * u0;
-          TC kz = (q[f][0] + q[f][6]) - (TC)6 * (q[f][1] + q[f][5]) + (TC)15 * (q[f][2] + q[f][4]) - (TC)20 * u0;
-          kof[f] = kx * ko[0] + kyv * ko[1] + kz * ko[2];
-        }
-        TC rhs_pi = (TC)0;
-#pragma unroll
-        for (int a = 0; a < 3; a++) rhs_pi += m_[a] * dphi[a] + b2_[a] * dpi[a] + h_[a] * d2phi[a];
-        if (moving && FORM == 1) {
-          // g^{ij} D_i Psi_j: the off-diagonal pairs enter as (D_i Psi_j + D_j Psi_i) / 2
-          const TC sxy = ddx(Bf[3]) + ddy(Bf[2]);
-          const TC sxz = ddx(Bf[4]) + ddz(2);
-          const TC syz = ddy(Bf[4]) + ddz(3);
-          rhs_pi -= (TC)0.5 * (bb_[0] * sxy + bb_[1] * sxz + bb_[2] * syz);
-        } else if (moving) {
-          const TC *F = Bf[0];
-          TC sxy = (TC)0;
-#pragma unroll
-          for (int o2 = 0; o2 < 5; o2++) {
-            if (o2 == 2) continue;
-            TC inner = (TC)0;
-#pragma unroll
-            for (int o1 = 0; o1 < 5; o1++) {
-              if (o1 == 2) continue;
-              inner += w1[o1] * F[own + (o1 - 2) + (o2 - 2) * ST_PX];
+    for (int r = 0; r < RY; r++) {
+      // row r of the thread, under the names of the one-row form
+      TC(&q)[5][7] = qr[r];
+      const int own = ownr[r], j = jr[r];
+      const bool icol = icolr[r];
+      const uint32_t col = colr[r];
+      const double(&cu)[5] = cur_[r];
+      const double(&ca)[5] = car_[r];
+      const float(&cus)[5] = cusr_[r];
+      const float(&cd)[5] = cdr_[r];
+      if (do_c && icol) {
+        const int k = zn - 3;
+        bool live = true;
+        if (GLOB && gflag) live = gflag[((long long)k * p.n[1] + j) * p.n[0] + i] == LIVE;
+        if (live) {
+          TC m_[3], b2_[3], h_[3], bb_[3];
+          if (COORD == CART) {
+            double bv[3] = {ps.b[0], ps.b[1], ps.b[2]}, av[3] = {ps.a[0], ps.a[1], ps.a[2]};
+            if (spin) {
+              const double y[3] = {p.lo[0] + (i + 0.5) * p.dx[0], p.lo[1] + (j + 0.5) * p.dx[1],
+                                   p.lo[2] + (k + 0.5) * p.dx[2]};
+              frame_terms(ps, y, bv, av);
             }
-            sxy += w1[o2] * inner;
-          }
-          TC dxy = sxy * i12dx[0] * i12dx[1];
-          TC sxz = (TC)0, syz = (TC)0;
 #pragma unroll
-          for (int o = 0; o < 5; o++) {
-            sxz += w1[o] * dqx[o];
-            syz += w1[o] * dqy[o];
-          }
-          TC dxz = sxz * i12dx[2], dyz = syz * i12dx[2];
-          rhs_pi -= bb_[0] * dxy + bb_[1] * dxz + bb_[2] * dyz;
-        }
-        TC K[5];
-        K[0] = q[1][3] + kof[0];
-        K[1] = rhs_pi + kof[1];
-#pragma unroll
-        for (int a = 0; a < 3; a++) K[2 + a] = dpi[a] + kof[2 + a];
-        const uint32_t x0 = col + (uint32_t)k * sz;
-        // classic RK4 (Table rk4): v_{s+1} = u_n + a_s dt K_s; acc holds
-        // u_n + dt sum_l b_l K_l in FP64, or (FP32 increments) dt sum_l b_l K_l in
-        // FP32 with u_{n+1} = u_n + increment + b_4 dt K_4 formed in FP64.
-#pragma unroll
-        for (int f = 0; f < 5; f++) {
-          const uint32_t x = f * fs + x0;
-          if (INC) {
-            const float kf = (float)K[f];
-            if (STAGE == 0) {
-              gst(AccF, x, bdtf * kf);
-              gst(vout, x, (TOUT)((float)q[f][3] + adtf * kf));
-            } else if (STAGE == 3) {
-              const double un = cu[f] + ((double)cd[f] + bdt * (double)kf);
-              gst(U, x, un);
-              gst(Us, x, (float)un);
-            } else {
-              gst(AccF, x, cd[f] + bdtf * kf);
-              gst(vout, x, (TOUT)(cus[f] + adtf * kf));
+            for (int a = 0; a < 3; a++) {
+              m_[a] = (TC)av[a];
+              b2_[a] = (TC)(2.0 * bv[a]);
+              h_[a] = (TC)(v2 - bv[a] * bv[a]);
             }
-          } else if (MIX) {
-            const double kd = (double)K[f];
-            if (STAGE == 0) {
-              gst(Acc, x, cu[f] + bdt * kd);
-              gst(vout, x, (TOUT)(cu[f] + adt * kd));
-            } else if (STAGE == 3) {
-              const double un = ca[f] + bdt * kd;
-              gst(U, x, un);
-              gst(Us, x, (float)un);
-            } else {
-              gst(Acc, x, ca[f] + bdt * kd);
-              gst(vout, x, (TOUT)(cus[f] + adtf * (float)K[f]));
+            bb_[0] = (TC)(2.0 * bv[0] * bv[1]);
+            bb_[1] = (TC)(2.0 * bv[0] * bv[2]);
+            bb_[2] = (TC)(2.0 * bv[1] * bv[2]);
+          } else if (COORD == SPH) {
+            const double r = p.lo[0] + (i + 0.5) * p.dx[0];
+            double st, ct, sp, cp;
+            trig_axis(p, 0, p.n[1] + 2 * PW_NG, j, st, ct);
+            trig_axis(p, 2 * (p.n[1] + 2 * PW_NG), p.n[2] + 2 * PW_NG, k, sp, cp);
+            const double er[3] = {st * cp, st * sp, ct}, et[3] = {ct * cp, ct * sp, -st}, ep[2] = {-sp, cp};
+            double bv[3] = {ps.b[0], ps.b[1], ps.b[2]}, av[3] = {ps.a[0], ps.a[1], ps.a[2]};
+            if (spin) {
+              const double y[3] = {r * er[0], r * er[1], r * er[2]};
+              frame_terms(ps, y, bv, av);
             }
+            double ir = 1.0 / r, irs = ir / st, cot = ct / st;
+            double br = er[0] * bv[0] + er[1] * bv[1] + er[2] * bv[2];
+            double bt = et[0] * bv[0] + et[1] * bv[1] + et[2] * bv[2];
+            double bp = ep[0] * bv[0] + ep[1] * bv[1];
+            double ar = er[0] * av[0] + er[1] * av[1] + er[2] * av[2];
+            double at = et[0] * av[0] + et[1] * av[1] + et[2] * av[2];
+            double ap = ep[0] * av[0] + ep[1] * av[1];
+            double beta[3] = {br, bt * ir, bp * irs};
+            double Q0 = (bt * bt + bp * bp) * ir;
+            double Q1 = (-2.0 * br * bt + bp * bp * cot) * ir * ir;
+            double Q2 = -2.0 * bp * (br + bt * cot) * ir * irs;
+            double mm[3] = {ar - Q0 + v2 * 2.0 * ir, at * ir - Q1 + v2 * cot * ir * ir, ap * irs - Q2};
+            double hh[3] = {1.0, ir * ir, irs * irs};
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+              m_[a] = (TC)mm[a];
+              b2_[a] = (TC)(2.0 * beta[a]);
+              h_[a] = (TC)(v2 * hh[a] - beta[a] * beta[a]);
+            }
+            bb_[0] = (TC)(2.0 * beta[0] * beta[1]);
+            bb_[1] = (TC)(2.0 * beta[0] * beta[2]);
+            bb_[2] = (TC)(2.0 * beta[1] * beta[2]);
           } else {
-            const double kf = (double)K[f];
-            if (STAGE == 0) {
-              gst(Acc, x, cu[f] + bdt * kf);
-              gst(vout, x, (TOUT)(cu[f] + adt * kf));
-            } else if (STAGE == 3) {
-              gst(U, x, ca[f] + bdt * kf);
+            // cylindrical x' = (r, phi, z): phi along the numerical y axis
+            const double r = p.lo[0] + (i + 0.5) * p.dx[0];
+            double sp, cp;
+            trig_axis(p, 0, p.n[1] + 2 * PW_NG, j, sp, cp);
+            double bv[3] = {ps.b[0], ps.b[1], ps.b[2]}, av[3] = {ps.a[0], ps.a[1], ps.a[2]};
+            if (spin) {
+              const double y[3] = {r * cp, r * sp, p.lo[2] + (k + 0.5) * p.dx[2]};
+              frame_terms(ps, y, bv, av);
+            }
+            const double ir = 1.0 / r;
+            const double br = cp * bv[0] + sp * bv[1], bp = cp * bv[1] - sp * bv[0];
+            const double ar = cp * av[0] + sp * av[1], ap = cp * av[1] - sp * av[0];
+            const double beta[3] = {br, bp * ir, bv[2]};
+            const double Q0 = bp * bp * ir;
+            const double Q1 = -2.0 * br * bp * ir * ir;
+            const double mm[3] = {ar - Q0 + v2 * ir, ap * ir - Q1, av[2]};
+            const double hh[3] = {1.0, ir * ir, 1.0};
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+              m_[a] = (TC)mm[a];
+              b2_[a] = (TC)(2.0 * beta[a]);
+              h_[a] = (TC)(v2 * hh[a] - beta[a] * beta[a]);
+            }
+            bb_[0] = (TC)(2.0 * beta[0] * beta[1]);
+            bb_[1] = (TC)(2.0 * beta[0] * beta[2]);
+            bb_[2] = (TC)(2.0 * beta[1] * beta[2]);
+          }
+          const TC(*Bf)[ST_PW] = Bc[buf];
+          // first derivatives of LDS plane F along x, y and of z-window row f along z
+          auto ddx = [&](const TC *F) { return ((F[own - 2] - F[own + 2]) + (TC)8 * (F[own + 1] - F[own - 1])) * i12dx[0]; };
+          auto ddy = [&](const TC *F) {
+            return ((F[own - 2 * ST_PX] - F[own + 2 * ST_PX]) + (TC)8 * (F[own + ST_PX] - F[own - ST_PX])) * i12dx[1];
+          };
+          auto ddz = [&](int f) { return ((q[f][1] - q[f][5]) + (TC)8 * (q[f][4] - q[f][2])) * i12dx[2]; };
+          TC dphi[3], d2phi[3], dpi[3], kof[5];
+          if (FORM == 1) {
+            // first-order form: Psi_a for D_a phi and D_a Psi_a for D_aa phi
+#pragma unroll
+            for (int a = 0; a < 3; a++) dphi[a] = q[2 + a][3];
+            d2phi[0] = ddx(Bf[2]);
+            d2phi[1] = ddy(Bf[3]);
+            d2phi[2] = ddz(4);
+          } else {
+            const TC *F = Bf[0];
+            TC u0 = F[own];
+            TC xm1 = F[own - 1], xp1 = F[own + 1], xm2 = F[own - 2], xp2 = F[own + 2];
+            TC ym1 = F[own - ST_PX], yp1 = F[own + ST_PX], ym2 = F[own - 2 * ST_PX], yp2 = F[own + 2 * ST_PX];
+            TC zm1 = q[0][2], zp1 = q[0][4], zm2 = q[0][1], zp2 = q[0][5];
+            dphi[0] = ((xm2 - xp2) + (TC)8 * (xp1 - xm1)) * i12dx[0];
+            dphi[1] = ((ym2 - yp2) + (TC)8 * (yp1 - ym1)) * i12dx[1];
+            dphi[2] = ((zm2 - zp2) + (TC)8 * (zp1 - zm1)) * i12dx[2];
+            d2phi[0] = ((TC)16 * (xm1 + xp1) - (xm2 + xp2) - (TC)30 * u0) * i12dx2[0];
+            d2phi[1] = ((TC)16 * (ym1 + yp1) - (ym2 + yp2) - (TC)30 * u0) * i12dx2[1];
+            d2phi[2] = ((TC)16 * (zm1 + zp1) - (zm2 + zp2) - (TC)30 * u0) * i12dx2[2];
+          }
+          {
+            const TC *F = Bf[1];
+            dpi[0] = ((F[own - 2] - F[own + 2]) + (TC)8 * (F[own + 1] - F[own - 1])) * i12dx[0];
+            dpi[1] = ((F[own - 2 * ST_PX] - F[own + 2 * ST_PX]) + (TC)8 * (F[own + ST_PX] - F[own - ST_PX])) * i12dx[1];
+            dpi[2] = ((q[1][1] - q[1][5]) + (TC)8 * (q[1][4] - q[1][2])) * i12dx[2];
+          }
+#pragma unroll
+          for (int f = 0; f < 5; f++) {
+            const TC *F = Bf[f];
+            const TC u0 = q[f][3];
+            TC kx = (F[own - 3] + F[own + 3]) - (TC)6 * (F[own - 2] + F[own + 2]) + (TC)15 * (F[own - 1] + F[own + 1]) -
+                    (TC)20 * u0;
+            TC kyv = (F[own - 3 * ST_PX] + F[own + 3 * ST_PX]) - (TC)6 * (F[own - 2 * ST_PX] + F[own + 2 * ST_PX]) +
+                     (TC)15 * (F[own - ST_PX] + F[own + ST_PX]) - (TC)20 * u0;
+            TC kz = (q[f][0] + q[f][6]) - (TC)6 * (q[f][1] + q[f][5]) + (TC)15 * (q[f][2] + q[f][4]) - (TC)20 * u0;
+            kof[f] = kx * ko[0] + kyv * ko[1] + kz * ko[2];
+          }
+          TC rhs_pi = (TC)0;
+#pragma unroll
+          for (int a = 0; a < 3; a++) rhs_pi += m_[a] * dphi[a] + b2_[a] * dpi[a] + h_[a] * d2phi[a];
+          if (moving && FORM == 1) {
+            // g^{ij} D_i Psi_j: the off-diagonal pairs enter as (D_i Psi_j + D_j Psi_i) / 2
+            const TC sxy = ddx(Bf[3]) + ddy(Bf[2]);
+            const TC sxz = ddx(Bf[4]) + ddz(2);
+            const TC syz = ddy(Bf[4]) + ddz(3);
+            rhs_pi -= (TC)0.5 * (bb_[0] * sxy + bb_[1] * sxz + bb_[2] * syz);
+          } else if (moving) {
+            const TC *F = Bf[0];
+            TC sxy = (TC)0;
+#pragma unroll
+            for (int o2 = 0; o2 < 5; o2++) {
+              if (o2 == 2) continue;
+              TC inner = (TC)0;
+#pragma unroll
+              for (int o1 = 0; o1 < 5; o1++) {
+                if (o1 == 2) continue;
+                inner += w1[o1] * F[own + (o1 - 2) + (o2 - 2) * ST_PX];
+              }
+              sxy += w1[o2] * inner;
+            }
+            TC dxy = sxy * i12dx[0] * i12dx[1];
+            TC sxz = (TC)0, syz = (TC)0;
+#pragma unroll
+            for (int o = 0; o < 5; o++) {
+              sxz += w1[o] * dqx[o];
+              syz += w1[o] * dqy[o];
+            }
+            TC dxz = sxz * i12dx[2], dyz = syz * i12dx[2];
+            rhs_pi -= bb_[0] * dxy + bb_[1] * dxz + bb_[2] * dyz;
+          }
+          TC K[5];
+          K[0] = q[1][3] + kof[0];
+          K[1] = rhs_pi + kof[1];
+#pragma unroll
+          for (int a = 0; a < 3; a++) K[2 + a] = dpi[a] + kof[2 + a];
+          const uint32_t x0 = col + (uint32_t)k * sz;
+          // classic RK4 (Table rk4): v_{s+1} = u_n + a_s dt K_s; acc holds
+          // u_n + dt sum_l b_l K_l in FP64, or (FP32 increments) dt sum_l b_l K_l in
+          // FP32 with u_{n+1} = u_n + increment + b_4 dt K_4 formed in FP64.
+#pragma unroll
+          for (int f = 0; f < 5; f++) {
+            const uint32_t x = f * fs + x0;
+            if (INC) {
+              const float kf = (float)K[f];
+              if (STAGE == 0) {
+                gst(AccF, x, bdtf * kf);
+                gst(vout, x, (TOUT)((float)q[f][3] + adtf * kf));
+              } else if (STAGE == 3) {
+                const double un = cu[f] + ((double)cd[f] + bdt * (double)kf);
+                gst(U, x, un);
+                gst(Us, x, (float)un);
+              } else {
+                gst(AccF, x, cd[f] + bdtf * kf);
+                gst(vout, x, (TOUT)(cus[f] + adtf * kf));
+              }
+            } else if (MIX) {
+              const double kd = (double)K[f];
+              if (STAGE == 0) {
+                gst(Acc, x, cu[f] + bdt * kd);
+                gst(vout, x, (TOUT)(cu[f] + adt * kd));
+              } else if (STAGE == 3) {
+                const double un = ca[f] + bdt * kd;
+                gst(U, x, un);
+                gst(Us, x, (float)un);
+              } else {
+                gst(Acc, x, ca[f] + bdt * kd);
+                gst(vout, x, (TOUT)(cus[f] + adtf * (float)K[f]));
+              }
             } else {
-              gst(Acc, x, ca[f] + bdt * kf);
-              gst(vout, x, (TOUT)(cu[f] + adt * kf));
+              const double kf = (double)K[f];
+              if (STAGE == 0) {
+                gst(Acc, x, cu[f] + bdt * kf);
+                gst(vout, x, (TOUT)(cu[f] + adt * kf));
+              } else if (STAGE == 3) {
+                gst(U, x, ca[f] + bdt * kf);
+              } else {
+                gst(Acc, x, ca[f] + bdt * kf);
+                gst(vout, x, (TOUT)(cu[f] + adt * kf));
+              }
             }
           }
         }
@@ -2801,6 +2840,8 @@ static void launch_stage_t(hipStream_t s, const StageArgs &a) {
   const dim3 g(8 * chunk);
   if (a.global) {
     if (a.global_tile == 1) launch_stage_global<TIN, TOUT, TC, ST, AM, FORM, 1>(s, a, g, chunk);
+    else if (sizeof(TC) == 4 && a.global_tile == 2)  // mixed modes only (FP64 would spill registers)
+      launch_stage_global<TIN, TOUT, TC, ST, AM, FORM, (sizeof(TC) == 4 ? 2 : 1)>(s, a, g, chunk);
     else launch_stage_global<TIN, TOUT, TC, ST, AM, FORM, 0>(s, a, g, chunk);
   } else if (a.local_tile == 1) {
     launch_stage_local<TIN, TOUT, TC, ST, AM, FORM, 1>(s, a, g, chunk);

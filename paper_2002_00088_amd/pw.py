@@ -31,7 +31,7 @@ PW_FLAG_LIVE, PW_FLAG_EFFGHOST, PW_FLAG_DEACT = 0, 1, 2
 PW_SCHED_BATCHED, PW_SCHED_PER_PATCH = 0, 1
 PW_ORDER_BANDS, PW_ORDER_OCTANTS = 0, 1
 PW_CHAIN_GLOBAL, PW_CHAIN_LOCAL_AFTER, PW_CHAIN_LOCAL_BEFORE = 0, 1, 2
-PW_TILE_32X8, PW_TILE_16X16, PW_TILE_128X4 = 0, 1, 1
+PW_TILE_32X8, PW_TILE_16X16, PW_TILE_128X4, PW_TILE_128X8 = 0, 1, 1, 2
 PW_EXACT_NONE, PW_EXACT_PLANE, PW_EXACT_GAUSS = 0, 1, 2
 STATUS = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EDEVICE", -4: "PW_ESTATE", -5: "PW_EOVERLAP",
           -6: "PW_EMOTION"}

@@ -630,13 +630,17 @@ def _c4():
     return _C4["cfg"], _C4["oracle"]
 
 
-@pytest.mark.parametrize("prec", [pw.PW_FP64, pw.PW_MIXED, pw.PW_MIXED_INC])
-def test_full_size_batched_one_step(prec):
+@pytest.mark.parametrize("prec,gtile", [(pw.PW_FP64, None), (pw.PW_MIXED, None), (pw.PW_MIXED_INC, None),
+                                        (pw.PW_MIXED, pw.PW_TILE_128X8), (pw.PW_MIXED_INC, pw.PW_TILE_128X8)])
+def test_full_size_batched_one_step(prec, gtile):
     # the benchmark workload at full size (256^3 + 64 locals) in the benchmark's
-    # launch configuration (batched schedule, graph), one step against the oracle
+    # launch configuration (batched schedule, graph), one step against the oracle;
+    # also with the global tile shape of two rows per thread
     cfg, o = _c4()
-    say("full-size batched, 1 step, precision", prec)
+    say("full-size batched, 1 step, precision", prec, "global tile", gtile)
     g = pw.context_from_config(cfg, precision=prec, schedule=pw.PW_SCHED_BATCHED, use_graph=True)
+    if gtile is not None:
+        g.set_tuning(global_tile=gtile)
     g.init_exact(0.0)
     g.rk4_step(cfg["dt"], 1)
     tol = TOL64 if prec == pw.PW_FP64 else 1e-4
@@ -671,7 +675,9 @@ def test_tuning_changes_no_value():
                  dict(chain=pw.PW_CHAIN_LOCAL_AFTER), dict(chain=pw.PW_CHAIN_LOCAL_BEFORE, tile_z_local=6),
                  dict(local_tile=pw.PW_TILE_16X16), dict(local_tile=pw.PW_TILE_16X16, tile_z_local=3),
                  dict(global_tile=pw.PW_TILE_32X8), dict(global_tile=pw.PW_TILE_128X4, tile_z_global=5,
-                                                         global_order=pw.PW_ORDER_OCTANTS)):
+                                                         global_order=pw.PW_ORDER_OCTANTS),
+                 dict(global_tile=pw.PW_TILE_128X8, tile_z_global=7),
+                 dict(global_tile=pw.PW_TILE_128X8, tile_z_global=16, global_order=pw.PW_ORDER_OCTANTS)):
         g = pw.context_from_config(cfg, precision=pw.PW_MIXED)
         if tune:
             g.set_tuning(**tune)
@@ -695,6 +701,8 @@ def test_autotune_then_parity():
     assert 1 <= best["tile_z_global"] <= 512 and 1 <= best["tile_z_local"] <= 512
     with pytest.raises(pw.PwError):
         g.set_tuning(tile_z_global=0)
+    with pytest.raises(pw.PwError):
+        g.set_tuning(global_tile=pw.PW_TILE_128X8)  # two rows per thread: mixed modes only
     assert g.tuning() == best
     g.init_exact(0.0)
     g.rk4_step(cfg["dt"], 2)
