@@ -691,6 +691,40 @@ def test_tuning_changes_no_value():
             assert np.array_equal(a, b, equal_nan=True)
 
 
+def test_ragged_global_all_tile_shapes():
+    # a global patch of 64 x 44 x 41 cells: the 128-wide tiles overhang it along
+    # x, and in the last row of 8-row tiles the second row of a thread of the
+    # 128 x 8 shape lies partly outside the padded patch.  Every global tile shape
+    # and depth gives bitwise the same state; mixed parity with the oracle, and
+    # FP64 parity at 1e-12 for the shapes that exist in FP64
+    cfg = W.two_patch(seed=2, ng=64, nl=40, P=6, motion=W.LINEAR)
+    cfg["patches"][0] = W.patch([64, 44, 41], [-8.0, -5.5, -5.125], [8.0, 5.5, 5.125], is_global=1)
+    o = world_from_config(cfg)
+    o.init_exact(0.0)
+    o.step(cfg["dt"], 3)
+    outs = []
+    for gt in (pw.PW_TILE_32X8, pw.PW_TILE_128X4, pw.PW_TILE_128X8):
+        for tz in (5, 16):
+            g = pw.context_from_config(cfg, precision=pw.PW_MIXED)
+            g.set_tuning(global_tile=gt, tile_z_global=tz)
+            g.init_exact(0.0)
+            g.rk4_step(cfg["dt"], 3)
+            outs.append([g.get_state(pid) for pid in range(2)])
+            if tz == 16:
+                say("ragged global, mixed, global tile", gt, "worst rel err", compare(cfg, o, g, 2e-5))
+            g.close()
+    for out in outs[1:]:
+        for a, b in zip(out, outs[0]):
+            assert np.array_equal(a, b, equal_nan=True)
+    for gt in (pw.PW_TILE_32X8, pw.PW_TILE_128X4):
+        g = pw.context_from_config(cfg, precision=pw.PW_FP64)
+        g.set_tuning(global_tile=gt, tile_z_global=7)
+        g.init_exact(0.0)
+        g.rk4_step(cfg["dt"], 3)
+        say("ragged global, FP64, global tile", gt, "worst rel err", compare(cfg, o, g, TOL64))
+        g.close()
+
+
 def test_autotune_then_parity():
     cfg = W.two_patch(seed=2, ng=48, nl=40, P=6)
     g = pw.context_from_config(cfg)
