@@ -300,7 +300,9 @@ pw_status pw_exchange_ghosts(pw_context *ctx, double t);
  * and cells that become live at the step end are interpolated from the covering
  * local patch (Sec. 2.4.2).  Returns PW_EMOTION before launching if a patch
  * would move max(1, buffer_width - 3) global cells or more in one step,
- * PW_EOVERLAP if two local patches cover one global cell that is not live. */
+ * PW_EOVERLAP if two local patches cover one global cell that is not live.
+ * nsteps = 0 advances nothing (the flags, outer ghosts and step graph may be
+ * prepared); nsteps < 0 or dt <= 0 (or NaN): PW_EINVAL. */
 pw_status pw_rk4_step(pw_context *ctx, double dt, int32_t nsteps);
 
 /* Run-time tuning parameters.  None changes a computed value: every setting

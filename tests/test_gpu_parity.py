@@ -725,6 +725,32 @@ def test_ragged_global_all_tile_shapes():
         g.close()
 
 
+def test_zero_steps_and_invalid_step_arguments():
+    # nsteps = 0 leaves the state and the time as they are, and the steps after it
+    # give bitwise what a context that never made the call gives; nsteps < 0 and
+    # dt <= 0 are rejected before anything is enqueued
+    cfg = W.two_patch(seed=2, ng=48, nl=40, P=6)
+    a = pw.context_from_config(cfg, precision=pw.PW_MIXED)
+    b = pw.context_from_config(cfg, precision=pw.PW_MIXED)
+    for g in (a, b):
+        g.init_exact(0.0)
+    before = [a.get_state(pid) for pid in range(2)]
+    a.rk4_step(cfg["dt"], 0)
+    assert a.t == 0.0
+    for pid in range(2):
+        assert np.array_equal(a.get_state(pid), before[pid], equal_nan=True)
+    for bad in ((cfg["dt"], -1), (0.0, 1), (-cfg["dt"], 1), (float("nan"), 1)):
+        with pytest.raises(pw.PwError):
+            a.rk4_step(*bad)
+    a.rk4_step(cfg["dt"], 2)
+    b.rk4_step(cfg["dt"], 2)
+    assert a.t == b.t
+    for pid in range(2):
+        assert np.array_equal(a.get_state(pid), b.get_state(pid), equal_nan=True)
+    a.close()
+    b.close()
+
+
 def test_autotune_then_parity():
     cfg = W.two_patch(seed=2, ng=48, nl=40, P=6)
     g = pw.context_from_config(cfg)
