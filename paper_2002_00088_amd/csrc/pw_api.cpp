@@ -212,6 +212,12 @@ uint32_t pack_ijk(int i, int j, int k) {
 bool mixed(const pw_context *c) { return c->cfg.precision == PW_MIXED || c->cfg.precision == PW_MIXED_INC; }
 size_t stage_elem(const pw_context *c) { return mixed(c) ? sizeof(float) : sizeof(double); }
 bool has_locals(const pw_context *c) { return c->hp.size() > 1; }
+// The global patch's tile shape in effect, for the tile list and the launch
+// alike: the two-rows-per-thread shape exists in the mixed modes only (and
+// pw_set_tuning rejects it in FP64).
+int global_tile_in_effect(const pw_context *c) {
+  return (c->tune.global_tile == PW_TILE_128X8 && !mixed(c)) ? PW_TILE_128X4 : c->tune.global_tile;
+}
 // a buffer narrower than NG + 1 cells (the original Patchwork flags as an
 // ablation): global->local stencils may reach effective ghosts
 bool narrow_buffer(const pw_context *c) { return c->cfg.buffer_width < PW_NG + 1; }
@@ -433,7 +439,7 @@ pw_status upload_layout(pw_context *c) {
     const PatchDev &p = c->hp[pid];
     c->tileOff[pid] = (int)tiles.size();
     const bool sq = c->tune.local_tile == 1;
-    const int gt = c->tune.global_tile;
+    const int gt = global_tile_in_effect(c);
     const int TX = pid == 0 ? (gt == 2 ? StageTile<true, 2>::TX : gt == 1 ? StageTile<true, 1>::TX : StageTile<true, 0>::TX)
                             : (sq ? StageTile<false, 1>::TX : StageTile<false, 0>::TX);
     const int TY = pid == 0 ? (gt == 2 ? StageTile<true, 2>::TY : gt == 1 ? StageTile<true, 1>::TY : StageTile<true, 0>::TY)
@@ -719,7 +725,7 @@ void enqueue_stage(pw_context *c, int stage, const PoseDev *pose_slot, double dt
     a.inc = c->cfg.precision == PW_MIXED_INC;
     a.form = c->cfg.pi_form;
     a.local_tile = c->tune.local_tile;
-    a.global_tile = c->tune.global_tile;
+    a.global_tile = global_tile_in_effect(c);
     a.dt = dt;
     a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
     a.eps = c->cfg.ko_eps;
@@ -771,7 +777,7 @@ void enqueue_stage_part(pw_context *c, int stage, const PoseDev *pose_slot, doub
     a.inc = c->cfg.precision == PW_MIXED_INC;
     a.form = c->cfg.pi_form;
     a.local_tile = c->tune.local_tile;
-    a.global_tile = c->tune.global_tile;
+    a.global_tile = global_tile_in_effect(c);
     a.dt = dt;
     a.v2 = c->cfg.wave_speed[sv] * c->cfg.wave_speed[sv];
     a.eps = c->cfg.ko_eps;
