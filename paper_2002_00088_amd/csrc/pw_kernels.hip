@@ -785,41 +785,47 @@ __global__ void k_bucket_count(const PatchDev *__restrict__ P, const PoseDev *__
   }
 }
 
-// Exclusive scan of nb bucket counts by one workgroup of 1024 threads.
+// Exclusive scan of nb bucket counts by one workgroup of 1024 threads, in
+// tiles of 8192 counts: thread t takes counts 8t .. 8t + 7 of a tile (a
+// wavefront reads one contiguous 2 KB piece), the thread sums of the tile are
+// scanned by wavefront shuffles and then across the 16 wavefront totals in LDS,
+// and a running total carries from one tile to the next.
 __global__ __launch_bounds__(1024) void k_bucket_scan(const int *cnt, int *off, int nb) {
-  // thread t owns a contiguous segment of `per` buckets; its counts are loaded
-  // eight at a time so that the loads are in flight together
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int per = (nb + 1023) / 1024;
-  const int b0 = t * per, b1 = min(nb, b0 + per);
-  int s = 0;
-  for (int b = b0; b < b1; b += 8) {
+  __shared__ int wsum[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int carry = 0;  // the same in every thread
+  for (int base = 0; base < nb; base += 8 * 1024) {
+    const int b0 = base + 8 * t;
     int v[8];
 #pragma unroll
-    for (int m = 0; m < 8; m++) v[m] = b + m < b1 ? cnt[b + m] : 0;
+    for (int m = 0; m < 8; m++) v[m] = b0 + m < nb ? cnt[b0 + m] : 0;
+    int s = 0;
 #pragma unroll
     for (int m = 0; m < 8; m++) s += v[m];
-  }
-  part[t] = s;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    int v = t >= o ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int run = part[t] - s;
-  for (int b = b0; b < b1; b += 8) {
-    int v[8];
+    int x = s;  // inclusive scan of the thread sums over the wavefront
 #pragma unroll
-    for (int m = 0; m < 8; m++) v[m] = b + m < b1 ? cnt[b + m] : 0;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int wpre = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+      const int ws = wsum[q];
+      wpre += q < w ? ws : 0;
+      tot += ws;
+    }
+    int run = carry + wpre + (x - s);  // counts before this thread's first bucket
 #pragma unroll
     for (int m = 0; m < 8; m++)
-      if (b + m < b1) {
-        off[b + m] = run;
+      if (b0 + m < nb) {
+        off[b0 + m] = run;
         run += v[m];
       }
+    carry += tot;
+    __syncthreads();  // wsum is written again by the next tile
   }
 }
 
