@@ -414,6 +414,34 @@ def test_spherical_global_patch(case):
     say("  worst rel err", compare(cfg, o, g, 2e-5 if case == "mixed" else TOL64))
 
 
+def test_spherical_global_all_tile_shapes():
+    # the spherical global patch (per-cell angle terms by row) with 42 theta cells,
+    # so that the 128 x 8 shape's second row of a thread is partly outside the
+    # padded patch: every global tile shape gives bitwise the same state (mixed
+    # modes), and mixed parity with the oracle
+    cfg = _sph_global_cfg(False)
+    g0 = cfg["patches"][0]
+    cfg["patches"][0] = W.patch([g0["n"][0], 42, g0["n"][2]], g0["lo"], g0["hi"], coord=W.SPH, is_global=1,
+                                periodic=(0, 0, 1))
+    del cfg["dt"]
+    cfg = W._finish(cfg)
+    o = world_from_config(cfg)
+    o.init_exact(0.0)
+    o.step(cfg["dt"], 3)
+    outs = []
+    for gt in (pw.PW_TILE_32X8, pw.PW_TILE_128X4, pw.PW_TILE_128X8):
+        g = pw.context_from_config(cfg, precision=pw.PW_MIXED)
+        g.set_tuning(global_tile=gt, tile_z_global=16)
+        g.init_exact(0.0)
+        g.rk4_step(cfg["dt"], 3)
+        outs.append([g.get_state(pid) for pid in range(len(cfg["patches"]))])
+        say("spherical global, mixed, global tile", gt, "worst rel err", compare(cfg, o, g, 2e-5))
+        g.close()
+    for out in outs[1:]:
+        for a, b in zip(out, outs[0]):
+            assert np.array_equal(a, b, equal_nan=True)
+
+
 def test_paper_test_four_reduced():
     # the paper's fourth test at 0.6 of its cell counts (the coarsest whose radial
     # ghosts stay off r = 0): spherical global shell,
