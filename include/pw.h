@@ -342,9 +342,10 @@ pw_status pw_set_tuning(pw_context *ctx, const pw_tuning *t);
 /* Autotuner: times candidate settings on this context's own patches with HIP
  * events over steps_per_trial steps of size dt each (after one untimed step),
  * searching the two tile depths and the global tile order on a grid, then the
- * global tile shape, the place of the curvilinear local stage kernels, the local
- * tile shape and the two run lengths, and keeps
- * the fastest (written to *best unless best is NULL).  It advances the state and
+ * other global tile shapes (128x8 in the mixed modes only) with the global tile
+ * depths, the place of the curvilinear local stage kernels, the local tile shape
+ * with the local tile depths and the two run lengths, and keeps the fastest
+ * (written to *best unless best is NULL).  It advances the state and
  * the time by every step it takes, so call it before setting the initial data
  * (or set it again afterwards).  On an error the previous settings are restored. */
 pw_status pw_autotune(pw_context *ctx, double dt, int32_t steps_per_trial, pw_tuning *best);
